@@ -1,0 +1,405 @@
+"""CPU ORACLE -- test infrastructure only.
+
+A plain, slow, obviously correct FP64 implementation of what the HIP library
+computes, written from the paper (Yang, Thompson & Sklar, "Guarantees for
+Comprehensive Simulation Assessment of Statistical Methods"):
+
+  * the Monte Carlo loops (Philox stream, draws, statistics, rejection counts,
+    score sums) live in plain C (oracle_sim.c, oracle_hier.c), called here
+    through ctypes;
+  * the bound arithmetic (Clopper-Pearson, Tilt-Bound, its inverse, the
+    optimisation over q, the vertex enumeration of clipped tiles, the order
+    statistic and the global minimum) is plain numpy/scipy below.
+
+Only tests/, __graft_entry__.smoke() and the CPU-baseline leg of bench.py may
+import this package.  It shares no code with paper_2212_10042_amd/ and imports
+nothing from it.
+
+Parity status of each function is stated in its docstring ("pinned by" lists
+the independent checks in tests/test_oracle_*.py).
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import math
+import os
+
+import numpy as np
+import scipy.special as sps
+
+from . import build as _build
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N_PER_ARM = 35
+
+_lib = None
+
+
+def lib():
+    """Load (building on first use if absent) the oracle's C library."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        u32, u64, i32, i64, dbl = (ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32,
+                                   ctypes.c_int64, ctypes.c_double)
+        P = ctypes.c_void_p
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_word.argtypes = [u64, u32, u32]
+        L.orc_word.restype = u32
+        L.orc_bern_threshold.argtypes = [dbl]
+        L.orc_bern_threshold.restype = u32
+        L.orc_box_muller.argtypes = [u32, u32]
+        L.orc_box_muller.restype = dbl
+        L.orc_pooled_z.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.orc_pooled_z.restype = dbl
+        L.orc_ztest1.argtypes = [i64, P, P, u64, dbl, P, P, P, i64]
+        L.orc_binom2.argtypes = [i64, P, P, u64, ctypes.c_int, dbl, P, P, P, i64]
+        L.orc_arm_counts.argtypes = [ctypes.c_int, P, i32, u64, ctypes.c_int, P]
+        if hasattr(L, "orc_hier4_posterior"):
+            L.orc_hier4_posterior.argtypes = [P, P, P]
+            L.orc_hier4_posterior_nodes.argtypes = [ctypes.c_int, dbl, dbl]
+            L.orc_hier4_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, dbl, P, P, P, i64, P]
+            L.orc_hier4_table.argtypes = [ctypes.c_int, P, i64, i64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+# --------------------------------------------------------------- RNG & draws
+def philox(ctr, key):
+    """Philox4x32-10 block (Salmon et al., SC'11).  Pinned by published known-answer values."""
+    c = np.asarray(ctr, np.uint32).copy()
+    k = np.asarray(key, np.uint32).copy()
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def word(seed: int, sim: int, w: int) -> int:
+    return int(lib().orc_word(seed, sim, w))
+
+
+def bern_threshold(theta: float) -> int:
+    """round(2^32 expit(theta)) clamped to [0, 2^32-1]: Bernoulli(expit theta) from one word."""
+    return int(lib().orc_bern_threshold(float(theta)))
+
+
+def arm_counts(theta_vec, sims: int, seed: int, n: int = N_PER_ARM) -> np.ndarray:
+    """Per-simulation binomial counts Y[k, a] of a d-arm design at one parameter point."""
+    th = np.ascontiguousarray(theta_vec, np.float64)
+    Y = np.zeros((sims, th.size), np.int32)
+    lib().orc_arm_counts(th.size, _p(th), sims, seed, n, _p(Y))
+    return Y
+
+
+def pooled_z(y0: int, y1: int, n: int = N_PER_ARM) -> float:
+    return float(lib().orc_pooled_z(y0, y1, n))
+
+
+# ------------------------------------------------------------------- designs
+def sim_ztest1(theta, sims, seed: int, cut: float = 1.96, want_S: bool = False):
+    """1-D z-test (Section 4.2, Section 5.4): R, sum of Z over rejections, S = -X."""
+    th = np.ascontiguousarray(np.asarray(theta, np.float64).reshape(-1))
+    sm = np.ascontiguousarray(sims, np.int32)
+    n = th.size
+    R = np.zeros(n, np.int32)
+    sz = np.zeros(n, np.float64)
+    stride = int(sm.max()) if n else 0
+    S = np.full((n, stride), np.nan) if want_S else None
+    lib().orc_ztest1(n, _p(th), _p(sm), seed, cut, _p(R), _p(sz), _p(S), stride)
+    return R, sz, S
+
+
+def sim_binom2(theta, sims, seed: int, cut: float = 1.96, n: int = N_PER_ARM, want_S: bool = False):
+    """2-arm pooled two-proportion z design: R, sumT [n_tiles, 2], S = -z."""
+    th = np.ascontiguousarray(np.asarray(theta, np.float64).reshape(-1, 2))
+    sm = np.ascontiguousarray(sims, np.int32)
+    m = th.shape[0]
+    R = np.zeros(m, np.int32)
+    sT = np.zeros((m, 2), np.int64)
+    stride = int(sm.max()) if m else 0
+    S = np.full((m, stride), np.nan) if want_S else None
+    lib().orc_binom2(m, _p(th), _p(sm), seed, n, cut, _p(R), _p(sT), _p(S), stride)
+    return R, sT, S
+
+
+# --------------------------------------------------- exponential families
+def log_partition(family: str, theta: np.ndarray, n: int = N_PER_ARM) -> np.ndarray:
+    """A(theta) over the last axis: normal location theta^2/2 (Section 4.2);
+    independent binomial arms in logit, sum_a n softplus(theta_a) (Example 1)."""
+    if family == "normal":
+        return 0.5 * np.sum(theta * theta, axis=-1)
+    if family == "binom":
+        return n * np.sum(np.logaddexp(0.0, theta), axis=-1)
+    raise ValueError(family)
+
+
+def psi(family, theta0, v, q, n=N_PER_ARM):
+    """psi(theta0, v, q) = A(theta0 + q v) - A(theta0) for a natural exponential family (Example 1)."""
+    return log_partition(family, theta0 + q * v, n) - log_partition(family, theta0, n)
+
+
+def log_tilt(family, theta0, v, q, a, n=N_PER_ARM):
+    """log of the Tilt-Bound U(theta0, v, q, a) (Theorem 1, exponential-family form of Example 1)."""
+    return (1.0 - 1.0 / q) * np.log(a) + psi(family, theta0, v, q, n) / q - psi(family, theta0, v, 1.0, n)
+
+
+def log_inv_tilt(family, theta0, v, q, alpha, n=N_PER_ARM):
+    """log of the Inverted Tilt-Bound U^{-1}(theta0, v, q, alpha) (Section 6.2)."""
+    return q / (q - 1.0) * (np.log(alpha) - psi(family, theta0, v, q, n) / q + psi(family, theta0, v, 1.0, n))
+
+
+_GOLD = (math.sqrt(5.0) - 1.0) / 2.0
+S_LO, S_HI, GOLD_ITERS = -30.0, 30.0, 100
+
+
+def _golden(f, m: int, maximize: bool):
+    """Golden-section search on s = log(q - 1) in [S_LO, S_HI], vectorised over m problems.
+
+    Valid because the objective is quasi-convex in q (Theorem 2) and q -> log(q-1) is monotone.
+    """
+    sgn = -1.0 if maximize else 1.0
+    lo = np.full(m, S_LO)
+    hi = np.full(m, S_HI)
+    x1 = hi - _GOLD * (hi - lo)
+    x2 = lo + _GOLD * (hi - lo)
+    f1 = sgn * f(x1)
+    f2 = sgn * f(x2)
+    for _ in range(GOLD_ITERS):
+        left = f1 <= f2          # the minimum lies in [lo, x2]: drop (x2, hi]
+        nlo = np.where(left, lo, x1)
+        nhi = np.where(left, x2, hi)
+        nx1 = np.where(left, nhi - _GOLD * (nhi - nlo), x2)
+        nx2 = np.where(left, x1, nlo + _GOLD * (nhi - nlo))
+        fe = sgn * f(np.where(left, nx1, nx2))   # the one new evaluation
+        nf1 = np.where(left, fe, f2)
+        nf2 = np.where(left, f1, fe)
+        lo, hi, x1, x2, f1, f2 = nlo, nhi, nx1, nx2, nf1, nf2
+    s = 0.5 * (lo + hi)
+    return s, f(s)
+
+
+def tile_bound(family, theta0, V, a, n=N_PER_ARM):
+    """Tilewise Optimized Tilt-Bound inf_q max_{v in V} U(theta0, v, q, a) (Remark 3, Theorem 3).
+
+    theta0 [m, d]; V [m, nv, d] displacements of the tile's vertices from theta0;
+    a [m].  Returns (bound [m], q_star [m]).  a == 0 gives 0; a >= 1 gives 1.
+    """
+    theta0 = np.asarray(theta0, np.float64)
+    V = np.asarray(V, np.float64)
+    a = np.asarray(a, np.float64)
+    m = theta0.shape[0]
+    a_safe = np.clip(a, 1e-300, 1.0)
+    A0 = log_partition(family, theta0, n)[:, None]                      # [m, 1]
+    psi1 = log_partition(family, theta0[:, None, :] + V, n) - A0       # [m, nv]
+
+    def W(s):
+        q = (1.0 + np.exp(s))[:, None]                                  # [m, 1]
+        psiq = log_partition(family, theta0[:, None, :] + q[:, :, None] * V, n) - A0
+        lu = (1.0 - 1.0 / q) * np.log(a_safe)[:, None] + psiq / q - psi1
+        return lu.max(axis=1)
+
+    s, w = _golden(W, m, maximize=False)
+    with np.errstate(over="ignore"):
+        out = np.exp(w)
+    out = np.where(a <= 0.0, 0.0, out)
+    out = np.where(a >= 1.0, 1.0, np.minimum(out, 1.0))
+    return out, 1.0 + np.exp(s)
+
+
+def tile_inverse(family, theta0, V, alpha, n=N_PER_ARM):
+    """alpha' = sup_q min_{v in V} U^{-1}(theta0, v, q, alpha) (Section 6.2).  Returns (alpha', q_star)."""
+    theta0 = np.asarray(theta0, np.float64)
+    V = np.asarray(V, np.float64)
+    m = theta0.shape[0]
+    al = np.broadcast_to(np.asarray(alpha, np.float64), (m,))
+    A0 = log_partition(family, theta0, n)[:, None]
+    psi1 = log_partition(family, theta0[:, None, :] + V, n) - A0
+
+    def W(s):
+        q = (1.0 + np.exp(s))[:, None]
+        psiq = log_partition(family, theta0[:, None, :] + q[:, :, None] * V, n) - A0
+        li = q / (q - 1.0) * (np.log(al)[:, None] - psiq / q + psi1)
+        return li.min(axis=1)
+
+    s, w = _golden(W, m, maximize=True)
+    return np.exp(w), 1.0 + np.exp(s)
+
+
+def cp_upper(R, N, delta):
+    """Clopper-Pearson (1-delta) upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 5.1); 1 when R == N."""
+    R = np.asarray(R, np.float64)
+    N = np.asarray(N, np.float64)
+    out = np.ones(np.broadcast(R, N).shape)
+    ok = R < N
+    out[ok] = sps.betaincinv((R + 1.0)[ok] if R.ndim else R + 1.0, (N - R)[ok] if N.ndim else N - R,
+                             1.0 - delta)
+    return out
+
+
+# ------------------------------------------------------------- the platten
+def hypotheses(design: str, d: int):
+    """Null hypotheses as half-spaces g . theta <= h (Section 4):
+    z-test H0: theta <= 0; multi-arm designs (arm 0 control): H_i: theta_i <= theta_0."""
+    if design == "ztest1":
+        return [(np.array([1.0]), 0.0)]
+    out = []
+    for i in range(1, d):
+        g = np.zeros(d)
+        g[i] = 1.0
+        g[0] = -1.0
+        out.append((g, 0.0))
+    return out
+
+
+def family_of(design: str) -> str:
+    return "normal" if design == "ztest1" else "binom"
+
+
+def _enumerate_vertices(G, h, d, tol=1e-12):
+    """Vertices of {x : G x <= h} by brute force over d-subsets of active constraints."""
+    verts = []
+    for idx in itertools.combinations(range(G.shape[0]), d):
+        A = G[list(idx)]
+        if abs(np.linalg.det(A)) < 1e-12:
+            continue
+        x = np.linalg.solve(A, h[list(idx)])
+        if np.all(G @ x <= h + tol * (1.0 + np.abs(h))):
+            if not any(np.allclose(x, y, rtol=0, atol=1e-12) for y in verts):
+                verts.append(x)
+    return np.array(verts)
+
+
+def subtiles(design: str, theta, radii, keep_all: bool = False):
+    """Split each box into its null-configuration pieces box ∩ P(b) with non-empty interior
+    (Section 4, Definition 1).  Returns a list of (box index, b bitmask, vertices [nv, d],
+    in_null flag); b bit j-1 is hypothesis j.  With keep_all (single-hypothesis designs only),
+    a box that meets no null is kept whole with in_null = False.
+    """
+    theta = np.asarray(theta, np.float64)
+    radii = np.asarray(radii, np.float64)
+    m, d = theta.shape
+    hyps = hypotheses(design, d)
+    p = len(hyps)
+    out = []
+    corners_sign = np.array(list(itertools.product([-1.0, 1.0], repeat=d)))
+    for i in range(m):
+        lo = theta[i] - radii[i]
+        hi = theta[i] + radii[i]
+        corners = theta[i] + corners_sign * radii[i]
+        met = False
+        for b in range(1, 1 << p):
+            cons = []
+            for j, (g, hh) in enumerate(hyps):
+                if (b >> j) & 1:
+                    cons.append((g, hh))          # g.x <= h
+                else:
+                    cons.append((-g, -hh))        # closure of the complement: g.x >= h
+            vals = [corners @ g - hh for g, hh in cons]
+            if any(v.min() >= 0.0 for v in vals):
+                continue                           # a constraint holds nowhere inside: no interior
+            if all(v.max() <= 0.0 for v in vals):
+                out.append((i, b, corners.copy(), True))
+                met = True
+                continue
+            G = np.vstack([np.eye(d), -np.eye(d)] + [g[None, :] for g, _ in cons])
+            h = np.concatenate([hi, -lo, [hh for _, hh in cons]])
+            V = _enumerate_vertices(G, h, d)
+            if V.shape[0] < d + 1:
+                continue
+            c = V.mean(axis=0)
+            if np.all(G @ c < h - 1e-12):
+                out.append((i, b, V, True))
+                met = True
+        if not met and keep_all:
+            if p != 1:
+                raise ValueError("keep_all is defined for single-hypothesis designs")
+            out.append((i, 1, corners.copy(), False))
+    return out
+
+
+def _pad_vertices(subs, theta):
+    nv = max(len(s[2]) for s in subs)
+    d = theta.shape[1]
+    V = np.zeros((len(subs), nv, d))
+    for t, (i, b, verts, _) in enumerate(subs):
+        disp = verts - theta[i]
+        V[t, : len(disp)] = disp
+        V[t, len(disp):] = disp[0]
+    return V
+
+
+# -------------------------------------------------------------- procedures
+def simulate(design: str, theta, sims, seed: int, cut: float = 1.96, want_S: bool = False):
+    """Per box: (R, score sums, S) from the design's simulator at the box centre."""
+    if design == "ztest1":
+        return sim_ztest1(theta, sims, seed, cut, want_S)
+    if design == "binom2":
+        return sim_binom2(theta, sims, seed, cut, N_PER_ARM, want_S)
+    raise ValueError(design)
+
+
+def score_gradient(design: str, theta, R, score, sims, n: int = N_PER_ARM):
+    """Score-function estimate of d TIE / d theta: (sum over rejections of T(x) - R grad A(theta)) / N.
+
+    T(x) is the sufficient statistic of the exponential family (Example 1): for the
+    z-test the score sum is already sum Z = sum (X - theta); for binomial arms
+    grad_a A = n expit(theta_a)."""
+    theta = np.asarray(theta, np.float64)
+    N = np.asarray(sims, np.float64)
+    if design == "ztest1":
+        return (np.asarray(score, np.float64).reshape(-1) / N)[:, None]
+    gA = n * sps.expit(theta)
+    return (np.asarray(score, np.float64) - np.asarray(R, np.float64)[:, None] * gA) / N[:, None]
+
+
+def validate(design: str, theta, radii, sims, seed: int, delta: float, cut: float = 1.96,
+             keep_all: bool = False):
+    """Validation (Algorithm 1): per sub-tile R, CP upper bound, tilewise optimized Tilt-Bound."""
+    theta = np.asarray(theta, np.float64)
+    subs = subtiles(design, theta, radii, keep_all)
+    R, score, _ = simulate(design, theta, sims, seed, cut)
+    box = np.array([s[0] for s in subs])
+    N = np.asarray(sims)[box]
+    Rb = R[box]
+    cp = cp_upper(Rb, N, delta)
+    V = _pad_vertices(subs, theta)
+    ub, qs = tile_bound(family_of(design), theta[box], V, cp)
+    return dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
+                q=qs, R_box=R, score_box=score, subs=subs)
+
+
+def order_statistic(S_row: np.ndarray, k: int) -> float:
+    """k-th smallest value (1-based) of S_row; -inf when k == 0 (no rejection, Theorem 4's range)."""
+    if k <= 0:
+        return -math.inf
+    return float(np.sort(S_row)[k - 1])
+
+
+def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False):
+    """Calibration (Algorithm 2): alpha'_i, k_i = floor((N_i+1) alpha'_i), lambda*_i = S_(k_i),
+    lambda* = min_i lambda*_i, and #{S < lambda*_i} per sub-tile."""
+    theta = np.asarray(theta, np.float64)
+    sims = np.asarray(sims, np.int32)
+    subs = subtiles(design, theta, radii, keep_all)
+    box = np.array([s[0] for s in subs])
+    V = _pad_vertices(subs, theta)
+    ap, qs = tile_inverse(family_of(design), theta[box], V, alpha)
+    N = sims[box]
+    k = np.floor((N + 1.0) * ap).astype(np.int64)
+    _, _, S = simulate(design, theta, sims, seed, 1.96, want_S=True)
+    lam = np.empty(len(subs))
+    rej = np.empty(len(subs), np.int64)
+    for t, i in enumerate(box):
+        row = S[i, : sims[i]]
+        lam[t] = order_statistic(row, int(k[t]))
+        rej[t] = int(np.sum(row < lam[t]))
+    return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, q=qs, k=k,
+                lam=lam, lam_global=float(lam.min()) if len(lam) else math.inf,
+                reject_at_lam=rej, N=N, subs=subs)
