@@ -1,0 +1,212 @@
+/*
+ * cse.h -- C ABI of the MI355X (gfx950) Continuous Simulation Extension library (libcse.so).
+ *
+ * Method: Yang, Thompson & Sklar, "Guarantees for Comprehensive Simulation
+ * Assessment of Statistical Methods".  The library simulates a trial design at
+ * the points of a platten (Section 4, Definition 1), counts rejections, forms
+ * score-function gradient sums, selects the calibrated threshold of each tile
+ * as an order statistic (Section 6.1), and evaluates the Clopper-Pearson plus
+ * Tilt-Bound over each tile (Sections 5.1-5.2, 6.2).
+ *
+ * Conventions for every entry point:
+ *   - Status: CSE_OK (0) or a negative cse_status; errors never cross the ABI
+ *     as exceptions.  cse_last_error() returns a thread-local message for the
+ *     last non-OK status of the calling thread.
+ *   - Memory: arrays named "host" are read during the call only; all other
+ *     array arguments are DEVICE pointers owned by the caller, written
+ *     asynchronously on `stream` (a hipStream_t passed as void*, NULL = the
+ *     null stream).  The library never frees caller memory.  Workspace the
+ *     library needs is allocated at platten creation or on first use and
+ *     released by cse_platten_destroy.
+ *   - Calls are asynchronous: a CSE_OK status covers argument validation and
+ *     launch errors; results are ready when `stream` is synchronised.
+ *   - A "tile" below is one piece box ∩ P(b) of a caller box with non-empty
+ *     interior (null configuration b, Section 4).  Tiles are numbered in box
+ *     order, then by b ascending.  cse_platten_describe maps them back.
+ *   - Random numbers: simulation k of every tile uses the words
+ *     Philox4x32-10(key = (seed lo, seed hi), ctr = (w/4, k, 0, 0))[w mod 4]
+ *     (Salmon et al., SC'11), i.e. common random numbers across tiles, which
+ *     the calibration guarantee allows (Section 6.3).
+ */
+#ifndef CSE_H
+#define CSE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSE_OK = 0,
+    CSE_EINVAL = -1,       /* invalid argument (sizes, probabilities, pointers)   */
+    CSE_ENOMEM = -2,       /* device or host allocation failed                    */
+    CSE_EHIP = -3,         /* a HIP runtime call or a kernel launch failed        */
+    CSE_EUNSUPPORTED = -4, /* design/option not supported                         */
+    CSE_ECALIB = -5        /* calibration: every tile has k_i = 0 (Theorem 4 range) */
+} cse_status;
+
+/* Designs (the protocol D that maps simulated data to a rejection / statistic S). */
+typedef enum {
+    /* One-sided z-test (Section 4.2): X ~ N(theta, 1), H0: theta <= 0, reject X > cut;
+     * calibration statistic S = -X.  d = 1. */
+    CSE_ZTEST1 = 1,
+    /* Two Bernoulli arms with n patients each (arm 0 control, arm 1 treatment, natural
+     * parameter = logit), H0: theta1 <= theta0, pooled two-proportion z, reject z > cut;
+     * calibration statistic S = -z.  d = 2. */
+    CSE_BINOM2_Z = 2,
+    /* Four Bernoulli arms, n patients each (arm 0 control), hierarchical model of
+     * Section 10.1 (theta_i ~ N(mu, sigma^2), mu ~ N(-1.34, 100), sigma^2 ~ IG(0.0005,
+     * 0.000005)); H_i: theta_i <= theta_0 for i = 1..3; statistic for null configuration
+     * b: S_b = min_{i in b} (1 - P(p_i > p_0 | y)); reject when S_b < cut.  d = 4. */
+    CSE_HIER4 = 3
+} cse_design_kind;
+
+typedef struct {
+    int32_t kind;       /* cse_design_kind                                      */
+    int32_t n_arms;     /* d: 1 (ZTEST1), 2 (BINOM2_Z), 4 (HIER4)                */
+    int32_t n_per_arm;  /* patients per arm for binomial designs (1..63); ignored for ZTEST1 */
+    int32_t reserved;   /* must be 0                                             */
+    double cut;         /* fixed rule of the design used by cse_simulate/validate */
+} cse_design;
+
+typedef struct cse_platten cse_platten;
+
+/* Platten flags. */
+#define CSE_PLATTEN_KEEP_ALL 1 /* single-hypothesis designs: keep boxes that meet no
+                                  null (their tile is the whole box, in_null = 0)   */
+
+/*
+ * cse_platten_create -- build the platten of Definition 1 (Section 4) from caller boxes.
+ *   design   host, read once.
+ *   n_boxes  number of boxes (>= 1).
+ *   theta    host, float64 [n_boxes][d], the simulation point of each box (its centre).
+ *   radii    host, float64 [n_boxes][d], box half-widths (> 0).
+ *   sims     host, int32 [n_boxes], simulations per box (1 .. 2^24).
+ *   flags    0 or CSE_PLATTEN_KEEP_ALL.
+ *   out      receives the handle (destroy with cse_platten_destroy).
+ * Splits each box into tiles box ∩ P(b) with non-empty interior (eq. of the null
+ * partition, Section 4), enumerates each tile's vertices in float64 (the supremum of
+ * the bound over a convex polytope is attained at a vertex, Theorem 3), computes the
+ * per-arm Bernoulli thresholds round(2^32 expit(theta)) in float64, plans the tile
+ * batches the kernels run, and uploads everything to the current HIP device.
+ * Errors: CSE_EINVAL (bad sizes/values, no box meets a null), CSE_ENOMEM, CSE_EHIP.
+ */
+int cse_platten_create(const cse_design *design, int64_t n_boxes, const double *theta,
+                       const double *radii, const int32_t *sims, int32_t flags,
+                       cse_platten **out);
+
+/* Release the platten and its device workspaces (synchronises the device first). */
+int cse_platten_destroy(cse_platten *p);
+
+/* Number of tiles (box pieces) in the platten; < 0 on a NULL handle. */
+int64_t cse_platten_size(const cse_platten *p);
+
+/*
+ * cse_platten_describe -- host copies of the tile list (any pointer may be NULL):
+ *   box      int64 [n_tiles]  box index of each tile
+ *   cfg      int32 [n_tiles]  null configuration b (bit j-1 = hypothesis j is true)
+ *   n_vert   int32 [n_tiles]  number of vertices of box ∩ P(b)
+ *   in_null  int32 [n_tiles]  1 when the tile lies in the null space
+ */
+int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32_t *n_vert,
+                         int32_t *in_null);
+
+/*
+ * cse_simulate -- Monte Carlo at every tile with the design's fixed rule (Section 5.1 input).
+ *   reject   int32 [n_tiles]       R_i = number of simulations whose F_b(X) = 1 (FWER event of
+ *                                  the tile's configuration b, Section 4).
+ *   score_T  int64 [n_tiles][d] or NULL: binomial designs, sum over rejecting simulations of
+ *                                  the sufficient statistic T(x) (arm success counts, Example 1).
+ *   score_Z  float64 [n_tiles] or NULL: ZTEST1, sum over rejecting simulations of X - theta.
+ *   grad     float64 [n_tiles][d] or NULL: score-function estimate of d f / d theta,
+ *                                  (sum_rej T(x) - R grad A(theta)) / N  (exponential family).
+ * Errors: CSE_EINVAL (NULL reject, bad handle), CSE_EHIP.
+ */
+int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *score_T,
+                 double *score_Z, double *grad, void *stream);
+
+/*
+ * cse_validate -- Validation procedure (Algorithm 1, Section 5): simulate as cse_simulate, then
+ *   cp_upper   float64 [n_tiles] Clopper-Pearson (1-delta) upper bound at theta_i (Section 5.1)
+ *   tile_bound float64 [n_tiles] inf_q max_{v in vertices} U(theta_i, v, q, cp_upper_i)
+ *                                (Tilewise Optimized Tilt-Bound, Remark 3, Section 5.2)
+ *   q_star     float64 [n_tiles] or NULL: the optimising Holder exponent q.
+ * reject/score_T/score_Z/grad as in cse_simulate (score pointers may be NULL).
+ * Errors: CSE_EINVAL (delta outside (0,1)), CSE_EHIP.
+ */
+int cse_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *reject,
+                 int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                 double *tile_bound, double *q_star, void *stream);
+
+/*
+ * cse_calibrate -- Calibration procedure (Algorithm 2, Section 6):
+ *   alpha_prime   float64 [n_tiles]  sup_q min_v U^{-1}(theta_i, v, q, alpha) (Section 6.2)
+ *   k             int32   [n_tiles]  floor((N_i + 1) alpha'_i)
+ *   lambda_tile   float64 [n_tiles]  lambda*_i = S_(k_i), the k_i-th smallest statistic of the
+ *                                    tile (Section 6.1); -inf when k_i = 0
+ *   lambda_global float64 [1]        min_i lambda*_i (Section 6.3)
+ *   reject_at_lambda int32 [n_tiles] or NULL: #{simulations with S < lambda*_i}
+ * Validation outputs at the design's fixed rule (reject, score_T, score_Z, grad, cp_upper,
+ * tile_bound) may be requested in the same pass (each may be NULL; cp_upper/tile_bound use
+ * `delta`, which is ignored when both are NULL).
+ * Errors: CSE_EINVAL (alpha or delta outside (0,1)), CSE_ENOMEM (key workspace), CSE_EHIP.
+ * Tiles with k_i = 0 get lambda*_i = -inf (no calibrated rejection); CSE_ECALIB is not
+ * raised from the asynchronous path -- check lambda_global on the host.
+ */
+int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime,
+                  int32_t *k, double *lambda_tile, double *lambda_global,
+                  int32_t *reject_at_lambda, double delta, int32_t *reject, int64_t *score_T,
+                  double *score_Z, double *grad, double *cp_upper, double *tile_bound,
+                  void *stream);
+
+/*
+ * cse_bound -- the float64 bound of each tile, without simulation.
+ *   mode 0 (validate): R int32 [n_tiles] device rejection counts; out = tilewise optimized
+ *          Tilt-Bound of the Clopper-Pearson bound at level delta_or_alpha = delta.
+ *   mode 1 (invert):   R ignored (may be NULL); out = alpha' for level delta_or_alpha = alpha.
+ *   mode 2 (tilt only): R ignored; `a` float64 [n_tiles] device values f(theta_i) in [0,1];
+ *          out = inf_q max_v U(theta_i, v, q, a_i) (Remark 3).
+ *   q_star float64 [n_tiles] or NULL.
+ * Errors: CSE_EINVAL, CSE_EHIP.
+ */
+int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double *a,
+              double delta_or_alpha, double *out, double *q_star, void *stream);
+
+/*
+ * cse_simulate_per_tile -- the plain forward-only path: one kernel launch per tile, no
+ * common-random-number batching across tiles, rejection counts only (the design's fixed rule).
+ * Same Philox stream and draw rules as cse_simulate, hence identical R.  Processes tiles
+ * [tile_begin, tile_end).  Used as the reference point for the batched path's speed.
+ * Errors: CSE_EINVAL, CSE_EHIP.
+ */
+int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begin,
+                          int64_t tile_end, int32_t *reject, void *stream);
+
+/*
+ * cse_platten_stats -- sizes of the planned launch (host), out[0..7] =
+ *   n_tiles, n_batches (tile batches of the fused kernel), n_work_items (waves launched by one
+ *   simulation pass), n_key_slots (calibration keys), total simulations (sum of N over tiles),
+ *   tiles per batch, max N, simulation-batch pairs (sum over batches of their N).
+ */
+int cse_platten_stats(const cse_platten *p, int64_t out[8]);
+
+/*
+ * Kernel timing for measurement (process-wide, not thread-safe against concurrent calls):
+ * while enabled, every kernel launch of the library is bracketed by two HIP events recorded
+ * on the launch's own stream.  cse_profile_get synchronises the recorded events and returns,
+ * for the kernel `name` (e.g. "binom2_calib"), the number of timed launches and their total
+ * duration in milliseconds.  Do not enable while capturing a HIP graph.
+ */
+int cse_profile_enable(int32_t on);
+int cse_profile_get(const char *name, int64_t *launches, double *total_ms);
+int cse_profile_reset(void);
+
+/* Thread-local message for the last non-OK status returned on this thread. */
+const char *cse_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSE_H */

@@ -1,0 +1,298 @@
+"""Continuous Simulation Extension on MI355X (gfx950): Python binding of libcse.so.
+
+The functions named ``cse_*`` marshal arguments to the C ABI of the same name
+(include/cse.h): torch tensors supply device memory and the current HIP stream,
+every computation runs in the library's HIP kernels.  If libcse.so is missing the
+import fails; there is no other execution path.
+
+Method: Yang, Thompson & Sklar, "Guarantees for Comprehensive Simulation
+Assessment of Statistical Methods" -- validation (Algorithm 1, Section 5) and
+calibration (Algorithm 2, Section 6) over a platten of tiles (Definition 1,
+Section 4), with the Tilt-Bound of Theorem 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcse.so")
+
+CSE_OK, CSE_EINVAL, CSE_ENOMEM, CSE_EHIP, CSE_EUNSUPPORTED, CSE_ECALIB = 0, -1, -2, -3, -4, -5
+CSE_ZTEST1, CSE_BINOM2_Z, CSE_HIER4 = 1, 2, 3
+CSE_PLATTEN_KEEP_ALL = 1
+
+EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
+            "cse_simulate", "cse_validate", "cse_calibrate", "cse_bound", "cse_simulate_per_tile",
+            "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
+            "cse_last_error")
+
+
+class CseError(RuntimeError):
+    def __init__(self, fn: str, status: int, msg: str):
+        super().__init__(f"{fn} -> status {status}: {msg}")
+        self.status = status
+
+
+class cse_design(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_arms", ctypes.c_int32), ("n_per_arm", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("cut", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built (python -m paper_2212_10042_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    missing = [fn for fn in EXPORTED if not hasattr(L, fn)]
+    if missing:
+        raise ImportError(f"{LIB_PATH} is stale (missing {missing}); rebuild it")
+    P, i32, i64, u64, dbl = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double
+    L.cse_platten_create.argtypes = [ctypes.POINTER(cse_design), i64, P, P, P, i32, ctypes.POINTER(P)]
+    L.cse_platten_destroy.argtypes = [P]
+    L.cse_platten_size.argtypes = [P]
+    L.cse_platten_size.restype = i64
+    L.cse_platten_describe.argtypes = [P, P, P, P, P]
+    L.cse_simulate.argtypes = [P, u64, P, P, P, P, P]
+    L.cse_validate.argtypes = [P, u64, dbl, P, P, P, P, P, P, P, P]
+    L.cse_calibrate.argtypes = [P, u64, dbl, P, P, P, P, P, dbl, P, P, P, P, P, P, P]
+    L.cse_bound.argtypes = [P, i32, P, P, dbl, P, P, P]
+    L.cse_simulate_per_tile.argtypes = [P, u64, i64, i64, P, P]
+    L.cse_platten_stats.argtypes = [P, P]
+    L.cse_profile_enable.argtypes = [i32]
+    L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
+    L.cse_profile_reset.argtypes = []
+    L.cse_last_error.restype = ctypes.c_char_p
+    for fn in EXPORTED:
+        if fn not in ("cse_platten_size", "cse_last_error"):
+            getattr(L, fn).restype = ctypes.c_int
+    return L
+
+
+_L = _load()
+
+
+def lib():
+    return _L
+
+
+def _check(fn: str, status: int):
+    if status != CSE_OK:
+        raise CseError(fn, status, _L.cse_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if isinstance(t, torch.Tensor):
+        return ctypes.c_void_p(t.data_ptr())
+    if isinstance(t, np.ndarray):
+        return t.ctypes.data_as(ctypes.c_void_p)
+    raise TypeError(type(t))
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+# ------------------------------------------------------------------ C-ABI mirrors
+def make_design(kind: str | int, cut: float | None = None, n_per_arm: int = 35) -> cse_design:
+    k = {"ztest1": CSE_ZTEST1, "binom2": CSE_BINOM2_Z, "hier4": CSE_HIER4}.get(kind, kind)
+    d = {CSE_ZTEST1: 1, CSE_BINOM2_Z: 2, CSE_HIER4: 4}[k]
+    if cut is None:
+        cut = 1.96 if k in (CSE_ZTEST1, CSE_BINOM2_Z) else 0.05
+    return cse_design(k, d, n_per_arm if k != CSE_ZTEST1 else 0, 0, float(cut))
+
+
+def cse_platten_create(design: cse_design, theta, radii, sims, flags: int = 0):
+    th = np.ascontiguousarray(theta, np.float64)
+    rd = np.ascontiguousarray(radii, np.float64)
+    sm = np.ascontiguousarray(sims, np.int32)
+    h = ctypes.c_void_p()
+    _check("cse_platten_create",
+           _L.cse_platten_create(ctypes.byref(design), th.shape[0], _ptr(th), _ptr(rd), _ptr(sm),
+                                 flags, ctypes.byref(h)))
+    return h
+
+
+def cse_platten_destroy(h):
+    _check("cse_platten_destroy", _L.cse_platten_destroy(h))
+
+
+def cse_platten_size(h) -> int:
+    return int(_L.cse_platten_size(h))
+
+
+def cse_platten_describe(h):
+    n = cse_platten_size(h)
+    box = np.zeros(n, np.int64)
+    cfg = np.zeros(n, np.int32)
+    nv = np.zeros(n, np.int32)
+    inn = np.zeros(n, np.int32)
+    _check("cse_platten_describe", _L.cse_platten_describe(h, _ptr(box), _ptr(cfg), _ptr(nv), _ptr(inn)))
+    return dict(box=box, cfg=cfg, n_vert=nv, in_null=inn)
+
+
+def cse_simulate(h, seed, reject, score_T=None, score_Z=None, grad=None, stream=None):
+    _check("cse_simulate", _L.cse_simulate(h, seed, _ptr(reject), _ptr(score_T), _ptr(score_Z),
+                                           _ptr(grad), _stream(stream)))
+
+
+def cse_validate(h, seed, delta, reject, score_T, score_Z, grad, cp_upper, tile_bound, q_star=None,
+                 stream=None):
+    _check("cse_validate", _L.cse_validate(h, seed, delta, _ptr(reject), _ptr(score_T), _ptr(score_Z),
+                                           _ptr(grad), _ptr(cp_upper), _ptr(tile_bound), _ptr(q_star),
+                                           _stream(stream)))
+
+
+def cse_calibrate(h, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda=None,
+                  delta=0.01, reject=None, score_T=None, score_Z=None, grad=None, cp_upper=None,
+                  tile_bound=None, stream=None):
+    _check("cse_calibrate", _L.cse_calibrate(h, seed, alpha, _ptr(alpha_prime), _ptr(k), _ptr(lambda_tile),
+                                             _ptr(lambda_global), _ptr(reject_at_lambda), delta,
+                                             _ptr(reject), _ptr(score_T), _ptr(score_Z), _ptr(grad),
+                                             _ptr(cp_upper), _ptr(tile_bound), _stream(stream)))
+
+
+def cse_bound(h, mode, R, a, level, out, q_star=None, stream=None):
+    _check("cse_bound", _L.cse_bound(h, mode, _ptr(R), _ptr(a), level, _ptr(out), _ptr(q_star),
+                                     _stream(stream)))
+
+
+def cse_simulate_per_tile(h, seed, tile_begin, tile_end, reject, stream=None):
+    _check("cse_simulate_per_tile", _L.cse_simulate_per_tile(h, seed, tile_begin, tile_end, _ptr(reject),
+                                                             _stream(stream)))
+
+
+def cse_platten_stats(h) -> dict:
+    out = np.zeros(8, np.int64)
+    _check("cse_platten_stats", _L.cse_platten_stats(h, _ptr(out)))
+    keys = ("n_tiles", "n_batches", "n_work_items", "n_key_slots", "total_sims", "tiles_per_batch",
+            "max_sims", "batch_sims")
+    return {k: int(v) for k, v in zip(keys, out)}
+
+
+def cse_profile_enable(on: bool = True):
+    _check("cse_profile_enable", _L.cse_profile_enable(1 if on else 0))
+
+
+def cse_profile_get(name: str):
+    n = ctypes.c_int64()
+    ms = ctypes.c_double()
+    _check("cse_profile_get", _L.cse_profile_get(name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+    return int(n.value), float(ms.value)
+
+
+def cse_profile_reset():
+    _check("cse_profile_reset", _L.cse_profile_reset())
+
+
+# ------------------------------------------------------------------ convenience layer
+@dataclass
+class Platten:
+    """A platten on the current device: the handle plus its tile description."""
+    handle: ctypes.c_void_p
+    design: cse_design
+    n_tiles: int
+    d: int
+    tiles: dict
+
+    @classmethod
+    def create(cls, kind, theta, radii, sims, cut=None, keep_all=False):
+        des = make_design(kind, cut)
+        h = cse_platten_create(des, theta, radii, sims, CSE_PLATTEN_KEEP_ALL if keep_all else 0)
+        return cls(h, des, cse_platten_size(h), des.n_arms, cse_platten_describe(h))
+
+    def close(self):
+        if self.handle:
+            cse_platten_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _alloc(self, device):
+        n, d = self.n_tiles, self.d
+        dev = torch.device(device)
+        return dict(
+            reject=torch.empty(n, dtype=torch.int32, device=dev),
+            score_T=torch.empty((n, d), dtype=torch.int64, device=dev) if self.design.kind != CSE_ZTEST1 else None,
+            score_Z=torch.empty(n, dtype=torch.float64, device=dev) if self.design.kind == CSE_ZTEST1 else None,
+            grad=torch.empty((n, d), dtype=torch.float64, device=dev),
+        )
+
+    def simulate(self, seed=0, device="cuda"):
+        o = self._alloc(device)
+        cse_simulate(self.handle, seed, o["reject"], o["score_T"], o["score_Z"], o["grad"])
+        return o
+
+    def validate(self, seed=0, delta=0.01, device="cuda"):
+        o = self._alloc(device)
+        n = self.n_tiles
+        o["cp_upper"] = torch.empty(n, dtype=torch.float64, device=device)
+        o["tile_bound"] = torch.empty(n, dtype=torch.float64, device=device)
+        o["q_star"] = torch.empty(n, dtype=torch.float64, device=device)
+        cse_validate(self.handle, seed, delta, o["reject"], o["score_T"], o["score_Z"], o["grad"],
+                     o["cp_upper"], o["tile_bound"], o["q_star"])
+        return o
+
+    def calibrate(self, seed=0, alpha=0.025, delta=0.01, with_validation=True, device="cuda"):
+        n = self.n_tiles
+        o = self._alloc(device) if with_validation else {}
+        o.update(alpha_prime=torch.empty(n, dtype=torch.float64, device=device),
+                 k=torch.empty(n, dtype=torch.int32, device=device),
+                 lambda_tile=torch.empty(n, dtype=torch.float64, device=device),
+                 lambda_global=torch.empty(1, dtype=torch.float64, device=device),
+                 reject_at_lambda=torch.empty(n, dtype=torch.int32, device=device))
+        if with_validation:
+            o["cp_upper"] = torch.empty(n, dtype=torch.float64, device=device)
+            o["tile_bound"] = torch.empty(n, dtype=torch.float64, device=device)
+        cse_calibrate(self.handle, seed, alpha, o["alpha_prime"], o["k"], o["lambda_tile"], o["lambda_global"],
+                      o["reject_at_lambda"], delta, o.get("reject"), o.get("score_T"), o.get("score_Z"),
+                      o.get("grad"), o.get("cp_upper"), o.get("tile_bound"))
+        return o
+
+    def bound(self, mode, R=None, a=None, level=0.01, device="cuda"):
+        out = torch.empty(self.n_tiles, dtype=torch.float64, device=device)
+        q = torch.empty(self.n_tiles, dtype=torch.float64, device=device)
+        cse_bound(self.handle, mode, R, a, level, out, q)
+        return out, q
+
+
+class TIE(torch.autograd.Function):
+    """Type I Error of each box (rejection rate of the design's fixed rule) with its
+    score-function gradient, both from one simulation pass.
+
+    forward(theta [n_boxes, d] float64, radii, sims, kind, seed) -> R / N per box;
+    backward returns grad_out * (sum_rej T(x) - R grad A(theta)) / N.  Single-hypothesis
+    designs only (each box is one tile)."""
+
+    @staticmethod
+    def forward(ctx, theta, radii, sims, kind, seed):
+        th = theta.detach().to("cpu", torch.float64).numpy()
+        P = Platten.create(kind, th, np.asarray(radii, np.float64), np.asarray(sims, np.int32), keep_all=True)
+        try:
+            if P.n_tiles != th.shape[0]:
+                raise ValueError("TIE needs one tile per box (single-hypothesis design)")
+            o = P.simulate(seed, device=theta.device if theta.is_cuda else "cuda")
+            N = torch.as_tensor(np.asarray(sims, np.float64), device=o["reject"].device)
+            f = o["reject"].to(torch.float64) / N
+            g = o["grad"]
+            torch.cuda.current_stream().synchronize()
+        finally:
+            P.close()
+        ctx.save_for_backward(g.to(theta.device))
+        return f.to(theta.device)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout[:, None] * g, None, None, None, None

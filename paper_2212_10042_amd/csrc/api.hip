@@ -1,0 +1,364 @@
+// api.hip -- the extern "C" entry points of libcse.so (declared in include/cse.h).
+#include <math.h>
+
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "cse_internal.h"
+#include "kernels.h"
+
+struct cse_platten {
+    cse::Platten P;
+};
+
+namespace {
+
+using cse::set_error;
+
+#define CSE_LAUNCH(expr)                                                                   \
+    do {                                                                                   \
+        hipError_t _e = (expr);                                                            \
+        if (_e != hipSuccess) {                                                            \
+            set_error(std::string("launch failed: ") + hipGetErrorString(_e));             \
+            return CSE_EHIP;                                                               \
+        }                                                                                  \
+    } while (0)
+
+int check_handle(const cse_platten *h, const char *fn) {
+    if (!h) {
+        set_error(std::string(fn) + ": NULL platten");
+        return CSE_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != h->P.device) {
+        set_error(std::string(fn) + ": the current HIP device is not the platten's device");
+        return CSE_EINVAL;
+    }
+    return CSE_OK;
+}
+
+bool in_unit(double x) { return x > 0.0 && x < 1.0; }
+
+// ---- launch timing (cse_profile_*) ----
+struct ProfRec {
+    std::string name;
+    hipEvent_t a, b;
+};
+std::mutex g_prof_mu;
+bool g_prof_on = false;
+std::vector<ProfRec> g_pending;
+std::vector<hipEvent_t> g_pool;
+std::map<std::string, std::pair<int64_t, double>> g_totals;
+
+hipEvent_t pool_event() {
+    if (!g_pool.empty()) {
+        hipEvent_t e = g_pool.back();
+        g_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+struct Timed {
+    ProfRec rec{};
+    hipStream_t st;
+    bool on = false;
+    Timed(const char *name, hipStream_t s) : st(s) {
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (!g_prof_on) return;
+        rec.name = name;
+        rec.a = pool_event();
+        rec.b = pool_event();
+        if (!rec.a || !rec.b) return;
+        on = hipEventRecord(rec.a, st) == hipSuccess;
+    }
+    ~Timed() {
+        if (!on) return;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        if (hipEventRecord(rec.b, st) == hipSuccess) g_pending.push_back(rec);
+    }
+};
+
+void prof_collect() {
+    for (auto &r : g_pending) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto &t = g_totals[r.name];
+            t.first += 1;
+            t.second += ms;
+        }
+        g_pool.push_back(r.a);
+        g_pool.push_back(r.b);
+    }
+    g_pending.clear();
+}
+
+// Simulation with the design's fixed rule into the workspaces (R, score sums, optional keys).
+int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
+    CSE_LAUNCH(cse::launch_zero(P.d_Rw, P.n_tiles * sizeof(uint32_t), st));
+    if (P.family == cse::FAM_NORMAL) {
+        CSE_LAUNCH(cse::launch_zero(P.d_Zw, P.n_tiles * sizeof(unsigned long long), st));
+        Timed tm(keys ? "ztest1_calib" : "ztest1", st);
+        CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, keys ? (float *)P.d_keys : nullptr, st));
+    } else {
+        CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
+        Timed tm(keys ? "binom2_calib" : "binom2", st);
+        CSE_LAUNCH(cse::launch_binom2(P, seed, P.d_Rw, P.d_Tw, keys ? (uint16_t *)P.d_keys : nullptr, st));
+    }
+    return CSE_OK;
+}
+
+int ensure_keys(cse::Platten &P) {
+    const size_t esz = (P.family == cse::FAM_NORMAL) ? 4 : 2;
+    const size_t need = (size_t)P.n_keys * esz;
+    if (P.d_keys && P.keys_bytes >= need) return CSE_OK;
+    if (P.d_keys) {
+        (void)hipFree(P.d_keys);
+        P.d_keys = nullptr;
+    }
+    if (hipMalloc(&P.d_keys, need) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("cse_calibrate: cannot allocate the calibration key workspace");
+        return CSE_ENOMEM;
+    }
+    P.keys_bytes = need;
+    return CSE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *cse_last_error(void) { return cse::get_error(); }
+
+int cse_platten_create(const cse_design *design, int64_t n_boxes, const double *theta,
+                       const double *radii, const int32_t *sims, int32_t flags, cse_platten **out) {
+    if (!out) {
+        set_error("cse_platten_create: NULL out");
+        return CSE_EINVAL;
+    }
+    *out = nullptr;
+    cse_platten *h = new (std::nothrow) cse_platten();
+    if (!h) {
+        set_error("cse_platten_create: out of host memory");
+        return CSE_ENOMEM;
+    }
+    int e;
+    try {
+        e = cse::build_platten(design, n_boxes, theta, radii, sims, flags, &h->P);
+    } catch (const std::bad_alloc &) {
+        set_error("cse_platten_create: out of host memory");
+        e = CSE_ENOMEM;
+    } catch (...) {
+        set_error("cse_platten_create: unexpected host exception");
+        e = CSE_EINVAL;
+    }
+    if (e != CSE_OK) {
+        cse::free_platten(&h->P);
+        delete h;
+        return e;
+    }
+    *out = h;
+    return CSE_OK;
+}
+
+int cse_platten_destroy(cse_platten *p) {
+    if (!p) return CSE_OK;
+    cse::free_platten(&p->P);
+    delete p;
+    return CSE_OK;
+}
+
+int64_t cse_platten_size(const cse_platten *p) { return p ? p->P.n_tiles : -1; }
+
+int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32_t *n_vert,
+                         int32_t *in_null) {
+    if (!p) {
+        set_error("cse_platten_describe: NULL platten");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    for (int64_t t = 0; t < P.n_tiles; ++t) {
+        if (box) box[t] = P.tile_box[t];
+        if (cfg) cfg[t] = P.tile_cfg[t];
+        if (n_vert) n_vert[t] = P.tile_nv[t];
+        if (in_null) in_null[t] = P.tile_in_null[t];
+    }
+    return CSE_OK;
+}
+
+int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *score_T,
+                 double *score_Z, double *grad, void *stream) {
+    if (int e = check_handle(p, "cse_simulate")) return e;
+    if (!reject) {
+        set_error("cse_simulate: reject must not be NULL");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    hipStream_t st = (hipStream_t)stream;
+    if (int e = run_sim(P, seed, false, st)) return e;
+    CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
+    return CSE_OK;
+}
+
+int cse_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *reject,
+                 int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                 double *tile_bound, double *q_star, void *stream) {
+    if (int e = check_handle(p, "cse_validate")) return e;
+    if (!in_unit(delta)) {
+        set_error("cse_validate: delta must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    if (!tile_bound) {
+        set_error("cse_validate: tile_bound must not be NULL");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    hipStream_t st = (hipStream_t)stream;
+    if (int e = run_sim(P, seed, false, st)) return e;
+    CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
+    Timed tm("bound_validate", st);
+    CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tile_bound, q_star, nullptr, cp_upper, st));
+    return CSE_OK;
+}
+
+int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime,
+                  int32_t *k, double *lambda_tile, double *lambda_global,
+                  int32_t *reject_at_lambda, double delta, int32_t *reject, int64_t *score_T,
+                  double *score_Z, double *grad, double *cp_upper, double *tile_bound,
+                  void *stream) {
+    if (int e = check_handle(p, "cse_calibrate")) return e;
+    if (!in_unit(alpha)) {
+        set_error("cse_calibrate: alpha must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    const bool want_bound = cp_upper || tile_bound;
+    if (want_bound && !in_unit(delta)) {
+        set_error("cse_calibrate: delta must lie in (0, 1) when cp_upper or tile_bound is requested");
+        return CSE_EINVAL;
+    }
+    auto &P = const_cast<cse_platten *>(p)->P;
+    if (int e = ensure_keys(P)) return e;
+    hipStream_t st = (hipStream_t)stream;
+    double *ap = alpha_prime ? alpha_prime : P.d_apw;
+    int32_t *kk = k ? k : P.d_kw;
+    double *lam = lambda_tile ? lambda_tile : P.d_lamw;
+    // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
+    {
+        Timed tm("bound_invert", st);
+        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, st));
+    }
+    if (int e = run_sim(P, seed, true, st)) return e;
+    {
+        Timed tm("select", st);
+        CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));
+    }
+    CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
+    if (reject || score_T || score_Z || grad)
+        CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
+    if (want_bound) {
+        // alpha' lives in the caller's buffer or in d_apw, and is no longer read once k is
+        // known, so d_apw can hold the bound the caller did not ask for.
+        double *tb = tile_bound ? tile_bound : P.d_apw;
+        Timed tm("bound_validate", st);
+        CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tb, nullptr, nullptr, cp_upper, st));
+    }
+    return CSE_OK;
+}
+
+int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double *a,
+              double delta_or_alpha, double *out, double *q_star, void *stream) {
+    if (int e = check_handle(p, "cse_bound")) return e;
+    if (!out || mode < 0 || mode > 2) {
+        set_error("cse_bound: NULL out or mode outside {0, 1, 2}");
+        return CSE_EINVAL;
+    }
+    if (mode == 0 && !R) {
+        set_error("cse_bound: mode 0 needs R");
+        return CSE_EINVAL;
+    }
+    if (mode == 2 && !a) {
+        set_error("cse_bound: mode 2 needs a");
+        return CSE_EINVAL;
+    }
+    if (mode != 2 && !in_unit(delta_or_alpha)) {
+        set_error("cse_bound: delta/alpha must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    CSE_LAUNCH(cse::launch_bound(P, mode, (const uint32_t *)R, a, delta_or_alpha, out, q_star,
+                                 nullptr, nullptr, (hipStream_t)stream));
+    return CSE_OK;
+}
+
+int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begin, int64_t tile_end,
+                          int32_t *reject, void *stream) {
+    if (int e = check_handle(p, "cse_simulate_per_tile")) return e;
+    const auto &P = p->P;
+    if (!reject || tile_begin < 0 || tile_end > P.n_tiles || tile_begin > tile_end) {
+        set_error("cse_simulate_per_tile: bad tile range or NULL reject");
+        return CSE_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CSE_LAUNCH(cse::launch_zero(reject + tile_begin, (tile_end - tile_begin) * sizeof(int32_t), st));
+    for (int64_t t = tile_begin; t < tile_end; ++t) {
+        Timed tm("plain_tile", st);
+        uint32_t T0 = 0, T1 = 0;
+        if (P.family == cse::FAM_BINOM) {
+            T0 = P.tile_T[t * 2];
+            T1 = P.tile_T[t * 2 + 1];
+        }
+        CSE_LAUNCH(cse::launch_plain_tile(P, seed, t, T0, T1, (uint32_t *)(reject + t), st));
+    }
+    return CSE_OK;
+}
+
+int cse_platten_stats(const cse_platten *p, int64_t out[8]) {
+    if (!p || !out) {
+        set_error("cse_platten_stats: NULL argument");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    out[0] = P.n_tiles;
+    out[1] = P.n_blocks;
+    out[2] = P.n_items;
+    out[3] = P.n_keys;
+    out[4] = P.total_sims;
+    out[5] = (P.family == cse::FAM_NORMAL) ? cse::B1T : cse::B2U * cse::B2V;
+    out[6] = P.max_N;
+    out[7] = P.block_sims;
+    return CSE_OK;
+}
+
+int cse_profile_enable(int32_t on) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof_on = on != 0;
+    return CSE_OK;
+}
+
+int cse_profile_get(const char *name, int64_t *launches, double *total_ms) {
+    if (!name || !launches || !total_ms) {
+        set_error("cse_profile_get: NULL argument");
+        return CSE_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof_collect();
+    auto it = g_totals.find(name);
+    *launches = it == g_totals.end() ? 0 : it->second.first;
+    *total_ms = it == g_totals.end() ? 0.0 : it->second.second;
+    return CSE_OK;
+}
+
+int cse_profile_reset(void) {
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    prof_collect();
+    g_totals.clear();
+    return CSE_OK;
+}
+
+}  // extern "C"

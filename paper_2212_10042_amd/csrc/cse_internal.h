@@ -1,0 +1,124 @@
+// cse_internal.h -- data structures shared by the files of libcse.so (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "cse.h"
+
+namespace cse {
+
+constexpr int WAVE = 64;
+constexpr int WG = 256;              // 4 waves per workgroup
+constexpr int MAX_D = 4;
+constexpr int NP35 = 35;             // patients per arm of the binomial designs
+
+// ---- tile batches ("blocks"): each wave owns one block for a range of simulations ----
+// 2-arm designs: an 8 x 8 product of distinct arm-0 and arm-1 thresholds, so one
+// simulation's success counts at 16 thresholds serve 64 tiles (common random numbers).
+constexpr int B2U = 8, B2V = 8;
+struct Blk2 {
+    uint32_t T0[B2U];          // arm-0 Bernoulli thresholds (uint32, see platten.cpp)
+    uint32_t T1[B2V];          // arm-1 thresholds
+    int32_t tile[B2U * B2V];   // tile id of slot (u, v) = u * B2V + v, or -1
+    int32_t n_sims;            // simulations of every tile of this block
+    int32_t pad;
+    int64_t key_base;          // calibration keys of slot s live at key_base + s * n_sims + k
+};
+
+// z-test: 64 tiles share each simulation's normal draw.
+constexpr int B1T = 64;
+struct Blk1 {
+    float theta[B1T];
+    int32_t tile[B1T];
+    int32_t n_sims;
+    int32_t pad;
+    int64_t key_base;          // keys of slot s live at key_base + s * n_sims + k
+};
+
+// Work item: one wave simulates sims [k_begin, k_end) of block blk.
+struct WorkItem {
+    int32_t blk;
+    uint32_t k_begin;
+    uint32_t k_end;
+    int32_t pad;
+};
+
+// Family of the data model for the bound (Example 1 / Section 4.2).
+enum Family : int32_t { FAM_NORMAL = 1, FAM_BINOM = 2 };
+
+struct Platten {
+    cse_design design{};
+    int d = 0;              // parameter dimension
+    int p = 0;              // number of null hypotheses
+    int32_t family = 0;
+    int32_t n_per_arm = 0;
+    int64_t n_boxes = 0, n_tiles = 0;
+    int device = 0;
+
+    // host copies
+    std::vector<int64_t> tile_box;
+    std::vector<int32_t> tile_cfg, tile_nv, tile_in_null, tile_N;
+    std::vector<double> tile_theta;      // [n_tiles * d]
+    std::vector<int32_t> vert_off;       // [n_tiles + 1]
+    std::vector<double> verts;           // [total vertices * d] displacements from theta
+    int32_t max_N = 0;
+    int64_t total_sims = 0;              // sum of N over tiles
+    int64_t block_sims = 0;              // sum over batches of their N
+
+    // device copies (owned)
+    double *d_theta = nullptr;
+    int32_t *d_N = nullptr;
+    int32_t *d_vert_off = nullptr;
+    double *d_verts = nullptr;
+    int64_t *d_key_off = nullptr;        // [n_tiles] start of each tile's keys in d_keys
+    int64_t n_keys = 0;                  // key slots (sum over blocks of 64 * n_sims)
+    void *d_blocks = nullptr;
+    int64_t n_blocks = 0;
+    WorkItem *d_items = nullptr;
+    int64_t n_items = 0;
+
+    // design tables (device)
+    int32_t *d_cut_tbl = nullptr;        // 2-arm: c(y0) = min{y1 : z(y0, y1) > cut}, [n+1]
+    double *d_S_tbl = nullptr;           // 2-arm: S = -z per outcome y0*(n+1)+y1
+    int32_t *d_S_order = nullptr;        // 2-arm: outcomes sorted by S ascending
+    int32_t *d_S_group = nullptr;        // 2-arm: index of first outcome with equal S in that order
+    int32_t n_outcomes = 0;
+
+    std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
+
+    // per-tile workspaces (allocated with the platten)
+    uint32_t *d_Rw = nullptr;            // rejection counts
+    unsigned long long *d_Tw = nullptr;  // score sums T (binomial) [n_tiles * d]
+    unsigned long long *d_Zw = nullptr;  // score sums Z (z-test), fixed point 2^-32
+    double *d_apw = nullptr;             // alpha'
+    int32_t *d_kw = nullptr;             // k
+    double *d_lamw = nullptr;            // lambda*_i
+    double *d_lamg = nullptr;            // lambda* (1)
+
+    // calibration keys (allocated on first calibration): n_keys entries of 2 (outcome
+    // index) or 4 (float32 statistic) bytes
+    void *d_keys = nullptr;
+    size_t keys_bytes = 0;
+};
+
+// error reporting
+void set_error(const std::string &msg);
+const char *get_error();
+
+int build_platten(const cse_design *design, int64_t n_boxes, const double *theta,
+                  const double *radii, const int32_t *sims, int32_t flags, Platten *P);
+void free_platten(Platten *P);
+
+}  // namespace cse
+
+#define CSE_HIP_TRY(expr)                                                                   \
+    do {                                                                                    \
+        hipError_t _e = (expr);                                                             \
+        if (_e != hipSuccess) {                                                             \
+            ::cse::set_error(std::string(#expr " failed: ") + hipGetErrorString(_e));       \
+            return CSE_EHIP;                                                                \
+        }                                                                                   \
+    } while (0)

@@ -1,0 +1,241 @@
+// k_select.hip -- the calibrated threshold of each tile, lambda*_i = S_(k_i), the k_i-th
+// smallest statistic among the tile's N_i simulations (Section 6.1), the count of
+// simulations strictly below it, and lambda* = min_i lambda*_i (Section 6.3).
+// One workgroup per tile, counts in LDS.  Plus the small per-tile finishing kernels
+// (score gradient, fixed-point conversion, zero fill).
+#include <math.h>
+
+#include "cse_internal.h"
+#include "kernels.h"
+
+namespace cse {
+
+constexpr int SEL_WG = 256;
+constexpr int MAX_OUTCOMES = 4096;
+
+// Block-wide exclusive scan of one value per thread (SEL_WG threads), result in part[].
+__device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
+    const int tid = threadIdx.x;
+    part[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < SEL_WG; off <<= 1) {
+        const uint32_t add = (tid >= off) ? part[tid - off] : 0u;
+        __syncthreads();
+        part[tid] += add;
+        __syncthreads();
+    }
+    const uint32_t incl = part[tid];
+    __syncthreads();
+    part[tid] = incl - v;
+    __syncthreads();
+}
+
+// ---- discrete statistic (2-arm design): keys are outcome indices y0*(n+1)+y1 ----
+// The histogram of outcomes is permuted into ascending-S order (S_order, ties grouped by
+// S_group); the first position whose cumulative count reaches k holds lambda*.
+__global__ __launch_bounds__(SEL_WG) void k_select_outcomes(
+    const uint16_t *__restrict__ keys, const int64_t *__restrict__ key_off,
+    const int32_t *__restrict__ N, const int32_t *__restrict__ kk, const double *__restrict__ S_tbl,
+    const int32_t *__restrict__ S_order, const int32_t *__restrict__ S_group, int n_out,
+    double *__restrict__ lam, int32_t *__restrict__ rej_at) {
+    __shared__ uint32_t hist[MAX_OUTCOMES];
+    __shared__ uint32_t cumx[MAX_OUTCOMES];
+    __shared__ uint32_t part[SEL_WG];
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int j = tid; j < n_out; j += SEL_WG) hist[j] = 0u;
+    __syncthreads();
+    const int32_t n = N[t];
+    const uint16_t *__restrict__ kt = keys + key_off[t];
+    for (int j = tid; j < n; j += SEL_WG) atomicAdd(&hist[kt[j]], 1u);
+    __syncthreads();
+    const int per = (n_out + SEL_WG - 1) / SEL_WG;
+    const int p0 = tid * per, p1 = min(n_out, p0 + per);
+    uint32_t local = 0u;
+    for (int p = p0; p < p1; ++p) local += hist[S_order[p]];
+    block_exclusive_scan(local, part);
+    uint32_t run = part[tid];
+    for (int p = p0; p < p1; ++p) {
+        cumx[p] = run;
+        run += hist[S_order[p]];
+    }
+    __syncthreads();
+    const int32_t k = kk[t];
+    if (k <= 0) {
+        if (tid == 0) {
+            lam[t] = -INFINITY;
+            if (rej_at) rej_at[t] = 0;
+        }
+        return;
+    }
+    if (k > n) {
+        if (tid == 0) {
+            lam[t] = INFINITY;
+            if (rej_at) rej_at[t] = n;
+        }
+        return;
+    }
+    for (int p = p0; p < p1; ++p) {
+        const uint32_t c = hist[S_order[p]];
+        if (cumx[p] < (uint32_t)k && cumx[p] + c >= (uint32_t)k) {
+            lam[t] = S_tbl[S_order[p]];
+            if (rej_at) rej_at[t] = (int32_t)cumx[S_group[p]];
+        }
+    }
+}
+
+// ---- continuous statistic (float32 keys): three-pass radix selection (11/11/10 bits) ----
+__device__ __forceinline__ uint32_t f2ord(float f) {
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+__global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__ keys,
+                                                       const int64_t *__restrict__ key_off,
+                                                       const int32_t *__restrict__ N,
+                                                       const int32_t *__restrict__ kk,
+                                                       double *__restrict__ lam,
+                                                       int32_t *__restrict__ rej_at) {
+    constexpr int BINS = 2048;
+    __shared__ uint32_t hist[BINS];
+    __shared__ uint32_t part[SEL_WG];
+    __shared__ uint32_t s_bin, s_below;
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int32_t n = N[t];
+    const int32_t k = kk[t];
+    if (k <= 0 || k > n) {
+        if (tid == 0) {
+            lam[t] = k <= 0 ? -INFINITY : INFINITY;
+            if (rej_at) rej_at[t] = k <= 0 ? 0 : n;
+        }
+        return;
+    }
+    const float *__restrict__ kt = keys + key_off[t];
+    uint32_t prefix = 0u, below = 0u, need = (uint32_t)k;
+    const int shifts[3] = {21, 10, 0};
+    const int widths[3] = {11, 11, 10};
+    for (int pass = 0; pass < 3; ++pass) {
+        const int sh = shifts[pass], wd = widths[pass];
+        const uint32_t mask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + wd));
+        for (int j = tid; j < BINS; j += SEL_WG) hist[j] = 0u;
+        __syncthreads();
+        for (int j = tid; j < n; j += SEL_WG) {
+            const uint32_t u = f2ord(kt[j]);
+            if ((u & mask_hi) == prefix) atomicAdd(&hist[(u >> sh) & ((1u << wd) - 1u)], 1u);
+        }
+        __syncthreads();
+        const int nb = 1 << wd;
+        const int per = nb / SEL_WG;
+        uint32_t local = 0u;
+        for (int j = tid * per; j < (tid + 1) * per; ++j) local += hist[j];
+        block_exclusive_scan(local, part);
+        uint32_t run = part[tid];
+        for (int j = tid * per; j < (tid + 1) * per; ++j) {
+            if (run < need && run + hist[j] >= need) {
+                s_bin = (uint32_t)j;
+                s_below = run;
+            }
+            run += hist[j];
+        }
+        __syncthreads();
+        prefix |= s_bin << sh;
+        below += s_below;
+        need -= s_below;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        lam[t] = (double)ord2f(prefix);
+        if (rej_at) rej_at[t] = (int32_t)below;
+    }
+}
+
+// min over tiles of lambda*_i, one workgroup.
+__global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, int64_t n,
+                                              double *__restrict__ out) {
+    __shared__ double sm[1024];
+    double m = INFINITY;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmin(m, v[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// Score-function gradient (sum over rejections of T(x) - R grad A(theta)) / N, float64;
+// also the float64 score sums and int32 counts for the caller's buffers.
+__global__ void k_finish(int fam, int n, int d, int64_t n_tiles, const double *__restrict__ theta,
+                         const int32_t *__restrict__ N, const uint32_t *__restrict__ R,
+                         const unsigned long long *__restrict__ sumT,
+                         const unsigned long long *__restrict__ sumZfx, int32_t *__restrict__ R_out,
+                         int64_t *__restrict__ T_out, double *__restrict__ Z_out,
+                         double *__restrict__ grad) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const double r = (double)R[t];
+    const double inv = 1.0 / (double)N[t];
+    if (R_out) R_out[t] = (int32_t)R[t];
+    if (fam == FAM_NORMAL) {
+        const double z = (double)(long long)sumZfx[t] * (1.0 / 4294967296.0);
+        if (Z_out) Z_out[t] = z;
+        if (grad) grad[t] = z * inv;
+        return;
+    }
+    for (int a = 0; a < d; ++a) {
+        const unsigned long long s = sumT[t * d + a];
+        if (T_out) T_out[t * d + a] = (int64_t)s;
+        if (grad) {
+            const double th = theta[t * d + a];
+            const double p = 1.0 / (1.0 + exp(-th));
+            grad[t * d + a] = ((double)s - r * (double)n * p) * inv;
+        }
+    }
+}
+
+__global__ void k_zero(uint32_t *__restrict__ p, int64_t n_words) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_words) p[i] = 0u;
+}
+
+// ------------------------------------------------------------------------------ launchers
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
+    const int64_t words = (int64_t)((bytes + 3) / 4);
+    if (words == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, st, (uint32_t *)p,
+                       words);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
+                         hipStream_t st) {
+    if (P.design.kind == CSE_ZTEST1)
+        hipLaunchKernelGGL(k_select_f32, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
+                           (const float *)P.d_keys, P.d_key_off, P.d_N, k, lam, rej_at);
+    else
+        hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
+                           (const uint16_t *)P.d_keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
+                           P.d_S_group, P.n_outcomes, lam, rej_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, st, v, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const Platten &P, const uint32_t *R, const unsigned long long *sumT,
+                         const unsigned long long *sumZfx, int32_t *R_out, int64_t *T_out,
+                         double *Z_out, double *grad, hipStream_t st) {
+    const int64_t grid = (P.n_tiles + 255) / 256;
+    hipLaunchKernelGGL(k_finish, dim3((uint32_t)grid), dim3(256), 0, st, P.family, P.n_per_arm, P.d,
+                       P.n_tiles, P.d_theta, P.d_N, R, sumT, sumZfx, R_out, T_out, Z_out, grad);
+    return hipGetLastError();
+}
+
+}  // namespace cse

@@ -1,0 +1,334 @@
+// k_sim.hip -- fused Monte Carlo kernels for gfx950.
+//
+// One wave owns one tile batch for a range of simulations.  Per simulation (one per lane)
+// the Philox words are generated in registers, turned into draws, shared by every tile
+// of the batch (common random numbers, Section 6.3), and reduced into per-tile rejection
+// counts R and score sums (sufficient statistic over rejections, Example 1).  In
+// calibration mode each (simulation, tile) also stores its key: the outcome index
+// (2-arm design) or the statistic S in float32 (z-test).  Nothing else reaches memory.
+#include "cse_internal.h"
+#include "kernels.h"
+#include "philox.hpp"
+
+namespace cse {
+
+// Lanes of one wave exchange values through LDS between these two points.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------------------------
+// 2-arm binomial, n = 35 per arm, pooled z.  Words 0..34 are arm 0, 35..69 arm 1
+// (18 Philox blocks).  The batch is an 8 x 8 product of thresholds: the success counts
+// y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  Rejection at the
+// design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0; checked on the host).
+//
+// Per-lane accumulators are packed per tile: bits 0-5 rejections, 6-18 sum of y0 over
+// rejections, 19-31 sum of y1 over rejections; exact for up to 63 simulations per lane
+// between flushes.  A flush transposes the 64 x 64 (lane, tile) matrix through LDS so
+// lane t sums tile t's column into 32-bit totals; the final totals are added to global
+// memory with integer atomics (order-independent, hence deterministic).
+// ------------------------------------------------------------------------------------
+template <bool KEYS>
+__global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
+                                               const WorkItem *__restrict__ items, int64_t n_items,
+                                               uint32_t key0, uint32_t key1,
+                                               const int32_t *__restrict__ cut_tbl,
+                                               uint32_t *__restrict__ R,
+                                               unsigned long long *__restrict__ sumT,
+                                               uint16_t *__restrict__ keys) {
+    constexpr int NT = B2U * B2V;
+    constexpr int NW = 2 * NP35;
+    constexpr int NB = (NW + 3) / 4;
+    __shared__ uint32_t xbuf[WG / WAVE][NT][WAVE + 1];
+    __shared__ int32_t s_cut[64];
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (threadIdx.x < 64) s_cut[threadIdx.x] = threadIdx.x <= NP35 ? cut_tbl[threadIdx.x] : 64;
+    __syncthreads();
+    const int64_t it = (int64_t)blockIdx.x * (WG / WAVE) + wv;
+    if (it >= n_items) return;
+
+    const WorkItem W = items[it];
+    const Blk2 *__restrict__ B = blocks + W.blk;
+    uint32_t T0[B2U], T1[B2V];
+#pragma unroll
+    for (int u = 0; u < B2U; ++u) T0[u] = B->T0[u];
+#pragma unroll
+    for (int v = 0; v < B2V; ++v) T1[v] = B->T1[v];
+    const uint32_t n_sims = (uint32_t)B->n_sims;
+    const int64_t key_base = B->key_base;
+
+    uint32_t acc[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) acc[s] = 0u;
+    uint32_t totR = 0u, tot0 = 0u, tot1 = 0u;
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int s = 0; s < NT; ++s) xbuf[wv][s][lane] = acc[s];
+        wave_sync();
+        for (int l = 0; l < WAVE; ++l) {
+            const uint32_t x = xbuf[wv][lane][l];
+            totR += x & 63u;
+            tot0 += (x >> 6) & 8191u;
+            tot1 += x >> 19;
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NT; ++s) acc[s] = 0u;
+    };
+
+    int since = 0;
+    for (uint32_t k0 = W.k_begin; k0 < W.k_end; k0 += WAVE) {
+        const uint32_t k = k0 + (uint32_t)lane;
+        const bool act = k < W.k_end;
+        int y0[B2U], y1[B2V];
+#pragma unroll
+        for (int u = 0; u < B2U; ++u) y0[u] = 0;
+#pragma unroll
+        for (int v = 0; v < B2V; ++v) y1[v] = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int widx = 4 * b + l;
+                const uint32_t x = u32x4_get(w, l);
+                if (widx < NP35) {
+#pragma unroll
+                    for (int u = 0; u < B2U; ++u) y0[u] += (x < T0[u]) ? 1 : 0;
+                } else if (widx < NW) {
+#pragma unroll
+                    for (int v = 0; v < B2V; ++v) y1[v] += (x < T1[v]) ? 1 : 0;
+                }
+            }
+        }
+        int c[B2U];
+        uint32_t P0[B2U], P1[B2V];
+#pragma unroll
+        for (int u = 0; u < B2U; ++u) {
+            c[u] = act ? s_cut[y0[u]] : 64;
+            P0[u] = 1u | ((uint32_t)y0[u] << 6);
+        }
+#pragma unroll
+        for (int v = 0; v < B2V; ++v) P1[v] = (uint32_t)y1[v] << 19;
+#pragma unroll
+        for (int u = 0; u < B2U; ++u)
+#pragma unroll
+            for (int v = 0; v < B2V; ++v) acc[u * B2V + v] += (y1[v] >= c[u]) ? (P0[u] + P1[v]) : 0u;
+        if (KEYS) {
+#pragma unroll
+            for (int u = 0; u < B2U; ++u)
+#pragma unroll
+                for (int v = 0; v < B2V; ++v) {
+                    const int s = u * B2V + v;
+                    if (B->tile[s] >= 0 && act)
+                        keys[key_base + (int64_t)s * n_sims + k] = (uint16_t)(y0[u] * (NP35 + 1) + y1[v]);
+                }
+        }
+        if (++since == 63) {
+            flush();
+            since = 0;
+        }
+    }
+    flush();
+    const int32_t tile = B->tile[lane];
+    if (tile >= 0) {
+        atomicAdd(&R[tile], totR);
+        atomicAdd(&sumT[2 * (int64_t)tile], (unsigned long long)tot0);
+        atomicAdd(&sumT[2 * (int64_t)tile + 1], (unsigned long long)tot1);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// z-test: X = theta + Z, Z from words 0 and 1 by Box-Muller in float32,
+// u = ((word >> 9) + 1/2) 2^-23.  Reject X > cut; score term X - theta = Z; key S = -X.
+// Score sums are carried in 64-bit fixed point (2^-32) so the cross-wave sum is exact.
+// ------------------------------------------------------------------------------------
+__device__ __forceinline__ float unit23(uint32_t w) {
+    return ((float)(w >> 9) + 0.5f) * (1.0f / 8388608.0f);
+}
+
+template <bool KEYS>
+__global__ __launch_bounds__(WG) void k_ztest1(const Blk1 *__restrict__ blocks,
+                                               const WorkItem *__restrict__ items, int64_t n_items,
+                                               uint32_t key0, uint32_t key1, float cut,
+                                               uint32_t *__restrict__ R,
+                                               unsigned long long *__restrict__ sumZfx,
+                                               float *__restrict__ keys) {
+    constexpr int NT = B1T;
+    __shared__ uint32_t xbuf[WG / WAVE][NT][WAVE + 1];
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t it = (int64_t)blockIdx.x * (WG / WAVE) + wv;
+    if (it >= n_items) return;
+    const WorkItem W = items[it];
+    const Blk1 *__restrict__ B = blocks + W.blk;
+    const uint32_t n_sims = (uint32_t)B->n_sims;
+    const int64_t key_base = B->key_base;
+
+    uint32_t accR[NT];
+    float accZ[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        accR[s] = 0u;
+        accZ[s] = 0.0f;
+    }
+    uint32_t totR = 0u;
+    long long totZ = 0;
+
+    auto flush = [&]() {
+#pragma unroll
+        for (int s = 0; s < NT; ++s) xbuf[wv][s][lane] = accR[s];
+        wave_sync();
+        for (int l = 0; l < WAVE; ++l) totR += xbuf[wv][lane][l];
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NT; ++s) xbuf[wv][s][lane] = __float_as_uint(accZ[s]);
+        wave_sync();
+        for (int l = 0; l < WAVE; ++l)
+            totZ += (long long)__double2ll_rn((double)__uint_as_float(xbuf[wv][lane][l]) * 4294967296.0);
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            accR[s] = 0u;
+            accZ[s] = 0.0f;
+        }
+    };
+
+    int since = 0;
+    for (uint32_t k0 = W.k_begin; k0 < W.k_end; k0 += WAVE) {
+        const uint32_t k = k0 + (uint32_t)lane;
+        const bool act = k < W.k_end;
+        const u32x4 w = philox_block(0u, k, key0, key1);
+        const float u0 = unit23(w.x), u1 = unit23(w.y);
+        const float Z = sqrtf(-2.0f * logf(u0)) * cospif(2.0f * u1);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            const float X = B->theta[s] + Z;
+            const bool r = act && (X > cut);
+            accR[s] += r ? 1u : 0u;
+            accZ[s] += r ? Z : 0.0f;
+            if (KEYS && act && B->tile[s] >= 0) keys[key_base + (int64_t)s * n_sims + k] = -X;
+        }
+        if (++since == 16) {
+            flush();
+            since = 0;
+        }
+    }
+    flush();
+    const int32_t tile = B->tile[lane];
+    if (tile >= 0) {
+        atomicAdd(&R[tile], totR);
+        atomicAdd(&sumZfx[tile], (unsigned long long)totZ);
+    }
+}
+
+// ------------------------------------------------------------------------------------
+// The plain forward-only path: one launch per tile, one simulation per thread, the tile's
+// own thresholds, no sharing across tiles, rejection count only.
+// ------------------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_binom2_plain(uint32_t T0, uint32_t T1, uint32_t n_sims,
+                                                     uint32_t key0, uint32_t key1,
+                                                     const int32_t *__restrict__ cut_tbl,
+                                                     uint32_t *__restrict__ R_tile) {
+    constexpr int NW = 2 * NP35;
+    constexpr int NB = (NW + 3) / 4;
+    __shared__ uint32_t s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
+    const uint32_t k = blockIdx.x * WG + threadIdx.x;
+    uint32_t r = 0u;
+    if (k < n_sims) {
+        int y0 = 0, y1 = 0;
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int widx = 4 * b + l;
+                const uint32_t x = u32x4_get(w, l);
+                if (widx < NP35)
+                    y0 += (x < T0) ? 1 : 0;
+                else if (widx < NW)
+                    y1 += (x < T1) ? 1 : 0;
+            }
+        }
+        r = (y1 >= cut_tbl[y0]) ? 1u : 0u;
+    }
+    const unsigned long long m = __ballot(r);
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(R_tile, s_cnt);
+}
+
+__global__ __launch_bounds__(WG) void k_ztest1_plain(float theta, float cut, uint32_t n_sims,
+                                                     uint32_t key0, uint32_t key1,
+                                                     uint32_t *__restrict__ R_tile) {
+    __shared__ uint32_t s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
+    const uint32_t k = blockIdx.x * WG + threadIdx.x;
+    uint32_t r = 0u;
+    if (k < n_sims) {
+        const u32x4 w = philox_block(0u, k, key0, key1);
+        const float Z = sqrtf(-2.0f * logf(unit23(w.x))) * cospif(2.0f * unit23(w.y));
+        r = (theta + Z > cut) ? 1u : 0u;
+    }
+    const unsigned long long m = __ballot(r);
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(R_tile, s_cnt);
+}
+
+// ------------------------------------------------------------------------------ launchers
+hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
+                         uint16_t *keys, hipStream_t st) {
+    const int64_t grid = (P.n_items + (WG / WAVE) - 1) / (WG / WAVE);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (keys)
+        hipLaunchKernelGGL(k_binom2<true>, dim3((uint32_t)grid), dim3(WG), 0, st,
+                           (const Blk2 *)P.d_blocks, P.d_items, P.n_items, k0, k1, P.d_cut_tbl, R,
+                           sumT, keys);
+    else
+        hipLaunchKernelGGL(k_binom2<false>, dim3((uint32_t)grid), dim3(WG), 0, st,
+                           (const Blk2 *)P.d_blocks, P.d_items, P.n_items, k0, k1, P.d_cut_tbl, R,
+                           sumT, keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_ztest1(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumZfx,
+                         float *keys, hipStream_t st) {
+    const int64_t grid = (P.n_items + (WG / WAVE) - 1) / (WG / WAVE);
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const float cut = (float)P.design.cut;
+    if (keys)
+        hipLaunchKernelGGL(k_ztest1<true>, dim3((uint32_t)grid), dim3(WG), 0, st,
+                           (const Blk1 *)P.d_blocks, P.d_items, P.n_items, k0, k1, cut, R, sumZfx,
+                           keys);
+    else
+        hipLaunchKernelGGL(k_ztest1<false>, dim3((uint32_t)grid), dim3(WG), 0, st,
+                           (const Blk1 *)P.d_blocks, P.d_items, P.n_items, k0, k1, cut, R, sumZfx,
+                           keys);
+    return hipGetLastError();
+}
+
+hipError_t launch_plain_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t T0, uint32_t T1,
+                             uint32_t *R_tile, hipStream_t st) {
+    const uint32_t N = (uint32_t)P.tile_N[t];
+    const uint32_t grid = (N + WG - 1) / WG;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (P.design.kind == CSE_ZTEST1)
+        hipLaunchKernelGGL(k_ztest1_plain, dim3(grid), dim3(WG), 0, st, (float)P.tile_theta[t],
+                           (float)P.design.cut, N, k0, k1, R_tile);
+    else
+        hipLaunchKernelGGL(k_binom2_plain, dim3(grid), dim3(WG), 0, st, T0, T1, N, k0, k1,
+                           P.d_cut_tbl, R_tile);
+    return hipGetLastError();
+}
+
+}  // namespace cse

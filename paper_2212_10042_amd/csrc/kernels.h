@@ -1,0 +1,24 @@
+// kernels.h -- launchers of the device kernels (library-internal).
+#pragma once
+#include "cse_internal.h"
+
+namespace cse {
+
+hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
+                         uint16_t *keys, hipStream_t st);
+hipError_t launch_ztest1(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumZfx,
+                         float *keys, hipStream_t st);
+hipError_t launch_plain_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t T0, uint32_t T1,
+                             uint32_t *R_tile, hipStream_t st);
+hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const double *a_in,
+                        double level, double *out, double *q_out, int32_t *k_out, double *cp_out,
+                        hipStream_t st);
+hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
+                         hipStream_t st);
+hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st);
+hipError_t launch_finish(const Platten &P, const uint32_t *R, const unsigned long long *sumT,
+                         const unsigned long long *sumZfx, int32_t *R_out, int64_t *T_out,
+                         double *Z_out, double *grad, hipStream_t st);
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+
+}  // namespace cse

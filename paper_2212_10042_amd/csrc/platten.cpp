@@ -1,0 +1,476 @@
+// platten.cpp -- host side of the platten (Section 4, Definition 1): the null partition of
+// each box, the vertices of every tile (float64), the Bernoulli thresholds, the design
+// tables and the tile batches ("blocks") the kernels run.  Everything is uploaded once.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <map>
+#include <numeric>
+#include <tuple>
+
+#include "cse_internal.h"
+
+namespace cse {
+
+static thread_local std::string g_err;
+void set_error(const std::string &msg) { g_err = msg; }
+const char *get_error() { return g_err.c_str(); }
+
+namespace {
+
+// Bernoulli(expit theta) from one uniform 32-bit word u: success iff u < T,
+// T = round(2^32 / (1 + exp(-theta))), clamped to [0, 2^32 - 1].
+uint32_t bern_threshold(double theta) {
+    double p = 1.0 / (1.0 + exp(-theta));
+    double t = floor(p * 4294967296.0 + 0.5);
+    if (t < 0.0) t = 0.0;
+    if (t > 4294967295.0) t = 4294967295.0;
+    return (uint32_t)t;
+}
+
+// Pooled two-proportion z for y0 (control) and y1 (treatment) successes out of n each;
+// 0 when the pooled rate is 0 or 1.
+double pooled_z(int y0, int y1, int n) {
+    double pbar = (double)(y0 + y1) / (2.0 * n);
+    if (pbar <= 0.0 || pbar >= 1.0) return 0.0;
+    double se = sqrt(pbar * (1.0 - pbar) * 2.0 / n);
+    return ((double)y1 / n - (double)y0 / n) / se;
+}
+
+// Half-space g . x <= h.
+struct HalfSpace {
+    double g[MAX_D];
+    double h;
+};
+
+// Solve the d x d system A x = b by Gaussian elimination with partial pivoting.
+bool solve(int d, double A[MAX_D][MAX_D], double b[MAX_D], double x[MAX_D]) {
+    for (int c = 0; c < d; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < d; ++r)
+            if (fabs(A[r][c]) > fabs(A[piv][c])) piv = r;
+        if (fabs(A[piv][c]) < 1e-12) return false;
+        if (piv != c) {
+            for (int j = 0; j < d; ++j) std::swap(A[c][j], A[piv][j]);
+            std::swap(b[c], b[piv]);
+        }
+        for (int r = c + 1; r < d; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int j = c; j < d; ++j) A[r][j] -= f * A[c][j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = d - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < d; ++j) s -= A[r][j] * x[j];
+        x[r] = s / A[r][r];
+    }
+    return true;
+}
+
+// Vertices of the polytope {x : g_i . x <= h_i} (bounded by construction: it lies in a box).
+// Every vertex is the solution of d active constraints; enumerate all d-subsets.
+std::vector<std::vector<double>> enumerate_vertices(int d, const std::vector<HalfSpace> &H) {
+    std::vector<std::vector<double>> V;
+    const int m = (int)H.size();
+    std::vector<int> idx(d);
+    std::function<void(int, int)> rec = [&](int start, int depth) {
+        if (depth == d) {
+            double A[MAX_D][MAX_D], b[MAX_D], x[MAX_D];
+            for (int r = 0; r < d; ++r) {
+                for (int j = 0; j < d; ++j) A[r][j] = H[idx[r]].g[j];
+                b[r] = H[idx[r]].h;
+            }
+            if (!solve(d, A, b, x)) return;
+            for (int i = 0; i < m; ++i) {
+                double s = 0.0;
+                for (int j = 0; j < d; ++j) s += H[i].g[j] * x[j];
+                if (s > H[i].h + 1e-12 * (1.0 + fabs(H[i].h))) return;
+            }
+            for (auto &v : V) {
+                double dm = 0.0;
+                for (int j = 0; j < d; ++j) dm = std::max(dm, fabs(v[j] - x[j]));
+                if (dm <= 1e-12) return;
+            }
+            V.emplace_back(x, x + d);
+            return;
+        }
+        for (int i = start; i < m; ++i) {
+            idx[depth] = i;
+            rec(i + 1, depth + 1);
+        }
+    };
+    rec(0, 0);
+    return V;
+}
+
+template <class T>
+int upload(T **dst, const T *src, size_t n) {
+    if (n == 0) {
+        *dst = nullptr;
+        return CSE_OK;
+    }
+    CSE_HIP_TRY(hipMalloc((void **)dst, n * sizeof(T)));
+    CSE_HIP_TRY(hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice));
+    return CSE_OK;
+}
+
+}  // namespace
+
+int build_platten(const cse_design *design, int64_t n_boxes, const double *theta,
+                  const double *radii, const int32_t *sims, int32_t flags, Platten *P) {
+    if (!design || !theta || !radii || !sims || n_boxes < 1) {
+        set_error("cse_platten_create: NULL argument or n_boxes < 1");
+        return CSE_EINVAL;
+    }
+    if (design->reserved != 0) {
+        set_error("cse_platten_create: design.reserved must be 0");
+        return CSE_EINVAL;
+    }
+    const int kind = design->kind;
+    int d = 0, p = 0;
+    if (kind == CSE_ZTEST1) {
+        d = 1;
+        p = 1;
+        P->family = FAM_NORMAL;
+    } else if (kind == CSE_BINOM2_Z) {
+        d = 2;
+        p = 1;
+        P->family = FAM_BINOM;
+    } else if (kind == CSE_HIER4) {
+        set_error("cse_platten_create: CSE_HIER4 is not available in this build");
+        return CSE_EUNSUPPORTED;
+    } else {
+        set_error("cse_platten_create: unknown design kind");
+        return CSE_EINVAL;
+    }
+    if (design->n_arms != d) {
+        set_error("cse_platten_create: design.n_arms does not match the design kind");
+        return CSE_EINVAL;
+    }
+    if (P->family == FAM_BINOM && design->n_per_arm != NP35) {
+        set_error("cse_platten_create: binomial designs are built for n_per_arm = 35");
+        return CSE_EUNSUPPORTED;
+    }
+    if (!(fabs(design->cut) < 1e300)) {
+        set_error("cse_platten_create: design.cut must be finite");
+        return CSE_EINVAL;
+    }
+    const bool keep_all = (flags & CSE_PLATTEN_KEEP_ALL) != 0;
+    if (flags & ~CSE_PLATTEN_KEEP_ALL) {
+        set_error("cse_platten_create: unknown flag");
+        return CSE_EINVAL;
+    }
+    if (keep_all && p != 1) {
+        set_error("cse_platten_create: KEEP_ALL is defined for single-hypothesis designs");
+        return CSE_EINVAL;
+    }
+    for (int64_t i = 0; i < n_boxes; ++i) {
+        if (sims[i] < 1 || sims[i] > (1 << 24)) {
+            set_error("cse_platten_create: sims must lie in [1, 2^24]");
+            return CSE_EINVAL;
+        }
+        for (int j = 0; j < d; ++j) {
+            if (!(radii[i * d + j] > 0.0) || !(fabs(theta[i * d + j]) < 1e6)) {
+                set_error("cse_platten_create: radii must be > 0 and theta finite");
+                return CSE_EINVAL;
+            }
+        }
+    }
+    P->design = *design;
+    P->d = d;
+    P->p = p;
+    P->n_per_arm = design->n_per_arm;
+    P->n_boxes = n_boxes;
+    CSE_HIP_TRY(hipGetDevice(&P->device));
+
+    // Null hypotheses as half-spaces g . theta <= 0: z-test theta <= 0; multi-arm designs
+    // (arm 0 control) theta_i - theta_0 <= 0.
+    std::vector<HalfSpace> hyp(p);
+    for (int j = 0; j < p; ++j) {
+        HalfSpace hs{};
+        if (kind == CSE_ZTEST1) {
+            hs.g[0] = 1.0;
+        } else {
+            hs.g[j + 1] = 1.0;
+            hs.g[0] = -1.0;
+        }
+        hs.h = 0.0;
+        hyp[j] = hs;
+    }
+
+    // ---- the null partition of every box (Section 4) ----
+    const int ncorner = 1 << d;
+    for (int64_t i = 0; i < n_boxes; ++i) {
+        const double *c = theta + i * d;
+        const double *r = radii + i * d;
+        std::vector<std::vector<double>> corners(ncorner, std::vector<double>(d));
+        for (int m = 0; m < ncorner; ++m)
+            for (int j = 0; j < d; ++j) corners[m][j] = c[j] + (((m >> j) & 1) ? r[j] : -r[j]);
+        bool met = false;
+        for (int b = 1; b < (1 << p); ++b) {
+            std::vector<HalfSpace> cons;
+            for (int j = 0; j < p; ++j) {
+                HalfSpace hs = hyp[j];
+                if (!((b >> j) & 1)) {  // complement of H_j, closed: g . x >= h
+                    for (int a = 0; a < d; ++a) hs.g[a] = -hs.g[a];
+                    hs.h = -hs.h;
+                }
+                cons.push_back(hs);
+            }
+            bool empty = false, inside = true;
+            for (auto &hs : cons) {
+                double mn = 1e300, mx = -1e300;
+                for (auto &x : corners) {
+                    double s = -hs.h;
+                    for (int a = 0; a < d; ++a) s += hs.g[a] * x[a];
+                    mn = std::min(mn, s);
+                    mx = std::max(mx, s);
+                }
+                if (mn >= 0.0) empty = true;   // the constraint holds at most on a face
+                if (mx > 0.0) inside = false;
+            }
+            if (empty) continue;
+            std::vector<std::vector<double>> V;
+            if (inside) {
+                V = corners;
+            } else {
+                std::vector<HalfSpace> all;
+                for (int a = 0; a < d; ++a) {
+                    HalfSpace up{}, dn{};
+                    up.g[a] = 1.0;
+                    up.h = c[a] + r[a];
+                    dn.g[a] = -1.0;
+                    dn.h = -(c[a] - r[a]);
+                    all.push_back(up);
+                    all.push_back(dn);
+                }
+                for (auto &hs : cons) all.push_back(hs);
+                V = enumerate_vertices(d, all);
+                if ((int)V.size() < d + 1) continue;
+                // full dimension <=> the vertex centroid satisfies every constraint strictly
+                std::vector<double> cen(d, 0.0);
+                for (auto &v : V)
+                    for (int a = 0; a < d; ++a) cen[a] += v[a] / (double)V.size();
+                bool interior = true;
+                for (auto &hs : all) {
+                    double s = 0.0;
+                    for (int a = 0; a < d; ++a) s += hs.g[a] * cen[a];
+                    if (!(s < hs.h - 1e-12)) interior = false;
+                }
+                if (!interior) continue;
+            }
+            met = true;
+            P->tile_box.push_back(i);
+            P->tile_cfg.push_back(b);
+            P->tile_in_null.push_back(1);
+            P->tile_nv.push_back((int32_t)V.size());
+            P->vert_off.push_back((int32_t)(P->verts.size() / d));
+            for (auto &v : V)
+                for (int a = 0; a < d; ++a) P->verts.push_back(v[a] - c[a]);
+        }
+        if (!met && keep_all) {
+            P->tile_box.push_back(i);
+            P->tile_cfg.push_back(1);
+            P->tile_in_null.push_back(0);
+            P->tile_nv.push_back(ncorner);
+            P->vert_off.push_back((int32_t)(P->verts.size() / d));
+            for (auto &v : corners)
+                for (int a = 0; a < d; ++a) P->verts.push_back(v[a] - c[a]);
+        }
+    }
+    P->n_tiles = (int64_t)P->tile_box.size();
+    if (P->n_tiles == 0) {
+        set_error("cse_platten_create: no box meets the null hypothesis space");
+        return CSE_EINVAL;
+    }
+    P->vert_off.push_back((int32_t)(P->verts.size() / d));
+    P->tile_theta.resize(P->n_tiles * d);
+    P->tile_N.resize(P->n_tiles);
+    std::vector<int64_t> key_off(P->n_tiles, -1);
+    for (int64_t t = 0; t < P->n_tiles; ++t) {
+        for (int a = 0; a < d; ++a) P->tile_theta[t * d + a] = theta[P->tile_box[t] * d + a];
+        P->tile_N[t] = sims[P->tile_box[t]];
+        P->max_N = std::max(P->max_N, P->tile_N[t]);
+        P->total_sims += P->tile_N[t];
+        if (P->tile_nv[t] > 64) {
+            set_error("cse_platten_create: a tile has more than 64 vertices");
+            return CSE_EUNSUPPORTED;
+        }
+    }
+    if (P->family == FAM_BINOM) {
+        P->tile_T.resize(P->n_tiles * d);
+        for (int64_t t = 0; t < P->n_tiles * d; ++t) P->tile_T[t] = bern_threshold(P->tile_theta[t]);
+    }
+
+    // ---- tile batches ----
+    std::vector<int64_t> blk_sims;   // n_sims per block, for the work items
+    if (kind == CSE_ZTEST1) {
+        std::map<int32_t, std::vector<int64_t>> byN;
+        for (int64_t t = 0; t < P->n_tiles; ++t) byN[P->tile_N[t]].push_back(t);
+        std::vector<Blk1> blks;
+        for (auto &kv : byN) {
+            auto &ts = kv.second;
+            for (size_t s = 0; s < ts.size(); s += B1T) {
+                Blk1 B{};
+                for (int j = 0; j < B1T; ++j) {
+                    B.tile[j] = -1;
+                    B.theta[j] = 0.0f;
+                }
+                for (size_t j = 0; j < B1T && s + j < ts.size(); ++j) {
+                    B.tile[j] = (int32_t)ts[s + j];
+                    B.theta[j] = (float)P->tile_theta[ts[s + j]];
+                }
+                B.n_sims = kv.first;
+                blks.push_back(B);
+            }
+        }
+        P->n_blocks = (int64_t)blks.size();
+        for (auto &B : blks) {
+            blk_sims.push_back(B.n_sims);
+            B.key_base = P->n_keys;
+            for (int j = 0; j < B1T; ++j)
+                if (B.tile[j] >= 0) key_off[B.tile[j]] = B.key_base + (int64_t)j * B.n_sims;
+            P->n_keys += (int64_t)B1T * B.n_sims;
+        }
+        if (int e = upload((Blk1 **)&P->d_blocks, blks.data(), blks.size())) return e;
+    } else {
+        // distinct arm values -> integer coordinates; 8 x 8 coordinate blocks per N class
+        std::vector<double> u0, u1;
+        for (int64_t t = 0; t < P->n_tiles; ++t) {
+            u0.push_back(P->tile_theta[t * 2 + 0]);
+            u1.push_back(P->tile_theta[t * 2 + 1]);
+        }
+        std::sort(u0.begin(), u0.end());
+        u0.erase(std::unique(u0.begin(), u0.end()), u0.end());
+        std::sort(u1.begin(), u1.end());
+        u1.erase(std::unique(u1.begin(), u1.end()), u1.end());
+        std::map<std::tuple<int32_t, int64_t, int64_t>, std::vector<Blk2>> blkmap;
+        for (int64_t t = 0; t < P->n_tiles; ++t) {
+            int64_t c0 = std::lower_bound(u0.begin(), u0.end(), P->tile_theta[t * 2]) - u0.begin();
+            int64_t c1 = std::lower_bound(u1.begin(), u1.end(), P->tile_theta[t * 2 + 1]) - u1.begin();
+            auto key = std::make_tuple(P->tile_N[t], c0 / B2U, c1 / B2V);
+            auto &vec = blkmap[key];
+            int slot = (int)(c0 % B2U) * B2V + (int)(c1 % B2V);
+            Blk2 *B = nullptr;
+            for (auto &b : vec)
+                if (b.tile[slot] < 0) {
+                    B = &b;
+                    break;
+                }
+            if (!B) {
+                Blk2 nb{};
+                for (int j = 0; j < B2U * B2V; ++j) nb.tile[j] = -1;
+                int64_t b0 = (c0 / B2U) * B2U, b1 = (c1 / B2V) * B2V;
+                for (int u = 0; u < B2U; ++u)
+                    nb.T0[u] = (b0 + u < (int64_t)u0.size()) ? bern_threshold(u0[b0 + u]) : 0u;
+                for (int v = 0; v < B2V; ++v)
+                    nb.T1[v] = (b1 + v < (int64_t)u1.size()) ? bern_threshold(u1[b1 + v]) : 0u;
+                nb.n_sims = P->tile_N[t];
+                vec.push_back(nb);
+                B = &vec.back();
+            }
+            B->tile[slot] = (int32_t)t;
+        }
+        std::vector<Blk2> blks;
+        for (auto &kv : blkmap)
+            for (auto &b : kv.second) blks.push_back(b);
+        P->n_blocks = (int64_t)blks.size();
+        for (auto &B : blks) {
+            blk_sims.push_back(B.n_sims);
+            B.key_base = P->n_keys;
+            for (int j = 0; j < B2U * B2V; ++j)
+                if (B.tile[j] >= 0) key_off[B.tile[j]] = B.key_base + (int64_t)j * B.n_sims;
+            P->n_keys += (int64_t)(B2U * B2V) * B.n_sims;
+        }
+        if (int e = upload((Blk2 **)&P->d_blocks, blks.data(), blks.size())) return e;
+
+        // design tables of the pooled z test
+        const int n = P->n_per_arm, n1 = n + 1;
+        P->n_outcomes = n1 * n1;
+        std::vector<int32_t> cut(n1);
+        std::vector<double> S(n1 * n1);
+        for (int y0 = 0; y0 <= n; ++y0) {
+            cut[y0] = n1;   // no y1 rejects
+            for (int y1 = 0; y1 <= n; ++y1) {
+                double z = pooled_z(y0, y1, n);
+                S[y0 * n1 + y1] = -z;
+                if (z > design->cut && cut[y0] == n1) cut[y0] = y1;
+            }
+            // the kernels use {y1 >= c(y0)}: this needs z increasing in y1 for fixed y0
+            for (int y1 = 0; y1 <= n; ++y1)
+                if ((pooled_z(y0, y1, n) > design->cut) != (y1 >= cut[y0])) {
+                    set_error("internal: pooled z rejection region is not monotone in y1");
+                    return CSE_EUNSUPPORTED;
+                }
+        }
+        std::vector<int32_t> order(n1 * n1), group(n1 * n1);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return S[a] < S[b]; });
+        for (int j = 0; j < n1 * n1; ++j)
+            group[j] = (j > 0 && S[order[j]] == S[order[j - 1]]) ? group[j - 1] : j;
+        if (int e = upload(&P->d_cut_tbl, cut.data(), cut.size())) return e;
+        if (int e = upload(&P->d_S_tbl, S.data(), S.size())) return e;
+        if (int e = upload(&P->d_S_order, order.data(), order.size())) return e;
+        if (int e = upload(&P->d_S_group, group.data(), group.size())) return e;
+    }
+
+    for (int64_t t = 0; t < P->n_tiles; ++t)
+        if (key_off[t] < 0) {
+            set_error("internal: a tile was not placed in any batch");
+            return CSE_EINVAL;
+        }
+
+    // ---- work items: split each block's simulations so the grid has enough waves ----
+    {
+        const int64_t target = 16384;   // waves: several per SIMD on 256 CUs x 4 SIMDs
+        std::vector<WorkItem> items;
+        int64_t slices = std::max<int64_t>(1, (target + P->n_blocks - 1) / P->n_blocks);
+        for (int64_t b = 0; b < P->n_blocks; ++b) {
+            int64_t N = blk_sims[b];
+            P->block_sims += N;
+            int64_t chunks = (N + WAVE - 1) / WAVE;
+            int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
+            for (int64_t k0 = 0; k0 < N; k0 += per) {
+                WorkItem w{};
+                w.blk = (int32_t)b;
+                w.k_begin = (uint32_t)k0;
+                w.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
+                items.push_back(w);
+            }
+        }
+        P->n_items = (int64_t)items.size();
+        if (int e = upload(&P->d_items, items.data(), items.size())) return e;
+    }
+
+    if (int e = upload(&P->d_theta, P->tile_theta.data(), P->tile_theta.size())) return e;
+    if (int e = upload(&P->d_N, P->tile_N.data(), P->tile_N.size())) return e;
+    if (int e = upload(&P->d_vert_off, P->vert_off.data(), P->vert_off.size())) return e;
+    if (int e = upload(&P->d_verts, P->verts.data(), P->verts.size())) return e;
+    if (int e = upload(&P->d_key_off, key_off.data(), key_off.size())) return e;
+    const size_t nt = (size_t)P->n_tiles;
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_Rw, nt * sizeof(uint32_t)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_Tw, nt * d * sizeof(unsigned long long)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_Zw, nt * sizeof(unsigned long long)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_apw, nt * sizeof(double)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
+    return CSE_OK;
+}
+
+void free_platten(Platten *P) {
+    if (!P) return;
+    (void)hipDeviceSynchronize();
+    void *ptrs[] = {P->d_theta, P->d_N,    P->d_vert_off, P->d_verts,   P->d_key_off,
+                    P->d_blocks, P->d_items, P->d_cut_tbl, P->d_S_tbl,  P->d_S_order,
+                    P->d_S_group, P->d_keys, P->d_Rw,      P->d_Tw,     P->d_Zw,
+                    P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+}
+
+}  // namespace cse

@@ -1,0 +1,180 @@
+"""GPU parity: 2-arm binomial design (pooled z, n = 35) through the C ABI vs the CPU oracle.
+
+Bar: integers (rejections, score sums, k, counts below lambda*) bit-exact; lambda*_i exact
+(the statistic table is float64 on both sides); float64 bounds within 1e-9 relative
+(different optimiser round-off on the same golden-section search).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2212_10042_amd as cse
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+RTOL_BOUND = 1e-9
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _tiles_match(P, subs):
+    got = list(zip(P.tiles["box"].tolist(), P.tiles["cfg"].tolist()))
+    want = [(int(s[0]), int(s[1])) for s in subs]
+    assert got == want
+    assert np.array_equal(P.tiles["n_vert"], [len(s[2]) for s in subs])
+
+
+def _check_k(k_gpu, k_orc, ap_orc, N):
+    frac = (N + 1.0) * ap_orc
+    near = np.abs(frac - np.round(frac)) < 1e-7
+    assert np.all((k_gpu == k_orc) | near)
+
+
+def _full_compare(w, seed, keep_all=False):
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    print(f"[binom2] compare {w['name']} seed={seed} tiles={th.shape[0]}", flush=True)
+    P = cse.Platten.create("binom2", th, rd, sm, keep_all=keep_all)
+    ov = O.validate("binom2", th, rd, sm, seed, w["delta"], keep_all=keep_all)
+    oc = O.calibrate("binom2", th, rd, sm, seed, w["alpha"], keep_all=keep_all)
+    _tiles_match(P, ov["subs"])
+    g = P.calibrate(seed, alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    box = ov["box"]
+    assert np.array_equal(_np(g["reject"]), ov["R"])
+    assert np.array_equal(_np(g["score_T"]), ov["score_box"][box])
+    gr = O.score_gradient("binom2", th[box], ov["R"], ov["score_box"][box], ov["N"])
+    np.testing.assert_allclose(_np(g["grad"]), gr, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(_np(g["cp_upper"]), ov["cp"], rtol=RTOL_BOUND)
+    np.testing.assert_allclose(_np(g["tile_bound"]), ov["bound"], rtol=RTOL_BOUND)
+    np.testing.assert_allclose(_np(g["alpha_prime"]), oc["alpha_prime"], rtol=RTOL_BOUND)
+    _check_k(_np(g["k"]), oc["k"], oc["alpha_prime"], oc["N"])
+    same_k = _np(g["k"]) == oc["k"]
+    assert np.array_equal(_np(g["lambda_tile"])[same_k], oc["lam"][same_k])
+    assert np.array_equal(_np(g["reject_at_lambda"])[same_k], oc["reject_at_lam"][same_k])
+    assert float(_np(g["lambda_global"])[0]) == oc["lam_global"]
+    # validate entry point agrees with the calibrate pass
+    v = P.validate(seed, delta=w["delta"])
+    torch.cuda.synchronize()
+    assert np.array_equal(_np(v["reject"]), ov["R"])
+    np.testing.assert_allclose(_np(v["tile_bound"]), ov["bound"], rtol=RTOL_BOUND)
+    P.close()
+
+
+def test_small_lower_triangle_ragged():
+    # 20 x 20 boxes: 8x8 tile batches with ragged edges; 1000 sims: ragged last wave chunk
+    _full_compare(W.binom2_grid(20, 1000, seed=3), seed=3)
+
+
+def test_keep_all_square_uneven_sims():
+    w = W.binom2_grid(12, 300, lower_triangle=False, seed=5)
+    w["sims"] = W.uneven_sims(w["theta"].shape[0], seed=1, lo_pow=5, n_classes=4)  # 32..256
+    _full_compare(w, seed=5, keep_all=True)
+
+
+def test_edge_single_tile_and_one_sim():
+    for sims in (1, 63, 64, 65):
+        w = dict(name=f"single{sims}", theta=np.array([[0.25, -0.5]]), radii=np.array([[0.125, 0.125]]),
+                 sims=np.array([sims], np.int32), delta=0.01, alpha=0.3)
+        _full_compare(w, seed=11)
+
+
+def test_edge_extreme_logits():
+    # thresholds clamp at 0 and 2^32-1 in the corners of a wide grid
+    w = W.binom2_grid(16, 200, lo=-40.0, hi=40.0, seed=2)
+    _full_compare(w, seed=2)
+
+
+def test_full_size_workload_sampled_tiles():
+    """256x256 lower-triangle grid, 8,192 sims (the benchmark's launch), oracle on sampled tiles."""
+    w = W.binom2_256_tri()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("binom2", th, rd, sm)
+    g = P.calibrate(w["seed"], alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    n = th.shape[0]
+    rng = np.random.default_rng(0)
+    diag = np.flatnonzero(th[:, 0] == th[:, 1])
+    idx = np.unique(np.concatenate([[0, n - 1], diag[[0, 100, 255]], rng.choice(n, 40, replace=False)]))
+    print(f"[binom2] full-size sampled tiles: {idx.size}", flush=True)
+    sub = W.subsample(w, idx)
+    oc = O.calibrate("binom2", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["alpha"])
+    ov = O.validate("binom2", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["delta"])
+    # every box of this workload has exactly one tile, in box order
+    assert P.n_tiles == n and np.array_equal(P.tiles["box"], np.arange(n))
+    assert np.array_equal(_np(g["reject"])[idx], ov["R"])
+    assert np.array_equal(_np(g["score_T"])[idx], ov["score_box"])
+    np.testing.assert_allclose(_np(g["tile_bound"])[idx], ov["bound"], rtol=RTOL_BOUND)
+    np.testing.assert_allclose(_np(g["alpha_prime"])[idx], oc["alpha_prime"], rtol=RTOL_BOUND)
+    _check_k(_np(g["k"])[idx], oc["k"], oc["alpha_prime"], oc["N"])
+    same = _np(g["k"])[idx] == oc["k"]
+    assert np.array_equal(_np(g["lambda_tile"])[idx][same], oc["lam"][same])
+    assert np.array_equal(_np(g["reject_at_lambda"])[idx][same], oc["reject_at_lam"][same])
+    # properties at every tile: lambda* is the global min; counts below it are < k <= N
+    lam = _np(g["lambda_tile"])
+    assert float(_np(g["lambda_global"])[0]) == lam.min()
+    assert np.all(_np(g["reject_at_lambda"]) < _np(g["k"]))
+    assert np.all((_np(g["tile_bound"]) >= _np(g["cp_upper"])) & (_np(g["tile_bound"]) <= 1.0))
+    P.close()
+
+
+def test_per_tile_path_and_determinism():
+    w = W.binom2_grid(24, 700, seed=9)
+    P = cse.Platten.create("binom2", w["theta"], w["radii"], w["sims"])
+    a = P.simulate(9)
+    b = P.simulate(9)
+    plain = torch.empty(P.n_tiles, dtype=torch.int32, device="cuda")
+    cse.cse_simulate_per_tile(P.handle, 9, 0, P.n_tiles, plain)
+    torch.cuda.synchronize()
+    assert torch.equal(a["reject"], b["reject"]) and torch.equal(a["score_T"], b["score_T"])
+    assert torch.equal(a["reject"], plain)
+    c1 = P.calibrate(9)
+    c2 = P.calibrate(9)
+    torch.cuda.synchronize()
+    for key in ("lambda_tile", "reject_at_lambda", "k", "reject", "score_T"):
+        assert torch.equal(c1[key], c2[key])
+    P.close()
+
+
+def test_tie_autograd_matches_score_and_exact_gradient():
+    w = W.binom2_grid(8, 20000, lo=-1.0, hi=1.0, lower_triangle=False, seed=0)
+    th = torch.tensor(w["theta"], dtype=torch.float64, device="cuda", requires_grad=True)
+    f = cse.TIE.apply(th, w["radii"], w["sims"], "binom2", 0)
+    f.sum().backward()
+    R, sT, _ = O.sim_binom2(w["theta"], w["sims"], 0)
+    assert np.array_equal(np.round(_np(f) * w["sims"]).astype(np.int64), R)
+    g_orc = O.score_gradient("binom2", w["theta"], R, sT, w["sims"])
+    np.testing.assert_allclose(_np(th.grad), g_orc, rtol=1e-12, atol=1e-15)
+
+
+def test_score_gradient_vs_central_differences_crn():
+    """Central differences under common random numbers (h = 1e-3) against the score
+    estimate; tolerance from the per-simulation spread of the score terms."""
+    N = 16384
+    pts = np.array([[0.0, 0.0], [-0.5, -0.75], [0.25, -1.0]])
+    h = 1e-3
+    rows = [pts]
+    for a in range(2):
+        for sgn in (1, -1):
+            q = pts.copy()
+            q[:, a] += sgn * h
+            rows.append(q)
+    allp = np.concatenate(rows)
+    sims = np.full(allp.shape[0], N, np.int32)
+    th = torch.tensor(allp, dtype=torch.float64, device="cuda", requires_grad=True)
+    f = cse.TIE.apply(th, np.full_like(allp, 1e-3), sims, "binom2", 7)
+    f.sum().backward()
+    f = _np(f)
+    g = _np(th.grad)[: pts.shape[0]]
+    m = pts.shape[0]
+    for a in range(2):
+        fd = (f[m * (1 + 2 * a): m * (2 + 2 * a)] - f[m * (2 + 2 * a): m * (3 + 2 * a)]) / (2 * h)
+        # score terms are bounded by 35 in magnitude; FD noise under CRN is ~ sqrt(#flips)/(N 2h)
+        flips = np.abs(fd) * N * 2 * h + 1.0
+        tol = 5 * (35 / math.sqrt(N)) + 5 * np.sqrt(flips) / (N * 2 * h)
+        assert np.all(np.abs(fd - g[:, a]) <= tol)
