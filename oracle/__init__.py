@@ -58,11 +58,11 @@ def lib():
         L.orc_ztest1.argtypes = [i64, P, P, u64, dbl, P, P, P, i64]
         L.orc_binom2.argtypes = [i64, P, P, u64, ctypes.c_int, dbl, P, P, P, i64]
         L.orc_arm_counts.argtypes = [ctypes.c_int, P, i32, u64, ctypes.c_int, P]
-        if hasattr(L, "orc_hier4_posterior"):
-            L.orc_hier4_posterior.argtypes = [P, P, P]
-            L.orc_hier4_posterior_nodes.argtypes = [ctypes.c_int, dbl, dbl]
-            L.orc_hier4_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, dbl, P, P, P, i64, P]
-            L.orc_hier4_table.argtypes = [ctypes.c_int, P, i64, i64, P]
+        L.orc_hier4_posterior.argtypes = [P, ctypes.c_int, P]
+        L.orc_hier4_posterior_full.argtypes = [P, ctypes.c_int, P, P, P, P]
+        L.orc_hier4_node.argtypes = [ctypes.c_int, P, P]
+        L.orc_hier4_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, dbl, P, P, P, i64, P]
+        L.orc_hier4_table.argtypes = [ctypes.c_int, P, i64, P]
         _lib = L
     return _lib
 

@@ -1,0 +1,264 @@
+/*
+ * CPU ORACLE -- test infrastructure only (see oracle_sim.c for the conventions).
+ *
+ * Four Bernoulli arms (arm 0 control), n patients each, hierarchical model of the
+ * Bayesian basket case study (Section 10.1):
+ *     theta_i | mu, s2 ~ N(mu, s2),  mu ~ N(-1.34, 100),  s2 ~ InvGamma(0.0005, 0.000005),
+ *     y_i ~ Binom(n, expit(theta_i)).
+ * The statistic of treatment arm i is P(p_i > p_0 | y) = P(theta_i > theta_0 | y).
+ *
+ * The paper gives the model but not how its posterior is computed.  Reading used here:
+ *   1. mu is integrated out exactly: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T.
+ *   2. For each of 90 nodes s2_j (equally spaced in log s2 over [log 1e-6, log 1e3]), the
+ *      conditional posterior of theta is replaced by its Laplace (Gaussian) approximation:
+ *      mode by Newton's method, covariance C_j = (-H)^{-1} at the mode.
+ *   3. Node weights: Laplace evidence  l(mode) + log|Q| / 2 - log|-H| / 2  (Q = Sigma^{-1}),
+ *      plus the log prior density of s2_j, plus the log trapezoid weight in log s2
+ *      (ds2 = s2 dlog s2); normalised by log-sum-exp in float64.
+ *   4. P_i(y) = sum_j pi_j Phi((mode_i - mode_0) / sqrt(C_ii + C_00 - 2 C_i0)).
+ * Property of this reading: at the boundary counts y_i in {0, n} the Gaussian replacing the
+ * skewed conditional posterior is very wide, so P_i is not monotone there (it is monotone
+ * for interior counts).
+ * All float64, generic 4x4 linear algebra (Gaussian elimination), no structure exploited.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#define D 4
+#define NODES 90
+
+static const double M0 = -1.34, TAU2 = 100.0;
+static const double IG_A = 0.0005, IG_B = 0.000005;
+static const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137; /* log 1e-6, log 1e3 */
+
+uint32_t orc_bern_threshold(double theta);
+uint32_t orc_word(uint64_t seed, uint32_t sim, uint32_t w);
+
+static double softplus(double x) { return x > 0 ? x + log1p(exp(-x)) : log1p(exp(x)); }
+static double expit(double x) { return 1.0 / (1.0 + exp(-x)); }
+
+/* Solve A x = b (A is overwritten) by Gaussian elimination with partial pivoting. */
+static void solve4(double A[D][D], double b[D], double x[D]) {
+    for (int c = 0; c < D; ++c) {
+        int p = c;
+        for (int r = c + 1; r < D; ++r)
+            if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (p != c) {
+            for (int j = 0; j < D; ++j) { double t = A[c][j]; A[c][j] = A[p][j]; A[p][j] = t; }
+            double t = b[c]; b[c] = b[p]; b[p] = t;
+        }
+        for (int r = c + 1; r < D; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int j = c; j < D; ++j) A[r][j] -= f * A[c][j];
+            b[r] -= f * b[c];
+        }
+    }
+    for (int r = D - 1; r >= 0; --r) {
+        double s = b[r];
+        for (int j = r + 1; j < D; ++j) s -= A[r][j] * x[j];
+        x[r] = s / A[r][r];
+    }
+}
+
+/* log det of a symmetric positive definite matrix by elimination (product of pivots). */
+static double logdet4(const double M[D][D]) {
+    double A[D][D];
+    memcpy(A, M, sizeof A);
+    double ld = 0.0;
+    for (int c = 0; c < D; ++c) {
+        int p = c;
+        for (int r = c + 1; r < D; ++r)
+            if (fabs(A[r][c]) > fabs(A[p][c])) p = r;
+        if (p != c)
+            for (int j = 0; j < D; ++j) { double t = A[c][j]; A[c][j] = A[p][j]; A[p][j] = t; }
+        ld += log(fabs(A[c][c]));
+        for (int r = c + 1; r < D; ++r) {
+            double f = A[r][c] / A[c][c];
+            for (int j = c; j < D; ++j) A[r][j] -= f * A[c][j];
+        }
+    }
+    return ld;
+}
+
+static void inverse4(const double M[D][D], double Inv[D][D]) {
+    for (int k = 0; k < D; ++k) {
+        double A[D][D], e[D] = {0}, x[D];
+        memcpy(A, M, sizeof A);
+        e[k] = 1.0;
+        solve4(A, e, x);
+        for (int r = 0; r < D; ++r) Inv[r][k] = x[r];
+    }
+}
+
+static double Phi(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+/* Node j: log s2 value and trapezoid weight (in log s2). */
+void orc_hier4_node(int j, double *ls2, double *logw) {
+    double h = (LS2_HI - LS2_LO) / (NODES - 1);
+    *ls2 = LS2_LO + h * j;
+    double w = (j == 0 || j == NODES - 1) ? 0.5 * h : h;
+    *logw = log(w) + *ls2;   /* ds2 = s2 dlog s2 */
+}
+
+/* Posterior of one outcome y (counts out of n per arm).  Outputs P[3] = P(theta_i > theta_0 | y)
+ * for i = 1, 2, 3; if diag != NULL also per-node mode [NODES][D], log weight [NODES] and
+ * Newton iterations [NODES] (for the tests). */
+void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_mode,
+                              double *diag_logw, int32_t *diag_iters) {
+    double lw[NODES], pr[NODES][3];
+    for (int j = 0; j < NODES; ++j) {
+        double ls2, logtrap;
+        orc_hier4_node(j, &ls2, &logtrap);
+        double s2 = exp(ls2);
+        /* Q = Sigma^{-1}, Sigma = s2 I + TAU2 11^T */
+        double Sig[D][D], Q[D][D];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) Sig[r][c] = TAU2 + (r == c ? s2 : 0.0);
+        inverse4(Sig, Q);
+        double th[D];
+        for (int a = 0; a < D; ++a) th[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
+        int it = 0;
+        double H[D][D];
+        for (it = 0; it < 200; ++it) {
+            double g[D];
+            for (int a = 0; a < D; ++a) {
+                double qa = 0.0;
+                for (int c = 0; c < D; ++c) qa += Q[a][c] * (th[c] - M0);
+                g[a] = y[a] - n * expit(th[a]) - qa;
+            }
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    double p = expit(th[r]);
+                    H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
+                }
+            double A[D][D], step[D], rhs[D];
+            memcpy(A, H, sizeof A);
+            for (int a = 0; a < D; ++a) rhs[a] = g[a];
+            solve4(A, rhs, step);                    /* H step = g  ->  theta -= step */
+            double mx = 0.0;
+            for (int a = 0; a < D; ++a) {
+                th[a] -= step[a];
+                mx = fmax(mx, fabs(step[a]));
+            }
+            if (mx < 1e-10) break;   /* rounding floor of the step is ~1e-11 at the smallest s2 */
+        }
+        /* curvature at the final mode */
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                double p = expit(th[r]);
+                H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
+            }
+        double negH[D][D], C[D][D];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) negH[r][c] = -H[r][c];
+        inverse4(negH, C);
+        double ll = 0.0, quad = 0.0;
+        for (int a = 0; a < D; ++a) ll += y[a] * th[a] - n * softplus(th[a]);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) quad += (th[r] - M0) * Q[r][c] * (th[c] - M0);
+        double lap = ll - 0.5 * quad + 0.5 * logdet4(Q) - 0.5 * logdet4(negH);
+        double logprior = IG_A * log(IG_B) - lgamma(IG_A) - (IG_A + 1.0) * ls2 - IG_B / s2;
+        lw[j] = lap + logprior + logtrap;
+        for (int i = 1; i < D; ++i) {
+            double sd = sqrt(C[i][i] + C[0][0] - 2.0 * C[i][0]);
+            pr[j][i - 1] = Phi((th[i] - th[0]) / sd);
+        }
+        if (diag_mode)
+            for (int a = 0; a < D; ++a) diag_mode[j * D + a] = th[a];
+        if (diag_iters) diag_iters[j] = it;
+    }
+    double mx = -INFINITY;
+    for (int j = 0; j < NODES; ++j) mx = fmax(mx, lw[j]);
+    double s = 0.0;
+    for (int j = 0; j < NODES; ++j) s += exp(lw[j] - mx);
+    double lse = mx + log(s);
+    for (int i = 0; i < 3; ++i) P[i] = 0.0;
+    for (int j = 0; j < NODES; ++j) {
+        double pj = exp(lw[j] - lse);
+        if (diag_logw) diag_logw[j] = lw[j] - lse;
+        for (int i = 0; i < 3; ++i) P[i] += pj * pr[j][i];
+    }
+}
+
+void orc_hier4_posterior(const int32_t *y, int n, double *P) {
+    orc_hier4_posterior_full(y, n, P, NULL, NULL, NULL);
+}
+
+/* Posterior statistics for a list of outcome indices idx = ((y0*(n+1)+y1)*(n+1)+y2)*(n+1)+y3. */
+void orc_hier4_table(int n, const int64_t *idx, int64_t count, double *out /* [count][3] */) {
+    const int64_t m = n + 1;
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t v = idx[t];
+        int32_t y[D];
+        for (int a = D - 1; a >= 0; --a) {
+            y[a] = (int32_t)(v % m);
+            v /= m;
+        }
+        orc_hier4_posterior(y, n, out + 3 * t);
+    }
+}
+
+/* ------------------------------------------------------------------ simulation
+ * Tiles are (box centre theta [4], null configuration b) pairs; simulation k draws arm a,
+ * patient j from word a*n + j, as in oracle_sim.c.  For configuration b (bit i-1 set when
+ * H_i: theta_i <= theta_0 is true) the statistic is S_b = min_{i in b} (1 - P_i(y)) and the
+ * design rejects (a true null, i.e. the FWER event of the configuration) when S_b < cut.
+ * Outputs per tile: R, sumT[4] = sum over rejections of y, optional S [tile][stride] and the
+ * outcome index of every simulation.  Posteriors are memoised by outcome.
+ */
+#include <stdlib.h>
+
+static double *g_memo = NULL;
+static unsigned char *g_have = NULL;
+static int g_memo_n = -1;
+
+static const double *memo_posterior(const int32_t *y, int n) {
+    const int64_t m = n + 1;
+    if (g_memo_n != n) {
+        free(g_memo);
+        free(g_have);
+        g_memo = (double *)malloc(sizeof(double) * 3 * m * m * m * m);
+        g_have = (unsigned char *)calloc((size_t)(m * m * m * m), 1);
+        g_memo_n = n;
+    }
+    int64_t idx = ((y[0] * m + y[1]) * m + y[2]) * m + y[3];
+    if (!g_have[idx]) {
+        orc_hier4_posterior(y, n, g_memo + 3 * idx);
+        g_have[idx] = 1;
+    }
+    return g_memo + 3 * idx;
+}
+
+void orc_hier4_sim(int64_t n_tiles, const double *theta, const int32_t *cfg, const int32_t *sims,
+                   uint64_t seed, int n, double cut, int32_t *R, int64_t *sumT, double *S,
+                   int64_t s_stride, int64_t *outcome) {
+    const int64_t m = n + 1;
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        uint32_t T[D];
+        for (int a = 0; a < D; ++a) T[a] = orc_bern_threshold(theta[t * D + a]);
+        int32_t r = 0;
+        int64_t st[D] = {0, 0, 0, 0};
+        for (int32_t k = 0; k < sims[t]; ++k) {
+            int32_t y[D];
+            for (int a = 0; a < D; ++a) {
+                y[a] = 0;
+                for (int j = 0; j < n; ++j)
+                    if (orc_word(seed, (uint32_t)k, (uint32_t)(a * n + j)) < T[a]) y[a] += 1;
+            }
+            const double *P = memo_posterior(y, n);
+            double s = INFINITY;
+            for (int i = 1; i < D; ++i)
+                if ((cfg[t] >> (i - 1)) & 1) s = fmin(s, 1.0 - P[i - 1]);
+            if (s < cut) {
+                r += 1;
+                for (int a = 0; a < D; ++a) st[a] += y[a];
+            }
+            if (S) S[t * s_stride + k] = s;
+            if (outcome) outcome[t * s_stride + k] = ((y[0] * m + y[1]) * m + y[2]) * m + y[3];
+        }
+        R[t] = r;
+        if (sumT)
+            for (int a = 0; a < D; ++a) sumT[t * D + a] = st[a];
+    }
+}

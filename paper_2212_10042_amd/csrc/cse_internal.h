@@ -25,8 +25,10 @@ struct Blk2 {
     int32_t tile[B2U * B2V];   // tile id of slot (u, v) = u * B2V + v, or -1
     int32_t n_sims;            // simulations of every tile of this block
     int32_t pad;
-    int64_t key_base;          // calibration keys of slot s live at key_base + s * n_sims + k
+    int64_t key_base;          // calibration keys: chunk-major, key of simulation k in slot s
+                               // at key_base + ((k / 64) * 64 + s) * 64 + k % 64
 };
+constexpr int64_t KEY_CHUNK = (int64_t)B2U * B2V * 64;   // keys per 64-simulation chunk
 
 // z-test: 64 tiles share each simulation's normal draw.
 constexpr int B1T = 64;
@@ -44,6 +46,15 @@ struct WorkItem {
     uint32_t k_begin;
     uint32_t k_end;
     int32_t pad;
+};
+
+// Workgroup item of the 2-arm kernel: its 4 waves simulate the same sims [k_begin, k_end)
+// for up to 4 blocks of equal N (blk = -1: idle wave), sharing each simulation's Philox words.
+struct GroupItem {
+    int32_t blk[4];
+    uint32_t k_begin;
+    uint32_t k_end;
+    int32_t pad[2];
 };
 
 // Family of the data model for the bound (Example 1 / Section 4.2).
@@ -73,12 +84,15 @@ struct Platten {
     int32_t *d_N = nullptr;
     int32_t *d_vert_off = nullptr;
     double *d_verts = nullptr;
-    int64_t *d_key_off = nullptr;        // [n_tiles] start of each tile's keys in d_keys
+    int64_t *d_key_off = nullptr;        // [n_tiles] each tile's first key in d_keys (2-arm:
+                                         // chunk 0 of its slot; chunk stride KEY_CHUNK)
     int64_t n_keys = 0;                  // key slots (sum over blocks of 64 * n_sims)
     void *d_blocks = nullptr;
     int64_t n_blocks = 0;
     WorkItem *d_items = nullptr;
     int64_t n_items = 0;
+    GroupItem *d_gitems = nullptr;       // 2-arm design
+    int64_t n_gitems = 0;
 
     // design tables (device)
     int32_t *d_cut_tbl = nullptr;        // 2-arm: c(y0) = min{y1 : z(y0, y1) > cut}, [n+1]

@@ -1,4 +1,4 @@
-// k_bound.hip -- float64 bound of each tile, one thread per tile.
+// k_bound.hip -- float64 bound of each tile, eight lanes per tile.
 //
 //  * Clopper-Pearson upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 5.1): the regularized
 //    incomplete beta function by the continued fraction of DLMF 8.17.22 (modified Lentz
@@ -7,7 +7,9 @@
 //    Remark 3, Theorem 3) and the calibration target sup_q min_v U^{-1}(theta, v, q, alpha)
 //    (Section 6.2), exponential-family form psi(theta, v, q) = A(theta + q v) - A(theta)
 //    (Example 1).  Both objectives are quasi-convex (quasi-concave) in q (Theorem 2), so a
-//    golden-section search over s = log(q - 1) in [-30, 30] finds the optimum.
+//    parallel section search over s = log(q - 1) in [-30, 30] finds the optimum.
+//  Log-partition A(theta): normal location sum theta^2/2; independent Bernoulli arms with n
+//  patients each in logit parametrisation, n * sum softplus(theta_a).
 #include <math.h>
 
 #include "cse_internal.h"
@@ -19,17 +21,6 @@ constexpr int MAXV = 64;   // vertices per tile handled by the bound kernel
 
 __device__ __forceinline__ double softplus(double x) {
     return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x));
-}
-
-// Log-partition A(theta): normal location sum theta^2/2; independent Bernoulli arms with
-// n patients each in logit parametrisation, n * sum softplus(theta_a).
-__device__ double log_partition(int fam, int n, int d, const double *th, double q, const double *v) {
-    double s = 0.0;
-    for (int a = 0; a < d; ++a) {
-        const double x = th[a] + q * v[a];
-        s += (fam == FAM_NORMAL) ? 0.5 * x * x : softplus(x);
-    }
-    return (fam == FAM_NORMAL) ? s : (double)n * s;
 }
 
 // ---- regularized incomplete beta ----
@@ -60,169 +51,199 @@ __device__ double beta_cf(double a, double b, double x) {
     return 1.0 / f;
 }
 
-// x^a (1-x)^b / (a B(a,b)) * fraction  =  I_x(a,b)   where the fraction converges fast.
-__device__ double ibeta_front(double a, double b, double x) {
-    return exp(a * log(x) + b * log1p(-x) - lbeta(a, b)) / a * beta_cf(a, b, x);
-}
-
-// Upper tail Q(x) = 1 - I_x(a, b), accurate when it is small.
-__device__ double ibeta_upper(double a, double b, double x) {
+// Upper tail Q(x) = 1 - I_x(a, b) given lb = log B(a, b): the fraction is evaluated on the
+// side where it converges fast (x < (a+1)/(a+b+2) for I_x(a,b), else I_{1-x}(b,a) directly).
+__device__ double ibeta_upper(double a, double b, double x, double lb) {
     if (x <= 0.0) return 1.0;
     if (x >= 1.0) return 0.0;
-    if (x < (a + 1.0) / (a + b + 2.0)) return 1.0 - ibeta_front(a, b, x);
-    return ibeta_front(b, a, 1.0 - x);
+    const double lf = a * log(x) + b * log1p(-x) - lb;
+    if (x < (a + 1.0) / (a + b + 2.0)) return 1.0 - exp(lf) / a * beta_cf(a, b, x);
+    return exp(lf) / b * beta_cf(b, a, 1.0 - x);
 }
 
 // Clopper-Pearson (1 - delta) upper bound: the x with P(Binom(N, x) <= R) = Q(x; R+1, N-R) = delta.
-__device__ double cp_upper(int R, int N, double delta) {
+// Start at the normal approximation mean + z sd (z = upper delta quantile of N(0,1), from the
+// host), then Newton steps on log Q - log delta kept inside a bisection bracket.
+__device__ double cp_upper(int R, int N, double delta, double z) {
     if (R >= N) return 1.0;
     const double a = (double)R + 1.0, b = (double)(N - R);
+    const double lb = lbeta(a, b);
     const double ld = log(delta);
     double lo = 0.0, hi = 1.0;
-    double x = a / (a + b);
+    const double mu = a / (a + b), sd = sqrt(a * b / ((a + b) * (a + b) * (a + b + 1.0)));
+    double x = mu + z * sd;
+    if (!(x > 0.0 && x < 1.0)) x = 0.5 * (mu + 1.0);
     for (int it = 0; it < 200; ++it) {
-        const double Q = ibeta_upper(a, b, x);
+        const double Q = ibeta_upper(a, b, x, lb);
         if (Q > delta)
             lo = x;
         else
             hi = x;
-        const double ldens = (a - 1.0) * log(x) + (b - 1.0) * log1p(-x) - lbeta(a, b);
+        const double ldens = (a - 1.0) * log(x) + (b - 1.0) * log1p(-x) - lb;
         // Newton step on h(x) = log Q(x) - log delta, h'(x) = -density / Q
         double xn = x + (log(Q) - ld) * Q / exp(ldens);
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        if (fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-16 * hi) {
-            x = xn;
-            break;
-        }
+        const bool done = fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-16 * hi;
         x = xn;
+        if (done) break;
     }
     return x;
 }
 
-// ---- golden-section search over s = log(q - 1) ----
-struct TileView {
-    int fam, n, d, nv;
-    const double *th;
-    const double *V;
-    double A0;
-    double psi1[MAXV];
-};
+// ---- optimisation over q ----
+// GB lanes cooperate on one tile: each round they evaluate the objective at GB interior points
+// of the current bracket of s = log(q - 1), keep the two intervals around the best point
+// (valid for a unimodal objective, Theorem 2) and shrink the bracket by (GB+1)/2.
+constexpr int GB = 8;
+constexpr int SECTION_ROUNDS = 20;     // 60 * (2/9)^20 ~ 5e-12
 
-__device__ double obj_tilt(const TileView &T, double s, double loga) {
+template <int FAM>
+__device__ __forceinline__ double part(int n, int d, const double *th, double q, const double *v) {
+    double s = 0.0;
+    for (int a = 0; a < d; ++a) {
+        const double x = th[a] + q * v[a];
+        s += (FAM == FAM_NORMAL) ? 0.5 * x * x : softplus(x);
+    }
+    return (FAM == FAM_NORMAL) ? s : (double)n * s;
+}
+
+template <int FAM, bool INV>
+__device__ double objective(int n, int d, const double *th, const double *V, int nv,
+                            const double *psi1, double A0, double loga, double s) {
     const double q = 1.0 + exp(s);
-    double w = -1e300;
-    for (int j = 0; j < T.nv; ++j) {
-        const double psiq = log_partition(T.fam, T.n, T.d, T.th, q, T.V + j * T.d) - T.A0;
-        const double lu = (1.0 - 1.0 / q) * loga + psiq / q - T.psi1[j];
-        w = fmax(w, lu);
+    double w = INV ? 1e300 : -1e300;
+    for (int j = 0; j < nv; ++j) {
+        const double psiq = part<FAM>(n, d, th, q, V + j * d) - A0;
+        if (INV)
+            w = fmin(w, q / (q - 1.0) * (loga - psiq / q + psi1[j]));
+        else
+            w = fmax(w, (1.0 - 1.0 / q) * loga + psiq / q - psi1[j]);
     }
     return w;
 }
 
-__device__ double obj_inv(const TileView &T, double s, double loga) {
-    const double q = 1.0 + exp(s);
-    double w = 1e300;
-    for (int j = 0; j < T.nv; ++j) {
-        const double psiq = log_partition(T.fam, T.n, T.d, T.th, q, T.V + j * T.d) - T.A0;
-        const double li = q / (q - 1.0) * (loga - psiq / q + T.psi1[j]);
-        w = fmin(w, li);
-    }
-    return w;
-}
-
-// Minimise sgn * obj over s; returns s* and writes obj(s*).
-template <bool INV>
-__device__ double golden(const TileView &T, double loga, double *val) {
-    const double g = 0.61803398874989484820;
-    const double sg = INV ? -1.0 : 1.0;
+template <int FAM, bool INV>
+__device__ double section_search(int lane, int n, int d, const double *th, const double *V, int nv,
+                                 const double *psi1, double A0, double loga, double *s_best) {
+    const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
     double lo = -30.0, hi = 30.0;
-    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
-    double f1 = sg * (INV ? obj_inv(T, x1, loga) : obj_tilt(T, x1, loga));
-    double f2 = sg * (INV ? obj_inv(T, x2, loga) : obj_tilt(T, x2, loga));
-    for (int it = 0; it < 100; ++it) {
-        if (f1 <= f2) {
-            hi = x2;
-            x2 = x1;
-            f2 = f1;
-            x1 = hi - g * (hi - lo);
-            f1 = sg * (INV ? obj_inv(T, x1, loga) : obj_tilt(T, x1, loga));
-        } else {
-            lo = x1;
-            x1 = x2;
-            f1 = f2;
-            x2 = lo + g * (hi - lo);
-            f2 = sg * (INV ? obj_inv(T, x2, loga) : obj_tilt(T, x2, loga));
+    double best = INFINITY, bs = 0.0;
+    for (int r = 0; r < SECTION_ROUNDS; ++r) {
+        const double h = (hi - lo) / (double)(GB + 1);
+        double f = sg * objective<FAM, INV>(n, d, th, V, nv, psi1, A0, loga, lo + (lane + 1) * h);
+        if (f != f) f = INFINITY;
+        int jm = lane;
+#pragma unroll
+        for (int m = 1; m < GB; m <<= 1) {
+            const double fo = __shfl_xor(f, m);
+            const int jo = __shfl_xor(jm, m);
+            if (fo < f || (fo == f && jo < jm)) {
+                f = fo;
+                jm = jo;
+            }
         }
+        if (f < best) {
+            best = f;
+            bs = lo + (jm + 1) * h;
+        }
+        const double nlo = lo + jm * h;
+        hi = lo + (jm + 2) * h;
+        lo = nlo;
     }
-    const double s = 0.5 * (lo + hi);
-    *val = INV ? obj_inv(T, s, loga) : obj_tilt(T, s, loga);
-    return s;
+    *s_best = bs;
+    return sg * best;
 }
 
 // mode 0: validate (CP then tilt), mode 1: invert (alpha', k), mode 2: tilt of given a.
-__global__ __launch_bounds__(64) void k_bound(int mode, int fam, int n, int d, int64_t n_tiles,
-                                              const double *__restrict__ theta,
-                                              const int32_t *__restrict__ vert_off,
-                                              const double *__restrict__ verts,
-                                              const int32_t *__restrict__ N,
-                                              const uint32_t *__restrict__ R,
-                                              const double *__restrict__ a_in, double level,
-                                              double *__restrict__ out, double *__restrict__ q_out,
-                                              int32_t *__restrict__ k_out,
-                                              double *__restrict__ cp_out) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_tiles) return;
-    TileView T;
-    T.fam = fam;
-    T.n = n;
-    T.d = d;
-    T.th = theta + t * d;
-    T.V = verts + (int64_t)vert_off[t] * d;
-    T.nv = min(vert_off[t + 1] - vert_off[t], MAXV);
+template <int FAM>
+__global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n_tiles,
+                                               const double *__restrict__ theta,
+                                               const int32_t *__restrict__ vert_off,
+                                               const double *__restrict__ verts,
+                                               const int32_t *__restrict__ N,
+                                               const uint32_t *__restrict__ R,
+                                               const double *__restrict__ a_in, double level,
+                                               double zq, double *__restrict__ out,
+                                               double *__restrict__ q_out,
+                                               int32_t *__restrict__ k_out,
+                                               double *__restrict__ cp_out) {
+    __shared__ double s_psi1[256 / GB][MAXV];
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x % GB, grp = threadIdx.x / GB;
+    int64_t t = gid / GB;
+    const bool valid = t < n_tiles;
+    if (!valid) t = n_tiles - 1;   // idle groups shadow the last tile and write nothing
+    double th[MAX_D];
+    for (int a = 0; a < d; ++a) th[a] = theta[t * d + a];
+    const double *V = verts + (int64_t)vert_off[t] * d;
+    const int nv = min(vert_off[t + 1] - vert_off[t], MAXV);
     const double zero[MAX_D] = {0.0, 0.0, 0.0, 0.0};
-    T.A0 = log_partition(fam, n, d, T.th, 0.0, zero);
-    for (int j = 0; j < T.nv; ++j) T.psi1[j] = log_partition(fam, n, d, T.th, 1.0, T.V + j * d) - T.A0;
+    const double A0 = part<FAM>(n, d, th, 0.0, zero);
+    for (int j = lane; j < nv; j += GB) s_psi1[grp][j] = part<FAM>(n, d, th, 1.0, V + j * d) - A0;
+    __syncthreads();
+    const double *psi1 = s_psi1[grp];
 
     if (mode == 1) {
-        double val;
-        const double s = golden<true>(T, log(level), &val);
-        const double ap = exp(val);
-        out[t] = ap;
-        if (q_out) q_out[t] = 1.0 + exp(s);
-        if (k_out) k_out[t] = (int32_t)floor(((double)N[t] + 1.0) * ap);
+        double sb;
+        const double val = section_search<FAM, true>(lane, n, d, th, V, nv, psi1, A0, log(level), &sb);
+        if (valid && lane == 0) {
+            const double ap = exp(val);
+            out[t] = ap;
+            if (q_out) q_out[t] = 1.0 + exp(sb);
+            if (k_out) k_out[t] = (int32_t)floor(((double)N[t] + 1.0) * ap);
+        }
         return;
     }
     double a;
     if (mode == 0) {
-        a = cp_upper((int)R[t], N[t], level);
-        if (cp_out) cp_out[t] = a;
+        a = cp_upper((int)R[t], N[t], level, zq);
+        if (valid && lane == 0 && cp_out) cp_out[t] = a;
     } else {
         a = a_in[t];
     }
-    if (a <= 0.0) {
-        out[t] = 0.0;
-        if (q_out) q_out[t] = INFINITY;
+    if (a <= 0.0 || a >= 1.0) {
+        if (valid && lane == 0) {
+            out[t] = a <= 0.0 ? 0.0 : 1.0;
+            if (q_out) q_out[t] = a <= 0.0 ? INFINITY : 1.0;
+        }
         return;
     }
-    if (a >= 1.0) {
-        out[t] = 1.0;
-        if (q_out) q_out[t] = 1.0;
-        return;
+    double sb;
+    const double val = section_search<FAM, false>(lane, n, d, th, V, nv, psi1, A0, log(a), &sb);
+    if (valid && lane == 0) {
+        out[t] = fmin(exp(val), 1.0);
+        if (q_out) q_out[t] = 1.0 + exp(sb);
     }
-    double val;
-    const double s = golden<false>(T, log(a), &val);
-    out[t] = fmin(exp(val), 1.0);
-    if (q_out) q_out[t] = 1.0 + exp(s);
+}
+
+// Upper delta quantile of N(0, 1) by bisection on erfc (host; starting point of the CP Newton).
+static double normal_upper_quantile(double delta) {
+    double lo = -40.0, hi = 40.0;
+    for (int i = 0; i < 200; ++i) {
+        const double m = 0.5 * (lo + hi);
+        if (0.5 * erfc(m / sqrt(2.0)) > delta)
+            lo = m;
+        else
+            hi = m;
+    }
+    return 0.5 * (lo + hi);
 }
 
 hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const double *a_in,
                         double level, double *out, double *q_out, int32_t *k_out, double *cp_out,
                         hipStream_t st) {
-    const int bs = 64;
-    const int64_t grid = (P.n_tiles + bs - 1) / bs;
-    hipLaunchKernelGGL(k_bound, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.family, P.n_per_arm,
-                       P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_N, R, a_in, level,
-                       out, q_out, k_out, cp_out);
+    const int bs = 256;
+    const int64_t threads = P.n_tiles * GB;
+    const int64_t grid = (threads + bs - 1) / bs;
+    const double zq = mode == 0 ? normal_upper_quantile(level) : 0.0;
+    if (P.family == FAM_NORMAL)
+        hipLaunchKernelGGL(k_bound<FAM_NORMAL>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
+                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_N, R, a_in, level,
+                           zq, out, q_out, k_out, cp_out);
+    else
+        hipLaunchKernelGGL(k_bound<FAM_BINOM>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
+                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_N, R, a_in, level,
+                           zq, out, q_out, k_out, cp_out);
     return hipGetLastError();
 }
 

@@ -11,7 +11,6 @@
 namespace cse {
 
 constexpr int SEL_WG = 256;
-constexpr int MAX_OUTCOMES = 4096;
 
 // Block-wide exclusive scan of one value per thread (SEL_WG threads), result in part[].
 __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
@@ -31,56 +30,74 @@ __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
 }
 
 // ---- discrete statistic (2-arm design): keys are outcome indices y0*(n+1)+y1 ----
-// The histogram of outcomes is permuted into ascending-S order (S_order, ties grouped by
-// S_group); the first position whose cumulative count reaches k holds lambda*.
+// The tile's histogram of outcomes is built in LDS; one wave then walks the outcomes in
+// ascending-S order (S_order, ties grouped by S_group) with wave prefix sums and stops at the
+// first position whose cumulative count reaches k: its S value is lambda*, and the count
+// before its tie group is the number of simulations with S < lambda*.
+__device__ __forceinline__ void lds_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ __launch_bounds__(SEL_WG) void k_select_outcomes(
     const uint16_t *__restrict__ keys, const int64_t *__restrict__ key_off,
     const int32_t *__restrict__ N, const int32_t *__restrict__ kk, const double *__restrict__ S_tbl,
     const int32_t *__restrict__ S_order, const int32_t *__restrict__ S_group, int n_out,
     double *__restrict__ lam, int32_t *__restrict__ rej_at) {
-    __shared__ uint32_t hist[MAX_OUTCOMES];
-    __shared__ uint32_t cumx[MAX_OUTCOMES];
-    __shared__ uint32_t part[SEL_WG];
+    extern __shared__ uint32_t sm[];
+    uint32_t *hist = sm;           // [n_out]
+    uint32_t *cumx = sm + n_out;   // [n_out] exclusive cumulative counts in S order
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
+    const int32_t n = N[t];
+    const int32_t k = kk[t];
+    if (k <= 0 || k > n) {
+        if (tid == 0) {
+            lam[t] = k <= 0 ? -INFINITY : INFINITY;
+            if (rej_at) rej_at[t] = k <= 0 ? 0 : n;
+        }
+        return;
+    }
     for (int j = tid; j < n_out; j += SEL_WG) hist[j] = 0u;
     __syncthreads();
-    const int32_t n = N[t];
+    // chunk-major keys: chunk c of this tile is 64 contiguous keys at key_off + c * KEY_CHUNK;
+    // eight threads read one chunk as eight 16-byte pieces
     const uint16_t *__restrict__ kt = keys + key_off[t];
-    for (int j = tid; j < n; j += SEL_WG) atomicAdd(&hist[kt[j]], 1u);
-    __syncthreads();
-    const int per = (n_out + SEL_WG - 1) / SEL_WG;
-    const int p0 = tid * per, p1 = min(n_out, p0 + per);
-    uint32_t local = 0u;
-    for (int p = p0; p < p1; ++p) local += hist[S_order[p]];
-    block_exclusive_scan(local, part);
-    uint32_t run = part[tid];
-    for (int p = p0; p < p1; ++p) {
-        cumx[p] = run;
-        run += hist[S_order[p]];
+    const int nch = (n + WAVE - 1) / WAVE;
+    for (int j = tid; j < nch * 8; j += SEL_WG) {
+        const int c = j >> 3, piece = j & 7;
+        const int k0 = c * WAVE + piece * 8;
+        const uint4 v = *reinterpret_cast<const uint4 *>(kt + (int64_t)c * KEY_CHUNK + piece * 8);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            if (k0 + e < n) atomicAdd(&hist[(w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
     }
     __syncthreads();
-    const int32_t k = kk[t];
-    if (k <= 0) {
-        if (tid == 0) {
-            lam[t] = -INFINITY;
-            if (rej_at) rej_at[t] = 0;
+    if (tid >= WAVE) return;
+    uint32_t run = 0u;
+    for (int base = 0; base < n_out; base += WAVE) {
+        const int p = base + tid;
+        const uint32_t c = p < n_out ? hist[S_order[p]] : 0u;
+        uint32_t incl = c;
+#pragma unroll
+        for (int o = 1; o < WAVE; o <<= 1) {
+            const uint32_t y = __shfl_up(incl, o);
+            if (tid >= o) incl += y;
         }
-        return;
-    }
-    if (k > n) {
-        if (tid == 0) {
-            lam[t] = INFINITY;
-            if (rej_at) rej_at[t] = n;
+        const uint32_t excl = run + incl - c;
+        if (p < n_out) cumx[p] = excl;
+        lds_wave_sync();
+        const bool hit = p < n_out && excl < (uint32_t)k && excl + c >= (uint32_t)k;
+        if (__ballot(hit)) {
+            if (hit) {
+                lam[t] = S_tbl[S_order[p]];
+                if (rej_at) rej_at[t] = (int32_t)cumx[S_group[p]];
+            }
+            return;
         }
-        return;
-    }
-    for (int p = p0; p < p1; ++p) {
-        const uint32_t c = hist[S_order[p]];
-        if (cumx[p] < (uint32_t)k && cumx[p] + c >= (uint32_t)k) {
-            lam[t] = S_tbl[S_order[p]];
-            if (rej_at) rej_at[t] = (int32_t)cumx[S_group[p]];
-        }
+        run += __shfl(incl, WAVE - 1);
     }
 }
 
@@ -218,7 +235,8 @@ hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_
         hipLaunchKernelGGL(k_select_f32, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
                            (const float *)P.d_keys, P.d_key_off, P.d_N, k, lam, rej_at);
     else
-        hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
+        hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG),
+                           2 * (size_t)P.n_outcomes * sizeof(uint32_t), st,
                            (const uint16_t *)P.d_keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
                            P.d_S_group, P.n_outcomes, lam, rej_at);
     return hipGetLastError();

@@ -21,20 +21,24 @@ __device__ __forceinline__ void wave_sync() {
 
 // ------------------------------------------------------------------------------------
 // 2-arm binomial, n = 35 per arm, pooled z.  Words 0..34 are arm 0, 35..69 arm 1
-// (18 Philox blocks).  The batch is an 8 x 8 product of thresholds: the success counts
-// y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  Rejection at the
-// design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0; checked on the host).
+// (18 Philox blocks).  Each wave's batch is an 8 x 8 product of thresholds: the success
+// counts y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  The four waves of
+// a workgroup run four batches over the same simulations: each wave generates a quarter of
+// the Philox blocks of the chunk's 64 simulations into LDS, and every wave reads all 70
+// words.  Rejection at the design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0;
+// checked on the host).
 //
-// Per-lane accumulators are packed per tile: bits 0-5 rejections, 6-18 sum of y0 over
-// rejections, 19-31 sum of y1 over rejections; exact for up to 63 simulations per lane
-// between flushes.  A flush transposes the 64 x 64 (lane, tile) matrix through LDS so
+// Per-lane accumulators are packed per tile: bits 0-5 rejections, 6-17 sum of y0 over
+// rejections, 18-29 sum of y1 over rejections; exact for up to 63 simulations per lane
+// between flushes (63 * 35 < 4096).  A flush transposes the 64 x 64 (lane, tile) matrix through LDS so
 // lane t sums tile t's column into 32-bit totals; the final totals are added to global
-// memory with integer atomics (order-independent, hence deterministic).
+// memory with integer atomics (order-independent, hence deterministic).  The word buffer
+// and the transpose buffers share LDS: workgroup barriers separate their uses.
 // ------------------------------------------------------------------------------------
 template <bool KEYS>
 __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
-                                               const WorkItem *__restrict__ items, int64_t n_items,
-                                               uint32_t key0, uint32_t key1,
+                                               const GroupItem *__restrict__ items,
+                                               int64_t n_items, uint32_t key0, uint32_t key1,
                                                const int32_t *__restrict__ cut_tbl,
                                                uint32_t *__restrict__ R,
                                                unsigned long long *__restrict__ sumT,
@@ -42,25 +46,27 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     constexpr int NT = B2U * B2V;
     constexpr int NW = 2 * NP35;
     constexpr int NB = (NW + 3) / 4;
-    __shared__ uint32_t xbuf[WG / WAVE][NT][WAVE + 1];
+    constexpr int NWAVES = WG / WAVE;
+    __shared__ uint32_t lds[NWAVES][NT][WAVE + 1];
     __shared__ int32_t s_cut[64];
+    uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [4*NB][64]
+    static_assert(4 * NB * WAVE <= NWAVES * NT * (WAVE + 1), "word buffer must fit");
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (threadIdx.x < 64) s_cut[threadIdx.x] = threadIdx.x <= NP35 ? cut_tbl[threadIdx.x] : 64;
-    __syncthreads();
-    const int64_t it = (int64_t)blockIdx.x * (WG / WAVE) + wv;
-    if (it >= n_items) return;
-
-    const WorkItem W = items[it];
-    const Blk2 *__restrict__ B = blocks + W.blk;
+    const int64_t it = blockIdx.x;
+    if (it >= n_items) return;   // uniform over the workgroup
+    const GroupItem G = items[it];
+    const int32_t blk = G.blk[wv];
+    const bool live = blk >= 0;
+    const Blk2 *__restrict__ B = blocks + (live ? blk : G.blk[0]);
     uint32_t T0[B2U], T1[B2V];
 #pragma unroll
     for (int u = 0; u < B2U; ++u) T0[u] = B->T0[u];
 #pragma unroll
     for (int v = 0; v < B2V; ++v) T1[v] = B->T1[v];
-    const uint32_t n_sims = (uint32_t)B->n_sims;
-    const int64_t key_base = B->key_base;
+    uint16_t *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
 
     uint32_t acc[NT];
 #pragma unroll
@@ -68,66 +74,84 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     uint32_t totR = 0u, tot0 = 0u, tot1 = 0u;
 
     auto flush = [&]() {
+        __syncthreads();   // every wave is done with the word buffer
 #pragma unroll
-        for (int s = 0; s < NT; ++s) xbuf[wv][s][lane] = acc[s];
+        for (int s = 0; s < NT; ++s) lds[wv][s][lane] = acc[s];
         wave_sync();
         for (int l = 0; l < WAVE; ++l) {
-            const uint32_t x = xbuf[wv][lane][l];
+            const uint32_t x = lds[wv][lane][l];
             totR += x & 63u;
-            tot0 += (x >> 6) & 8191u;
-            tot1 += x >> 19;
+            tot0 += (x >> 6) & 4095u;
+            tot1 += (x >> 18) & 4095u;
         }
-        wave_sync();
 #pragma unroll
         for (int s = 0; s < NT; ++s) acc[s] = 0u;
+        __syncthreads();   // transposes read before the next chunk's words land
     };
 
     int since = 0;
-    for (uint32_t k0 = W.k_begin; k0 < W.k_end; k0 += WAVE) {
+    for (uint32_t k0 = G.k_begin; k0 < G.k_end; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
-        const bool act = k < W.k_end;
+        const bool act = k < G.k_end;
+        // this wave's share of the chunk's Philox blocks
+        for (int b = wv; b < NB; b += NWAVES) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+            words[4 * b + 0][lane] = w.x;
+            words[4 * b + 1][lane] = w.y;
+            words[4 * b + 2][lane] = w.z;
+            words[4 * b + 3][lane] = w.w;
+        }
+        __syncthreads();
         int y0[B2U], y1[B2V];
 #pragma unroll
         for (int u = 0; u < B2U; ++u) y0[u] = 0;
 #pragma unroll
         for (int v = 0; v < B2V; ++v) y1[v] = 0;
+        if (live) {
+#pragma unroll 7
+            for (int j = 0; j < NP35; ++j) {
+                const uint32_t x = words[j][lane];
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+                for (int u = 0; u < B2U; ++u) y0[u] += (x < T0[u]) ? 1 : 0;
+            }
+#pragma unroll 7
+            for (int j = NP35; j < NW; ++j) {
+                const uint32_t x = words[j][lane];
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int widx = 4 * b + l;
-                const uint32_t x = u32x4_get(w, l);
-                if (widx < NP35) {
-#pragma unroll
-                    for (int u = 0; u < B2U; ++u) y0[u] += (x < T0[u]) ? 1 : 0;
-                } else if (widx < NW) {
-#pragma unroll
-                    for (int v = 0; v < B2V; ++v) y1[v] += (x < T1[v]) ? 1 : 0;
-                }
+                for (int v = 0; v < B2V; ++v) y1[v] += (x < T1[v]) ? 1 : 0;
             }
         }
-        int c[B2U];
-        uint32_t P0[B2U], P1[B2V];
+        __syncthreads();   // words consumed: the next chunk (or a flush) may overwrite them
+        if (live) {
+            if (KEYS) {
+                // chunk-major key layout: this chunk's 64 slots are 128-byte rows of one 8 KB
+                // piece.  Every slot and every lane of a chunk has storage (empty slots and the
+                // lanes past N in the last chunk included; the selection ignores them), so the
+                // stores need no test.
+                uint16_t *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * KEY_CHUNK + lane;
 #pragma unroll
-        for (int u = 0; u < B2U; ++u) {
-            c[u] = act ? s_cut[y0[u]] : 64;
-            P0[u] = 1u | ((uint32_t)y0[u] << 6);
-        }
+                for (int u = 0; u < B2U; ++u)
 #pragma unroll
-        for (int v = 0; v < B2V; ++v) P1[v] = (uint32_t)y1[v] << 19;
+                    for (int v = 0; v < B2V; ++v)
+                        kc[(u * B2V + v) * WAVE] = (uint16_t)(y0[u] * (NP35 + 1) + y1[v]);
+            }
+            // reject indicator r = [y1 >= c(y0)] = med3(y1 - c + 1, 0, 1), added as r * packed
+            // (24-bit multiply-add; no compare masks, so nothing is held in scalar registers)
+            int cm[B2U];
+            uint32_t P0[B2U], P1[B2V];
 #pragma unroll
-        for (int u = 0; u < B2U; ++u)
+            for (int u = 0; u < B2U; ++u) {
+                cm[u] = (act ? s_cut[y0[u]] : 64) - 1;
+                P0[u] = 1u | ((uint32_t)y0[u] << 6);
+            }
 #pragma unroll
-            for (int v = 0; v < B2V; ++v) acc[u * B2V + v] += (y1[v] >= c[u]) ? (P0[u] + P1[v]) : 0u;
-        if (KEYS) {
+            for (int v = 0; v < B2V; ++v) P1[v] = (uint32_t)y1[v] << 18;
 #pragma unroll
             for (int u = 0; u < B2U; ++u)
 #pragma unroll
                 for (int v = 0; v < B2V; ++v) {
-                    const int s = u * B2V + v;
-                    if (B->tile[s] >= 0 && act)
-                        keys[key_base + (int64_t)s * n_sims + k] = (uint16_t)(y0[u] * (NP35 + 1) + y1[v]);
+                    const uint32_t r = (uint32_t)min(max(y1[v] - cm[u], 0), 1);
+                    acc[u * B2V + v] += __umul24(r, P0[u] + P1[v]);
                 }
         }
         if (++since == 63) {
@@ -136,6 +160,7 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
         }
     }
     flush();
+    if (!live) return;
     const int32_t tile = B->tile[lane];
     if (tile >= 0) {
         atomicAdd(&R[tile], totR);
@@ -288,15 +313,15 @@ __global__ __launch_bounds__(WG) void k_ztest1_plain(float theta, float cut, uin
 // ------------------------------------------------------------------------------ launchers
 hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
                          uint16_t *keys, hipStream_t st) {
-    const int64_t grid = (P.n_items + (WG / WAVE) - 1) / (WG / WAVE);
+    const int64_t grid = P.n_gitems;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (keys)
         hipLaunchKernelGGL(k_binom2<true>, dim3((uint32_t)grid), dim3(WG), 0, st,
-                           (const Blk2 *)P.d_blocks, P.d_items, P.n_items, k0, k1, P.d_cut_tbl, R,
+                           (const Blk2 *)P.d_blocks, P.d_gitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
                            sumT, keys);
     else
         hipLaunchKernelGGL(k_binom2<false>, dim3((uint32_t)grid), dim3(WG), 0, st,
-                           (const Blk2 *)P.d_blocks, P.d_items, P.n_items, k0, k1, P.d_cut_tbl, R,
+                           (const Blk2 *)P.d_blocks, P.d_gitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
                            sumT, keys);
     return hipGetLastError();
 }

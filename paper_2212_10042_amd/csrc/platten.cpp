@@ -383,8 +383,8 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             blk_sims.push_back(B.n_sims);
             B.key_base = P->n_keys;
             for (int j = 0; j < B2U * B2V; ++j)
-                if (B.tile[j] >= 0) key_off[B.tile[j]] = B.key_base + (int64_t)j * B.n_sims;
-            P->n_keys += (int64_t)(B2U * B2V) * B.n_sims;
+                if (B.tile[j] >= 0) key_off[B.tile[j]] = B.key_base + (int64_t)j * 64;
+            P->n_keys += ((int64_t)B.n_sims + 63) / 64 * KEY_CHUNK;
         }
         if (int e = upload((Blk2 **)&P->d_blocks, blks.data(), blks.size())) return e;
 
@@ -445,6 +445,33 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         P->n_items = (int64_t)items.size();
         if (int e = upload(&P->d_items, items.data(), items.size())) return e;
     }
+    if (kind == CSE_BINOM2_Z) {
+        // groups of 4 consecutive blocks of equal N (blocks are ordered by N), split in sims
+        const int64_t target = 4096;    // workgroups
+        std::vector<std::vector<int64_t>> groups;
+        for (int64_t b = 0; b < P->n_blocks; ++b) {
+            if (groups.empty() || groups.back().size() == 4 || blk_sims[groups.back()[0]] != blk_sims[b])
+                groups.push_back({});
+            groups.back().push_back(b);
+        }
+        const int64_t ng = (int64_t)groups.size();
+        const int64_t slices = std::max<int64_t>(1, (target + ng - 1) / ng);
+        std::vector<GroupItem> gi;
+        for (auto &g : groups) {
+            const int64_t N = blk_sims[g[0]];
+            const int64_t chunks = (N + WAVE - 1) / WAVE;
+            const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
+            for (int64_t k0 = 0; k0 < N; k0 += per) {
+                GroupItem it{};
+                for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
+                it.k_begin = (uint32_t)k0;
+                it.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
+                gi.push_back(it);
+            }
+        }
+        P->n_gitems = (int64_t)gi.size();
+        if (int e = upload(&P->d_gitems, gi.data(), gi.size())) return e;
+    }
 
     if (int e = upload(&P->d_theta, P->tile_theta.data(), P->tile_theta.size())) return e;
     if (int e = upload(&P->d_N, P->tile_N.data(), P->tile_N.size())) return e;
@@ -466,7 +493,7 @@ void free_platten(Platten *P) {
     if (!P) return;
     (void)hipDeviceSynchronize();
     void *ptrs[] = {P->d_theta, P->d_N,    P->d_vert_off, P->d_verts,   P->d_key_off,
-                    P->d_blocks, P->d_items, P->d_cut_tbl, P->d_S_tbl,  P->d_S_order,
+                    P->d_blocks, P->d_items, P->d_gitems, P->d_cut_tbl, P->d_S_tbl,  P->d_S_order,
                     P->d_S_group, P->d_keys, P->d_Rw,      P->d_Tw,     P->d_Zw,
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg};
     for (void *q : ptrs)

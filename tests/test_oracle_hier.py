@@ -1,0 +1,156 @@
+"""Pins of the oracle's 4-arm hierarchical posterior (model of Section 10.1, reading in
+oracle_hier.c) against facts independent of its code:
+
+- exchangeability of the prior: P_i(y) = 1/2 exactly when y_i = y_0; swapping y_i and y_0
+  gives 1 - P_i; permuting the other two treatment arms changes nothing;
+- monotonicity: P_i increases with y_i and decreases with y_0 (interior counts);
+- the Newton mode of each node equals the maximiser found by scipy.optimize (BFGS) of a
+  log-density assembled from scipy.stats (binomial log-pmf + multivariate normal log-pdf with
+  Sigma = s2 I + 100 11^T), so a wrong gradient or Hessian term fails;
+- node weights: at large n the Laplace log-evidence must match adaptive Gauss-Hermite
+  quadrature of the exact marginal likelihood p(y | s2) (ratios across nodes), so a wrong
+  determinant or quadratic term fails;
+- the tilt bound of the 4-arm family follows from the same exponential-family code as the
+  2-arm one (pinned in test_oracle_bounds.py).
+"""
+import ctypes
+import itertools
+import math
+
+import numpy as np
+import pytest
+from scipy import optimize, stats
+
+import oracle as O
+
+N = 35
+
+
+def post(y, n=N):
+    y = np.asarray(y, np.int32)
+    P = np.zeros(3)
+    O.lib().orc_hier4_posterior(O._p(y), n, O._p(P))
+    return P
+
+
+def post_full(y, n=N):
+    y = np.asarray(y, np.int32)
+    P = np.zeros(3)
+    mode = np.zeros((90, 4))
+    lw = np.zeros(90)
+    it = np.zeros(90, np.int32)
+    O.lib().orc_hier4_posterior_full(O._p(y), n, O._p(P), O._p(mode), O._p(lw), O._p(it))
+    return P, mode, lw, it
+
+
+def node(j):
+    ls2 = ctypes.c_double()
+    lw = ctypes.c_double()
+    O.lib().orc_hier4_node(j, ctypes.byref(ls2), ctypes.byref(lw))
+    return ls2.value, lw.value
+
+
+@pytest.mark.parametrize("y", [(10, 10, 3, 30), (0, 0, 35, 17), (20, 12, 20, 20), (35, 35, 0, 1)])
+def test_equal_counts_give_one_half(y):
+    P = post(y)
+    for i in range(1, 4):
+        if y[i] == y[0]:
+            assert P[i - 1] == pytest.approx(0.5, abs=1e-12)
+
+
+@pytest.mark.parametrize("y", [(10, 14, 3, 30), (2, 0, 35, 17), (20, 12, 25, 21)])
+def test_swap_and_permutation_symmetry(y):
+    P = post(y)
+    for i in range(1, 4):
+        ys = list(y)
+        ys[0], ys[i] = ys[i], ys[0]
+        assert post(ys)[i - 1] == pytest.approx(1.0 - P[i - 1], abs=1e-10)
+    yp = (y[0], y[1], y[3], y[2])
+    Pp = post(yp)
+    assert Pp[0] == pytest.approx(P[0], abs=1e-12)
+    assert Pp[1] == pytest.approx(P[2], abs=1e-12) and Pp[2] == pytest.approx(P[1], abs=1e-12)
+
+
+def test_monotone_in_own_and_control_counts():
+    """Interior counts only: at y in {0, n} the Laplace reading is not monotone (see oracle_hier.c)."""
+    base = [12, 12, 20, 5]
+    prev = -1.0
+    for y1 in range(1, 35, 3):
+        p = post([12, y1, 20, 5])[0]
+        assert p > prev
+        prev = p
+    prev = 2.0
+    for y0 in range(1, 35, 3):
+        p = post([y0] + base[1:])[0]
+        assert p < prev
+        prev = p
+
+
+def _logdens(th, y, n, s2):
+    cov = s2 * np.eye(4) + 100.0 * np.ones((4, 4))
+    p = 1.0 / (1.0 + np.exp(-th))
+    return (np.sum(stats.binom.logpmf(y, n, p))
+            + stats.multivariate_normal(mean=np.full(4, -1.34), cov=cov).logpdf(th))
+
+
+@pytest.mark.parametrize("y", [(10, 14, 3, 30), (0, 1, 35, 17)])
+def test_newton_mode_matches_independent_optimizer(y):
+    """At every tested node the oracle's mode is at least as good as BFGS's maximiser of the
+    scipy.stats log-density, and that density's numerical gradient and curvature there place
+    the true maximiser within 1e-5 of it."""
+    _, mode, _, it = post_full(y)
+    assert it.max() < 200
+    yy = np.array(y)
+    for j in (0, 30, 60, 89):
+        s2 = math.exp(node(j)[0])
+        f = lambda th: _logdens(th, yy, N, s2)
+        res = optimize.minimize(lambda th: -f(th), mode[j] + 0.3, method="BFGS", options=dict(gtol=1e-10))
+        assert f(mode[j]) >= -res.fun - 1e-9
+        h = 1e-4
+        for a in range(4):
+            e = np.zeros(4)
+            e[a] = h
+            g = (f(mode[j] + e) - f(mode[j] - e)) / (2 * h)
+            c = (f(mode[j] + e) - 2 * f(mode[j]) + f(mode[j] - e)) / (h * h)
+            assert c < 0 and abs(g / c) < 1e-5
+
+
+def _gh_log_evidence(y, n, s2, mode):
+    """log p(y | s2) by adaptive Gauss-Hermite quadrature (12 points per dimension) around `mode`."""
+    z, w = np.polynomial.hermite.hermgauss(12)
+    cov = s2 * np.eye(4) + 100.0 * np.ones((4, 4))
+    # curvature at the mode sets the scale of the rule
+    p = 1.0 / (1.0 + np.exp(-mode))
+    H = np.linalg.inv(cov) + np.diag(n * p * (1 - p))
+    L = np.linalg.cholesky(np.linalg.inv(H))
+    Z = np.array(list(itertools.product(z, repeat=4)))
+    W = np.prod(np.array(list(itertools.product(w, repeat=4))), axis=1)
+    th = mode + math.sqrt(2.0) * Z @ L.T
+    pp = 1.0 / (1.0 + np.exp(-th))
+    ll = (stats.binom.logpmf(np.array(y)[None, :], n, pp).sum(axis=1)
+          + stats.multivariate_normal(mean=np.full(4, -1.34), cov=cov).logpdf(th))
+    lf = ll + np.sum(Z * Z, axis=1)
+    m = lf.max()
+    return m + math.log(np.sum(W * np.exp(lf - m))) + math.log(abs(np.linalg.det(math.sqrt(2.0) * L)))
+
+
+def test_laplace_node_weights_match_quadrature_at_large_n():
+    """At n = 2000 per arm the Laplace evidence is accurate to O(1/n): the differences of the
+    oracle's log node weights must match quadrature of the exact marginal likelihood."""
+    n = 2000
+    y = (800, 840, 780, 900)
+    _, mode, lw, _ = post_full(y, n)
+    js = [20, 45, 70, 89]
+    gh = []
+    orc = []
+    for j in js:
+        ls2, logtrap = node(j)
+        s2 = math.exp(ls2)
+        logprior = 0.0005 * math.log(0.000005) - math.lgamma(0.0005) - 1.0005 * ls2 - 0.000005 / s2
+        # the binomial coefficients are common to all nodes and cancel in differences
+        coef = sum(math.lgamma(n + 1) - math.lgamma(k + 1) - math.lgamma(n - k + 1) for k in y)
+        gh.append(_gh_log_evidence(y, n, s2, mode[j]) - coef + logprior + logtrap)
+        orc.append(lw[j])
+    gh = np.array(gh) - gh[0]
+    orc = np.array(orc) - orc[0]
+    np.testing.assert_allclose(orc, gh, atol=5e-3)
