@@ -28,9 +28,10 @@ sys.path.insert(0, ROOT)
 METRIC = "sim·tiles/s, TIE+gradient+calibration vs plain fwd at equal bound; % roofline"
 VALU_PEAK = 256 * 4 * 64 * 2.4e9 / 4   # lane-ops/s: 256 CUs x 4 SIMDs x one wave64 op per 4 clocks
 # Algorithmic integer work of the fused 2-arm kernel:
-OPS_PHILOX_PER_SIM = 18 * 10 * 4       # 18 blocks x 10 rounds x (2 32x32->64 products + 2 xor3)
-OPS_COUNT_PER_SIM = 2 * 35 * 8 * 2     # 70 words x 8 thresholds of their arm x (compare + add)
-OPS_PER_SIM_TILE = 5                   # compare with c(y0), select, accumulate, key store
+OPS_PHILOX_PER_SIM = 18 * 10 * 4       # per (workgroup, simulation): 18 blocks x 10 rounds x
+                                       # (2 32x32->64 products + 2 xor3), shared by the 4 batches
+OPS_COUNT_PER_SIM = 2 * 35 * 8 * 2     # per (batch, simulation): 70 words x 8 thresholds x (cmp+add)
+OPS_PER_SIM_TILE = 5                   # decision, accumulate, key store
 
 
 def cpu_baseline(w, target_s: float = 15.0):
@@ -125,7 +126,7 @@ def main():
     dt = time.perf_counter() - t
     cse.cse_profile_enable(False)
     kern = {}
-    for name in ("binom2_calib", "select", "bound_invert", "bound_validate"):
+    for name in ("binom2_calib", "select", "bound_invert", "bound_validate", "cp_table"):
         cnt, ms = cse.cse_profile_get(name)
         kern[name] = round(ms / max(cnt, 1), 5)
     total = st["total_sims"] * args.steps
@@ -133,7 +134,8 @@ def main():
     ms_step = dt / args.steps * 1e3
 
     # roofline of the dominant kernel (fused simulation, calibration variant)
-    ops = st["batch_sims"] * (OPS_PHILOX_PER_SIM + OPS_COUNT_PER_SIM) + st["total_sims"] * OPS_PER_SIM_TILE
+    ops = (st["group_sims"] * OPS_PHILOX_PER_SIM + st["batch_sims"] * OPS_COUNT_PER_SIM
+           + st["total_sims"] * OPS_PER_SIM_TILE)
     k_s = kern["binom2_calib"] * 1e-3
     achieved = ops / k_s if k_s > 0 else 0.0
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tops/s (int32 VALU)",

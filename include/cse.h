@@ -184,12 +184,14 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
                           int64_t tile_end, int32_t *reject, void *stream);
 
 /*
- * cse_platten_stats -- sizes of the planned launch (host), out[0..7] =
- *   n_tiles, n_batches (tile batches of the fused kernel), n_work_items (waves launched by one
- *   simulation pass), n_key_slots (calibration keys), total simulations (sum of N over tiles),
- *   tiles per batch, max N, simulation-batch pairs (sum over batches of their N).
+ * cse_platten_stats -- sizes of the planned launch (host), out[0..11] =
+ *   n_tiles, n_batches (tile batches of the fused kernel), n_work_items (waves or workgroups
+ *   launched by one simulation pass), n_key_slots (calibration keys), total simulations (sum of N
+ *   over tiles), tiles per batch, max N, batch-simulation pairs (sum over batches of their N),
+ *   workgroup-simulation pairs (sum over workgroup items of their simulation count; the unit of
+ *   shared random-number generation), number of distinct N, 0, 0.
  */
-int cse_platten_stats(const cse_platten *p, int64_t out[8]);
+int cse_platten_stats(const cse_platten *p, int64_t out[12]);
 
 /*
  * Kernel timing for measurement (process-wide, not thread-safe against concurrent calls):

@@ -170,10 +170,10 @@ def cse_simulate_per_tile(h, seed, tile_begin, tile_end, reject, stream=None):
 
 
 def cse_platten_stats(h) -> dict:
-    out = np.zeros(8, np.int64)
+    out = np.zeros(12, np.int64)
     _check("cse_platten_stats", _L.cse_platten_stats(h, _ptr(out)))
     keys = ("n_tiles", "n_batches", "n_work_items", "n_key_slots", "total_sims", "tiles_per_batch",
-            "max_sims", "batch_sims")
+            "max_sims", "batch_sims", "group_sims", "n_sim_classes")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -318,7 +318,7 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
     return CSE_OK;
 }
 
-int cse_platten_stats(const cse_platten *p, int64_t out[8]) {
+int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     if (!p || !out) {
         set_error("cse_platten_stats: NULL argument");
         return CSE_EINVAL;
@@ -332,6 +332,10 @@ int cse_platten_stats(const cse_platten *p, int64_t out[8]) {
     out[5] = (P.family == cse::FAM_NORMAL) ? cse::B1T : cse::B2U * cse::B2V;
     out[6] = P.max_N;
     out[7] = P.block_sims;
+    out[8] = P.group_sims;
+    out[9] = P.n_cls;
+    out[10] = 0;
+    out[11] = 0;
     return CSE_OK;
 }
 

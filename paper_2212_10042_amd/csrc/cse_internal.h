@@ -75,15 +75,20 @@ struct Platten {
     std::vector<double> tile_theta;      // [n_tiles * d]
     std::vector<int32_t> vert_off;       // [n_tiles + 1]
     std::vector<double> verts;           // [total vertices * d] displacements from theta
+    std::vector<double> tile_radii;      // [n_tiles * d]
+    std::vector<int32_t> tile_is_box;    // [n_tiles]
     int32_t max_N = 0;
     int64_t total_sims = 0;              // sum of N over tiles
     int64_t block_sims = 0;              // sum over batches of their N
+    int64_t group_sims = 0;              // sum over workgroup items of their simulation count
 
     // device copies (owned)
     double *d_theta = nullptr;
     int32_t *d_N = nullptr;
     int32_t *d_vert_off = nullptr;
     double *d_verts = nullptr;
+    double *d_radii = nullptr;           // [n_tiles * d] half-widths of the tile's box
+    int32_t *d_is_box = nullptr;         // [n_tiles] 1 when the tile is its whole box
     int64_t *d_key_off = nullptr;        // [n_tiles] each tile's first key in d_keys (2-arm:
                                          // chunk 0 of its slot; chunk stride KEY_CHUNK)
     int64_t n_keys = 0;                  // key slots (sum over blocks of 64 * n_sims)
@@ -102,6 +107,16 @@ struct Platten {
     int32_t n_outcomes = 0;
 
     std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
+
+    // Clopper-Pearson table: one entry per (N class, R), R = 0..N (classes = distinct N)
+    int32_t n_cls = 0;
+    int64_t n_cp = 0;                    // sum over classes of N + 1
+    int32_t *d_cls_N = nullptr;          // [n_cls]
+    int64_t *d_cls_off = nullptr;        // [n_cls] first entry of each class
+    int64_t *d_cp_base = nullptr;        // [n_tiles] first entry of the tile's class
+    uint32_t *d_cp_mark = nullptr;       // [n_cp] R values present in this call
+    double *d_cp_tbl = nullptr;          // [n_cp]
+    int32_t max_cls_N = 0;
 
     // per-tile workspaces (allocated with the platten)
     uint32_t *d_Rw = nullptr;            // rejection counts

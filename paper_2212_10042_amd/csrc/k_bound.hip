@@ -62,10 +62,13 @@ __device__ double ibeta_upper(double a, double b, double x, double lb) {
 }
 
 // Clopper-Pearson (1 - delta) upper bound: the x with P(Binom(N, x) <= R) = Q(x; R+1, N-R) = delta.
-// Start at the normal approximation mean + z sd (z = upper delta quantile of N(0,1), from the
-// host), then Newton steps on log Q - log delta kept inside a bisection bracket.
+// R = 0 has the closed form 1 - delta^(1/N).  Otherwise start at the normal approximation
+// mean + z sd (z = upper delta quantile of N(0,1), from the host) and take Halley steps on
+// h(x) = log Q(x) - log delta inside a bisection bracket:  h' = -r, h'' = -r (g + r) with
+// r = density / Q and g = (a-1)/x - (b-1)/(1-x) the log-derivative of the density.
 __device__ double cp_upper(int R, int N, double delta, double z) {
     if (R >= N) return 1.0;
+    if (R == 0) return -expm1(log(delta) / (double)N);
     const double a = (double)R + 1.0, b = (double)(N - R);
     const double lb = lbeta(a, b);
     const double ld = log(delta);
@@ -73,19 +76,24 @@ __device__ double cp_upper(int R, int N, double delta, double z) {
     const double mu = a / (a + b), sd = sqrt(a * b / ((a + b) * (a + b) * (a + b + 1.0)));
     double x = mu + z * sd;
     if (!(x > 0.0 && x < 1.0)) x = 0.5 * (mu + 1.0);
-    for (int it = 0; it < 200; ++it) {
+    for (int it = 0; it < 60; ++it) {
         const double Q = ibeta_upper(a, b, x, lb);
         if (Q > delta)
             lo = x;
         else
             hi = x;
-        const double ldens = (a - 1.0) * log(x) + (b - 1.0) * log1p(-x) - lb;
-        // Newton step on h(x) = log Q(x) - log delta, h'(x) = -density / Q
-        double xn = x + (log(Q) - ld) * Q / exp(ldens);
+        const double h = log(Q) - ld;
+        const double r = exp((a - 1.0) * log(x) + (b - 1.0) * log1p(-x) - lb) / Q;
+        const double g = (a - 1.0) / x - (b - 1.0) / (1.0 - x);
+        // Newton step h / r, Halley's correction 1 / (1 + h (g + r) / (2 r)) when it is moderate
+        const double newton = h / r;
+        const double fac = 1.0 + 0.5 * newton * (g + r);
+        double xn = x + ((fac > 0.5 && fac < 2.0) ? newton / fac : newton);
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
-        const bool done = fabs(xn - x) <= 1e-15 * x || hi - lo <= 1e-16 * hi;
+        // stop when the residual is below the rounding noise of log Q (~1e-13, from the log-beta
+        // normalisation), or the bracket has collapsed
+        if (fabs(h) < 4e-12 || hi - lo <= 4e-16 * hi) break;
         x = xn;
-        if (done) break;
     }
     return x;
 }
@@ -95,7 +103,7 @@ __device__ double cp_upper(int R, int N, double delta, double z) {
 // of the current bracket of s = log(q - 1), keep the two intervals around the best point
 // (valid for a unimodal objective, Theorem 2) and shrink the bracket by (GB+1)/2.
 constexpr int GB = 8;
-constexpr int SECTION_ROUNDS = 20;     // 60 * (2/9)^20 ~ 5e-12
+constexpr int SECTION_ROUNDS = 14;     // bracket 60 * (2/9)^14 ~ 4e-8 in s
 
 template <int FAM>
 __device__ __forceinline__ double part(int n, int d, const double *th, double q, const double *v) {
@@ -107,30 +115,63 @@ __device__ __forceinline__ double part(int n, int d, const double *th, double q,
     return (FAM == FAM_NORMAL) ? s : (double)n * s;
 }
 
-template <int FAM, bool INV>
-__device__ double objective(int n, int d, const double *th, const double *V, int nv,
-                            const double *psi1, double A0, double loga, double s) {
-    const double q = 1.0 + exp(s);
-    double w = INV ? 1e300 : -1e300;
-    for (int j = 0; j < nv; ++j) {
-        const double psiq = part<FAM>(n, d, th, q, V + j * d) - A0;
-        if (INV)
-            w = fmin(w, q / (q - 1.0) * (loga - psiq / q + psi1[j]));
-        else
-            w = fmax(w, (1.0 - 1.0 / q) * loga + psiq / q - psi1[j]);
+template <int FAM>
+__device__ __forceinline__ double part1(int n, double x) {
+    return (FAM == FAM_NORMAL) ? 0.5 * x * x : (double)n * softplus(x);
+}
+
+// One tile's data for the search over q.
+struct TileGeom {
+    int n, d, nv;
+    bool box;                 // whole box: the objective is separable over arms
+    double th[MAX_D], r[MAX_D];
+    double A0a[MAX_D];        // per-arm log partition at theta (box form)
+    double p1[MAX_D][2];      // per-arm psi(theta, -r / +r, 1) (box form)
+    const double *V;          // vertex displacements (general form)
+    const double *psi1;       // per-vertex psi(theta, v, 1) (general form)
+    double A0;
+};
+
+// max over the tile's vertices of  psi(theta, v, q) / q - psi(theta, v, 1).
+// For a whole box A is a sum over arms and the vertices are all sign patterns (+-r_a), so the
+// maximum is the sum over arms of the larger of the two one-arm terms (same value as the
+// vertex loop, 2d instead of d 2^d log-partition terms).
+template <int FAM>
+__device__ double max_tilt_term(const TileGeom &T, double q) {
+    if (T.box) {
+        double s = 0.0;
+        for (int a = 0; a < T.d; ++a) {
+            const double lo = (part1<FAM>(T.n, T.th[a] - q * T.r[a]) - T.A0a[a]) / q - T.p1[a][0];
+            const double hi = (part1<FAM>(T.n, T.th[a] + q * T.r[a]) - T.A0a[a]) / q - T.p1[a][1];
+            s += fmax(lo, hi);
+        }
+        return s;
+    }
+    double w = -1e300;
+    for (int j = 0; j < T.nv; ++j) {
+        const double psiq = part<FAM>(T.n, T.d, T.th, q, T.V + j * T.d) - T.A0;
+        w = fmax(w, psiq / q - T.psi1[j]);
     }
     return w;
 }
 
+// log U (forward, max over vertices) or log U^{-1} (inverse, min over vertices); the inverse's
+// min over v of q/(q-1) (log alpha - psi_q/q + psi_1) is q/(q-1) (log alpha - max_v(...)).
 template <int FAM, bool INV>
-__device__ double section_search(int lane, int n, int d, const double *th, const double *V, int nv,
-                                 const double *psi1, double A0, double loga, double *s_best) {
+__device__ double objective(const TileGeom &T, double loga, double s) {
+    const double q = 1.0 + exp(s);
+    const double m = max_tilt_term<FAM>(T, q);
+    return INV ? q / (q - 1.0) * (loga - m) : (1.0 - 1.0 / q) * loga + m;
+}
+
+template <int FAM, bool INV>
+__device__ double section_search(int lane, const TileGeom &T, double loga, double *s_best) {
     const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
     double lo = -30.0, hi = 30.0;
     double best = INFINITY, bs = 0.0;
     for (int r = 0; r < SECTION_ROUNDS; ++r) {
         const double h = (hi - lo) / (double)(GB + 1);
-        double f = sg * objective<FAM, INV>(n, d, th, V, nv, psi1, A0, loga, lo + (lane + 1) * h);
+        double f = sg * objective<FAM, INV>(T, loga, lo + (lane + 1) * h);
         if (f != f) f = INFINITY;
         int jm = lane;
 #pragma unroll
@@ -160,10 +201,14 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
                                                const double *__restrict__ theta,
                                                const int32_t *__restrict__ vert_off,
                                                const double *__restrict__ verts,
+                                               const double *__restrict__ radii,
+                                               const int32_t *__restrict__ is_box,
                                                const int32_t *__restrict__ N,
                                                const uint32_t *__restrict__ R,
                                                const double *__restrict__ a_in, double level,
-                                               double zq, double *__restrict__ out,
+                                               const double *__restrict__ cp_tbl,
+                                               const int64_t *__restrict__ cp_base,
+                                               double *__restrict__ out,
                                                double *__restrict__ q_out,
                                                int32_t *__restrict__ k_out,
                                                double *__restrict__ cp_out) {
@@ -173,19 +218,31 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
     int64_t t = gid / GB;
     const bool valid = t < n_tiles;
     if (!valid) t = n_tiles - 1;   // idle groups shadow the last tile and write nothing
-    double th[MAX_D];
-    for (int a = 0; a < d; ++a) th[a] = theta[t * d + a];
-    const double *V = verts + (int64_t)vert_off[t] * d;
-    const int nv = min(vert_off[t + 1] - vert_off[t], MAXV);
+    TileGeom T;
+    T.n = n;
+    T.d = d;
+    T.box = is_box[t] != 0;
+    for (int a = 0; a < d; ++a) {
+        T.th[a] = theta[t * d + a];
+        T.r[a] = radii[t * d + a];
+    }
+    T.V = verts + (int64_t)vert_off[t] * d;
+    T.nv = min(vert_off[t + 1] - vert_off[t], MAXV);
     const double zero[MAX_D] = {0.0, 0.0, 0.0, 0.0};
-    const double A0 = part<FAM>(n, d, th, 0.0, zero);
-    for (int j = lane; j < nv; j += GB) s_psi1[grp][j] = part<FAM>(n, d, th, 1.0, V + j * d) - A0;
+    T.A0 = part<FAM>(n, d, T.th, 0.0, zero);
+    for (int a = 0; a < d; ++a) {
+        T.A0a[a] = part1<FAM>(n, T.th[a]);
+        T.p1[a][0] = part1<FAM>(n, T.th[a] - T.r[a]) - T.A0a[a];
+        T.p1[a][1] = part1<FAM>(n, T.th[a] + T.r[a]) - T.A0a[a];
+    }
+    if (!T.box)
+        for (int j = lane; j < T.nv; j += GB) s_psi1[grp][j] = part<FAM>(n, d, T.th, 1.0, T.V + j * d) - T.A0;
     __syncthreads();
-    const double *psi1 = s_psi1[grp];
+    T.psi1 = s_psi1[grp];
 
     if (mode == 1) {
         double sb;
-        const double val = section_search<FAM, true>(lane, n, d, th, V, nv, psi1, A0, log(level), &sb);
+        const double val = section_search<FAM, true>(lane, T, log(level), &sb);
         if (valid && lane == 0) {
             const double ap = exp(val);
             out[t] = ap;
@@ -196,7 +253,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
     }
     double a;
     if (mode == 0) {
-        a = cp_upper((int)R[t], N[t], level, zq);
+        a = cp_tbl[cp_base[t] + (int64_t)R[t]];
         if (valid && lane == 0 && cp_out) cp_out[t] = a;
     } else {
         a = a_in[t];
@@ -209,11 +266,32 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
         return;
     }
     double sb;
-    const double val = section_search<FAM, false>(lane, n, d, th, V, nv, psi1, A0, log(a), &sb);
+    const double val = section_search<FAM, false>(lane, T, log(a), &sb);
     if (valid && lane == 0) {
         out[t] = fmin(exp(val), 1.0);
         if (q_out) q_out[t] = 1.0 + exp(sb);
     }
+}
+
+
+// Clopper-Pearson once per (N class, R) present in this call: mark, then solve marked entries.
+__global__ void k_cp_mark(int64_t n_tiles, const uint32_t *__restrict__ R, const int32_t *__restrict__ N,
+                          const int64_t *__restrict__ cp_base, uint32_t *__restrict__ mark) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const uint32_t r = min(R[t], (uint32_t)N[t]);
+    mark[cp_base[t] + r] = 1u;
+}
+
+__global__ void k_cp_table(const int32_t *__restrict__ cls_N, const int64_t *__restrict__ cls_off,
+                           const uint32_t *__restrict__ mark, double delta, double zq,
+                           double *__restrict__ tbl) {
+    const int c = blockIdx.y;
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = cls_N[c];
+    if (r > n) return;
+    const int64_t e = cls_off[c] + r;
+    if (mark[e]) tbl[e] = cp_upper(r, n, delta, zq);
 }
 
 // Upper delta quantile of N(0, 1) by bisection on erfc (host; starting point of the CP Newton).
@@ -232,18 +310,26 @@ static double normal_upper_quantile(double delta) {
 hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const double *a_in,
                         double level, double *out, double *q_out, int32_t *k_out, double *cp_out,
                         hipStream_t st) {
+    if (mode == 0) {
+        hipError_t e = launch_zero(P.d_cp_mark, (size_t)P.n_cp * sizeof(uint32_t), st);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_cp_mark, dim3((uint32_t)((P.n_tiles + 255) / 256)), dim3(256), 0, st,
+                           P.n_tiles, R, P.d_N, P.d_cp_base, P.d_cp_mark);
+        const double zq = normal_upper_quantile(level);
+        hipLaunchKernelGGL(k_cp_table, dim3((uint32_t)((P.max_cls_N + 1 + 63) / 64), (uint32_t)P.n_cls),
+                           dim3(64), 0, st, P.d_cls_N, P.d_cls_off, P.d_cp_mark, level, zq, P.d_cp_tbl);
+    }
     const int bs = 256;
     const int64_t threads = P.n_tiles * GB;
     const int64_t grid = (threads + bs - 1) / bs;
-    const double zq = mode == 0 ? normal_upper_quantile(level) : 0.0;
     if (P.family == FAM_NORMAL)
         hipLaunchKernelGGL(k_bound<FAM_NORMAL>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
-                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_N, R, a_in, level,
-                           zq, out, q_out, k_out, cp_out);
+                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, a_in, level,
+                           P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);
     else
         hipLaunchKernelGGL(k_bound<FAM_BINOM>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
-                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_N, R, a_in, level,
-                           zq, out, q_out, k_out, cp_out);
+                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, a_in, level,
+                           P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);
     return hipGetLastError();
 }
 

@@ -267,6 +267,8 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             P->tile_box.push_back(i);
             P->tile_cfg.push_back(b);
             P->tile_in_null.push_back(1);
+            P->tile_is_box.push_back(inside ? 1 : 0);
+            for (int a = 0; a < d; ++a) P->tile_radii.push_back(r[a]);
             P->tile_nv.push_back((int32_t)V.size());
             P->vert_off.push_back((int32_t)(P->verts.size() / d));
             for (auto &v : V)
@@ -276,6 +278,8 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             P->tile_box.push_back(i);
             P->tile_cfg.push_back(1);
             P->tile_in_null.push_back(0);
+            P->tile_is_box.push_back(1);
+            for (int a = 0; a < d; ++a) P->tile_radii.push_back(r[a]);
             P->tile_nv.push_back(ncorner);
             P->vert_off.push_back((int32_t)(P->verts.size() / d));
             for (auto &v : corners)
@@ -466,6 +470,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
                 for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
                 it.k_begin = (uint32_t)k0;
                 it.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
+                P->group_sims += (int64_t)(it.k_end - it.k_begin);
                 gi.push_back(it);
             }
         }
@@ -477,7 +482,31 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     if (int e = upload(&P->d_N, P->tile_N.data(), P->tile_N.size())) return e;
     if (int e = upload(&P->d_vert_off, P->vert_off.data(), P->vert_off.size())) return e;
     if (int e = upload(&P->d_verts, P->verts.data(), P->verts.size())) return e;
+    if (int e = upload(&P->d_radii, P->tile_radii.data(), P->tile_radii.size())) return e;
+    if (int e = upload(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size())) return e;
     if (int e = upload(&P->d_key_off, key_off.data(), key_off.size())) return e;
+    // N classes for the Clopper-Pearson table
+    {
+        std::vector<int32_t> cls(P->tile_N.begin(), P->tile_N.end());
+        std::sort(cls.begin(), cls.end());
+        cls.erase(std::unique(cls.begin(), cls.end()), cls.end());
+        std::vector<int64_t> off(cls.size()), base(P->n_tiles);
+        int64_t e = 0;
+        for (size_t c = 0; c < cls.size(); ++c) {
+            off[c] = e;
+            e += (int64_t)cls[c] + 1;
+            P->max_cls_N = std::max(P->max_cls_N, cls[c]);
+        }
+        for (int64_t t = 0; t < P->n_tiles; ++t)
+            base[t] = off[std::lower_bound(cls.begin(), cls.end(), P->tile_N[t]) - cls.begin()];
+        P->n_cls = (int32_t)cls.size();
+        P->n_cp = e;
+        if (int r = upload(&P->d_cls_N, cls.data(), cls.size())) return r;
+        if (int r = upload(&P->d_cls_off, off.data(), off.size())) return r;
+        if (int r = upload(&P->d_cp_base, base.data(), base.size())) return r;
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_cp_mark, (size_t)e * sizeof(uint32_t)));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_cp_tbl, (size_t)e * sizeof(double)));
+    }
     const size_t nt = (size_t)P->n_tiles;
     CSE_HIP_TRY(hipMalloc((void **)&P->d_Rw, nt * sizeof(uint32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_Tw, nt * d * sizeof(unsigned long long)));
@@ -495,7 +524,9 @@ void free_platten(Platten *P) {
     void *ptrs[] = {P->d_theta, P->d_N,    P->d_vert_off, P->d_verts,   P->d_key_off,
                     P->d_blocks, P->d_items, P->d_gitems, P->d_cut_tbl, P->d_S_tbl,  P->d_S_order,
                     P->d_S_group, P->d_keys, P->d_Rw,      P->d_Tw,     P->d_Zw,
-                    P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg};
+                    P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
+                    P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
+                    P->d_is_box};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }

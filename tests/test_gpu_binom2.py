@@ -178,3 +178,49 @@ def test_score_gradient_vs_central_differences_crn():
         flips = np.abs(fd) * N * 2 * h + 1.0
         tol = 5 * (35 / math.sqrt(N)) + 5 * np.sqrt(flips) / (N * 2 * h)
         assert np.all(np.abs(fd - g[:, a]) <= tol)
+
+
+def test_cse_bound_modes_vs_oracle():
+    """cse_bound without simulation: mode 0 (CP + tilt) for arbitrary counts including R = 0 and
+    R = N, mode 1 (alpha'), mode 2 (tilt of a given f(theta_i))."""
+    w = W.binom2_grid(12, 999, seed=0)
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("binom2", th, rd, sm)
+    n = P.n_tiles
+    rng = np.random.default_rng(5)
+    R = rng.integers(0, 999, n).astype(np.int32)
+    R[:3] = [0, 999, 998]
+    Rt = torch.tensor(R, device="cuda")
+    a = rng.uniform(0.0, 0.3, n)
+    a[:2] = [0.0, 1.0]
+    at = torch.tensor(a, device="cuda")
+    b0, _ = P.bound(0, R=Rt, level=0.05)
+    b1, _ = P.bound(1, level=0.1)
+    b2, _ = P.bound(2, a=at)
+    torch.cuda.synchronize()
+    subs = O.subtiles("binom2", th, rd)
+    V = O._pad_vertices(subs, th)
+    box = np.array([s[0] for s in subs])
+    cp = O.cp_upper(R, sm[box], 0.05)
+    e0, _ = O.tile_bound("binom", th[box], V, cp)
+    e1, _ = O.tile_inverse("binom", th[box], V, 0.1)
+    e2, _ = O.tile_bound("binom", th[box], V, a)
+    np.testing.assert_allclose(_np(b0), e0, rtol=RTOL_BOUND)
+    np.testing.assert_allclose(_np(b1), e1, rtol=RTOL_BOUND)
+    np.testing.assert_allclose(_np(b2), e2, rtol=RTOL_BOUND, atol=1e-300)
+    assert _np(b0)[1] == 1.0 and _np(b2)[0] == 0.0 and _np(b2)[1] == 1.0
+    P.close()
+
+
+def test_paper_worked_value_through_gpu_bound():
+    """The optimized Tilt-Bound of the z-test at theta0 = -0.25, v = 0.25 with the exact
+    f(theta0) is 2.73% (Section 4.3); the GPU bound kernel on the tile [-0.5, 0] reproduces it."""
+    from scipy import stats
+    P = cse.Platten.create("ztest1", np.array([[-0.25]]), np.array([[0.25]]), np.array([100], np.int32))
+    f0 = stats.norm.cdf(-0.25 - stats.norm.ppf(0.975))
+    b, _ = P.bound(2, a=torch.tensor([f0], device="cuda"))
+    torch.cuda.synchronize()
+    assert round(100 * float(_np(b)[0]), 2) == 2.73
+    L = -math.log(f0)
+    assert float(_np(b)[0]) == pytest.approx(math.exp(-(math.sqrt(L) - 0.25 / math.sqrt(2)) ** 2), rel=1e-10)
+    P.close()
