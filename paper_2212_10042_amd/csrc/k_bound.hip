@@ -13,15 +13,15 @@
 #include <math.h>
 
 #include "cse_internal.h"
+#include "fp64_math.hpp"
 #include "kernels.h"
 
 namespace cse {
 
 constexpr int MAXV = 64;   // vertices per tile handled by the bound kernel
 
-__device__ __forceinline__ double softplus(double x) {
-    return x > 0.0 ? x + log1p(exp(-x)) : log1p(exp(x));
-}
+// log(1 + e^x), the Bernoulli log partition per patient in logit parametrisation
+__device__ __forceinline__ double softplus(double x) { return softplus_fast(x); }
 
 // ---- regularized incomplete beta ----
 __device__ double lbeta(double a, double b) { return lgamma(a) + lgamma(b) - lgamma(a + b); }
@@ -105,10 +105,11 @@ __device__ double cp_upper(int R, int N, double delta, double z) {
 constexpr int GB = 8;
 constexpr int SECTION_ROUNDS = 14;     // bracket 60 * (2/9)^14 ~ 4e-8 in s
 
-template <int FAM>
-__device__ __forceinline__ double part(int n, int d, const double *th, double q, const double *v) {
+template <int FAM, int D>
+__device__ __forceinline__ double part(int n, const double *th, double q, const double *v) {
     double s = 0.0;
-    for (int a = 0; a < d; ++a) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
         const double x = th[a] + q * v[a];
         s += (FAM == FAM_NORMAL) ? 0.5 * x * x : softplus(x);
     }
@@ -120,13 +121,15 @@ __device__ __forceinline__ double part1(int n, double x) {
     return (FAM == FAM_NORMAL) ? 0.5 * x * x : (double)n * softplus(x);
 }
 
-// One tile's data for the search over q.
+// One tile's data for the search over q (D = parameter dimension, a compile-time constant so
+// the per-arm arrays stay in registers).
+template <int D>
 struct TileGeom {
-    int n, d, nv;
+    int n, nv;
     bool box;                 // whole box: the objective is separable over arms
-    double th[MAX_D], r[MAX_D];
-    double A0a[MAX_D];        // per-arm log partition at theta (box form)
-    double p1[MAX_D][2];      // per-arm psi(theta, -r / +r, 1) (box form)
+    double th[D], r[D];
+    double A0a[D];            // per-arm log partition at theta (box form)
+    double p1[D][2];          // per-arm psi(theta, -r / +r, 1) (box form)
     const double *V;          // vertex displacements (general form)
     const double *psi1;       // per-vertex psi(theta, v, 1) (general form)
     double A0;
@@ -136,11 +139,12 @@ struct TileGeom {
 // For a whole box A is a sum over arms and the vertices are all sign patterns (+-r_a), so the
 // maximum is the sum over arms of the larger of the two one-arm terms (same value as the
 // vertex loop, 2d instead of d 2^d log-partition terms).
-template <int FAM>
-__device__ double max_tilt_term(const TileGeom &T, double q) {
+template <int FAM, int D>
+__device__ double max_tilt_term(const TileGeom<D> &T, double q) {
     if (T.box) {
         double s = 0.0;
-        for (int a = 0; a < T.d; ++a) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
             const double lo = (part1<FAM>(T.n, T.th[a] - q * T.r[a]) - T.A0a[a]) / q - T.p1[a][0];
             const double hi = (part1<FAM>(T.n, T.th[a] + q * T.r[a]) - T.A0a[a]) / q - T.p1[a][1];
             s += fmax(lo, hi);
@@ -149,7 +153,7 @@ __device__ double max_tilt_term(const TileGeom &T, double q) {
     }
     double w = -1e300;
     for (int j = 0; j < T.nv; ++j) {
-        const double psiq = part<FAM>(T.n, T.d, T.th, q, T.V + j * T.d) - T.A0;
+        const double psiq = part<FAM, D>(T.n, T.th, q, T.V + j * D) - T.A0;
         w = fmax(w, psiq / q - T.psi1[j]);
     }
     return w;
@@ -157,21 +161,21 @@ __device__ double max_tilt_term(const TileGeom &T, double q) {
 
 // log U (forward, max over vertices) or log U^{-1} (inverse, min over vertices); the inverse's
 // min over v of q/(q-1) (log alpha - psi_q/q + psi_1) is q/(q-1) (log alpha - max_v(...)).
-template <int FAM, bool INV>
-__device__ double objective(const TileGeom &T, double loga, double s) {
-    const double q = 1.0 + exp(s);
-    const double m = max_tilt_term<FAM>(T, q);
+template <int FAM, int D, bool INV>
+__device__ double objective(const TileGeom<D> &T, double loga, double s) {
+    const double q = 1.0 + exp_cw(s);
+    const double m = max_tilt_term<FAM, D>(T, q);
     return INV ? q / (q - 1.0) * (loga - m) : (1.0 - 1.0 / q) * loga + m;
 }
 
-template <int FAM, bool INV>
-__device__ double section_search(int lane, const TileGeom &T, double loga, double *s_best) {
+template <int FAM, int D, bool INV>
+__device__ double section_search(int lane, const TileGeom<D> &T, double loga, double *s_best) {
     const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
     double lo = -30.0, hi = 30.0;
     double best = INFINITY, bs = 0.0;
     for (int r = 0; r < SECTION_ROUNDS; ++r) {
         const double h = (hi - lo) / (double)(GB + 1);
-        double f = sg * objective<FAM, INV>(T, loga, lo + (lane + 1) * h);
+        double f = sg * objective<FAM, D, INV>(T, loga, lo + (lane + 1) * h);
         if (f != f) f = INFINITY;
         int jm = lane;
 #pragma unroll
@@ -196,8 +200,8 @@ __device__ double section_search(int lane, const TileGeom &T, double loga, doubl
 }
 
 // mode 0: validate (CP then tilt), mode 1: invert (alpha', k), mode 2: tilt of given a.
-template <int FAM>
-__global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n_tiles,
+template <int FAM, int D>
+__global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
                                                const double *__restrict__ theta,
                                                const int32_t *__restrict__ vert_off,
                                                const double *__restrict__ verts,
@@ -218,35 +222,38 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
     int64_t t = gid / GB;
     const bool valid = t < n_tiles;
     if (!valid) t = n_tiles - 1;   // idle groups shadow the last tile and write nothing
-    TileGeom T;
+    TileGeom<D> T;
     T.n = n;
-    T.d = d;
     T.box = is_box[t] != 0;
-    for (int a = 0; a < d; ++a) {
-        T.th[a] = theta[t * d + a];
-        T.r[a] = radii[t * d + a];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        T.th[a] = theta[t * D + a];
+        T.r[a] = radii[t * D + a];
     }
-    T.V = verts + (int64_t)vert_off[t] * d;
+    T.V = verts + (int64_t)vert_off[t] * D;
     T.nv = min(vert_off[t + 1] - vert_off[t], MAXV);
-    const double zero[MAX_D] = {0.0, 0.0, 0.0, 0.0};
-    T.A0 = part<FAM>(n, d, T.th, 0.0, zero);
-    for (int a = 0; a < d; ++a) {
+    double zero[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) zero[a] = 0.0;
+    T.A0 = part<FAM, D>(n, T.th, 0.0, zero);
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
         T.A0a[a] = part1<FAM>(n, T.th[a]);
         T.p1[a][0] = part1<FAM>(n, T.th[a] - T.r[a]) - T.A0a[a];
         T.p1[a][1] = part1<FAM>(n, T.th[a] + T.r[a]) - T.A0a[a];
     }
     if (!T.box)
-        for (int j = lane; j < T.nv; j += GB) s_psi1[grp][j] = part<FAM>(n, d, T.th, 1.0, T.V + j * d) - T.A0;
+        for (int j = lane; j < T.nv; j += GB) s_psi1[grp][j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
     __syncthreads();
     T.psi1 = s_psi1[grp];
 
     if (mode == 1) {
         double sb;
-        const double val = section_search<FAM, true>(lane, T, log(level), &sb);
+        const double val = section_search<FAM, D, true>(lane, T, log(level), &sb);
         if (valid && lane == 0) {
             const double ap = exp(val);
             out[t] = ap;
-            if (q_out) q_out[t] = 1.0 + exp(sb);
+            if (q_out) q_out[t] = 1.0 + exp_cw(sb);
             if (k_out) k_out[t] = (int32_t)floor(((double)N[t] + 1.0) * ap);
         }
         return;
@@ -266,7 +273,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int d, int64_t n
         return;
     }
     double sb;
-    const double val = section_search<FAM, false>(lane, T, log(a), &sb);
+    const double val = section_search<FAM, D, false>(lane, T, log(a), &sb);
     if (valid && lane == 0) {
         out[t] = fmin(exp(val), 1.0);
         if (q_out) q_out[t] = 1.0 + exp(sb);
@@ -322,14 +329,19 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
     const int bs = 256;
     const int64_t threads = P.n_tiles * GB;
     const int64_t grid = (threads + bs - 1) / bs;
-    if (P.family == FAM_NORMAL)
-        hipLaunchKernelGGL(k_bound<FAM_NORMAL>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
-                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, a_in, level,
-                           P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);
+#define CSE_BOUND_LAUNCH(FAM, D)                                                                  \
+    hipLaunchKernelGGL((k_bound<FAM, D>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,   \
+                       P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
+                       a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out)
+    if (P.family == FAM_NORMAL && P.d == 1)
+        CSE_BOUND_LAUNCH(FAM_NORMAL, 1);
+    else if (P.family == FAM_BINOM && P.d == 2)
+        CSE_BOUND_LAUNCH(FAM_BINOM, 2);
+    else if (P.family == FAM_BINOM && P.d == 4)
+        CSE_BOUND_LAUNCH(FAM_BINOM, 4);
     else
-        hipLaunchKernelGGL(k_bound<FAM_BINOM>, dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,
-                           P.d, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, a_in, level,
-                           P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);
+        return hipErrorInvalidValue;
+#undef CSE_BOUND_LAUNCH
     return hipGetLastError();
 }
 

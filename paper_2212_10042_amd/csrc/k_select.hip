@@ -65,14 +65,25 @@ __global__ __launch_bounds__(SEL_WG) void k_select_outcomes(
     // eight threads read one chunk as eight 16-byte pieces
     const uint16_t *__restrict__ kt = keys + key_off[t];
     const int nch = (n + WAVE - 1) / WAVE;
-    for (int j = tid; j < nch * 8; j += SEL_WG) {
-        const int c = j >> 3, piece = j & 7;
-        const int k0 = c * WAVE + piece * 8;
-        const uint4 v = *reinterpret_cast<const uint4 *>(kt + (int64_t)c * KEY_CHUNK + piece * 8);
-        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    constexpr int LPT = 4;   // 16-byte loads in flight per thread before its LDS atomics
+    for (int j0 = tid; j0 < nch * 8; j0 += SEL_WG * LPT) {
+        uint4 v[LPT];
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-            if (k0 + e < n) atomicAdd(&hist[(w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+        for (int l = 0; l < LPT; ++l) {
+            const int j = j0 + l * SEL_WG;
+            if (j < nch * 8)
+                v[l] = *reinterpret_cast<const uint4 *>(kt + (int64_t)(j >> 3) * KEY_CHUNK + (j & 7) * 8);
+        }
+#pragma unroll
+        for (int l = 0; l < LPT; ++l) {
+            const int j = j0 + l * SEL_WG;
+            if (j >= nch * 8) break;
+            const int k0 = (j >> 3) * WAVE + (j & 7) * 8;
+            const uint32_t w[4] = {v[l].x, v[l].y, v[l].z, v[l].w};
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (k0 + e < n) atomicAdd(&hist[(w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+        }
     }
     __syncthreads();
     if (tid >= WAVE) return;
