@@ -8,18 +8,19 @@
  * The statistic of treatment arm i is P(p_i > p_0 | y) = P(theta_i > theta_0 | y).
  *
  * The paper gives the model but not how its posterior is computed.  Reading used here:
- *   1. mu is integrated out exactly: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T.
+ *   1. mu is integrated out exactly: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T, with
+ *      Sigma^{-1} and log|Sigma| in closed form (Sherman-Morrison, determinant lemma).
  *   2. For each of 90 nodes s2_j (equally spaced in log s2 over [log 1e-6, log 1e3]), the
  *      conditional posterior of theta is replaced by its Laplace (Gaussian) approximation:
  *      mode by Newton's method, covariance C_j = (-H)^{-1} at the mode.
  *   3. Node weights: Laplace evidence  l(mode) + log|Q| / 2 - log|-H| / 2  (Q = Sigma^{-1}),
  *      plus the log prior density of s2_j, plus the log trapezoid weight in log s2
  *      (ds2 = s2 dlog s2); normalised by log-sum-exp in float64.
- *   4. P_i(y) = sum_j pi_j Phi((mode_i - mode_0) / sqrt(C_ii + C_00 - 2 C_i0)).
+ *   4. P_i(y) = sum_j pi_j Phi((mode_i - mode_0) / sd), sd^2 = Var(theta_i - theta_0) under C_j.
  * Property of this reading: at the boundary counts y_i in {0, n} the Gaussian replacing the
  * skewed conditional posterior is very wide, so P_i is not monotone there (it is monotone
  * for interior counts).
- * All float64, generic 4x4 linear algebra (Gaussian elimination), no structure exploited.
+ * All float64; the Newton systems and variances by generic 4x4 Gaussian elimination.
  */
 #include <math.h>
 #include <stdint.h>
@@ -81,7 +82,7 @@ static double logdet4(const double M[D][D]) {
     return ld;
 }
 
-static void inverse4(const double M[D][D], double Inv[D][D]) {
+static __attribute__((unused)) void inverse4(const double M[D][D], double Inv[D][D]) {
     for (int k = 0; k < D; ++k) {
         double A[D][D], e[D] = {0}, x[D];
         memcpy(A, M, sizeof A);
@@ -111,11 +112,15 @@ void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_m
         double ls2, logtrap;
         orc_hier4_node(j, &ls2, &logtrap);
         double s2 = exp(ls2);
-        /* Q = Sigma^{-1}, Sigma = s2 I + TAU2 11^T */
-        double Sig[D][D], Q[D][D];
+        /* Q = Sigma^{-1} for Sigma = s2 I + TAU2 11^T, in closed form (Sherman-Morrison):
+         * Q = (I - cq 11^T) / s2 with cq = TAU2 / (s2 + D TAU2).  (Inverting Sigma numerically
+         * loses ~8 digits: its condition number is (s2 + D TAU2) / s2, ~4e8 at s2 = 1e-6.) */
+        double Q[D][D];
+        const double cq = TAU2 / (s2 + D * TAU2);
         for (int r = 0; r < D; ++r)
-            for (int c = 0; c < D; ++c) Sig[r][c] = TAU2 + (r == c ? s2 : 0.0);
-        inverse4(Sig, Q);
+            for (int c = 0; c < D; ++c) Q[r][c] = ((r == c ? 1.0 : 0.0) - cq) / s2;
+        /* log|Q| = -log|Sigma| = -((D - 1) log s2 + log(s2 + D TAU2)) (matrix determinant lemma) */
+        const double logdetQ = -((D - 1) * ls2 + log(s2 + D * TAU2));
         double th[D];
         for (int a = 0; a < D; ++a) th[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
         int it = 0;
@@ -149,19 +154,25 @@ void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_m
                 double p = expit(th[r]);
                 H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
             }
-        double negH[D][D], C[D][D];
+        double negH[D][D];
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) negH[r][c] = -H[r][c];
-        inverse4(negH, C);
         double ll = 0.0, quad = 0.0;
         for (int a = 0; a < D; ++a) ll += y[a] * th[a] - n * softplus(th[a]);
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) quad += (th[r] - M0) * Q[r][c] * (th[c] - M0);
-        double lap = ll - 0.5 * quad + 0.5 * logdet4(Q) - 0.5 * logdet4(negH);
+        double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet4(negH);
         double logprior = IG_A * log(IG_B) - lgamma(IG_A) - (IG_A + 1.0) * ls2 - IG_B / s2;
         lw[j] = lap + logprior + logtrap;
         for (int i = 1; i < D; ++i) {
-            double sd = sqrt(C[i][i] + C[0][0] - 2.0 * C[i][0]);
+            /* Var(theta_i - theta_0) = e^T C e = e^T x with (-H) x = e, e = e_i - e_0: solving for
+             * x avoids the cancellation in C_ii + C_00 - 2 C_i0 when the arms are tightly linked */
+            double A[D][D], e[D] = {0, 0, 0, 0}, x[D];
+            memcpy(A, negH, sizeof A);
+            e[i] = 1.0;
+            e[0] = -1.0;
+            solve4(A, e, x);
+            double sd = sqrt(x[i] - x[0]);
             pr[j][i - 1] = Phi((th[i] - th[0]) / sd);
         }
         if (diag_mode)
