@@ -59,6 +59,7 @@ def lib():
         L.orc_binom2.argtypes = [i64, P, P, u64, ctypes.c_int, dbl, P, P, P, i64]
         L.orc_arm_counts.argtypes = [ctypes.c_int, P, i32, u64, ctypes.c_int, P]
         L.orc_hier4_posterior.argtypes = [P, ctypes.c_int, P]
+        L.orc_hier4_complement.argtypes = [P, ctypes.c_int, P]
         L.orc_hier4_posterior_full.argtypes = [P, ctypes.c_int, P, P, P, P]
         L.orc_hier4_node.argtypes = [ctypes.c_int, P, P]
         L.orc_hier4_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, dbl, P, P, P, i64, P]
@@ -127,6 +128,39 @@ def sim_binom2(theta, sims, seed: int, cut: float = 1.96, n: int = N_PER_ARM, wa
     S = np.full((m, stride), np.nan) if want_S else None
     lib().orc_binom2(m, _p(th), _p(sm), seed, n, cut, _p(R), _p(sT), _p(S), stride)
     return R, sT, S
+
+
+def hier4_posterior(y, n: int = N_PER_ARM) -> np.ndarray:
+    """P(p_i > p_0 | y), i = 1..3, of the 4-arm hierarchical model (oracle_hier.c, Section 10.1)."""
+    yy = np.ascontiguousarray(y, np.int32)
+    P = np.zeros(3)
+    lib().orc_hier4_posterior(_p(yy), n, _p(P))
+    return P
+
+
+def hier4_table(idx, n: int = N_PER_ARM) -> np.ndarray:
+    """The design statistics 1 - P(p_i > p_0 | y) [len(idx), 3] for outcome indices
+    ((y0 m + y1) m + y2) m + y3, m = n + 1 (summed as complements, oracle_hier.c)."""
+    ii = np.ascontiguousarray(idx, np.int64)
+    out = np.zeros((ii.size, 3))
+    lib().orc_hier4_table(n, _p(ii), ii.size, _p(out))
+    return out
+
+
+def sim_hier4(theta_tiles, cfg, sims, seed: int, cut: float, n: int = N_PER_ARM, want_S: bool = False):
+    """4-arm design per tile (box centre, null configuration b): R = #{S_b < cut}, sumT [m, 4],
+    optionally S_b per simulation (float64) and the outcome index of every simulation."""
+    th = np.ascontiguousarray(np.asarray(theta_tiles, np.float64).reshape(-1, 4))
+    cf = np.ascontiguousarray(cfg, np.int32)
+    sm = np.ascontiguousarray(sims, np.int32)
+    m = th.shape[0]
+    R = np.zeros(m, np.int32)
+    sT = np.zeros((m, 4), np.int64)
+    stride = int(sm.max()) if m else 0
+    S = np.full((m, stride), np.nan) if want_S else None
+    Y = np.full((m, stride), -1, np.int64) if want_S else None
+    lib().orc_hier4_sim(m, _p(th), _p(cf), _p(sm), seed, n, cut, _p(R), _p(sT), _p(S), stride, _p(Y))
+    return R, sT, S, Y
 
 
 # --------------------------------------------------- exponential families
@@ -359,20 +393,35 @@ def score_gradient(design: str, theta, R, score, sims, n: int = N_PER_ARM):
     return (np.asarray(score, np.float64) - np.asarray(R, np.float64)[:, None] * gA) / N[:, None]
 
 
+def _tile_simulation(design, theta, sims, subs, seed, cut, want_S):
+    """Per-tile (R, score, S) for the tiles `subs`: single-hypothesis designs simulate per box;
+    the 4-arm design per (box, b) because its event depends on b."""
+    box = np.array([s[0] for s in subs])
+    if design == "hier4":
+        cfg = np.array([s[1] for s in subs], np.int32)
+        R, sT, S, _ = sim_hier4(theta[box], cfg, np.asarray(sims)[box], seed, cut, want_S=want_S)
+        return R, sT, S
+    R, score, S = simulate(design, theta, sims, seed, cut, want_S)
+    return R[box], score[box], (S[box] if S is not None else None)
+
+
 def validate(design: str, theta, radii, sims, seed: int, delta: float, cut: float = 1.96,
              keep_all: bool = False):
     """Validation (Algorithm 1): per sub-tile R, CP upper bound, tilewise optimized Tilt-Bound."""
     theta = np.asarray(theta, np.float64)
     subs = subtiles(design, theta, radii, keep_all)
-    R, score, _ = simulate(design, theta, sims, seed, cut)
     box = np.array([s[0] for s in subs])
     N = np.asarray(sims)[box]
-    Rb = R[box]
+    Rb, score, _ = _tile_simulation(design, theta, sims, subs, seed, cut, False)
     cp = cp_upper(Rb, N, delta)
     V = _pad_vertices(subs, theta)
     ub, qs = tile_bound(family_of(design), theta[box], V, cp)
-    return dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
-                q=qs, R_box=R, score_box=score, subs=subs)
+    out = dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
+               q=qs, score=score, subs=subs)
+    if design != "hier4":
+        R, sc, _ = simulate(design, theta, sims, seed, cut)
+        out.update(R_box=R, score_box=sc)
+    return out
 
 
 def order_statistic(S_row: np.ndarray, k: int) -> float:
@@ -382,9 +431,12 @@ def order_statistic(S_row: np.ndarray, k: int) -> float:
     return float(np.sort(S_row)[k - 1])
 
 
-def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False):
+def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False,
+              key_dtype=np.float64, cut: float = 1.96):
     """Calibration (Algorithm 2): alpha'_i, k_i = floor((N_i+1) alpha'_i), lambda*_i = S_(k_i),
-    lambda* = min_i lambda*_i, and #{S < lambda*_i} per sub-tile."""
+    lambda* = min_i lambda*_i, and #{S < lambda*_i} per sub-tile.  key_dtype=np.float32 takes the
+    order statistic and the comparisons in float32 (the precision in which the GPU compares
+    the 4-arm statistic)."""
     theta = np.asarray(theta, np.float64)
     sims = np.asarray(sims, np.int32)
     subs = subtiles(design, theta, radii, keep_all)
@@ -393,13 +445,13 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
     ap, qs = tile_inverse(family_of(design), theta[box], V, alpha)
     N = sims[box]
     k = np.floor((N + 1.0) * ap).astype(np.int64)
-    _, _, S = simulate(design, theta, sims, seed, 1.96, want_S=True)
+    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True)
     lam = np.empty(len(subs))
     rej = np.empty(len(subs), np.int64)
-    for t, i in enumerate(box):
-        row = S[i, : sims[i]]
+    for t in range(len(subs)):
+        row = S[t, : N[t]].astype(key_dtype)
         lam[t] = order_statistic(row, int(k[t]))
-        rej[t] = int(np.sum(row < lam[t]))
+        rej[t] = int(np.sum(row < key_dtype(lam[t]) if np.isfinite(lam[t]) else 0))
     return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, q=qs, k=k,
                 lam=lam, lam_global=float(lam.min()) if len(lam) else math.inf,
                 reject_at_lam=rej, N=N, subs=subs)

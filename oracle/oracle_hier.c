@@ -105,9 +105,9 @@ void orc_hier4_node(int j, double *ls2, double *logw) {
 /* Posterior of one outcome y (counts out of n per arm).  Outputs P[3] = P(theta_i > theta_0 | y)
  * for i = 1, 2, 3; if diag != NULL also per-node mode [NODES][D], log weight [NODES] and
  * Newton iterations [NODES] (for the tests). */
-void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_mode,
-                              double *diag_logw, int32_t *diag_iters) {
-    double lw[NODES], pr[NODES][3];
+static void posterior_full(const int32_t *y, int n, double *P, double *Sc, double *diag_mode,
+                           double *diag_logw, int32_t *diag_iters) {
+    double lw[NODES], pr[NODES][3], pc[NODES][3];
     for (int j = 0; j < NODES; ++j) {
         double ls2, logtrap;
         orc_hier4_node(j, &ls2, &logtrap);
@@ -174,6 +174,7 @@ void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_m
             solve4(A, e, x);
             double sd = sqrt(x[i] - x[0]);
             pr[j][i - 1] = Phi((th[i] - th[0]) / sd);
+            pc[j][i - 1] = Phi(-(th[i] - th[0]) / sd);   /* 1 - Phi(z), no cancellation */
         }
         if (diag_mode)
             for (int a = 0; a < D; ++a) diag_mode[j * D + a] = th[a];
@@ -184,19 +185,37 @@ void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_m
     double s = 0.0;
     for (int j = 0; j < NODES; ++j) s += exp(lw[j] - mx);
     double lse = mx + log(s);
-    for (int i = 0; i < 3; ++i) P[i] = 0.0;
+    for (int i = 0; i < 3; ++i) P[i] = Sc[i] = 0.0;
     for (int j = 0; j < NODES; ++j) {
         double pj = exp(lw[j] - lse);
         if (diag_logw) diag_logw[j] = lw[j] - lse;
-        for (int i = 0; i < 3; ++i) P[i] += pj * pr[j][i];
+        for (int i = 0; i < 3; ++i) {
+            P[i] += pj * pr[j][i];
+            Sc[i] += pj * pc[j][i];
+        }
     }
 }
 
-void orc_hier4_posterior(const int32_t *y, int n, double *P) {
-    orc_hier4_posterior_full(y, n, P, NULL, NULL, NULL);
+void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_mode,
+                              double *diag_logw, int32_t *diag_iters) {
+    double Sc[3];
+    posterior_full(y, n, P, Sc, diag_mode, diag_logw, diag_iters);
 }
 
-/* Posterior statistics for a list of outcome indices idx = ((y0*(n+1)+y1)*(n+1)+y2)*(n+1)+y3. */
+void orc_hier4_posterior(const int32_t *y, int n, double *P) {
+    double Sc[3];
+    posterior_full(y, n, P, Sc, NULL, NULL, NULL);
+}
+
+/* The design statistic 1 - P_i(y) summed as sum_j pi_j Phi(-z_j): relative precision for
+ * small values, which a subtraction 1 - P would lose when P is near 1. */
+void orc_hier4_complement(const int32_t *y, int n, double *S) {
+    double P[3];
+    posterior_full(y, n, P, S, NULL, NULL, NULL);
+}
+
+/* The statistics 1 - P_i(y), i = 1..3, for a list of outcome indices
+ * idx = ((y0*(n+1)+y1)*(n+1)+y2)*(n+1)+y3. */
 void orc_hier4_table(int n, const int64_t *idx, int64_t count, double *out /* [count][3] */) {
     const int64_t m = n + 1;
     for (int64_t t = 0; t < count; ++t) {
@@ -206,7 +225,7 @@ void orc_hier4_table(int n, const int64_t *idx, int64_t count, double *out /* [c
             y[a] = (int32_t)(v % m);
             v /= m;
         }
-        orc_hier4_posterior(y, n, out + 3 * t);
+        orc_hier4_complement(y, n, out + 3 * t);
     }
 }
 
@@ -235,7 +254,7 @@ static const double *memo_posterior(const int32_t *y, int n) {
     }
     int64_t idx = ((y[0] * m + y[1]) * m + y[2]) * m + y[3];
     if (!g_have[idx]) {
-        orc_hier4_posterior(y, n, g_memo + 3 * idx);
+        orc_hier4_complement(y, n, g_memo + 3 * idx);
         g_have[idx] = 1;
     }
     return g_memo + 3 * idx;
@@ -257,10 +276,10 @@ void orc_hier4_sim(int64_t n_tiles, const double *theta, const int32_t *cfg, con
                 for (int j = 0; j < n; ++j)
                     if (orc_word(seed, (uint32_t)k, (uint32_t)(a * n + j)) < T[a]) y[a] += 1;
             }
-            const double *P = memo_posterior(y, n);
+            const double *Sc = memo_posterior(y, n);   /* 1 - P_i(y) */
             double s = INFINITY;
             for (int i = 1; i < D; ++i)
-                if ((cfg[t] >> (i - 1)) & 1) s = fmin(s, 1.0 - P[i - 1]);
+                if ((cfg[t] >> (i - 1)) & 1) s = fmin(s, Sc[i - 1]);
             if (s < cut) {
                 r += 1;
                 for (int a = 0; a < D; ++a) st[a] += y[a];

@@ -154,3 +154,47 @@ def test_laplace_node_weights_match_quadrature_at_large_n():
     gh = np.array(gh) - gh[0]
     orc = np.array(orc) - orc[0]
     np.testing.assert_allclose(orc, gh, atol=5e-3)
+
+
+def comp(y, n=N):
+    y = np.asarray(y, np.int32)
+    S = np.zeros(3)
+    O.lib().orc_hier4_complement(O._p(y), n, O._p(S))
+    return S
+
+
+@pytest.mark.parametrize("y", [(2, 33, 17, 34), (3, 32, 30, 31), (12, 30, 5, 20)])
+def test_complement_keeps_relative_precision(y):
+    """1 - P_i(y) equals P_i of the outcome with arms i and 0 swapped (exchangeability); where
+    P_i(y) is near 1 the statistic is tiny and must still agree to relative precision, and it
+    must equal 1 - P_i(y) in absolute terms."""
+    S = comp(y)
+    P = post(y)
+    np.testing.assert_allclose(S, 1.0 - P, rtol=0, atol=1e-14)
+    for i in range(1, 4):
+        ys = list(y)
+        ys[0], ys[i] = ys[i], ys[0]
+        assert S[i - 1] == pytest.approx(post(ys)[i - 1], rel=1e-9, abs=0)
+    assert S.min() < 1e-4   # the cases reach the small-statistic regime
+
+
+def test_design_simulation_reduces_to_counts_and_posteriors():
+    """The 4-arm design simulation of a tile equals: arm counts from the Bernoulli draws
+    (pinned in test_oracle_designs.py), S_b = min over the true nulls i in b of 1 - P_i(y),
+    a rejection when S_b < cut, and the score sums over the rejected simulations."""
+    theta = np.array([[-1.0, -0.2, -1.3, 0.4], [-0.5, -0.5, -0.5, -0.5], [0.3, -2.0, 0.9, 0.3]])
+    cfg = np.array([7, 1, 6], np.int32)
+    sims = np.array([60, 45, 30], np.int32)
+    seed, cut = 11, 0.3
+    R, sT, S, Y = O.sim_hier4(theta, cfg, sims, seed, cut, want_S=True)
+    M = N + 1
+    for t in range(3):
+        y = O.arm_counts(theta[t], int(sims[t]), seed)
+        idx = ((y[:, 0] * M + y[:, 1]) * M + y[:, 2]) * M + y[:, 3]
+        assert np.array_equal(Y[t, : sims[t]], idx)
+        bits = [i for i in range(1, 4) if (cfg[t] >> (i - 1)) & 1]
+        want = np.array([min(1.0 - post(yk)[i - 1] for i in bits) for yk in y])
+        np.testing.assert_allclose(S[t, : sims[t]], want, rtol=0, atol=1e-14)
+        rej = S[t, : sims[t]] < cut
+        assert R[t] == rej.sum() and 0 < R[t] < sims[t]
+        assert np.array_equal(sT[t], y[rej].sum(axis=0))
