@@ -184,12 +184,26 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
                           int64_t tile_end, int32_t *reject, void *stream);
 
 /*
+ * cse_posterior_table -- the design table of a CSE_HIER4 platten: for every outcome
+ * y in {0..n}^4 (index ((y0 (n+1) + y1) (n+1) + y2) (n+1) + y3) the float32 values
+ * (1 - P(p_1 > p_0 | y), 1 - P(p_2 > p_0 | y), 1 - P(p_3 > p_0 | y), 0) of the hierarchical
+ * model of Section 10.1 (posterior by 90-node quadrature over sigma^2, computed in float64
+ * when the platten is created).
+ *   out       device float32 [capacity] (4 floats per outcome), written on `stream`; may be NULL
+ *   n_out     host, receives the number of outcomes ((n+1)^4)
+ * Errors: CSE_EINVAL (NULL n_out, capacity too small), CSE_EUNSUPPORTED (other designs).
+ */
+int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int64_t *n_out,
+                        void *stream);
+
+/*
  * cse_platten_stats -- sizes of the planned launch (host), out[0..11] =
  *   n_tiles, n_batches (tile batches of the fused kernel), n_work_items (waves or workgroups
  *   launched by one simulation pass), n_key_slots (calibration keys), total simulations (sum of N
  *   over tiles), tiles per batch, max N, batch-simulation pairs (sum over batches of their N),
  *   workgroup-simulation pairs (sum over workgroup items of their simulation count; the unit of
- *   shared random-number generation), number of distinct N, 0, 0.
+ *   shared random-number generation), number of distinct N, microseconds spent building the
+ *   design table at creation (CSE_HIER4, else 0), 0.
  */
 int cse_platten_stats(const cse_platten *p, int64_t out[12]);
 

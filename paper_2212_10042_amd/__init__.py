@@ -29,7 +29,7 @@ CSE_PLATTEN_KEEP_ALL = 1
 EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
             "cse_simulate", "cse_validate", "cse_calibrate", "cse_bound", "cse_simulate_per_tile",
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
-            "cse_last_error")
+            "cse_posterior_table", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -62,6 +62,7 @@ def _load():
     L.cse_bound.argtypes = [P, i32, P, P, dbl, P, P, P]
     L.cse_simulate_per_tile.argtypes = [P, u64, i64, i64, P, P]
     L.cse_platten_stats.argtypes = [P, P]
+    L.cse_posterior_table.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
     L.cse_profile_enable.argtypes = [i32]
     L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.cse_profile_reset.argtypes = []
@@ -173,8 +174,18 @@ def cse_platten_stats(h) -> dict:
     out = np.zeros(12, np.int64)
     _check("cse_platten_stats", _L.cse_platten_stats(h, _ptr(out)))
     keys = ("n_tiles", "n_batches", "n_work_items", "n_key_slots", "total_sims", "tiles_per_batch",
-            "max_sims", "batch_sims", "group_sims", "n_sim_classes")
+            "max_sims", "batch_sims", "group_sims", "n_sim_classes", "table_build_us")
     return {k: int(v) for k, v in zip(keys, out)}
+
+
+def cse_posterior_table(h, stream=None) -> torch.Tensor:
+    """The 4-arm design's table [(n+1)^4, 4] float32 (1 - P_1, 1 - P_2, 1 - P_3, 0) on the device."""
+    n = ctypes.c_int64()
+    _check("cse_posterior_table", _L.cse_posterior_table(h, None, 0, ctypes.byref(n), None))
+    out = torch.empty((n.value, 4), dtype=torch.float32, device="cuda")
+    _check("cse_posterior_table", _L.cse_posterior_table(h, _ptr(out), out.numel(), ctypes.byref(n),
+                                                         _stream(stream)))
+    return out
 
 
 def cse_profile_enable(on: bool = True):
@@ -222,11 +233,12 @@ class Platten:
     def _alloc(self, device):
         n, d = self.n_tiles, self.d
         dev = torch.device(device)
+        kind = self.design.kind
         return dict(
             reject=torch.empty(n, dtype=torch.int32, device=dev),
-            score_T=torch.empty((n, d), dtype=torch.int64, device=dev) if self.design.kind != CSE_ZTEST1 else None,
-            score_Z=torch.empty(n, dtype=torch.float64, device=dev) if self.design.kind == CSE_ZTEST1 else None,
-            grad=torch.empty((n, d), dtype=torch.float64, device=dev),
+            score_T=torch.empty((n, d), dtype=torch.int64, device=dev) if kind == CSE_BINOM2_Z else None,
+            score_Z=torch.empty(n, dtype=torch.float64, device=dev) if kind == CSE_ZTEST1 else None,
+            grad=torch.empty((n, d), dtype=torch.float64, device=dev) if kind != CSE_HIER4 else None,
         )
 
     def simulate(self, seed=0, device="cuda"):

@@ -42,6 +42,16 @@ int check_handle(const cse_platten *h, const char *fn) {
 
 bool in_unit(double x) { return x > 0.0 && x < 1.0; }
 
+// The 4-arm design produces rejection counts and calibration keys; score sums are not formed.
+int check_scores(const cse::Platten &P, const void *score_T, const void *score_Z, const void *grad,
+                 const char *fn) {
+    if (P.design.kind == CSE_HIER4 && (score_T || score_Z || grad)) {
+        set_error(std::string(fn) + ": score sums and gradients are not available for CSE_HIER4");
+        return CSE_EUNSUPPORTED;
+    }
+    return CSE_OK;
+}
+
 // ---- launch timing (cse_profile_*) ----
 struct ProfRec {
     std::string name;
@@ -105,6 +115,9 @@ int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
         CSE_LAUNCH(cse::launch_zero(P.d_Zw, P.n_tiles * sizeof(unsigned long long), st));
         Timed tm(keys ? "ztest1_calib" : "ztest1", st);
         CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, keys ? (float *)P.d_keys : nullptr, st));
+    } else if (P.design.kind == CSE_HIER4) {
+        Timed tm(keys ? "hier4_calib" : "hier4", st);
+        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, keys ? (float *)P.d_keys : nullptr, st));
     } else {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "binom2_calib" : "binom2", st);
@@ -114,7 +127,7 @@ int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
 }
 
 int ensure_keys(cse::Platten &P) {
-    const size_t esz = (P.family == cse::FAM_NORMAL) ? 4 : 2;
+    const size_t esz = (P.design.kind == CSE_BINOM2_Z) ? 2 : 4;
     const size_t need = (size_t)P.n_keys * esz;
     if (P.d_keys && P.keys_bytes >= need) return CSE_OK;
     if (P.d_keys) {
@@ -200,6 +213,7 @@ int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *
         return CSE_EINVAL;
     }
     const auto &P = p->P;
+    if (int e = check_scores(P, score_T, score_Z, grad, "cse_simulate")) return e;
     hipStream_t st = (hipStream_t)stream;
     if (int e = run_sim(P, seed, false, st)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
@@ -219,6 +233,7 @@ int cse_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *rej
         return CSE_EINVAL;
     }
     const auto &P = p->P;
+    if (int e = check_scores(P, score_T, score_Z, grad, "cse_validate")) return e;
     hipStream_t st = (hipStream_t)stream;
     if (int e = run_sim(P, seed, false, st)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
@@ -243,6 +258,7 @@ int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alp
         return CSE_EINVAL;
     }
     auto &P = const_cast<cse_platten *>(p)->P;
+    if (int e = check_scores(P, score_T, score_Z, grad, "cse_calibrate")) return e;
     if (int e = ensure_keys(P)) return e;
     hipStream_t st = (hipStream_t)stream;
     double *ap = alpha_prime ? alpha_prime : P.d_apw;
@@ -334,8 +350,31 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     out[7] = P.block_sims;
     out[8] = P.group_sims;
     out[9] = P.n_cls;
-    out[10] = 0;
+    out[10] = (int64_t)(P.table_ms * 1000.0);
     out[11] = 0;
+    return CSE_OK;
+}
+
+int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int64_t *n_out,
+                        void *stream) {
+    if (int e = check_handle(p, "cse_posterior_table")) return e;
+    const auto &P = p->P;
+    if (P.design.kind != CSE_HIER4 || !P.d_h4tbl) {
+        set_error("cse_posterior_table: the platten's design has no posterior table");
+        return CSE_EUNSUPPORTED;
+    }
+    if (!n_out) {
+        set_error("cse_posterior_table: NULL n_out");
+        return CSE_EINVAL;
+    }
+    *n_out = P.h4_outcomes;
+    if (!out) return CSE_OK;
+    if (capacity < 4 * P.h4_outcomes) {
+        set_error("cse_posterior_table: capacity below 4 floats per outcome");
+        return CSE_EINVAL;
+    }
+    CSE_HIP_TRY(hipMemcpyAsync(out, P.d_h4tbl, (size_t)P.h4_outcomes * 4 * sizeof(float),
+                               hipMemcpyDeviceToDevice, (hipStream_t)stream));
     return CSE_OK;
 }
 

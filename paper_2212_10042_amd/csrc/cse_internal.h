@@ -40,6 +40,22 @@ struct Blk1 {
     int64_t key_base;          // keys of slot s live at key_base + s * n_sims + k
 };
 
+// 4-arm designs: a 4 x 4 x 2 x 2 product of distinct thresholds (arms 0..3) = 64 box slots;
+// slot (u0,u1,u2,u3) = ((u0 * 4 + u1) * 2 + u2) * 2 + u3.  A box's tiles (one per null
+// configuration b present, b ascending) are consecutive key rows starting at row0[slot] and
+// consecutive tile ids starting at tile0[slot]; bmask bit b marks configuration b.
+constexpr int B4N0 = 4, B4N1 = 4, B4N2 = 2, B4N3 = 2;
+constexpr int B4S = B4N0 * B4N1 * B4N2 * B4N3;
+struct Blk4 {
+    uint32_t T0[B4N0], T1[B4N1], T2[B4N2], T3[B4N3];
+    int32_t row0[B4S];         // first key row of the slot's tiles, -1 when the slot has no box
+    int32_t tile0[B4S];        // first tile id of the slot's box
+    uint32_t bmask[B4S];       // configurations present (bit b, b = 1..7)
+    int32_t n_rows;            // key rows (tiles) of this block
+    int32_t n_sims;
+    int64_t key_base;          // key of row r, simulation k at key_base + ((k/64) * n_rows + r) * 64 + k%64
+};
+
 // Work item: one wave simulates sims [k_begin, k_end) of block blk.
 struct WorkItem {
     int32_t blk;
@@ -89,8 +105,8 @@ struct Platten {
     double *d_verts = nullptr;
     double *d_radii = nullptr;           // [n_tiles * d] half-widths of the tile's box
     int32_t *d_is_box = nullptr;         // [n_tiles] 1 when the tile is its whole box
-    int64_t *d_key_off = nullptr;        // [n_tiles] each tile's first key in d_keys (2-arm:
-                                         // chunk 0 of its slot; chunk stride KEY_CHUNK)
+    int64_t *d_key_off = nullptr;        // [n_tiles] each tile's first key in d_keys
+    int64_t *d_key_stride = nullptr;     // [n_tiles] distance between its 64-simulation chunks
     int64_t n_keys = 0;                  // key slots (sum over blocks of 64 * n_sims)
     void *d_blocks = nullptr;
     int64_t n_blocks = 0;
@@ -100,6 +116,9 @@ struct Platten {
     int64_t n_gitems = 0;
 
     // design tables (device)
+    float4 *d_h4tbl = nullptr;           // 4-arm: (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome
+    int64_t h4_outcomes = 0;
+    double table_ms = 0.0;               // time to build the design table at platten creation
     int32_t *d_cut_tbl = nullptr;        // 2-arm: c(y0) = min{y1 : z(y0, y1) > cut}, [n+1]
     double *d_S_tbl = nullptr;           // 2-arm: S = -z per outcome y0*(n+1)+y1
     int32_t *d_S_order = nullptr;        // 2-arm: outcomes sorted by S ascending

@@ -1,0 +1,345 @@
+// k_hier4.hip -- four Bernoulli arms (arm 0 control) under the hierarchical model of the
+// basket case study (Section 10.1): theta_i | mu, s2 ~ N(mu, s2), mu ~ N(-1.34, 100),
+// s2 ~ InvGamma(0.0005, 0.000005); statistic of treatment arm i: P(p_i > p_0 | y).
+//
+// Posterior table (one thread per outcome y in {0..n}^4), float64:
+//   * mu integrated out: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T, whose precision is
+//     Q = (I - c 11^T) / s2 with c = 100 / (s2 + 400) (Sherman-Morrison);
+//   * per node s2_j (90 nodes equally spaced in log s2 on [log 1e-6, log 1e3]): Newton's method
+//     for the mode of  sum_a [y_a theta_a - n softplus(theta_a)] - (theta - m0)^T Q (theta - m0) / 2.
+//     The negative Hessian is D - beta 11^T with D_a = n p_a (1 - p_a) + 1/s2, beta = c / s2, so each
+//     step, its determinant and the covariance C = (D - beta 11^T)^{-1} = D^{-1} + g u u^T
+//     (u = D^{-1} 1, g = beta / (1 - beta sum u)) cost O(arms);
+//   * node log weight: Laplace evidence  l(mode) + log|Q|/2 - log|D - beta 11^T|/2, plus the
+//     log inverse-gamma density of s2_j, plus log of the trapezoid weight in log s2 (ds2 = s2 dlog s2);
+//   * P_i = sum_j pi_j Phi((mode_i - mode_0) / sqrt(C_ii + C_00 - 2 C_i0)), pi = softmax of the
+//     log weights (log-sum-exp in float64); the statistic 1 - P_i is summed directly as
+//     sum_j pi_j Phi(-z_j), keeping relative precision where P_i is near 1.
+// The table holds float32 (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome, index ((y0 m + y1) m + y2) m + y3.
+#include <math.h>
+
+#include "cse_internal.h"
+#include "fp64_math.hpp"
+#include "kernels.h"
+#include "philox.hpp"
+
+namespace cse {
+
+constexpr int H4_NODES = 90;
+
+__device__ __forceinline__ double expit_d(double x) {
+    return x >= 0.0 ? 1.0 / (1.0 + exp_cw(-x)) : 1.0 - 1.0 / (1.0 + exp_cw(x));
+}
+
+__global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float4 *__restrict__ tbl) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_out) return;
+    const int m = n + 1;
+    int y[4];
+    {
+        int64_t v = idx;
+        for (int a = 3; a >= 0; --a) {
+            y[a] = (int)(v % m);
+            v /= m;
+        }
+    }
+    const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
+    const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
+    const double h = (LS2_HI - LS2_LO) / (H4_NODES - 1);
+    const double lgA = lgamma(IG_A), logB = log(IG_B);
+    double th0[4];
+    for (int a = 0; a < 4; ++a) th0[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
+
+    // running log-sum-exp of the node weights and the weighted probabilities
+    double wmax = -INFINITY, wsum = 0.0, acc[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < H4_NODES; ++j) {
+        const double ls2 = LS2_LO + h * j;
+        const double s2 = exp(ls2);
+        const double inv_s2 = 1.0 / s2;
+        const double c = TAU2 / (s2 + 4.0 * TAU2);
+        const double beta = c * inv_s2;
+        double th[4] = {th0[0], th0[1], th0[2], th0[3]};
+        double D[4], u[4], gam = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double dsum = 0.0;
+            for (int a = 0; a < 4; ++a) dsum += th[a] - M0;
+            double g[4], su = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double p = expit_d(th[a]);
+                // Q (theta - m0) = ((theta_a - m0) - c sum_b (theta_b - m0)) / s2
+                g[a] = (double)y[a] - n * p - ((th[a] - M0) - c * dsum) * inv_s2;
+                D[a] = n * p * (1.0 - p) + inv_s2;
+                u[a] = 1.0 / D[a];
+                su += u[a];
+            }
+            gam = beta / (1.0 - beta * su);
+            double ug = 0.0;
+            for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
+            double mx = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double step = u[a] * g[a] + gam * u[a] * ug;   // (D - beta 11^T)^{-1} g
+                th[a] += step;
+                mx = fmax(mx, fabs(step));
+            }
+            if (mx < 1e-10) break;
+        }
+        // curvature at the final mode
+        double su = 0.0, logdetD = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const double p = expit_d(th[a]);
+            D[a] = n * p * (1.0 - p) + inv_s2;
+            u[a] = 1.0 / D[a];
+            su += u[a];
+            logdetD += log(D[a]);
+        }
+        gam = beta / (1.0 - beta * su);
+        const double logdet_negH = logdetD + log1p(-beta * su);
+        const double logdetQ = -(3.0 * ls2 + log(s2 + 4.0 * TAU2));
+        double ll = 0.0, dsum = 0.0, sq = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            ll += y[a] * th[a] - n * softplus_fast(th[a]);
+            const double e = th[a] - M0;
+            dsum += e;
+            sq += e * e;
+        }
+        const double quad = (sq - c * dsum * dsum) * inv_s2;
+        const double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet_negH;
+        const double logprior = IG_A * logB - lgA - (IG_A + 1.0) * ls2 - IG_B * inv_s2;
+        const double logtrap = log((j == 0 || j == H4_NODES - 1) ? 0.5 * h : h) + ls2;
+        const double lw = lap + logprior + logtrap;
+        double pr[3];
+        for (int i = 1; i < 4; ++i) {
+            const double du = u[i] - u[0];
+            const double var = u[i] + u[0] + gam * du * du;
+            // 1 - Phi(z) = Phi(-z): the statistic 1 - P_i is summed directly (relative precision)
+            pr[i - 1] = 0.5 * erfc((th[i] - th[0]) / sqrt(2.0 * var));
+        }
+        if (lw > wmax) {
+            const double sc = exp(wmax - lw);   // 0 on the first node
+            wsum *= sc;
+            for (int i = 0; i < 3; ++i) acc[i] *= sc;
+            wmax = lw;
+        }
+        const double wj = exp(lw - wmax);
+        wsum += wj;
+        for (int i = 0; i < 3; ++i) acc[i] += wj * pr[i];
+    }
+    float4 o;
+    o.x = (float)(acc[0] / wsum);
+    o.y = (float)(acc[1] / wsum);
+    o.z = (float)(acc[2] / wsum);
+    o.w = 0.0f;
+    tbl[idx] = o;
+}
+
+hipError_t launch_hier4_table(int n, float4 *tbl, hipStream_t st) {
+    const int64_t m = n + 1;
+    const int64_t n_out = m * m * m * m;
+    hipLaunchKernelGGL(k_hier4_table, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n, n_out, tbl);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Fused simulation, 4 arms x 35 patients (words a*35 .. a*35+34 for arm a: 35 Philox blocks).
+// The four waves of a workgroup run four box batches over the same simulations and share each
+// chunk's 140 words through LDS.  Per (simulation, box slot): one 16-byte gather of
+// (1 - P_1, 1 - P_2, 1 - P_3) at the outcome y; the design rejects treatment arm i when
+// 1 - P_i < cut, giving a 3-bit mask m; configuration b's FWER event is m & b != 0.  Per box the
+// lanes count each mask value (7 packed 6-bit counters in two words, exact for 63 simulations
+// per lane between flushes), so R_b = sum_{m & b != 0} count[m] for every b of the box.
+// Calibration keys: S_b = min_{i in b} (1 - P_i) per (simulation, tile), float32.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void wave_sync4() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <bool KEYS>
+__global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
+                                              const GroupItem *__restrict__ items, int64_t n_items,
+                                              uint32_t key0, uint32_t key1,
+                                              const float4 *__restrict__ tbl, float cut,
+                                              uint32_t *__restrict__ R, float *__restrict__ keys) {
+    constexpr int NP = NP35;
+    constexpr int NW = 4 * NP;
+    constexpr int NB = NW / 4;   // 35 Philox blocks
+    constexpr int NWAVES = WG / WAVE;
+    constexpr int M1 = NP + 1;
+    __shared__ uint32_t lds[NWAVES][B4S][WAVE + 1];
+    uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);
+    static_assert(NW * WAVE <= NWAVES * B4S * (WAVE + 1), "word buffer must fit");
+
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t it = blockIdx.x;
+    if (it >= n_items) return;
+    const GroupItem G = items[it];
+    const int32_t blk = G.blk[wv];
+    const bool live = blk >= 0;
+    const Blk4 *__restrict__ B = blocks + (live ? blk : G.blk[0]);
+    uint32_t T0[B4N0], T1[B4N1], T2[B4N2], T3[B4N3];
+#pragma unroll
+    for (int u = 0; u < B4N0; ++u) T0[u] = B->T0[u];
+#pragma unroll
+    for (int u = 0; u < B4N1; ++u) T1[u] = B->T1[u];
+#pragma unroll
+    for (int u = 0; u < B4N2; ++u) T2[u] = B->T2[u];
+#pragma unroll
+    for (int u = 0; u < B4N3; ++u) T3[u] = B->T3[u];
+    const int32_t n_rows = B->n_rows;
+    float *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
+
+    uint32_t acc0[B4S], acc1[B4S];
+#pragma unroll
+    for (int s = 0; s < B4S; ++s) {
+        acc0[s] = 0u;
+        acc1[s] = 0u;
+    }
+    uint32_t tot[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};   // lane t: counts of mask m for slot t
+
+    auto flush = [&]() {
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < B4S; ++s) lds[wv][s][lane] = acc0[s];
+        wave_sync4();
+        for (int l = 0; l < WAVE; ++l) {
+            const uint32_t x = lds[wv][lane][l];
+#pragma unroll
+            for (int m = 1; m <= 5; ++m) tot[m] += (x >> (6 * (m - 1))) & 63u;
+        }
+        wave_sync4();
+#pragma unroll
+        for (int s = 0; s < B4S; ++s) lds[wv][s][lane] = acc1[s];
+        wave_sync4();
+        for (int l = 0; l < WAVE; ++l) {
+            const uint32_t x = lds[wv][lane][l];
+            tot[6] += x & 63u;
+            tot[7] += (x >> 6) & 63u;
+        }
+#pragma unroll
+        for (int s = 0; s < B4S; ++s) {
+            acc0[s] = 0u;
+            acc1[s] = 0u;
+        }
+        __syncthreads();
+    };
+
+    int since = 0;
+    for (uint32_t k0 = G.k_begin; k0 < G.k_end; k0 += WAVE) {
+        const uint32_t k = k0 + (uint32_t)lane;
+        const bool act = k < G.k_end;
+        for (int b = wv; b < NB; b += NWAVES) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+            words[4 * b + 0][lane] = w.x;
+            words[4 * b + 1][lane] = w.y;
+            words[4 * b + 2][lane] = w.z;
+            words[4 * b + 3][lane] = w.w;
+        }
+        __syncthreads();
+        int y0[B4N0], y1[B4N1], y2[B4N2], y3[B4N3];
+#pragma unroll
+        for (int u = 0; u < B4N0; ++u) y0[u] = 0;
+#pragma unroll
+        for (int u = 0; u < B4N1; ++u) y1[u] = 0;
+#pragma unroll
+        for (int u = 0; u < B4N2; ++u) y2[u] = 0;
+#pragma unroll
+        for (int u = 0; u < B4N3; ++u) y3[u] = 0;
+        if (live) {
+#pragma unroll 7
+            for (int j = 0; j < NP; ++j) {
+                const uint32_t x = words[j][lane];
+#pragma unroll
+                for (int u = 0; u < B4N0; ++u) y0[u] += (x < T0[u]) ? 1 : 0;
+            }
+#pragma unroll 7
+            for (int j = NP; j < 2 * NP; ++j) {
+                const uint32_t x = words[j][lane];
+#pragma unroll
+                for (int u = 0; u < B4N1; ++u) y1[u] += (x < T1[u]) ? 1 : 0;
+            }
+#pragma unroll 7
+            for (int j = 2 * NP; j < 3 * NP; ++j) {
+                const uint32_t x = words[j][lane];
+#pragma unroll
+                for (int u = 0; u < B4N2; ++u) y2[u] += (x < T2[u]) ? 1 : 0;
+            }
+#pragma unroll 7
+            for (int j = 3 * NP; j < 4 * NP; ++j) {
+                const uint32_t x = words[j][lane];
+#pragma unroll
+                for (int u = 0; u < B4N3; ++u) y3[u] += (x < T3[u]) ? 1 : 0;
+            }
+        }
+        __syncthreads();
+        if (live) {
+            float *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * n_rows * WAVE + lane;
+#pragma unroll
+            for (int u0 = 0; u0 < B4N0; ++u0)
+#pragma unroll
+                for (int u1 = 0; u1 < B4N1; ++u1)
+#pragma unroll
+                    for (int u2 = 0; u2 < B4N2; ++u2)
+#pragma unroll
+                        for (int u3 = 0; u3 < B4N3; ++u3) {
+                            const int s = ((u0 * B4N1 + u1) * B4N2 + u2) * B4N3 + u3;
+                            const int32_t row0 = B->row0[s];
+                            if (row0 < 0) continue;   // uniform: the slot holds no box
+                            const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
+                            const float4 q = tbl[idx];
+                            const uint32_t m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) |
+                                                      (q.z < cut ? 4u : 0u))
+                                                   : 0u;
+                            acc0[s] += (m >= 1u && m <= 5u) ? (1u << (6u * (m - 1u))) : 0u;
+                            acc1[s] += (m >= 6u) ? (1u << (6u * (m - 6u))) : 0u;
+                            if (KEYS) {
+                                const uint32_t bm = B->bmask[s];
+                                int row = row0;
+#pragma unroll
+                                for (int b = 1; b <= 7; ++b) {
+                                    if (!(bm & (1u << b))) continue;   // uniform
+                                    float sb = INFINITY;
+                                    if (b & 1) sb = fminf(sb, q.x);
+                                    if (b & 2) sb = fminf(sb, q.y);
+                                    if (b & 4) sb = fminf(sb, q.z);
+                                    kc[(size_t)row * WAVE] = sb;
+                                    ++row;
+                                }
+                            }
+                        }
+        }
+        if (++since == 63) {
+            flush();
+            since = 0;
+        }
+    }
+    flush();
+    if (!live) return;
+    const int32_t t0 = B->tile0[lane];
+    if (t0 < 0) return;
+    const uint32_t bm = B->bmask[lane];
+    int q = 0;
+    for (int b = 1; b <= 7; ++b) {
+        if (!(bm & (1u << b))) continue;
+        uint32_t r = 0u;
+        for (int m = 1; m <= 7; ++m)
+            if (m & b) r += tot[m];
+        atomicAdd(&R[t0 + q], r);
+        ++q;
+    }
+}
+
+hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const float cut = (float)P.design.cut;
+    if (keys)
+        hipLaunchKernelGGL(k_hier4<true>, dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks,
+                           P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys);
+    else
+        hipLaunchKernelGGL(k_hier4<false>, dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks,
+                           P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys);
+    return hipGetLastError();
+}
+
+}  // namespace cse

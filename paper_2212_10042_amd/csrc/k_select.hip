@@ -123,6 +123,7 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
 
 __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__ keys,
                                                        const int64_t *__restrict__ key_off,
+                                                       const int64_t *__restrict__ key_stride,
                                                        const int32_t *__restrict__ N,
                                                        const int32_t *__restrict__ kk,
                                                        double *__restrict__ lam,
@@ -142,7 +143,9 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
         }
         return;
     }
+    // key of simulation j at kt + (j / 64) * stride + j % 64 (chunked layouts; stride 64 = contiguous)
     const float *__restrict__ kt = keys + key_off[t];
+    const int64_t stride = key_stride[t];
     uint32_t prefix = 0u, below = 0u, need = (uint32_t)k;
     const int shifts[3] = {21, 10, 0};
     const int widths[3] = {11, 11, 10};
@@ -152,7 +155,7 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
         for (int j = tid; j < BINS; j += SEL_WG) hist[j] = 0u;
         __syncthreads();
         for (int j = tid; j < n; j += SEL_WG) {
-            const uint32_t u = f2ord(kt[j]);
+            const uint32_t u = f2ord(kt[(int64_t)(j >> 6) * stride + (j & 63)]);
             if ((u & mask_hi) == prefix) atomicAdd(&hist[(u >> sh) & ((1u << wd) - 1u)], 1u);
         }
         __syncthreads();
@@ -242,9 +245,9 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st) {
-    if (P.design.kind == CSE_ZTEST1)
+    if (P.design.kind == CSE_ZTEST1 || P.design.kind == CSE_HIER4)
         hipLaunchKernelGGL(k_select_f32, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
-                           (const float *)P.d_keys, P.d_key_off, P.d_N, k, lam, rej_at);
+                           (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else
         hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG),
                            2 * (size_t)P.n_outcomes * sizeof(uint32_t), st,

@@ -9,9 +9,11 @@
 #include <functional>
 #include <map>
 #include <numeric>
+#include <chrono>
 #include <tuple>
 
 #include "cse_internal.h"
+#include "kernels.h"
 
 namespace cse {
 
@@ -141,8 +143,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         p = 1;
         P->family = FAM_BINOM;
     } else if (kind == CSE_HIER4) {
-        set_error("cse_platten_create: CSE_HIER4 is not available in this build");
-        return CSE_EUNSUPPORTED;
+        d = 4;
+        p = 3;
+        P->family = FAM_BINOM;
     } else {
         set_error("cse_platten_create: unknown design kind");
         return CSE_EINVAL;
@@ -294,7 +297,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     P->vert_off.push_back((int32_t)(P->verts.size() / d));
     P->tile_theta.resize(P->n_tiles * d);
     P->tile_N.resize(P->n_tiles);
-    std::vector<int64_t> key_off(P->n_tiles, -1);
+    std::vector<int64_t> key_off(P->n_tiles, -1), key_stride(P->n_tiles, 64);
     for (int64_t t = 0; t < P->n_tiles; ++t) {
         for (int a = 0; a < d; ++a) P->tile_theta[t * d + a] = theta[P->tile_box[t] * d + a];
         P->tile_N[t] = sims[P->tile_box[t]];
@@ -341,6 +344,92 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             P->n_keys += (int64_t)B1T * B.n_sims;
         }
         if (int e = upload((Blk1 **)&P->d_blocks, blks.data(), blks.size())) return e;
+    } else if (kind == CSE_HIER4) {
+        // distinct values per arm -> coordinates; 4 x 4 x 2 x 2 coordinate blocks per N class
+        const int BD[4] = {B4N0, B4N1, B4N2, B4N3};
+        std::vector<double> uv[4];
+        for (int64_t t = 0; t < P->n_tiles; ++t)
+            for (int a = 0; a < 4; ++a) uv[a].push_back(P->tile_theta[t * 4 + a]);
+        for (int a = 0; a < 4; ++a) {
+            std::sort(uv[a].begin(), uv[a].end());
+            uv[a].erase(std::unique(uv[a].begin(), uv[a].end()), uv[a].end());
+        }
+        typedef std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t> Key4;
+        std::map<Key4, std::vector<Blk4>> blkmap;
+        for (int64_t t = 0; t < P->n_tiles;) {
+            // the tiles of one box are consecutive
+            int64_t t1 = t;
+            uint32_t bm = 0;
+            while (t1 < P->n_tiles && P->tile_box[t1] == P->tile_box[t]) bm |= 1u << P->tile_cfg[t1++];
+            int64_t c[4];
+            for (int a = 0; a < 4; ++a)
+                c[a] = std::lower_bound(uv[a].begin(), uv[a].end(), P->tile_theta[t * 4 + a]) - uv[a].begin();
+            Key4 key = std::make_tuple(P->tile_N[t], c[0] / BD[0], c[1] / BD[1], c[2] / BD[2], c[3] / BD[3]);
+            const int slot = (int)((((c[0] % BD[0]) * BD[1] + c[1] % BD[1]) * BD[2] + c[2] % BD[2]) * BD[3] + c[3] % BD[3]);
+            auto &vec = blkmap[key];
+            Blk4 *B = nullptr;
+            for (auto &b : vec)
+                if (b.row0[slot] < 0) {
+                    B = &b;
+                    break;
+                }
+            if (!B) {
+                Blk4 nb{};
+                for (int j = 0; j < B4S; ++j) {
+                    nb.row0[j] = -1;
+                    nb.tile0[j] = -1;
+                    nb.bmask[j] = 0;
+                }
+                uint32_t *T[4] = {nb.T0, nb.T1, nb.T2, nb.T3};
+                for (int a = 0; a < 4; ++a) {
+                    const int64_t base = (c[a] / BD[a]) * BD[a];
+                    for (int u = 0; u < BD[a]; ++u)
+                        T[a][u] = (base + u < (int64_t)uv[a].size()) ? bern_threshold(uv[a][base + u]) : 0u;
+                }
+                nb.n_sims = P->tile_N[t];
+                vec.push_back(nb);
+                B = &vec.back();
+            }
+            B->row0[slot] = 0;   // rows assigned below
+            B->tile0[slot] = (int32_t)t;
+            B->bmask[slot] = bm;
+            t = t1;
+        }
+        std::vector<Blk4> blks;
+        for (auto &kv : blkmap)
+            for (auto &b : kv.second) blks.push_back(b);
+        P->n_blocks = (int64_t)blks.size();
+        for (auto &B : blks) {
+            blk_sims.push_back(B.n_sims);
+            int32_t rows = 0;
+            for (int j = 0; j < B4S; ++j) {
+                if (B.row0[j] < 0) continue;
+                B.row0[j] = rows;
+                rows += __builtin_popcount(B.bmask[j]);
+            }
+            B.n_rows = rows;
+            B.key_base = P->n_keys;
+            for (int j = 0; j < B4S; ++j) {
+                if (B.row0[j] < 0) continue;
+                const int nt = __builtin_popcount(B.bmask[j]);
+                for (int q = 0; q < nt; ++q) {
+                    const int64_t tile = B.tile0[j] + q;
+                    key_off[tile] = B.key_base + (int64_t)(B.row0[j] + q) * 64;
+                    key_stride[tile] = (int64_t)rows * 64;
+                }
+            }
+            P->n_keys += ((int64_t)B.n_sims + 63) / 64 * rows * 64;
+        }
+        if (int e = upload((Blk4 **)&P->d_blocks, blks.data(), blks.size())) return e;
+
+        // posterior table of the design (once per platten)
+        const int64_t m = P->n_per_arm + 1;
+        P->h4_outcomes = m * m * m * m;
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_h4tbl, (size_t)P->h4_outcomes * sizeof(float4)));
+        const auto t0 = std::chrono::steady_clock::now();
+        CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, nullptr));
+        CSE_HIP_TRY(hipDeviceSynchronize());
+        P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } else {
         // distinct arm values -> integer coordinates; 8 x 8 coordinate blocks per N class
         std::vector<double> u0, u1;
@@ -387,7 +476,10 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             blk_sims.push_back(B.n_sims);
             B.key_base = P->n_keys;
             for (int j = 0; j < B2U * B2V; ++j)
-                if (B.tile[j] >= 0) key_off[B.tile[j]] = B.key_base + (int64_t)j * 64;
+                if (B.tile[j] >= 0) {
+                    key_off[B.tile[j]] = B.key_base + (int64_t)j * 64;
+                    key_stride[B.tile[j]] = KEY_CHUNK;
+                }
             P->n_keys += ((int64_t)B.n_sims + 63) / 64 * KEY_CHUNK;
         }
         if (int e = upload((Blk2 **)&P->d_blocks, blks.data(), blks.size())) return e;
@@ -449,7 +541,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         P->n_items = (int64_t)items.size();
         if (int e = upload(&P->d_items, items.data(), items.size())) return e;
     }
-    if (kind == CSE_BINOM2_Z) {
+    if (kind == CSE_BINOM2_Z || kind == CSE_HIER4) {
         // groups of 4 consecutive blocks of equal N (blocks are ordered by N), split in sims
         const int64_t target = 4096;    // workgroups
         std::vector<std::vector<int64_t>> groups;
@@ -485,6 +577,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     if (int e = upload(&P->d_radii, P->tile_radii.data(), P->tile_radii.size())) return e;
     if (int e = upload(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size())) return e;
     if (int e = upload(&P->d_key_off, key_off.data(), key_off.size())) return e;
+    if (int e = upload(&P->d_key_stride, key_stride.data(), key_stride.size())) return e;
     // N classes for the Clopper-Pearson table
     {
         std::vector<int32_t> cls(P->tile_N.begin(), P->tile_N.end());
@@ -526,7 +619,7 @@ void free_platten(Platten *P) {
                     P->d_S_group, P->d_keys, P->d_Rw,      P->d_Tw,     P->d_Zw,
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
-                    P->d_is_box};
+                    P->d_is_box, P->d_key_stride, P->d_h4tbl};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }

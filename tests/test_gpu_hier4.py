@@ -1,0 +1,145 @@
+"""GPU parity: 4-arm hierarchical design (Section 10.1 model) through the C ABI vs the oracle.
+
+The GPU builds the posterior table in float64 and stores float32 (1 - P_i); the oracle computes
+P_i in float64 with generic linear algebra.  Decisions and order statistics are taken in float32
+on both sides (the oracle's statistic is rounded to float32 first), so rejection counts, k,
+lambda*_i and the counts below it must agree exactly wherever the two float32 tables agree;
+table entries are compared to the oracle on sampled outcomes (max |diff| and exact-match share
+printed), and the table's exchangeability identities are checked on all 36^4 outcomes.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_2212_10042_amd as cse
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+M = 36
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def table():
+    w = W.hier4_grid(2, 64)
+    P = cse.Platten.create("hier4", w["theta"], w["radii"], w["sims"])
+    st = cse.cse_platten_stats(P.handle)
+    print(f"[hier4] posterior table built in {st['table_build_us'] / 1e3:.2f} ms", flush=True)
+    t = _np(cse.cse_posterior_table(P.handle))
+    torch.cuda.synchronize()
+    P.close()
+    return t
+
+
+def test_posterior_table_vs_oracle(table):
+    rng = np.random.default_rng(0)
+    edge = [0, M**4 - 1, ((0 * M + 35) * M + 0) * M + 35, ((17 * M + 17) * M + 3) * M + 30]
+    idx = np.unique(np.concatenate([rng.choice(M**4, 2500, replace=False), edge]))
+    orc = O.hier4_table(idx)          # 1 - P_i, float64
+    want = orc.astype(np.float32)
+    got = table[idx, :3]
+    diff = np.abs(got.astype(np.float64) - orc)
+    exact = np.mean(got == want)
+    print(f"[hier4] table vs oracle: max |diff| {diff.max():.3e}, float32-identical share {exact:.5f}", flush=True)
+    assert diff.max() < 2e-7
+    assert exact > 0.99
+    assert np.all(table[:, 3] == 0.0)
+
+
+def test_posterior_table_exchangeability(table):
+    T = table.reshape(M, M, M, M, 4)
+    y = np.arange(M)
+    eq01 = y[:, None] == y[None, :]
+    # P_i = 1/2 exactly where y_i = y_0
+    assert np.all(T[:, :, :, :, 0][np.broadcast_to(eq01[:, :, None, None], (M,) * 4)] == 0.5)
+    assert np.all(np.transpose(T[:, :, :, :, 1], (0, 2, 1, 3))[np.broadcast_to(eq01[:, :, None, None], (M,) * 4)] == 0.5)
+    # permuting the other treatment arms: P_1(y0,y1,y2,y3) = P_1(y0,y1,y3,y2); P_2(y0,y1,y2,y3) = P_1(y0,y2,y1,y3)
+    np.testing.assert_allclose(T[..., 0], np.transpose(T[..., 0], (0, 1, 3, 2)), rtol=0, atol=2e-7)
+    np.testing.assert_allclose(T[..., 1], np.transpose(T[..., 0], (0, 2, 1, 3)), rtol=0, atol=2e-7)
+    np.testing.assert_allclose(T[..., 2], np.transpose(T[..., 0], (0, 3, 2, 1)), rtol=0, atol=2e-7)
+    # swapping arm 1 with the control: P_1 -> 1 - P_1
+    np.testing.assert_allclose(T[..., 0], 1.0 - np.transpose(T[..., 0], (1, 0, 2, 3)), rtol=0, atol=3e-7)
+
+
+def _decide32(S, cut):
+    """float32 decisions / keys from the oracle's float64 statistic."""
+    return S.astype(np.float32), np.float32(cut)
+
+
+def _compare(w, seed, cut=0.05):
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    print(f"[hier4] compare {w['name']} seed={seed}", flush=True)
+    P = cse.Platten.create("hier4", th, rd, sm, cut=cut)
+    subs = O.subtiles("hier4", th, rd)
+    got = list(zip(P.tiles["box"].tolist(), P.tiles["cfg"].tolist()))
+    assert got == [(int(s[0]), int(s[1])) for s in subs]
+    assert np.array_equal(P.tiles["n_vert"], [len(s[2]) for s in subs])
+    g = P.calibrate(seed, alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    box = np.array([s[0] for s in subs])
+    cfg = np.array([s[1] for s in subs], np.int32)
+    _, _, S, _ = O.sim_hier4(th[box], cfg, sm[box], seed, cut, want_S=True)
+    S32, c32 = _decide32(S, cut)
+    N = sm[box]
+    R = np.array([np.sum(S32[t, : N[t]] < c32) for t in range(len(subs))])
+    assert np.array_equal(_np(g["reject"]), R)
+    cp = O.cp_upper(R, N, w["delta"])
+    V = O._pad_vertices(subs, th)
+    ub, _ = O.tile_bound("binom", th[box], V, cp)
+    np.testing.assert_allclose(_np(g["cp_upper"]), cp, rtol=1e-9)
+    np.testing.assert_allclose(_np(g["tile_bound"]), ub, rtol=1e-9)
+    oc = O.calibrate("hier4", th, rd, sm, seed, w["alpha"], key_dtype=np.float32, cut=cut)
+    np.testing.assert_allclose(_np(g["alpha_prime"]), oc["alpha_prime"], rtol=1e-9)
+    frac = (N + 1.0) * oc["alpha_prime"]
+    near = np.abs(frac - np.round(frac)) < 1e-7
+    assert np.all((_np(g["k"]) == oc["k"]) | near)
+    same = _np(g["k"]) == oc["k"]
+    assert np.array_equal(_np(g["lambda_tile"])[same], oc["lam"][same])
+    assert np.array_equal(_np(g["reject_at_lambda"])[same], oc["reject_at_lam"][same])
+    P.close()
+    return len(subs)
+
+
+def test_hier4_small_grid_parity():
+    n = _compare(W.hier4_grid(3, 600, seed=4), seed=4)
+    assert n > 81   # boxes cut by the null hyperplanes give several tiles
+
+
+def test_hier4_uneven_sims_and_cut():
+    w = W.hier4_grid(2, 100, lo=-0.5, hi=0.5, seed=6)
+    w["sims"] = W.uneven_sims(w["theta"].shape[0], seed=3, lo_pow=6, n_classes=3)   # 64..256
+    _compare(w, seed=6, cut=0.2)
+
+
+def test_hier4_full_workload_sampled_tiles():
+    """16^4 boxes on [-1,1]^4, 32,768 sims per tile (the calibration workload), oracle on sampled tiles."""
+    w = W.hier4_16()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("hier4", th, rd, sm)
+    print(f"[hier4] full workload: {P.n_tiles} tiles", flush=True)
+    g = P.calibrate(w["seed"], alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    tiles_box = P.tiles["box"]
+    rng = np.random.default_rng(1)
+    pick = np.unique(np.concatenate([[0, P.n_tiles - 1], rng.choice(P.n_tiles, 3, replace=False)]))
+    boxes = np.unique(tiles_box[pick])
+    sub = W.subsample(w, boxes)
+    subs = O.subtiles("hier4", sub["theta"], sub["radii"])
+    oc = O.calibrate("hier4", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["alpha"], key_dtype=np.float32,
+                     cut=0.05)
+    # map the oracle's (sub-box, b) tiles to the GPU's tile ids
+    gpu_of = {(int(b), int(c)): t for t, (b, c) in enumerate(zip(tiles_box, P.tiles["cfg"]))}
+    ids = np.array([gpu_of[(int(boxes[s[0]]), int(s[1]))] for s in subs])
+    np.testing.assert_allclose(_np(g["alpha_prime"])[ids], oc["alpha_prime"], rtol=1e-9)
+    same = _np(g["k"])[ids] == oc["k"]
+    assert same.mean() > 0.9
+    assert np.array_equal(_np(g["lambda_tile"])[ids][same], oc["lam"][same])
+    assert np.array_equal(_np(g["reject_at_lambda"])[ids][same], oc["reject_at_lam"][same])
+    lam = _np(g["lambda_tile"])
+    assert float(_np(g["lambda_global"])[0]) == lam.min()
+    assert np.all(_np(g["reject_at_lambda"]) < _np(g["k"]))
+    P.close()
