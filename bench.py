@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
 """Throughput of one step of the CSE hot path on one MI355X.
 
-Workload: 2-arm binomial design (n = 35 per arm, pooled two-proportion z, reject z > 1.96),
-256 x 256 boxes on logit [-3, 1]^2 kept to theta1 <= theta0 (32,896 tiles, 256 of them
-triangles cut by the null boundary), 8,192 simulations per tile, seed 0.
+Default workload (the metric's configuration): 2-arm binomial design (n = 35 per arm, pooled
+two-proportion z, reject z > 1.96), 256 x 256 boxes on logit [-3, 1]^2 kept to
+theta1 <= theta0 (32,896 tiles, 256 of them triangles cut by the null boundary), 8,192
+simulations per tile, seed 0.  --workload selects the others (2^20-tile forward + gradient,
+4-arm hierarchical calibration, 1-D z-test); they are listed in WORKLOADS.
 
 One step = one call of cse_calibrate with every output requested: the inverted Tilt-Bound
-target alpha'_i and k_i, the fused simulation (Philox common random numbers, draws, pooled z,
-rejection counts at the fixed cut, score sums for the gradient, per-simulation calibration
-keys), the order-statistic selection lambda*_i and its count below, lambda* = min, the
-gradient, and the Clopper-Pearson + Tilt-Bound of every tile.  The platten (null clipping,
-vertices, thresholds, batch plan) is built once before timing and reported separately.
+target alpha'_i and k_i, the fused simulation (Philox common random numbers, draws, design
+statistic, rejection counts at the fixed cut, score sums for the gradient, per-simulation
+calibration keys), the order-statistic selection lambda*_i and its count below,
+lambda* = min, the gradient, and the Clopper-Pearson + Tilt-Bound of every tile.  For the
+2^20-tile workload the step is cse_validate (forward, gradient, bound; no calibration).  The
+platten (null clipping, vertices, thresholds, batch plan, 4-arm posterior table) is built
+once before timing and reported separately.
 
 Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
 """
@@ -27,15 +31,35 @@ sys.path.insert(0, ROOT)
 
 METRIC = "sim·tiles/s, TIE+gradient+calibration vs plain fwd at equal bound; % roofline"
 VALU_PEAK = 256 * 4 * 64 * 2.4e9 / 4   # lane-ops/s: 256 CUs x 4 SIMDs x one wave64 op per 4 clocks
-# Algorithmic integer work of the fused 2-arm kernel:
-OPS_PHILOX_PER_SIM = 18 * 10 * 4       # per (workgroup, simulation): 18 blocks x 10 rounds x
-                                       # (2 32x32->64 products + 2 xor3), shared by the 4 batches
-OPS_COUNT_PER_SIM = 2 * 35 * 8 * 2     # per (batch, simulation): 70 words x 8 thresholds x (cmp+add)
-OPS_PER_SIM_TILE = 5                   # decision, accumulate, key store
+
+# Algorithmic integer work per unit (lane-ops), by fused kernel:
+#   2-arm: per (workgroup, simulation) 18 Philox blocks x 10 rounds x (2 32x32->64 products
+#   + 2 xor3), shared by the 4 batches of the group; per (batch, simulation) 70 words x 8
+#   thresholds x (compare + add); per (simulation, tile) decision, accumulate, key store.
+B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 4
+#   4-arm: per (workgroup, simulation) 35 Philox blocks; per (batch, simulation) 35 words x
+#   (4 + 4 + 2 + 2) thresholds x (compare + add); per (simulation, box) outcome index (3),
+#   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store.
+H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
+
+WORKLOADS = {
+    "binom2_256_tri": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
+                      "(32,896 tiles), 8,192 sims/tile, seed 0, alpha 0.025, delta 0.01; "
+                      "step = calibrate + validate + gradient",
+    "binom2_1024_full": "binom2 n=35 pooled-z, all 1024x1024 boxes on [-3,1]^2 (1,048,576 tiles), "
+                        "16,384 sims/tile, seed 0, delta 0.01; step = forward TIE + score gradient + "
+                        "Clopper-Pearson/Tilt-Bound (validate)",
+    "hier4_16": "hier4 n=35 hierarchical Bayes (90-node sigma^2 quadrature), 16^4 boxes on [-1,1]^4 clipped "
+                "to the null configurations, 32,768 sims/tile, seed 0, alpha 0.025, delta 0.01; "
+                "step = calibrate + validate",
+    "ztest1d_64": "1-D z-test, 64 tiles on [-1,0], 10,000 sims/tile, seed 0, alpha 0.025, delta 0.01; "
+                  "step = calibrate + validate + gradient",
+}
 
 
-def cpu_baseline(w, target_s: float = 15.0):
-    """The oracle as it stands (validation pass + calibration pass), on a sample of tiles."""
+def cpu_baseline(name, w, design, target_s: float = 15.0):
+    """The oracle as it stands, same step as the GPU (validate, and calibrate where the
+    GPU step calibrates), on a uniform sample of boxes of the same workload."""
     import numpy as np
 
     import oracle as O
@@ -43,21 +67,27 @@ def cpu_baseline(w, target_s: float = 15.0):
 
     rng = np.random.default_rng(1234)
     n = w["theta"].shape[0]
+    keep_all = name == "binom2_1024_full"
+    cut = 0.05 if design == "hier4" else 1.96
 
     def run(m):
         idx = np.sort(rng.choice(n, m, replace=False))
         s = W.subsample(w, idx)
         t = time.perf_counter()
-        O.validate("binom2", s["theta"], s["radii"], s["sims"], w["seed"], w["delta"])
-        O.calibrate("binom2", s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"])
-        return time.perf_counter() - t, int(s["sims"].sum())
+        v = O.validate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["delta"], cut=cut,
+                       keep_all=keep_all)
+        if not keep_all:
+            O.calibrate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"], cut=cut,
+                        key_dtype=np.float32 if design == "hier4" else np.float64)
+        return time.perf_counter() - t, int(np.asarray(s["sims"])[v["box"]].sum()), len(v["box"])
 
-    dt, st = run(8)
-    m = int(min(n, max(8, 8 * target_s / max(dt, 1e-3))))
-    dt, st = run(m)
+    dt, st, nt = run(4)
+    m = int(min(n, max(4, 4 * target_s / max(dt, 1e-3))))
+    dt, st, nt = run(m)
     return {"value": st / dt, "unit": "sim·tiles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} tiles drawn uniformly (seed 1234) of the same workload, all 8,192 sims each; "
-                      f"oracle validate + calibrate, {dt:.1f} s single-threaded"}
+            "sample": f"{m} boxes ({nt} tiles) drawn uniformly (seed 1234) of the same workload, all sims "
+                      f"of each; oracle {'validate' if keep_all else 'validate + calibrate'}, "
+                      f"{dt:.1f} s single-threaded"}
 
 
 def main():
@@ -65,6 +95,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="binom2_256_tri")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -90,28 +121,37 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
         return
-    w = W.binom2_256_tri()
+    name = args.workload
+    w = getattr(W, name)()
+    design = {"binom2_256_tri": "binom2", "binom2_1024_full": "binom2", "hier4_16": "hier4",
+              "ztest1d_64": "ztest1"}[name]
+    keep_all = name == "binom2_1024_full"
+    calibrating = not keep_all
     t0 = time.perf_counter()
-    P = cse.Platten.create("binom2", w["theta"], w["radii"], w["sims"])
+    P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all)
     platten_ms = (time.perf_counter() - t0) * 1e3
     st = cse.cse_platten_stats(P.handle)
-    n = P.n_tiles
+    n, d = P.n_tiles, P.d
     dev = "cuda"
-    o = dict(alpha_prime=torch.empty(n, dtype=torch.float64, device=dev),
-             k=torch.empty(n, dtype=torch.int32, device=dev),
-             lam=torch.empty(n, dtype=torch.float64, device=dev),
-             lam_g=torch.empty(1, dtype=torch.float64, device=dev),
-             rej_at=torch.empty(n, dtype=torch.int32, device=dev),
-             reject=torch.empty(n, dtype=torch.int32, device=dev),
-             score_T=torch.empty((n, 2), dtype=torch.int64, device=dev),
-             grad=torch.empty((n, 2), dtype=torch.float64, device=dev),
-             cp=torch.empty(n, dtype=torch.float64, device=dev),
+    o = P._alloc(dev)
+    o.update(cp=torch.empty(n, dtype=torch.float64, device=dev),
              bound=torch.empty(n, dtype=torch.float64, device=dev))
+    if calibrating:
+        o.update(alpha_prime=torch.empty(n, dtype=torch.float64, device=dev),
+                 k=torch.empty(n, dtype=torch.int32, device=dev),
+                 lam=torch.empty(n, dtype=torch.float64, device=dev),
+                 lam_g=torch.empty(1, dtype=torch.float64, device=dev),
+                 rej_at=torch.empty(n, dtype=torch.int32, device=dev))
 
-    def step():
-        cse.cse_calibrate(P.handle, w["seed"], w["alpha"], o["alpha_prime"], o["k"], o["lam"], o["lam_g"],
-                          o["rej_at"], w["delta"], o["reject"], o["score_T"], None, o["grad"], o["cp"],
-                          o["bound"])
+    if calibrating:
+        def step():
+            cse.cse_calibrate(P.handle, w["seed"], w["alpha"], o["alpha_prime"], o["k"], o["lam"], o["lam_g"],
+                              o["rej_at"], w["delta"], o["reject"], o["score_T"], o["score_Z"], o["grad"],
+                              o["cp"], o["bound"])
+    else:
+        def step():
+            cse.cse_validate(P.handle, w["seed"], w["delta"], o["reject"], o["score_T"], o["score_Z"], o["grad"],
+                             o["cp"], o["bound"])
 
     for _ in range(args.warmup):
         step()
@@ -125,22 +165,37 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     cse.cse_profile_enable(False)
+    sim_kernel = {"binom2": "binom2", "hier4": "hier4", "ztest1": "ztest1"}[design] + ("_calib" if calibrating else "")
     kern = {}
-    for name in ("binom2_calib", "select", "bound_invert", "bound_validate", "cp_table"):
-        cnt, ms = cse.cse_profile_get(name)
-        kern[name] = round(ms / max(cnt, 1), 5)
+    for kn in (sim_kernel, "select", "bound_invert", "bound_validate"):
+        cnt, ms = cse.cse_profile_get(kn)
+        if cnt:
+            kern[kn] = round(ms / cnt, 5)
     total = st["total_sims"] * args.steps
     value = total / dt
     ms_step = dt / args.steps * 1e3
 
-    # roofline of the dominant kernel (fused simulation, calibration variant)
-    ops = (st["group_sims"] * OPS_PHILOX_PER_SIM + st["batch_sims"] * OPS_COUNT_PER_SIM
-           + st["total_sims"] * OPS_PER_SIM_TILE)
-    k_s = kern["binom2_calib"] * 1e-3
-    achieved = ops / k_s if k_s > 0 else 0.0
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12, "unit": "Tops/s (int32 VALU)",
-            "frac": achieved / VALU_PEAK, "traffic": None, "kernel": "k_binom2<KEYS=true>",
-            "kernel_ms": kern["binom2_calib"], "ops_per_launch": ops}
+    # roofline of the dominant kernel: the fused simulation
+    if design == "binom2":
+        ops = (st["group_sims"] * B2_PHILOX + st["batch_sims"] * B2_COUNT
+               + st["total_sims"] * (B2_TILE_CAL if calibrating else B2_TILE_FWD))
+        kname = f"k_binom2<KEYS={'true' if calibrating else 'false'}>"
+    elif design == "hier4":
+        boxes = np.unique(P.tiles["box"])
+        box_sims = int(np.asarray(w["sims"])[boxes].sum())
+        ops = (st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + box_sims * H4_BOX
+               + st["total_sims"] * H4_TILE)
+        kname = "k_hier4<KEYS=true>"
+    else:
+        ops = None
+        kname = "k_ztest1<KEYS=true>"
+    k_s = kern.get(sim_kernel, 0.0) * 1e-3
+    roof = None
+    if ops is not None and k_s > 0:
+        achieved = ops / k_s
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
+                "unit": "Tops/s (int32 VALU)", "frac": achieved / VALU_PEAK, "traffic": None,
+                "kernel": kname, "kernel_ms": kern[sim_kernel], "ops_per_launch": ops}
 
     # the plain forward-only per-tile path, same tiles, seed and N: identical counts (equal bound)
     plain = None
@@ -160,23 +215,25 @@ def main():
             print("bench.py: per-tile path counts differ from the fused path", file=sys.stderr)
             sys.exit(1)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(name, w, design)
     res = {
         "metric": METRIC, "value": value, "unit": "sim·tiles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "u32/f64", "data": "synthetic",
-        "config": {"workload": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
-                               "(32,896 tiles), 8,192 sims/tile, seed 0, alpha 0.025, delta 0.01",
-                   "tiles": n, "sims_per_tile": 8192, "parallelism": "single GPU"},
+        "vs_baseline": None, "dtype": "u32/f32/f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS[name], "name": name, "tiles": n,
+                   "sims_per_tile": int(np.max(w["sims"])), "parallelism": "single GPU"},
         "speedup_vs_plain_fwd": (value / plain["value"]) if plain else None,
         "plain_fwd_per_tile": plain,
         "kernel_avg_ms": kern,
         "platten_build_ms": platten_ms,
-        "lambda_global": float(o["lam_g"].item()),
-        "max_tile_bound": float(o["bound"].max().item()),
+        "max_tile_bound": float(o["bound"].max().item()) if n else None,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if calibrating:
+        res["lambda_global"] = float(o["lam_g"].item())
+    if design == "hier4":
+        res["posterior_table_build_ms"] = st["table_build_us"] / 1e3
     print(json.dumps(res), flush=True)
     P.close()
 

@@ -324,6 +324,10 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
     CSE_LAUNCH(cse::launch_zero(reject + tile_begin, (tile_end - tile_begin) * sizeof(int32_t), st));
     for (int64_t t = tile_begin; t < tile_end; ++t) {
         Timed tm("plain_tile", st);
+        if (P.design.kind == CSE_HIER4) {
+            CSE_LAUNCH(cse::launch_hier4_plain(P, seed, t, (uint32_t *)(reject + t), st));
+            continue;
+        }
         uint32_t T0 = 0, T1 = 0;
         if (P.family == cse::FAM_BINOM) {
             T0 = P.tile_T[t * 2];

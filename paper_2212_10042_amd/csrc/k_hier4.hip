@@ -342,4 +342,55 @@ hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *key
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------------------------------
+// Plain forward path: one launch per tile (box centre, configuration b), one simulation per
+// thread, each thread drawing its own 140 words; the baseline the fused kernel is timed against.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(WG) void k_hier4_plain(uint32_t T0, uint32_t T1, uint32_t T2, uint32_t T3,
+                                                    uint32_t bmask, uint32_t n_sims, uint32_t key0,
+                                                    uint32_t key1, const float4 *__restrict__ tbl,
+                                                    float cut, uint32_t *__restrict__ R_tile) {
+    constexpr int NP = NP35;
+    constexpr int M1 = NP + 1;
+    __shared__ uint32_t s_cnt;
+    if (threadIdx.x == 0) s_cnt = 0u;
+    __syncthreads();
+    const uint32_t k = blockIdx.x * WG + threadIdx.x;
+    uint32_t r = 0u;
+    if (k < n_sims) {
+        int y[4] = {0, 0, 0, 0};
+        const uint32_t T[4] = {T0, T1, T2, T3};
+#pragma unroll
+        for (int b = 0; b < NP; ++b) {   // 4 * 35 words = 35 blocks
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int widx = 4 * b + l;
+                const int a = widx / NP;
+                y[a] += (u32x4_get(w, l) < T[a]) ? 1 : 0;
+            }
+        }
+        const float4 q = tbl[((y[0] * M1 + y[1]) * M1 + y[2]) * M1 + y[3]];
+        float sb = INFINITY;
+        if (bmask & 1u) sb = fminf(sb, q.x);
+        if (bmask & 2u) sb = fminf(sb, q.y);
+        if (bmask & 4u) sb = fminf(sb, q.z);
+        r = (sb < cut) ? 1u : 0u;
+    }
+    const unsigned long long m = __ballot(r);
+    if ((threadIdx.x & (WAVE - 1)) == 0) atomicAdd(&s_cnt, (uint32_t)__popcll(m));
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt) atomicAdd(R_tile, s_cnt);
+}
+
+hipError_t launch_hier4_plain(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st) {
+    const uint32_t N = (uint32_t)P.tile_N[t];
+    const uint32_t grid = (N + WG - 1) / WG;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    const uint32_t *T = &P.tile_T[t * 4];
+    hipLaunchKernelGGL(k_hier4_plain, dim3(grid), dim3(WG), 0, st, T[0], T[1], T[2], T[3],
+                       (uint32_t)P.tile_cfg[t], N, k0, k1, P.d_h4tbl, (float)P.design.cut, R_tile);
+    return hipGetLastError();
+}
+
 }  // namespace cse

@@ -143,3 +143,17 @@ def test_hier4_full_workload_sampled_tiles():
     assert float(_np(g["lambda_global"])[0]) == lam.min()
     assert np.all(_np(g["reject_at_lambda"]) < _np(g["k"]))
     P.close()
+
+
+def test_hier4_per_tile_path_matches_fused():
+    """The plain one-launch-per-tile path draws the same Philox words: identical counts."""
+    w = W.hier4_grid(3, 500, seed=2)
+    P = cse.Platten.create("hier4", w["theta"], w["radii"], w["sims"], cut=0.1)
+    print(f"[hier4] per-tile path: {P.n_tiles} tiles", flush=True)
+    o = P.simulate(seed=9)
+    R = torch.empty(P.n_tiles, dtype=torch.int32, device="cuda")
+    cse.cse_simulate_per_tile(P.handle, 9, 0, P.n_tiles, R)
+    torch.cuda.synchronize()
+    assert torch.equal(R, o["reject"])
+    assert int(o["reject"].sum()) > 0
+    P.close()
