@@ -64,6 +64,13 @@ def lib():
         L.orc_hier4_node.argtypes = [ctypes.c_int, P, P]
         L.orc_hier4_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, dbl, P, P, P, i64, P]
         L.orc_hier4_table.argtypes = [ctypes.c_int, P, i64, P]
+        L.orc_hier4_summary.argtypes = [P, P, P, P, P]
+        L.orc_gh16.argtypes = [P, P]
+        L.orc_z95.restype = dbl
+        L.orc_pbest.argtypes = [P, P, P]
+        L.orc_psucc.argtypes = [dbl, dbl, dbl, dbl, ctypes.c_int]
+        L.orc_psucc.restype = dbl
+        L.orc_phase23_sim.argtypes = [i64, P, P, P, u64, dbl, P, P, P, P, i64, P, P]
         _lib = L
     return _lib
 
@@ -161,6 +168,64 @@ def sim_hier4(theta_tiles, cfg, sims, seed: int, cut: float, n: int = N_PER_ARM,
     Y = np.full((m, stride), -1, np.int64) if want_S else None
     lib().orc_hier4_sim(m, _p(th), _p(cf), _p(sm), seed, n, cut, _p(R), _p(sT), _p(S), stride, _p(Y))
     return R, sT, S, Y
+
+
+N_EMBED_P23 = 350   # patients per arm in the embedding of the Phase II/III design (Section 8)
+
+
+def hier4_summary(y, n):
+    """Posterior summary with per-arm sample sizes (oracle_hier.c): dict of P[3], Sc[3] = 1 - P,
+    mean[4], var[4] (moment-matched node mixture), dmean[3], dvar[3] of theta_i - theta_0."""
+    yy = np.ascontiguousarray(y, np.int32)
+    nn = np.ascontiguousarray(n, np.int32)
+    out = np.zeros(20)
+    lib().orc_hier4_summary(_p(yy), _p(nn), _p(out), None, None)
+    return dict(P=out[0:3], Sc=out[3:6], mean=out[6:10], var=out[10:14], dmean=out[14:17], dvar=out[17:20])
+
+
+def gh16():
+    x = np.zeros(16)
+    w = np.zeros(16)
+    lib().orc_gh16(_p(x), _p(w))
+    return x, w
+
+
+def z95() -> float:
+    return float(lib().orc_z95())
+
+
+def pbest(m, v):
+    """P(theta_i is the largest) for independent normal marginals (oracle_phase23.c)."""
+    mm = np.ascontiguousarray(m, np.float64)
+    vv = np.ascontiguousarray(v, np.float64)
+    out = np.zeros(4)
+    lib().orc_pbest(_p(mm), _p(vv), _p(out))
+    return out
+
+
+def psucc(md, vd, m0, mi, m_add) -> float:
+    return float(lib().orc_psucc(md, vd, m0, mi, m_add))
+
+
+def sim_phase23(theta_tiles, cfg, sims, seed: int, lam: float, want_S=False, want_info=False,
+                want_trace=False):
+    """Phase II/III design per tile (box centre, configuration b): R = #{S < lam}, sumY [m, 4],
+    sumN [m, 4] (observed counts / sample sizes summed over those simulations), optionally S,
+    info [m, stride, 11] (outcome, selected arm, looks, n[4], y[4]) and trace [m, stride, 5, 8]."""
+    th = np.ascontiguousarray(np.asarray(theta_tiles, np.float64).reshape(-1, 4))
+    cf = np.ascontiguousarray(cfg, np.int32)
+    sm = np.ascontiguousarray(sims, np.int32)
+    m = th.shape[0]
+    R = np.zeros(m, np.int32)
+    sY = np.zeros((m, 4), np.int64)
+    sN = np.zeros((m, 4), np.int64)
+    stride = int(sm.max()) if m else 0
+    S = np.full((m, stride), np.nan) if want_S else None
+    info = np.full((m, stride, 11), -1, np.int32) if want_info else None
+    tr = np.full((m, stride, 5, 8), -1, np.int32) if want_trace else None
+    lib().orc_phase23_sim(m, _p(th), _p(cf), _p(sm), seed, lam, _p(R), _p(sY), _p(sN), _p(S), stride,
+                          _p(info), _p(tr))
+    return dict(R=R, sumY=sY, sumN=sN, S=S, info=info, trace=tr)
 
 
 # --------------------------------------------------- exponential families
@@ -296,6 +361,12 @@ def family_of(design: str) -> str:
     return "normal" if design == "ztest1" else "binom"
 
 
+def n_of(design: str) -> int:
+    """Patients per arm of the exponential family the bound is taken in: the Phase II/III
+    design is a function of its embedding with 350 potential patients per arm (Section 8)."""
+    return N_EMBED_P23 if design == "phase23" else N_PER_ARM
+
+
 def _enumerate_vertices(G, h, d, tol=1e-12):
     """Vertices of {x : G x <= h} by brute force over d-subsets of active constraints."""
     verts = []
@@ -389,6 +460,8 @@ def score_gradient(design: str, theta, R, score, sims, n: int = N_PER_ARM):
     N = np.asarray(sims, np.float64)
     if design == "ztest1":
         return (np.asarray(score, np.float64).reshape(-1) / N)[:, None]
+    if design == "phase23":   # score already sum (y_obs - n_obs expit theta) over rejections
+        return np.asarray(score, np.float64) / N[:, None]
     gA = n * sps.expit(theta)
     return (np.asarray(score, np.float64) - np.asarray(R, np.float64)[:, None] * gA) / N[:, None]
 
@@ -401,6 +474,11 @@ def _tile_simulation(design, theta, sims, subs, seed, cut, want_S):
         cfg = np.array([s[1] for s in subs], np.int32)
         R, sT, S, _ = sim_hier4(theta[box], cfg, np.asarray(sims)[box], seed, cut, want_S=want_S)
         return R, sT, S
+    if design == "phase23":
+        cfg = np.array([s[1] for s in subs], np.int32)
+        o = sim_phase23(theta[box], cfg, np.asarray(sims)[box], seed, cut, want_S=want_S)
+        score = o["sumY"] - o["sumN"] * sps.expit(theta[box])
+        return o["R"], score, o["S"]
     R, score, S = simulate(design, theta, sims, seed, cut, want_S)
     return R[box], score[box], (S[box] if S is not None else None)
 
@@ -415,10 +493,10 @@ def validate(design: str, theta, radii, sims, seed: int, delta: float, cut: floa
     Rb, score, _ = _tile_simulation(design, theta, sims, subs, seed, cut, False)
     cp = cp_upper(Rb, N, delta)
     V = _pad_vertices(subs, theta)
-    ub, qs = tile_bound(family_of(design), theta[box], V, cp)
+    ub, qs = tile_bound(family_of(design), theta[box], V, cp, n=n_of(design))
     out = dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
                q=qs, score=score, subs=subs)
-    if design != "hier4":
+    if design not in ("hier4", "phase23"):
         R, sc, _ = simulate(design, theta, sims, seed, cut)
         out.update(R_box=R, score_box=sc)
     return out
@@ -442,7 +520,7 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
     subs = subtiles(design, theta, radii, keep_all)
     box = np.array([s[0] for s in subs])
     V = _pad_vertices(subs, theta)
-    ap, qs = tile_inverse(family_of(design), theta[box], V, alpha)
+    ap, qs = tile_inverse(family_of(design), theta[box], V, alpha, n=n_of(design))
     N = sims[box]
     k = np.floor((N + 1.0) * ap).astype(np.int64)
     _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True)

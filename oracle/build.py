@@ -10,7 +10,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["oracle_sim.c", "oracle_hier.c"]
+SOURCES = ["oracle_sim.c", "oracle_hier.c", "oracle_phase23.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

@@ -105,9 +105,12 @@ void orc_hier4_node(int j, double *ls2, double *logw) {
 /* Posterior of one outcome y (counts out of n per arm).  Outputs P[3] = P(theta_i > theta_0 | y)
  * for i = 1, 2, 3; if diag != NULL also per-node mode [NODES][D], log weight [NODES] and
  * Newton iterations [NODES] (for the tests). */
-static void posterior_full(const int32_t *y, int n, double *P, double *Sc, double *diag_mode,
-                           double *diag_logw, int32_t *diag_iters) {
+/* Per-arm sample sizes nv[4].  Outputs P[3], Sc[3] = 1 - P (summed as complements); if
+ * mix != NULL the moment-matched mixture summary (see orc_hier4_summary). */
+static void posterior_nv(const int32_t *y, const int32_t *nv, double *P, double *Sc, double *mix,
+                         double *diag_mode, double *diag_logw, int32_t *diag_iters) {
     double lw[NODES], pr[NODES][3], pc[NODES][3];
+    double mode[NODES][D], cdiag[NODES][D], dvar[NODES][3];
     for (int j = 0; j < NODES; ++j) {
         double ls2, logtrap;
         orc_hier4_node(j, &ls2, &logtrap);
@@ -122,7 +125,7 @@ static void posterior_full(const int32_t *y, int n, double *P, double *Sc, doubl
         /* log|Q| = -log|Sigma| = -((D - 1) log s2 + log(s2 + D TAU2)) (matrix determinant lemma) */
         const double logdetQ = -((D - 1) * ls2 + log(s2 + D * TAU2));
         double th[D];
-        for (int a = 0; a < D; ++a) th[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
+        for (int a = 0; a < D; ++a) th[a] = log((y[a] + 0.5) / (nv[a] - y[a] + 0.5));
         int it = 0;
         double H[D][D];
         for (it = 0; it < 200; ++it) {
@@ -130,12 +133,12 @@ static void posterior_full(const int32_t *y, int n, double *P, double *Sc, doubl
             for (int a = 0; a < D; ++a) {
                 double qa = 0.0;
                 for (int c = 0; c < D; ++c) qa += Q[a][c] * (th[c] - M0);
-                g[a] = y[a] - n * expit(th[a]) - qa;
+                g[a] = y[a] - nv[a] * expit(th[a]) - qa;
             }
             for (int r = 0; r < D; ++r)
                 for (int c = 0; c < D; ++c) {
                     double p = expit(th[r]);
-                    H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
+                    H[r][c] = -Q[r][c] - (r == c ? nv[r] * p * (1.0 - p) : 0.0);
                 }
             double A[D][D], step[D], rhs[D];
             memcpy(A, H, sizeof A);
@@ -152,13 +155,13 @@ static void posterior_full(const int32_t *y, int n, double *P, double *Sc, doubl
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) {
                 double p = expit(th[r]);
-                H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
+                H[r][c] = -Q[r][c] - (r == c ? nv[r] * p * (1.0 - p) : 0.0);
             }
         double negH[D][D];
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) negH[r][c] = -H[r][c];
         double ll = 0.0, quad = 0.0;
-        for (int a = 0; a < D; ++a) ll += y[a] * th[a] - n * softplus(th[a]);
+        for (int a = 0; a < D; ++a) ll += y[a] * th[a] - nv[a] * softplus(th[a]);
         for (int r = 0; r < D; ++r)
             for (int c = 0; c < D; ++c) quad += (th[r] - M0) * Q[r][c] * (th[c] - M0);
         double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet4(negH);
@@ -175,6 +178,16 @@ static void posterior_full(const int32_t *y, int n, double *P, double *Sc, doubl
             double sd = sqrt(x[i] - x[0]);
             pr[j][i - 1] = Phi((th[i] - th[0]) / sd);
             pc[j][i - 1] = Phi(-(th[i] - th[0]) / sd);   /* 1 - Phi(z), no cancellation */
+            dvar[j][i - 1] = x[i] - x[0];
+        }
+        for (int a = 0; a < D; ++a) {
+            /* C_aa = e_a^T (-H)^{-1} e_a */
+            double A[D][D], e[D] = {0, 0, 0, 0}, x[D];
+            memcpy(A, negH, sizeof A);
+            e[a] = 1.0;
+            solve4(A, e, x);
+            cdiag[j][a] = x[a];
+            mode[j][a] = th[a];
         }
         if (diag_mode)
             for (int a = 0; a < D; ++a) diag_mode[j * D + a] = th[a];
@@ -186,14 +199,52 @@ static void posterior_full(const int32_t *y, int n, double *P, double *Sc, doubl
     for (int j = 0; j < NODES; ++j) s += exp(lw[j] - mx);
     double lse = mx + log(s);
     for (int i = 0; i < 3; ++i) P[i] = Sc[i] = 0.0;
+    double pj[NODES];
     for (int j = 0; j < NODES; ++j) {
-        double pj = exp(lw[j] - lse);
+        pj[j] = exp(lw[j] - lse);
         if (diag_logw) diag_logw[j] = lw[j] - lse;
         for (int i = 0; i < 3; ++i) {
-            P[i] += pj * pr[j][i];
-            Sc[i] += pj * pc[j][i];
+            P[i] += pj[j] * pr[j][i];
+            Sc[i] += pj[j] * pc[j][i];
         }
     }
+    if (!mix) return;
+    /* Moment matching of the node mixture (two passes: means, then spreads about them):
+     * mean_a = sum_j pi_j mode_ja, var_a = sum_j pi_j (C_j,aa + (mode_ja - mean_a)^2), and the
+     * same for the differences d_i = theta_i - theta_0. */
+    double mean[D] = {0, 0, 0, 0}, var[D] = {0, 0, 0, 0}, dm[3] = {0, 0, 0}, dv[3] = {0, 0, 0};
+    for (int j = 0; j < NODES; ++j)
+        for (int a = 0; a < D; ++a) mean[a] += pj[j] * mode[j][a];
+    for (int i = 0; i < 3; ++i) dm[i] = mean[i + 1] - mean[0];
+    for (int j = 0; j < NODES; ++j) {
+        for (int a = 0; a < D; ++a) {
+            double e = mode[j][a] - mean[a];
+            var[a] += pj[j] * (cdiag[j][a] + e * e);
+        }
+        for (int i = 0; i < 3; ++i) {
+            double e = (mode[j][i + 1] - mode[j][0]) - dm[i];
+            dv[i] += pj[j] * (dvar[j][i] + e * e);
+        }
+    }
+    for (int i = 0; i < 3; ++i) { mix[i] = P[i]; mix[3 + i] = Sc[i]; }
+    for (int a = 0; a < D; ++a) { mix[6 + a] = mean[a]; mix[10 + a] = var[a]; }
+    for (int i = 0; i < 3; ++i) { mix[14 + i] = dm[i]; mix[17 + i] = dv[i]; }
+}
+
+static void posterior_full(const int32_t *y, int n, double *P, double *Sc, double *diag_mode,
+                           double *diag_logw, int32_t *diag_iters) {
+    const int32_t nv[D] = {n, n, n, n};
+    posterior_nv(y, nv, P, Sc, NULL, diag_mode, diag_logw, diag_iters);
+}
+
+/* Posterior summary with per-arm sample sizes n[4] (counts y[a] out of n[a]):
+ * out[0..2] P(theta_i > theta_0), out[3..5] their complements, out[6..9] mixture means of
+ * theta_a, out[10..13] mixture variances, out[14..16] means and out[17..19] variances of
+ * theta_i - theta_0.  Diagnostics as in orc_hier4_posterior_full when non-NULL. */
+void orc_hier4_summary(const int32_t *y, const int32_t *n, double *out, double *diag_mode,
+                       double *diag_logw) {
+    double P[3], Sc[3];
+    posterior_nv(y, n, P, Sc, out, diag_mode, diag_logw, NULL);
 }
 
 void orc_hier4_posterior_full(const int32_t *y, int n, double *P, double *diag_mode,
