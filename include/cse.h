@@ -59,13 +59,25 @@ typedef enum {
      * Section 10.1 (theta_i ~ N(mu, sigma^2), mu ~ N(-1.34, 100), sigma^2 ~ IG(0.0005,
      * 0.000005)); H_i: theta_i <= theta_0 for i = 1..3; statistic for null configuration
      * b: S_b = min_{i in b} (1 - P(p_i > p_0 | y)); reject when S_b < cut.  d = 4. */
-    CSE_HIER4 = 3
+    CSE_HIER4 = 3,
+    /* Phase II/III Bayesian selection design (Section 10.2 and its appendix): four Bernoulli
+     * arms (arm 0 control) embedded with n_per_arm = 350 potential patients each (Section 8);
+     * Phase II of up to 400 patients with three looks (arm dropping for p_best < 0.15,
+     * selection when p_success > 0.70, 0.60 at the last look), Phase III of up to 200 + 200
+     * on the selected arm s and control with an interim (success when
+     * P(p_s > p_0) > 0.95, futility when p_success < 0.20) and a final analysis that rejects
+     * H_s when P(p_s > p_0) > 1 - cut.  Decisions use the hierarchical model of CSE_HIER4 with
+     * the observed sample sizes.  Statistic for null configuration b: -inf for an early
+     * success with s in b, 1 - P_final(p_s > p_0) for a final analysis with s in b, +inf
+     * otherwise; a false rejection at lambda is S < lambda.  d = 4. */
+    CSE_PHASE23 = 4
 } cse_design_kind;
 
 typedef struct {
     int32_t kind;       /* cse_design_kind                                      */
-    int32_t n_arms;     /* d: 1 (ZTEST1), 2 (BINOM2_Z), 4 (HIER4)                */
-    int32_t n_per_arm;  /* patients per arm for binomial designs (1..63); ignored for ZTEST1 */
+    int32_t n_arms;     /* d: 1 (ZTEST1), 2 (BINOM2_Z), 4 (HIER4, PHASE23)       */
+    int32_t n_per_arm;  /* patients per arm: 35 for BINOM2_Z and HIER4, 350 (the embedding)
+                           for PHASE23; ignored for ZTEST1                        */
     int32_t reserved;   /* must be 0                                             */
     double cut;         /* fixed rule of the design used by cse_simulate/validate */
 } cse_design;
@@ -117,10 +129,15 @@ int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32
  *   reject   int32 [n_tiles]       R_i = number of simulations whose F_b(X) = 1 (FWER event of
  *                                  the tile's configuration b, Section 4).
  *   score_T  int64 [n_tiles][d] or NULL: binomial designs, sum over rejecting simulations of
- *                                  the sufficient statistic T(x) (arm success counts, Example 1).
+ *                                  the sufficient statistic T(x) (arm success counts, Example 1);
+ *                                  PHASE23: int64 [n_tiles][2d], the sums of the observed success
+ *                                  counts y_a, then of the observed sample sizes n_a.
  *   score_Z  float64 [n_tiles] or NULL: ZTEST1, sum over rejecting simulations of X - theta.
  *   grad     float64 [n_tiles][d] or NULL: score-function estimate of d f / d theta,
- *                                  (sum_rej T(x) - R grad A(theta)) / N  (exponential family).
+ *                                  (sum_rej T(x) - R grad A(theta)) / N  (exponential family);
+ *                                  PHASE23: (sum_rej y_a - sum_rej n_a expit(theta_a)) / N (the
+ *                                  unobserved embedded patients contribute zero in expectation).
+ *                                  CSE_HIER4 provides neither (CSE_EUNSUPPORTED).
  * Errors: CSE_EINVAL (NULL reject, bad handle), CSE_EHIP.
  */
 int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *score_T,

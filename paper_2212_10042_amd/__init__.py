@@ -23,7 +23,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcse.so")
 
 CSE_OK, CSE_EINVAL, CSE_ENOMEM, CSE_EHIP, CSE_EUNSUPPORTED, CSE_ECALIB = 0, -1, -2, -3, -4, -5
-CSE_ZTEST1, CSE_BINOM2_Z, CSE_HIER4 = 1, 2, 3
+CSE_ZTEST1, CSE_BINOM2_Z, CSE_HIER4, CSE_PHASE23 = 1, 2, 3, 4
 CSE_PLATTEN_KEEP_ALL = 1
 
 EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
@@ -102,12 +102,16 @@ def _stream(stream=None):
 
 
 # ------------------------------------------------------------------ C-ABI mirrors
-def make_design(kind: str | int, cut: float | None = None, n_per_arm: int = 35) -> cse_design:
-    k = {"ztest1": CSE_ZTEST1, "binom2": CSE_BINOM2_Z, "hier4": CSE_HIER4}.get(kind, kind)
-    d = {CSE_ZTEST1: 1, CSE_BINOM2_Z: 2, CSE_HIER4: 4}[k]
+def make_design(kind: str | int, cut: float | None = None, n_per_arm: int | None = None) -> cse_design:
+    """Design descriptor.  cut defaults: 1.96 (z designs), 0.05 (4-arm hierarchical),
+    0.06253 (Phase II/III final-analysis lambda); n_per_arm: 35, or the embedding's 350."""
+    k = {"ztest1": CSE_ZTEST1, "binom2": CSE_BINOM2_Z, "hier4": CSE_HIER4, "phase23": CSE_PHASE23}.get(kind, kind)
+    d = {CSE_ZTEST1: 1, CSE_BINOM2_Z: 2, CSE_HIER4: 4, CSE_PHASE23: 4}[k]
     if cut is None:
-        cut = 1.96 if k in (CSE_ZTEST1, CSE_BINOM2_Z) else 0.05
-    return cse_design(k, d, n_per_arm if k != CSE_ZTEST1 else 0, 0, float(cut))
+        cut = {CSE_ZTEST1: 1.96, CSE_BINOM2_Z: 1.96, CSE_HIER4: 0.05, CSE_PHASE23: 0.06253}[k]
+    if n_per_arm is None:
+        n_per_arm = 0 if k == CSE_ZTEST1 else (350 if k == CSE_PHASE23 else 35)
+    return cse_design(k, d, n_per_arm, 0, float(cut))
 
 
 def cse_platten_create(design: cse_design, theta, radii, sims, flags: int = 0):
@@ -236,7 +240,8 @@ class Platten:
         kind = self.design.kind
         return dict(
             reject=torch.empty(n, dtype=torch.int32, device=dev),
-            score_T=torch.empty((n, d), dtype=torch.int64, device=dev) if kind == CSE_BINOM2_Z else None,
+            score_T=(torch.empty((n, d), dtype=torch.int64, device=dev) if kind == CSE_BINOM2_Z else
+                     torch.empty((n, 2 * d), dtype=torch.int64, device=dev) if kind == CSE_PHASE23 else None),
             score_Z=torch.empty(n, dtype=torch.float64, device=dev) if kind == CSE_ZTEST1 else None,
             grad=torch.empty((n, d), dtype=torch.float64, device=dev) if kind != CSE_HIER4 else None,
         )

@@ -118,6 +118,10 @@ int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
     } else if (P.design.kind == CSE_HIER4) {
         Timed tm(keys ? "hier4_calib" : "hier4", st);
         CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, keys ? (float *)P.d_keys : nullptr, st));
+    } else if (P.design.kind == CSE_PHASE23) {
+        CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * 2 * P.d * sizeof(unsigned long long), st));
+        Timed tm(keys ? "phase23_calib" : "phase23", st);
+        CSE_LAUNCH(cse::launch_phase23(P, seed, P.d_Rw, P.d_Tw, keys ? (float *)P.d_keys : nullptr, st));
     } else {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "binom2_calib" : "binom2", st);
@@ -326,6 +330,10 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
         Timed tm("plain_tile", st);
         if (P.design.kind == CSE_HIER4) {
             CSE_LAUNCH(cse::launch_hier4_plain(P, seed, t, (uint32_t *)(reject + t), st));
+            continue;
+        }
+        if (P.design.kind == CSE_PHASE23) {
+            CSE_LAUNCH(cse::launch_phase23_tile(P, seed, t, (uint32_t *)(reject + t), st));
             continue;
         }
         uint32_t T0 = 0, T1 = 0;

@@ -14,6 +14,7 @@ constexpr int WAVE = 64;
 constexpr int WG = 256;              // 4 waves per workgroup
 constexpr int MAX_D = 4;
 constexpr int NP35 = 35;             // patients per arm of the binomial designs
+constexpr int P23_NMAX_ARM = 350;    // embedded patients per arm of the Phase II/III design
 
 // ---- tile batches ("blocks"): each wave owns one block for a range of simulations ----
 // 2-arm designs: an 8 x 8 product of distinct arm-0 and arm-1 thresholds, so one
@@ -73,6 +74,25 @@ struct GroupItem {
     int32_t pad[2];
 };
 
+// Arguments of the Phase II/III kernel (device pointers owned by the platten, except the
+// outputs filled in per launch).
+struct P23Args {
+    const WorkItem *items;          // (tile in blk, simulation range) queue entries
+    int64_t n_items;
+    uint32_t *counter;              // queue head, zeroed before each launch
+    const uint32_t *tileT;          // [n_tiles][4] Bernoulli thresholds
+    const int32_t *cfg;             // [n_tiles] null configuration b
+    const int64_t *key_off;         // [n_tiles] first key of the tile (keys contiguous per tile)
+    uint32_t key0, key1;            // Philox key (seed)
+    float cut;                      // lambda of the final analysis (the design's fixed rule)
+    int32_t pad;
+    uint32_t *R;                    // [n_tiles] rejections at cut
+    unsigned long long *sumT;       // [n_tiles][8] sums of observed y_a, then n_a, over rejections
+    float *keys;                    // calibration keys S or NULL
+    const double *gh;               // Gauss-Hermite rule (weight e^{-x^2}): nodes [16], weights [16]
+    double sqrt_pi, z95;            // sqrt(pi), Phi^{-1}(0.95)
+};
+
 // Family of the data model for the bound (Example 1 / Section 4.2).
 enum Family : int32_t { FAM_NORMAL = 1, FAM_BINOM = 2 };
 
@@ -117,6 +137,16 @@ struct Platten {
 
     // design tables (device)
     float4 *d_h4tbl = nullptr;           // 4-arm: (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome
+    // Phase II/III design: per-tile thresholds / configurations, the work queue
+    uint32_t *d_tileT = nullptr;
+    int32_t *d_cfg = nullptr;
+    uint32_t *d_queue = nullptr;
+    double *d_gh = nullptr;              // Gauss-Hermite nodes and weights
+    WorkItem *d_p23items = nullptr;
+    P23Args p23{};
+    int64_t p23_grid = 0;
+    int32_t p23_chunk = 0;               // simulations per queue item
+    std::vector<int64_t> p23_item_off;   // [n_tiles + 1] first queue item of each tile
     int64_t h4_outcomes = 0;
     double table_ms = 0.0;               // time to build the design table at platten creation
     int32_t *d_cut_tbl = nullptr;        // 2-arm: c(y0) = min{y1 : z(y0, y1) > cut}, [n+1]

@@ -1,0 +1,170 @@
+// hier_post.hpp -- float64 posterior of the four-arm hierarchical model of the basket case
+// study (Section 10.1), per thread, for counts y_a out of n_a patients on arm a (arm 0 control):
+//   theta_a | mu, s2 ~ N(mu, s2), mu ~ N(-1.34, 100), s2 ~ InvGamma(0.0005, 0.000005).
+//
+//   * mu is integrated out: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T, with precision
+//     Q = (I - c 11^T) / s2, c = 100 / (s2 + 400) (Sherman-Morrison);
+//   * per node s2_j (90 nodes equally spaced in log s2 on [log 1e-6, log 1e3]) the conditional
+//     posterior of theta is replaced by its Laplace approximation: the mode by Newton's method on
+//     sum_a [y_a theta_a - n_a softplus(theta_a)] - (theta - m0)^T Q (theta - m0) / 2, whose
+//     negative Hessian D - beta 11^T (D_a = n_a p_a (1 - p_a) + 1/s2, beta = c / s2) makes every
+//     step, determinant and covariance C = D^{-1} + g u u^T (u = D^{-1} 1,
+//     g = beta / (1 - beta sum u)) cost O(arms);
+//   * node log weight: Laplace evidence l(mode) + log|Q|/2 - log|D - beta 11^T|/2, plus the log
+//     inverse-gamma density of s2_j and the log trapezoid weight in log s2 (ds2 = s2 dlog s2),
+//     normalised by a running log-sum-exp in float64;
+//   * P_i = sum_j pi_j Phi(z_ij), z_ij = (mode_i - mode_0) / sqrt(C_ii + C_00 - 2 C_i0); the
+//     complements 1 - P_i are summed directly as sum_j pi_j Phi(-z_ij) (relative precision where
+//     P_i is near 1);
+//   * with FULL, the node mixture's moments: means and variances of theta_a and of
+//     theta_i - theta_0 (variance = mean over nodes of C + spread of the modes, accumulated
+//     about a fixed reference point so that no large terms cancel).
+#pragma once
+#include <math.h>
+
+#include "fp64_math.hpp"
+
+namespace cse {
+
+constexpr int HP_NODES = 90;
+
+__device__ __forceinline__ double hp_expit(double x) {
+    return x >= 0.0 ? 1.0 / (1.0 + exp_cw(-x)) : 1.0 - 1.0 / (1.0 + exp_cw(x));
+}
+
+struct HierSummary {
+    double P[3];      // P(theta_i > theta_0 | data), i = 1..3
+    double Sc[3];     // 1 - P_i
+    double mean[4];   // mixture mean of theta_a                    (FULL only)
+    double var[4];    // mixture variance of theta_a                (FULL only)
+    double dvar[3];   // mixture variance of theta_i - theta_0      (FULL only)
+};
+
+// Posterior of counts y[4] out of n[4].  WARM starts each node's Newton iterations at the
+// previous node's mode (the converged mode is the same; only the path differs).
+template <bool FULL, bool WARM>
+__device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], HierSummary &out) {
+    const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
+    const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
+    const double h = (LS2_HI - LS2_LO) / (HP_NODES - 1);
+    const double lgA = lgamma(IG_A), logB = log(IG_B);
+    double th0[4];
+    for (int a = 0; a < 4; ++a) th0[a] = log((y[a] + 0.5) / (n[a] - y[a] + 0.5));
+    double th[4] = {th0[0], th0[1], th0[2], th0[3]};
+
+    double wmax = -INFINITY, wsum = 0.0;
+    double accP[3] = {0.0, 0.0, 0.0}, accS[3] = {0.0, 0.0, 0.0};
+    double m1[4] = {0.0, 0.0, 0.0, 0.0}, m2[4] = {0.0, 0.0, 0.0, 0.0}, d2[3] = {0.0, 0.0, 0.0};
+    for (int j = 0; j < HP_NODES; ++j) {
+        const double ls2 = LS2_LO + h * j;
+        const double s2 = exp(ls2);
+        const double inv_s2 = 1.0 / s2;
+        const double c = TAU2 / (s2 + 4.0 * TAU2);
+        const double beta = c * inv_s2;
+        if (!WARM)
+            for (int a = 0; a < 4; ++a) th[a] = th0[a];
+        double D[4], u[4], gam = 0.0;
+        for (int it = 0; it < 100; ++it) {
+            double dsum = 0.0;
+            for (int a = 0; a < 4; ++a) dsum += th[a] - M0;
+            double g[4], su = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double p = hp_expit(th[a]);
+                // Q (theta - m0) = ((theta_a - m0) - c sum_b (theta_b - m0)) / s2
+                g[a] = (double)y[a] - n[a] * p - ((th[a] - M0) - c * dsum) * inv_s2;
+                D[a] = n[a] * p * (1.0 - p) + inv_s2;
+                u[a] = 1.0 / D[a];
+                su += u[a];
+            }
+            gam = beta / (1.0 - beta * su);
+            double ug = 0.0;
+            for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
+            double mx = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double step = u[a] * g[a] + gam * u[a] * ug;   // (D - beta 11^T)^{-1} g
+                th[a] += step;
+                mx = fmax(mx, fabs(step));
+            }
+            if (mx < 1e-10) break;
+        }
+        // curvature at the final mode
+        double su = 0.0, logdetD = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            const double p = hp_expit(th[a]);
+            D[a] = n[a] * p * (1.0 - p) + inv_s2;
+            u[a] = 1.0 / D[a];
+            su += u[a];
+            logdetD += log(D[a]);
+        }
+        gam = beta / (1.0 - beta * su);
+        const double logdet_negH = logdetD + log1p(-beta * su);
+        const double logdetQ = -(3.0 * ls2 + log(s2 + 4.0 * TAU2));
+        double ll = 0.0, dsum = 0.0, sq = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            ll += y[a] * th[a] - n[a] * softplus_fast(th[a]);
+            const double e = th[a] - M0;
+            dsum += e;
+            sq += e * e;
+        }
+        const double quad = (sq - c * dsum * dsum) * inv_s2;
+        const double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet_negH;
+        const double logprior = IG_A * logB - lgA - (IG_A + 1.0) * ls2 - IG_B * inv_s2;
+        const double logtrap = log((j == 0 || j == HP_NODES - 1) ? 0.5 * h : h) + ls2;
+        const double lw = lap + logprior + logtrap;
+        double pc[3], pr[3], vd[3];
+        for (int i = 1; i < 4; ++i) {
+            const double du = u[i] - u[0];
+            vd[i - 1] = u[i] + u[0] + gam * du * du;
+            const double zs = (th[i] - th[0]) / sqrt(2.0 * vd[i - 1]);
+            pc[i - 1] = 0.5 * erfc(zs);          // Phi(-z)
+            if (FULL) pr[i - 1] = 0.5 * erfc(-zs);   // Phi(z)
+        }
+        if (lw > wmax) {
+            const double sc = exp(wmax - lw);   // 0 on the first node
+            wsum *= sc;
+            for (int i = 0; i < 3; ++i) accS[i] *= sc;
+            if (FULL) {
+                for (int i = 0; i < 3; ++i) {
+                    accP[i] *= sc;
+                    d2[i] *= sc;
+                }
+                for (int a = 0; a < 4; ++a) {
+                    m1[a] *= sc;
+                    m2[a] *= sc;
+                }
+            }
+            wmax = lw;
+        }
+        const double wj = exp(lw - wmax);
+        wsum += wj;
+        for (int i = 0; i < 3; ++i) accS[i] += wj * pc[i];
+        if (FULL) {
+            for (int i = 0; i < 3; ++i) {
+                accP[i] += wj * pr[i];
+                const double e = (th[i + 1] - th[0]) - (th0[i + 1] - th0[0]);
+                d2[i] += wj * (vd[i] + e * e);
+            }
+            for (int a = 0; a < 4; ++a) {
+                const double e = th[a] - th0[a];
+                m1[a] += wj * e;
+                m2[a] += wj * (u[a] + gam * u[a] * u[a] + e * e);   // C_aa + (mode - ref)^2
+            }
+        }
+    }
+    for (int i = 0; i < 3; ++i) out.Sc[i] = accS[i] / wsum;
+    if (FULL) {
+        for (int i = 0; i < 3; ++i) out.P[i] = accP[i] / wsum;
+        double em[4];
+        for (int a = 0; a < 4; ++a) {
+            em[a] = m1[a] / wsum;                       // mean - reference
+            out.mean[a] = th0[a] + em[a];
+            out.var[a] = m2[a] / wsum - em[a] * em[a];
+        }
+        for (int i = 0; i < 3; ++i) {
+            const double ed = em[i + 1] - em[0];
+            out.dvar[i] = d2[i] / wsum - ed * ed;
+        }
+    }
+}
+
+}  // namespace cse

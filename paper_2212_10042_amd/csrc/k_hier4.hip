@@ -2,34 +2,18 @@
 // basket case study (Section 10.1): theta_i | mu, s2 ~ N(mu, s2), mu ~ N(-1.34, 100),
 // s2 ~ InvGamma(0.0005, 0.000005); statistic of treatment arm i: P(p_i > p_0 | y).
 //
-// Posterior table (one thread per outcome y in {0..n}^4), float64:
-//   * mu integrated out: theta | s2 ~ N(m0 1, Sigma), Sigma = s2 I + 100 11^T, whose precision is
-//     Q = (I - c 11^T) / s2 with c = 100 / (s2 + 400) (Sherman-Morrison);
-//   * per node s2_j (90 nodes equally spaced in log s2 on [log 1e-6, log 1e3]): Newton's method
-//     for the mode of  sum_a [y_a theta_a - n softplus(theta_a)] - (theta - m0)^T Q (theta - m0) / 2.
-//     The negative Hessian is D - beta 11^T with D_a = n p_a (1 - p_a) + 1/s2, beta = c / s2, so each
-//     step, its determinant and the covariance C = (D - beta 11^T)^{-1} = D^{-1} + g u u^T
-//     (u = D^{-1} 1, g = beta / (1 - beta sum u)) cost O(arms);
-//   * node log weight: Laplace evidence  l(mode) + log|Q|/2 - log|D - beta 11^T|/2, plus the
-//     log inverse-gamma density of s2_j, plus log of the trapezoid weight in log s2 (ds2 = s2 dlog s2);
-//   * P_i = sum_j pi_j Phi((mode_i - mode_0) / sqrt(C_ii + C_00 - 2 C_i0)), pi = softmax of the
-//     log weights (log-sum-exp in float64); the statistic 1 - P_i is summed directly as
-//     sum_j pi_j Phi(-z_j), keeping relative precision where P_i is near 1.
+// Posterior table (one thread per outcome y in {0..n}^4), float64, by the Laplace node mixture
+// of hier_post.hpp; the statistic 1 - P_i is summed directly as sum_j pi_j Phi(-z_j).
 // The table holds float32 (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome, index ((y0 m + y1) m + y2) m + y3.
 #include <math.h>
 
 #include "cse_internal.h"
 #include "fp64_math.hpp"
+#include "hier_post.hpp"
 #include "kernels.h"
 #include "philox.hpp"
 
 namespace cse {
-
-constexpr int H4_NODES = 90;
-
-__device__ __forceinline__ double expit_d(double x) {
-    return x >= 0.0 ? 1.0 / (1.0 + exp_cw(-x)) : 1.0 - 1.0 / (1.0 + exp_cw(x));
-}
 
 __global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float4 *__restrict__ tbl) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -43,91 +27,13 @@ __global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float
             v /= m;
         }
     }
-    const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
-    const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
-    const double h = (LS2_HI - LS2_LO) / (H4_NODES - 1);
-    const double lgA = lgamma(IG_A), logB = log(IG_B);
-    double th0[4];
-    for (int a = 0; a < 4; ++a) th0[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
-
-    // running log-sum-exp of the node weights and the weighted probabilities
-    double wmax = -INFINITY, wsum = 0.0, acc[3] = {0.0, 0.0, 0.0};
-    for (int j = 0; j < H4_NODES; ++j) {
-        const double ls2 = LS2_LO + h * j;
-        const double s2 = exp(ls2);
-        const double inv_s2 = 1.0 / s2;
-        const double c = TAU2 / (s2 + 4.0 * TAU2);
-        const double beta = c * inv_s2;
-        double th[4] = {th0[0], th0[1], th0[2], th0[3]};
-        double D[4], u[4], gam = 0.0;
-        for (int it = 0; it < 100; ++it) {
-            double dsum = 0.0;
-            for (int a = 0; a < 4; ++a) dsum += th[a] - M0;
-            double g[4], su = 0.0;
-            for (int a = 0; a < 4; ++a) {
-                const double p = expit_d(th[a]);
-                // Q (theta - m0) = ((theta_a - m0) - c sum_b (theta_b - m0)) / s2
-                g[a] = (double)y[a] - n * p - ((th[a] - M0) - c * dsum) * inv_s2;
-                D[a] = n * p * (1.0 - p) + inv_s2;
-                u[a] = 1.0 / D[a];
-                su += u[a];
-            }
-            gam = beta / (1.0 - beta * su);
-            double ug = 0.0;
-            for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
-            double mx = 0.0;
-            for (int a = 0; a < 4; ++a) {
-                const double step = u[a] * g[a] + gam * u[a] * ug;   // (D - beta 11^T)^{-1} g
-                th[a] += step;
-                mx = fmax(mx, fabs(step));
-            }
-            if (mx < 1e-10) break;
-        }
-        // curvature at the final mode
-        double su = 0.0, logdetD = 0.0;
-        for (int a = 0; a < 4; ++a) {
-            const double p = expit_d(th[a]);
-            D[a] = n * p * (1.0 - p) + inv_s2;
-            u[a] = 1.0 / D[a];
-            su += u[a];
-            logdetD += log(D[a]);
-        }
-        gam = beta / (1.0 - beta * su);
-        const double logdet_negH = logdetD + log1p(-beta * su);
-        const double logdetQ = -(3.0 * ls2 + log(s2 + 4.0 * TAU2));
-        double ll = 0.0, dsum = 0.0, sq = 0.0;
-        for (int a = 0; a < 4; ++a) {
-            ll += y[a] * th[a] - n * softplus_fast(th[a]);
-            const double e = th[a] - M0;
-            dsum += e;
-            sq += e * e;
-        }
-        const double quad = (sq - c * dsum * dsum) * inv_s2;
-        const double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet_negH;
-        const double logprior = IG_A * logB - lgA - (IG_A + 1.0) * ls2 - IG_B * inv_s2;
-        const double logtrap = log((j == 0 || j == H4_NODES - 1) ? 0.5 * h : h) + ls2;
-        const double lw = lap + logprior + logtrap;
-        double pr[3];
-        for (int i = 1; i < 4; ++i) {
-            const double du = u[i] - u[0];
-            const double var = u[i] + u[0] + gam * du * du;
-            // 1 - Phi(z) = Phi(-z): the statistic 1 - P_i is summed directly (relative precision)
-            pr[i - 1] = 0.5 * erfc((th[i] - th[0]) / sqrt(2.0 * var));
-        }
-        if (lw > wmax) {
-            const double sc = exp(wmax - lw);   // 0 on the first node
-            wsum *= sc;
-            for (int i = 0; i < 3; ++i) acc[i] *= sc;
-            wmax = lw;
-        }
-        const double wj = exp(lw - wmax);
-        wsum += wj;
-        for (int i = 0; i < 3; ++i) acc[i] += wj * pr[i];
-    }
+    const double nv[4] = {(double)n, (double)n, (double)n, (double)n};
+    HierSummary s;
+    hier_posterior<false, false>(y, nv, s);
     float4 o;
-    o.x = (float)(acc[0] / wsum);
-    o.y = (float)(acc[1] / wsum);
-    o.z = (float)(acc[2] / wsum);
+    o.x = (float)s.Sc[0];
+    o.y = (float)s.Sc[1];
+    o.z = (float)s.Sc[2];
     o.w = 0.0f;
     tbl[idx] = o;
 }

@@ -1,0 +1,277 @@
+// k_phase23.hip -- the Phase II/III Bayesian selection design (Section 10.2 and the design
+// appendix), one simulated trial per lane, decisions from the hierarchical posterior of
+// hier_post.hpp (float64) at every look.
+//
+// Protocol (the reading of the appendix):
+//   Phase II: 50 patients per arm; looks after 200, 300 and 400 randomised patients.  At each
+//   look, for every active treatment arm i: p_best_i = P(theta_i is the largest of the four)
+//   under independent normal marginals moment-matched to the posterior mixture (16-point
+//   Gauss-Hermite), and p_succ_i = probability under a Gaussian predictive that adding 200
+//   patients to arm i and to control gives P(theta_i > theta_0) > 0.95 at the end.  If some
+//   active arm has p_succ > 0.70 (0.60 at the third look) the one with the largest p_best among
+//   them is selected (ties: lowest index); otherwise, at looks 1-2, arms with p_best < 0.15 are
+//   dropped (futility when none remains) and the next 100 patients are split evenly over the
+//   remaining arms and control, the remainder discarded; at look 3 the trial stops.
+//   Phase III: 100 + 100 on the selected arm s and control, interim: success if
+//   P(theta_s > theta_0) > 0.95, futility if p_succ_s (100 added) < 0.20; else 100 + 100 more and
+//   the final analysis.
+//   Embedding (Section 8): patient j of arm a draws word a * 350 + j of the simulation's stream.
+//   Statistic of a tile with null configuration b: -inf for an early success with s in b,
+//   1 - P_final(theta_s > theta_0) for a final analysis with s in b, +inf otherwise; the
+//   design's rule at lambda rejects (falsely) when S < lambda.
+//
+// Scheduling: a persistent grid; each wave pops items (tile, simulation range) from a global
+// queue.  Every lane runs its own trial as a state machine, one posterior per step, and takes
+// the next simulation (from the wave's current item, or the next item) as soon as its trial
+// ends, so lanes whose trials stop early do not wait for long ones.  Per trial: the key S is
+// stored, and a rejection at the fixed lambda adds to the tile's R and to its sums of the
+// observed counts and sample sizes (integer atomics: exact, order-independent).
+#include <math.h>
+
+#include "cse_internal.h"
+#include "hier_post.hpp"
+#include "kernels.h"
+#include "philox.hpp"
+
+namespace cse {
+
+namespace {
+
+constexpr int P23_NMAX = 350;   // embedded patients per arm
+
+// Add m patients to arm a (patients n .. n+m-1): count responses among their words.
+__device__ __forceinline__ void p23_draw(int a, int m, uint32_t T, uint32_t k, uint32_t key0,
+                                         uint32_t key1, int &n, int &y) {
+    if (m <= 0) return;
+    const uint32_t w0 = (uint32_t)(a * P23_NMAX + n), w1 = w0 + (uint32_t)m;   // [w0, w1)
+    int cnt = 0;
+    for (uint32_t b = w0 >> 2; b <= (w1 - 1) >> 2; ++b) {
+        const u32x4 w = philox_block(b, k, key0, key1);
+        const uint32_t base = b << 2;
+        cnt += (base + 0 >= w0 && base + 0 < w1 && w.x < T) ? 1 : 0;
+        cnt += (base + 1 >= w0 && base + 1 < w1 && w.y < T) ? 1 : 0;
+        cnt += (base + 2 >= w0 && base + 2 < w1 && w.z < T) ? 1 : 0;
+        cnt += (base + 3 >= w0 && base + 3 < w1 && w.w < T) ? 1 : 0;
+    }
+    n += m;
+    y += cnt;
+}
+
+__device__ __forceinline__ double p23_Phi(double z) { return 0.5 * erfc(-z / sqrt(2.0)); }
+
+// p_succ for d ~ N(md, vd), control / arm posterior means m0, mi, m_add patients per arm.
+__device__ __forceinline__ double p23_psucc(double md, double vd, double m0, double mi, double m_add,
+                                            double z95) {
+    const double p0 = hp_expit(m0), pi = hp_expit(mi);
+    const double V = 1.0 / (m_add * pi * (1.0 - pi)) + 1.0 / (m_add * p0 * (1.0 - p0));
+    const double vf = vd * V / (vd + V);
+    const double sd_mean = vd / sqrt(vd + V);
+    return p23_Phi((md - z95 * sqrt(vf)) / sd_mean);
+}
+
+// v[i] for a run-time i in 0..3 without dynamic register indexing.
+template <class T>
+__device__ __forceinline__ T pick4(const T (&v)[4], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : (i == 2 ? v[2] : v[3]));
+}
+template <class T>
+__device__ __forceinline__ T pick3(const T (&v)[3], int i) {
+    return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
+}
+
+}  // namespace
+
+// Two waves per SIMD: the float64 posterior keeps about 250 registers live.
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_phase23(P23Args A) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (WAVE - lane));
+    // wave-uniform current item
+    int32_t it_tile = -1;
+    uint32_t it_k = 0, it_end = 0;
+    bool queue_open = true;
+
+    // lane state: busy = a trial in progress; add[a] = patients to enrol on arm a before the
+    // next look; look 0..2 Phase II, 3 Phase III interim, 4 final analysis
+    bool busy = false;
+    int32_t tile = 0;
+    uint32_t k = 0, T[4] = {0u, 0u, 0u, 0u};
+    int cfg = 0, look = 0, sel = 0, active = 0;
+    int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, add[4] = {0, 0, 0, 0};
+
+    for (;;) {
+        // ---- give idle lanes the next simulations of the wave's item stream ----
+        unsigned long long need = __ballot(!busy);
+        while (need) {
+            if (it_k >= it_end) {
+                if (!queue_open) break;
+                uint32_t idx = 0;
+                if (lane == 0) idx = atomicAdd(A.counter, 1u);
+                idx = __builtin_amdgcn_readfirstlane(idx);
+                if ((int64_t)idx >= A.n_items) {
+                    queue_open = false;
+                    break;
+                }
+                const WorkItem W = A.items[idx];
+                it_tile = W.blk;
+                it_k = W.k_begin;
+                it_end = W.k_end;
+                continue;
+            }
+            const uint32_t avail = it_end - it_k;
+            const uint32_t rank = (uint32_t)__popcll(need & below);
+            if (((need >> lane) & 1ull) && rank < avail) {
+                busy = true;
+                tile = it_tile;
+                k = it_k + rank;
+                for (int a = 0; a < 4; ++a) {
+                    T[a] = A.tileT[(int64_t)tile * 4 + a];
+                    n[a] = 0;
+                    y[a] = 0;
+                    add[a] = 50;   // Phase II opens with 50 patients per arm
+                }
+                cfg = A.cfg[tile];
+                look = 0;
+                sel = 0;
+                active = 7;
+            }
+            const uint32_t asked = (uint32_t)__popcll(need);
+            it_k += asked < avail ? asked : avail;
+            need = __ballot(!busy);
+        }
+        if (!__ballot(busy)) break;   // queue drained and every trial finished
+        if (busy) {
+
+            // ---- enrol, then one look ----
+#pragma unroll
+            for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
+            HierSummary s;
+            {
+                const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
+                hier_posterior<true, true>(y, nd, s);
+            }
+            float S = INFINITY;
+            bool done = false;
+            if (look < 3) {
+                // Phase II look: p_best of the treatment arms, p_succ of the active ones
+                double pb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 1; i < 4; ++i) {
+                    const double si = sqrt(2.0 * s.var[i]);
+                    double acc = 0.0;
+                    for (int g = 0; g < 16; ++g) {
+                        const double t = s.mean[i] + si * A.gh[g];
+                        double prod = 1.0;
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk)
+                            if (kk != i) prod *= p23_Phi((t - s.mean[kk]) / sqrt(s.var[kk]));
+                        acc += A.gh[16 + g] * prod;
+                    }
+                    pb[i] = acc / A.sqrt_pi;
+                }
+                const double thr = (look < 2) ? 0.70 : 0.60;
+                int best = 0;
+                double pb_best = 0.0;
+#pragma unroll
+                for (int i = 1; i < 4; ++i) {
+                    if (!((active >> (i - 1)) & 1)) continue;
+                    const double ps = p23_psucc(s.mean[i] - s.mean[0], s.dvar[i - 1], s.mean[0], s.mean[i], 200.0,
+                                                A.z95);
+                    if (ps > thr && (best == 0 || pb[i] > pb_best)) {
+                        best = i;
+                        pb_best = pb[i];
+                    }
+                }
+                if (best) {
+                    sel = best;
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == best) ? 100 : 0;
+                    look = 3;
+                } else if (look == 2) {
+                    done = true;
+                } else {
+                    int r = 0;
+#pragma unroll
+                    for (int i = 1; i < 4; ++i) {
+                        if (((active >> (i - 1)) & 1) && pb[i] < 0.15) active &= ~(1 << (i - 1));
+                        r += (active >> (i - 1)) & 1;
+                    }
+                    if (r == 0) {
+                        done = true;
+                    } else {
+                        const int per = 100 / (r + 1);
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) add[a] = (a == 0 || ((active >> (a - 1)) & 1)) ? per : 0;
+                        look += 1;
+                    }
+                }
+            } else {
+                const bool in_b = (cfg >> (sel - 1)) & 1;
+                if (look == 3) {
+                    // Phase III interim
+                    const double ms = pick4(s.mean, sel);
+                    if (pick3(s.P, sel - 1) > 0.95) {
+                        S = in_b ? -INFINITY : INFINITY;
+                        done = true;
+                    } else if (p23_psucc(ms - s.mean[0], pick3(s.dvar, sel - 1), s.mean[0], ms, 100.0, A.z95) < 0.20) {
+                        done = true;
+                    } else {
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == sel) ? 100 : 0;
+                        look = 4;
+                    }
+                } else {
+                    // final analysis
+                    S = in_b ? (float)pick3(s.Sc, sel - 1) : INFINITY;
+                    done = true;
+                }
+            }
+            if (done) {
+                if (A.keys) A.keys[A.key_off[tile] + k] = S;
+                if (S < A.cut) {
+                    atomicAdd(&A.R[tile], 1u);
+                    if (A.sumT)
+#pragma unroll
+                        for (int a = 0; a < 4; ++a) {
+                            atomicAdd(&A.sumT[(int64_t)tile * 8 + a], (unsigned long long)y[a]);
+                            atomicAdd(&A.sumT[(int64_t)tile * 8 + 4 + a], (unsigned long long)n[a]);
+                        }
+                }
+                busy = false;
+            }
+        }
+    }
+}
+
+hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
+                          hipStream_t st) {
+    hipError_t e = launch_zero(P.d_queue, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    P23Args A = P.p23;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.R = R;
+    A.sumT = sumT;
+    A.keys = keys;
+    hipLaunchKernelGGL(k_phase23, dim3((uint32_t)P.p23_grid), dim3(WG), 0, st, A);
+    return hipGetLastError();
+}
+
+// The plain path: one launch per tile over that tile's own queue items (no other tiles share
+// the grid); counts only.
+hipError_t launch_phase23_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st) {
+    hipError_t e = launch_zero(P.d_queue, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    P23Args A = P.p23;
+    const int64_t i0 = P.p23_item_off[t], i1 = P.p23_item_off[t + 1];
+    A.items = P.d_p23items + i0;
+    A.n_items = i1 - i0;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.R = R_tile - t;   // the kernel indexes R by tile id
+    A.sumT = nullptr;
+    A.keys = nullptr;
+    hipLaunchKernelGGL(k_phase23, dim3((uint32_t)((A.n_items + 3) / 4)), dim3(WG), 0, st, A);
+    return hipGetLastError();
+}
+
+}  // namespace cse

@@ -201,7 +201,7 @@ __global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, int6
 
 // Score-function gradient (sum over rejections of T(x) - R grad A(theta)) / N, float64;
 // also the float64 score sums and int32 counts for the caller's buffers.
-__global__ void k_finish(int fam, int n, int d, int64_t n_tiles, const double *__restrict__ theta,
+__global__ void k_finish(int fam, int n, int d, int score_n, int64_t n_tiles, const double *__restrict__ theta,
                          const int32_t *__restrict__ N, const uint32_t *__restrict__ R,
                          const unsigned long long *__restrict__ sumT,
                          const unsigned long long *__restrict__ sumZfx, int32_t *__restrict__ R_out,
@@ -216,6 +216,21 @@ __global__ void k_finish(int fam, int n, int d, int64_t n_tiles, const double *_
         const double z = (double)(long long)sumZfx[t] * (1.0 / 4294967296.0);
         if (Z_out) Z_out[t] = z;
         if (grad) grad[t] = z * inv;
+        return;
+    }
+    if (score_n) {
+        // observed sample sizes: sumT[t] = (sum y_a over a, then sum n_a over a)
+        for (int a = 0; a < d; ++a) {
+            const unsigned long long sy = sumT[t * 2 * d + a], sn = sumT[t * 2 * d + d + a];
+            if (T_out) {
+                T_out[t * 2 * d + a] = (int64_t)sy;
+                T_out[t * 2 * d + d + a] = (int64_t)sn;
+            }
+            if (grad) {
+                const double p = 1.0 / (1.0 + exp(-theta[t * d + a]));
+                grad[t * d + a] = ((double)sy - (double)sn * p) * inv;
+            }
+        }
         return;
     }
     for (int a = 0; a < d; ++a) {
@@ -245,7 +260,7 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st) {
-    if (P.design.kind == CSE_ZTEST1 || P.design.kind == CSE_HIER4)
+    if (P.design.kind != CSE_BINOM2_Z)
         hipLaunchKernelGGL(k_select_f32, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
                            (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else
@@ -266,7 +281,7 @@ hipError_t launch_finish(const Platten &P, const uint32_t *R, const unsigned lon
                          double *Z_out, double *grad, hipStream_t st) {
     const int64_t grid = (P.n_tiles + 255) / 256;
     hipLaunchKernelGGL(k_finish, dim3((uint32_t)grid), dim3(256), 0, st, P.family, P.n_per_arm, P.d,
-                       P.n_tiles, P.d_theta, P.d_N, R, sumT, sumZfx, R_out, T_out, Z_out, grad);
+                       P.design.kind == CSE_PHASE23 ? 1 : 0, P.n_tiles, P.d_theta, P.d_N, R, sumT, sumZfx, R_out, T_out, Z_out, grad);
     return hipGetLastError();
 }
 

@@ -109,6 +109,62 @@ std::vector<std::vector<double>> enumerate_vertices(int d, const std::vector<Hal
     return V;
 }
 
+// 16-point Gauss-Hermite rule (weight e^{-x^2}): the nodes are the zeros of H_16, found by
+// Newton's method on the orthonormal Hermite functions h_k (h_0 = pi^{-1/4},
+// h_{k+1} = x sqrt(2/(k+1)) h_k - sqrt(k/(k+1)) h_{k-1}, h_16' = sqrt(32) h_15) from starting
+// points bracketed by sign changes on a grid; weight 1 / (16 h_15(x)^2).
+void gauss_hermite16(double *x, double *w) {
+    const int n = 16;
+    auto eval = [&](double t, double &hn, double &hn1) {
+        double a = pow(M_PI, -0.25), b = sqrt(2.0) * t * a;
+        for (int k = 1; k < n; ++k) {
+            const double c = t * sqrt(2.0 / (k + 1)) * b - sqrt((double)k / (k + 1)) * a;
+            a = b;
+            b = c;
+        }
+        hn = b;
+        hn1 = a;
+    };
+    int found = 0;
+    double prev = -7.0, fp, dummy;
+    eval(prev, fp, dummy);
+    for (int g = 1; g <= 1400 && found < n; ++g) {
+        const double t = -7.0 + 0.01 * g;
+        double ft;
+        eval(t, ft, dummy);
+        if ((fp < 0.0) != (ft < 0.0)) {
+            double r = 0.5 * (prev + t);
+            for (int it = 0; it < 50; ++it) {
+                double hn, hn1;
+                eval(r, hn, hn1);
+                const double step = hn / (sqrt(2.0 * n) * hn1);
+                r -= step;
+                if (fabs(step) < 1e-16 * (1.0 + fabs(r))) break;
+            }
+            double hn, hn1;
+            eval(r, hn, hn1);
+            x[found] = r;
+            w[found] = 1.0 / (n * hn1 * hn1);
+            ++found;
+        }
+        prev = t;
+        fp = ft;
+    }
+}
+
+// Phi^{-1}(0.95) by Newton's method on Phi(z) = erfc(-z / sqrt 2) / 2.
+double normal_q95() {
+    double z = 1.6;
+    for (int it = 0; it < 50; ++it) {
+        const double f = 0.5 * erfc(-z / sqrt(2.0)) - 0.95;
+        const double dens = exp(-0.5 * z * z) / sqrt(2.0 * M_PI);
+        const double step = f / dens;
+        z -= step;
+        if (fabs(step) < 1e-16) break;
+    }
+    return z;
+}
+
 template <class T>
 int upload(T **dst, const T *src, size_t n) {
     if (n == 0) {
@@ -142,7 +198,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         d = 2;
         p = 1;
         P->family = FAM_BINOM;
-    } else if (kind == CSE_HIER4) {
+    } else if (kind == CSE_HIER4 || kind == CSE_PHASE23) {
         d = 4;
         p = 3;
         P->family = FAM_BINOM;
@@ -154,7 +210,11 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         set_error("cse_platten_create: design.n_arms does not match the design kind");
         return CSE_EINVAL;
     }
-    if (P->family == FAM_BINOM && design->n_per_arm != NP35) {
+    if (kind == CSE_PHASE23 && design->n_per_arm != P23_NMAX_ARM) {
+        set_error("cse_platten_create: the Phase II/III design embeds n_per_arm = 350 patients per arm");
+        return CSE_EUNSUPPORTED;
+    }
+    if (kind != CSE_PHASE23 && P->family == FAM_BINOM && design->n_per_arm != NP35) {
         set_error("cse_platten_create: binomial designs are built for n_per_arm = 35");
         return CSE_EUNSUPPORTED;
     }
@@ -430,6 +490,45 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, nullptr));
         CSE_HIP_TRY(hipDeviceSynchronize());
         P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    } else if (kind == CSE_PHASE23) {
+        // one trial per lane: keys contiguous per tile, work items of p23_chunk simulations
+        for (int64_t t = 0; t < P->n_tiles; ++t) {
+            key_off[t] = P->n_keys;
+            key_stride[t] = 64;   // contiguous: chunk c of 64 keys starts at 64 c
+            P->n_keys += P->tile_N[t];
+        }
+        P->p23_chunk = 256;
+        std::vector<WorkItem> items;
+        for (int64_t t = 0; t < P->n_tiles; ++t) {
+            P->p23_item_off.push_back((int64_t)items.size());
+            for (int64_t k0 = 0; k0 < P->tile_N[t]; k0 += P->p23_chunk) {
+                WorkItem w{};
+                w.blk = (int32_t)t;
+                w.k_begin = (uint32_t)k0;
+                w.k_end = (uint32_t)std::min<int64_t>(P->tile_N[t], k0 + P->p23_chunk);
+                items.push_back(w);
+            }
+        }
+        P->p23_item_off.push_back((int64_t)items.size());
+        if (int e = upload(&P->d_p23items, items.data(), items.size())) return e;
+        if (int e = upload(&P->d_tileT, P->tile_T.data(), P->tile_T.size())) return e;
+        if (int e = upload(&P->d_cfg, P->tile_cfg.data(), P->tile_cfg.size())) return e;
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_queue, sizeof(uint32_t)));
+        P23Args &A = P->p23;
+        A.items = P->d_p23items;
+        A.n_items = (int64_t)items.size();
+        A.counter = P->d_queue;
+        A.tileT = P->d_tileT;
+        A.cfg = P->d_cfg;
+        A.cut = (float)design->cut;
+        double gh[32];
+        gauss_hermite16(gh, gh + 16);
+        if (int e = upload(&P->d_gh, gh, 32)) return e;
+        A.gh = P->d_gh;
+        A.sqrt_pi = sqrt(M_PI);
+        A.z95 = normal_q95();
+        // persistent grid: enough workgroups of 4 waves to fill the chip, no more than the items
+        P->p23_grid = std::max<int64_t>(1, std::min<int64_t>((A.n_items + 3) / 4, 2048));
     } else {
         // distinct arm values -> integer coordinates; 8 x 8 coordinate blocks per N class
         std::vector<double> u0, u1;
@@ -521,7 +620,8 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         }
 
     // ---- work items: split each block's simulations so the grid has enough waves ----
-    {
+    // (the Phase II/III design has no blocks: its queue items were made above)
+    if (P->n_blocks > 0) {
         const int64_t target = 16384;   // waves: several per SIMD on 256 CUs x 4 SIMDs
         std::vector<WorkItem> items;
         int64_t slices = std::max<int64_t>(1, (target + P->n_blocks - 1) / P->n_blocks);
@@ -578,6 +678,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     if (int e = upload(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size())) return e;
     if (int e = upload(&P->d_key_off, key_off.data(), key_off.size())) return e;
     if (int e = upload(&P->d_key_stride, key_stride.data(), key_stride.size())) return e;
+    if (kind == CSE_PHASE23) P->p23.key_off = P->d_key_off;
     // N classes for the Clopper-Pearson table
     {
         std::vector<int32_t> cls(P->tile_N.begin(), P->tile_N.end());
@@ -602,7 +703,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     }
     const size_t nt = (size_t)P->n_tiles;
     CSE_HIP_TRY(hipMalloc((void **)&P->d_Rw, nt * sizeof(uint32_t)));
-    CSE_HIP_TRY(hipMalloc((void **)&P->d_Tw, nt * d * sizeof(unsigned long long)));
+    // score sums: sum of T per arm; the Phase II/III design also sums the observed n per arm
+    const size_t tw = (kind == CSE_PHASE23) ? 2 * (size_t)d : (size_t)d;
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_Tw, nt * tw * sizeof(unsigned long long)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_Zw, nt * sizeof(unsigned long long)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_apw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
@@ -619,7 +722,8 @@ void free_platten(Platten *P) {
                     P->d_S_group, P->d_keys, P->d_Rw,      P->d_Tw,     P->d_Zw,
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
-                    P->d_is_box, P->d_key_stride, P->d_h4tbl};
+                    P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
+                    P->d_queue,  P->d_p23items, P->d_gh};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }

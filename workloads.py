@@ -72,6 +72,22 @@ def hier4_grid(m: int = 16, sims: int = 32_768, lo: float = -1.0, hi: float = 1.
                 delta=0.01, alpha=0.025)
 
 
+def phase23_grid(shape=(4, 4, 4, 4), sims=None, lo: float = -0.9946, hi: float = 1.1527,
+                 seed: int = 0, sims_seed: int = 0, lam: float = 0.06253) -> dict:
+    """4-arm grid for the Phase II/III design: shape[a] equal boxes per arm on [lo, hi] (the
+    logit box of p in [27%, 76%], Section 10.2), arm 0 first (row-major).  sims: an int for
+    equal counts, or None for the uneven 2^(11+g), g uniform on {0..5} (PCG64(sims_seed))."""
+    cs = [_centres(lo, hi, m) for m in shape]
+    rs = [(hi - lo) / (2 * m) for m in shape]
+    g = np.stack(np.meshgrid(*cs, indexing="ij"), axis=-1).reshape(-1, 4)
+    n = g.shape[0]
+    radii = np.tile(np.array(rs), (n, 1))
+    sm = np.full(n, sims, np.int32) if sims is not None else uneven_sims(n, sims_seed)
+    tag = "x".join(str(m) for m in shape)
+    return dict(name=f"phase23_{tag}x{'uneven' if sims is None else sims}", design="phase23",
+                theta=g.copy(), radii=radii, sims=sm, seed=seed, delta=0.01, alpha=0.025, cut=lam)
+
+
 def uneven_sims(n_tiles: int, seed: int = 0, lo_pow: int = 11, n_classes: int = 6) -> np.ndarray:
     """Simulations per tile 2^(lo_pow+g), g uniform on {0..n_classes-1} (PCG64 seeded)."""
     g = np.random.Generator(np.random.PCG64(seed)).integers(0, n_classes, n_tiles)
@@ -108,3 +124,9 @@ def binom2_1024_full() -> dict:
 def hier4_16() -> dict:
     """4-arm n=35 hierarchical design, 16^4 boxes on [-1,1]^4, 32,768 sims."""
     return hier4_grid(16, 32_768)
+
+
+def phase23_c5() -> dict:
+    """Phase II/III design, 16 x 16 x 32 x 32 boxes (2^18) on the logit box [-0.9946, 1.1527]^4,
+    2^(11+g) sims per box with g uniform on {0..5} (PCG64(0)), seed 0, lambda 0.06253."""
+    return phase23_grid((16, 16, 32, 32), None)
