@@ -42,6 +42,13 @@ B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 
 #   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store.
 H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
 
+#   Phase II/III: float64 lane-ops of one posterior look (hier_post.hpp), counted by operation
+#   (exp 22, log 30, erfc 50, division 10, sqrt 10, log1p series 25): per node 1,186 outside
+#   Newton, 261 per Newton step; per look p_best 10,700 + p_success 500 (counted at every look,
+#   which overstates Phase III looks by under 10%).  Looks and Newton steps are the kernel's
+#   own counters for the launch (cse_work_counters).
+P23_NODE, P23_NEWTON, P23_LOOK_EXTRA = 1186, 261, 11200
+
 WORKLOADS = {
     "binom2_256_tri": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
                       "(32,896 tiles), 8,192 sims/tile, seed 0, alpha 0.025, delta 0.01; "
@@ -54,6 +61,12 @@ WORKLOADS = {
                 "step = calibrate + validate",
     "ztest1d_64": "1-D z-test, 64 tiles on [-1,0], 10,000 sims/tile, seed 0, alpha 0.025, delta 0.01; "
                   "step = calibrate + validate + gradient",
+    "phase23_c5": "Phase II/III selection design (350/arm embedding, hierarchical posterior at every look), "
+                  "16x16x32x32 boxes on logit [-0.9946,1.1527]^4 clipped to the null configurations, "
+                  "2^(11+g) sims per box (g uniform on 0..5, PCG64(0)), seed 0, lambda 0.06253, alpha 0.025, "
+                  "delta 0.01; step = calibrate + validate + gradient",
+    "phase23_c5_sub256": "the Phase II/III workload restricted to every 256th box (1,024 boxes), same sims "
+                         "per box; step = calibrate + validate + gradient",
 }
 
 
@@ -68,25 +81,28 @@ def cpu_baseline(name, w, design, target_s: float = 15.0):
     rng = np.random.default_rng(1234)
     n = w["theta"].shape[0]
     keep_all = name == "binom2_1024_full"
-    cut = 0.05 if design == "hier4" else 1.96
+    cut = w.get("cut", 0.05 if design == "hier4" else 1.96)
 
     def run(m):
         idx = np.sort(rng.choice(n, m, replace=False))
         s = W.subsample(w, idx)
+        if design == "phase23":
+            s["sims"] = np.minimum(s["sims"], 256).astype(np.int32)   # ~0.6 ms per oracle trial
         t = time.perf_counter()
         v = O.validate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["delta"], cut=cut,
                        keep_all=keep_all)
         if not keep_all:
             O.calibrate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"], cut=cut,
-                        key_dtype=np.float32 if design == "hier4" else np.float64)
+                        key_dtype=np.float32 if design in ("hier4", "phase23") else np.float64)
         return time.perf_counter() - t, int(np.asarray(s["sims"])[v["box"]].sum()), len(v["box"])
 
     dt, st, nt = run(4)
     m = int(min(n, max(4, 4 * target_s / max(dt, 1e-3))))
     dt, st, nt = run(m)
+    sims_note = "min(N, 256) sims of each" if design == "phase23" else "all sims of each"
     return {"value": st / dt, "unit": "sim·tiles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} boxes ({nt} tiles) drawn uniformly (seed 1234) of the same workload, all sims "
-                      f"of each; oracle {'validate' if keep_all else 'validate + calibrate'}, "
+            "sample": f"{m} boxes ({nt} tiles) drawn uniformly (seed 1234) of the same workload, {sims_note}; "
+                      f"oracle {'validate' if keep_all else 'validate + calibrate'}, "
                       f"{dt:.1f} s single-threaded"}
 
 
@@ -122,13 +138,17 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
         return
     name = args.workload
-    w = getattr(W, name)()
+    if name == "phase23_c5_sub256":
+        w5 = W.phase23_c5()
+        w = W.subsample(w5, np.arange(0, w5["theta"].shape[0], 256))
+    else:
+        w = getattr(W, name)()
     design = {"binom2_256_tri": "binom2", "binom2_1024_full": "binom2", "hier4_16": "hier4",
-              "ztest1d_64": "ztest1"}[name]
+              "ztest1d_64": "ztest1", "phase23_c5": "phase23", "phase23_c5_sub256": "phase23"}[name]
     keep_all = name == "binom2_1024_full"
     calibrating = not keep_all
     t0 = time.perf_counter()
-    P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all)
+    P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all, cut=w.get("cut"))
     platten_ms = (time.perf_counter() - t0) * 1e3
     st = cse.cse_platten_stats(P.handle)
     n, d = P.n_tiles, P.d
@@ -165,7 +185,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     cse.cse_profile_enable(False)
-    sim_kernel = {"binom2": "binom2", "hier4": "hier4", "ztest1": "ztest1"}[design] + ("_calib" if calibrating else "")
+    sim_kernel = {"binom2": "binom2", "hier4": "hier4", "ztest1": "ztest1", "phase23": "phase23"}[design] + \
+        ("_calib" if calibrating else "")
     kern = {}
     for kn in (sim_kernel, "select", "bound_invert", "bound_validate"):
         cnt, ms = cse.cse_profile_get(kn)
@@ -186,6 +207,10 @@ def main():
         ops = (st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + box_sims * H4_BOX
                + st["total_sims"] * H4_TILE)
         kname = "k_hier4<KEYS=true>"
+    elif design == "phase23":
+        wc = cse.cse_work_counters(P.handle)
+        ops = (wc["looks"] * (90 * P23_NODE + P23_LOOK_EXTRA) + wc["newton_steps"] * P23_NEWTON)
+        kname = "k_phase23"
     else:
         ops = None
         kname = "k_ztest1<KEYS=true>"
@@ -194,8 +219,11 @@ def main():
     if ops is not None and k_s > 0:
         achieved = ops / k_s
         roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK / 1e12,
-                "unit": "Tops/s (int32 VALU)", "frac": achieved / VALU_PEAK, "traffic": None,
+                "unit": "Tops/s (float64 VALU)" if design == "phase23" else "Tops/s (int32 VALU)",
+                "frac": achieved / VALU_PEAK, "traffic": None,
                 "kernel": kname, "kernel_ms": kern[sim_kernel], "ops_per_launch": ops}
+        if design == "phase23":
+            roof["work"] = wc
 
     # the plain forward-only per-tile path, same tiles, seed and N: identical counts (equal bound)
     plain = None

@@ -201,6 +201,15 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
                           int64_t tile_end, int32_t *reject, void *stream);
 
 /*
+ * cse_work_counters -- work done by the last simulation launch on a CSE_PHASE23 platten
+ * (cse_simulate / cse_validate / cse_calibrate): out (host int64 [3]) = trials simulated,
+ * posterior evaluations (looks), Newton steps over all nodes of those looks.  Synchronises
+ * `stream`.  Used to state the kernel's arithmetic per launch.
+ * Errors: CSE_EINVAL (NULL out), CSE_EUNSUPPORTED (other designs), CSE_EHIP.
+ */
+int cse_work_counters(const cse_platten *p, int64_t out[3], void *stream);
+
+/*
  * cse_posterior_table -- the design table of a CSE_HIER4 platten: for every outcome
  * y in {0..n}^4 (index ((y0 (n+1) + y1) (n+1) + y2) (n+1) + y3) the float32 values
  * (1 - P(p_1 > p_0 | y), 1 - P(p_2 > p_0 | y), 1 - P(p_3 > p_0 | y), 0) of the hierarchical

@@ -29,7 +29,7 @@ CSE_PLATTEN_KEEP_ALL = 1
 EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
             "cse_simulate", "cse_validate", "cse_calibrate", "cse_bound", "cse_simulate_per_tile",
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
-            "cse_posterior_table", "cse_last_error")
+            "cse_posterior_table", "cse_work_counters", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -63,6 +63,7 @@ def _load():
     L.cse_simulate_per_tile.argtypes = [P, u64, i64, i64, P, P]
     L.cse_platten_stats.argtypes = [P, P]
     L.cse_posterior_table.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
+    L.cse_work_counters.argtypes = [P, P, P]
     L.cse_profile_enable.argtypes = [i32]
     L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.cse_profile_reset.argtypes = []
@@ -172,6 +173,13 @@ def cse_bound(h, mode, R, a, level, out, q_star=None, stream=None):
 def cse_simulate_per_tile(h, seed, tile_begin, tile_end, reject, stream=None):
     _check("cse_simulate_per_tile", _L.cse_simulate_per_tile(h, seed, tile_begin, tile_end, _ptr(reject),
                                                              _stream(stream)))
+
+
+def cse_work_counters(h, stream=None) -> dict:
+    """Phase II/III design: trials, posterior looks and Newton steps of the last simulation."""
+    out = np.zeros(3, np.int64)
+    _check("cse_work_counters", _L.cse_work_counters(h, _ptr(out), _stream(stream)))
+    return dict(trials=int(out[0]), looks=int(out[1]), newton_steps=int(out[2]))
 
 
 def cse_platten_stats(h) -> dict:

@@ -367,6 +367,25 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     return CSE_OK;
 }
 
+int cse_work_counters(const cse_platten *p, int64_t out[3], void *stream) {
+    if (int e = check_handle(p, "cse_work_counters")) return e;
+    const auto &P = p->P;
+    if (!out) {
+        set_error("cse_work_counters: NULL out");
+        return CSE_EINVAL;
+    }
+    if (P.design.kind != CSE_PHASE23) {
+        set_error("cse_work_counters: only the Phase II/III design counts its work");
+        return CSE_EUNSUPPORTED;
+    }
+    unsigned long long h[3] = {0, 0, 0};
+    hipStream_t st = (hipStream_t)stream;
+    CSE_HIP_TRY(hipMemcpyAsync(h, P.d_p23stats, sizeof h, hipMemcpyDeviceToHost, st));
+    CSE_HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < 3; ++i) out[i] = (int64_t)h[i];
+    return CSE_OK;
+}
+
 int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int64_t *n_out,
                         void *stream) {
     if (int e = check_handle(p, "cse_posterior_table")) return e;

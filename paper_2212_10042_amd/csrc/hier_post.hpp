@@ -43,7 +43,8 @@ struct HierSummary {
 // Posterior of counts y[4] out of n[4].  WARM starts each node's Newton iterations at the
 // previous node's mode (the converged mode is the same; only the path differs).
 template <bool FULL, bool WARM>
-__device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], HierSummary &out) {
+__device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], HierSummary &out,
+                                               int *newton_steps = nullptr) {
     const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
     const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
     const double h = (LS2_HI - LS2_LO) / (HP_NODES - 1);
@@ -85,6 +86,7 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
                 th[a] += step;
                 mx = fmax(mx, fabs(step));
             }
+            if (newton_steps) *newton_steps += 1;
             if (mx < 1e-10) break;
         }
         // curvature at the final mode

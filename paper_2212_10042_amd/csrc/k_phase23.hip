@@ -97,6 +97,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     uint32_t k = 0, T[4] = {0u, 0u, 0u, 0u};
     int cfg = 0, look = 0, sel = 0, active = 0;
     int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, add[4] = {0, 0, 0, 0};
+    int c_trials = 0, c_looks = 0, c_newton = 0;   // this lane's work (for the stats counters)
 
     for (;;) {
         // ---- give idle lanes the next simulations of the wave's item stream ----
@@ -147,8 +148,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             HierSummary s;
             {
                 const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
-                hier_posterior<true, true>(y, nd, s);
+                hier_posterior<true, true>(y, nd, s, &c_newton);
             }
+            c_looks += 1;
             float S = INFINITY;
             bool done = false;
             if (look < 3) {
@@ -237,7 +239,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                         }
                 }
                 busy = false;
+                c_trials += 1;
             }
+        }
+    }
+    if (A.stats) {
+        // one atomic per wave: reduce the lane counters across the wave first
+        unsigned long long t = (unsigned long long)c_trials, l = (unsigned long long)c_looks,
+                           w = (unsigned long long)c_newton;
+        for (int off = 32; off >= 1; off >>= 1) {
+            t += __shfl_xor(t, off);
+            l += __shfl_xor(l, off);
+            w += __shfl_xor(w, off);
+        }
+        if (lane == 0) {
+            atomicAdd(&A.stats[0], t);
+            atomicAdd(&A.stats[1], l);
+            atomicAdd(&A.stats[2], w);
         }
     }
 }
@@ -252,6 +270,9 @@ hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned
     A.R = R;
     A.sumT = sumT;
     A.keys = keys;
+    A.stats = P.d_p23stats;
+    e = launch_zero(P.d_p23stats, 3 * sizeof(unsigned long long), st);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_phase23, dim3((uint32_t)P.p23_grid), dim3(WG), 0, st, A);
     return hipGetLastError();
 }
@@ -270,6 +291,7 @@ hipError_t launch_phase23_tile(const Platten &P, uint64_t seed, int64_t t, uint3
     A.R = R_tile - t;   // the kernel indexes R by tile id
     A.sumT = nullptr;
     A.keys = nullptr;
+    A.stats = nullptr;
     hipLaunchKernelGGL(k_phase23, dim3((uint32_t)((A.n_items + 3) / 4)), dim3(WG), 0, st, A);
     return hipGetLastError();
 }

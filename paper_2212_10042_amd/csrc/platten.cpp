@@ -514,6 +514,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         if (int e = upload(&P->d_tileT, P->tile_T.data(), P->tile_T.size())) return e;
         if (int e = upload(&P->d_cfg, P->tile_cfg.data(), P->tile_cfg.size())) return e;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_queue, sizeof(uint32_t)));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_p23stats, 3 * sizeof(unsigned long long)));
         P23Args &A = P->p23;
         A.items = P->d_p23items;
         A.n_items = (int64_t)items.size();
@@ -723,7 +724,7 @@ void free_platten(Platten *P) {
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
-                    P->d_queue,  P->d_p23items, P->d_gh};
+                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
