@@ -43,11 +43,18 @@ B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 
 H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
 
 #   Phase II/III: float64 lane-ops of one posterior look (hier_post.hpp), counted by operation
-#   (exp 22, log 30, erfc 50, division 10, sqrt 10, log1p series 25): per node 1,186 outside
-#   Newton, 261 per Newton step; per look p_best 10,700 + p_success 500 (counted at every look,
-#   which overstates Phase III looks by under 10%).  Looks and Newton steps are the kernel's
-#   own counters for the launch (cse_work_counters).
-P23_NODE, P23_NEWTON, P23_LOOK_EXTRA = 1186, 261, 11200
+#   (exp 22, log 30, erfc 50, division 10, sqrt 10, log1p series 25): per node 826 outside
+#   Newton and the normal tails, 261 per Newton step, 125 per arm whose tails a look needs;
+#   per Phase II look p_best 10,700 + p_success 500 (no tails); per Phase III look the
+#   selected arm's tails and one p_success (500).  The first look of a trial is a table
+#   lookup (no posterior).  Looks and Newton steps are the kernel's own counters for the
+#   launch (cse_work_counters).
+P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 826, 261, 125, 11200, 500
+
+# HBM bytes per dispatch of k_binom2<true> on binom2_256_tri, from the FETCH_SIZE / WRITE_SIZE
+# counter runs in profiles/binom2_256_tri_hbm_counters.md (scaled by a 256 MiB copy).  Valid
+# only while that kernel is unchanged; other workloads report null.
+TRAFFIC_BINOM2_256_TRI = 602_990_414
 
 WORKLOADS = {
     "binom2_256_tri": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
@@ -114,6 +121,8 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="binom2_256_tri")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--progress", action="store_true",
+                    help="synchronise and report on stderr after every step (for steps of a minute or more)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device-to-device 3 times (scales HBM counters)")
     args = ap.parse_args()
@@ -173,15 +182,27 @@ def main():
             cse.cse_validate(P.handle, w["seed"], w["delta"], o["reject"], o["score_T"], o["score_Z"], o["grad"],
                              o["cp"], o["bound"])
 
-    for _ in range(args.warmup):
+    def note(msg):
+        if args.progress:
+            print(f"bench.py: {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
+
+    t_start = time.perf_counter()
+    note(f"platten of {P.n_tiles} tiles built in {platten_ms:.0f} ms")
+    for i in range(args.warmup):
         step()
+        if args.progress:
+            torch.cuda.synchronize()
+        note(f"warmup step {i + 1} done")
     torch.cuda.synchronize()
     cse.cse_profile_reset()
     cse.cse_profile_enable(True)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
         step()
+        if args.progress:
+            torch.cuda.synchronize()
+        note(f"timed step {i + 1} done")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     cse.cse_profile_enable(False)
@@ -209,7 +230,9 @@ def main():
         kname = "k_hier4<KEYS=true>"
     elif design == "phase23":
         wc = cse.cse_work_counters(P.handle)
-        ops = (wc["looks"] * (90 * P23_NODE + P23_LOOK_EXTRA) + wc["newton_steps"] * P23_NEWTON)
+        ops = (wc["looks_phase2"] * (90 * P23_NODE + P23_P2_EXTRA)
+               + wc["looks_phase3"] * (90 * (P23_NODE + P23_TAIL) + P23_P3_EXTRA)
+               + wc["newton_steps"] * P23_NEWTON)
         kname = "k_phase23"
     else:
         ops = None
@@ -224,6 +247,9 @@ def main():
                 "kernel": kname, "kernel_ms": kern[sim_kernel], "ops_per_launch": ops}
         if design == "phase23":
             roof["work"] = wc
+        if name == "binom2_256_tri":
+            roof["traffic"] = TRAFFIC_BINOM2_256_TRI
+            roof["traffic_unit"] = "bytes per launch"
 
     # the plain forward-only per-tile path, same tiles, seed and N: identical counts (equal bound)
     plain = None
@@ -260,8 +286,8 @@ def main():
     }
     if calibrating:
         res["lambda_global"] = float(o["lam_g"].item())
-    if design == "hier4":
-        res["posterior_table_build_ms"] = st["table_build_us"] / 1e3
+    if design in ("hier4", "phase23"):
+        res["design_table_build_ms"] = st["table_build_us"] / 1e3
     print(json.dumps(res), flush=True)
     P.close()
 

@@ -202,12 +202,13 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
 
 /*
  * cse_work_counters -- work done by the last simulation launch on a CSE_PHASE23 platten
- * (cse_simulate / cse_validate / cse_calibrate): out (host int64 [3]) = trials simulated,
- * posterior evaluations (looks), Newton steps over all nodes of those looks.  Synchronises
- * `stream`.  Used to state the kernel's arithmetic per launch.
+ * (cse_simulate / cse_validate / cse_calibrate): out (host int64 [4]) = trials simulated,
+ * posterior evaluations at Phase II looks and at Phase III looks (the first look of every
+ * trial is a table lookup and is not counted), Newton steps over all nodes of those looks.
+ * Synchronises `stream`.  Used to state the kernel's arithmetic per launch.
  * Errors: CSE_EINVAL (NULL out), CSE_EUNSUPPORTED (other designs), CSE_EHIP.
  */
-int cse_work_counters(const cse_platten *p, int64_t out[3], void *stream);
+int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream);
 
 /*
  * cse_posterior_table -- the design table of a CSE_HIER4 platten: for every outcome

@@ -176,10 +176,12 @@ def cse_simulate_per_tile(h, seed, tile_begin, tile_end, reject, stream=None):
 
 
 def cse_work_counters(h, stream=None) -> dict:
-    """Phase II/III design: trials, posterior looks and Newton steps of the last simulation."""
-    out = np.zeros(3, np.int64)
+    """Phase II/III design: trials, posterior looks (Phase II, Phase III) and Newton steps of
+    the last simulation launch."""
+    out = np.zeros(4, np.int64)
     _check("cse_work_counters", _L.cse_work_counters(h, _ptr(out), _stream(stream)))
-    return dict(trials=int(out[0]), looks=int(out[1]), newton_steps=int(out[2]))
+    return dict(trials=int(out[0]), looks_phase2=int(out[1]), looks_phase3=int(out[2]),
+                newton_steps=int(out[3]))
 
 
 def cse_platten_stats(h) -> dict:

@@ -367,7 +367,7 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     return CSE_OK;
 }
 
-int cse_work_counters(const cse_platten *p, int64_t out[3], void *stream) {
+int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream) {
     if (int e = check_handle(p, "cse_work_counters")) return e;
     const auto &P = p->P;
     if (!out) {
@@ -378,11 +378,11 @@ int cse_work_counters(const cse_platten *p, int64_t out[3], void *stream) {
         set_error("cse_work_counters: only the Phase II/III design counts its work");
         return CSE_EUNSUPPORTED;
     }
-    unsigned long long h[3] = {0, 0, 0};
+    unsigned long long h[4] = {0, 0, 0, 0};
     hipStream_t st = (hipStream_t)stream;
     CSE_HIP_TRY(hipMemcpyAsync(h, P.d_p23stats, sizeof h, hipMemcpyDeviceToHost, st));
     CSE_HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < 3; ++i) out[i] = (int64_t)h[i];
+    for (int i = 0; i < 4; ++i) out[i] = (int64_t)h[i];
     return CSE_OK;
 }
 

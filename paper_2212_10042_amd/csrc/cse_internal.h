@@ -89,8 +89,9 @@ struct P23Args {
     uint32_t *R;                    // [n_tiles] rejections at cut
     unsigned long long *sumT;       // [n_tiles][8] sums of observed y_a, then n_a, over rejections
     float *keys;                    // calibration keys S or NULL
-    unsigned long long *stats;      // NULL or [3]: trials, posterior looks, Newton steps (added)
+    unsigned long long *stats;      // NULL or [4]: trials, Phase II / Phase III posterior looks, Newton steps
     const double *gh;               // Gauss-Hermite rule (weight e^{-x^2}): nodes [16], weights [16]
+    const uint8_t *look1;           // decision code of the first look per outcome, 51^4 entries
     double sqrt_pi, z95;            // sqrt(pi), Phi^{-1}(0.95)
 };
 
@@ -143,7 +144,8 @@ struct Platten {
     int32_t *d_cfg = nullptr;
     uint32_t *d_queue = nullptr;
     double *d_gh = nullptr;              // Gauss-Hermite nodes and weights
-    unsigned long long *d_p23stats = nullptr;   // [3] work counters of the last launch
+    unsigned long long *d_p23stats = nullptr;   // [4] work counters of the last launch
+    uint8_t *d_p23look1 = nullptr;       // first-look decisions (51^4)
     WorkItem *d_p23items = nullptr;
     P23Args p23{};
     int64_t p23_grid = 0;

@@ -41,10 +41,11 @@ struct HierSummary {
 };
 
 // Posterior of counts y[4] out of n[4].  WARM starts each node's Newton iterations at the
-// previous node's mode (the converged mode is the same; only the path differs).
+// previous node's mode (the converged mode is the same; only the path differs).  Bit i-1 of
+// `need` asks for P_i and 1 - P_i (the others are left 0).
 template <bool FULL, bool WARM>
 __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], HierSummary &out,
-                                               int *newton_steps = nullptr) {
+                                               int *newton_steps = nullptr, int need = 7) {
     const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
     const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
     const double h = (LS2_HI - LS2_LO) / (HP_NODES - 1);
@@ -117,9 +118,13 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
         for (int i = 1; i < 4; ++i) {
             const double du = u[i] - u[0];
             vd[i - 1] = u[i] + u[0] + gam * du * du;
-            const double zs = (th[i] - th[0]) / sqrt(2.0 * vd[i - 1]);
-            pc[i - 1] = 0.5 * erfc(zs);          // Phi(-z)
-            if (FULL) pr[i - 1] = 0.5 * erfc(-zs);   // Phi(z)
+            pc[i - 1] = 0.0;
+            pr[i - 1] = 0.0;
+            if ((need >> (i - 1)) & 1) {
+                const double zs = (th[i] - th[0]) / sqrt(2.0 * vd[i - 1]);
+                pc[i - 1] = 0.5 * erfc(zs);              // Phi(-z)
+                if (FULL) pr[i - 1] = 0.5 * erfc(-zs);   // Phi(z)
+            }
         }
         if (lw > wmax) {
             const double sc = exp(wmax - lw);   // 0 on the first node

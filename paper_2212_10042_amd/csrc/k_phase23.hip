@@ -23,7 +23,10 @@
 // Scheduling: a persistent grid; each wave pops items (tile, simulation range) from a global
 // queue.  Every lane runs its own trial as a state machine, one posterior per step, and takes
 // the next simulation (from the wave's current item, or the next item) as soon as its trial
-// ends, so lanes whose trials stop early do not wait for long ones.  Per trial: the key S is
+// ends, so lanes whose trials stop early do not wait for long ones.  The first look always has
+// 50 patients per arm, so its decision is precomputed per outcome (51^4 bytes, the same decision
+// code run once per outcome when the platten is created).  Looks compute only the normal tails
+// they use (none in Phase II, the selected arm's in Phase III).  Per trial: the key S is
 // stored, and a rejection at the fixed lambda adds to the tile's R and to its sums of the
 // observed counts and sample sizes (integer atomics: exact, order-independent).
 #include <math.h>
@@ -79,7 +82,71 @@ __device__ __forceinline__ T pick3(const T (&v)[3], int i) {
     return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
 }
 
+// Decision at Phase II look `look` (0..2) for the active treatment arms (bit i-1 = arm i):
+// code = sel | (active after drops) << 2 | stop << 5, sel = 0 when no arm is selected.
+__device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int active, const double *gh,
+                                          double sqrt_pi, double z95) {
+    double pb[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        const double si = sqrt(2.0 * s.var[i]);
+        double acc = 0.0;
+        for (int g = 0; g < 16; ++g) {
+            const double t = s.mean[i] + si * gh[g];
+            double prod = 1.0;
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                if (kk != i) prod *= p23_Phi((t - s.mean[kk]) / sqrt(s.var[kk]));
+            acc += gh[16 + g] * prod;
+        }
+        pb[i] = acc / sqrt_pi;
+    }
+    const double thr = (look < 2) ? 0.70 : 0.60;
+    int best = 0;
+    double pb_best = 0.0;
+#pragma unroll
+    for (int i = 1; i < 4; ++i) {
+        if (!((active >> (i - 1)) & 1)) continue;
+        const double ps = p23_psucc(s.mean[i] - s.mean[0], s.dvar[i - 1], s.mean[0], s.mean[i], 200.0, z95);
+        if (ps > thr && (best == 0 || pb[i] > pb_best)) {
+            best = i;
+            pb_best = pb[i];
+        }
+    }
+    if (best) return best | (active << 2);
+    if (look == 2) return (active << 2) | (1 << 5);
+#pragma unroll
+    for (int i = 1; i < 4; ++i)
+        if (((active >> (i - 1)) & 1) && pb[i] < 0.15) active &= ~(1 << (i - 1));
+    return (active << 2) | ((active == 0 ? 1 : 0) << 5);
+}
+
 }  // namespace
+
+// Decision of the first look (50 patients per arm) for every outcome y in {0..50}^4, index
+// ((y0 51 + y1) 51 + y2) 51 + y3; the trials take it from here instead of a posterior.
+__global__ __launch_bounds__(128) void k_p23_look1(int64_t n_out, uint8_t *__restrict__ tbl,
+                                                   const double *__restrict__ gh, double sqrt_pi, double z95) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_out) return;
+    int y[4];
+    int64_t v = idx;
+    for (int a = 3; a >= 0; --a) {
+        y[a] = (int)(v % 51);
+        v /= 51;
+    }
+    const double n[4] = {50.0, 50.0, 50.0, 50.0};
+    HierSummary s;
+    hier_posterior<true, true>(y, n, s, nullptr, 0);
+    tbl[idx] = (uint8_t)p23_phase2(s, 0, 7, gh, sqrt_pi, z95);
+}
+
+hipError_t launch_p23_look1(const Platten &P, hipStream_t st) {
+    const int64_t n_out = 51LL * 51 * 51 * 51;
+    hipLaunchKernelGGL(k_p23_look1, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n_out, P.d_p23look1,
+                       P.d_gh, P.p23.sqrt_pi, P.p23.z95);
+    return hipGetLastError();
+}
 
 // Two waves per SIMD: the float64 posterior keeps about 250 registers live.
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_phase23(P23Args A) {
@@ -97,7 +164,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     uint32_t k = 0, T[4] = {0u, 0u, 0u, 0u};
     int cfg = 0, look = 0, sel = 0, active = 0;
     int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, add[4] = {0, 0, 0, 0};
-    int c_trials = 0, c_looks = 0, c_newton = 0;   // this lane's work (for the stats counters)
+    int c_trials = 0, c_look2 = 0, c_look3 = 0, c_newton = 0;   // this lane's work (stats counters)
 
     for (;;) {
         // ---- give idle lanes the next simulations of the wave's item stream ----
@@ -141,90 +208,73 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         }
         if (!__ballot(busy)) break;   // queue drained and every trial finished
         if (busy) {
-
-            // ---- enrol, then one look ----
-#pragma unroll
-            for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
-            HierSummary s;
-            {
-                const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
-                hier_posterior<true, true>(y, nd, s, &c_newton);
-            }
-            c_looks += 1;
             float S = INFINITY;
             bool done = false;
-            if (look < 3) {
-                // Phase II look: p_best of the treatment arms, p_succ of the active ones
-                double pb[4] = {0.0, 0.0, 0.0, 0.0};
+            // Phase II decision code -> next enrolment (or the end of the trial)
+            auto apply = [&](int code) {
+                const int s_arm = code & 3;
+                if (s_arm) {
+                    sel = s_arm;
 #pragma unroll
-                for (int i = 1; i < 4; ++i) {
-                    const double si = sqrt(2.0 * s.var[i]);
-                    double acc = 0.0;
-                    for (int g = 0; g < 16; ++g) {
-                        const double t = s.mean[i] + si * A.gh[g];
-                        double prod = 1.0;
-#pragma unroll
-                        for (int kk = 0; kk < 4; ++kk)
-                            if (kk != i) prod *= p23_Phi((t - s.mean[kk]) / sqrt(s.var[kk]));
-                        acc += A.gh[16 + g] * prod;
-                    }
-                    pb[i] = acc / A.sqrt_pi;
-                }
-                const double thr = (look < 2) ? 0.70 : 0.60;
-                int best = 0;
-                double pb_best = 0.0;
-#pragma unroll
-                for (int i = 1; i < 4; ++i) {
-                    if (!((active >> (i - 1)) & 1)) continue;
-                    const double ps = p23_psucc(s.mean[i] - s.mean[0], s.dvar[i - 1], s.mean[0], s.mean[i], 200.0,
-                                                A.z95);
-                    if (ps > thr && (best == 0 || pb[i] > pb_best)) {
-                        best = i;
-                        pb_best = pb[i];
-                    }
-                }
-                if (best) {
-                    sel = best;
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == best) ? 100 : 0;
+                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == s_arm) ? 100 : 0;
                     look = 3;
-                } else if (look == 2) {
+                } else if ((code >> 5) & 1) {
                     done = true;
                 } else {
-                    int r = 0;
+                    active = (code >> 2) & 7;
+                    const int per = 100 / (__popc(active) + 1);
 #pragma unroll
-                    for (int i = 1; i < 4; ++i) {
-                        if (((active >> (i - 1)) & 1) && pb[i] < 0.15) active &= ~(1 << (i - 1));
-                        r += (active >> (i - 1)) & 1;
-                    }
-                    if (r == 0) {
-                        done = true;
-                    } else {
-                        const int per = 100 / (r + 1);
-#pragma unroll
-                        for (int a = 0; a < 4; ++a) add[a] = (a == 0 || ((active >> (a - 1)) & 1)) ? per : 0;
-                        look += 1;
-                    }
+                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || ((active >> (a - 1)) & 1)) ? per : 0;
+                    look += 1;
                 }
-            } else {
-                const bool in_b = (cfg >> (sel - 1)) & 1;
-                if (look == 3) {
-                    // Phase III interim
-                    const double ms = pick4(s.mean, sel);
-                    if (pick3(s.P, sel - 1) > 0.95) {
-                        S = in_b ? -INFINITY : INFINITY;
-                        done = true;
-                    } else if (p23_psucc(ms - s.mean[0], pick3(s.dvar, sel - 1), s.mean[0], ms, 100.0, A.z95) < 0.20) {
-                        done = true;
-                    } else {
+            };
+
+            // ---- enrol; the first look is a table lookup ----
 #pragma unroll
-                        for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == sel) ? 100 : 0;
-                        look = 4;
-                    }
+            for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
+            if (look == 0) {
+                apply(A.look1[((y[0] * 51 + y[1]) * 51 + y[2]) * 51 + y[3]]);
+                if (!done) {
+#pragma unroll
+                    for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
+                }
+            }
+            if (!done) {
+                // ---- one posterior look ----
+                HierSummary s;
+                {
+                    const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
+                    // tails the wave needs (a uniform mask keeps the branch scalar)
+                    const int mine = look < 3 ? 0 : 1 << (sel - 1);
+                    int wneed = 0;
+#pragma unroll
+                    for (int i = 0; i < 3; ++i) wneed |= __ballot((mine >> i) & 1) ? (1 << i) : 0;
+                    hier_posterior<true, true>(y, nd, s, &c_newton, __builtin_amdgcn_readfirstlane(wneed));
+                }
+                if (look < 3) c_look2 += 1; else c_look3 += 1;
+                if (look < 3) {
+                    apply(p23_phase2(s, look, active, A.gh, A.sqrt_pi, A.z95));
                 } else {
-                    // final analysis
-                    S = in_b ? (float)pick3(s.Sc, sel - 1) : INFINITY;
-                    done = true;
+                    const bool in_b = (cfg >> (sel - 1)) & 1;
+                    if (look == 3) {
+                        // Phase III interim
+                        const double ms = pick4(s.mean, sel);
+                        if (pick3(s.P, sel - 1) > 0.95) {
+                            S = in_b ? -INFINITY : INFINITY;
+                            done = true;
+                        } else if (p23_psucc(ms - s.mean[0], pick3(s.dvar, sel - 1), s.mean[0], ms, 100.0, A.z95) <
+                                   0.20) {
+                            done = true;
+                        } else {
+#pragma unroll
+                            for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == sel) ? 100 : 0;
+                            look = 4;
+                        }
+                    } else {
+                        // final analysis
+                        S = in_b ? (float)pick3(s.Sc, sel - 1) : INFINITY;
+                        done = true;
+                    }
                 }
             }
             if (done) {
@@ -244,19 +294,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
         }
     }
     if (A.stats) {
-        // one atomic per wave: reduce the lane counters across the wave first
-        unsigned long long t = (unsigned long long)c_trials, l = (unsigned long long)c_looks,
-                           w = (unsigned long long)c_newton;
-        for (int off = 32; off >= 1; off >>= 1) {
-            t += __shfl_xor(t, off);
-            l += __shfl_xor(l, off);
-            w += __shfl_xor(w, off);
-        }
-        if (lane == 0) {
-            atomicAdd(&A.stats[0], t);
-            atomicAdd(&A.stats[1], l);
-            atomicAdd(&A.stats[2], w);
-        }
+        // one atomic per counter and wave: reduce the lane counters across the wave first
+        unsigned long long c[4] = {(unsigned long long)c_trials, (unsigned long long)c_look2,
+                                   (unsigned long long)c_look3, (unsigned long long)c_newton};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            for (int off = 32; off >= 1; off >>= 1) c[i] += __shfl_xor(c[i], off);
+        if (lane == 0)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) atomicAdd(&A.stats[i], c[i]);
     }
 }
 
@@ -271,7 +317,7 @@ hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned
     A.sumT = sumT;
     A.keys = keys;
     A.stats = P.d_p23stats;
-    e = launch_zero(P.d_p23stats, 3 * sizeof(unsigned long long), st);
+    e = launch_zero(P.d_p23stats, 4 * sizeof(unsigned long long), st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_phase23, dim3((uint32_t)P.p23_grid), dim3(WG), 0, st, A);
     return hipGetLastError();

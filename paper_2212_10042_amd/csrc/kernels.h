@@ -24,6 +24,7 @@ hipError_t launch_hier4_table(int n, float4 *tbl, hipStream_t st);
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st);
 hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
                           hipStream_t st);
+hipError_t launch_p23_look1(const Platten &P, hipStream_t st);
 hipError_t launch_phase23_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st);
 hipError_t launch_hier4_plain(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st);
 

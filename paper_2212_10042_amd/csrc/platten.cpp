@@ -514,7 +514,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         if (int e = upload(&P->d_tileT, P->tile_T.data(), P->tile_T.size())) return e;
         if (int e = upload(&P->d_cfg, P->tile_cfg.data(), P->tile_cfg.size())) return e;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_queue, sizeof(uint32_t)));
-        CSE_HIP_TRY(hipMalloc((void **)&P->d_p23stats, 3 * sizeof(unsigned long long)));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_p23stats, 4 * sizeof(unsigned long long)));
         P23Args &A = P->p23;
         A.items = P->d_p23items;
         A.n_items = (int64_t)items.size();
@@ -528,6 +528,15 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         A.gh = P->d_gh;
         A.sqrt_pi = sqrt(M_PI);
         A.z95 = normal_q95();
+        // decisions of the first look (50 patients per arm) for every outcome, once per platten
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_p23look1, (size_t)51 * 51 * 51 * 51));
+        A.look1 = P->d_p23look1;
+        {
+            const auto t0 = std::chrono::steady_clock::now();
+            CSE_HIP_TRY(launch_p23_look1(*P, nullptr));
+            CSE_HIP_TRY(hipDeviceSynchronize());
+            P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
         // persistent grid: enough workgroups of 4 waves to fill the chip, no more than the items
         P->p23_grid = std::max<int64_t>(1, std::min<int64_t>((A.n_items + 3) / 4, 2048));
     } else {
@@ -724,7 +733,7 @@ void free_platten(Platten *P) {
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
-                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats};
+                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
 }
