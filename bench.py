@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="binom2_256_tri")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick the fused kernel's launch shape with cse_autotune before timing")
+    ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
     ap.add_argument("--progress", action="store_true",
                     help="synchronise and report on stderr after every step (for steps of a minute or more)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -182,6 +185,12 @@ def main():
             cse.cse_validate(P.handle, w["seed"], w["delta"], o["reject"], o["score_T"], o["score_Z"], o["grad"],
                              o["cp"], o["bound"])
 
+    tune = None
+    if args.autotune:
+        t_tune = time.perf_counter()
+        v, g = cse.cse_autotune(P.handle, seed=w["seed"])
+        tune = {"value": v, "grid": g, "seconds": time.perf_counter() - t_tune}
+
     def note(msg):
         if args.progress:
             print(f"bench.py: {msg} ({time.perf_counter() - t_start:.1f} s)", file=sys.stderr, flush=True)
@@ -216,6 +225,37 @@ def main():
     total = st["total_sims"] * args.steps
     value = total / dt
     ms_step = dt / args.steps * 1e3
+
+    # the same step captured once as a HIP graph and replayed (outputs checked against eager)
+    graph = None
+    if not args.no_graph:
+        ref = {k: v.clone() for k, v in o.items() if v is not None}
+        t_cap = time.perf_counter()
+        if calibrating:
+            plan = cse.cse_plan_calibrate(P.handle, w["seed"], w["alpha"], o["alpha_prime"], o["k"], o["lam"],
+                                          o["lam_g"], o["rej_at"], w["delta"], o["reject"], o["score_T"],
+                                          o["score_Z"], o["grad"], o["cp"], o["bound"])
+        else:
+            plan = cse.cse_plan_validate(P.handle, w["seed"], w["delta"], o["reject"], o["score_T"], o["score_Z"],
+                                         o["grad"], o["cp"], o["bound"])
+        cap_ms = (time.perf_counter() - t_cap) * 1e3
+        cse.cse_plan_launch(plan)
+        torch.cuda.synchronize()
+        tg = time.perf_counter()
+        for i in range(args.steps):
+            cse.cse_plan_launch(plan)
+            if args.progress:
+                torch.cuda.synchronize()
+            note(f"graph replay {i + 1} done")
+        torch.cuda.synchronize()
+        dtg = time.perf_counter() - tg
+        same = all(torch.equal(ref[k], o[k]) for k in ref)
+        graph = {"ms_per_step": dtg / args.steps * 1e3, "value": st["total_sims"] * args.steps / dtg,
+                 "capture_ms": cap_ms, "nodes": cse.cse_plan_nodes(plan), "identical_to_eager": same}
+        cse.cse_plan_destroy(plan)
+        if not same:
+            print("bench.py: graph replay outputs differ from the eager step", file=sys.stderr)
+            sys.exit(1)
 
     # roofline of the dominant kernel: the fused simulation
     if design == "binom2":
@@ -279,6 +319,9 @@ def main():
         "speedup_vs_plain_fwd": (value / plain["value"]) if plain else None,
         "plain_fwd_per_tile": plain,
         "kernel_avg_ms": kern,
+        "graph_replay": graph,
+        "autotune": tune,
+        "launch_shape": cse.cse_platten_stats(P.handle)["launch_shape"],
         "platten_build_ms": platten_ms,
         "max_tile_bound": float(o["bound"].max().item()) if n else None,
         "roofline": roof,

@@ -191,6 +191,51 @@ int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double
               double delta_or_alpha, double *out, double *q_star, void *stream);
 
 /*
+ * Plans: one validation or calibration step captured once into a HIP graph and replayed.
+ * The step is exactly the launches of cse_validate / cse_calibrate with the same arguments
+ * (Algorithms 1 and 2: alpha' -> simulation -> selection -> reductions -> bound); every
+ * pointer, the seed and the levels are fixed when the plan is made, so each replay writes
+ * the same outputs as the eager call would.  The calibration key workspace is allocated
+ * before capture; the graph contains kernel launches only.
+ *   cse_plan_validate / cse_plan_calibrate: arguments and errors as cse_validate /
+ *        cse_calibrate (no stream: capture uses a private stream); out receives the plan.
+ *   cse_plan_launch: enqueue one replay on `stream` (asynchronous).  Replays of one plan,
+ *        and plans or eager calls on the same platten, share the platten's workspaces:
+ *        order them on one stream.
+ *   cse_plan_nodes: number of graph nodes (-1 for NULL).
+ *   cse_plan_destroy: synchronises the device and releases the graph; NULL is a no-op.
+ * Errors: CSE_EINVAL, CSE_ENOMEM, CSE_EHIP (capture or instantiation failed).
+ */
+typedef struct cse_plan cse_plan;
+int cse_plan_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *reject,
+                      int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                      double *tile_bound, double *q_star, cse_plan **out);
+int cse_plan_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime,
+                       int32_t *k, double *lambda_tile, double *lambda_global,
+                       int32_t *reject_at_lambda, double delta, int32_t *reject,
+                       int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                       double *tile_bound, cse_plan **out);
+int cse_plan_launch(const cse_plan *plan, void *stream);
+int64_t cse_plan_nodes(const cse_plan *plan);
+int cse_plan_destroy(cse_plan *plan);
+
+/*
+ * cse_autotune -- choose the launch shape of the platten's fused simulation kernel by timing
+ * candidates on the current device (synchronises `stream`):
+ *   CSE_ZTEST1:            waves of the grid, from {4096 .. 65536};
+ *   CSE_BINOM2_Z, HIER4:   workgroups of the grid (simulation ranges per group of batches),
+ *                          from {1024 .. 16384}, timed on the calibration launch;
+ *   CSE_PHASE23:           trials per queue item {64, 128, 256, 512} x persistent grid
+ *                          {512, 1024, 2048} workgroups, timed on a strided sample of tiles
+ *                          holding at most max_trials trials.
+ * The fastest is kept in the platten.  Results of every later call are unchanged (integer
+ * reductions are order-independent and keys are laid out by tile, not by launch shape).
+ *   out  host int64 [2]: the chosen value and, for CSE_PHASE23, the grid (else 0).
+ * Errors: CSE_EINVAL (NULL out, max_trials < 1), CSE_ENOMEM, CSE_EHIP.
+ */
+int cse_autotune(cse_platten *p, uint64_t seed, int64_t max_trials, int64_t out[2], void *stream);
+
+/*
  * cse_simulate_per_tile -- the plain forward-only path: one kernel launch per tile, no
  * common-random-number batching across tiles, rejection counts only (the design's fixed rule).
  * Same Philox stream and draw rules as cse_simulate, hence identical R.  Processes tiles
@@ -230,7 +275,9 @@ int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int6
  *   over tiles), tiles per batch, max N, batch-simulation pairs (sum over batches of their N),
  *   workgroup-simulation pairs (sum over workgroup items of their simulation count; the unit of
  *   shared random-number generation), number of distinct N, microseconds spent building the
- *   design table at creation (CSE_HIER4, else 0), 0.
+ *   design table at creation (CSE_HIER4 posterior table, CSE_PHASE23 first-look table, else
+ *   0), the launch shape (CSE_ZTEST1 waves, CSE_BINOM2_Z / CSE_HIER4 workgroups, CSE_PHASE23
+ *   trials per queue item; see cse_autotune).
  */
 int cse_platten_stats(const cse_platten *p, int64_t out[12]);
 

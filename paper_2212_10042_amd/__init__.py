@@ -29,7 +29,8 @@ CSE_PLATTEN_KEEP_ALL = 1
 EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
             "cse_simulate", "cse_validate", "cse_calibrate", "cse_bound", "cse_simulate_per_tile",
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
-            "cse_posterior_table", "cse_work_counters", "cse_last_error")
+            "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
+            "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -64,12 +65,19 @@ def _load():
     L.cse_platten_stats.argtypes = [P, P]
     L.cse_posterior_table.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
     L.cse_work_counters.argtypes = [P, P, P]
+    L.cse_plan_validate.argtypes = [P, u64, dbl] + [P] * 7 + [ctypes.POINTER(P)]
+    L.cse_plan_calibrate.argtypes = [P, u64, dbl, P, P, P, P, P, dbl] + [P] * 6 + [ctypes.POINTER(P)]
+    L.cse_plan_launch.argtypes = [P, P]
+    L.cse_plan_nodes.argtypes = [P]
+    L.cse_plan_nodes.restype = i64
+    L.cse_plan_destroy.argtypes = [P]
+    L.cse_autotune.argtypes = [P, u64, i64, P, P]
     L.cse_profile_enable.argtypes = [i32]
     L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.cse_profile_reset.argtypes = []
     L.cse_last_error.restype = ctypes.c_char_p
     for fn in EXPORTED:
-        if fn not in ("cse_platten_size", "cse_last_error"):
+        if fn not in ("cse_platten_size", "cse_last_error", "cse_plan_nodes"):
             getattr(L, fn).restype = ctypes.c_int
     return L
 
@@ -175,6 +183,44 @@ def cse_simulate_per_tile(h, seed, tile_begin, tile_end, reject, stream=None):
                                                              _stream(stream)))
 
 
+def cse_plan_validate(h, seed, delta, reject, score_T, score_Z, grad, cp_upper, tile_bound, q_star=None):
+    out = ctypes.c_void_p()
+    _check("cse_plan_validate", _L.cse_plan_validate(h, seed, delta, _ptr(reject), _ptr(score_T), _ptr(score_Z),
+                                                     _ptr(grad), _ptr(cp_upper), _ptr(tile_bound), _ptr(q_star),
+                                                     ctypes.byref(out)))
+    return out
+
+
+def cse_plan_calibrate(h, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda=None,
+                       delta=0.01, reject=None, score_T=None, score_Z=None, grad=None, cp_upper=None,
+                       tile_bound=None):
+    out = ctypes.c_void_p()
+    _check("cse_plan_calibrate", _L.cse_plan_calibrate(
+        h, seed, alpha, _ptr(alpha_prime), _ptr(k), _ptr(lambda_tile), _ptr(lambda_global), _ptr(reject_at_lambda),
+        delta, _ptr(reject), _ptr(score_T), _ptr(score_Z), _ptr(grad), _ptr(cp_upper), _ptr(tile_bound),
+        ctypes.byref(out)))
+    return out
+
+
+def cse_plan_launch(plan, stream=None):
+    _check("cse_plan_launch", _L.cse_plan_launch(plan, _stream(stream)))
+
+
+def cse_plan_nodes(plan) -> int:
+    return int(_L.cse_plan_nodes(plan))
+
+
+def cse_plan_destroy(plan):
+    _check("cse_plan_destroy", _L.cse_plan_destroy(plan))
+
+
+def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):
+    """Pick the fused kernel's launch shape on this device; returns (value, grid)."""
+    out = np.zeros(2, np.int64)
+    _check("cse_autotune", _L.cse_autotune(h, seed, max_trials, _ptr(out), _stream(stream)))
+    return int(out[0]), int(out[1])
+
+
 def cse_work_counters(h, stream=None) -> dict:
     """Phase II/III design: trials, posterior looks (Phase II, Phase III) and Newton steps of
     the last simulation launch."""
@@ -188,7 +234,7 @@ def cse_platten_stats(h) -> dict:
     out = np.zeros(12, np.int64)
     _check("cse_platten_stats", _L.cse_platten_stats(h, _ptr(out)))
     keys = ("n_tiles", "n_batches", "n_work_items", "n_key_slots", "total_sims", "tiles_per_batch",
-            "max_sims", "batch_sims", "group_sims", "n_sim_classes", "table_build_us")
+            "max_sims", "batch_sims", "group_sims", "n_sim_classes", "table_build_us", "launch_shape")
     return {k: int(v) for k, v in zip(keys, out)}
 
 

@@ -1,6 +1,8 @@
 // api.hip -- the extern "C" entry points of libcse.so (declared in include/cse.h).
 #include <math.h>
 
+#include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <new>
@@ -12,6 +14,13 @@
 
 struct cse_platten {
     cse::Platten P;
+};
+
+struct cse_plan {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int device = 0;
+    int64_t n_nodes = 0;
 };
 
 namespace {
@@ -74,11 +83,14 @@ hipEvent_t pool_event() {
     return e;
 }
 
+thread_local bool t_capturing = false;   // no timing events inside a graph capture
+
 struct Timed {
     ProfRec rec{};
     hipStream_t st;
     bool on = false;
     Timed(const char *name, hipStream_t s) : st(s) {
+        if (t_capturing) return;
         std::lock_guard<std::mutex> g(g_prof_mu);
         if (!g_prof_on) return;
         rec.name = name;
@@ -144,6 +156,77 @@ int ensure_keys(cse::Platten &P) {
         return CSE_ENOMEM;
     }
     P.keys_bytes = need;
+    return CSE_OK;
+}
+
+int check_validate(const cse_platten *p, double delta, const void *score_T, const void *score_Z, const void *grad,
+                   const double *tile_bound, const char *fn) {
+    if (int e = check_handle(p, fn)) return e;
+    if (!in_unit(delta)) {
+        set_error(std::string(fn) + ": delta must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    if (!tile_bound) {
+        set_error(std::string(fn) + ": tile_bound must not be NULL");
+        return CSE_EINVAL;
+    }
+    return check_scores(p->P, score_T, score_Z, grad, fn);
+}
+
+int check_calibrate(const cse_platten *p, double alpha, double delta, const void *score_T, const void *score_Z,
+                    const void *grad, bool want_bound, const char *fn) {
+    if (int e = check_handle(p, fn)) return e;
+    if (!in_unit(alpha)) {
+        set_error(std::string(fn) + ": alpha must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    if (want_bound && !in_unit(delta)) {
+        set_error(std::string(fn) + ": delta must lie in (0, 1) when cp_upper or tile_bound is requested");
+        return CSE_EINVAL;
+    }
+    return check_scores(p->P, score_T, score_Z, grad, fn);
+}
+
+// Validation (Algorithm 1) on stream st: simulate with the design's fixed rule, then the
+// Clopper-Pearson + Tilt-Bound of every tile.  Arguments checked by the caller.
+int validate_impl(const cse::Platten &P, uint64_t seed, double delta, int32_t *reject, int64_t *score_T,
+                  double *score_Z, double *grad, double *cp_upper, double *tile_bound, double *q_star,
+                  hipStream_t st) {
+    if (int e = run_sim(P, seed, false, st)) return e;
+    CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
+    Timed tm("bound_validate", st);
+    CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tile_bound, q_star, nullptr, cp_upper, st));
+    return CSE_OK;
+}
+
+// Calibration (Algorithm 2) on stream st; the key workspace must exist (ensure_keys).
+int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+                   double *lambda_tile, double *lambda_global, int32_t *reject_at_lambda, double delta,
+                   int32_t *reject, int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                   double *tile_bound, hipStream_t st) {
+    double *ap = alpha_prime ? alpha_prime : P.d_apw;
+    int32_t *kk = k ? k : P.d_kw;
+    double *lam = lambda_tile ? lambda_tile : P.d_lamw;
+    // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
+    {
+        Timed tm("bound_invert", st);
+        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, st));
+    }
+    if (int e = run_sim(P, seed, true, st)) return e;
+    {
+        Timed tm("select", st);
+        CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));
+    }
+    CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
+    if (reject || score_T || score_Z || grad)
+        CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
+    if (cp_upper || tile_bound) {
+        // alpha' lives in the caller's buffer or in d_apw, and is no longer read once k is
+        // known, so d_apw can hold the bound the caller did not ask for.
+        double *tb = tile_bound ? tile_bound : P.d_apw;
+        Timed tm("bound_validate", st);
+        CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tb, nullptr, nullptr, cp_upper, st));
+    }
     return CSE_OK;
 }
 
@@ -227,23 +310,9 @@ int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *
 int cse_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *reject,
                  int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
                  double *tile_bound, double *q_star, void *stream) {
-    if (int e = check_handle(p, "cse_validate")) return e;
-    if (!in_unit(delta)) {
-        set_error("cse_validate: delta must lie in (0, 1)");
-        return CSE_EINVAL;
-    }
-    if (!tile_bound) {
-        set_error("cse_validate: tile_bound must not be NULL");
-        return CSE_EINVAL;
-    }
-    const auto &P = p->P;
-    if (int e = check_scores(P, score_T, score_Z, grad, "cse_validate")) return e;
-    hipStream_t st = (hipStream_t)stream;
-    if (int e = run_sim(P, seed, false, st)) return e;
-    CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
-    Timed tm("bound_validate", st);
-    CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tile_bound, q_star, nullptr, cp_upper, st));
-    return CSE_OK;
+    if (int e = check_validate(p, delta, score_T, score_Z, grad, tile_bound, "cse_validate")) return e;
+    return validate_impl(p->P, seed, delta, reject, score_T, score_Z, grad, cp_upper, tile_bound, q_star,
+                         (hipStream_t)stream);
 }
 
 int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime,
@@ -251,43 +320,219 @@ int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alp
                   int32_t *reject_at_lambda, double delta, int32_t *reject, int64_t *score_T,
                   double *score_Z, double *grad, double *cp_upper, double *tile_bound,
                   void *stream) {
-    if (int e = check_handle(p, "cse_calibrate")) return e;
-    if (!in_unit(alpha)) {
-        set_error("cse_calibrate: alpha must lie in (0, 1)");
-        return CSE_EINVAL;
-    }
-    const bool want_bound = cp_upper || tile_bound;
-    if (want_bound && !in_unit(delta)) {
-        set_error("cse_calibrate: delta must lie in (0, 1) when cp_upper or tile_bound is requested");
-        return CSE_EINVAL;
-    }
+    if (int e = check_calibrate(p, alpha, delta, score_T, score_Z, grad, cp_upper || tile_bound, "cse_calibrate"))
+        return e;
     auto &P = const_cast<cse_platten *>(p)->P;
-    if (int e = check_scores(P, score_T, score_Z, grad, "cse_calibrate")) return e;
     if (int e = ensure_keys(P)) return e;
+    return calibrate_impl(P, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
+                          reject, score_T, score_Z, grad, cp_upper, tile_bound, (hipStream_t)stream);
+}
+
+// ---- plans: one validation or calibration step captured into a HIP graph ----
+namespace {
+int capture_plan(const cse_platten *p, const std::function<int(hipStream_t)> &body, cse_plan **out,
+                 const char *fn) {
+    if (!out) {
+        set_error(std::string(fn) + ": NULL out");
+        return CSE_EINVAL;
+    }
+    *out = nullptr;
+    hipStream_t cs = nullptr;
+    CSE_HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    int e = CSE_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        set_error(std::string(fn) + ": hipStreamBeginCapture failed");
+        e = CSE_EHIP;
+    } else {
+        t_capturing = true;
+        e = body(cs);
+        t_capturing = false;
+        const hipError_t ee = hipStreamEndCapture(cs, &g);
+        if (e == CSE_OK && ee != hipSuccess) {
+            set_error(std::string(fn) + ": hipStreamEndCapture failed: " + hipGetErrorString(ee));
+            e = CSE_EHIP;
+        }
+    }
+    hipGraphExec_t ex = nullptr;
+    if (e == CSE_OK && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        set_error(std::string(fn) + ": hipGraphInstantiate failed");
+        e = CSE_EHIP;
+    }
+    (void)hipStreamDestroy(cs);
+    if (e != CSE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return e;
+    }
+    cse_plan *pl = new (std::nothrow) cse_plan();
+    if (!pl) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipGraphDestroy(g);
+        set_error(std::string(fn) + ": out of host memory");
+        return CSE_ENOMEM;
+    }
+    pl->graph = g;
+    pl->exec = ex;
+    pl->device = p->P.device;
+    pl->n_nodes = 0;
+    size_t nn = 0;
+    if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess) pl->n_nodes = (int64_t)nn;
+    *out = pl;
+    return CSE_OK;
+}
+}  // namespace
+
+int cse_plan_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *reject, int64_t *score_T,
+                      double *score_Z, double *grad, double *cp_upper, double *tile_bound, double *q_star,
+                      cse_plan **out) {
+    if (int e = check_validate(p, delta, score_T, score_Z, grad, tile_bound, "cse_plan_validate")) return e;
+    const auto &P = p->P;
+    return capture_plan(p, [&](hipStream_t cs) {
+        return validate_impl(P, seed, delta, reject, score_T, score_Z, grad, cp_upper, tile_bound, q_star, cs);
+    }, out, "cse_plan_validate");
+}
+
+int cse_plan_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+                       double *lambda_tile, double *lambda_global, int32_t *reject_at_lambda, double delta,
+                       int32_t *reject, int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                       double *tile_bound, cse_plan **out) {
+    if (int e = check_calibrate(p, alpha, delta, score_T, score_Z, grad, cp_upper || tile_bound,
+                                "cse_plan_calibrate"))
+        return e;
+    auto &P = const_cast<cse_platten *>(p)->P;
+    if (int e = ensure_keys(P)) return e;   // allocation stays outside the graph
+    return capture_plan(p, [&](hipStream_t cs) {
+        return calibrate_impl(P, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
+                              reject, score_T, score_Z, grad, cp_upper, tile_bound, cs);
+    }, out, "cse_plan_calibrate");
+}
+
+int cse_plan_launch(const cse_plan *plan, void *stream) {
+    if (!plan) {
+        set_error("cse_plan_launch: NULL plan");
+        return CSE_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) {
+        set_error("cse_plan_launch: the current HIP device is not the plan's device");
+        return CSE_EINVAL;
+    }
+    CSE_HIP_TRY(hipGraphLaunch(plan->exec, (hipStream_t)stream));
+    return CSE_OK;
+}
+
+int64_t cse_plan_nodes(const cse_plan *plan) { return plan ? plan->n_nodes : -1; }
+
+int cse_autotune(cse_platten *p, uint64_t seed, int64_t max_trials, int64_t out[2], void *stream) {
+    if (int e = check_handle(p, "cse_autotune")) return e;
+    if (!out || max_trials < 1) {
+        set_error("cse_autotune: NULL out or max_trials < 1");
+        return CSE_EINVAL;
+    }
+    auto &P = p->P;
     hipStream_t st = (hipStream_t)stream;
-    double *ap = alpha_prime ? alpha_prime : P.d_apw;
-    int32_t *kk = k ? k : P.d_kw;
-    double *lam = lambda_tile ? lambda_tile : P.d_lamw;
-    // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
-    {
-        Timed tm("bound_invert", st);
-        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, st));
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    CSE_HIP_TRY(hipEventCreate(&e0));
+    CSE_HIP_TRY(hipEventCreate(&e1));
+    struct Ev {
+        hipEvent_t a, b;
+        ~Ev() {
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+        }
+    } ev{e0, e1};
+    // mean time of `reps` launches of f after one untimed launch
+    auto timeit = [&](const std::function<int()> &f, int reps, float *ms) -> int {
+        if (int e = f()) return e;
+        CSE_HIP_TRY(hipEventRecord(e0, st));
+        for (int r = 0; r < reps; ++r)
+            if (int e = f()) return e;
+        CSE_HIP_TRY(hipEventRecord(e1, st));
+        CSE_HIP_TRY(hipEventSynchronize(e1));
+        CSE_HIP_TRY(hipEventElapsedTime(ms, e0, e1));
+        *ms /= (float)reps;
+        return CSE_OK;
+    };
+    out[0] = out[1] = 0;
+    if (P.design.kind == CSE_PHASE23) {
+        // a strided sample of tiles holding at most max_trials trials
+        int64_t total = P.total_sims, stride = std::max<int64_t>(1, (total + max_trials - 1) / max_trials);
+        std::vector<int64_t> tiles;
+        for (int64_t t = 0; t < P.n_tiles; t += stride) tiles.push_back(t);
+        const int32_t chunks[4] = {64, 128, 256, 512};
+        const int64_t grids[3] = {512, 1024, 2048};
+        float best = 3.4e38f;
+        int32_t bc = P.p23_chunk;
+        int64_t bg = P.p23_grid;
+        struct DevItems {   // the sample's item list, freed on every exit
+            cse::WorkItem *p = nullptr;
+            ~DevItems() {
+                if (p) (void)hipFree(p);
+            }
+        } d_it;
+        for (int32_t c : chunks) {
+            std::vector<cse::WorkItem> items;
+            for (int64_t t : tiles)
+                for (int64_t k0 = 0; k0 < P.tile_N[t]; k0 += c) {
+                    cse::WorkItem w{};
+                    w.blk = (int32_t)t;
+                    w.k_begin = (uint32_t)k0;
+                    w.k_end = (uint32_t)std::min<int64_t>(P.tile_N[t], k0 + c);
+                    items.push_back(w);
+                }
+            if (d_it.p) CSE_HIP_TRY(hipFree(d_it.p));
+            d_it.p = nullptr;
+            CSE_HIP_TRY(hipMalloc((void **)&d_it.p, items.size() * sizeof(cse::WorkItem)));
+            CSE_HIP_TRY(hipMemcpy(d_it.p, items.data(), items.size() * sizeof(cse::WorkItem), hipMemcpyHostToDevice));
+            const int64_t full = std::max<int64_t>(1, ((int64_t)items.size() + 3) / 4);
+            for (int64_t g : grids) {
+                const int64_t gg = std::min(g, full);
+                float ms = 0.0f;
+                if (int e = timeit([&]() -> int {
+                        CSE_LAUNCH(cse::launch_phase23_items(P, seed, d_it.p, (int64_t)items.size(), gg, P.d_Rw, st));
+                        return CSE_OK;
+                    }, 1, &ms))
+                    return e;
+                if (ms < best) {
+                    best = ms;
+                    bc = c;
+                    bg = g;
+                }
+            }
+        }
+        if (int e = cse::plan_queue_items(&P, bc, bg)) return e;
+        out[0] = P.p23_chunk;
+        out[1] = P.p23_grid;
+        return CSE_OK;
     }
-    if (int e = run_sim(P, seed, true, st)) return e;
-    {
-        Timed tm("select", st);
-        CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));
+    // one-wave-per-block (z-test) or group kernels (2-arm, 4-arm): time the calibration launch
+    if (int e = ensure_keys(P)) return e;
+    const bool group = P.design.kind == CSE_BINOM2_Z || P.design.kind == CSE_HIER4;
+    const int64_t cands[5] = {1024, 2048, 4096, 8192, 16384};
+    const int64_t wave_cands[5] = {4096, 8192, 16384, 32768, 65536};
+    float best = 3.4e38f;
+    int64_t bv = group ? P.tune_wgs : P.tune_waves;
+    for (int i = 0; i < 5; ++i) {
+        const int64_t v = group ? cands[i] : wave_cands[i];
+        if (int e = group ? cse::plan_group_items(&P, v) : cse::plan_work_items(&P, v)) return e;
+        float ms = 0.0f;
+        if (int e = timeit([&]() { return run_sim(P, seed, true, st); }, 3, &ms)) return e;
+        if (ms < best) {
+            best = ms;
+            bv = v;
+        }
     }
-    CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
-    if (reject || score_T || score_Z || grad)
-        CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
-    if (want_bound) {
-        // alpha' lives in the caller's buffer or in d_apw, and is no longer read once k is
-        // known, so d_apw can hold the bound the caller did not ask for.
-        double *tb = tile_bound ? tile_bound : P.d_apw;
-        Timed tm("bound_validate", st);
-        CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tb, nullptr, nullptr, cp_upper, st));
-    }
+    if (int e = group ? cse::plan_group_items(&P, bv) : cse::plan_work_items(&P, bv)) return e;
+    out[0] = bv;
+    return CSE_OK;
+}
+
+int cse_plan_destroy(cse_plan *plan) {
+    if (!plan) return CSE_OK;
+    (void)hipDeviceSynchronize();
+    if (plan->exec) (void)hipGraphExecDestroy(plan->exec);
+    if (plan->graph) (void)hipGraphDestroy(plan->graph);
+    delete plan;
     return CSE_OK;
 }
 
@@ -363,7 +608,8 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     out[8] = P.group_sims;
     out[9] = P.n_cls;
     out[10] = (int64_t)(P.table_ms * 1000.0);
-    out[11] = 0;
+    out[11] = P.design.kind == CSE_PHASE23 ? P.p23_chunk
+              : (P.design.kind == CSE_ZTEST1 ? P.tune_waves : P.tune_wgs);
     return CSE_OK;
 }
 

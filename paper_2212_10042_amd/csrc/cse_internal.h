@@ -149,7 +149,11 @@ struct Platten {
     WorkItem *d_p23items = nullptr;
     P23Args p23{};
     int64_t p23_grid = 0;
-    int32_t p23_chunk = 0;               // simulations per queue item
+    int32_t p23_chunk = 256;             // simulations per queue item
+    // launch shapes (cse_autotune): waves of the one-wave-per-block kernels, workgroups of the
+    // group kernels
+    int64_t tune_waves = 16384, tune_wgs = 4096;
+    std::vector<int64_t> blk_sims;       // simulations of each block
     std::vector<int64_t> p23_item_off;   // [n_tiles + 1] first queue item of each tile
     int64_t h4_outcomes = 0;
     double table_ms = 0.0;               // time to build the design table at platten creation
@@ -193,6 +197,9 @@ const char *get_error();
 int build_platten(const cse_design *design, int64_t n_boxes, const double *theta,
                   const double *radii, const int32_t *sims, int32_t flags, Platten *P);
 void free_platten(Platten *P);
+int plan_work_items(Platten *P, int64_t target_waves);
+int plan_group_items(Platten *P, int64_t target_wgs);
+int plan_queue_items(Platten *P, int32_t chunk, int64_t grid);
 
 }  // namespace cse
 

@@ -323,6 +323,24 @@ hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned
     return hipGetLastError();
 }
 
+// A launch over a caller-made item list (schedule tuning on a sample of tiles); counts only.
+hipError_t launch_phase23_items(const Platten &P, uint64_t seed, const WorkItem *items, int64_t n_items, int64_t grid,
+                                uint32_t *R, hipStream_t st) {
+    hipError_t e = launch_zero(P.d_queue, sizeof(uint32_t), st);
+    if (e != hipSuccess) return e;
+    P23Args A = P.p23;
+    A.items = items;
+    A.n_items = n_items;
+    A.key0 = (uint32_t)seed;
+    A.key1 = (uint32_t)(seed >> 32);
+    A.R = R;
+    A.sumT = nullptr;
+    A.keys = nullptr;
+    A.stats = nullptr;
+    hipLaunchKernelGGL(k_phase23, dim3((uint32_t)grid), dim3(WG), 0, st, A);
+    return hipGetLastError();
+}
+
 // The plain path: one launch per tile over that tile's own queue items (no other tiles share
 // the grid); counts only.
 hipError_t launch_phase23_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st) {

@@ -25,6 +25,8 @@ hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *key
 hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
                           hipStream_t st);
 hipError_t launch_p23_look1(const Platten &P, hipStream_t st);
+hipError_t launch_phase23_items(const Platten &P, uint64_t seed, const WorkItem *items, int64_t n_items, int64_t grid,
+                                uint32_t *R, hipStream_t st);
 hipError_t launch_phase23_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st);
 hipError_t launch_hier4_plain(const Platten &P, uint64_t seed, int64_t t, uint32_t *R_tile, hipStream_t st);
 

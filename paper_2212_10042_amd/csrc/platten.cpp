@@ -374,7 +374,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     }
 
     // ---- tile batches ----
-    std::vector<int64_t> blk_sims;   // n_sims per block, for the work items
+    std::vector<int64_t> &blk_sims = P->blk_sims;   // n_sims per block, for the work items
     if (kind == CSE_ZTEST1) {
         std::map<int32_t, std::vector<int64_t>> byN;
         for (int64_t t = 0; t < P->n_tiles; ++t) byN[P->tile_N[t]].push_back(t);
@@ -497,27 +497,12 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             key_stride[t] = 64;   // contiguous: chunk c of 64 keys starts at 64 c
             P->n_keys += P->tile_N[t];
         }
-        P->p23_chunk = 256;
-        std::vector<WorkItem> items;
-        for (int64_t t = 0; t < P->n_tiles; ++t) {
-            P->p23_item_off.push_back((int64_t)items.size());
-            for (int64_t k0 = 0; k0 < P->tile_N[t]; k0 += P->p23_chunk) {
-                WorkItem w{};
-                w.blk = (int32_t)t;
-                w.k_begin = (uint32_t)k0;
-                w.k_end = (uint32_t)std::min<int64_t>(P->tile_N[t], k0 + P->p23_chunk);
-                items.push_back(w);
-            }
-        }
-        P->p23_item_off.push_back((int64_t)items.size());
-        if (int e = upload(&P->d_p23items, items.data(), items.size())) return e;
+        if (int e = plan_queue_items(P, P->p23_chunk, -1)) return e;
         if (int e = upload(&P->d_tileT, P->tile_T.data(), P->tile_T.size())) return e;
         if (int e = upload(&P->d_cfg, P->tile_cfg.data(), P->tile_cfg.size())) return e;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_queue, sizeof(uint32_t)));
         CSE_HIP_TRY(hipMalloc((void **)&P->d_p23stats, 4 * sizeof(unsigned long long)));
         P23Args &A = P->p23;
-        A.items = P->d_p23items;
-        A.n_items = (int64_t)items.size();
         A.counter = P->d_queue;
         A.tileT = P->d_tileT;
         A.cfg = P->d_cfg;
@@ -537,8 +522,6 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             CSE_HIP_TRY(hipDeviceSynchronize());
             P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
         }
-        // persistent grid: enough workgroups of 4 waves to fill the chip, no more than the items
-        P->p23_grid = std::max<int64_t>(1, std::min<int64_t>((A.n_items + 3) / 4, 2048));
     } else {
         // distinct arm values -> integer coordinates; 8 x 8 coordinate blocks per N class
         std::vector<double> u0, u1;
@@ -629,56 +612,12 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             return CSE_EINVAL;
         }
 
-    // ---- work items: split each block's simulations so the grid has enough waves ----
-    // (the Phase II/III design has no blocks: its queue items were made above)
-    if (P->n_blocks > 0) {
-        const int64_t target = 16384;   // waves: several per SIMD on 256 CUs x 4 SIMDs
-        std::vector<WorkItem> items;
-        int64_t slices = std::max<int64_t>(1, (target + P->n_blocks - 1) / P->n_blocks);
-        for (int64_t b = 0; b < P->n_blocks; ++b) {
-            int64_t N = blk_sims[b];
-            P->block_sims += N;
-            int64_t chunks = (N + WAVE - 1) / WAVE;
-            int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
-            for (int64_t k0 = 0; k0 < N; k0 += per) {
-                WorkItem w{};
-                w.blk = (int32_t)b;
-                w.k_begin = (uint32_t)k0;
-                w.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
-                items.push_back(w);
-            }
-        }
-        P->n_items = (int64_t)items.size();
-        if (int e = upload(&P->d_items, items.data(), items.size())) return e;
-    }
-    if (kind == CSE_BINOM2_Z || kind == CSE_HIER4) {
-        // groups of 4 consecutive blocks of equal N (blocks are ordered by N), split in sims
-        const int64_t target = 4096;    // workgroups
-        std::vector<std::vector<int64_t>> groups;
-        for (int64_t b = 0; b < P->n_blocks; ++b) {
-            if (groups.empty() || groups.back().size() == 4 || blk_sims[groups.back()[0]] != blk_sims[b])
-                groups.push_back({});
-            groups.back().push_back(b);
-        }
-        const int64_t ng = (int64_t)groups.size();
-        const int64_t slices = std::max<int64_t>(1, (target + ng - 1) / ng);
-        std::vector<GroupItem> gi;
-        for (auto &g : groups) {
-            const int64_t N = blk_sims[g[0]];
-            const int64_t chunks = (N + WAVE - 1) / WAVE;
-            const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
-            for (int64_t k0 = 0; k0 < N; k0 += per) {
-                GroupItem it{};
-                for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
-                it.k_begin = (uint32_t)k0;
-                it.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
-                P->group_sims += (int64_t)(it.k_end - it.k_begin);
-                gi.push_back(it);
-            }
-        }
-        P->n_gitems = (int64_t)gi.size();
-        if (int e = upload(&P->d_gitems, gi.data(), gi.size())) return e;
-    }
+    // ---- work items (launch shapes; cse_autotune may rebuild them) ----
+    for (int64_t b = 0; b < P->n_blocks; ++b) P->block_sims += blk_sims[b];
+    if (P->n_blocks > 0)
+        if (int e = plan_work_items(P, P->tune_waves)) return e;
+    if (kind == CSE_BINOM2_Z || kind == CSE_HIER4)
+        if (int e = plan_group_items(P, P->tune_wgs)) return e;
 
     if (int e = upload(&P->d_theta, P->tile_theta.data(), P->tile_theta.size())) return e;
     if (int e = upload(&P->d_N, P->tile_N.data(), P->tile_N.size())) return e;
@@ -721,6 +660,92 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
+    return CSE_OK;
+}
+
+// Work items of the one-wave-per-block kernels: each block's simulations split into slices of
+// whole 64-simulation chunks so that the grid has about target_waves waves.
+int plan_work_items(Platten *P, int64_t target_waves) {
+    std::vector<WorkItem> items;
+    const int64_t slices = std::max<int64_t>(1, (target_waves + P->n_blocks - 1) / P->n_blocks);
+    for (int64_t b = 0; b < P->n_blocks; ++b) {
+        const int64_t N = P->blk_sims[b];
+        const int64_t chunks = (N + WAVE - 1) / WAVE;
+        const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
+        for (int64_t k0 = 0; k0 < N; k0 += per) {
+            WorkItem w{};
+            w.blk = (int32_t)b;
+            w.k_begin = (uint32_t)k0;
+            w.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
+            items.push_back(w);
+        }
+    }
+    if (P->d_items) CSE_HIP_TRY(hipFree(P->d_items));
+    P->d_items = nullptr;
+    P->n_items = (int64_t)items.size();
+    P->tune_waves = target_waves;
+    return upload(&P->d_items, items.data(), items.size());
+}
+
+// Workgroup items of the 2-arm and 4-arm kernels: groups of 4 consecutive blocks of equal N
+// (blocks are ordered by N) whose four waves share the Philox words of a simulation range;
+// ranges sliced so that the grid has about target_wgs workgroups.
+int plan_group_items(Platten *P, int64_t target_wgs) {
+    std::vector<std::vector<int64_t>> groups;
+    for (int64_t b = 0; b < P->n_blocks; ++b) {
+        if (groups.empty() || groups.back().size() == 4 || P->blk_sims[groups.back()[0]] != P->blk_sims[b])
+            groups.push_back({});
+        groups.back().push_back(b);
+    }
+    const int64_t ng = (int64_t)groups.size();
+    const int64_t slices = std::max<int64_t>(1, (target_wgs + ng - 1) / ng);
+    std::vector<GroupItem> gi;
+    int64_t gs = 0;
+    for (auto &g : groups) {
+        const int64_t N = P->blk_sims[g[0]];
+        const int64_t chunks = (N + WAVE - 1) / WAVE;
+        const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
+        for (int64_t k0 = 0; k0 < N; k0 += per) {
+            GroupItem it{};
+            for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
+            it.k_begin = (uint32_t)k0;
+            it.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
+            gs += (int64_t)(it.k_end - it.k_begin);
+            gi.push_back(it);
+        }
+    }
+    if (P->d_gitems) CSE_HIP_TRY(hipFree(P->d_gitems));
+    P->d_gitems = nullptr;
+    P->n_gitems = (int64_t)gi.size();
+    P->group_sims = gs;
+    P->tune_wgs = target_wgs;
+    return upload(&P->d_gitems, gi.data(), gi.size());
+}
+
+// Queue items of the Phase II/III kernel: (tile, `chunk` consecutive trials); the persistent
+// grid has `grid` workgroups (-1: enough to fill the chip, at most one per 4 items).
+int plan_queue_items(Platten *P, int32_t chunk, int64_t grid) {
+    std::vector<WorkItem> items;
+    P->p23_item_off.clear();
+    for (int64_t t = 0; t < P->n_tiles; ++t) {
+        P->p23_item_off.push_back((int64_t)items.size());
+        for (int64_t k0 = 0; k0 < P->tile_N[t]; k0 += chunk) {
+            WorkItem w{};
+            w.blk = (int32_t)t;
+            w.k_begin = (uint32_t)k0;
+            w.k_end = (uint32_t)std::min<int64_t>(P->tile_N[t], k0 + chunk);
+            items.push_back(w);
+        }
+    }
+    P->p23_item_off.push_back((int64_t)items.size());
+    if (P->d_p23items) CSE_HIP_TRY(hipFree(P->d_p23items));
+    P->d_p23items = nullptr;
+    if (int e = upload(&P->d_p23items, items.data(), items.size())) return e;
+    P->p23_chunk = chunk;
+    P->p23.items = P->d_p23items;
+    P->p23.n_items = (int64_t)items.size();
+    const int64_t full = std::max<int64_t>(1, (P->p23.n_items + 3) / 4);
+    P->p23_grid = grid > 0 ? std::min<int64_t>(grid, full) : std::min<int64_t>(full, 2048);
     return CSE_OK;
 }
 
