@@ -21,9 +21,17 @@ def _np(t):
     return t.detach().cpu().numpy()
 
 
-@pytest.mark.parametrize("cfg", ["ztest1d_64", "ragged"])
+@pytest.mark.parametrize("cfg", ["ztest1d_64", "ragged", "mixed_sizes"])
 def test_ztest_parity(cfg):
-    w = W.ztest1d_64() if cfg == "ztest1d_64" else W.ztest_1d(37, 777, seed=4)
+    """mixed_sizes: tiles on both sides of the 32,768 keys that one workgroup's LDS holds, so
+    both selection kernels (one HBM pass into LDS, three passes over HBM) run in one launch."""
+    if cfg == "ztest1d_64":
+        w = W.ztest1d_64()
+    elif cfg == "ragged":
+        w = W.ztest_1d(37, 777, seed=4)
+    else:
+        w = W.ztest_1d(8, 1, seed=2)
+        w["sims"] = np.array([5, 100, 32768, 32769, 40000, 1000, 65536, 2], np.int32)
     th, rd, sm, seed = w["theta"], w["radii"], w["sims"], w["seed"]
     print(f"[ztest] {w['name']}", flush=True)
     P = cse.Platten.create("ztest1", th, rd, sm)
@@ -42,12 +50,14 @@ def test_ztest_parity(cfg):
     np.testing.assert_allclose(_np(g["alpha_prime"]), oc["alpha_prime"], rtol=1e-9)
     assert np.array_equal(_np(g["k"]), oc["k"])
     np.testing.assert_allclose(_np(g["lambda_tile"]), oc["lam"], rtol=0, atol=2e-6)
-    assert abs(float(_np(g["lambda_global"])[0]) - oc["lam_global"]) <= 2e-6
+    lg = float(_np(g["lambda_global"])[0])
+    assert lg == oc["lam_global"] if np.isinf(oc["lam_global"]) else abs(lg - oc["lam_global"]) <= 2e-6
     # continuous statistic: exactly k - 1 simulations below the k-th smallest
-    assert np.array_equal(_np(g["reject_at_lambda"]), _np(g["k"]) - 1)
+    assert np.array_equal(_np(g["reject_at_lambda"]), np.maximum(_np(g["k"]) - 1, 0))
     # common random numbers: lambda*_i + theta_i is the same order statistic of -Z
-    s = _np(g["lambda_tile"]) + th[:, 0]
-    assert np.ptp(s) < 1e-5
+    if np.all(sm == sm[0]):
+        s = _np(g["lambda_tile"]) + th[:, 0]
+        assert np.ptp(s) < 1e-5
     P.close()
 
 
