@@ -51,8 +51,10 @@ hipError_t launch_hier4_table(int n, float4 *tbl, hipStream_t st) {
 // chunk's 140 words through LDS.  Per (simulation, box slot): one 16-byte gather of
 // (1 - P_1, 1 - P_2, 1 - P_3) at the outcome y; the design rejects treatment arm i when
 // 1 - P_i < cut, giving a 3-bit mask m; configuration b's FWER event is m & b != 0.  Per box the
-// lanes count each mask value (7 packed 6-bit counters in two words, exact for 63 simulations
-// per lane between flushes), so R_b = sum_{m & b != 0} count[m] for every b of the box.
+// lanes count each mask value (7 packed 4-bit counters in one word, exact for 15 simulations
+// per lane between flushes, which transpose the counters through the word buffer in two
+// halves of 32 slots), so R_b = sum_{m & b != 0} count[m] for every b of the box.  LDS is the
+// 35 KB word buffer only, so four workgroups fit on a CU.
 // Calibration keys: S_b = min_{i in b} (1 - P_i) per (simulation, tile), float32.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync4() {
@@ -62,7 +64,7 @@ __device__ __forceinline__ void wave_sync4() {
 }
 
 template <bool KEYS>
-__global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
                                               const float4 *__restrict__ tbl, float cut,
@@ -72,18 +74,23 @@ __global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
     constexpr int NB = NW / 4;   // 35 Philox blocks
     constexpr int NWAVES = WG / WAVE;
     constexpr int M1 = NP + 1;
-    __shared__ uint32_t lds[NWAVES][B4S][WAVE + 1];
-    uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);
-    static_assert(NW * WAVE <= NWAVES * B4S * (WAVE + 1), "word buffer must fit");
+    constexpr int HALF = B4S / 2;          // slots per flush half
+    constexpr int FLUSH_EVERY = 15;        // 4-bit counters: at most 15 increments between flushes
+    // The chunk's Philox words; between chunks the same memory holds the flush transposes
+    // (per wave HALF x (64 + 1) words, padded against bank conflicts).
+    __shared__ uint32_t words[NW][WAVE];
+    static_assert(NWAVES * HALF * (WAVE + 1) <= NW * WAVE, "flush transposes must fit in the word buffer");
+    uint32_t(*tr)[HALF][WAVE + 1] = reinterpret_cast<uint32_t(*)[HALF][WAVE + 1]>(&words[0][0]);
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int64_t it = blockIdx.x;
     if (it >= n_items) return;
-    const GroupItem G = items[it];
-    const int32_t blk = G.blk[wv];
+    const GroupItem *__restrict__ G = items + it;
+    const int32_t blk = G->blk[wv];   // read in place: a register copy indexed by wv would go to scratch
     const bool live = blk >= 0;
-    const Blk4 *__restrict__ B = blocks + (live ? blk : G.blk[0]);
+    const Blk4 *__restrict__ B = blocks + (live ? blk : G->blk[0]);
+    const uint32_t kb = G->k_begin, ke = G->k_end;
     uint32_t T0[B4N0], T1[B4N1], T2[B4N2], T3[B4N3];
 #pragma unroll
     for (int u = 0; u < B4N0; ++u) T0[u] = B->T0[u];
@@ -96,45 +103,43 @@ __global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
     const int32_t n_rows = B->n_rows;
     float *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
 
-    uint32_t acc0[B4S], acc1[B4S];
+    // per slot: seven 4-bit counters, field m-1 counting the simulations with rejection mask m
+    uint32_t acc[B4S];
 #pragma unroll
-    for (int s = 0; s < B4S; ++s) {
-        acc0[s] = 0u;
-        acc1[s] = 0u;
-    }
-    uint32_t tot[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};   // lane t: counts of mask m for slot t
+    for (int s = 0; s < B4S; ++s) acc[s] = 0u;
+    // lane l: partial totals (over lanes of half l >> 5) of slot l & 31 (tot0) and 32 + (l & 31) (tot1)
+    uint32_t tot0[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}, tot1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
 
     auto flush = [&]() {
-        __syncthreads();
+        __syncthreads();   // the word buffer is free: every wave has finished counting
 #pragma unroll
-        for (int s = 0; s < B4S; ++s) lds[wv][s][lane] = acc0[s];
-        wave_sync4();
-        for (int l = 0; l < WAVE; ++l) {
-            const uint32_t x = lds[wv][lane][l];
+        for (int h = 0; h < 2; ++h) {
 #pragma unroll
-            for (int m = 1; m <= 5; ++m) tot[m] += (x >> (6 * (m - 1))) & 63u;
+            for (int s = 0; s < HALF; ++s) tr[wv][s][lane] = acc[h * HALF + s];
+            wave_sync4();
+            const int sl = lane & (HALF - 1), j0 = (lane >> 5) * HALF;
+            for (int j = j0; j < j0 + HALF; ++j) {
+                const uint32_t x = tr[wv][sl][j];
+#pragma unroll
+                for (int m = 1; m <= 7; ++m) {
+                    const uint32_t f = (x >> (4 * (m - 1))) & 15u;
+                    if (h == 0)
+                        tot0[m] += f;
+                    else
+                        tot1[m] += f;
+                }
+            }
+            wave_sync4();
         }
-        wave_sync4();
 #pragma unroll
-        for (int s = 0; s < B4S; ++s) lds[wv][s][lane] = acc1[s];
-        wave_sync4();
-        for (int l = 0; l < WAVE; ++l) {
-            const uint32_t x = lds[wv][lane][l];
-            tot[6] += x & 63u;
-            tot[7] += (x >> 6) & 63u;
-        }
-#pragma unroll
-        for (int s = 0; s < B4S; ++s) {
-            acc0[s] = 0u;
-            acc1[s] = 0u;
-        }
-        __syncthreads();
+        for (int s = 0; s < B4S; ++s) acc[s] = 0u;
+        __syncthreads();   // transposes read before the next chunk's words overwrite them
     };
 
     int since = 0;
-    for (uint32_t k0 = G.k_begin; k0 < G.k_end; k0 += WAVE) {
+    for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
-        const bool act = k < G.k_end;
+        const bool act = k < ke;
         for (int b = wv; b < NB; b += NWAVES) {
             const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
             words[4 * b + 0][lane] = w.x;
@@ -197,8 +202,7 @@ __global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
                             const uint32_t m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) |
                                                       (q.z < cut ? 4u : 0u))
                                                    : 0u;
-                            acc0[s] += (m >= 1u && m <= 5u) ? (1u << (6u * (m - 1u))) : 0u;
-                            acc1[s] += (m >= 6u) ? (1u << (6u * (m - 6u))) : 0u;
+                            acc[s] += m ? (1u << (4u * (m - 1u))) : 0u;
                             if (KEYS) {
                                 const uint32_t bm = B->bmask[s];
                                 int row = row0;
@@ -215,24 +219,37 @@ __global__ __launch_bounds__(WG) void k_hier4(const Blk4 *__restrict__ blocks,
                             }
                         }
         }
-        if (++since == 63) {
+        if (++since == FLUSH_EVERY) {
             flush();
             since = 0;
         }
     }
     flush();
     if (!live) return;
-    const int32_t t0 = B->tile0[lane];
-    if (t0 < 0) return;
-    const uint32_t bm = B->bmask[lane];
-    int q = 0;
-    for (int b = 1; b <= 7; ++b) {
-        if (!(bm & (1u << b))) continue;
-        uint32_t r = 0u;
-        for (int m = 1; m <= 7; ++m)
-            if (m & b) r += tot[m];
-        atomicAdd(&R[t0 + q], r);
-        ++q;
+    // totals of slot s: lanes s & 31 and (s & 31) + 32 each hold half of the lanes' counts
+#pragma unroll
+    for (int m = 1; m <= 7; ++m) {
+        tot0[m] += __shfl_xor(tot0[m], HALF);
+        tot1[m] += __shfl_xor(tot1[m], HALF);
+    }
+    if (lane >= HALF) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int s = h * HALF + lane;
+        const int32_t t0 = B->tile0[s];
+        if (t0 < 0) continue;
+        const uint32_t bm = B->bmask[s];
+        int q = 0;
+#pragma unroll
+        for (int b = 1; b <= 7; ++b) {
+            if (!(bm & (1u << b))) continue;
+            uint32_t r = 0u;
+#pragma unroll
+            for (int m = 1; m <= 7; ++m)
+                if (m & b) r += (h == 0) ? tot0[m] : tot1[m];
+            atomicAdd(&R[t0 + q], r);
+            ++q;
+        }
     }
 }
 
