@@ -121,6 +121,60 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
 }
 
+// k-th smallest (k >= 1) of the n order-preserving keys get(j), j < n, by three radix passes
+// (11/11/10 bits) with an LDS histogram; also the number of keys strictly below it.  Called by
+// the whole workgroup.
+template <class Get>
+__device__ void radix_kth(int n, uint32_t k, Get get, uint32_t *hist, uint32_t *part, uint32_t *s_bin,
+                          uint32_t *s_below, uint32_t &key, uint32_t &below_out) {
+    constexpr int BINS = 2048;
+    const int tid = threadIdx.x;
+    uint32_t prefix = 0u, below = 0u, need = k;
+    const int shifts[3] = {21, 10, 0};
+    const int widths[3] = {11, 11, 10};
+    for (int pass = 0; pass < 3; ++pass) {
+        const int sh = shifts[pass], wd = widths[pass];
+        const uint32_t mask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + wd));
+        for (int j = tid; j < BINS; j += SEL_WG) hist[j] = 0u;
+        __syncthreads();
+        for (int j = tid; j < n; j += SEL_WG) {
+            const uint32_t u = get(j);
+            if ((u & mask_hi) == prefix) atomicAdd(&hist[(u >> sh) & ((1u << wd) - 1u)], 1u);
+        }
+        __syncthreads();
+        const int nb = 1 << wd;
+        const int per = nb / SEL_WG;
+        uint32_t local = 0u;
+        for (int j = tid * per; j < (tid + 1) * per; ++j) local += hist[j];
+        block_exclusive_scan(local, part);
+        uint32_t run = part[tid];
+        for (int j = tid * per; j < (tid + 1) * per; ++j) {
+            if (run < need && run + hist[j] >= need) {
+                *s_bin = (uint32_t)j;
+                *s_below = run;
+            }
+            run += hist[j];
+        }
+        __syncthreads();
+        prefix |= *s_bin << sh;
+        below += *s_below;
+        need -= *s_below;
+        __syncthreads();
+    }
+    key = prefix;
+    below_out = below;
+}
+
+// Selection of lambda*_i for float32 keys.  Tiles of at most SEL_SAMPLE keys are selected in
+// LDS.  Larger tiles: the first SEL_SAMPLE simulations (i.i.d. draws of the statistic) give
+// sample order statistics lo, hi that bracket rank k/N with a 5-sigma margin; one pass over
+// the tile's keys counts those below lo and gathers those in [lo, hi] into LDS; if the k-th
+// smallest lies among them it is selected there, else the exact radix passes run over HBM.
+// Either way the result is the exact k-th smallest key.
+constexpr int SEL_SAMPLE = 2048;
+constexpr int SEL_CAND = 4096;
+
+template <bool VEC4>
 __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__ keys,
                                                        const int64_t *__restrict__ key_off,
                                                        const int64_t *__restrict__ key_stride,
@@ -128,12 +182,14 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
                                                        const int32_t *__restrict__ kk,
                                                        double *__restrict__ lam,
                                                        int32_t *__restrict__ rej_at) {
-    constexpr int BINS = 2048;
-    __shared__ uint32_t hist[BINS];
+    __shared__ uint32_t hist[2048];
     __shared__ uint32_t part[SEL_WG];
-    __shared__ uint32_t s_bin, s_below;
+    __shared__ uint32_t samp[SEL_SAMPLE];
+    __shared__ uint32_t cand[SEL_CAND];
+    __shared__ uint32_t s_bin, s_below, s_cnt, s_lt;
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
     const int32_t n = N[t];
     const int32_t k = kk[t];
     if (k <= 0 || k > n) {
@@ -146,40 +202,95 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
     // key of simulation j at kt + (j / 64) * stride + j % 64 (chunked layouts; stride 64 = contiguous)
     const float *__restrict__ kt = keys + key_off[t];
     const int64_t stride = key_stride[t];
-    uint32_t prefix = 0u, below = 0u, need = (uint32_t)k;
-    const int shifts[3] = {21, 10, 0};
-    const int widths[3] = {11, 11, 10};
-    for (int pass = 0; pass < 3; ++pass) {
-        const int sh = shifts[pass], wd = widths[pass];
-        const uint32_t mask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + wd));
-        for (int j = tid; j < BINS; j += SEL_WG) hist[j] = 0u;
-        __syncthreads();
-        for (int j = tid; j < n; j += SEL_WG) {
-            const uint32_t u = f2ord(kt[(int64_t)(j >> 6) * stride + (j & 63)]);
-            if ((u & mask_hi) == prefix) atomicAdd(&hist[(u >> sh) & ((1u << wd) - 1u)], 1u);
+    auto hbm = [&](int j) { return f2ord(kt[(int64_t)(j >> 6) * stride + (j & 63)]); };
+    auto from_samp = [&](int j) { return samp[j]; };
+    auto from_cand = [&](int j) { return cand[j]; };
+    const int m = n < SEL_SAMPLE ? n : SEL_SAMPLE;
+#pragma unroll
+    for (int i = 0; i < SEL_SAMPLE / SEL_WG; ++i) {
+        const int j = i * SEL_WG + tid;
+        if (j < m) samp[j] = hbm(j);
+    }
+    __syncthreads();
+    uint32_t key = 0u, below = 0u;
+    if (n <= SEL_SAMPLE) {
+        radix_kth(n, (uint32_t)k, from_samp, hist, part, &s_bin, &s_below, key, below);
+    } else {
+        const double pr = (double)k / (double)n;
+        const double sd = sqrt((double)m * pr * (1.0 - pr));
+        const int lo_r = (int)floor(pr * m - 5.0 * sd) - 1;   // sample ranks (1-based) of the bracket
+        const int hi_r = (int)ceil(pr * m + 5.0 * sd) + 1;
+        uint32_t lo = 0u, hi = 0xFFFFFFFFu, dummy = 0u;
+        if (lo_r >= 1) radix_kth(m, (uint32_t)lo_r, from_samp, hist, part, &s_bin, &s_below, lo, dummy);
+        if (hi_r <= m) radix_kth(m, (uint32_t)hi_r, from_samp, hist, part, &s_bin, &s_below, hi, dummy);
+        if (tid == 0) {
+            s_cnt = 0u;
+            s_lt = 0u;
         }
         __syncthreads();
-        const int nb = 1 << wd;
-        const int per = nb / SEL_WG;
-        uint32_t local = 0u;
-        for (int j = tid * per; j < (tid + 1) * per; ++j) local += hist[j];
-        block_exclusive_scan(local, part);
-        uint32_t run = part[tid];
-        for (int j = tid * per; j < (tid + 1) * per; ++j) {
-            if (run < need && run + hist[j] >= need) {
-                s_bin = (uint32_t)j;
-                s_below = run;
+        // one pass over the tile: count below the bracket, gather the bracket into LDS.  Each
+        // thread loads a batch of keys before using any (many loads in flight; with VEC4 the
+        // tile's 64-key chunks are 256-byte aligned and read as float4), and the trip count is
+        // uniform so that every lane takes part in the ballots.
+        uint32_t lt = 0u;
+        auto take = [&](uint32_t u, bool valid) {
+            lt += (valid && u < lo) ? 1u : 0u;
+            const bool in = valid && u >= lo && u <= hi;
+            const unsigned long long bal = __ballot(in);
+            if (bal) {   // uniform
+                uint32_t base = 0u;
+                if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
+                base = __shfl(base, 0);
+                const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+                if (in && pos < (uint32_t)SEL_CAND) cand[pos] = u;
             }
-            run += hist[j];
+        };
+        if (VEC4) {
+            constexpr int QB = 8;   // float4 per thread per round: 32 keys
+            const int nq = ((n + 63) >> 6) * 16;
+            for (int q0 = 0; q0 < nq; q0 += SEL_WG * QB) {
+                float4 v[QB];
+#pragma unroll
+                for (int i = 0; i < QB; ++i) {
+                    const int q = q0 + i * SEL_WG + tid;
+                    v[i] = q < nq ? *reinterpret_cast<const float4 *>(kt + (int64_t)(q >> 4) * stride + (q & 15) * 4)
+                                  : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+#pragma unroll
+                for (int i = 0; i < QB; ++i) {
+                    const int j = 4 * (q0 + i * SEL_WG + tid);
+                    take(f2ord(v[i].x), j + 0 < n);
+                    take(f2ord(v[i].y), j + 1 < n);
+                    take(f2ord(v[i].z), j + 2 < n);
+                    take(f2ord(v[i].w), j + 3 < n);
+                }
+            }
+        } else {
+            constexpr int SEL_BATCH = 8;
+            for (int j0 = 0; j0 < n; j0 += SEL_WG * SEL_BATCH) {
+                uint32_t u[SEL_BATCH];
+#pragma unroll
+                for (int i = 0; i < SEL_BATCH; ++i) {
+                    const int j = j0 + i * SEL_WG + tid;
+                    u[i] = j < n ? hbm(j) : 0u;
+                }
+#pragma unroll
+                for (int i = 0; i < SEL_BATCH; ++i) take(u[i], j0 + i * SEL_WG + tid < n);
+            }
         }
+        for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
+        if (lane == 0) atomicAdd(&s_lt, lt);
         __syncthreads();
-        prefix |= s_bin << sh;
-        below += s_below;
-        need -= s_below;
-        __syncthreads();
+        const uint32_t nc = s_cnt, nlt = s_lt;
+        if (nc <= (uint32_t)SEL_CAND && nlt < (uint32_t)k && (uint32_t)k <= nlt + nc) {
+            radix_kth((int)nc, (uint32_t)k - nlt, from_cand, hist, part, &s_bin, &s_below, key, below);
+            below += nlt;
+        } else {
+            radix_kth(n, (uint32_t)k, hbm, hist, part, &s_bin, &s_below, key, below);   // exact fallback
+        }
     }
     if (tid == 0) {
-        lam[t] = (double)ord2f(prefix);
+        lam[t] = (double)ord2f(key);
         if (rej_at) rej_at[t] = (int32_t)below;
     }
 }
@@ -260,8 +371,11 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st) {
-    if (P.design.kind != CSE_BINOM2_Z)
-        hipLaunchKernelGGL(k_select_f32, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
+    if (P.design.kind == CSE_HIER4)   // 64-key chunks at 256-byte offsets: float4 loads
+        hipLaunchKernelGGL(k_select_f32<true>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
+                           (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
+    else if (P.design.kind != CSE_BINOM2_Z)
+        hipLaunchKernelGGL(k_select_f32<false>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
                            (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else
         hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG),

@@ -106,3 +106,14 @@ def test_phase23_per_tile_path_and_determinism():
     assert torch.equal(R, a["reject"])
     assert int(R.sum()) > 0
     P.close()
+
+
+def test_phase23_large_tiles_selection_paths():
+    """Tiles above the 2,048-trial sample of the float32 selection: the bracket path, and tiles
+    whose k-th smallest key is +inf among thousands of +inf keys (the candidate list overflows
+    and the exact radix passes over all keys run)."""
+    w = W.phase23_grid((2, 1, 1, 1), 1, lo=-0.2, hi=0.2, seed=9)
+    w["theta"] = np.array([[0.6, -0.5, -0.5, -0.5], [0.1, 0.1, 0.1, 0.1]])
+    w["radii"] = np.full((2, 4), 0.05)
+    w["sims"] = np.array([5000, 2200], np.int32)
+    n, R = _compare(w, seed=9, lam=0.06253)
