@@ -30,10 +30,12 @@ __device__ __forceinline__ void wave_sync() {
 //
 // Per-lane accumulators are packed per tile: bits 0-5 rejections, 6-17 sum of y0 over
 // rejections, 18-29 sum of y1 over rejections; exact for up to 63 simulations per lane
-// between flushes (63 * 35 < 4096).  A flush transposes the 64 x 64 (lane, tile) matrix through LDS so
-// lane t sums tile t's column into 32-bit totals; the final totals are added to global
-// memory with integer atomics (order-independent, hence deterministic).  The word buffer
-// and the transpose buffers share LDS: workgroup barriers separate their uses.
+// between flushes (63 * 35 < 4096).  A flush transposes the 64 x 64 (lane, tile) matrix through
+// LDS in two halves of 32 tiles, lanes l and l + 32 each summing half of tile l's column into
+// 32-bit totals (joined by one shuffle at the end); the final totals are added to global
+// memory with integer atomics (order-independent, hence deterministic).  The word buffer and
+// the transpose buffers share 33 KB of LDS (workgroup barriers separate their uses), so four
+// workgroups fit on a CU.
 // ------------------------------------------------------------------------------------
 template <bool KEYS>
 __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
@@ -47,20 +49,24 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     constexpr int NW = 2 * NP35;
     constexpr int NB = (NW + 3) / 4;
     constexpr int NWAVES = WG / WAVE;
-    __shared__ uint32_t lds[NWAVES][NT][WAVE + 1];
+    constexpr int HALF = NT / 2;   // slots per flush half
+    // flush transposes (per wave HALF x (64 + 1) words, padded against bank conflicts); between
+    // flushes the same memory holds the chunk's Philox words.  33 KB: three workgroups per CU.
+    __shared__ uint32_t lds[NWAVES][HALF][WAVE + 1];
     __shared__ int32_t s_cut[64];
     uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [4*NB][64]
-    static_assert(4 * NB * WAVE <= NWAVES * NT * (WAVE + 1), "word buffer must fit");
+    static_assert(4 * NB * WAVE <= NWAVES * HALF * (WAVE + 1), "word buffer must fit");
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (threadIdx.x < 64) s_cut[threadIdx.x] = threadIdx.x <= NP35 ? cut_tbl[threadIdx.x] : 64;
     const int64_t it = blockIdx.x;
     if (it >= n_items) return;   // uniform over the workgroup
-    const GroupItem G = items[it];
-    const int32_t blk = G.blk[wv];
+    const GroupItem *__restrict__ G = items + it;
+    const int32_t blk = G->blk[wv];   // read in place: a register copy indexed by wv would go to scratch
     const bool live = blk >= 0;
-    const Blk2 *__restrict__ B = blocks + (live ? blk : G.blk[0]);
+    const Blk2 *__restrict__ B = blocks + (live ? blk : G->blk[0]);
+    const uint32_t kb = G->k_begin, ke = G->k_end;
     uint32_t T0[B2U], T1[B2V];
 #pragma unroll
     for (int u = 0; u < B2U; ++u) T0[u] = B->T0[u];
@@ -71,18 +77,24 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     uint32_t acc[NT];
 #pragma unroll
     for (int s = 0; s < NT; ++s) acc[s] = 0u;
-    uint32_t totR = 0u, tot0 = 0u, tot1 = 0u;
+    // lane l: partial totals (over the lanes of half l >> 5) of slots l & 31 ([0]) and 32 + (l & 31) ([1])
+    uint32_t totR[2] = {0u, 0u}, tot0[2] = {0u, 0u}, tot1[2] = {0u, 0u};
 
     auto flush = [&]() {
         __syncthreads();   // every wave is done with the word buffer
 #pragma unroll
-        for (int s = 0; s < NT; ++s) lds[wv][s][lane] = acc[s];
-        wave_sync();
-        for (int l = 0; l < WAVE; ++l) {
-            const uint32_t x = lds[wv][lane][l];
-            totR += x & 63u;
-            tot0 += (x >> 6) & 4095u;
-            tot1 += (x >> 18) & 4095u;
+        for (int h = 0; h < 2; ++h) {
+#pragma unroll
+            for (int s = 0; s < HALF; ++s) lds[wv][s][lane] = acc[h * HALF + s];
+            wave_sync();
+            const int sl = lane & (HALF - 1), j0 = (lane >> 5) * HALF;
+            for (int l = j0; l < j0 + HALF; ++l) {
+                const uint32_t x = lds[wv][sl][l];
+                totR[h] += x & 63u;
+                tot0[h] += (x >> 6) & 4095u;
+                tot1[h] += (x >> 18) & 4095u;
+            }
+            wave_sync();
         }
 #pragma unroll
         for (int s = 0; s < NT; ++s) acc[s] = 0u;
@@ -90,9 +102,9 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     };
 
     int since = 0;
-    for (uint32_t k0 = G.k_begin; k0 < G.k_end; k0 += WAVE) {
+    for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
-        const bool act = k < G.k_end;
+        const bool act = k < ke;
         // this wave's share of the chunk's Philox blocks
         for (int b = wv; b < NB; b += NWAVES) {
             const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
@@ -161,11 +173,21 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     }
     flush();
     if (!live) return;
-    const int32_t tile = B->tile[lane];
-    if (tile >= 0) {
-        atomicAdd(&R[tile], totR);
-        atomicAdd(&sumT[2 * (int64_t)tile], (unsigned long long)tot0);
-        atomicAdd(&sumT[2 * (int64_t)tile + 1], (unsigned long long)tot1);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // combine the two lane halves of each slot
+        totR[h] += __shfl_xor(totR[h], HALF);
+        tot0[h] += __shfl_xor(tot0[h], HALF);
+        tot1[h] += __shfl_xor(tot1[h], HALF);
+    }
+    if (lane >= HALF) return;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int32_t tile = B->tile[h * HALF + lane];
+        if (tile >= 0) {
+            atomicAdd(&R[tile], totR[h]);
+            atomicAdd(&sumT[2 * (int64_t)tile], (unsigned long long)tot0[h]);
+            atomicAdd(&sumT[2 * (int64_t)tile + 1], (unsigned long long)tot1[h]);
+        }
     }
 }
 
