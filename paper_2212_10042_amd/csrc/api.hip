@@ -207,12 +207,30 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
     double *ap = alpha_prime ? alpha_prime : P.d_apw;
     int32_t *kk = k ? k : P.d_kw;
     double *lam = lambda_tile ? lambda_tile : P.d_lamw;
+    // The step's dependencies: alpha' -> k -> selection; simulation -> selection, finish and
+    // the validation bound.  The fused simulation runs alone (it fills the chip); afterwards
+    // the validation bound (float64, latency-bound) runs on the side stream beside the
+    // selection, forked from and joined into `st` by events.
     // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
     {
         Timed tm("bound_invert", st);
         CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, st));
     }
     if (int e = run_sim(P, seed, true, st)) return e;
+    const bool want_bound = cp_upper || tile_bound;
+    if (want_bound) {
+        hipStream_t side = P.side;
+        CSE_HIP_TRY(hipEventRecord(P.ev_sim, st));
+        CSE_HIP_TRY(hipStreamWaitEvent(side, P.ev_sim, 0));
+        // alpha' lives in the caller's buffer or in d_apw, and is no longer read once k is
+        // known, so d_apw can hold the bound the caller did not ask for.
+        double *tb = tile_bound ? tile_bound : P.d_apw;
+        {
+            Timed tm("bound_validate", side);
+            CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tb, nullptr, nullptr, cp_upper, side));
+        }
+        CSE_HIP_TRY(hipEventRecord(P.ev_val, side));
+    }
     {
         Timed tm("select", st);
         CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));
@@ -220,13 +238,7 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
     CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
     if (reject || score_T || score_Z || grad)
         CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
-    if (cp_upper || tile_bound) {
-        // alpha' lives in the caller's buffer or in d_apw, and is no longer read once k is
-        // known, so d_apw can hold the bound the caller did not ask for.
-        double *tb = tile_bound ? tile_bound : P.d_apw;
-        Timed tm("bound_validate", st);
-        CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tb, nullptr, nullptr, cp_upper, st));
-    }
+    if (want_bound) CSE_HIP_TRY(hipStreamWaitEvent(st, P.ev_val, 0));   // join
     return CSE_OK;
 }
 

@@ -165,6 +165,11 @@ struct Platten {
 
     std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
 
+    // side stream (default priority) and fork/join events of the calibration step: the
+    // validation bound runs beside the selection
+    hipStream_t side = nullptr;
+    hipEvent_t ev_sim = nullptr, ev_val = nullptr;
+
     // Clopper-Pearson table: one entry per (N class, R), R = 0..N (classes = distinct N)
     int32_t n_cls = 0;
     int64_t n_cp = 0;                    // sum over classes of N + 1

@@ -660,6 +660,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
+    CSE_HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    for (hipEvent_t *e : {&P->ev_sim, &P->ev_val})
+        CSE_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return CSE_OK;
 }
 
@@ -761,6 +764,9 @@ void free_platten(Platten *P) {
                     P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
+    for (hipEvent_t e : {P->ev_sim, P->ev_val})
+        if (e) (void)hipEventDestroy(e);
+    if (P->side) (void)hipStreamDestroy(P->side);
 }
 
 }  // namespace cse
