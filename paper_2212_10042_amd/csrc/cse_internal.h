@@ -74,6 +74,15 @@ struct GroupItem {
     int32_t pad[2];
 };
 
+// Per-node constants of the hierarchical posterior (90 nodes equally spaced in log s2 on
+// [log 1e-6, log 1e3]), computed once on the host: log s2, s2, 1/s2, c = 100 / (s2 + 400),
+// beta = c / s2, and lconst = log|Q|/2 + log of the inverse-gamma density of s2 + log of the
+// trapezoid weight in log s2 times s2.
+constexpr int HIER_NODES = 90;
+struct HierNode {
+    double ls2, s2, inv_s2, c, beta, lconst;
+};
+
 // Arguments of the Phase II/III kernel (device pointers owned by the platten, except the
 // outputs filled in per launch).
 struct P23Args {
@@ -91,6 +100,7 @@ struct P23Args {
     float *keys;                    // calibration keys S or NULL
     unsigned long long *stats;      // NULL or [4]: trials, Phase II / Phase III posterior looks, Newton steps
     const double *gh;               // Gauss-Hermite rule (weight e^{-x^2}): nodes [16], weights [16]
+    const HierNode *nodes;          // per-node constants of the hierarchical posterior [90]
     const uint8_t *look1;           // decision code of the first look per outcome, 51^4 entries
     double sqrt_pi, z95;            // sqrt(pi), Phi^{-1}(0.95)
 };
@@ -139,6 +149,7 @@ struct Platten {
 
     // design tables (device)
     float4 *d_h4tbl = nullptr;           // 4-arm: (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome
+    HierNode *d_hnodes = nullptr;        // per-node constants of the hierarchical posterior
     // Phase II/III design: per-tile thresholds / configurations, the work queue
     uint32_t *d_tileT = nullptr;
     int32_t *d_cfg = nullptr;

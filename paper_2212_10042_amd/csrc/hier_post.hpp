@@ -22,14 +22,35 @@
 #pragma once
 #include <math.h>
 
+#include "cse_internal.h"
 #include "fp64_math.hpp"
 
 namespace cse {
 
 constexpr int HP_NODES = 90;
 
+// Per-node constants (HierNode, cse_internal.h) are computed once on the host.
+
+// 1/d for finite d > 0: hardware reciprocal and two Newton steps (error below one ulp).
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+// expit(x), and with it softplus(x) = max(x, 0) + log1p(exp(-|x|)) from the same exponential.
 __device__ __forceinline__ double hp_expit(double x) {
-    return x >= 0.0 ? 1.0 / (1.0 + exp_cw(-x)) : 1.0 - 1.0 / (1.0 + exp_cw(x));
+    const double e = exp_cw(-fabs(x));          // in (0, 1]
+    const double r = rcp_nr(1.0 + e);           // argument in (1, 2]
+    return x >= 0.0 ? r : 1.0 - r;
+}
+__device__ __forceinline__ double hp_expit_softplus(double x, double &sp) {
+    const double e = exp_cw(-fabs(x));
+    const double r = rcp_nr(1.0 + e);
+    sp = fmax(x, 0.0) + log1p_unit(e);
+    return x >= 0.0 ? r : 1.0 - r;
 }
 
 struct HierSummary {
@@ -44,12 +65,9 @@ struct HierSummary {
 // previous node's mode (the converged mode is the same; only the path differs).  Bit i-1 of
 // `need` asks for P_i and 1 - P_i (the others are left 0).
 template <bool FULL, bool WARM>
-__device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], HierSummary &out,
-                                               int *newton_steps = nullptr, int need = 7) {
-    const double M0 = -1.34, TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
-    const double LS2_LO = -13.815510557964274, LS2_HI = 6.907755278982137;
-    const double h = (LS2_HI - LS2_LO) / (HP_NODES - 1);
-    const double lgA = lgamma(IG_A), logB = log(IG_B);
+__device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], const HierNode *__restrict__ nodes,
+                                               HierSummary &out, int *newton_steps = nullptr, int need = 7) {
+    const double M0 = -1.34;
     double th0[4];
     for (int a = 0; a < 4; ++a) th0[a] = log((y[a] + 0.5) / (n[a] - y[a] + 0.5));
     double th[4] = {th0[0], th0[1], th0[2], th0[3]};
@@ -58,11 +76,8 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
     double accP[3] = {0.0, 0.0, 0.0}, accS[3] = {0.0, 0.0, 0.0};
     double m1[4] = {0.0, 0.0, 0.0, 0.0}, m2[4] = {0.0, 0.0, 0.0, 0.0}, d2[3] = {0.0, 0.0, 0.0};
     for (int j = 0; j < HP_NODES; ++j) {
-        const double ls2 = LS2_LO + h * j;
-        const double s2 = exp(ls2);
-        const double inv_s2 = 1.0 / s2;
-        const double c = TAU2 / (s2 + 4.0 * TAU2);
-        const double beta = c * inv_s2;
+        const HierNode nd = nodes[j];   // uniform across lanes
+        const double inv_s2 = nd.inv_s2, c = nd.c, beta = nd.beta;
         if (!WARM)
             for (int a = 0; a < 4; ++a) th[a] = th0[a];
         double D[4], u[4], gam = 0.0;
@@ -75,10 +90,10 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
                 // Q (theta - m0) = ((theta_a - m0) - c sum_b (theta_b - m0)) / s2
                 g[a] = (double)y[a] - n[a] * p - ((th[a] - M0) - c * dsum) * inv_s2;
                 D[a] = n[a] * p * (1.0 - p) + inv_s2;
-                u[a] = 1.0 / D[a];
+                u[a] = rcp_nr(D[a]);
                 su += u[a];
             }
-            gam = beta / (1.0 - beta * su);
+            gam = beta * rcp_nr(1.0 - beta * su);
             double ug = 0.0;
             for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
             double mx = 0.0;
@@ -90,30 +105,25 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
             if (newton_steps) *newton_steps += 1;
             if (mx < 1e-10) break;
         }
-        // curvature at the final mode
-        double su = 0.0, logdetD = 0.0;
+        // curvature at the final mode; log|D| as the log of the product (each D_a lies in
+        // [1e-3, 1e6 + n/4], so the product of four cannot overflow)
+        double su = 0.0, prodD = 1.0, ll = 0.0, dsum = 0.0, sq = 0.0;
         for (int a = 0; a < 4; ++a) {
-            const double p = hp_expit(th[a]);
+            double sp;
+            const double p = hp_expit_softplus(th[a], sp);
             D[a] = n[a] * p * (1.0 - p) + inv_s2;
-            u[a] = 1.0 / D[a];
+            u[a] = rcp_nr(D[a]);
             su += u[a];
-            logdetD += log(D[a]);
-        }
-        gam = beta / (1.0 - beta * su);
-        const double logdet_negH = logdetD + log1p(-beta * su);
-        const double logdetQ = -(3.0 * ls2 + log(s2 + 4.0 * TAU2));
-        double ll = 0.0, dsum = 0.0, sq = 0.0;
-        for (int a = 0; a < 4; ++a) {
-            ll += y[a] * th[a] - n[a] * softplus_fast(th[a]);
+            prodD *= D[a];
+            ll += y[a] * th[a] - n[a] * sp;
             const double e = th[a] - M0;
             dsum += e;
             sq += e * e;
         }
+        gam = beta * rcp_nr(1.0 - beta * su);
+        const double logdet_negH = log(prodD) + log1p(-beta * su);
         const double quad = (sq - c * dsum * dsum) * inv_s2;
-        const double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet_negH;
-        const double logprior = IG_A * logB - lgA - (IG_A + 1.0) * ls2 - IG_B * inv_s2;
-        const double logtrap = log((j == 0 || j == HP_NODES - 1) ? 0.5 * h : h) + ls2;
-        const double lw = lap + logprior + logtrap;
+        const double lw = ll - 0.5 * quad - 0.5 * logdet_negH + nd.lconst;
         double pc[3], pr[3], vd[3];
         for (int i = 1; i < 4; ++i) {
             const double du = u[i] - u[0];

@@ -15,7 +15,8 @@
 
 namespace cse {
 
-__global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float4 *__restrict__ tbl) {
+__global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float4 *__restrict__ tbl,
+                                                     const HierNode *__restrict__ nodes) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_out) return;
     const int m = n + 1;
@@ -29,7 +30,7 @@ __global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float
     }
     const double nv[4] = {(double)n, (double)n, (double)n, (double)n};
     HierSummary s;
-    hier_posterior<false, false>(y, nv, s);
+    hier_posterior<false, false>(y, nv, nodes, s);
     float4 o;
     o.x = (float)s.Sc[0];
     o.y = (float)s.Sc[1];
@@ -38,10 +39,11 @@ __global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float
     tbl[idx] = o;
 }
 
-hipError_t launch_hier4_table(int n, float4 *tbl, hipStream_t st) {
+hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st) {
     const int64_t m = n + 1;
     const int64_t n_out = m * m * m * m;
-    hipLaunchKernelGGL(k_hier4_table, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n, n_out, tbl);
+    hipLaunchKernelGGL(k_hier4_table, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n, n_out, tbl,
+                       nodes);
     return hipGetLastError();
 }
 

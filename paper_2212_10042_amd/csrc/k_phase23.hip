@@ -87,6 +87,9 @@ __device__ __forceinline__ T pick3(const T (&v)[3], int i) {
 __device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int active, const double *gh,
                                           double sqrt_pi, double z95) {
     double pb[4] = {0.0, 0.0, 0.0, 0.0};
+    double isd[4];   // 1 / (sd * sqrt 2): Phi(z / sd) = erfc(-z isd) / 2
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) isd[kk] = rcp_nr(sqrt(2.0 * s.var[kk]));
 #pragma unroll
     for (int i = 1; i < 4; ++i) {
         const double si = sqrt(2.0 * s.var[i]);
@@ -96,7 +99,7 @@ __device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int ac
             double prod = 1.0;
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk)
-                if (kk != i) prod *= p23_Phi((t - s.mean[kk]) / sqrt(s.var[kk]));
+                if (kk != i) prod *= 0.5 * erfc(-(t - s.mean[kk]) * isd[kk]);
             acc += gh[16 + g] * prod;
         }
         pb[i] = acc / sqrt_pi;
@@ -126,6 +129,7 @@ __device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int ac
 // Decision of the first look (50 patients per arm) for every outcome y in {0..50}^4, index
 // ((y0 51 + y1) 51 + y2) 51 + y3; the trials take it from here instead of a posterior.
 __global__ __launch_bounds__(128) void k_p23_look1(int64_t n_out, uint8_t *__restrict__ tbl,
+                                                   const HierNode *__restrict__ nodes,
                                                    const double *__restrict__ gh, double sqrt_pi, double z95) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= n_out) return;
@@ -137,14 +141,14 @@ __global__ __launch_bounds__(128) void k_p23_look1(int64_t n_out, uint8_t *__res
     }
     const double n[4] = {50.0, 50.0, 50.0, 50.0};
     HierSummary s;
-    hier_posterior<true, true>(y, n, s, nullptr, 0);
+    hier_posterior<true, true>(y, n, nodes, s, nullptr, 0);
     tbl[idx] = (uint8_t)p23_phase2(s, 0, 7, gh, sqrt_pi, z95);
 }
 
 hipError_t launch_p23_look1(const Platten &P, hipStream_t st) {
     const int64_t n_out = 51LL * 51 * 51 * 51;
     hipLaunchKernelGGL(k_p23_look1, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n_out, P.d_p23look1,
-                       P.d_gh, P.p23.sqrt_pi, P.p23.z95);
+                       P.d_hnodes, P.d_gh, P.p23.sqrt_pi, P.p23.z95);
     return hipGetLastError();
 }
 
@@ -249,7 +253,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
                     int wneed = 0;
 #pragma unroll
                     for (int i = 0; i < 3; ++i) wneed |= __ballot((mine >> i) & 1) ? (1 << i) : 0;
-                    hier_posterior<true, true>(y, nd, s, &c_newton, __builtin_amdgcn_readfirstlane(wneed));
+                    hier_posterior<true, true>(y, nd, A.nodes, s, &c_newton, __builtin_amdgcn_readfirstlane(wneed));
                 }
                 if (look < 3) c_look2 += 1; else c_look3 += 1;
                 if (look < 3) {

@@ -152,6 +152,28 @@ void gauss_hermite16(double *x, double *w) {
     }
 }
 
+// Node constants of the hierarchical posterior (Section 10.1 model: mu ~ N(-1.34, 100) integrated
+// out, s2 ~ InvGamma(0.0005, 0.000005), trapezoid rule in log s2 with ds2 = s2 dlog s2).
+std::vector<HierNode> hier_nodes() {
+    const double TAU2 = 100.0, IG_A = 0.0005, IG_B = 0.000005;
+    const double LS2_LO = log(1e-6), LS2_HI = log(1e3);
+    const double h = (LS2_HI - LS2_LO) / (HIER_NODES - 1);
+    std::vector<HierNode> v(HIER_NODES);
+    for (int j = 0; j < HIER_NODES; ++j) {
+        HierNode &nd = v[j];
+        nd.ls2 = LS2_LO + h * j;
+        nd.s2 = exp(nd.ls2);
+        nd.inv_s2 = 1.0 / nd.s2;
+        nd.c = TAU2 / (nd.s2 + 4.0 * TAU2);
+        nd.beta = nd.c * nd.inv_s2;
+        const double logdetQ = -(3.0 * nd.ls2 + log(nd.s2 + 4.0 * TAU2));   // determinant lemma
+        const double logprior = IG_A * log(IG_B) - lgamma(IG_A) - (IG_A + 1.0) * nd.ls2 - IG_B * nd.inv_s2;
+        const double logtrap = log((j == 0 || j == HIER_NODES - 1) ? 0.5 * h : h) + nd.ls2;
+        nd.lconst = 0.5 * logdetQ + logprior + logtrap;
+    }
+    return v;
+}
+
 // Phi^{-1}(0.95) by Newton's method on Phi(z) = erfc(-z / sqrt 2) / 2.
 double normal_q95() {
     double z = 1.6;
@@ -483,11 +505,13 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         if (int e = upload((Blk4 **)&P->d_blocks, blks.data(), blks.size())) return e;
 
         // posterior table of the design (once per platten)
+        const std::vector<HierNode> nodes = hier_nodes();
+        if (int e = upload(&P->d_hnodes, nodes.data(), nodes.size())) return e;
         const int64_t m = P->n_per_arm + 1;
         P->h4_outcomes = m * m * m * m;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_h4tbl, (size_t)P->h4_outcomes * sizeof(float4)));
         const auto t0 = std::chrono::steady_clock::now();
-        CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, nullptr));
+        CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, P->d_hnodes, nullptr));
         CSE_HIP_TRY(hipDeviceSynchronize());
         P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } else if (kind == CSE_PHASE23) {
@@ -511,6 +535,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         gauss_hermite16(gh, gh + 16);
         if (int e = upload(&P->d_gh, gh, 32)) return e;
         A.gh = P->d_gh;
+        const std::vector<HierNode> nodes = hier_nodes();
+        if (int e = upload(&P->d_hnodes, nodes.data(), nodes.size())) return e;
+        A.nodes = P->d_hnodes;
         A.sqrt_pi = sqrt(M_PI);
         A.z95 = normal_q95();
         // decisions of the first look (50 patients per arm) for every outcome, once per platten
@@ -761,7 +788,7 @@ void free_platten(Platten *P) {
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
-                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1};
+                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : {P->ev_sim, P->ev_val})

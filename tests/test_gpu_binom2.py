@@ -224,3 +224,56 @@ def test_paper_worked_value_through_gpu_bound():
     L = -math.log(f0)
     assert float(_np(b)[0]) == pytest.approx(math.exp(-(math.sqrt(L) - 0.25 / math.sqrt(2)) ** 2), rel=1e-10)
     P.close()
+
+
+def test_full_c3_forward_gradient_sampled_and_fd():
+    """All 1024^2 boxes on [-3,1]^2 with 16,384 sims (the 2^20-tile forward + gradient launch):
+    R, score sums, gradient and bound vs the oracle on sampled tiles; the score gradient vs
+    central differences under common random numbers (h = 1e-3) on every 256th tile."""
+    w = W.binom2_1024_full()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("binom2", th, rd, sm, keep_all=True)
+    n = P.n_tiles
+    assert n == 1 << 20
+    g = P.validate(w["seed"], delta=w["delta"])
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(3)
+    idx = np.unique(np.concatenate([[0, n - 1, n // 2], rng.choice(n, 24, replace=False)]))
+    print(f"[binom2] 2^20-tile launch, {idx.size} sampled tiles", flush=True)
+    sub = W.subsample(w, idx)
+    ov = O.validate("binom2", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["delta"], keep_all=True)
+    assert np.array_equal(_np(g["reject"])[idx], ov["R"])
+    assert np.array_equal(_np(g["score_T"])[idx], ov["score_box"])
+    go = O.score_gradient("binom2", sub["theta"], ov["R"], ov["score_box"], sub["sims"])
+    np.testing.assert_allclose(_np(g["grad"])[idx], go, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(_np(g["tile_bound"])[idx], ov["bound"], rtol=RTOL_BOUND)
+    P.close()
+    # central differences on every 256th tile, same seed (common random numbers)
+    sel = np.arange(0, n, 256)
+    h = 1e-3
+    pts = th[sel]
+    rows = [pts]
+    for a in range(2):
+        for sgn in (1, -1):
+            q = pts.copy()
+            q[:, a] += sgn * h
+            rows.append(q)
+    allp = np.concatenate(rows)
+    N = int(sm[0])
+    Q = cse.Platten.create("binom2", allp, np.full_like(allp, rd[0, 0]), np.full(allp.shape[0], N, np.int32),
+                           keep_all=True)
+    o = Q.simulate(w["seed"])
+    torch.cuda.synchronize()
+    f = _np(o["reject"]).astype(np.float64) / N
+    m = sel.size
+    gs = _np(g["grad"])[sel]
+    for a in range(2):
+        fd = (f[m * (1 + 2 * a): m * (2 + 2 * a)] - f[m * (2 + 2 * a): m * (3 + 2 * a)]) / (2 * h)
+        flips = np.abs(fd) * N * 2 * h + 1.0
+        tol = 5 * (35 / math.sqrt(N)) + 5 * np.sqrt(flips) / (N * 2 * h)
+        d = fd - gs[:, a]
+        assert np.all(np.abs(d) <= tol)
+        z = d.mean() / (d.std(ddof=1) / math.sqrt(m))
+        print(f"[binom2] FD vs score, arm {a}: mean diff {d.mean():.2e}, z {z:.2f} over {m} tiles", flush=True)
+        assert abs(z) < 5
+    Q.close()
