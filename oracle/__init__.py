@@ -331,6 +331,38 @@ def tile_inverse(family, theta0, V, alpha, n=N_PER_ARM):
     return np.exp(w), 1.0 + np.exp(s)
 
 
+def curvature_bound(family, theta0, radii, n=N_PER_ARM):
+    """h_a = sup over the box |theta - theta0| <= r of d^2 A / d theta_a^2: 1 for the normal
+    location family, n p(1 - p) at the point of [theta0_a - r_a, theta0_a + r_a] nearest 0 for
+    independent binomial arms.  Bounds v' Hess f v by v' Hess A v (reading of Section 4.3's
+    f'' <= 1, see taylor_bound)."""
+    theta0 = np.asarray(theta0, np.float64)
+    r = np.asarray(radii, np.float64)
+    if family == "normal":
+        return np.ones_like(theta0)
+    lo, hi = theta0 - r, theta0 + r
+    x = np.where((lo <= 0.0) & (hi >= 0.0), 0.0, np.where(hi < 0.0, hi, lo))
+    p = sps.expit(x)
+    return n * p * (1.0 - p)
+
+
+def taylor_bound(family, theta0, radii, V, f, g, n=N_PER_ARM):
+    """Second-order Taylor comparison bound over each tile (Section 4.3):
+    f(theta0 + v) <= f + g . v + (1/2) sum_a h_a v_a^2 with h = curvature_bound (the remainder
+    v' Hess f(xi) v is at most v' Hess A(xi) v for a rejection probability in an exponential
+    family).  The right side is convex in v, so its maximum over the tile is at a vertex.
+    V [m, nv, d] vertex displacements (NaN rows ignored).  Returns (bound clipped to 1, index of
+    the maximising vertex)."""
+    theta0 = np.asarray(theta0, np.float64)
+    V = np.asarray(V, np.float64)
+    h = curvature_bound(family, theta0, radii, n)
+    val = (np.asarray(f, np.float64)[:, None] + np.einsum("mvd,md->mv", V, np.asarray(g, np.float64))
+           + 0.5 * np.einsum("mvd,md->mv", V * V, h))
+    val = np.where(np.isnan(val), -np.inf, val)
+    j = np.argmax(val, axis=1)
+    return np.minimum(val[np.arange(len(j)), j], 1.0), j
+
+
 def cp_upper(R, N, delta):
     """Clopper-Pearson (1-delta) upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 5.1); 1 when R == N."""
     R = np.asarray(R, np.float64)
