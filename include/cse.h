@@ -191,6 +191,28 @@ int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double
               double delta_or_alpha, double *out, double *q_star, void *stream);
 
 /*
+ * cse_taylor -- the second-order Taylor comparison bound of Section 4.3 over each tile, and the
+ * gradient-guided worst-case candidate point of the tile.
+ *   f      float64 [n_tiles]    f(theta_i) to expand from (the exact value for a comparison,
+ *                               or an upper confidence bound such as cp_upper in practice)
+ *   grad   float64 [n_tiles][d] the gradient at theta_i (exact, or the score estimate of
+ *                               cse_simulate / cse_validate)
+ *   bound  float64 [n_tiles]    max over the tile's vertices v of
+ *                               f + grad.v + (1/2) sum_a h_a v_a^2, clipped to 1, where h_a is
+ *                               the supremum over the tile's box of d^2 A / d theta_a^2 (1 for
+ *                               the z-test, n p (1 - p) for a binomial arm), which bounds the
+ *                               remainder of a rejection probability in the exponential family
+ *                               (the paper's f'' <= 1 for the z-test)
+ *   vertex int32 [n_tiles] or NULL: index of the maximising vertex (first on ties; vertex order
+ *                               as in cse_platten_describe's enumeration)
+ *   point  float64 [n_tiles][d] or NULL: that vertex, theta_i + v (the worst-case candidate)
+ * The bound is convex in v, so its maximum over the convex tile is attained at a vertex.
+ * Errors: CSE_EINVAL (NULL f, grad or bound), CSE_EHIP.
+ */
+int cse_taylor(const cse_platten *p, const double *f, const double *grad, double *bound, int32_t *vertex,
+               double *point, void *stream);
+
+/*
  * Plans: one validation or calibration step captured once into a HIP graph and replayed.
  * The step is exactly the launches of cse_validate / cse_calibrate with the same arguments
  * (Algorithms 1 and 2: alpha' -> simulation -> selection -> reductions -> bound); every

@@ -30,7 +30,8 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_simulate", "cse_validate", "cse_calibrate", "cse_bound", "cse_simulate_per_tile",
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
-            "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_last_error")
+            "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
+            "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -72,6 +73,7 @@ def _load():
     L.cse_plan_nodes.restype = i64
     L.cse_plan_destroy.argtypes = [P]
     L.cse_autotune.argtypes = [P, u64, i64, P, P]
+    L.cse_taylor.argtypes = [P, P, P, P, P, P, P]
     L.cse_profile_enable.argtypes = [i32]
     L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.cse_profile_reset.argtypes = []
@@ -214,6 +216,11 @@ def cse_plan_destroy(plan):
     _check("cse_plan_destroy", _L.cse_plan_destroy(plan))
 
 
+def cse_taylor(h, f, grad, bound, vertex=None, point=None, stream=None):
+    _check("cse_taylor", _L.cse_taylor(h, _ptr(f), _ptr(grad), _ptr(bound), _ptr(vertex), _ptr(point),
+                                       _stream(stream)))
+
+
 def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):
     """Pick the fused kernel's launch shape on this device; returns (value, grid)."""
     out = np.zeros(2, np.int64)
@@ -332,6 +339,15 @@ class Platten:
                       o["reject_at_lambda"], delta, o.get("reject"), o.get("score_T"), o.get("score_Z"),
                       o.get("grad"), o.get("cp_upper"), o.get("tile_bound"))
         return o
+
+    def taylor(self, f, grad, device="cuda"):
+        """Taylor comparison bound over each tile and its worst-case candidate vertex (Section 4.3)."""
+        n = self.n_tiles
+        out = dict(bound=torch.empty(n, dtype=torch.float64, device=device),
+                   vertex=torch.empty(n, dtype=torch.int32, device=device),
+                   point=torch.empty((n, self.d), dtype=torch.float64, device=device))
+        cse_taylor(self.handle, f, grad, out["bound"], out["vertex"], out["point"])
+        return out
 
     def bound(self, mode, R=None, a=None, level=0.01, device="cuda"):
         out = torch.empty(self.n_tiles, dtype=torch.float64, device=device)

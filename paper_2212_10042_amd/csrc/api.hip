@@ -573,6 +573,19 @@ int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double
     return CSE_OK;
 }
 
+int cse_taylor(const cse_platten *p, const double *f, const double *grad, double *bound, int32_t *vertex,
+               double *point, void *stream) {
+    if (int e = check_handle(p, "cse_taylor")) return e;
+    if (!f || !grad || !bound) {
+        set_error("cse_taylor: f, grad and bound must not be NULL");
+        return CSE_EINVAL;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    Timed tm("taylor", st);
+    CSE_LAUNCH(cse::launch_taylor(p->P, f, grad, bound, vertex, point, st));
+    return CSE_OK;
+}
+
 int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begin, int64_t tile_end,
                           int32_t *reject, void *stream) {
     if (int e = check_handle(p, "cse_simulate_per_tile")) return e;

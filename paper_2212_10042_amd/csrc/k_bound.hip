@@ -281,6 +281,74 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
 }
 
 
+// ---- Taylor comparison bound (Section 4.3) and the gradient-guided worst vertex ----
+// Per tile: h_a = sup over the box of d^2 A / d theta_a^2 (1 for the normal family; for a
+// binomial arm n p (1 - p) at the point of [theta_a - r_a, theta_a + r_a] nearest 0), which
+// bounds the second-order remainder of a rejection probability in the exponential family;
+// the bound f + g.v + (1/2) sum_a h_a v_a^2 is convex in v, so its maximum over the tile is at
+// a vertex: that vertex (first on ties) is also the tile's worst-case candidate point.
+template <int FAM, int D>
+__global__ void k_taylor(int n, int64_t n_tiles, const double *__restrict__ theta,
+                         const double *__restrict__ radii, const int32_t *__restrict__ vert_off,
+                         const double *__restrict__ verts, const double *__restrict__ f,
+                         const double *__restrict__ g, double *__restrict__ bound,
+                         int32_t *__restrict__ vertex, double *__restrict__ point) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    double th[D], h[D], gg[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        th[a] = theta[t * D + a];
+        gg[a] = g[t * D + a];
+        if (FAM == FAM_NORMAL) {
+            h[a] = 1.0;
+        } else {
+            const double r = radii[t * D + a], lo = th[a] - r, hi = th[a] + r;
+            const double x = (lo <= 0.0 && hi >= 0.0) ? 0.0 : (hi < 0.0 ? hi : lo);
+            const double p = 1.0 / (1.0 + exp(-x));
+            h[a] = (double)n * p * (1.0 - p);
+        }
+    }
+    const int32_t v0 = vert_off[t], nv = vert_off[t + 1] - v0;
+    double best = -INFINITY;
+    int jb = 0;
+    for (int j = 0; j < nv; ++j) {
+        double val = f[t];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double v = verts[(int64_t)(v0 + j) * D + a];
+            val += gg[a] * v + 0.5 * h[a] * v * v;
+        }
+        if (val > best) {
+            best = val;
+            jb = j;
+        }
+    }
+    bound[t] = fmin(best, 1.0);
+    if (vertex) vertex[t] = jb;
+    if (point)
+#pragma unroll
+        for (int a = 0; a < D; ++a) point[t * D + a] = th[a] + verts[(int64_t)(v0 + jb) * D + a];
+}
+
+hipError_t launch_taylor(const Platten &P, const double *f, const double *g, double *bound, int32_t *vertex,
+                         double *point, hipStream_t st) {
+    const dim3 grid((uint32_t)((P.n_tiles + 255) / 256));
+#define CSE_TAYLOR_LAUNCH(FAM, D)                                                                         \
+    hipLaunchKernelGGL((k_taylor<FAM, D>), grid, dim3(256), 0, st, P.n_per_arm, P.n_tiles, P.d_theta, P.d_radii, \
+                       P.d_vert_off, P.d_verts, f, g, bound, vertex, point)
+    if (P.family == FAM_NORMAL && P.d == 1)
+        CSE_TAYLOR_LAUNCH(FAM_NORMAL, 1);
+    else if (P.family == FAM_BINOM && P.d == 2)
+        CSE_TAYLOR_LAUNCH(FAM_BINOM, 2);
+    else if (P.family == FAM_BINOM && P.d == 4)
+        CSE_TAYLOR_LAUNCH(FAM_BINOM, 4);
+    else
+        return hipErrorInvalidValue;
+#undef CSE_TAYLOR_LAUNCH
+    return hipGetLastError();
+}
+
 // Clopper-Pearson once per (N class, R) present in this call: mark, then solve marked entries.
 __global__ void k_cp_mark(int64_t n_tiles, const uint32_t *__restrict__ R, const int32_t *__restrict__ N,
                           const int64_t *__restrict__ cp_base, uint32_t *__restrict__ mark) {

@@ -20,6 +20,8 @@ hipError_t launch_finish(const Platten &P, const uint32_t *R, const unsigned lon
                          const unsigned long long *sumZfx, int32_t *R_out, int64_t *T_out,
                          double *Z_out, double *grad, hipStream_t st);
 hipError_t launch_zero(void *p, size_t bytes, hipStream_t st);
+hipError_t launch_taylor(const Platten &P, const double *f, const double *g, double *bound, int32_t *vertex,
+                         double *point, hipStream_t st);
 hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st);
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st);
 hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
