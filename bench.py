@@ -43,13 +43,13 @@ B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 
 H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
 
 #   Phase II/III: float64 lane-ops of one posterior look (hier_post.hpp), counted by operation
-#   (exp 22, log 30, erfc 50, division 10, sqrt 10, log1p series 25): per node 826 outside
-#   Newton and the normal tails, 261 per Newton step, 125 per arm whose tails a look needs;
-#   per Phase II look p_best 10,700 + p_success 500 (no tails); per Phase III look the
-#   selected arm's tails and one p_success (500).  The first look of a trial is a table
-#   lookup (no posterior).  Looks and Newton steps are the kernel's own counters for the
-#   launch (cse_work_counters).
-P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 826, 261, 125, 11200, 500
+#   (exp 20, log 30, log1p series 22, erfc 40, reciprocal 5, sqrt 10; the per-node constants
+#   come from a table): per node 400 outside Newton and the normal tails, 200 per Newton step,
+#   104 per arm whose tails a look needs (two erfc); per Phase II look p_best 6,500 + p_success
+#   300 (no tails); per Phase III look one p_success (100) and the selected arm's tails.  The
+#   first look of a trial is a table lookup (no posterior).  Looks and Newton steps are the
+#   kernel's own counters for the launch (cse_work_counters).
+P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800, 100
 
 # HBM bytes per dispatch of k_binom2<true> on binom2_256_tri, from the FETCH_SIZE / WRITE_SIZE
 # counter runs in profiles/binom2_256_tri_hbm_counters.md (scaled by a 256 MiB copy).  Valid
@@ -226,6 +226,20 @@ def main():
     value = total / dt
     ms_step = dt / args.steps * 1e3
 
+    # the Taylor comparison bound and worst-case vertex (Section 4.3) from this step's outputs,
+    # timed on its own (not part of the step)
+    taylor = None
+    if "grad" in o and o["grad"] is not None:
+        cse.cse_profile_reset()
+        cse.cse_profile_enable(True)
+        for _ in range(5):
+            to = P.taylor(o["cp"], o["grad"])
+        torch.cuda.synchronize()
+        cse.cse_profile_enable(False)
+        cnt, ms = cse.cse_profile_get("taylor")
+        taylor = {"kernel_ms": ms / max(cnt, 1), "max_bound": float(to["bound"].max().item()),
+                  "max_tilt_bound": float(o["bound"].max().item())}
+
     # the same step captured once as a HIP graph and replayed (outputs checked against eager)
     graph = None
     if not args.no_graph:
@@ -320,6 +334,7 @@ def main():
         "plain_fwd_per_tile": plain,
         "kernel_avg_ms": kern,
         "graph_replay": graph,
+        "taylor": taylor,
         "autotune": tune,
         "launch_shape": cse.cse_platten_stats(P.handle)["launch_shape"],
         "platten_build_ms": platten_ms,
