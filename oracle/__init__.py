@@ -374,6 +374,24 @@ def cp_upper(R, N, delta):
     return out
 
 
+def cp_lower(R, N, delta):
+    """Clopper-Pearson (1-delta) lower bound Beta^{-1}(delta; R, N-R+1) (Section 5.1); 0 when R == 0."""
+    R = np.asarray(R, np.float64)
+    N = np.asarray(N, np.float64)
+    out = np.zeros(np.broadcast(R, N).shape)
+    ok = R > 0
+    out[ok] = sps.betaincinv(R[ok] if R.ndim else R, (N - R + 1.0)[ok] if N.ndim else N - R + 1.0, delta)
+    return out
+
+
+def tile_lower(family, theta0, V, b, n=N_PER_ARM):
+    """Lower Tilt-Bound over each tile (Remark 2 applied to 1 - F): with b <= f(theta0),
+    f(theta0 + v) >= 1 - U(theta0, v, q, 1 - b) for every q, so over the tile
+    f >= 1 - inf_q max_v U(theta0, v, q, 1 - b).  Returns (lower bound, q_star)."""
+    ub, q = tile_bound(family, theta0, V, 1.0 - np.asarray(b, np.float64), n)
+    return 1.0 - ub, q
+
+
 # ------------------------------------------------------------- the platten
 def hypotheses(design: str, d: int):
     """Null hypotheses as half-spaces g . theta <= h (Section 4):
@@ -526,8 +544,10 @@ def validate(design: str, theta, radii, sims, seed: int, delta: float, cut: floa
     cp = cp_upper(Rb, N, delta)
     V = _pad_vertices(subs, theta)
     ub, qs = tile_bound(family_of(design), theta[box], V, cp, n=n_of(design))
+    cpl = cp_lower(Rb, N, delta)
+    lb, _ = tile_lower(family_of(design), theta[box], V, cpl, n=n_of(design))
     out = dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
-               q=qs, score=score, subs=subs)
+               q=qs, score=score, subs=subs, cp_lower=cpl, lower=lb)
     if design not in ("hier4", "phase23"):
         R, sc, _ = simulate(design, theta, sims, seed, cut)
         out.update(R_box=R, score_box=sc)

@@ -203,3 +203,51 @@ def test_subtiles_hier4_partition_by_sampling():
         b = ((x[:, 1] <= x[:, 0]) * 1 + (x[:, 2] <= x[:, 0]) * 2 + (x[:, 3] <= x[:, 0]) * 4)
         seen = set(np.unique(b[b > 0]).tolist())
         assert seen == by_box.get(i, set())
+
+
+# ------------------------------------------------------------- lower bounds (Remark 2)
+def test_cp_lower_scipy_and_symmetry():
+    from scipy import special
+    N = np.array([10, 100, 10000, 10000, 37])
+    R = np.array([3, 0, 250, 10000, 37])
+    lo = O.cp_lower(R, N, 0.01)
+    assert lo[1] == 0.0
+    ok = R > 0
+    np.testing.assert_allclose(lo[ok], special.betaincinv(R[ok], N[ok] - R[ok] + 1, 0.01), rtol=1e-12)
+    # lower bound of p from R successes = 1 - upper bound of 1 - p from N - R successes
+    np.testing.assert_allclose(lo, 1.0 - O.cp_upper(N - R, N, 0.01), rtol=0, atol=1e-12)
+    # R = N: Beta(N, 1) quantile = delta^(1/N)
+    assert lo[3] == pytest.approx(0.01 ** (1 / 10000), rel=1e-12)
+
+
+@pytest.mark.parametrize("r", [1 / 128, 0.05, 0.25])
+def test_lower_tilt_bound_under_exact_power(r):
+    """With the exact f(theta0), the tilewise lower bound is below the exact z-test power at
+    every point of the tile (zero exceptions)."""
+    from scipy import stats
+    th0 = np.linspace(-1.0, 0.5, 31)[:, None]
+    V = np.stack([np.full((31, 1), -r), np.full((31, 1), r)], axis=1)
+    f0 = stats.norm.cdf(th0[:, 0] - 1.96)
+    lb, _ = O.tile_lower("normal", th0, V, f0)
+    assert np.all(lb <= f0 + 1e-15)
+    for i in range(31):
+        x = np.linspace(th0[i, 0] - r, th0[i, 0] + r, 401)
+        assert np.all(stats.norm.cdf(x - 1.96) >= lb[i] - 1e-15)
+
+
+def test_lower_tilt_bound_two_arm_exact():
+    """2-arm pooled z design, exact TIE by enumeration: lower bound below the exact TIE at
+    vertices and interior points of boxes and diagonal triangles."""
+    from test_oracle_taylor import _binom2_exact
+    theta = np.array([[-0.5, -0.5], [0.3, -0.2], [-1.2, -1.6]])
+    radii = np.full((3, 2), 0.1)
+    subs = O.subtiles("binom2", theta, radii)
+    box = np.array([s[0] for s in subs])
+    f0 = np.array([_binom2_exact(t)[0] for t in theta[box]])
+    lb, _ = O.tile_lower("binom", theta[box], O._pad_vertices(subs, theta), f0)
+    rng = np.random.default_rng(1)
+    for t, (i, b, verts, _) in enumerate(subs):
+        pts = list(verts) + [rng.dirichlet(np.ones(len(verts))) @ verts for _ in range(20)]
+        for x in pts:
+            assert _binom2_exact(x)[0] >= lb[t] - 1e-12
+        assert lb[t] <= f0[t]
