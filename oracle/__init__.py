@@ -70,6 +70,7 @@ def lib():
         L.orc_pbest.argtypes = [P, P, P]
         L.orc_psucc.argtypes = [dbl, dbl, dbl, dbl, ctypes.c_int]
         L.orc_psucc.restype = dbl
+        L.orc_tiebreak_u.argtypes = [u64, i64, P]
         L.orc_phase23_sim.argtypes = [i64, P, P, P, u64, dbl, P, P, P, P, i64, P, P]
         _lib = L
     return _lib
@@ -561,6 +562,26 @@ def order_statistic(S_row: np.ndarray, k: int) -> float:
     return float(np.sort(S_row)[k - 1])
 
 
+def tiebreak_u(seed: int, n: int) -> np.ndarray:
+    """The uniform adjoined to each simulation by the randomised test (discussion of Theorem
+    (pointwise calibration), Section 6.1): u_k = first word of Philox4x32-10 at counter
+    (0, k, 1, 0) with the seed as key, as an integer in [0, 2^32); P(u < c) = c / 2^32.  It is
+    disjoint from the data words (counter word 2 = 0) and shared by all tiles."""
+    out = np.zeros(max(int(n), 0), np.uint32)
+    if n > 0:
+        lib().orc_tiebreak_u(seed, int(n), _p(out))
+    return out
+
+
+def order_statistic_pair(S_row: np.ndarray, u_row: np.ndarray, k: int):
+    """k-th smallest pair (S, u) in lexicographic order (1-based); (-inf, 0) when k == 0."""
+    if k <= 0:
+        return -math.inf, 0
+    idx = np.lexsort((u_row, S_row))   # primary key S, secondary u
+    j = idx[k - 1]
+    return float(S_row[j]), int(u_row[j])
+
+
 def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False,
               key_dtype=np.float64, cut: float = 1.96):
     """Calibration (Algorithm 2): alpha'_i, k_i = floor((N_i+1) alpha'_i), lambda*_i = S_(k_i),
@@ -585,3 +606,74 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
     return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, q=qs, k=k,
                 lam=lam, lam_global=float(lam.min()) if len(lam) else math.inf,
                 reject_at_lam=rej, N=N, subs=subs)
+
+
+def calibrate_tiebreak(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False,
+                       key_dtype=np.float64, cut: float = 1.96):
+    """Randomised calibration: the statistic becomes the pair (S, u) with u from tiebreak_u and
+    the threshold the pair (lambda, c), both compared lexicographically.  Per tile: alpha'_i and
+    k_i as in calibrate, (lambda_i, c_i) = the k_i-th smallest pair, and the number of pairs
+    strictly below it; globally the lexicographic minimum of (lambda_i, c_i)."""
+    theta = np.asarray(theta, np.float64)
+    sims = np.asarray(sims, np.int32)
+    subs = subtiles(design, theta, radii, keep_all)
+    box = np.array([s[0] for s in subs])
+    V = _pad_vertices(subs, theta)
+    ap, _ = tile_inverse(family_of(design), theta[box], V, alpha, n=n_of(design))
+    N = sims[box]
+    k = np.floor((N + 1.0) * ap).astype(np.int64)
+    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True)
+    u = tiebreak_u(seed, int(N.max()) if len(N) else 0)
+    lam = np.empty(len(subs))
+    c = np.zeros(len(subs), np.int64)
+    rej = np.zeros(len(subs), np.int64)
+    for t in range(len(subs)):
+        row = S[t, : N[t]].astype(key_dtype)
+        ur = u[: N[t]]
+        lam[t], c[t] = order_statistic_pair(row, ur, int(k[t]))
+        if k[t] > 0:
+            L = key_dtype(lam[t])
+            rej[t] = int(np.sum(row < L) + np.sum((row == L) & (ur < c[t])))
+    g = int(np.lexsort((c, lam))[0]) if len(lam) else 0
+    return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, k=k, lam=lam, c=c,
+                reject_at=rej, lam_global=float(lam[g]) if len(lam) else math.inf,
+                c_global=int(c[g]) if len(lam) else 0, N=N, subs=subs)
+
+
+# ---------------------------------------------------- confidence sets (Section 7)
+def estimand_range(subs, coef, link: str = "linear"):
+    """Range of e over each tile (Section 7's image of a tile under e):
+    e(theta) = c0 + sum_a c_a g(theta_a), coef = (c_1 .. c_d, c0), g the identity ("linear")
+    or expit ("expit", e.g. p_1 - p_0).  Linear: min / max over the tile's vertices (exact on a
+    polytope).  Expit: the sum over coordinates of the extremes of c_a expit(theta_a) over the
+    tile's bounding box (exact on a box, an enclosing interval on a clipped tile)."""
+    coef = np.asarray(coef, np.float64)
+    c, c0 = coef[:-1], coef[-1]
+    lo = np.empty(len(subs))
+    hi = np.empty(len(subs))
+    for t, s in enumerate(subs):
+        V = np.asarray(s[2], np.float64)
+        if link == "linear":
+            vals = V @ c + c0
+            lo[t], hi[t] = vals.min(), vals.max()
+        elif link == "expit":
+            a = c * sps.expit(V.min(axis=0))
+            b = c * sps.expit(V.max(axis=0))
+            lo[t] = c0 + np.minimum(a, b).sum()
+            hi[t] = c0 + np.maximum(a, b).sum()
+        else:
+            raise ValueError(link)
+    return lo, hi
+
+
+def confidence_set(subs, lam, s_obs, coef, link: str = "linear"):
+    """Section 7: with the observed statistic s_i of each tile and its calibrated threshold
+    lambda_i, the confidence region is the union of the tiles not rejected, s_i >= lambda_i
+    (the test rejects when s_i < lambda_i; compared in float32, the statistic's precision),
+    and the confidence set of e is the image of that region: returns (keep mask, per-tile
+    range (lo, hi), (min lo, max hi) over kept tiles, or (+inf, -inf) when none is kept)."""
+    s32 = np.broadcast_to(np.asarray(s_obs, np.float32), (len(subs),))
+    keep = ~(s32 < np.asarray(lam, np.float64).astype(np.float32))
+    lo, hi = estimand_range(subs, coef, link)
+    rng = (float(lo[keep].min()), float(hi[keep].max())) if keep.any() else (math.inf, -math.inf)
+    return keep, lo, hi, rng

@@ -64,6 +64,19 @@ uint32_t orc_word(uint64_t seed, uint32_t sim, uint32_t w) {
     return out[w % 4u];
 }
 
+/* Adjoined uniform of the randomised test: first word of the block at counter (0, sim, 1, 0).
+ * Data words use counter word 2 = 0, so this stream is disjoint from them, and like them it does
+ * not depend on the tile (common random numbers). */
+void orc_tiebreak_u(uint64_t seed, int64_t n, uint32_t *out) {
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int64_t k = 0; k < n; ++k) {
+        uint32_t ctr[4] = {0u, (uint32_t)k, 1u, 0u};
+        uint32_t o[4];
+        orc_philox4x32_10(ctr, key, o);
+        out[k] = o[0];
+    }
+}
+
 /* ------------------------------------------------------- draw conventions */
 
 uint32_t orc_bern_threshold(double theta) {
