@@ -213,6 +213,69 @@ int cse_taylor(const cse_platten *p, const double *f, const double *grad, double
                double *point, void *stream);
 
 /*
+ * cse_validate_lower -- the lower side of a two-sided validation band (Remark 2, Section 4: the
+ * Tilt-Bound applied to 1 - F gives f(theta0 + v) >= 1 - U(theta0, v, q, 1 - f(theta0))).
+ *   R        int32 [n_tiles] device rejection counts of this platten's tiles (the `reject`
+ *                            output of cse_simulate / cse_validate / cse_calibrate)
+ *   cp_lower float64 [n_tiles] or NULL: Clopper-Pearson (1-delta) lower bound
+ *                            Beta^{-1}(delta; R, N - R + 1) at theta_i (0 when R = 0), computed
+ *                            as 1 - cp_upper(N - R) (Section 5.1)
+ *   lower    float64 [n_tiles] 1 - inf_q max_v U(theta_i, v, q, 1 - cp_lower_i): with
+ *                            probability >= 1 - delta, f >= lower on the whole tile
+ *                            (with cse_validate's tile_bound: a band at level 1 - 2 delta)
+ *   q_star   float64 [n_tiles] or NULL: the optimising Holder exponent.
+ * Errors: CSE_EINVAL (NULL R or lower, delta outside (0,1)), CSE_EHIP.
+ */
+int cse_validate_lower(const cse_platten *p, const int32_t *R, double delta, double *cp_lower, double *lower,
+                       double *q_star, void *stream);
+
+/*
+ * cse_confidence_set -- confidence set from a calibration (Section 7).  Each tile's test
+ * rejects the observed statistic when s_i < lambda_i; the confidence region is the union of
+ * the tiles it does not reject, and the confidence set of an estimand e(theta) is the image of
+ * that region.
+ *   s_obs       float64 device, the observed statistic: [n_tiles] (s_stride 1) or one value
+ *               for every tile (s_stride 0).  Compared in the precision of the design's
+ *               simulated statistic: float64 for CSE_BINOM2_Z, float32 otherwise.
+ *   lambda_tile float64 [n_tiles] device, the tiles' calibrated thresholds (cse_calibrate's
+ *               lambda_tile at the chosen alpha; -inf keeps a tile whatever s is)
+ *   coef        float64 [d + 1] HOST: e(theta) = coef[d] + sum_a coef[a] g(theta_a)
+ *   link        0: g = identity (range over the tile = min / max over its vertices, exact);
+ *               1: g = expit, e.g. p_1 - p_0 (each term's extremes over the tile's bounding
+ *               box: exact on a box, an enclosing interval on a clipped tile)
+ *   keep        int32 [n_tiles]   1 when the tile is in the confidence region
+ *   e_lo, e_hi  float64 [n_tiles] range of e over each tile (kept or not)
+ *   e_range     float64 [2] device: (min e_lo, max e_hi) over kept tiles; (+inf, -inf) when
+ *               no tile is kept.
+ * Coverage is that of the calibration (>= 1 - alpha); for a two-sided interval intersect an
+ * upper and a lower one, each at level alpha / 2.
+ * Errors: CSE_EINVAL (NULL pointers, link or s_stride out of range, non-finite coef), CSE_EHIP.
+ */
+int cse_confidence_set(const cse_platten *p, const double *s_obs, int64_t s_stride, const double *lambda_tile,
+                       const double *coef, int32_t link, int32_t *keep, double *e_lo, double *e_hi,
+                       double *e_range, void *stream);
+
+/*
+ * cse_calibrate_tiebreak -- randomised calibration (the adjoined uniform discussed with
+ * Theorem (pointwise calibration), Section 6.1): every simulation k also draws
+ * u_k = first word of Philox4x32-10(key = seed, counter = (0, k, 1, 0)) (shared by all tiles,
+ * disjoint from the data words), the statistic is the pair (S, u) and the threshold the pair
+ * (lambda, c), both ordered lexicographically; a new observation (s, u) is rejected when
+ * s < lambda, or s == lambda and u < c.  This removes the discreteness term of the
+ * calibration's mean and variance.
+ *   alpha_prime, k  as cse_calibrate (k may be NULL, alpha_prime may be NULL)
+ *   lambda_tile     float64 [n_tiles], u_tile uint32 [n_tiles]: the k_i-th smallest pair
+ *                   ((-inf, 0) when k_i = 0)
+ *   lambda_global   float64 [1], u_global uint32 [1]: the lexicographic minimum over tiles
+ *   reject_at_lambda int32 [n_tiles]: pairs strictly below (lambda_i, c_i) (k_i - 1 when the
+ *                   tied simulations' u are distinct)
+ * Errors: CSE_EINVAL (alpha outside (0,1), NULL outputs, empty platten), CSE_ENOMEM, CSE_EHIP.
+ */
+int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+                           double *lambda_tile, uint32_t *u_tile, double *lambda_global, uint32_t *u_global,
+                           int32_t *reject_at_lambda, void *stream);
+
+/*
  * Plans: one validation or calibration step captured once into a HIP graph and replayed.
  * The step is exactly the launches of cse_validate / cse_calibrate with the same arguments
  * (Algorithms 1 and 2: alpha' -> simulation -> selection -> reductions -> bound); every

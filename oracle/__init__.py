@@ -666,14 +666,15 @@ def estimand_range(subs, coef, link: str = "linear"):
     return lo, hi
 
 
-def confidence_set(subs, lam, s_obs, coef, link: str = "linear"):
+def confidence_set(subs, lam, s_obs, coef, link: str = "linear", key_dtype=np.float32):
     """Section 7: with the observed statistic s_i of each tile and its calibrated threshold
     lambda_i, the confidence region is the union of the tiles not rejected, s_i >= lambda_i
-    (the test rejects when s_i < lambda_i; compared in float32, the statistic's precision),
-    and the confidence set of e is the image of that region: returns (keep mask, per-tile
-    range (lo, hi), (min lo, max hi) over kept tiles, or (+inf, -inf) when none is kept)."""
-    s32 = np.broadcast_to(np.asarray(s_obs, np.float32), (len(subs),))
-    keep = ~(s32 < np.asarray(lam, np.float64).astype(np.float32))
+    (the test rejects when s_i < lambda_i; compared in key_dtype, the precision of the
+    simulated statistic), and the confidence set of e is the image of that region: returns
+    (keep mask, per-tile range (lo, hi), (min lo, max hi) over kept tiles, or (+inf, -inf)
+    when none is kept)."""
+    sk = np.broadcast_to(np.asarray(s_obs, np.float64).astype(key_dtype), (len(subs),))
+    keep = ~(sk < np.asarray(lam, np.float64).astype(key_dtype))
     lo, hi = estimand_range(subs, coef, link)
     rng = (float(lo[keep].min()), float(hi[keep].max())) if keep.any() else (math.inf, -math.inf)
     return keep, lo, hi, rng

@@ -31,7 +31,7 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
             "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
-            "cse_last_error")
+            "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -74,6 +74,9 @@ def _load():
     L.cse_plan_destroy.argtypes = [P]
     L.cse_autotune.argtypes = [P, u64, i64, P, P]
     L.cse_taylor.argtypes = [P, P, P, P, P, P, P]
+    L.cse_validate_lower.argtypes = [P, P, dbl, P, P, P, P]
+    L.cse_confidence_set.argtypes = [P, P, i64, P, P, i32, P, P, P, P, P]
+    L.cse_calibrate_tiebreak.argtypes = [P, u64, dbl] + [P] * 8
     L.cse_profile_enable.argtypes = [i32]
     L.cse_profile_get.argtypes = [ctypes.c_char_p, ctypes.POINTER(i64), ctypes.POINTER(dbl)]
     L.cse_profile_reset.argtypes = []
@@ -221,6 +224,25 @@ def cse_taylor(h, f, grad, bound, vertex=None, point=None, stream=None):
                                        _stream(stream)))
 
 
+def cse_validate_lower(h, R, delta, cp_lower, lower, q_star=None, stream=None):
+    _check("cse_validate_lower", _L.cse_validate_lower(h, _ptr(R), delta, _ptr(cp_lower), _ptr(lower), _ptr(q_star),
+                                                       _stream(stream)))
+
+
+def cse_confidence_set(h, s_obs, s_stride, lambda_tile, coef, link, keep, e_lo, e_hi, e_range, stream=None):
+    c = np.ascontiguousarray(coef, np.float64)
+    _check("cse_confidence_set", _L.cse_confidence_set(h, _ptr(s_obs), s_stride, _ptr(lambda_tile), _ptr(c), link,
+                                                       _ptr(keep), _ptr(e_lo), _ptr(e_hi), _ptr(e_range),
+                                                       _stream(stream)))
+
+
+def cse_calibrate_tiebreak(h, seed, alpha, alpha_prime, k, lambda_tile, u_tile, lambda_global, u_global,
+                           reject_at_lambda, stream=None):
+    _check("cse_calibrate_tiebreak", _L.cse_calibrate_tiebreak(
+        h, seed, alpha, _ptr(alpha_prime), _ptr(k), _ptr(lambda_tile), _ptr(u_tile), _ptr(lambda_global),
+        _ptr(u_global), _ptr(reject_at_lambda), _stream(stream)))
+
+
 def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):
     """Pick the fused kernel's launch shape on this device; returns (value, grid)."""
     out = np.zeros(2, np.int64)
@@ -348,6 +370,46 @@ class Platten:
                    point=torch.empty((n, self.d), dtype=torch.float64, device=device))
         cse_taylor(self.handle, f, grad, out["bound"], out["vertex"], out["point"])
         return out
+
+    def validate_lower(self, R, delta=0.01, device="cuda"):
+        """Lower side of the two-sided band (Remark 2) from rejection counts R (device int32)."""
+        n = self.n_tiles
+        out = dict(cp_lower=torch.empty(n, dtype=torch.float64, device=device),
+                   lower=torch.empty(n, dtype=torch.float64, device=device),
+                   q_star=torch.empty(n, dtype=torch.float64, device=device))
+        cse_validate_lower(self.handle, R, delta, out["cp_lower"], out["lower"], out["q_star"])
+        return out
+
+    def confidence_set(self, s_obs, lambda_tile, coef, link="linear", device="cuda"):
+        """Confidence set from a calibration (Section 7): keep mask, per-tile range of e and the
+        range over kept tiles.  s_obs: a float or a per-tile float64 tensor."""
+        n = self.n_tiles
+        if isinstance(s_obs, torch.Tensor):
+            s, stride = s_obs.to(device=device, dtype=torch.float64).contiguous(), 1
+        else:
+            s, stride = torch.full((1,), float(s_obs), dtype=torch.float64, device=device), 0
+        out = dict(keep=torch.empty(n, dtype=torch.int32, device=device),
+                   e_lo=torch.empty(n, dtype=torch.float64, device=device),
+                   e_hi=torch.empty(n, dtype=torch.float64, device=device),
+                   e_range=torch.empty(2, dtype=torch.float64, device=device))
+        cse_confidence_set(self.handle, s, stride, lambda_tile, coef, {"linear": 0, "expit": 1}[link],
+                           out["keep"], out["e_lo"], out["e_hi"], out["e_range"])
+        return out
+
+    def calibrate_tiebreak(self, seed=0, alpha=0.025, device="cuda"):
+        """Randomised calibration: thresholds (lambda_i, c_i) on the pair (S, u).  The uint32
+        values c are returned in int32 tensors (reinterpret with .view(numpy.uint32))."""
+        n = self.n_tiles
+        o = dict(alpha_prime=torch.empty(n, dtype=torch.float64, device=device),
+                 k=torch.empty(n, dtype=torch.int32, device=device),
+                 lambda_tile=torch.empty(n, dtype=torch.float64, device=device),
+                 u_tile=torch.empty(n, dtype=torch.int32, device=device),
+                 lambda_global=torch.empty(1, dtype=torch.float64, device=device),
+                 u_global=torch.empty(1, dtype=torch.int32, device=device),
+                 reject_at_lambda=torch.empty(n, dtype=torch.int32, device=device))
+        cse_calibrate_tiebreak(self.handle, seed, alpha, o["alpha_prime"], o["k"], o["lambda_tile"], o["u_tile"],
+                               o["lambda_global"], o["u_global"], o["reject_at_lambda"])
+        return o
 
     def bound(self, mode, R=None, a=None, level=0.01, device="cuda"):
         out = torch.empty(self.n_tiles, dtype=torch.float64, device=device)

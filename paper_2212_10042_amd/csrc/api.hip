@@ -2,6 +2,7 @@
 #include <math.h>
 
 #include <algorithm>
+#include <cmath>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -570,6 +571,81 @@ int cse_bound(const cse_platten *p, int32_t mode, const int32_t *R, const double
     const auto &P = p->P;
     CSE_LAUNCH(cse::launch_bound(P, mode, (const uint32_t *)R, a, delta_or_alpha, out, q_star,
                                  nullptr, nullptr, (hipStream_t)stream));
+    return CSE_OK;
+}
+
+int cse_validate_lower(const cse_platten *p, const int32_t *R, double delta, double *cp_lower, double *lower,
+                       double *q_star, void *stream) {
+    if (int e = check_handle(p, "cse_validate_lower")) return e;
+    if (!R || !lower) {
+        set_error("cse_validate_lower: R and lower must not be NULL");
+        return CSE_EINVAL;
+    }
+    if (!in_unit(delta)) {
+        set_error("cse_validate_lower: delta must lie in (0, 1)");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    if (P.n_tiles == 0) return CSE_OK;
+    hipStream_t st = (hipStream_t)stream;
+    Timed tm("bound_lower", st);
+    CSE_LAUNCH(cse::launch_bound(P, 3, (const uint32_t *)R, nullptr, delta, lower, q_star, nullptr, cp_lower, st));
+    return CSE_OK;
+}
+
+int cse_confidence_set(const cse_platten *p, const double *s_obs, int64_t s_stride, const double *lambda_tile,
+                       const double *coef, int32_t link, int32_t *keep, double *e_lo, double *e_hi,
+                       double *e_range, void *stream) {
+    if (int e = check_handle(p, "cse_confidence_set")) return e;
+    if (!s_obs || !lambda_tile || !coef || !keep || !e_lo || !e_hi || !e_range) {
+        set_error("cse_confidence_set: s_obs, lambda_tile, coef, keep, e_lo, e_hi and e_range must not be NULL");
+        return CSE_EINVAL;
+    }
+    if (link != 0 && link != 1) {
+        set_error("cse_confidence_set: link must be 0 (identity) or 1 (expit)");
+        return CSE_EINVAL;
+    }
+    if (s_stride != 0 && s_stride != 1) {
+        set_error("cse_confidence_set: s_stride must be 0 (one statistic for all tiles) or 1");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    for (int a = 0; a <= P.d; ++a)
+        if (!std::isfinite(coef[a])) {
+            set_error("cse_confidence_set: coefficients must be finite");
+            return CSE_EINVAL;
+        }
+    hipStream_t st = (hipStream_t)stream;
+    Timed tm("confidence_set", st);
+    CSE_LAUNCH(cse::launch_confset(P, s_obs, s_stride, lambda_tile, coef, link, keep, e_lo, e_hi, e_range, st));
+    return CSE_OK;
+}
+
+int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+                           double *lambda_tile, uint32_t *u_tile, double *lambda_global, uint32_t *u_global,
+                           int32_t *reject_at_lambda, void *stream) {
+    if (int e = check_calibrate(p, alpha, 0.5, nullptr, nullptr, nullptr, false, "cse_calibrate_tiebreak")) return e;
+    if (!lambda_tile || !u_tile || !lambda_global || !u_global || !reject_at_lambda) {
+        set_error("cse_calibrate_tiebreak: lambda_tile, u_tile, lambda_global, u_global and reject_at_lambda "
+                  "must not be NULL");
+        return CSE_EINVAL;
+    }
+    auto &P = const_cast<cse_platten *>(p)->P;
+    if (P.n_tiles == 0) {
+        set_error("cse_calibrate_tiebreak: the platten has no tiles");
+        return CSE_EINVAL;
+    }
+    if (int e = ensure_keys(P)) return e;
+    hipStream_t st = (hipStream_t)stream;
+    int32_t *kk = k ? k : P.d_kw;
+    if (int e = calibrate_impl(P, seed, alpha, alpha_prime, kk, lambda_tile, nullptr, reject_at_lambda, 0.5, nullptr,
+                               nullptr, nullptr, nullptr, nullptr, nullptr, st))
+        return e;
+    {
+        Timed tm("tiebreak", st);
+        CSE_LAUNCH(cse::launch_tiebreak(P, seed, kk, lambda_tile, reject_at_lambda, u_tile, st));
+    }
+    CSE_LAUNCH(cse::launch_min_pair(lambda_tile, u_tile, P.n_tiles, lambda_global, u_global, st));
     return CSE_OK;
 }
 

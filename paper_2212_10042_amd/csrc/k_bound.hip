@@ -199,7 +199,11 @@ __device__ double section_search(int lane, const TileGeom<D> &T, double loga, do
     return sg * best;
 }
 
-// mode 0: validate (CP then tilt), mode 1: invert (alpha', k), mode 2: tilt of given a.
+__global__ void k_negate1(double *x) { x[0] = -x[0]; }
+
+// mode 0: validate (CP then tilt), mode 1: invert (alpha', k), mode 2: tilt of given a,
+// mode 3: lower validation bound (Remark 2: the tilt of 1 - cp_lower = cp_upper(N - R), then
+// lower = 1 - that; cp_out receives cp_lower).
 template <int FAM, int D>
 __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
                                                const double *__restrict__ theta,
@@ -262,12 +266,18 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
     if (mode == 0) {
         a = cp_tbl[cp_base[t] + (int64_t)R[t]];
         if (valid && lane == 0 && cp_out) cp_out[t] = a;
+    } else if (mode == 3) {
+        const uint32_t r = min(R[t], (uint32_t)N[t]);
+        a = cp_tbl[cp_base[t] + (int64_t)((uint32_t)N[t] - r)];
+        if (valid && lane == 0 && cp_out) cp_out[t] = 1.0 - a;
     } else {
         a = a_in[t];
     }
+    const bool lower = mode == 3;
     if (a <= 0.0 || a >= 1.0) {
         if (valid && lane == 0) {
-            out[t] = a <= 0.0 ? 0.0 : 1.0;
+            const double ub = a <= 0.0 ? 0.0 : 1.0;
+            out[t] = lower ? 1.0 - ub : ub;
             if (q_out) q_out[t] = a <= 0.0 ? INFINITY : 1.0;
         }
         return;
@@ -275,7 +285,8 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
     double sb;
     const double val = section_search<FAM, D, false>(lane, T, log(a), &sb);
     if (valid && lane == 0) {
-        out[t] = fmin(exp(val), 1.0);
+        const double ub = fmin(exp(val), 1.0);
+        out[t] = lower ? 1.0 - ub : ub;
         if (q_out) q_out[t] = 1.0 + exp(sb);
     }
 }
@@ -349,13 +360,105 @@ hipError_t launch_taylor(const Platten &P, const double *f, const double *g, dou
     return hipGetLastError();
 }
 
+// ---- confidence sets from calibration (Section 7) ----
+// Per tile: kept when its test does not reject the observed statistic, s_i >= lambda_i
+// (compared in the precision of the design's keys: float64 outcome statistics for the 2-arm
+// design, float32 otherwise), and the range of e(theta) = c0 + sum_a c_a g(theta_a) over the
+// tile: g = identity, min / max over the vertices (exact on a polytope); g = expit, the sum of
+// each term's extremes over the tile's bounding box (exact on a box, enclosing on a clipped
+// tile).  Tiles not kept get the empty range (+inf, -inf).
+struct ConfCoef {
+    double c[4];
+    double c0;
+};
+
+template <int D>
+__global__ void k_confset(int64_t n_tiles, const double *__restrict__ theta, const int32_t *__restrict__ vert_off,
+                          const double *__restrict__ verts, const double *__restrict__ s_obs, int64_t s_stride,
+                          const double *__restrict__ lam, ConfCoef cf, int link, bool f64_keys,
+                          int32_t *__restrict__ keep, double *__restrict__ e_lo, double *__restrict__ e_hi,
+                          double *__restrict__ e_min, double *__restrict__ e_max) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    const double s = s_obs[t * s_stride], L = lam[t];
+    const bool kp = f64_keys ? !(s < L) : !((float)s < (float)L);
+    double th[D], mn[D], mx[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        th[a] = theta[t * D + a];
+        mn[a] = INFINITY;
+        mx[a] = -INFINITY;
+    }
+    const int32_t v0 = vert_off[t], nv = vert_off[t + 1] - v0;
+    double lo = INFINITY, hi = -INFINITY;
+    for (int j = 0; j < nv; ++j) {
+        double val = cf.c0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double x = th[a] + verts[(int64_t)(v0 + j) * D + a];
+            val += cf.c[a] * x;
+            mn[a] = fmin(mn[a], x);
+            mx[a] = fmax(mx[a], x);
+        }
+        lo = fmin(lo, val);
+        hi = fmax(hi, val);
+    }
+    if (link == 1) {
+        lo = hi = cf.c0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            const double u = cf.c[a] / (1.0 + exp(-mn[a])), w = cf.c[a] / (1.0 + exp(-mx[a]));
+            lo += fmin(u, w);
+            hi += fmax(u, w);
+        }
+    }
+    keep[t] = kp ? 1 : 0;
+    e_lo[t] = lo;
+    e_hi[t] = hi;
+    e_min[t] = kp ? lo : INFINITY;
+    e_max[t] = kp ? -hi : INFINITY;   // negated: both reductions take a minimum
+}
+
+hipError_t launch_confset(const Platten &P, const double *s_obs, int64_t s_stride, const double *lam,
+                          const double *coef, int link, int32_t *keep, double *e_lo, double *e_hi,
+                          double *e_range, hipStream_t st) {
+    ConfCoef cf{};
+    for (int a = 0; a < P.d; ++a) cf.c[a] = coef[a];
+    cf.c0 = coef[P.d];
+    const dim3 grid((uint32_t)((P.n_tiles + 255) / 256));
+    const bool f64 = P.design.kind == CSE_BINOM2_Z;
+    // the per-tile minima land in two float64 workspaces of n_tiles entries
+    double *wmin = P.d_apw, *wmax = P.d_lamw;
+#define CSE_CONF_LAUNCH(D)                                                                                    \
+    hipLaunchKernelGGL((k_confset<D>), grid, dim3(256), 0, st, P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts,   \
+                       s_obs, s_stride, lam, cf, link, f64, keep, e_lo, e_hi, wmin, wmax)
+    if (P.n_tiles == 0)
+        ;   // nothing kept: the reductions below give the empty range (+inf, -inf)
+    else if (P.d == 1)
+        CSE_CONF_LAUNCH(1);
+    else if (P.d == 2)
+        CSE_CONF_LAUNCH(2);
+    else if (P.d == 4)
+        CSE_CONF_LAUNCH(4);
+    else
+        return hipErrorInvalidValue;
+#undef CSE_CONF_LAUNCH
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = launch_min(wmin, P.n_tiles, e_range, st)) != hipSuccess) return e;
+    if ((e = launch_min(wmax, P.n_tiles, e_range + 1, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_negate1, dim3(1), dim3(1), 0, st, e_range + 1);
+    return hipGetLastError();
+}
+
 // Clopper-Pearson once per (N class, R) present in this call: mark, then solve marked entries.
+// flip: mark N - R instead (the lower bound, cp_lower(R) = 1 - cp_upper(N - R)).
 __global__ void k_cp_mark(int64_t n_tiles, const uint32_t *__restrict__ R, const int32_t *__restrict__ N,
-                          const int64_t *__restrict__ cp_base, uint32_t *__restrict__ mark) {
+                          const int64_t *__restrict__ cp_base, bool flip, uint32_t *__restrict__ mark) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_tiles) return;
     const uint32_t r = min(R[t], (uint32_t)N[t]);
-    mark[cp_base[t] + r] = 1u;
+    mark[cp_base[t] + (flip ? (uint32_t)N[t] - r : r)] = 1u;
 }
 
 __global__ void k_cp_table(const int32_t *__restrict__ cls_N, const int64_t *__restrict__ cls_off,
@@ -385,11 +488,11 @@ static double normal_upper_quantile(double delta) {
 hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const double *a_in,
                         double level, double *out, double *q_out, int32_t *k_out, double *cp_out,
                         hipStream_t st) {
-    if (mode == 0) {
+    if (mode == 0 || mode == 3) {
         hipError_t e = launch_zero(P.d_cp_mark, (size_t)P.n_cp * sizeof(uint32_t), st);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_cp_mark, dim3((uint32_t)((P.n_tiles + 255) / 256)), dim3(256), 0, st,
-                           P.n_tiles, R, P.d_N, P.d_cp_base, P.d_cp_mark);
+                           P.n_tiles, R, P.d_N, P.d_cp_base, mode == 3, P.d_cp_mark);
         const double zq = normal_upper_quantile(level);
         hipLaunchKernelGGL(k_cp_table, dim3((uint32_t)((P.max_cls_N + 1 + 63) / 64), (uint32_t)P.n_cls),
                            dim3(64), 0, st, P.d_cls_N, P.d_cls_off, P.d_cp_mark, level, zq, P.d_cp_tbl);

@@ -7,6 +7,7 @@
 
 #include "cse_internal.h"
 #include "kernels.h"
+#include "philox.hpp"
 
 namespace cse {
 
@@ -295,6 +296,117 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
     }
 }
 
+// ---- randomised calibration: the statistic is the pair (S, u), u the simulation's adjoined
+// uniform (philox_tiebreak), ordered lexicographically.  Given the k-th smallest S, lambda, and
+// the count `below` of keys strictly under it (the selection's outputs), the k-th smallest pair
+// is (lambda, c) with c the (k - below)-th smallest u among the simulations whose key equals
+// lambda.  The tied simulations' u are regenerated from the counter and gathered in LDS; more
+// than SEL_CAND ties fall back to radix passes over the whole tile with every non-tied key
+// mapped to 0xFFFFFFFF (which cannot change a rank <= the number of ties).  On exit rej_at[t]
+// holds the number of pairs strictly below (lambda, c).
+template <bool OUTCOMES>
+__global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ keys_,
+                                                     const int64_t *__restrict__ key_off,
+                                                     const int64_t *__restrict__ key_stride,
+                                                     const double *__restrict__ S_tbl,
+                                                     const int32_t *__restrict__ N,
+                                                     const int32_t *__restrict__ kk,
+                                                     const double *__restrict__ lam, uint32_t key0,
+                                                     uint32_t key1, int32_t *__restrict__ rej_at,
+                                                     uint32_t *__restrict__ c_out) {
+    __shared__ uint32_t hist[2048];
+    __shared__ uint32_t part[SEL_WG];
+    __shared__ uint32_t cand[SEL_CAND];
+    __shared__ uint32_t s_bin, s_below, s_cnt;
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int lane = tid & (WAVE - 1);
+    const int32_t n = N[t];
+    const int32_t k = kk[t];
+    if (k <= 0 || k > n) {
+        if (tid == 0) c_out[t] = k <= 0 ? 0u : 0xFFFFFFFFu;
+        return;
+    }
+    const double L = lam[t];
+    const uint32_t Lord = f2ord((float)L);
+    const uint32_t below_lam = (uint32_t)rej_at[t];
+    const uint32_t need = (uint32_t)k - below_lam;   // >= 1: the k-th key is a tie
+    auto tied = [&](int j) -> bool {
+        if (OUTCOMES) {
+            const uint16_t *kt = (const uint16_t *)keys_ + key_off[t];
+            return S_tbl[kt[(int64_t)(j >> 6) * KEY_CHUNK + (j & 63)]] == L;
+        } else {
+            const float *kt = (const float *)keys_ + key_off[t];
+            return f2ord(kt[(int64_t)(j >> 6) * key_stride[t] + (j & 63)]) == Lord;
+        }
+    };
+    if (tid == 0) s_cnt = 0u;
+    __syncthreads();
+    // uniform trip count: every lane takes part in the ballots
+    for (int j0 = 0; j0 < n; j0 += SEL_WG) {
+        const int j = j0 + tid;
+        const bool in = j < n && tied(j);
+        const unsigned long long bal = __ballot(in);
+        if (bal) {
+            uint32_t base = 0u;
+            if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
+            base = __shfl(base, 0);
+            const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
+            if (in && pos < (uint32_t)SEL_CAND) cand[pos] = philox_tiebreak((uint32_t)j, key0, key1);
+        }
+    }
+    __syncthreads();
+    const uint32_t m = s_cnt;
+    uint32_t c = 0u, below_u = 0u;
+    if (m <= (uint32_t)SEL_CAND) {
+        auto from_cand = [&](int j) { return cand[j]; };
+        radix_kth((int)m, need, from_cand, hist, part, &s_bin, &s_below, c, below_u);
+    } else {
+        auto all = [&](int j) { return tied(j) ? philox_tiebreak((uint32_t)j, key0, key1) : 0xFFFFFFFFu; };
+        radix_kth(n, need, all, hist, part, &s_bin, &s_below, c, below_u);
+    }
+    if (tid == 0) {
+        c_out[t] = c;
+        rej_at[t] = (int32_t)(below_lam + below_u);
+    }
+}
+
+// lexicographic minimum over tiles of (lambda_i, c_i), one workgroup.
+__global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v, const uint32_t *__restrict__ c,
+                                                   int64_t n, double *__restrict__ out_v,
+                                                   uint32_t *__restrict__ out_c) {
+    __shared__ double sv[1024];
+    __shared__ uint32_t sc[1024];
+    double mv = INFINITY;
+    uint32_t mc = 0xFFFFFFFFu;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double x = v[i];
+        const uint32_t y = c[i];
+        if (x < mv || (x == mv && y < mc)) {
+            mv = x;
+            mc = y;
+        }
+    }
+    sv[threadIdx.x] = mv;
+    sc[threadIdx.x] = mc;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) {
+            const double x = sv[threadIdx.x + s];
+            const uint32_t y = sc[threadIdx.x + s];
+            if (x < sv[threadIdx.x] || (x == sv[threadIdx.x] && y < sc[threadIdx.x])) {
+                sv[threadIdx.x] = x;
+                sc[threadIdx.x] = y;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out_v[0] = sv[0];
+        out_c[0] = sc[0];
+    }
+}
+
 // min over tiles of lambda*_i, one workgroup.
 __global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, int64_t n,
                                               double *__restrict__ out) {
@@ -382,6 +494,24 @@ hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_
                            2 * (size_t)P.n_outcomes * sizeof(uint32_t), st,
                            (const uint16_t *)P.d_keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
                            P.d_S_group, P.n_outcomes, lam, rej_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,
+                           uint32_t *c_tile, hipStream_t st) {
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    if (P.design.kind == CSE_BINOM2_Z)
+        hipLaunchKernelGGL(k_tiebreak<true>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, P.d_keys, P.d_key_off,
+                           P.d_key_stride, P.d_S_tbl, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    else
+        hipLaunchKernelGGL(k_tiebreak<false>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, P.d_keys, P.d_key_off,
+                           P.d_key_stride, P.d_S_tbl, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    return hipGetLastError();
+}
+
+hipError_t launch_min_pair(const double *v, const uint32_t *c, int64_t n, double *out_v, uint32_t *out_c,
+                           hipStream_t st) {
+    hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, v, c, n, out_v, out_c);
     return hipGetLastError();
 }
 

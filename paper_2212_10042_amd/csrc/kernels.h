@@ -16,6 +16,13 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
 hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st);
 hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st);
+hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,
+                           uint32_t *c_tile, hipStream_t st);
+hipError_t launch_min_pair(const double *v, const uint32_t *c, int64_t n, double *out_v, uint32_t *out_c,
+                           hipStream_t st);
+hipError_t launch_confset(const Platten &P, const double *s_obs, int64_t s_stride, const double *lam,
+                          const double *coef, int link, int32_t *keep, double *e_lo, double *e_hi,
+                          double *e_range, hipStream_t st);
 hipError_t launch_finish(const Platten &P, const uint32_t *R, const unsigned long long *sumT,
                          const unsigned long long *sumZfx, int32_t *R_out, int64_t *T_out,
                          double *Z_out, double *grad, hipStream_t st);

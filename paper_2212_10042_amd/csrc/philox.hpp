@@ -41,6 +41,19 @@ __device__ __forceinline__ u32x4 philox_block(uint32_t blk, uint32_t sim, uint32
     return u32x4{c0, c1, c2, c3};
 }
 
+// The uniform adjoined to simulation `sim` by the randomised test: first word of the block at
+// counter (0, sim, 1, 0).  Data blocks have counter word 2 = 0, so the two streams never meet.
+__device__ __forceinline__ uint32_t philox_tiebreak(uint32_t sim, uint32_t k0, uint32_t k1) {
+    uint32_t c0 = 0u, c1 = sim, c2 = 1u, c3 = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        philox_round(c0, c1, c2, c3, k0, k1);
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c0;
+}
+
 __device__ __forceinline__ uint32_t u32x4_get(const u32x4 &v, int i) {
     return i == 0 ? v.x : (i == 1 ? v.y : (i == 2 ? v.z : v.w));
 }
