@@ -124,6 +124,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the fused kernel's launch shape with cse_autotune before timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--no-extensions", action="store_true",
+                    help="skip the lower-bound, confidence-set and randomised-calibration timings")
     ap.add_argument("--progress", action="store_true",
                     help="synchronise and report on stderr after every step (for steps of a minute or more)")
     ap.add_argument("--copy-probe", type=int, default=0,
@@ -240,6 +242,43 @@ def main():
         taylor = {"kernel_ms": ms / max(cnt, 1), "max_bound": float(to["bound"].max().item()),
                   "max_tilt_bound": float(o["bound"].max().item())}
 
+    # the two-sided band (Remark 2), a confidence set (Section 7) and the randomised calibration,
+    # each on this step's outputs and timed on its own (not part of the step)
+    ext = None
+    if not args.no_extensions and n:
+        ext = {}
+        cse.cse_profile_reset()
+        cse.cse_profile_enable(True)
+        for _ in range(5):
+            lo = P.validate_lower(o["reject"], delta=w["delta"])
+        torch.cuda.synchronize()
+        cnt, ms = cse.cse_profile_get("bound_lower")
+        ext["lower_bound"] = {"kernel_ms": ms / max(cnt, 1), "min_lower": float(lo["lower"].min().item())}
+        if calibrating:
+            coef = [-1.0, 1.0] + [0.0] * (d - 2) + [0.0]      # e(theta) = theta_1 - theta_0
+            for _ in range(5):
+                cs = P.confidence_set(float(o["lam"].median().item()), o["lam"], coef)
+            torch.cuda.synchronize()
+            cnt, ms = cse.cse_profile_get("confidence_set")
+            ext["confidence_set"] = {"ms": ms / max(cnt, 1), "kept": int(cs["keep"].sum().item()),
+                                     "e_range": [float(x) for x in cs["e_range"].tolist()]}
+            reps = args.steps if ms_step < 1000.0 else 1      # long steps: one call, no warm-up
+            if reps > 1:
+                tb = P.calibrate_tiebreak(w["seed"], alpha=w["alpha"])
+                torch.cuda.synchronize()
+            cse.cse_profile_reset()
+            tt = time.perf_counter()
+            for _ in range(reps):
+                tb = P.calibrate_tiebreak(w["seed"], alpha=w["alpha"])
+            torch.cuda.synchronize()
+            dtt = (time.perf_counter() - tt) / reps
+            cnt, ms = cse.cse_profile_get("tiebreak")
+            ext["tiebreak"] = {"ms_per_step": dtt * 1e3, "kernel_ms": ms / max(cnt, 1),
+                               "value": st["total_sims"] / dtt,
+                               "same_lambda_as_plain": bool(torch.equal(tb["lambda_tile"], o["lam"])),
+                               "step": "alpha' -> simulation -> selection -> tie-break, no validation bound"}
+        cse.cse_profile_enable(False)
+
     # the same step captured once as a HIP graph and replayed (outputs checked against eager)
     graph = None
     if not args.no_graph:
@@ -335,6 +374,7 @@ def main():
         "kernel_avg_ms": kern,
         "graph_replay": graph,
         "taylor": taylor,
+        "extensions": ext,
         "autotune": tune,
         "launch_shape": cse.cse_platten_stats(P.handle)["launch_shape"],
         "platten_build_ms": platten_ms,

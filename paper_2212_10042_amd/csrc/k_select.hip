@@ -304,11 +304,19 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
 // than SEL_CAND ties fall back to radix passes over the whole tile with every non-tied key
 // mapped to 0xFFFFFFFF (which cannot change a rank <= the number of ties).  On exit rej_at[t]
 // holds the number of pairs strictly below (lambda, c).
-template <bool OUTCOMES>
+// Key layouts: TB_F32 float32 keys at kt[(j / 64) * stride + j % 64]; TB_F32V4 the same with
+// 256-byte aligned 64-key chunks (read as float4); TB_OUT 2-arm outcome indices, chunk-major
+// (64 keys per KEY_CHUNK), read as 16-byte pieces of eight keys and tested against an LDS
+// bitmask of the outcomes whose statistic equals lambda.
+enum { TB_F32 = 0, TB_F32V4 = 1, TB_OUT = 2 };
+constexpr int TB_MASK_WORDS = 2048;   // 65,536 outcome indices (16-bit keys)
+constexpr int TB_RANK = 512;          // tie classes up to this size are ranked by counting
+
+template <int MODE>
 __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ keys_,
                                                      const int64_t *__restrict__ key_off,
                                                      const int64_t *__restrict__ key_stride,
-                                                     const double *__restrict__ S_tbl,
+                                                     const double *__restrict__ S_tbl, int n_out,
                                                      const int32_t *__restrict__ N,
                                                      const int32_t *__restrict__ kk,
                                                      const double *__restrict__ lam, uint32_t key0,
@@ -317,6 +325,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     __shared__ uint32_t hist[2048];
     __shared__ uint32_t part[SEL_WG];
     __shared__ uint32_t cand[SEL_CAND];
+    __shared__ uint32_t tmask[MODE == TB_OUT ? TB_MASK_WORDS : 1];
     __shared__ uint32_t s_bin, s_below, s_cnt;
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
@@ -331,37 +340,123 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     const uint32_t Lord = f2ord((float)L);
     const uint32_t below_lam = (uint32_t)rej_at[t];
     const uint32_t need = (uint32_t)k - below_lam;   // >= 1: the k-th key is a tie
-    auto tied = [&](int j) -> bool {
-        if (OUTCOMES) {
-            const uint16_t *kt = (const uint16_t *)keys_ + key_off[t];
-            return S_tbl[kt[(int64_t)(j >> 6) * KEY_CHUNK + (j & 63)]] == L;
-        } else {
-            const float *kt = (const float *)keys_ + key_off[t];
-            return f2ord(kt[(int64_t)(j >> 6) * key_stride[t] + (j & 63)]) == Lord;
-        }
-    };
+    const int64_t stride = key_stride[t];
+    const float *__restrict__ kf = (const float *)keys_ + key_off[t];
+    const uint16_t *__restrict__ ko = (const uint16_t *)keys_ + key_off[t];
+    if (MODE == TB_OUT) {
+        for (int w = tid; w < TB_MASK_WORDS; w += SEL_WG) tmask[w] = 0u;
+        __syncthreads();
+        for (int o = tid; o < n_out; o += SEL_WG)
+            if (S_tbl[o] == L) atomicOr(&tmask[o >> 5], 1u << (o & 31));
+    }
     if (tid == 0) s_cnt = 0u;
     __syncthreads();
-    // uniform trip count: every lane takes part in the ballots
-    for (int j0 = 0; j0 < n; j0 += SEL_WG) {
-        const int j = j0 + tid;
-        const bool in = j < n && tied(j);
+    auto is_tie_out = [&](uint32_t key) { return (tmask[key >> 5] >> (key & 31)) & 1u; };
+    auto tied = [&](int j) -> bool {
+        if (MODE == TB_OUT) return is_tie_out(ko[(int64_t)(j >> 6) * KEY_CHUNK + (j & 63)]);
+        return f2ord(kf[(int64_t)(j >> 6) * stride + (j & 63)]) == Lord;
+    };
+    // append simulation j's uniform when `in` (called by every lane of the wave)
+    auto take = [&](bool in, int j) {
         const unsigned long long bal = __ballot(in);
-        if (bal) {
+        if (bal) {   // uniform
             uint32_t base = 0u;
             if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
             base = __shfl(base, 0);
             const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
             if (in && pos < (uint32_t)SEL_CAND) cand[pos] = philox_tiebreak((uint32_t)j, key0, key1);
         }
+    };
+    // one pass over the tile with several 16-byte (or 4-byte) loads in flight per thread; trip
+    // counts are uniform so that every lane takes part in the ballots
+    constexpr int LB = 4;
+    if (MODE == TB_OUT) {
+        const int nq = ((n + 63) >> 6) * 8;   // 16-byte pieces
+        for (int q0 = 0; q0 < nq; q0 += SEL_WG * LB) {
+            uint4 v[LB];
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int q = q0 + i * SEL_WG + tid;
+                v[i] = q < nq ? *reinterpret_cast<const uint4 *>(ko + (int64_t)(q >> 3) * KEY_CHUNK + (q & 7) * 8)
+                              : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int q = q0 + i * SEL_WG + tid;
+                const int j0 = (q >> 3) * 64 + (q & 7) * 8;
+                const uint32_t wd[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t key = (wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
+                    take(q < nq && j0 + e < n && is_tie_out(key), j0 + e);
+                }
+            }
+        }
+    } else if (MODE == TB_F32V4) {
+        const int nq = ((n + 63) >> 6) * 16;   // float4 pieces
+        for (int q0 = 0; q0 < nq; q0 += SEL_WG * LB) {
+            float4 v[LB];
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int q = q0 + i * SEL_WG + tid;
+                v[i] = q < nq ? *reinterpret_cast<const float4 *>(kf + (int64_t)(q >> 4) * stride + (q & 15) * 4)
+                              : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int i = 0; i < LB; ++i) {
+                const int q = q0 + i * SEL_WG + tid;
+                const int j0 = 4 * q;
+                const bool ok = q < nq;
+                take(ok && j0 + 0 < n && f2ord(v[i].x) == Lord, j0 + 0);
+                take(ok && j0 + 1 < n && f2ord(v[i].y) == Lord, j0 + 1);
+                take(ok && j0 + 2 < n && f2ord(v[i].z) == Lord, j0 + 2);
+                take(ok && j0 + 3 < n && f2ord(v[i].w) == Lord, j0 + 3);
+            }
+        }
+    } else {
+        constexpr int LS = 8;
+        for (int j0 = 0; j0 < n; j0 += SEL_WG * LS) {
+            uint32_t u[LS];
+#pragma unroll
+            for (int i = 0; i < LS; ++i) {
+                const int j = j0 + i * SEL_WG + tid;
+                u[i] = j < n ? f2ord(kf[(int64_t)(j >> 6) * stride + (j & 63)]) : 0u;
+            }
+#pragma unroll
+            for (int i = 0; i < LS; ++i) {
+                const int j = j0 + i * SEL_WG + tid;
+                take(j < n && u[i] == Lord, j);
+            }
+        }
     }
     __syncthreads();
     const uint32_t m = s_cnt;
     uint32_t c = 0u, below_u = 0u;
-    if (m <= (uint32_t)SEL_CAND) {
+    if (m <= (uint32_t)TB_RANK) {
+        // few ties: the candidate whose rank (smaller values, then equal values at lower
+        // positions) is need - 1 is the answer; one pass, no histograms
+        for (uint32_t i = (uint32_t)tid; i < m; i += SEL_WG) {
+            const uint32_t x = cand[i];
+            uint32_t lt = 0u, eq_before = 0u;
+            for (uint32_t j = 0; j < m; ++j) {
+                const uint32_t y = cand[j];
+                lt += y < x ? 1u : 0u;
+                eq_before += (y == x && j < i) ? 1u : 0u;
+            }
+            if (lt + eq_before == need - 1u) {
+                s_bin = x;
+                s_below = lt;
+            }
+        }
+        __syncthreads();
+        c = s_bin;
+        below_u = s_below;
+    } else if (m <= (uint32_t)SEL_CAND) {
         auto from_cand = [&](int j) { return cand[j]; };
         radix_kth((int)m, need, from_cand, hist, part, &s_bin, &s_below, c, below_u);
     } else {
+        // more ties than LDS holds: radix passes over the whole tile, non-tied keys mapped to
+        // 0xFFFFFFFF (cannot change a rank <= the number of ties)
         auto all = [&](int j) { return tied(j) ? philox_tiebreak((uint32_t)j, key0, key1) : 0xFFFFFFFFu; };
         radix_kth(n, need, all, hist, part, &s_bin, &s_below, c, below_u);
     }
@@ -500,12 +595,18 @@ hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_
 hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,
                            uint32_t *c_tile, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    if (P.design.kind == CSE_BINOM2_Z)
-        hipLaunchKernelGGL(k_tiebreak<true>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, P.d_keys, P.d_key_off,
-                           P.d_key_stride, P.d_S_tbl, P.d_N, k, lam, k0, k1, rej_at, c_tile);
-    else
-        hipLaunchKernelGGL(k_tiebreak<false>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, P.d_keys, P.d_key_off,
-                           P.d_key_stride, P.d_S_tbl, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    const dim3 grid((uint32_t)P.n_tiles), blk(SEL_WG);
+    if (P.design.kind == CSE_BINOM2_Z) {
+        if (P.n_outcomes > 32 * TB_MASK_WORDS) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_tiebreak<TB_OUT>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
+                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    } else if (P.design.kind == CSE_HIER4) {   // 64-key chunks at 256-byte offsets
+        hipLaunchKernelGGL(k_tiebreak<TB_F32V4>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
+                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    } else {
+        hipLaunchKernelGGL(k_tiebreak<TB_F32>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
+                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    }
     return hipGetLastError();
 }
 
