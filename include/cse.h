@@ -276,6 +276,52 @@ int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, do
                            int32_t *reject_at_lambda, void *stream);
 
 /*
+ * Adaptive gridding and simulation allocation from pilot runs (the paper's Phase II/III
+ * calibration chooses tile sizes and simulation counts adaptively, Section 10.2).  Host-only
+ * calls: all arrays are HOST memory; no GPU work.  One round of the rule, between the GPU
+ * passes (cse_validate or cse_calibrate on the boxes that changed):
+ *
+ * cse_adagrid_decide -- per-box decision from its tiles' results:
+ *   rule->mode 0 (validation): a = tile_bound, b = cp_upper, c = R / N per tile.  A box whose
+ *     largest bound U <= target is done (0).  Otherwise: G = max(bound - cp_upper) (the
+ *     part a smaller tile removes), M = max(cp_upper - R/N) (the part more simulations
+ *     remove); split (1) when G >= M, else double N (2).
+ *   rule->mode 1 (calibration): a = lambda_i, b = alpha'_i, c = N_i per tile; lambda* = min
+ *     over the tiles given.  A box is critical when its smallest lambda_i <= lambda* + margin
+ *     (every box when margin = +inf);
+ *     for that tile, split when alpha - alpha'_i >= sqrt(alpha'(1 - alpha')/(N + 2)) (the
+ *     spread of f(lambda_hat) ~ Beta(k, N - k + 1), Theorem 4), else double N.
+ *   Either way a split needs min half-width / 2 >= r_min and doubling needs 2 N <= n_max;
+ *   when the preferred move is not allowed the other one is taken, and a box that can do
+ *   neither is stuck (3).  Boxes without tiles are done.
+ *   radii [n_boxes][d], sims [n_boxes], tile_box [n_tiles] (box index of each tile),
+ *   decision int32 [n_boxes] out.
+ * cse_adagrid_apply -- the next box list: a split box is replaced in place by its 2^d
+ *   children (child c has coordinate k in the upper half when bit k of c is set, half-width
+ *   r/2, the parent's N); a doubled box keeps its place with 2 N; others are copied.
+ *   With theta_out == NULL only *n_out (the new count) is written.  parent_out [n_out] (or
+ *   NULL): index of the box each new box comes from; changed_out [n_out] (or NULL): 1 for
+ *   children and doubled boxes (the ones to simulate next).
+ * Errors: CSE_EINVAL (bad rule, sizes, codes, capacity, or an N that would exceed int32).
+ */
+typedef struct cse_adagrid_rule {
+    int32_t mode;    /* 0 validation, 1 calibration */
+    int32_t d;       /* parameter dimension (1..4) */
+    double target;   /* validation: largest acceptable tile bound */
+    double alpha;    /* calibration: the level */
+    double margin;   /* calibration: critical boxes have lambda <= lambda* + margin */
+    double r_min;    /* smallest half-width a split may produce */
+    int64_t n_max;   /* largest simulation count a doubling may produce */
+} cse_adagrid_rule;
+
+int cse_adagrid_decide(const cse_adagrid_rule *rule, int64_t n_boxes, const double *radii, const int32_t *sims,
+                       int64_t n_tiles, const int64_t *tile_box, const double *a, const double *b, const double *c,
+                       int32_t *decision);
+int cse_adagrid_apply(int32_t d, int64_t n_boxes, const double *theta, const double *radii, const int32_t *sims,
+                      const int32_t *decision, int64_t cap, double *theta_out, double *radii_out,
+                      int32_t *sims_out, int64_t *parent_out, int32_t *changed_out, int64_t *n_out);
+
+/*
  * Plans: one validation or calibration step captured once into a HIP graph and replayed.
  * The step is exactly the launches of cse_validate / cse_calibrate with the same arguments
  * (Algorithms 1 and 2: alpha' -> simulation -> selection -> reductions -> bound); every

@@ -88,10 +88,13 @@ def decide_calibration(radii, sims, box_of_tile, lam, alpha_prime, N, alpha, mar
     for t, b in enumerate(box_of_tile):
         if best[b] is None or lam[t] < lam[best[b]]:
             best[b] = t
+    thr = lam_star + margin
+    if math.isnan(thr):                    # lambda* = -inf with an infinite margin: every box
+        thr = math.inf
     dec = np.zeros(n, np.int32)
     for i in range(n):
         t = best[i]
-        if t is None or not lam[t] <= lam_star + margin:
+        if t is None or not lam[t] <= thr:
             continue
         ap = float(alpha_prime[t])
         slack = alpha - ap

@@ -31,13 +31,20 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_platten_stats", "cse_profile_enable", "cse_profile_get", "cse_profile_reset",
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
             "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
-            "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_last_error")
+            "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_adagrid_decide",
+            "cse_adagrid_apply", "cse_last_error")
 
 
 class CseError(RuntimeError):
     def __init__(self, fn: str, status: int, msg: str):
         super().__init__(f"{fn} -> status {status}: {msg}")
         self.status = status
+
+
+class cse_adagrid_rule(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("d", ctypes.c_int32), ("target", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("margin", ctypes.c_double), ("r_min", ctypes.c_double),
+                ("n_max", ctypes.c_int64)]
 
 
 class cse_design(ctypes.Structure):
@@ -75,6 +82,8 @@ def _load():
     L.cse_autotune.argtypes = [P, u64, i64, P, P]
     L.cse_taylor.argtypes = [P, P, P, P, P, P, P]
     L.cse_validate_lower.argtypes = [P, P, dbl, P, P, P, P]
+    L.cse_adagrid_decide.argtypes = [ctypes.POINTER(cse_adagrid_rule), i64, P, P, i64, P, P, P, P, P]
+    L.cse_adagrid_apply.argtypes = [i32, i64, P, P, P, P, i64, P, P, P, P, P, ctypes.POINTER(i64)]
     L.cse_confidence_set.argtypes = [P, P, i64, P, P, i32, P, P, P, P, P]
     L.cse_calibrate_tiebreak.argtypes = [P, u64, dbl] + [P] * 8
     L.cse_profile_enable.argtypes = [i32]
@@ -241,6 +250,37 @@ def cse_calibrate_tiebreak(h, seed, alpha, alpha_prime, k, lambda_tile, u_tile, 
     _check("cse_calibrate_tiebreak", _L.cse_calibrate_tiebreak(
         h, seed, alpha, _ptr(alpha_prime), _ptr(k), _ptr(lambda_tile), _ptr(u_tile), _ptr(lambda_global),
         _ptr(u_global), _ptr(reject_at_lambda), _stream(stream)))
+
+
+def cse_adagrid_decide(rule, radii, sims, tile_box, a, b, c):
+    """Host call: per-box decision codes (0 done, 1 split, 2 double N, 3 stuck)."""
+    radii = np.ascontiguousarray(radii, np.float64)
+    sims = np.ascontiguousarray(sims, np.int32)
+    tb = np.ascontiguousarray(tile_box, np.int64)
+    a, b, c = (np.ascontiguousarray(x, np.float64) for x in (a, b, c))
+    dec = np.zeros(len(sims), np.int32)
+    _check("cse_adagrid_decide", _L.cse_adagrid_decide(ctypes.byref(rule), len(sims), _ptr(radii), _ptr(sims),
+                                                       len(tb), _ptr(tb), _ptr(a), _ptr(b), _ptr(c), _ptr(dec)))
+    return dec
+
+
+def cse_adagrid_apply(theta, radii, sims, decision):
+    """Host call: the next box list (theta, radii, sims, parent, changed)."""
+    theta = np.ascontiguousarray(theta, np.float64)
+    radii = np.ascontiguousarray(radii, np.float64)
+    sims = np.ascontiguousarray(sims, np.int32)
+    dec = np.ascontiguousarray(decision, np.int32)
+    d = theta.shape[1]
+    n = ctypes.c_int64()
+    _check("cse_adagrid_apply", _L.cse_adagrid_apply(d, len(sims), _ptr(theta), _ptr(radii), _ptr(sims), _ptr(dec),
+                                                     0, None, None, None, None, None, ctypes.byref(n)))
+    m = n.value
+    th, rd = np.zeros((m, d)), np.zeros((m, d))
+    sm, par, ch = np.zeros(m, np.int32), np.zeros(m, np.int64), np.zeros(m, np.int32)
+    _check("cse_adagrid_apply", _L.cse_adagrid_apply(d, len(sims), _ptr(theta), _ptr(radii), _ptr(sims), _ptr(dec),
+                                                     m, _ptr(th), _ptr(rd), _ptr(sm), _ptr(par), _ptr(ch),
+                                                     ctypes.byref(n)))
+    return th, rd, sm, par, ch.astype(bool)
 
 
 def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):

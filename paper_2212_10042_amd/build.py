@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build", "cse")
 LIB = os.path.join(PKG, "libcse.so")
 ARCH = os.environ.get("CSE_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["platten.cpp", "api.hip", "k_sim.hip", "k_bound.hip", "k_select.hip", "k_hier4.hip", "k_phase23.hip"]
+SOURCES = ["platten.cpp", "adagrid.cpp", "api.hip", "k_sim.hip", "k_bound.hip", "k_select.hip", "k_hier4.hip", "k_phase23.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -1,0 +1,82 @@
+"""GPU: adaptive gridding runs (rounds of GPU validation or calibration on the boxes that
+changed, the library's host decision step, checkpoints) against the oracle's run of the same
+rule.  The 2-arm design's counts and thresholds are exact on both sides, so every round's
+decisions, the final boxes and simulation counts must be identical; bounds agree to 1e-9.
+A run stopped after two rounds and resumed from its checkpoint ends where an uninterrupted
+run ends."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2212_10042_amd.adagrid as AG
+import workloads as W
+from oracle import adagrid as OA
+
+pytestmark = pytest.mark.gpu
+
+
+def _case():
+    w = W.binom2_grid(4, 512, lo=-2.5, hi=0.5, seed=1)
+    return w["theta"], w["radii"], w["sims"]
+
+
+def _same_boxes(g, o):
+    assert np.array_equal(g["theta"], o["theta"]) and np.array_equal(g["radii"], o["radii"])
+    assert np.array_equal(g["sims"], o["sims"])
+    assert np.array_equal(g["decision"], o["decision"])
+    assert [tuple(h) for h in g["history"]] == [tuple(h) for h in o["history"]]
+    assert np.array_equal(g["tile_box"], o["box_of_tile"])
+
+
+def test_adaptive_validation_binom2_matches_oracle():
+    th, rd, sm = _case()
+    kw = dict(mode="validate", target=0.03, delta=0.01, r_min=3.0 / 256, n_max=16384, max_rounds=6)
+    print("[adagrid] validation binom2", flush=True)
+    g = AG.run("binom2", th, rd, sm, seed=4, **kw, on_round=lambda r, h: print(f"  round {r}: {h}", flush=True))
+    o = OA.run("binom2", th, rd, sm, seed=4, **kw)
+    _same_boxes(g, o)
+    assert g["rounds"] >= 2 and sum(h[1] for h in g["history"]) > 0 and sum(h[2] for h in g["history"]) > 0
+    np.testing.assert_allclose(g["a"], o["tiles"]["bound"], rtol=1e-9)
+    np.testing.assert_allclose(g["b"], o["tiles"]["cp"], rtol=1e-9)
+    assert np.array_equal(g["c"], o["tiles"]["fhat"])
+
+
+def test_adaptive_calibration_binom2_matches_oracle():
+    th, rd, sm = _case()
+    kw = dict(mode="calibrate", alpha=0.025, margin=0.05, r_min=3.0 / 512, n_max=1 << 15, max_rounds=5)
+    print("[adagrid] calibration binom2", flush=True)
+    g = AG.run("binom2", th, rd, sm, seed=6, **kw, on_round=lambda r, h: print(f"  round {r}: {h}", flush=True))
+    o = OA.run("binom2", th, rd, sm, seed=6, **kw)
+    _same_boxes(g, o)
+    assert np.array_equal(g["a"], o["tiles"]["lam"])
+    np.testing.assert_allclose(g["b"], o["tiles"]["alpha_prime"], rtol=1e-9)
+    assert g["a"].min() >= o["tiles"]["lam"].min()
+
+
+def test_checkpoint_resume(tmp_path):
+    th, rd, sm = _case()
+    kw = dict(mode="validate", target=0.03, delta=0.01, r_min=3.0 / 256, n_max=16384)
+    path = os.path.join(str(tmp_path), "grid.npz")
+    full = AG.run("binom2", th, rd, sm, seed=4, max_rounds=6, **kw)
+    AG.run("binom2", th, rd, sm, seed=4, max_rounds=2, checkpoint=path, **kw)
+    assert os.path.exists(path)
+    res = AG.run("binom2", th, rd, sm, seed=4, max_rounds=6, checkpoint=path, resume=True, **kw)
+    for k in ("theta", "radii", "sims", "decision", "tile_box", "a", "b", "c"):
+        assert np.array_equal(res[k], full[k]), k
+    assert res["history"] == full["history"]
+    with pytest.raises(ValueError):
+        AG.run("binom2", th, rd, sm, seed=5, max_rounds=6, checkpoint=path, resume=True, **kw)
+
+
+def test_ztest_adaptive_calibration_near_exact_threshold():
+    """z-test (float32 draws): adaptive calibration moves -lambda* to within 0.06 above the
+    exact level-alpha critical value 1.96."""
+    th = (np.arange(8) * 0.125 - 1.0 + 0.0625)[:, None]
+    rd = np.full((8, 1), 0.0625)
+    sims = np.full(8, 1000, np.int32)
+    g = AG.run("ztest1", th, rd, sims, seed=5, mode="calibrate", alpha=0.025, margin=0.0, r_min=1.0 / 1024,
+               n_max=1 << 17, max_rounds=40)
+    lam = g["a"].min()
+    print(f"[adagrid] ztest1 -lambda* {-lam:.4f} after {g['rounds']} rounds, {len(g['sims'])} boxes", flush=True)
+    assert 1.959963 <= -lam <= 1.96 + 0.06
