@@ -74,7 +74,86 @@ WORKLOADS = {
                   "delta 0.01; step = calibrate + validate + gradient",
     "phase23_c5_sub256": "the Phase II/III workload restricted to every 256th box (1,024 boxes), same sims "
                          "per box; step = calibrate + validate + gradient",
+    "binom2_adaptive": "binom2 n=35 pooled-z on [-3,1]^2 kept to theta1<=theta0, adaptive validation from "
+                       "16x16 boxes with 2,048 sims: rounds of GPU validation of the changed boxes, then split "
+                       "(half-width down to 1/128, the 256x256 grid's) or double N (up to 131,072) where the "
+                       "bound exceeds 0.03; seed 0, delta 0.01, at most 12 rounds; step = the whole adaptive run",
 }
+
+ADAPTIVE = dict(target=0.03, delta=0.01, r_min=1.0 / 128, n_max=1 << 17, max_rounds=12)
+
+
+def run_adaptive(args):
+    """The adaptive-gridding workload: a step is one whole adaptive run (every round's GPU
+    validation of the changed boxes, the library's host decisions, platten builds)."""
+    import numpy as np
+    import torch
+
+    import paper_2212_10042_amd as cse
+    import paper_2212_10042_amd.adagrid as AG
+    import workloads as W
+
+    w = W.binom2_grid(16, 2048, seed=0)
+
+    def once(progress=False):
+        return AG.run("binom2", w["theta"], w["radii"], w["sims"], seed=0, mode="validate", **ADAPTIVE,
+                      on_round=(lambda r, h: print(f"bench.py: round {r}: boxes, splits, doubles, stuck, "
+                                                   f"sims = {h}", file=sys.stderr, flush=True))
+                      if progress else None)
+
+    for _ in range(args.warmup):
+        once()
+    torch.cuda.synchronize()
+    cse.cse_profile_reset()
+    cse.cse_profile_enable(True)
+    t = time.perf_counter()
+    for i in range(args.steps):
+        res = once(progress=args.progress and i == 0)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / args.steps
+    cse.cse_profile_enable(False)
+    kern = {}
+    for kn in ("binom2", "bound_validate"):
+        cnt, ms = cse.cse_profile_get(kn)
+        if cnt:
+            kern[kn] = {"launches_per_step": cnt // args.steps, "ms_per_step": ms / args.steps}
+    spent = sum(h[4] for h in res["history"])
+    # the same domain on a uniform grid at the finest half-width, with the largest N used
+    m = int(round(4.0 / (2 * ADAPTIVE["r_min"])))
+    uniform = (m * (m + 1) // 2) * int(res["sims"].max())
+    U = np.full(len(res["sims"]), -np.inf)
+    np.maximum.at(U, res["tile_box"], res["a"])
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle as O
+        rng = np.random.default_rng(1234)
+        idx = np.sort(rng.choice(len(res["sims"]), min(len(res["sims"]), 24), replace=False))
+        tt = time.perf_counter()
+        v = O.validate("binom2", res["theta"][idx], res["radii"][idx], res["sims"][idx], 0, ADAPTIVE["delta"])
+        dtc = time.perf_counter() - tt
+        st = int(res["sims"][idx][np.unique(v["box"])].sum())
+        cpu = {"value": st / dtc, "unit": "sim·tiles/s", "cores": 1, "kind": "oracle",
+               "sample": f"oracle validate of {len(idx)} of the final boxes (uniform, seed 1234) at their final "
+                         f"sims, {dtc:.1f} s single-threaded"}
+    out = {
+        "metric": METRIC, "value": spent / dt, "unit": "sim·tiles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u32/f32/f64", "data": "synthetic",
+        "config": {"workload": WORKLOADS["binom2_adaptive"], "name": "binom2_adaptive",
+                   "parallelism": "single GPU"},
+        "adaptive": {"rounds": res["rounds"], "history": [list(h) for h in res["history"]],
+                     "final_boxes": len(res["sims"]), "final_tiles": len(res["tile_box"]),
+                     "sims_simulated": spent, "uniform_equivalent_sims": uniform,
+                     "savings": uniform / spent, "max_final_bound": float(U.max()),
+                     "boxes_above_target": int(np.sum(U > ADAPTIVE["target"])),
+                     "stuck_boxes": int(np.sum(res["decision"] == 3)),
+                     "sims_range": [int(res["sims"].min()), int(res["sims"].max())],
+                     "half_width_range": [float(res["radii"].min()), float(res["radii"].max())]},
+        "kernel_per_step": kern,
+        "roofline": None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def cpu_baseline(name, w, design, target_s: float = 15.0):
@@ -132,8 +211,8 @@ def main():
                     help="only copy this many bytes device-to-device 3 times (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU sharding is described "
-              "in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU sharding is not built",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -143,6 +222,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload == "binom2_adaptive":
+        run_adaptive(args)
+        return
     if args.copy_probe:
         src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
