@@ -71,6 +71,9 @@ def lib():
         L.orc_psucc.argtypes = [dbl, dbl, dbl, dbl, ctypes.c_int]
         L.orc_psucc.restype = dbl
         L.orc_tiebreak_u.argtypes = [u64, i64, P]
+        L.orc_basket_complement.argtypes = [P, ctypes.c_int, P, P]
+        L.orc_basket_table.argtypes = [ctypes.c_int, P, P, i64, P]
+        L.orc_basket_sim.argtypes = [i64, P, P, P, u64, ctypes.c_int, P, dbl, P, P, P, i64]
         L.orc_phase23_sim.argtypes = [i64, P, P, P, u64, dbl, P, P, P, P, i64, P, P]
         _lib = L
     return _lib
@@ -230,6 +233,81 @@ def sim_phase23(theta_tiles, cfg, sims, seed: int, lam: float, want_S=False, wan
 
 
 # --------------------------------------------------- exponential families
+# ------------------------------------------------------------ basket design (Section 10.1)
+# The standard-of-care rates p_0a are not given in the paper; Berry et al. (2013), whose design
+# the case study follows, use a null response rate of 15% in every basket.  The 85% posterior
+# rule rejects arm a when 1 - P(p_a > p_0a | y) < 0.15.
+BASKET_P0 = 0.15
+BASKET_THETA0 = np.full(4, math.log(BASKET_P0 / (1.0 - BASKET_P0)))
+BASKET_CUT = 0.15
+
+
+def _theta0(theta0):
+    return np.ascontiguousarray(BASKET_THETA0 if theta0 is None else theta0, np.float64).reshape(4)
+
+
+def basket_complement(y, n: int = N_PER_ARM, theta0=None) -> np.ndarray:
+    """1 - P(p_a > p_0a | y), a = 0..3, under the hierarchical model on the offsets
+    theta_a - theta_0a (Laplace mixture over 90 s2 nodes; pinned in tests/test_oracle_basket.py)."""
+    yy = np.ascontiguousarray(y, np.int32)
+    out = np.zeros(4)
+    lib().orc_basket_complement(_p(yy), n, _p(_theta0(theta0)), _p(out))
+    return out
+
+
+def basket_table(idx, n: int = N_PER_ARM, theta0=None) -> np.ndarray:
+    ii = np.ascontiguousarray(idx, np.int64)
+    out = np.zeros((ii.size, 4))
+    lib().orc_basket_table(n, _p(_theta0(theta0)), _p(ii), ii.size, _p(out))
+    return out
+
+
+def sim_basket(theta_tiles, cfg, sims, seed: int, cut: float = BASKET_CUT, theta0=None, n: int = N_PER_ARM,
+               want_S: bool = False):
+    """Basket design per tile (centre, configuration b, bit a = H_a): R, sum_rej y, S_b."""
+    th = np.ascontiguousarray(theta_tiles, np.float64).reshape(-1, 4)
+    cf = np.ascontiguousarray(cfg, np.int32)
+    sm = np.ascontiguousarray(sims, np.int32)
+    m = th.shape[0]
+    R = np.zeros(m, np.int32)
+    sT = np.zeros((m, 4), np.int64)
+    stride = int(sm.max()) if m else 0
+    S = np.full((m, stride), np.nan) if want_S else None
+    lib().orc_basket_sim(m, _p(th), _p(cf), _p(sm), seed, n, _p(_theta0(theta0)), cut, _p(R), _p(sT), _p(S),
+                         stride)
+    return R, sT, S
+
+
+def basket_subboxes(theta, radii, theta0=None):
+    """The basket design's null boundaries theta_a = theta_0a are axis-aligned, so every piece
+    box ∩ P(b) is itself a box: each box is cut at the boundaries it straddles, and each piece
+    with b != 0 (bit a set when the piece lies in theta_a <= theta_0a) becomes a tile simulated
+    at its own centre.  Pieces of a box are listed by b ascending.  Returns a list of
+    (box index, b, centre [4], radii [4])."""
+    t0 = _theta0(theta0)
+    theta = np.asarray(theta, np.float64)
+    radii = np.asarray(radii, np.float64)
+    out = []
+    for i in range(theta.shape[0]):
+        parts = []   # per arm: list of (centre, radius, in_null)
+        for a in range(4):
+            c, r = theta[i, a], radii[i, a]
+            lo, hi = c - r, c + r
+            if lo < t0[a] < hi:
+                parts.append([(0.5 * (lo + t0[a]), 0.5 * (t0[a] - lo), True),
+                              (0.5 * (t0[a] + hi), 0.5 * (hi - t0[a]), False)])
+            else:
+                parts.append([(c, r, hi <= t0[a])])
+        pieces = []
+        for combo in itertools.product(*parts):
+            b = sum(1 << a for a in range(4) if combo[a][2])
+            if b:
+                pieces.append((b, np.array([x[0] for x in combo]), np.array([x[1] for x in combo])))
+        for b, c, r in sorted(pieces, key=lambda q: q[0]):
+            out.append((i, b, c, r))
+    return out
+
+
 def log_partition(family: str, theta: np.ndarray, n: int = N_PER_ARM) -> np.ndarray:
     """A(theta) over the last axis: normal location theta^2/2 (Section 4.2);
     independent binomial arms in logit, sum_a n softplus(theta_a) (Example 1)."""
@@ -409,6 +487,8 @@ def hypotheses(design: str, d: int):
 
 
 def family_of(design: str) -> str:
+    if design == "basket4":
+        return "binom"
     return "normal" if design == "ztest1" else "binom"
 
 
@@ -432,7 +512,7 @@ def _enumerate_vertices(G, h, d, tol=1e-12):
     return np.array(verts)
 
 
-def subtiles(design: str, theta, radii, keep_all: bool = False):
+def subtiles(design: str, theta, radii, keep_all: bool = False, theta0=None):
     """Split each box into its null-configuration pieces box ∩ P(b) with non-empty interior
     (Section 4, Definition 1).  Returns a list of (box index, b bitmask, vertices [nv, d],
     in_null flag); b bit j-1 is hypothesis j.  With keep_all (single-hypothesis designs only),
@@ -440,6 +520,10 @@ def subtiles(design: str, theta, radii, keep_all: bool = False):
     """
     theta = np.asarray(theta, np.float64)
     radii = np.asarray(radii, np.float64)
+    if design == "basket4":
+        # (box, b, vertices, in_null, centre): the pieces are boxes simulated at their centres
+        sgn = np.array(list(itertools.product([-1.0, 1.0], repeat=4)))[:, ::-1]
+        return [(i, b, c + sgn * r, True, c) for i, b, c, r in basket_subboxes(theta, radii, theta0)]
     m, d = theta.shape
     hyps = hypotheses(design, d)
     p = len(hyps)
@@ -480,12 +564,19 @@ def subtiles(design: str, theta, radii, keep_all: bool = False):
     return out
 
 
+def _tile_centres(subs, theta):
+    """Simulation point of each tile: the box centre, or the piece's own centre (basket)."""
+    return np.array([s[4] if len(s) > 4 else theta[s[0]] for s in subs]).reshape(len(subs), -1)
+
+
 def _pad_vertices(subs, theta):
     nv = max(len(s[2]) for s in subs)
     d = theta.shape[1]
     V = np.zeros((len(subs), nv, d))
-    for t, (i, b, verts, _) in enumerate(subs):
-        disp = verts - theta[i]
+    cen = _tile_centres(subs, theta)
+    for t, s in enumerate(subs):
+        verts = s[2]
+        disp = verts - cen[t]
         V[t, : len(disp)] = disp
         V[t, len(disp):] = disp[0]
     return V
@@ -517,10 +608,15 @@ def score_gradient(design: str, theta, R, score, sims, n: int = N_PER_ARM):
     return (np.asarray(score, np.float64) - np.asarray(R, np.float64)[:, None] * gA) / N[:, None]
 
 
-def _tile_simulation(design, theta, sims, subs, seed, cut, want_S):
+def _tile_simulation(design, theta, sims, subs, seed, cut, want_S, theta0=None):
     """Per-tile (R, score, S) for the tiles `subs`: single-hypothesis designs simulate per box;
     the 4-arm design per (box, b) because its event depends on b."""
     box = np.array([s[0] for s in subs])
+    if design == "basket4":
+        cfg = np.array([s[1] for s in subs], np.int32)
+        R, sT, S = sim_basket(_tile_centres(subs, theta), cfg, np.asarray(sims)[box], seed, cut, theta0,
+                              want_S=want_S)
+        return R, sT, S
     if design == "hier4":
         cfg = np.array([s[1] for s in subs], np.int32)
         R, sT, S, _ = sim_hier4(theta[box], cfg, np.asarray(sims)[box], seed, cut, want_S=want_S)
@@ -535,21 +631,22 @@ def _tile_simulation(design, theta, sims, subs, seed, cut, want_S):
 
 
 def validate(design: str, theta, radii, sims, seed: int, delta: float, cut: float = 1.96,
-             keep_all: bool = False):
+             keep_all: bool = False, theta0=None):
     """Validation (Algorithm 1): per sub-tile R, CP upper bound, tilewise optimized Tilt-Bound."""
     theta = np.asarray(theta, np.float64)
-    subs = subtiles(design, theta, radii, keep_all)
+    subs = subtiles(design, theta, radii, keep_all, theta0)
     box = np.array([s[0] for s in subs])
     N = np.asarray(sims)[box]
-    Rb, score, _ = _tile_simulation(design, theta, sims, subs, seed, cut, False)
+    Rb, score, _ = _tile_simulation(design, theta, sims, subs, seed, cut, False, theta0)
     cp = cp_upper(Rb, N, delta)
     V = _pad_vertices(subs, theta)
-    ub, qs = tile_bound(family_of(design), theta[box], V, cp, n=n_of(design))
+    cen = _tile_centres(subs, theta)
+    ub, qs = tile_bound(family_of(design), cen, V, cp, n=n_of(design))
     cpl = cp_lower(Rb, N, delta)
-    lb, _ = tile_lower(family_of(design), theta[box], V, cpl, n=n_of(design))
+    lb, _ = tile_lower(family_of(design), cen, V, cpl, n=n_of(design))
     out = dict(box=box, b=np.array([s[1] for s in subs]), R=Rb, N=N, cp=cp, bound=ub,
                q=qs, score=score, subs=subs, cp_lower=cpl, lower=lb)
-    if design not in ("hier4", "phase23"):
+    if design not in ("hier4", "phase23", "basket4"):
         R, sc, _ = simulate(design, theta, sims, seed, cut)
         out.update(R_box=R, score_box=sc)
     return out
@@ -583,20 +680,20 @@ def order_statistic_pair(S_row: np.ndarray, u_row: np.ndarray, k: int):
 
 
 def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False,
-              key_dtype=np.float64, cut: float = 1.96):
+              key_dtype=np.float64, cut: float = 1.96, theta0=None):
     """Calibration (Algorithm 2): alpha'_i, k_i = floor((N_i+1) alpha'_i), lambda*_i = S_(k_i),
     lambda* = min_i lambda*_i, and #{S < lambda*_i} per sub-tile.  key_dtype=np.float32 takes the
     order statistic and the comparisons in float32 (the precision in which the GPU compares
     the 4-arm statistic)."""
     theta = np.asarray(theta, np.float64)
     sims = np.asarray(sims, np.int32)
-    subs = subtiles(design, theta, radii, keep_all)
+    subs = subtiles(design, theta, radii, keep_all, theta0)
     box = np.array([s[0] for s in subs])
     V = _pad_vertices(subs, theta)
-    ap, qs = tile_inverse(family_of(design), theta[box], V, alpha, n=n_of(design))
+    ap, qs = tile_inverse(family_of(design), _tile_centres(subs, theta), V, alpha, n=n_of(design))
     N = sims[box]
     k = np.floor((N + 1.0) * ap).astype(np.int64)
-    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True)
+    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True, theta0)
     lam = np.empty(len(subs))
     rej = np.empty(len(subs), np.int64)
     for t in range(len(subs)):
@@ -609,20 +706,20 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
 
 
 def calibrate_tiebreak(design: str, theta, radii, sims, seed: int, alpha: float, keep_all: bool = False,
-                       key_dtype=np.float64, cut: float = 1.96):
+                       key_dtype=np.float64, cut: float = 1.96, theta0=None):
     """Randomised calibration: the statistic becomes the pair (S, u) with u from tiebreak_u and
     the threshold the pair (lambda, c), both compared lexicographically.  Per tile: alpha'_i and
     k_i as in calibrate, (lambda_i, c_i) = the k_i-th smallest pair, and the number of pairs
     strictly below it; globally the lexicographic minimum of (lambda_i, c_i)."""
     theta = np.asarray(theta, np.float64)
     sims = np.asarray(sims, np.int32)
-    subs = subtiles(design, theta, radii, keep_all)
+    subs = subtiles(design, theta, radii, keep_all, theta0)
     box = np.array([s[0] for s in subs])
     V = _pad_vertices(subs, theta)
-    ap, _ = tile_inverse(family_of(design), theta[box], V, alpha, n=n_of(design))
+    ap, _ = tile_inverse(family_of(design), _tile_centres(subs, theta), V, alpha, n=n_of(design))
     N = sims[box]
     k = np.floor((N + 1.0) * ap).astype(np.int64)
-    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True)
+    _, _, S = _tile_simulation(design, theta, sims, subs, seed, cut, True, theta0)
     u = tiebreak_u(seed, int(N.max()) if len(N) else 0)
     lam = np.empty(len(subs))
     c = np.zeros(len(subs), np.int64)

@@ -343,3 +343,155 @@ void orc_hier4_sim(int64_t n_tiles, const double *theta, const int32_t *cfg, con
             for (int a = 0; a < D; ++a) sumT[t * D + a] = st[a];
     }
 }
+
+/* ------------------------------------------------------------------ basket design
+ * Bayesian basket trial (Section 10.1, validation case study): four arms, each against its own
+ * fixed standard-of-care rate p_0a (theta_0a = logit p_0a).  The hierarchical model is on the
+ * offsets delta_a = theta_a - theta_0a:
+ *     delta_a | mu, s2 ~ N(mu, s2),  mu ~ N(-1.34, 100),  s2 ~ InvGamma(0.0005, 0.000005),
+ *     y_a ~ Binom(n, expit(theta_a)).
+ * In theta the prior has mean -1.34 + theta_0a per arm and the same covariance, so the reading
+ * above applies unchanged (90 s2 nodes, Laplace per node, Laplace evidence weights).  The
+ * statistic of arm a is P(p_a > p_0a | y) = P(theta_a > theta_0a | y); its complement is
+ * summed directly, sum_j pi_j Phi(-(mode_ja - theta_0a) / sqrt(C_j,aa)).
+ * All float64, generic 4x4 elimination as above.
+ */
+void orc_basket_complement(const int32_t *y, int n, const double *theta0, double *Sc) {
+    double lw[NODES], pc[NODES][D];
+    for (int j = 0; j < NODES; ++j) {
+        double ls2, logtrap;
+        orc_hier4_node(j, &ls2, &logtrap);
+        const double s2 = exp(ls2);
+        double Q[D][D];
+        const double cq = TAU2 / (s2 + D * TAU2);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) Q[r][c] = ((r == c ? 1.0 : 0.0) - cq) / s2;
+        const double logdetQ = -((D - 1) * ls2 + log(s2 + D * TAU2));
+        double mean[D], th[D], H[D][D];
+        for (int a = 0; a < D; ++a) {
+            mean[a] = M0 + theta0[a];
+            th[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
+        }
+        for (int it = 0; it < 200; ++it) {
+            double g[D];
+            for (int a = 0; a < D; ++a) {
+                double qa = 0.0;
+                for (int c = 0; c < D; ++c) qa += Q[a][c] * (th[c] - mean[c]);
+                g[a] = y[a] - n * expit(th[a]) - qa;
+            }
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    const double p = expit(th[r]);
+                    H[r][c] = -Q[r][c] - (r == c ? n * p * (1.0 - p) : 0.0);
+                }
+            double A[D][D], step[D], rhs[D];
+            memcpy(A, H, sizeof A);
+            for (int a = 0; a < D; ++a) rhs[a] = g[a];
+            solve4(A, rhs, step);
+            double mx = 0.0;
+            for (int a = 0; a < D; ++a) {
+                th[a] -= step[a];
+                mx = fmax(mx, fabs(step[a]));
+            }
+            if (mx < 1e-10) break;
+        }
+        double negH[D][D];
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) {
+                const double p = expit(th[r]);
+                negH[r][c] = Q[r][c] + (r == c ? n * p * (1.0 - p) : 0.0);
+            }
+        double ll = 0.0, quad = 0.0;
+        for (int a = 0; a < D; ++a) ll += y[a] * th[a] - n * softplus(th[a]);
+        for (int r = 0; r < D; ++r)
+            for (int c = 0; c < D; ++c) quad += (th[r] - mean[r]) * Q[r][c] * (th[c] - mean[c]);
+        const double lap = ll - 0.5 * quad + 0.5 * logdetQ - 0.5 * logdet4(negH);
+        const double logprior = IG_A * log(IG_B) - lgamma(IG_A) - (IG_A + 1.0) * ls2 - IG_B / s2;
+        lw[j] = lap + logprior + logtrap;
+        for (int a = 0; a < D; ++a) {
+            double A[D][D], e[D] = {0, 0, 0, 0}, x[D];
+            memcpy(A, negH, sizeof A);
+            e[a] = 1.0;
+            solve4(A, e, x);                           /* x_a = C_aa */
+            pc[j][a] = Phi(-(th[a] - theta0[a]) / sqrt(x[a]));
+        }
+    }
+    double mx = -INFINITY;
+    for (int j = 0; j < NODES; ++j) mx = fmax(mx, lw[j]);
+    double s = 0.0;
+    for (int j = 0; j < NODES; ++j) s += exp(lw[j] - mx);
+    const double lse = mx + log(s);
+    for (int a = 0; a < D; ++a) Sc[a] = 0.0;
+    for (int j = 0; j < NODES; ++j) {
+        const double pj = exp(lw[j] - lse);
+        for (int a = 0; a < D; ++a) Sc[a] += pj * pc[j][a];
+    }
+}
+
+/* Statistics 1 - P_a(y), a = 0..3, for a list of outcome indices ((y0 m + y1) m + y2) m + y3. */
+void orc_basket_table(int n, const double *theta0, const int64_t *idx, int64_t count, double *out) {
+    const int64_t m = n + 1;
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t v = idx[t];
+        int32_t y[D];
+        for (int a = D - 1; a >= 0; --a) {
+            y[a] = (int32_t)(v % m);
+            v /= m;
+        }
+        orc_basket_complement(y, n, theta0, out + D * t);
+    }
+}
+
+/* Tiles are (centre theta [4], configuration b): bit a of b set when H_a: theta_a <= theta_0a
+ * holds on the tile.  Simulation k draws arm a, patient j from word a*n + j.  The statistic is
+ * S_b = min_{a in b} (1 - P_a(y)); the design rejects a true null (the FWER event) when
+ * S_b < cut (cut = 0.15 for the 85% rule).  Outputs as orc_hier4_sim. */
+static double *g_bmemo = NULL;
+static unsigned char *g_bhave = NULL;
+static int g_bmemo_n = -1;
+static double g_bmemo_t0[D];
+
+void orc_basket_sim(int64_t n_tiles, const double *theta, const int32_t *cfg, const int32_t *sims,
+                    uint64_t seed, int n, const double *theta0, double cut, int32_t *R, int64_t *sumT,
+                    double *S, int64_t s_stride) {
+    const int64_t m = n + 1;
+    if (g_bmemo_n != n || memcmp(g_bmemo_t0, theta0, sizeof g_bmemo_t0) != 0) {
+        free(g_bmemo);
+        free(g_bhave);
+        g_bmemo = (double *)malloc(sizeof(double) * D * m * m * m * m);
+        g_bhave = (unsigned char *)calloc((size_t)(m * m * m * m), 1);
+        g_bmemo_n = n;
+        memcpy(g_bmemo_t0, theta0, sizeof g_bmemo_t0);
+    }
+    for (int64_t t = 0; t < n_tiles; ++t) {
+        uint32_t T[D];
+        for (int a = 0; a < D; ++a) T[a] = orc_bern_threshold(theta[t * D + a]);
+        int32_t r = 0;
+        int64_t st[D] = {0, 0, 0, 0};
+        for (int32_t k = 0; k < sims[t]; ++k) {
+            int32_t y[D];
+            for (int a = 0; a < D; ++a) {
+                y[a] = 0;
+                for (int j = 0; j < n; ++j)
+                    if (orc_word(seed, (uint32_t)k, (uint32_t)(a * n + j)) < T[a]) y[a] += 1;
+            }
+            const int64_t idx = ((y[0] * m + y[1]) * m + y[2]) * m + y[3];
+            if (!g_bhave[idx]) {
+                orc_basket_complement(y, n, theta0, g_bmemo + D * idx);
+                g_bhave[idx] = 1;
+            }
+            const double *Sc = g_bmemo + D * idx;
+            double s = INFINITY;
+            for (int a = 0; a < D; ++a)
+                if ((cfg[t] >> a) & 1) s = fmin(s, Sc[a]);
+            if (s < cut) {
+                r += 1;
+                for (int a = 0; a < D; ++a) st[a] += y[a];
+            }
+            if (S) S[t * s_stride + k] = s;
+        }
+        R[t] = r;
+        if (sumT)
+            for (int a = 0; a < D; ++a) sumT[t * D + a] = st[a];
+    }
+}
