@@ -70,16 +70,25 @@ typedef enum {
      * the observed sample sizes.  Statistic for null configuration b: -inf for an early
      * success with s in b, 1 - P_final(p_s > p_0) for a final analysis with s in b, +inf
      * otherwise; a false rejection at lambda is S < lambda.  d = 4. */
-    CSE_PHASE23 = 4
+    CSE_PHASE23 = 4,
+    /* Bayesian basket trial (Section 10.1, the validation case study after Berry et al.):
+     * four arms of n patients, arm a against its fixed rate p_0a (theta0[a] = logit p_0a),
+     * hierarchical model of CSE_HIER4 on the offsets theta_a - theta0[a]; H_a: theta_a <=
+     * theta0[a] for a = 0..3 (bit a of b); statistic S_b = min_{a in b} (1 - P(p_a > p_0a | y)),
+     * reject when S_b < cut (0.15: the 85% rule).  The null boundaries are axis-aligned, so each
+     * piece box ∩ P(b) is a box: boxes are cut at the boundaries they straddle and every piece
+     * with b != 0 is a tile simulated at its own centre (cse_platten_tiles).  d = 4. */
+    CSE_BASKET4 = 5
 } cse_design_kind;
 
 typedef struct {
     int32_t kind;       /* cse_design_kind                                      */
-    int32_t n_arms;     /* d: 1 (ZTEST1), 2 (BINOM2_Z), 4 (HIER4, PHASE23)       */
-    int32_t n_per_arm;  /* patients per arm: 35 for BINOM2_Z and HIER4, 350 (the embedding)
-                           for PHASE23; ignored for ZTEST1                        */
+    int32_t n_arms;     /* d: 1 (ZTEST1), 2 (BINOM2_Z), 4 (HIER4, PHASE23, BASKET4) */
+    int32_t n_per_arm;  /* patients per arm: 35 for BINOM2_Z, HIER4 and BASKET4, 350 (the
+                           embedding) for PHASE23; ignored for ZTEST1             */
     int32_t reserved;   /* must be 0                                             */
     double cut;         /* fixed rule of the design used by cse_simulate/validate */
+    double theta0[4];   /* BASKET4: logit of each arm's fixed rate p_0a; ignored otherwise */
 } cse_design;
 
 typedef struct cse_platten cse_platten;
@@ -113,6 +122,14 @@ int cse_platten_destroy(cse_platten *p);
 
 /* Number of tiles (box pieces) in the platten; < 0 on a NULL handle. */
 int64_t cse_platten_size(const cse_platten *p);
+
+/*
+ * cse_platten_tiles -- host copies of each tile's simulation point and half-widths
+ * (float64 [n_tiles][d] each, either may be NULL): the box's centre and half-widths, except
+ * for CSE_BASKET4, whose tiles are the pieces of a box cut at the null boundaries.
+ * Errors: CSE_EINVAL (NULL platten).
+ */
+int cse_platten_tiles(const cse_platten *p, double *theta, double *radii);
 
 /*
  * cse_platten_describe -- host copies of the tile list (any pointer may be NULL):

@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libcse.so")
 
 CSE_OK, CSE_EINVAL, CSE_ENOMEM, CSE_EHIP, CSE_EUNSUPPORTED, CSE_ECALIB = 0, -1, -2, -3, -4, -5
-CSE_ZTEST1, CSE_BINOM2_Z, CSE_HIER4, CSE_PHASE23 = 1, 2, 3, 4
+CSE_ZTEST1, CSE_BINOM2_Z, CSE_HIER4, CSE_PHASE23, CSE_BASKET4 = 1, 2, 3, 4, 5
+BASKET_P0 = 0.15   # standard-of-care rate of every basket unless given (not stated in the paper)
 CSE_PLATTEN_KEEP_ALL = 1
 
 EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cse_platten_describe",
@@ -32,7 +33,7 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
             "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
             "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_adagrid_decide",
-            "cse_adagrid_apply", "cse_last_error")
+            "cse_adagrid_apply", "cse_platten_tiles", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -49,7 +50,7 @@ class cse_adagrid_rule(ctypes.Structure):
 
 class cse_design(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_arms", ctypes.c_int32), ("n_per_arm", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("cut", ctypes.c_double)]
+                ("reserved", ctypes.c_int32), ("cut", ctypes.c_double), ("theta0", ctypes.c_double * 4)]
 
 
 def _load():
@@ -65,6 +66,7 @@ def _load():
     L.cse_platten_size.argtypes = [P]
     L.cse_platten_size.restype = i64
     L.cse_platten_describe.argtypes = [P, P, P, P, P]
+    L.cse_platten_tiles.argtypes = [P, P, P]
     L.cse_simulate.argtypes = [P, u64, P, P, P, P, P]
     L.cse_validate.argtypes = [P, u64, dbl, P, P, P, P, P, P, P, P]
     L.cse_calibrate.argtypes = [P, u64, dbl, P, P, P, P, P, dbl, P, P, P, P, P, P, P]
@@ -125,16 +127,31 @@ def _stream(stream=None):
 
 
 # ------------------------------------------------------------------ C-ABI mirrors
-def make_design(kind: str | int, cut: float | None = None, n_per_arm: int | None = None) -> cse_design:
+def make_design(kind: str | int, cut: float | None = None, n_per_arm: int | None = None,
+                theta0=None) -> cse_design:
     """Design descriptor.  cut defaults: 1.96 (z designs), 0.05 (4-arm hierarchical),
-    0.06253 (Phase II/III final-analysis lambda); n_per_arm: 35, or the embedding's 350."""
-    k = {"ztest1": CSE_ZTEST1, "binom2": CSE_BINOM2_Z, "hier4": CSE_HIER4, "phase23": CSE_PHASE23}.get(kind, kind)
-    d = {CSE_ZTEST1: 1, CSE_BINOM2_Z: 2, CSE_HIER4: 4, CSE_PHASE23: 4}[k]
+    0.06253 (Phase II/III final-analysis lambda), 0.15 (basket: the 85% rule); n_per_arm: 35,
+    or the embedding's 350; theta0 (basket): logit of each arm's fixed rate, default
+    logit(0.15) for every arm."""
+    k = {"ztest1": CSE_ZTEST1, "binom2": CSE_BINOM2_Z, "hier4": CSE_HIER4, "phase23": CSE_PHASE23,
+         "basket4": CSE_BASKET4}.get(kind, kind)
+    d = {CSE_ZTEST1: 1, CSE_BINOM2_Z: 2, CSE_HIER4: 4, CSE_PHASE23: 4, CSE_BASKET4: 4}[k]
     if cut is None:
-        cut = {CSE_ZTEST1: 1.96, CSE_BINOM2_Z: 1.96, CSE_HIER4: 0.05, CSE_PHASE23: 0.06253}[k]
+        cut = {CSE_ZTEST1: 1.96, CSE_BINOM2_Z: 1.96, CSE_HIER4: 0.05, CSE_PHASE23: 0.06253, CSE_BASKET4: 0.15}[k]
     if n_per_arm is None:
         n_per_arm = 0 if k == CSE_ZTEST1 else (350 if k == CSE_PHASE23 else 35)
-    return cse_design(k, d, n_per_arm, 0, float(cut))
+    t0 = np.zeros(4)
+    if k == CSE_BASKET4:
+        t0 = np.full(4, np.log(BASKET_P0 / (1 - BASKET_P0))) if theta0 is None else np.asarray(theta0, np.float64)
+    return cse_design(k, d, n_per_arm, 0, float(cut), (ctypes.c_double * 4)(*[float(x) for x in t0]))
+
+
+def cse_platten_tiles(h, n_tiles: int, d: int):
+    """Host copies of every tile's simulation point and half-widths."""
+    th = np.zeros((n_tiles, d))
+    rd = np.zeros((n_tiles, d))
+    _check("cse_platten_tiles", _L.cse_platten_tiles(h, _ptr(th), _ptr(rd)))
+    return th, rd
 
 
 def cse_platten_create(design: cse_design, theta, radii, sims, flags: int = 0):
@@ -343,10 +360,13 @@ class Platten:
     tiles: dict
 
     @classmethod
-    def create(cls, kind, theta, radii, sims, cut=None, keep_all=False):
-        des = make_design(kind, cut)
+    def create(cls, kind, theta, radii, sims, cut=None, keep_all=False, theta0=None):
+        des = make_design(kind, cut, theta0=theta0)
         h = cse_platten_create(des, theta, radii, sims, CSE_PLATTEN_KEEP_ALL if keep_all else 0)
-        return cls(h, des, cse_platten_size(h), des.n_arms, cse_platten_describe(h))
+        n = cse_platten_size(h)
+        tiles = cse_platten_describe(h)
+        tiles["theta"], tiles["radii"] = cse_platten_tiles(h, n, des.n_arms)
+        return cls(h, des, n, des.n_arms, tiles)
 
     def close(self):
         if self.handle:
@@ -368,7 +388,7 @@ class Platten:
             score_T=(torch.empty((n, d), dtype=torch.int64, device=dev) if kind == CSE_BINOM2_Z else
                      torch.empty((n, 2 * d), dtype=torch.int64, device=dev) if kind == CSE_PHASE23 else None),
             score_Z=torch.empty(n, dtype=torch.float64, device=dev) if kind == CSE_ZTEST1 else None,
-            grad=torch.empty((n, d), dtype=torch.float64, device=dev) if kind != CSE_HIER4 else None,
+            grad=torch.empty((n, d), dtype=torch.float64, device=dev) if kind not in (CSE_HIER4, CSE_BASKET4) else None,
         )
 
     def simulate(self, seed=0, device="cuda"):

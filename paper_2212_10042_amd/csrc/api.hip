@@ -55,8 +55,8 @@ bool in_unit(double x) { return x > 0.0 && x < 1.0; }
 // The 4-arm design produces rejection counts and calibration keys; score sums are not formed.
 int check_scores(const cse::Platten &P, const void *score_T, const void *score_Z, const void *grad,
                  const char *fn) {
-    if (P.design.kind == CSE_HIER4 && (score_T || score_Z || grad)) {
-        set_error(std::string(fn) + ": score sums and gradients are not available for CSE_HIER4");
+    if ((P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) && (score_T || score_Z || grad)) {
+        set_error(std::string(fn) + ": score sums and gradients are not available for CSE_HIER4 and CSE_BASKET4");
         return CSE_EUNSUPPORTED;
     }
     return CSE_OK;
@@ -128,8 +128,9 @@ int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
         CSE_LAUNCH(cse::launch_zero(P.d_Zw, P.n_tiles * sizeof(unsigned long long), st));
         Timed tm(keys ? "ztest1_calib" : "ztest1", st);
         CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, keys ? (float *)P.d_keys : nullptr, st));
-    } else if (P.design.kind == CSE_HIER4) {
-        Timed tm(keys ? "hier4_calib" : "hier4", st);
+    } else if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {
+        const bool bk = P.design.kind == CSE_BASKET4;
+        Timed tm(keys ? (bk ? "basket4_calib" : "hier4_calib") : (bk ? "basket4" : "hier4"), st);
         CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, keys ? (float *)P.d_keys : nullptr, st));
     } else if (P.design.kind == CSE_PHASE23) {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * 2 * P.d * sizeof(unsigned long long), st));
@@ -288,6 +289,18 @@ int cse_platten_destroy(cse_platten *p) {
 }
 
 int64_t cse_platten_size(const cse_platten *p) { return p ? p->P.n_tiles : -1; }
+
+int cse_platten_tiles(const cse_platten *p, double *theta, double *radii) {
+    if (!p) {
+        set_error("cse_platten_tiles: NULL platten");
+        return CSE_EINVAL;
+    }
+    const auto &P = p->P;
+    const size_t n = (size_t)P.n_tiles * P.d;
+    if (theta) std::copy(P.tile_theta.begin(), P.tile_theta.begin() + n, theta);
+    if (radii) std::copy(P.tile_radii.begin(), P.tile_radii.begin() + n, radii);
+    return CSE_OK;
+}
 
 int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32_t *n_vert,
                          int32_t *in_null) {
@@ -520,7 +533,7 @@ int cse_autotune(cse_platten *p, uint64_t seed, int64_t max_trials, int64_t out[
     }
     // one-wave-per-block (z-test) or group kernels (2-arm, 4-arm): time the calibration launch
     if (int e = ensure_keys(P)) return e;
-    const bool group = P.design.kind == CSE_BINOM2_Z || P.design.kind == CSE_HIER4;
+    const bool group = P.design.kind == CSE_BINOM2_Z || P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4;
     const int64_t cands[5] = {1024, 2048, 4096, 8192, 16384};
     const int64_t wave_cands[5] = {4096, 8192, 16384, 32768, 65536};
     float best = 3.4e38f;
@@ -674,7 +687,7 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
     CSE_LAUNCH(cse::launch_zero(reject + tile_begin, (tile_end - tile_begin) * sizeof(int32_t), st));
     for (int64_t t = tile_begin; t < tile_end; ++t) {
         Timed tm("plain_tile", st);
-        if (P.design.kind == CSE_HIER4) {
+        if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {
             CSE_LAUNCH(cse::launch_hier4_plain(P, seed, t, (uint32_t *)(reject + t), st));
             continue;
         }
@@ -737,7 +750,7 @@ int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int6
                         void *stream) {
     if (int e = check_handle(p, "cse_posterior_table")) return e;
     const auto &P = p->P;
-    if (P.design.kind != CSE_HIER4 || !P.d_h4tbl) {
+    if ((P.design.kind != CSE_HIER4 && P.design.kind != CSE_BASKET4) || !P.d_h4tbl) {
         set_error("cse_posterior_table: the platten's design has no posterior table");
         return CSE_EUNSUPPORTED;
     }

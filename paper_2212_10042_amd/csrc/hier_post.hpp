@@ -184,4 +184,79 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
     }
 }
 
+// Basket design (Section 10.1's validation case study): arm a against its fixed rate,
+// theta0[a] = logit p_0a; the hierarchical model is on the offsets theta_a - theta0[a], so in
+// theta the prior mean is m0 + theta0[a] per arm with the same covariance, and the statistic
+// of arm a is P(theta_a > theta0[a] | y).  Writes the complements
+// Sc[a] = sum_j pi_j Phi(-(mode_a - theta0[a]) / sqrt(C_aa)), C_aa = u_a + g u_a^2.
+__device__ __forceinline__ void basket_posterior(const int y[4], double n, const double theta0[4],
+                                                 const HierNode *__restrict__ nodes, double Sc[4]) {
+    const double M0 = -1.34;
+    double mean[4], th[4];
+    for (int a = 0; a < 4; ++a) {
+        mean[a] = M0 + theta0[a];
+        th[a] = log((y[a] + 0.5) / (n - y[a] + 0.5));
+    }
+    double wmax = -INFINITY, wsum = 0.0, acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < HP_NODES; ++j) {
+        const HierNode nd = nodes[j];   // uniform across lanes
+        const double inv_s2 = nd.inv_s2, c = nd.c, beta = nd.beta;
+        double D[4], u[4], gam = 0.0;
+        for (int it = 0; it < 100; ++it) {   // warm start: the previous node's mode
+            double dsum = 0.0;
+            for (int a = 0; a < 4; ++a) dsum += th[a] - mean[a];
+            double g[4], su = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double p = hp_expit(th[a]);
+                g[a] = (double)y[a] - n * p - ((th[a] - mean[a]) - c * dsum) * inv_s2;
+                D[a] = n * p * (1.0 - p) + inv_s2;
+                u[a] = rcp_nr(D[a]);
+                su += u[a];
+            }
+            gam = beta * rcp_nr(1.0 - beta * su);
+            double ug = 0.0;
+            for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
+            double mx = 0.0;
+            for (int a = 0; a < 4; ++a) {
+                const double step = u[a] * g[a] + gam * u[a] * ug;
+                th[a] += step;
+                mx = fmax(mx, fabs(step));
+            }
+            if (mx < 1e-10) break;
+        }
+        double su = 0.0, prodD = 1.0, ll = 0.0, dsum = 0.0, sq = 0.0;
+        for (int a = 0; a < 4; ++a) {
+            double sp;
+            const double p = hp_expit_softplus(th[a], sp);
+            D[a] = n * p * (1.0 - p) + inv_s2;
+            u[a] = rcp_nr(D[a]);
+            su += u[a];
+            prodD *= D[a];
+            ll += y[a] * th[a] - n * sp;
+            const double e = th[a] - mean[a];
+            dsum += e;
+            sq += e * e;
+        }
+        gam = beta * rcp_nr(1.0 - beta * su);
+        const double logdet_negH = log(prodD) + log1p(-beta * su);
+        const double quad = (sq - c * dsum * dsum) * inv_s2;
+        const double lw = ll - 0.5 * quad - 0.5 * logdet_negH + nd.lconst;
+        double pc[4];
+        for (int a = 0; a < 4; ++a) {
+            const double caa = u[a] + gam * u[a] * u[a];
+            pc[a] = 0.5 * erfc((th[a] - theta0[a]) / sqrt(2.0 * caa));   // Phi(-z)
+        }
+        if (lw > wmax) {
+            const double sc = exp(wmax - lw);   // 0 on the first node
+            wsum *= sc;
+            for (int a = 0; a < 4; ++a) acc[a] *= sc;
+            wmax = lw;
+        }
+        const double wj = exp(lw - wmax);
+        wsum += wj;
+        for (int a = 0; a < 4; ++a) acc[a] += wj * pc[a];
+    }
+    for (int a = 0; a < 4; ++a) Sc[a] = acc[a] / wsum;
+}
+
 }  // namespace cse

@@ -39,6 +39,38 @@ __global__ __launch_bounds__(128) void k_hier4_table(int n, int64_t n_out, float
     tbl[idx] = o;
 }
 
+// Basket design table: float32 (1 - P_0, .., 1 - P_3) per outcome, P_a = P(p_a > p_0a | y).
+struct Theta0 {
+    double v[4];
+};
+__global__ __launch_bounds__(128) void k_basket_table(int n, int64_t n_out, Theta0 t0, float4 *__restrict__ tbl,
+                                                      const HierNode *__restrict__ nodes) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_out) return;
+    const int m = n + 1;
+    int y[4];
+    {
+        int64_t v = idx;
+        for (int a = 3; a >= 0; --a) {
+            y[a] = (int)(v % m);
+            v /= m;
+        }
+    }
+    double Sc[4];
+    basket_posterior(y, (double)n, t0.v, nodes, Sc);
+    tbl[idx] = make_float4((float)Sc[0], (float)Sc[1], (float)Sc[2], (float)Sc[3]);
+}
+
+hipError_t launch_basket_table(int n, const double *theta0, float4 *tbl, const HierNode *nodes, hipStream_t st) {
+    const int64_t m = n + 1;
+    const int64_t n_out = m * m * m * m;
+    Theta0 t0;
+    for (int a = 0; a < 4; ++a) t0.v[a] = theta0[a];
+    hipLaunchKernelGGL(k_basket_table, dim3((uint32_t)((n_out + 127) / 128)), dim3(128), 0, st, n, n_out, t0, tbl,
+                       nodes);
+    return hipGetLastError();
+}
+
 hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st) {
     const int64_t m = n + 1;
     const int64_t n_out = m * m * m * m;
@@ -65,7 +97,10 @@ __device__ __forceinline__ void wave_sync4() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <bool KEYS>
+// BASKET: the basket design (four hypotheses, arm a <-> bit a, q.w used): every slot holds one
+// piece with a single configuration b, so each lane counts that configuration's events in a
+// plain 32-bit counter per slot (no packed fields, one flush at the end).
+template <bool KEYS, bool BASKET>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
@@ -122,6 +157,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             const int sl = lane & (HALF - 1), j0 = (lane >> 5) * HALF;
             for (int j = j0; j < j0 + HALF; ++j) {
                 const uint32_t x = tr[wv][sl][j];
+                if (BASKET) {
+                    if (h == 0)
+                        tot0[1] += x;
+                    else
+                        tot1[1] += x;
+                    continue;
+                }
 #pragma unroll
                 for (int m = 1; m <= 7; ++m) {
                     const uint32_t f = (x >> (4 * (m - 1))) & 15u;
@@ -202,8 +244,21 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
                             const float4 q = tbl[idx];
                             const uint32_t m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) |
-                                                      (q.z < cut ? 4u : 0u))
+                                                      (q.z < cut ? 4u : 0u) | (BASKET && q.w < cut ? 8u : 0u))
                                                    : 0u;
+                            if (BASKET) {
+                                const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
+                                acc[s] += (m & b) ? 1u : 0u;
+                                if (KEYS) {
+                                    float sb = INFINITY;
+                                    if (b & 1u) sb = fminf(sb, q.x);
+                                    if (b & 2u) sb = fminf(sb, q.y);
+                                    if (b & 4u) sb = fminf(sb, q.z);
+                                    if (b & 8u) sb = fminf(sb, q.w);
+                                    kc[(size_t)row0 * WAVE] = sb;
+                                }
+                                continue;
+                            }
                             acc[s] += m ? (1u << (4u * (m - 1u))) : 0u;
                             if (KEYS) {
                                 const uint32_t bm = B->bmask[s];
@@ -221,7 +276,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             }
                         }
         }
-        if (++since == FLUSH_EVERY) {
+        if (!BASKET && ++since == FLUSH_EVERY) {   // basket counters are plain 32-bit
             flush();
             since = 0;
         }
@@ -240,6 +295,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         const int s = h * HALF + lane;
         const int32_t t0 = B->tile0[s];
         if (t0 < 0) continue;
+        if (BASKET) {
+            atomicAdd(&R[t0], (h == 0) ? tot0[1] : tot1[1]);
+            continue;
+        }
         const uint32_t bm = B->bmask[s];
         int q = 0;
 #pragma unroll
@@ -258,12 +317,19 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const float cut = (float)P.design.cut;
-    if (keys)
-        hipLaunchKernelGGL(k_hier4<true>, dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks,
-                           P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys);
+    const bool basket = P.design.kind == CSE_BASKET4;
+#define CSE_H4_LAUNCH(K, BK)                                                                                \
+    hipLaunchKernelGGL((k_hier4<K, BK>), dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
+                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys)
+    if (keys && basket)
+        CSE_H4_LAUNCH(true, true);
+    else if (keys)
+        CSE_H4_LAUNCH(true, false);
+    else if (basket)
+        CSE_H4_LAUNCH(false, true);
     else
-        hipLaunchKernelGGL(k_hier4<false>, dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks,
-                           P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys);
+        CSE_H4_LAUNCH(false, false);
+#undef CSE_H4_LAUNCH
     return hipGetLastError();
 }
 
@@ -300,6 +366,7 @@ __global__ __launch_bounds__(WG) void k_hier4_plain(uint32_t T0, uint32_t T1, ui
         if (bmask & 1u) sb = fminf(sb, q.x);
         if (bmask & 2u) sb = fminf(sb, q.y);
         if (bmask & 4u) sb = fminf(sb, q.z);
+        if (bmask & 8u) sb = fminf(sb, q.w);   // basket design only (arm 3 is a hypothesis)
         r = (sb < cut) ? 1u : 0u;
     }
     const unsigned long long m = __ballot(r);

@@ -578,7 +578,7 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
 
 hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st) {
-    if (P.design.kind == CSE_HIER4)   // 64-key chunks at 256-byte offsets: float4 loads
+    if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4)   // 64-key chunks at 256-byte offsets: float4 loads
         hipLaunchKernelGGL(k_select_f32<true>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
                            (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else if (P.design.kind != CSE_BINOM2_Z)
@@ -600,7 +600,7 @@ hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, co
         if (P.n_outcomes > 32 * TB_MASK_WORDS) return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_tiebreak<TB_OUT>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
                            P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
-    } else if (P.design.kind == CSE_HIER4) {   // 64-key chunks at 256-byte offsets
+    } else if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {   // 64-key chunks at 256-byte offsets
         hipLaunchKernelGGL(k_tiebreak<TB_F32V4>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
                            P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
     } else {

@@ -224,6 +224,15 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         d = 4;
         p = 3;
         P->family = FAM_BINOM;
+    } else if (kind == CSE_BASKET4) {
+        d = 4;
+        p = 4;
+        P->family = FAM_BINOM;
+        for (int a = 0; a < 4; ++a)
+            if (!(fabs(design->theta0[a]) < 1e6)) {
+                set_error("cse_platten_create: design.theta0 must be finite for the basket design");
+                return CSE_EINVAL;
+            }
     } else {
         set_error("cse_platten_create: unknown design kind");
         return CSE_EINVAL;
@@ -289,7 +298,73 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
 
     // ---- the null partition of every box (Section 4) ----
     const int ncorner = 1 << d;
-    for (int64_t i = 0; i < n_boxes; ++i) {
+    std::vector<double> centre;   // simulation point of each tile
+    if (kind == CSE_BASKET4) {
+        // axis-aligned null boundaries theta_a = theta0[a]: each box is cut at the boundaries it
+        // straddles and each piece with b != 0 (bit a: the piece lies in theta_a <= theta0[a])
+        // is a box-shaped tile simulated at its own centre; a box's pieces by b ascending
+        const double *t0 = design->theta0;
+        for (int64_t i = 0; i < n_boxes; ++i) {
+            const double *c = theta + i * d;
+            const double *r = radii + i * d;
+            double pc[4][2], pr[4][2];
+            int pn[4], pin[4][2];
+            for (int a = 0; a < 4; ++a) {
+                const double lo = c[a] - r[a], hi = c[a] + r[a];
+                if (lo < t0[a] && t0[a] < hi) {
+                    pn[a] = 2;
+                    pc[a][0] = 0.5 * (lo + t0[a]);
+                    pr[a][0] = 0.5 * (t0[a] - lo);
+                    pin[a][0] = 1;
+                    pc[a][1] = 0.5 * (t0[a] + hi);
+                    pr[a][1] = 0.5 * (hi - t0[a]);
+                    pin[a][1] = 0;
+                } else {
+                    pn[a] = 1;
+                    pc[a][0] = c[a];
+                    pr[a][0] = r[a];
+                    pin[a][0] = hi <= t0[a] ? 1 : 0;
+                }
+            }
+            struct Piece {
+                int b;
+                double c[4], r[4];
+            };
+            std::vector<Piece> pieces;
+            for (int i0 = 0; i0 < pn[0]; ++i0)
+                for (int i1 = 0; i1 < pn[1]; ++i1)
+                    for (int i2 = 0; i2 < pn[2]; ++i2)
+                        for (int i3 = 0; i3 < pn[3]; ++i3) {
+                            const int ix[4] = {i0, i1, i2, i3};
+                            Piece q{};
+                            for (int a = 0; a < 4; ++a) {
+                                q.c[a] = pc[a][ix[a]];
+                                q.r[a] = pr[a][ix[a]];
+                                q.b |= pin[a][ix[a]] << a;
+                            }
+                            if (q.b) pieces.push_back(q);
+                        }
+            std::sort(pieces.begin(), pieces.end(), [](const Piece &x, const Piece &y) { return x.b < y.b; });
+            for (auto &q : pieces) {
+                P->tile_box.push_back(i);
+                P->tile_cfg.push_back(q.b);
+                P->tile_in_null.push_back(1);
+                P->tile_is_box.push_back(1);
+                for (int a = 0; a < d; ++a) {
+                    P->tile_radii.push_back(q.r[a]);
+                    centre.push_back(q.c[a]);
+                }
+                P->tile_nv.push_back(ncorner);
+                P->vert_off.push_back((int32_t)(P->verts.size() / d));
+                for (int m = 0; m < ncorner; ++m)
+                    for (int a = 0; a < d; ++a) {
+                        const double v = q.c[a] + (((m >> a) & 1) ? q.r[a] : -q.r[a]);
+                        P->verts.push_back(v - q.c[a]);
+                    }
+            }
+        }
+    }
+    for (int64_t i = 0; i < (kind == CSE_BASKET4 ? 0 : n_boxes); ++i) {
         const double *c = theta + i * d;
         const double *r = radii + i * d;
         std::vector<std::vector<double>> corners(ncorner, std::vector<double>(d));
@@ -381,7 +456,8 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     P->tile_N.resize(P->n_tiles);
     std::vector<int64_t> key_off(P->n_tiles, -1), key_stride(P->n_tiles, 64);
     for (int64_t t = 0; t < P->n_tiles; ++t) {
-        for (int a = 0; a < d; ++a) P->tile_theta[t * d + a] = theta[P->tile_box[t] * d + a];
+        for (int a = 0; a < d; ++a)
+            P->tile_theta[t * d + a] = kind == CSE_BASKET4 ? centre[t * d + a] : theta[P->tile_box[t] * d + a];
         P->tile_N[t] = sims[P->tile_box[t]];
         P->max_N = std::max(P->max_N, P->tile_N[t]);
         P->total_sims += P->tile_N[t];
@@ -426,7 +502,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             P->n_keys += (int64_t)B1T * B.n_sims;
         }
         if (int e = upload((Blk1 **)&P->d_blocks, blks.data(), blks.size())) return e;
-    } else if (kind == CSE_HIER4) {
+    } else if (kind == CSE_HIER4 || kind == CSE_BASKET4) {
         // distinct values per arm -> coordinates; 4 x 4 x 2 x 2 coordinate blocks per N class
         const int BD[4] = {B4N0, B4N1, B4N2, B4N3};
         std::vector<double> uv[4];
@@ -439,10 +515,12 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         typedef std::tuple<int32_t, int64_t, int64_t, int64_t, int64_t> Key4;
         std::map<Key4, std::vector<Blk4>> blkmap;
         for (int64_t t = 0; t < P->n_tiles;) {
-            // the tiles of one box are consecutive
+            // the tiles of one simulation point are consecutive (a box's pieces, or one basket piece)
             int64_t t1 = t;
             uint32_t bm = 0;
-            while (t1 < P->n_tiles && P->tile_box[t1] == P->tile_box[t]) bm |= 1u << P->tile_cfg[t1++];
+            while (t1 < P->n_tiles && P->tile_box[t1] == P->tile_box[t] &&
+                   (kind != CSE_BASKET4 || t1 == t))
+                bm |= 1u << P->tile_cfg[t1++];
             int64_t c[4];
             for (int a = 0; a < 4; ++a)
                 c[a] = std::lower_bound(uv[a].begin(), uv[a].end(), P->tile_theta[t * 4 + a]) - uv[a].begin();
@@ -511,7 +589,10 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         P->h4_outcomes = m * m * m * m;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_h4tbl, (size_t)P->h4_outcomes * sizeof(float4)));
         const auto t0 = std::chrono::steady_clock::now();
-        CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, P->d_hnodes, nullptr));
+        if (kind == CSE_BASKET4)
+            CSE_HIP_TRY(launch_basket_table(P->n_per_arm, design->theta0, P->d_h4tbl, P->d_hnodes, nullptr));
+        else
+            CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, P->d_hnodes, nullptr));
         CSE_HIP_TRY(hipDeviceSynchronize());
         P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } else if (kind == CSE_PHASE23) {
@@ -643,7 +724,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     for (int64_t b = 0; b < P->n_blocks; ++b) P->block_sims += blk_sims[b];
     if (P->n_blocks > 0)
         if (int e = plan_work_items(P, P->tune_waves)) return e;
-    if (kind == CSE_BINOM2_Z || kind == CSE_HIER4)
+    if (kind == CSE_BINOM2_Z || kind == CSE_HIER4 || kind == CSE_BASKET4)
         if (int e = plan_group_items(P, P->tune_wgs)) return e;
 
     if (int e = upload(&P->d_theta, P->tile_theta.data(), P->tile_theta.size())) return e;

@@ -36,6 +36,8 @@ def _case(design):
         return W.binom2_grid(12, 3000, lo=-2.0, hi=0.5, seed=1)
     if design == "hier4":
         return W.hier4_grid(2, 3000, seed=1)
+    if design == "basket4":
+        return W.basket_grid(2, 3000, lo=-2.4, hi=-0.9, seed=1)
     return W.phase23_grid((2, 2, 1, 1), 300, seed=1)
 
 
@@ -133,7 +135,7 @@ def _tiebreak_compare(design, w, seed, alpha=0.05):
     return oc
 
 
-@pytest.mark.parametrize("design", ["ztest1", "binom2", "hier4", "phase23"])
+@pytest.mark.parametrize("design", ["ztest1", "binom2", "hier4", "phase23", "basket4"])
 def test_tiebreak_parity(design):
     oc = _tiebreak_compare(design, _case(design), seed=5)
     assert np.all(oc["reject_at"] == np.maximum(oc["k"] - 1, 0))

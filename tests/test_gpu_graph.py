@@ -22,11 +22,13 @@ def _case(kind):
         return W.binom2_grid(24, 500)
     if kind == "hier4":
         return W.hier4_grid(2, 300)
+    if kind == "basket4":
+        return W.basket_grid(2, 300, lo=-2.4, hi=-0.9)
     w = W.phase23_grid((2, 2, 2, 1), 100)
     return w
 
 
-KINDS = ["ztest1", "binom2", "hier4", "phase23"]
+KINDS = ["ztest1", "binom2", "hier4", "phase23", "basket4"]
 
 
 def _alloc(P, dev="cuda"):
@@ -43,7 +45,8 @@ def _alloc(P, dev="cuda"):
     o["score_T"] = (torch.empty((n, d), dtype=torch.int64, device=dev) if kind == cse.CSE_BINOM2_Z else
                     torch.empty((n, 2 * d), dtype=torch.int64, device=dev) if kind == cse.CSE_PHASE23 else None)
     o["score_Z"] = torch.empty(n, dtype=torch.float64, device=dev) if kind == cse.CSE_ZTEST1 else None
-    o["grad"] = torch.empty((n, d), dtype=torch.float64, device=dev) if kind != cse.CSE_HIER4 else None
+    o["grad"] = (torch.empty((n, d), dtype=torch.float64, device=dev)
+                 if kind not in (cse.CSE_HIER4, cse.CSE_BASKET4) else None)
     return o
 
 

@@ -88,6 +88,17 @@ def phase23_grid(shape=(4, 4, 4, 4), sims=None, lo: float = -0.9946, hi: float =
                 theta=g.copy(), radii=radii, sims=sm, seed=seed, delta=0.01, alpha=0.025, cut=lam)
 
 
+def basket_grid(m: int = 16, sims: int = 32_768, lo: float = -3.5, hi: float = 1.0, seed: int = 0) -> dict:
+    """Basket design grid, m^4 equal boxes on [lo, hi]^4 (Section 10.1's theta range [-3.5, 1]^4),
+    row-major; the design cuts the boxes that straddle theta_a = logit(0.15) into pieces."""
+    c = _centres(lo, hi, m)
+    r = (hi - lo) / (2 * m)
+    g = np.stack(np.meshgrid(c, c, c, c, indexing="ij"), axis=-1).reshape(-1, 4)
+    n = g.shape[0]
+    return dict(name=f"basket4_{m}^4x{sims}", design="basket4", theta=g.copy(), radii=np.full((n, 4), r),
+                sims=np.full(n, sims, np.int32), seed=seed, delta=0.01, alpha=0.025, cut=0.15)
+
+
 def uneven_sims(n_tiles: int, seed: int = 0, lo_pow: int = 11, n_classes: int = 6) -> np.ndarray:
     """Simulations per tile 2^(lo_pow+g), g uniform on {0..n_classes-1} (PCG64 seeded)."""
     g = np.random.Generator(np.random.PCG64(seed)).integers(0, n_classes, n_tiles)
