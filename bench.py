@@ -41,6 +41,9 @@ B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 
 #   (4 + 4 + 2 + 2) thresholds x (compare + add); per (simulation, box) outcome index (3),
 #   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store.
 H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
+#   basket (the same kernel, one configuration per slot): per (simulation, piece) outcome index
+#   (3), table gather (1), 4 compares, mask, event test, accumulate.
+BK_SLOT = 11
 
 #   Phase II/III: float64 lane-ops of one posterior look (hier_post.hpp), counted by operation
 #   (exp 20, log 30, log1p series 22, erfc 40, reciprocal 5, sqrt 10; the per-node constants
@@ -74,6 +77,10 @@ WORKLOADS = {
                   "delta 0.01; step = calibrate + validate + gradient",
     "phase23_c5_sub256": "the Phase II/III workload restricted to every 256th box (1,024 boxes), same sims "
                          "per box; step = calibrate + validate + gradient",
+    "basket4_16": "Bayesian basket design (4 arms, n=35, 85% posterior rule, hierarchical model on the "
+                  "offsets from p_0a = 15% assumed for every arm), 16^4 boxes on [-3.5,1]^4 cut at the null "
+                  "boundaries into pieces (73,521 tiles), 32,768 sims per piece, seed 0, delta 0.01; "
+                  "step = validate (rejections at the 85% rule + Clopper-Pearson + Tilt-Bound)",
     "binom2_adaptive": "binom2 n=35 pooled-z on [-3,1]^2 kept to theta1<=theta0, adaptive validation from "
                        "16x16 boxes with 2,048 sims: rounds of GPU validation of the changed boxes, then split "
                        "(half-width down to 1/128, the 256x256 grid's) or double N (up to 131,072) where the "
@@ -167,6 +174,7 @@ def cpu_baseline(name, w, design, target_s: float = 15.0):
     rng = np.random.default_rng(1234)
     n = w["theta"].shape[0]
     keep_all = name == "binom2_1024_full"
+    validation_only = name in ("binom2_1024_full", "basket4_16")
     cut = w.get("cut", 0.05 if design == "hier4" else 1.96)
 
     def run(m):
@@ -177,7 +185,7 @@ def cpu_baseline(name, w, design, target_s: float = 15.0):
         t = time.perf_counter()
         v = O.validate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["delta"], cut=cut,
                        keep_all=keep_all)
-        if not keep_all:
+        if not validation_only:
             O.calibrate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"], cut=cut,
                         key_dtype=np.float32 if design in ("hier4", "phase23") else np.float64)
         return time.perf_counter() - t, int(np.asarray(s["sims"])[v["box"]].sum()), len(v["box"])
@@ -188,7 +196,7 @@ def cpu_baseline(name, w, design, target_s: float = 15.0):
     sims_note = "min(N, 256) sims of each" if design == "phase23" else "all sims of each"
     return {"value": st / dt, "unit": "sim·tiles/s", "cores": 1, "kind": "oracle",
             "sample": f"{m} boxes ({nt} tiles) drawn uniformly (seed 1234) of the same workload, {sims_note}; "
-                      f"oracle {'validate' if keep_all else 'validate + calibrate'}, "
+                      f"oracle {'validate' if validation_only else 'validate + calibrate'}, "
                       f"{dt:.1f} s single-threaded"}
 
 
@@ -240,9 +248,10 @@ def main():
     else:
         w = getattr(W, name)()
     design = {"binom2_256_tri": "binom2", "binom2_1024_full": "binom2", "hier4_16": "hier4",
-              "ztest1d_64": "ztest1", "phase23_c5": "phase23", "phase23_c5_sub256": "phase23"}[name]
+              "ztest1d_64": "ztest1", "phase23_c5": "phase23", "phase23_c5_sub256": "phase23",
+              "basket4_16": "basket4"}[name]
     keep_all = name == "binom2_1024_full"
-    calibrating = not keep_all
+    calibrating = name not in ("binom2_1024_full", "basket4_16")
     t0 = time.perf_counter()
     P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all, cut=w.get("cut"))
     platten_ms = (time.perf_counter() - t0) * 1e3
@@ -299,7 +308,8 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t
     cse.cse_profile_enable(False)
-    sim_kernel = {"binom2": "binom2", "hier4": "hier4", "ztest1": "ztest1", "phase23": "phase23"}[design] + \
+    sim_kernel = {"binom2": "binom2", "hier4": "hier4", "ztest1": "ztest1", "phase23": "phase23",
+                  "basket4": "basket4"}[design] + \
         ("_calib" if calibrating else "")
     kern = {}
     for kn in (sim_kernel, "select", "bound_invert", "bound_validate"):
@@ -403,6 +413,9 @@ def main():
         ops = (st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + box_sims * H4_BOX
                + st["total_sims"] * H4_TILE)
         kname = "k_hier4<KEYS=true>"
+    elif design == "basket4":
+        ops = st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + st["total_sims"] * BK_SLOT
+        kname = "k_hier4<KEYS=false, BASKET=true>"
     elif design == "phase23":
         wc = cse.cse_work_counters(P.handle)
         ops = (wc["looks_phase2"] * (90 * P23_NODE + P23_P2_EXTRA)

@@ -137,6 +137,11 @@ def hier4_16() -> dict:
     return hier4_grid(16, 32_768)
 
 
+def basket4_16() -> dict:
+    """Basket design, 16^4 boxes on [-3.5, 1]^4, 32,768 sims per piece."""
+    return basket_grid(16, 32_768)
+
+
 def phase23_c5() -> dict:
     """Phase II/III design, 16 x 16 x 32 x 32 boxes (2^18) on the logit box [-0.9946, 1.1527]^4,
     2^(11+g) sims per box with g uniform on {0..5} (PCG64(0)), seed 0, lambda 0.06253."""
