@@ -28,6 +28,10 @@
 namespace cse {
 
 constexpr int HP_NODES = 90;
+// Newton stops after applying a step below this size: convergence is quadratic near the mode,
+// so the remaining error is of the order of its square (~1e-12), below the 1e-10 step a fully
+// converged iteration would still take.
+constexpr double HP_NEWTON_TOL = 1e-6;
 
 // Per-node constants (HierNode, cse_internal.h) are computed once on the host.
 
@@ -103,7 +107,7 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
                 mx = fmax(mx, fabs(step));
             }
             if (newton_steps) *newton_steps += 1;
-            if (mx < 1e-10) break;
+            if (mx < HP_NEWTON_TOL) break;
         }
         // curvature at the final mode; log|D| as the log of the product (each D_a lies in
         // [1e-3, 1e6 + n/4], so the product of four cannot overflow)
@@ -222,7 +226,7 @@ __device__ __forceinline__ void basket_posterior(const int y[4], double n, const
                 th[a] += step;
                 mx = fmax(mx, fabs(step));
             }
-            if (mx < 1e-10) break;
+            if (mx < HP_NEWTON_TOL) break;
         }
         double su = 0.0, prodD = 1.0, ll = 0.0, dsum = 0.0, sq = 0.0;
         for (int a = 0; a < 4; ++a) {

@@ -103,3 +103,33 @@ def test_per_tile_path_and_determinism():
     with pytest.raises(cse.CseError):
         cse.cse_simulate(P.handle, 5, R, None, None, torch.empty((P.n_tiles, 4), dtype=torch.float64, device="cuda"))
     P.close()
+
+
+def test_full_basket4_16_validation_sampled_boxes():
+    """The bench's launch (16^4 boxes on [-3.5, 1]^4, 73,521 pieces x 32,768 simulations):
+    every piece of sampled boxes (among them boxes cut at the boundaries) against the oracle;
+    properties at every tile."""
+    w = W.basket4_16()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("basket4", th, rd, sm)
+    print(f"[basket] full workload: {P.n_tiles} tiles", flush=True)
+    assert P.n_tiles == 73521
+    v = P.validate(w["seed"], delta=w["delta"])
+    torch.cuda.synchronize()
+    box = P.tiles["box"]
+    rng = np.random.default_rng(2)
+    counts = np.bincount(box, minlength=len(th))
+    split = np.flatnonzero(counts > 1)
+    pick = np.unique(np.concatenate([[box[0], box[-1]], rng.choice(split, 2, replace=False),
+                                     rng.choice(np.unique(box), 2, replace=False)]))
+    sub = W.subsample(w, pick)
+    ov = O.validate("basket4", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["delta"], cut=0.15)
+    ids = np.concatenate([np.flatnonzero(box == b) for b in pick])
+    print(f"[basket] {len(pick)} boxes, {len(ids)} pieces compared", flush=True)
+    assert np.array_equal(_np(v["reject"])[ids], ov["R"])
+    np.testing.assert_allclose(_np(v["cp_upper"])[ids], ov["cp"], rtol=1e-9)
+    np.testing.assert_allclose(_np(v["tile_bound"])[ids], ov["bound"], rtol=1e-9)
+    R = _np(v["reject"])
+    assert np.all((R >= 0) & (R <= 32768))
+    assert np.all(_np(v["tile_bound"]) >= _np(v["cp_upper"]) - 1e-15)
+    P.close()
