@@ -16,7 +16,7 @@ lambda* = min, the gradient, and the Clopper-Pearson + Tilt-Bound of every tile.
 platten (null clipping, vertices, thresholds, batch plan, 4-arm posterior table) is built
 once before timing and reported separately.
 
-Prints one JSON line.  --gpus above 1 is refused: this build runs on one GPU.
+Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
 from __future__ import annotations
 
@@ -219,7 +219,7 @@ def main():
                     help="only copy this many bytes device-to-device 3 times (scales HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (--gpus 1); multi-GPU sharding is not built",
+        print("bench.py: one GPU only (--gpus 1); multi-GPU sharding is not implemented",
               file=sys.stderr)
         sys.exit(2)
 
