@@ -238,3 +238,41 @@ def test_confidence_set_4d_float32_compare(design):
         cse.cse_confidence_set(P.handle, _dev([0.0]), 0, _dev(lam), coef, 2, c["keep"], c["e_lo"], c["e_hi"],
                                c["e_range"])
     P.close()
+
+
+def test_full_c2_workload_sampled_boxes():
+    """The headline 2-arm workload (256 x 256 boxes kept to theta1 <= theta0, 8,192 sims):
+    randomised calibration, the lower bound and a confidence set over all 32,896 tiles in one
+    launch each, compared with the oracle on sampled boxes (a diagonal one among them)."""
+    w = W.binom2_256_tri()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("binom2", th, rd, sm)
+    print(f"[full c2] {P.n_tiles} tiles", flush=True)
+    g = P.calibrate_tiebreak(w["seed"], alpha=w["alpha"])
+    v = P.validate(w["seed"], delta=w["delta"])
+    lo = P.validate_lower(v["reject"], delta=w["delta"])
+    coef = np.array([-1.0, 1.0, 0.0])
+    c = P.confidence_set(_dev(np.zeros(P.n_tiles)), g["lambda_tile"], coef)
+    torch.cuda.synchronize()
+    box = P.tiles["box"]
+    rng = np.random.default_rng(3)
+    diag = np.flatnonzero(np.isclose(th[:, 0], th[:, 1]))
+    pick = np.unique(np.concatenate([[0, len(th) - 1], rng.choice(len(th), 3, replace=False), diag[:1]]))
+    sub = W.subsample(w, pick)
+    oc = O.calibrate_tiebreak("binom2", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["alpha"])
+    ov = O.validate("binom2", sub["theta"], sub["radii"], sub["sims"], w["seed"], w["delta"])
+    ids = np.concatenate([np.flatnonzero(box == b) for b in pick])
+    assert len(ids) == len(oc["lam"])
+    assert 3 in P.tiles["n_vert"][ids]                            # the diagonal box is a triangle
+    k = _np(g["k"])[ids]
+    same = k == oc["k"]
+    assert same.mean() >= 0.8
+    assert np.array_equal(_np(g["lambda_tile"])[ids][same], oc["lam"][same])
+    assert np.array_equal(_np(g["u_tile"]).view(np.uint32)[ids][same].astype(np.int64), oc["c"][same])
+    assert np.array_equal(_np(g["reject_at_lambda"])[ids][same], oc["reject_at"][same])
+    assert np.array_equal(_np(v["reject"])[ids], ov["R"])
+    np.testing.assert_allclose(_np(lo["lower"])[ids], ov["lower"], rtol=1e-9, atol=1e-13)
+    keep, elo, ehi, _ = O.confidence_set(ov["subs"], oc["lam"], 0.0, coef, key_dtype=np.float64)
+    assert np.array_equal(_np(c["keep"])[ids].astype(bool)[same], keep[same])
+    np.testing.assert_allclose(_np(c["e_lo"])[ids], elo, rtol=0, atol=1e-12)
+    P.close()
