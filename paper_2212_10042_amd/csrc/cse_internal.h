@@ -149,6 +149,7 @@ struct Platten {
 
     // design tables (device)
     float4 *d_h4tbl = nullptr;           // 4-arm: (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome
+    uint8_t *d_h4mask = nullptr;         // 4-arm designs: rejection mask at the cut per outcome
     HierNode *d_hnodes = nullptr;        // per-node constants of the hierarchical posterior
     // Phase II/III design: per-tile thresholds / configurations, the work queue
     uint32_t *d_tileT = nullptr;

@@ -71,6 +71,23 @@ hipError_t launch_basket_table(int n, const double *theta0, float4 *tbl, const H
     return hipGetLastError();
 }
 
+// Rejection mask of every outcome at the design's cut (bit a-1 for treatment arm a of the
+// 4-arm design, bit a for arm a of the basket design): the forward pass gathers this byte
+// instead of the float4 row; the comparison is the one the keyed pass makes.
+__global__ void k_h4_mask(const float4 *__restrict__ tbl, int64_t n, float cut, int nbits, uint8_t *__restrict__ mask) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 q = tbl[i];
+    uint32_t m = (q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u);
+    if (nbits == 4 && q.w < cut) m |= 8u;
+    mask[i] = (uint8_t)m;
+}
+
+hipError_t launch_h4_mask(const float4 *tbl, int64_t n, float cut, int nbits, uint8_t *mask, hipStream_t st) {
+    hipLaunchKernelGGL(k_h4_mask, dim3((uint32_t)((n + 255) / 256)), dim3(256), 0, st, tbl, n, cut, nbits, mask);
+    return hipGetLastError();
+}
+
 hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st) {
     const int64_t m = n + 1;
     const int64_t n_out = m * m * m * m;
@@ -104,8 +121,8 @@ template <bool KEYS, bool BASKET>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
-                                              const float4 *__restrict__ tbl, float cut,
-                                              uint32_t *__restrict__ R, float *__restrict__ keys) {
+                                              const float4 *__restrict__ tbl, const uint8_t *__restrict__ mtbl,
+                                              float cut, uint32_t *__restrict__ R, float *__restrict__ keys) {
     constexpr int NP = NP35;
     constexpr int NW = 4 * NP;
     constexpr int NB = NW / 4;   // 35 Philox blocks
@@ -242,10 +259,18 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             const int32_t row0 = B->row0[s];
                             if (row0 < 0) continue;   // uniform: the slot holds no box
                             const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
-                            const float4 q = tbl[idx];
-                            const uint32_t m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) |
-                                                      (q.z < cut ? 4u : 0u) | (BASKET && q.w < cut ? 8u : 0u))
-                                                   : 0u;
+                            // without keys only the rejection mask at the cut is needed: one byte
+                            // per outcome (a 128-byte line covers 128 neighbouring outcomes)
+                            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                            uint32_t m;
+                            if (KEYS) {
+                                q = tbl[idx];
+                                m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u) |
+                                           (BASKET && q.w < cut ? 8u : 0u))
+                                        : 0u;
+                            } else {
+                                m = act ? (uint32_t)mtbl[idx] : 0u;
+                            }
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
                                 acc[s] += (m & b) ? 1u : 0u;
@@ -320,7 +345,7 @@ hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *key
     const bool basket = P.design.kind == CSE_BASKET4;
 #define CSE_H4_LAUNCH(K, BK)                                                                                \
     hipLaunchKernelGGL((k_hier4<K, BK>), dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
-                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, cut, R, keys)
+                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, P.d_h4mask, cut, R, keys)
     if (keys && basket)
         CSE_H4_LAUNCH(true, true);
     else if (keys)

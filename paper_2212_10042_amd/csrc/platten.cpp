@@ -593,6 +593,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             CSE_HIP_TRY(launch_basket_table(P->n_per_arm, design->theta0, P->d_h4tbl, P->d_hnodes, nullptr));
         else
             CSE_HIP_TRY(launch_hier4_table(P->n_per_arm, P->d_h4tbl, P->d_hnodes, nullptr));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_h4mask, (size_t)P->h4_outcomes));
+        CSE_HIP_TRY(launch_h4_mask(P->d_h4tbl, P->h4_outcomes, (float)design->cut, kind == CSE_BASKET4 ? 4 : 3,
+                                   P->d_h4mask, nullptr));
         CSE_HIP_TRY(hipDeviceSynchronize());
         P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     } else if (kind == CSE_PHASE23) {
@@ -869,7 +872,8 @@ void free_platten(Platten *P) {
                     P->d_apw,    P->d_kw,    P->d_lamw,    P->d_lamg,   P->d_cls_N,
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
-                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes};
+                    P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes,
+                    P->d_h4mask};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     for (hipEvent_t e : {P->ev_sim, P->ev_val})
