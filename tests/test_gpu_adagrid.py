@@ -80,3 +80,18 @@ def test_ztest_adaptive_calibration_near_exact_threshold():
     lam = g["a"].min()
     print(f"[adagrid] ztest1 -lambda* {-lam:.4f} after {g['rounds']} rounds, {len(g['sims'])} boxes", flush=True)
     assert 1.959963 <= -lam <= 1.96 + 0.06
+
+
+def test_adaptive_validation_basket_matches_oracle():
+    """The basket design's tiles are pieces of the boxes simulated at their own centres: the
+    same rounds, boxes and counts as the oracle's run, bounds within 1e-9."""
+    w = W.basket_grid(2, 256, lo=-2.6, hi=-0.8, seed=1)
+    kw = dict(mode="validate", target=0.5, delta=0.01, r_min=0.1, n_max=1024, max_rounds=2, cut=0.15)
+    print("[adagrid] validation basket4", flush=True)
+    g = AG.run("basket4", w["theta"], w["radii"], w["sims"], seed=2, **kw,
+               on_round=lambda r, h: print(f"  round {r}: {h}", flush=True))
+    o = OA.run("basket4", w["theta"], w["radii"], w["sims"], seed=2, **kw)
+    _same_boxes(g, o)
+    assert sum(h[1] + h[2] for h in g["history"]) > 0
+    np.testing.assert_allclose(g["a"], o["tiles"]["bound"], rtol=1e-9)
+    assert np.array_equal(g["c"], o["tiles"]["fhat"])
