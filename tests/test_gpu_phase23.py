@@ -117,3 +117,46 @@ def test_phase23_large_tiles_selection_paths():
     w["radii"] = np.full((2, 4), 0.05)
     w["sims"] = np.array([5000, 2200], np.int32)
     n, R = _compare(w, seed=9, lam=0.06253)
+
+
+def test_phase23_full_c5_sampled_boxes():
+    """The bench's full Phase II/III launch (2^18 boxes, 2,048 .. 65,536 trials each, one
+    calibration step with validation and gradient, ~40 s): every tile of sampled boxes with
+    2,048 trials against the oracle (the oracle takes ~0.6 ms per trial); properties at every
+    tile."""
+    w = W.phase23_c5()
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    P = cse.Platten.create("phase23", th, rd, sm, cut=w["cut"])
+    print(f"[phase23] full C5: {P.n_tiles} tiles, {int(sm[P.tiles['box']].sum())} trials", flush=True)
+    g = P.calibrate(w["seed"], alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    print("[phase23] full C5 step done", flush=True)
+    box = P.tiles["box"]
+    rng = np.random.default_rng(5)
+    small = np.flatnonzero(sm == 2048)
+    inbox = np.unique(box)
+    cand = np.intersect1d(small, inbox)
+    pick = np.sort(rng.choice(cand, 4, replace=False))
+    sub = W.subsample(w, pick)
+    subs, obox, cfg, N, S32, R, sY, sN = _oracle_tiles(sub, w["seed"], w["cut"])
+    ids = np.concatenate([np.flatnonzero(box == b) for b in pick])
+    assert len(ids) == len(subs)
+    assert np.array_equal(P.tiles["cfg"][ids], cfg)
+    Rg = _np(g["reject"])[ids]
+    print(f"[phase23] {len(pick)} boxes, {len(ids)} tiles, R {R.tolist()}, discordant {int(np.sum(Rg != R))}",
+          flush=True)
+    assert np.array_equal(Rg, R)
+    sc = _np(g["score_T"])[ids]
+    assert np.array_equal(sc[:, :4], sY) and np.array_equal(sc[:, 4:], sN)
+    oc_ap, _ = O.tile_inverse("binom", sub["theta"][obox], O._pad_vertices(subs, sub["theta"]), w["alpha"], n=350)
+    np.testing.assert_allclose(_np(g["alpha_prime"])[ids], oc_ap, rtol=1e-9)
+    k = np.floor((N + 1.0) * oc_ap).astype(np.int64)
+    same = _np(g["k"])[ids] == k
+    lam_o = np.array([O.order_statistic(S32[t, : N[t]], int(k[t])) for t in range(len(subs))])
+    assert np.array_equal(_np(g["lambda_tile"])[ids][same], lam_o[same])
+    # every tile: counts within N, the global threshold is the minimum
+    Rall = _np(g["reject"])
+    assert np.all((Rall >= 0) & (Rall <= sm[box]))
+    lam = _np(g["lambda_tile"])
+    assert float(_np(g["lambda_global"])[0]) == lam.min()
+    P.close()
