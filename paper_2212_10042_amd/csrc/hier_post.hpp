@@ -72,9 +72,15 @@ template <bool FULL, bool WARM>
 __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4], const HierNode *__restrict__ nodes,
                                                HierSummary &out, int *newton_steps = nullptr, int need = 7) {
     const double M0 = -1.34;
-    double th0[4];
-    for (int a = 0; a < 4; ++a) th0[a] = log((y[a] + 0.5) / (n[a] - y[a] + 0.5));
-    double th[4] = {th0[0], th0[1], th0[2], th0[3]};
+    // empirical logits: the first Newton start and the fixed reference point of the moment
+    // sums (any fixed point serves; held in float32 to keep registers for the trial state)
+    float th0[4];
+    double th[4];
+    for (int a = 0; a < 4; ++a) {
+        th[a] = log((y[a] + 0.5) / (n[a] - y[a] + 0.5));
+        th0[a] = (float)th[a];
+    }
+    float thp[4] = {th0[0], th0[1], th0[2], th0[3]};   // WARM: the mode two nodes back (float32)
 
     double wmax = -INFINITY, wsum = 0.0;
     double accP[3] = {0.0, 0.0, 0.0}, accS[3] = {0.0, 0.0, 0.0};
@@ -84,6 +90,12 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
         const double inv_s2 = nd.inv_s2, c = nd.c, beta = nd.beta;
         if (!WARM)
             for (int a = 0; a < 4; ++a) th[a] = th0[a];
+        if (WARM)   // the modes move smoothly in log s2: start from the line through the last two
+            for (int a = 0; a < 4; ++a) {
+                const double cur = th[a];
+                if (j >= 2) th[a] = 2.0 * cur - (double)thp[a];
+                thp[a] = (float)cur;
+            }
         double D[4], u[4], gam = 0.0;
         for (int it = 0; it < 100; ++it) {
             double dsum = 0.0;
