@@ -137,7 +137,7 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
             sq += e * e;
         }
         gam = beta * rcp_nr(1.0 - beta * su);
-        const double logdet_negH = log(prodD) + log1p(-beta * su);
+        const double logdet_negH = log(prodD * (1.0 - beta * su));   // both factors in range
         const double quad = (sq - c * dsum * dsum) * inv_s2;
         const double lw = ll - 0.5 * quad - 0.5 * logdet_negH + nd.lconst;
         double pc[3], pr[3], vd[3];
@@ -254,7 +254,7 @@ __device__ __forceinline__ void basket_posterior(const int y[4], double n, const
             sq += e * e;
         }
         gam = beta * rcp_nr(1.0 - beta * su);
-        const double logdet_negH = log(prodD) + log1p(-beta * su);
+        const double logdet_negH = log(prodD * (1.0 - beta * su));   // both factors in range
         const double quad = (sq - c * dsum * dsum) * inv_s2;
         const double lw = ll - 0.5 * quad - 0.5 * logdet_negH + nd.lconst;
         double pc[4];
