@@ -148,8 +148,13 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
             pr[i - 1] = 0.0;
             if ((need >> (i - 1)) & 1) {
                 const double zs = (th[i] - th[0]) / sqrt(2.0 * vd[i - 1]);
-                pc[i - 1] = 0.5 * erfc(zs);              // Phi(-z)
-                if (FULL) pr[i - 1] = 0.5 * erfc(-zs);   // Phi(z)
+                if (FULL) {   // one tail gives both: the smaller side directly, the other as 1 - it
+                    const double tail = 0.5 * erfc(fabs(zs));
+                    pc[i - 1] = zs >= 0.0 ? tail : 1.0 - tail;   // Phi(-z)
+                    pr[i - 1] = zs >= 0.0 ? 1.0 - tail : tail;   // Phi(z)
+                } else {
+                    pc[i - 1] = 0.5 * erfc(zs);
+                }
             }
         }
         if (lw > wmax) {
