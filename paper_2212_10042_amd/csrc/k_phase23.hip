@@ -170,131 +170,138 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
     int n[4] = {0, 0, 0, 0}, y[4] = {0, 0, 0, 0}, add[4] = {0, 0, 0, 0};
     int c_trials = 0, c_look2 = 0, c_look3 = 0, c_newton = 0;   // this lane's work (stats counters)
 
-    for (;;) {
-        // ---- give idle lanes the next simulations of the wave's item stream ----
-        unsigned long long need = __ballot(!busy);
-        while (need) {
-            if (it_k >= it_end) {
-                if (!queue_open) break;
-                uint32_t idx = 0;
-                if (lane == 0) idx = atomicAdd(A.counter, 1u);
-                idx = __builtin_amdgcn_readfirstlane(idx);
-                if ((int64_t)idx >= A.n_items) {
-                    queue_open = false;
-                    break;
-                }
-                const WorkItem W = A.items[idx];
-                it_tile = W.blk;
-                it_k = W.k_begin;
-                it_end = W.k_end;
-                continue;
-            }
-            const uint32_t avail = it_end - it_k;
-            const uint32_t rank = (uint32_t)__popcll(need & below);
-            if (((need >> lane) & 1ull) && rank < avail) {
-                busy = true;
-                tile = it_tile;
-                k = it_k + rank;
+    bool fresh = false, done = false;
+    float S = INFINITY;
+    // Phase II decision code -> next enrolment (or the end of the trial)
+    auto apply = [&](int code) {
+        const int s_arm = code & 3;
+        if (s_arm) {
+            sel = s_arm;
+#pragma unroll
+            for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == s_arm) ? 100 : 0;
+            look = 3;
+        } else if ((code >> 5) & 1) {
+            done = true;
+        } else {
+            active = (code >> 2) & 7;
+            const int per = 100 / (__popc(active) + 1);
+#pragma unroll
+            for (int a = 0; a < 4; ++a) add[a] = (a == 0 || ((active >> (a - 1)) & 1)) ? per : 0;
+            look += 1;
+        }
+    };
+    // the trial's result: its key, and the rejection sums when S is below the cut
+    auto finish = [&]() {
+        if (A.keys) A.keys[A.key_off[tile] + k] = S;
+        if (S < A.cut) {
+            atomicAdd(&A.R[tile], 1u);
+            if (A.sumT)
+#pragma unroll
                 for (int a = 0; a < 4; ++a) {
-                    T[a] = A.tileT[(int64_t)tile * 4 + a];
-                    n[a] = 0;
-                    y[a] = 0;
-                    add[a] = 50;   // Phase II opens with 50 patients per arm
+                    atomicAdd(&A.sumT[(int64_t)tile * 8 + a], (unsigned long long)y[a]);
+                    atomicAdd(&A.sumT[(int64_t)tile * 8 + 4 + a], (unsigned long long)n[a]);
                 }
-                cfg = A.cfg[tile];
-                look = 0;
-                sel = 0;
-                active = 7;
+        }
+        busy = false;
+        c_trials += 1;
+    };
+
+    for (;;) {
+        // ---- give idle lanes the next simulations of the wave's item stream and run their first
+        // look (a table lookup); a trial that ends there is finished at once and its lane takes
+        // another, so that lanes do not sit out the posterior below ----
+        for (;;) {
+            unsigned long long need = __ballot(!busy);
+            while (need) {
+                if (it_k >= it_end) {
+                    if (!queue_open) break;
+                    uint32_t idx = 0;
+                    if (lane == 0) idx = atomicAdd(A.counter, 1u);
+                    idx = __builtin_amdgcn_readfirstlane(idx);
+                    if ((int64_t)idx >= A.n_items) {
+                        queue_open = false;
+                        break;
+                    }
+                    const WorkItem W = A.items[idx];
+                    it_tile = W.blk;
+                    it_k = W.k_begin;
+                    it_end = W.k_end;
+                    continue;
+                }
+                const uint32_t avail = it_end - it_k;
+                const uint32_t rank = (uint32_t)__popcll(need & below);
+                if (((need >> lane) & 1ull) && rank < avail) {
+                    busy = true;
+                    fresh = true;
+                    tile = it_tile;
+                    k = it_k + rank;
+                    for (int a = 0; a < 4; ++a) {
+                        T[a] = A.tileT[(int64_t)tile * 4 + a];
+                        n[a] = 0;
+                        y[a] = 0;
+                    }
+                    cfg = A.cfg[tile];
+                    look = 0;
+                    sel = 0;
+                    active = 7;
+                }
+                const uint32_t asked = (uint32_t)__popcll(need);
+                it_k += asked < avail ? asked : avail;
+                need = __ballot(!busy);
             }
-            const uint32_t asked = (uint32_t)__popcll(need);
-            it_k += asked < avail ? asked : avail;
-            need = __ballot(!busy);
+            if (!__ballot(fresh)) break;   // nobody was given a trial: all lanes busy, or queue drained
+            if (fresh) {
+                // Phase II opens with 50 patients per arm; the first look's decision is tabulated
+                fresh = false;
+                done = false;
+                S = INFINITY;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) p23_draw(a, 50, T[a], k, A.key0, A.key1, n[a], y[a]);
+                apply(A.look1[((y[0] * 51 + y[1]) * 51 + y[2]) * 51 + y[3]]);
+                if (done) finish();
+            }
         }
         if (!__ballot(busy)) break;   // queue drained and every trial finished
         if (busy) {
-            float S = INFINITY;
-            bool done = false;
-            // Phase II decision code -> next enrolment (or the end of the trial)
-            auto apply = [&](int code) {
-                const int s_arm = code & 3;
-                if (s_arm) {
-                    sel = s_arm;
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == s_arm) ? 100 : 0;
-                    look = 3;
-                } else if ((code >> 5) & 1) {
-                    done = true;
-                } else {
-                    active = (code >> 2) & 7;
-                    const int per = 100 / (__popc(active) + 1);
-#pragma unroll
-                    for (int a = 0; a < 4; ++a) add[a] = (a == 0 || ((active >> (a - 1)) & 1)) ? per : 0;
-                    look += 1;
-                }
-            };
-
-            // ---- enrol; the first look is a table lookup ----
+            // ---- enrol the patients of the next look, then one posterior look ----
 #pragma unroll
             for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
-            if (look == 0) {
-                apply(A.look1[((y[0] * 51 + y[1]) * 51 + y[2]) * 51 + y[3]]);
-                if (!done) {
+            HierSummary s;
+            {
+                const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
+                // tails the wave needs (a uniform mask keeps the branch scalar)
+                const int mine = look < 3 ? 0 : 1 << (sel - 1);
+                int wneed = 0;
 #pragma unroll
-                    for (int a = 0; a < 4; ++a) p23_draw(a, add[a], T[a], k, A.key0, A.key1, n[a], y[a]);
-                }
+                for (int i = 0; i < 3; ++i) wneed |= __ballot((mine >> i) & 1) ? (1 << i) : 0;
+                hier_posterior<true, true>(y, nd, A.nodes, s, &c_newton, __builtin_amdgcn_readfirstlane(wneed));
             }
-            if (!done) {
-                // ---- one posterior look ----
-                HierSummary s;
-                {
-                    const double nd[4] = {(double)n[0], (double)n[1], (double)n[2], (double)n[3]};
-                    // tails the wave needs (a uniform mask keeps the branch scalar)
-                    const int mine = look < 3 ? 0 : 1 << (sel - 1);
-                    int wneed = 0;
-#pragma unroll
-                    for (int i = 0; i < 3; ++i) wneed |= __ballot((mine >> i) & 1) ? (1 << i) : 0;
-                    hier_posterior<true, true>(y, nd, A.nodes, s, &c_newton, __builtin_amdgcn_readfirstlane(wneed));
-                }
-                if (look < 3) c_look2 += 1; else c_look3 += 1;
-                if (look < 3) {
-                    apply(p23_phase2(s, look, active, A.gh, A.sqrt_pi, A.z95));
-                } else {
-                    const bool in_b = (cfg >> (sel - 1)) & 1;
-                    if (look == 3) {
-                        // Phase III interim
-                        const double ms = pick4(s.mean, sel);
-                        if (pick3(s.P, sel - 1) > 0.95) {
-                            S = in_b ? -INFINITY : INFINITY;
-                            done = true;
-                        } else if (p23_psucc(ms - s.mean[0], pick3(s.dvar, sel - 1), s.mean[0], ms, 100.0, A.z95) <
-                                   0.20) {
-                            done = true;
-                        } else {
-#pragma unroll
-                            for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == sel) ? 100 : 0;
-                            look = 4;
-                        }
-                    } else {
-                        // final analysis
-                        S = in_b ? (float)pick3(s.Sc, sel - 1) : INFINITY;
+            if (look < 3) c_look2 += 1; else c_look3 += 1;
+            if (look < 3) {
+                apply(p23_phase2(s, look, active, A.gh, A.sqrt_pi, A.z95));
+            } else {
+                const bool in_b = (cfg >> (sel - 1)) & 1;
+                if (look == 3) {
+                    // Phase III interim
+                    const double ms = pick4(s.mean, sel);
+                    if (pick3(s.P, sel - 1) > 0.95) {
+                        S = in_b ? -INFINITY : INFINITY;
                         done = true;
-                    }
-                }
-            }
-            if (done) {
-                if (A.keys) A.keys[A.key_off[tile] + k] = S;
-                if (S < A.cut) {
-                    atomicAdd(&A.R[tile], 1u);
-                    if (A.sumT)
+                    } else if (p23_psucc(ms - s.mean[0], pick3(s.dvar, sel - 1), s.mean[0], ms, 100.0, A.z95) <
+                               0.20) {
+                        done = true;
+                    } else {
 #pragma unroll
-                        for (int a = 0; a < 4; ++a) {
-                            atomicAdd(&A.sumT[(int64_t)tile * 8 + a], (unsigned long long)y[a]);
-                            atomicAdd(&A.sumT[(int64_t)tile * 8 + 4 + a], (unsigned long long)n[a]);
-                        }
+                        for (int a = 0; a < 4; ++a) add[a] = (a == 0 || a == sel) ? 100 : 0;
+                        look = 4;
+                    }
+                } else {
+                    // final analysis
+                    S = in_b ? (float)pick3(s.Sc, sel - 1) : INFINITY;
+                    done = true;
                 }
-                busy = false;
-                c_trials += 1;
             }
+            if (done) finish();
         }
     }
     if (A.stats) {
