@@ -13,21 +13,23 @@ namespace cse {
 
 constexpr int SEL_WG = 256;
 
-// Block-wide exclusive scan of one value per thread (SEL_WG threads), result in part[].
+// Block-wide exclusive scan of one value per thread (SEL_WG threads), result in part[tid]:
+// an inclusive scan within each wave by lane shuffles, then the totals of the waves before.
 __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
-    const int tid = threadIdx.x;
-    part[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < SEL_WG; off <<= 1) {
-        const uint32_t add = (tid >= off) ? part[tid - off] : 0u;
-        __syncthreads();
-        part[tid] += add;
-        __syncthreads();
+    __shared__ uint32_t wave_tot[SEL_WG / WAVE];
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), w = tid / WAVE;
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < WAVE; off <<= 1) {
+        const uint32_t y = __shfl_up(x, off);
+        if (lane >= off) x += y;
     }
-    const uint32_t incl = part[tid];
+    if (lane == WAVE - 1) wave_tot[w] = x;
     __syncthreads();
-    part[tid] = incl - v;
-    __syncthreads();
+    uint32_t before = 0u;
+    for (int i = 0; i < w; ++i) before += wave_tot[i];
+    part[tid] = before + x - v;
+    __syncthreads();   // wave_tot may be rewritten by the next call only after every wave read it
 }
 
 // ---- discrete statistic (2-arm design): keys are outcome indices y0*(n+1)+y1 ----
@@ -185,8 +187,9 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
                                                        int32_t *__restrict__ rej_at) {
     __shared__ uint32_t hist[2048];
     __shared__ uint32_t part[SEL_WG];
-    __shared__ uint32_t samp[SEL_SAMPLE];
-    __shared__ uint32_t cand[SEL_CAND];
+    // the sample is used up (bracket chosen) before the pass fills the candidates: one buffer
+    __shared__ uint32_t samp_cand[SEL_CAND > SEL_SAMPLE ? SEL_CAND : SEL_SAMPLE];
+    uint32_t *const samp = samp_cand, *const cand = samp_cand;
     __shared__ uint32_t s_bin, s_below, s_cnt, s_lt;
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
