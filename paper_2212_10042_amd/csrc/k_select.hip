@@ -125,9 +125,11 @@ __device__ __forceinline__ float ord2f(uint32_t u) {
 }
 
 // k-th smallest (k >= 1) of the n order-preserving keys get(j), j < n, by three radix passes
-// (11/11/10 bits) with an LDS histogram; also the number of keys strictly below it.  Called by
-// the whole workgroup.
-template <class Get>
+// (11/11/10 bits) with an LDS histogram; also the number of keys strictly below it.  With
+// PASSES = 2 only the top 22 bits are resolved: key is then the smallest value of the 1024-wide
+// bin that holds the k-th smallest, and below counts the keys under that bin.  Called by the
+// whole workgroup.
+template <int PASSES = 3, class Get>
 __device__ void radix_kth(int n, uint32_t k, Get get, uint32_t *hist, uint32_t *part, uint32_t *s_bin,
                           uint32_t *s_below, uint32_t &key, uint32_t &below_out) {
     constexpr int BINS = 2048;
@@ -135,7 +137,7 @@ __device__ void radix_kth(int n, uint32_t k, Get get, uint32_t *hist, uint32_t *
     uint32_t prefix = 0u, below = 0u, need = k;
     const int shifts[3] = {21, 10, 0};
     const int widths[3] = {11, 11, 10};
-    for (int pass = 0; pass < 3; ++pass) {
+    for (int pass = 0; pass < PASSES; ++pass) {
         const int sh = shifts[pass], wd = widths[pass];
         const uint32_t mask_hi = pass == 0 ? 0u : (0xFFFFFFFFu << (sh + wd));
         for (int j = tid; j < BINS; j += SEL_WG) hist[j] = 0u;
@@ -170,12 +172,14 @@ __device__ void radix_kth(int n, uint32_t k, Get get, uint32_t *hist, uint32_t *
 
 // Selection of lambda*_i for float32 keys.  Tiles of at most SEL_SAMPLE keys are selected in
 // LDS.  Larger tiles: the first SEL_SAMPLE simulations (i.i.d. draws of the statistic) give
-// sample order statistics lo, hi that bracket rank k/N with a 5-sigma margin; one pass over
+// sample order statistics lo, hi that bracket rank k/N with a margin of z binomial standard
+// deviations (z = 5, lowered to no less than 3 where the expected number of keys in the
+// bracket would exceed 60% of the SEL_CAND candidate slots); one pass over
 // the tile's keys counts those below lo and gathers those in [lo, hi] into LDS; if the k-th
 // smallest lies among them it is selected there, else the exact radix passes run over HBM.
 // Either way the result is the exact k-th smallest key.
 constexpr int SEL_SAMPLE = 2048;
-constexpr int SEL_CAND = 4096;
+constexpr int SEL_CAND = 2048;
 
 template <bool VEC4>
 __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__ keys,
@@ -222,11 +226,19 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
     } else {
         const double pr = (double)k / (double)n;
         const double sd = sqrt((double)m * pr * (1.0 - pr));
-        const int lo_r = (int)floor(pr * m - 5.0 * sd) - 1;   // sample ranks (1-based) of the bracket
-        const int hi_r = (int)ceil(pr * m + 5.0 * sd) + 1;
+        // expected keys in the bracket: n (2 z sd + 2) / m
+        const double z_fit = (0.6 * SEL_CAND * m / (double)n - 2.0) / (2.0 * sd);
+        const double z = fmin(5.0, fmax(3.0, z_fit));
+        const int lo_r = (int)floor(pr * m - z * sd) - 1;   // sample ranks (1-based) of the bracket
+        const int hi_r = (int)ceil(pr * m + z * sd) + 1;
+        // the bracket is widened to the 22-bit bins that hold those sample order statistics
+        // (two radix passes each instead of three; a few more candidates, the same result)
         uint32_t lo = 0u, hi = 0xFFFFFFFFu, dummy = 0u;
-        if (lo_r >= 1) radix_kth(m, (uint32_t)lo_r, from_samp, hist, part, &s_bin, &s_below, lo, dummy);
-        if (hi_r <= m) radix_kth(m, (uint32_t)hi_r, from_samp, hist, part, &s_bin, &s_below, hi, dummy);
+        if (lo_r >= 1) radix_kth<2>(m, (uint32_t)lo_r, from_samp, hist, part, &s_bin, &s_below, lo, dummy);
+        if (hi_r <= m) {
+            radix_kth<2>(m, (uint32_t)hi_r, from_samp, hist, part, &s_bin, &s_below, hi, dummy);
+            hi |= 0x3FFu;
+        }
         if (tid == 0) {
             s_cnt = 0u;
             s_lt = 0u;
@@ -304,7 +316,7 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
 // the count `below` of keys strictly under it (the selection's outputs), the k-th smallest pair
 // is (lambda, c) with c the (k - below)-th smallest u among the simulations whose key equals
 // lambda.  The tied simulations' u are regenerated from the counter and gathered in LDS; more
-// than SEL_CAND ties fall back to radix passes over the whole tile with every non-tied key
+// than TB_CAND ties fall back to radix passes over the whole tile with every non-tied key
 // mapped to 0xFFFFFFFF (which cannot change a rank <= the number of ties).  On exit rej_at[t]
 // holds the number of pairs strictly below (lambda, c).
 // Key layouts: TB_F32 float32 keys at kt[(j / 64) * stride + j % 64]; TB_F32V4 the same with
@@ -314,6 +326,7 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
 enum { TB_F32 = 0, TB_F32V4 = 1, TB_OUT = 2 };
 constexpr int TB_MASK_WORDS = 2048;   // 65,536 outcome indices (16-bit keys)
 constexpr int TB_RANK = 512;          // tie classes up to this size are ranked by counting
+constexpr int TB_CAND = 4096;         // tied simulations gathered in LDS
 
 template <int MODE>
 __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ keys_,
@@ -327,7 +340,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
                                                      uint32_t *__restrict__ c_out) {
     __shared__ uint32_t hist[2048];
     __shared__ uint32_t part[SEL_WG];
-    __shared__ uint32_t cand[SEL_CAND];
+    __shared__ uint32_t cand[TB_CAND];
     __shared__ uint32_t tmask[MODE == TB_OUT ? TB_MASK_WORDS : 1];
     __shared__ uint32_t s_bin, s_below, s_cnt;
     const int64_t t = blockIdx.x;
@@ -367,7 +380,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
             if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
             base = __shfl(base, 0);
             const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-            if (in && pos < (uint32_t)SEL_CAND) cand[pos] = philox_tiebreak((uint32_t)j, key0, key1);
+            if (in && pos < (uint32_t)TB_CAND) cand[pos] = philox_tiebreak((uint32_t)j, key0, key1);
         }
     };
     // one pass over the tile with several 16-byte (or 4-byte) loads in flight per thread; trip
@@ -454,7 +467,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
         __syncthreads();
         c = s_bin;
         below_u = s_below;
-    } else if (m <= (uint32_t)SEL_CAND) {
+    } else if (m <= (uint32_t)TB_CAND) {
         auto from_cand = [&](int j) { return cand[j]; };
         radix_kth((int)m, need, from_cand, hist, part, &s_bin, &s_below, c, below_u);
     } else {

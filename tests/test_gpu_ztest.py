@@ -61,6 +61,26 @@ def test_ztest_parity(cfg):
     P.close()
 
 
+@pytest.mark.parametrize("alpha", [0.005, 0.2, 0.5])
+def test_selection_bracket_any_rank(alpha):
+    """The sampled bracket of the float32 selection narrows its margin where rank k/N is far
+    from the tail (more keys per bracket) and falls back to exact passes when it misses: the
+    selected lambda*_i equals the oracle's k-th smallest at every rank, with exactly k - 1
+    simulations below it."""
+    w = W.ztest_1d(8, 1, seed=3)
+    sm = np.array([2049, 4096, 32768, 32769, 50000, 65536, 3000, 20000], np.int32)
+    th, rd = w["theta"], w["radii"]
+    print(f"[ztest] selection bracket alpha {alpha}", flush=True)
+    P = cse.Platten.create("ztest1", th, rd, sm)
+    g = P.calibrate(11, alpha=alpha, delta=w["delta"], with_validation=False)
+    torch.cuda.synchronize()
+    oc = O.calibrate("ztest1", th, rd, sm, 11, alpha)
+    assert np.array_equal(_np(g["k"]), oc["k"])
+    np.testing.assert_allclose(_np(g["lambda_tile"]), oc["lam"], rtol=0, atol=2e-6)
+    assert np.array_equal(_np(g["reject_at_lambda"]), np.maximum(_np(g["k"]) - 1, 0))
+    P.close()
+
+
 def test_ztest_tie_gradient_closed_form():
     th0 = np.linspace(-1.0, 0.0, 16)
     N = 200_000
