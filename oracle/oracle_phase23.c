@@ -21,7 +21,9 @@
  *                a mean with predictive law N(md, (vd / (vd + V))^2 (vd + V)), so
  *                p_succ = Phi((md - z95 sqrt(vf)) / (vd / sqrt(vd + V))), z95 = Phi^{-1}(0.95).
  *    If some active arm has p_succ > 0.70 (0.60 at look 3), the active arm with the largest
- *    p_best among those arms is selected (ties: lowest index).  Otherwise, at looks 1 and 2,
+ *    p_best among those arms is selected (ties: lowest index; arms with equal counts and
+ *    sizes have equal posteriors by exchangeability and so tie exactly, whatever rounding
+ *    their computed p_best carries).  Otherwise, at looks 1 and 2,
  *    active arms with p_best < 0.15 are dropped (stop for futility if none remains); at look 3
  *    the trial stops for futility.
  *  Phase III.  100 more patients on the selected arm s and on control, then an interim:
@@ -184,7 +186,9 @@ static double simulate_trial(trial *t, int cfg, int *outcome, int *sel_out, int 
         for (int i = 1; i < D; ++i) {
             if (!active[i]) continue;
             double ps = orc_psucc(dm[i - 1], dv[i - 1], mean[0], mean[i], 200);
-            if (ps > z_sel[look] && (best == 0 || pb[i] > pb[best])) best = i;
+            /* equal data give equal p_best whatever the rounding: the lower index stays */
+            const int same = best && t->y[i] == t->y[best] && t->n[i] == t->n[best];
+            if (ps > z_sel[look] && (best == 0 || (pb[i] > pb[best] && !same))) best = i;
         }
         if (best) { sel = best; break; }
         if (look == 2) break;

@@ -34,14 +34,16 @@ __host__ __device__ __forceinline__ double exp_cw(double x) {
     return ldexp(p, (int)k);
 }
 
-__host__ __device__ __forceinline__ double log1p_unit(double t) {
-    const double u = t / (2.0 + t);
+// log(1 + t) = 2 atanh(u) from u = t / (2 + t) in [0, 1/3].
+__host__ __device__ __forceinline__ double log1p_from_u(double u) {
     const double w = u * u;
     double s = 1.0 / 35.0;
 #pragma unroll
     for (int j = 33; j >= 1; j -= 2) s = fma(s, w, 1.0 / (double)j);
     return 2.0 * u * s;
 }
+
+__host__ __device__ __forceinline__ double log1p_unit(double t) { return log1p_from_u(t / (2.0 + t)); }
 
 __host__ __device__ __forceinline__ double softplus_fast(double x) {
     return fmax(x, 0.0) + log1p_unit(exp_cw(-fabs(x)));

@@ -57,6 +57,20 @@ __device__ __forceinline__ double hp_expit_softplus(double x, double &sp) {
     return x >= 0.0 ? r : 1.0 - r;
 }
 
+// 1 / x_a for four finite positive x_a with one reciprocal: the reciprocal of their product
+// times the other three factors (a few ulp; the products stay far inside the double range for
+// the values here: 1 + e in (1, 2], curvatures in [1e-3, 1e6 + n/4]).  The treatment arms'
+// cofactors are x0 times the product of the other two in ascending arm order, so arms 1..3
+// with equal x get bit-identical results and ties between them stay exact ties.
+__device__ __forceinline__ void rcp4(const double x[4], double r[4]) {
+    const double x12 = x[1] * x[2], x13 = x[1] * x[3], x23 = x[2] * x[3];
+    const double inv = rcp_nr(x[0] * (x12 * x[3]));
+    r[0] = inv * (x12 * x[3]);
+    r[1] = inv * (x[0] * x23);
+    r[2] = inv * (x[0] * x13);
+    r[3] = inv * (x[0] * x12);
+}
+
 struct HierSummary {
     double P[3];      // P(theta_i > theta_0 | data), i = 1..3
     double Sc[3];     // 1 - P_i
@@ -100,15 +114,17 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
         for (int it = 0; it < 100; ++it) {
             double dsum = 0.0;
             for (int a = 0; a < 4; ++a) dsum += th[a] - M0;
-            double g[4], su = 0.0;
+            double g[4], su = 0.0, q1[4], r1[4];
+            for (int a = 0; a < 4; ++a) q1[a] = 1.0 + exp_cw(-fabs(th[a]));
+            rcp4(q1, r1);   // expit(|theta_a|)
             for (int a = 0; a < 4; ++a) {
-                const double p = hp_expit(th[a]);
+                const double p = th[a] >= 0.0 ? r1[a] : 1.0 - r1[a];
                 // Q (theta - m0) = ((theta_a - m0) - c sum_b (theta_b - m0)) / s2
                 g[a] = (double)y[a] - n[a] * p - ((th[a] - M0) - c * dsum) * inv_s2;
                 D[a] = n[a] * p * (1.0 - p) + inv_s2;
-                u[a] = rcp_nr(D[a]);
-                su += u[a];
             }
+            rcp4(D, u);
+            for (int a = 0; a < 4; ++a) su += u[a];
             gam = beta * rcp_nr(1.0 - beta * su);
             double ug = 0.0;
             for (int a = 0; a < 4; ++a) ug += u[a] * g[a];
@@ -124,18 +140,28 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
         // curvature at the final mode; log|D| as the log of the product (each D_a lies in
         // [1e-3, 1e6 + n/4], so the product of four cannot overflow)
         double su = 0.0, prodD = 1.0, ll = 0.0, dsum = 0.0, sq = 0.0;
-        for (int a = 0; a < 4; ++a) {
-            double sp;
-            const double p = hp_expit_softplus(th[a], sp);
-            D[a] = n[a] * p * (1.0 - p) + inv_s2;
-            u[a] = rcp_nr(D[a]);
-            su += u[a];
-            prodD *= D[a];
-            ll += y[a] * th[a] - n[a] * sp;
-            const double e = th[a] - M0;
-            dsum += e;
-            sq += e * e;
+        {
+            double ex[4], q1[4], r1[4], q2[4], r2[4];
+            for (int a = 0; a < 4; ++a) {
+                ex[a] = exp_cw(-fabs(th[a]));
+                q1[a] = 1.0 + ex[a];
+                q2[a] = 2.0 + ex[a];   // in (2, 3]
+            }
+            rcp4(q1, r1);   // expit(|theta_a|)
+            rcp4(q2, r2);   // for softplus: log1p(e) = 2 atanh(e / (2 + e))
+            for (int a = 0; a < 4; ++a) {
+                const double p = th[a] >= 0.0 ? r1[a] : 1.0 - r1[a];
+                const double sp = fmax(th[a], 0.0) + log1p_from_u(ex[a] * r2[a]);
+                D[a] = n[a] * p * (1.0 - p) + inv_s2;
+                prodD *= D[a];
+                ll += y[a] * th[a] - n[a] * sp;
+                const double e = th[a] - M0;
+                dsum += e;
+                sq += e * e;
+            }
         }
+        rcp4(D, u);
+        for (int a = 0; a < 4; ++a) su += u[a];
         gam = beta * rcp_nr(1.0 - beta * su);
         const double logdet_negH = log(prodD * (1.0 - beta * su));   // both factors in range
         const double quad = (sq - c * dsum * dsum) * inv_s2;

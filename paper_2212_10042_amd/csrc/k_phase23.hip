@@ -82,9 +82,17 @@ __device__ __forceinline__ T pick3(const T (&v)[3], int i) {
     return i == 0 ? v[0] : (i == 1 ? v[1] : v[2]);
 }
 
+// Pairs of treatment arms with equal counts and sizes (bit 0: arms 1, 2; bit 1: 1, 3; bit 2: 2, 3).
+__device__ __forceinline__ int p23_ties(int y1, int y2, int y3, int n1, int n2, int n3) {
+    return ((y1 == y2 && n1 == n2) ? 1 : 0) | ((y1 == y3 && n1 == n3) ? 2 : 0) | ((y2 == y3 && n2 == n3) ? 4 : 0);
+}
+
 // Decision at Phase II look `look` (0..2) for the active treatment arms (bit i-1 = arm i):
-// code = sel | (active after drops) << 2 | stop << 5, sel = 0 when no arm is selected.
-__device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int active, const double *gh,
+// code = sel | (active after drops) << 2 | stop << 5, sel = 0 when no arm is selected.  Among
+// the arms that qualify the largest p_best wins, the lowest index on ties; arms with equal
+// counts and sizes have equal posteriors (exchangeable model), so they tie exactly whatever
+// rounding their computed p_best carries: `ties` bit 0 (arms 1, 2), bit 1 (1, 3), bit 2 (2, 3).
+__device__ __forceinline__ int p23_phase2(const HierSummary &s, int ties, int look, int active, const double *gh,
                                           double sqrt_pi, double z95) {
     double pb[4] = {0.0, 0.0, 0.0, 0.0};
     double isd[4];   // 1 / (sd * sqrt 2): Phi(z / sd) = erfc(-z isd) / 2
@@ -111,7 +119,8 @@ __device__ __forceinline__ int p23_phase2(const HierSummary &s, int look, int ac
     for (int i = 1; i < 4; ++i) {
         if (!((active >> (i - 1)) & 1)) continue;
         const double ps = p23_psucc(s.mean[i] - s.mean[0], s.dvar[i - 1], s.mean[0], s.mean[i], 200.0, z95);
-        if (ps > thr && (best == 0 || pb[i] > pb_best)) {
+        const bool same = best != 0 && ((ties >> (best + i - 3)) & 1);   // best < i
+        if (ps > thr && (best == 0 || (pb[i] > pb_best && !same))) {
             best = i;
             pb_best = pb[i];
         }
@@ -142,7 +151,7 @@ __global__ __launch_bounds__(128) void k_p23_look1(int64_t n_out, uint8_t *__res
     const double n[4] = {50.0, 50.0, 50.0, 50.0};
     HierSummary s;
     hier_posterior<true, true>(y, n, nodes, s, nullptr, 0);
-    tbl[idx] = (uint8_t)p23_phase2(s, 0, 7, gh, sqrt_pi, z95);
+    tbl[idx] = (uint8_t)p23_phase2(s, p23_ties(y[1], y[2], y[3], 50, 50, 50), 0, 7, gh, sqrt_pi, z95);
 }
 
 hipError_t launch_p23_look1(const Platten &P, hipStream_t st) {
@@ -278,7 +287,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(2, 2))) void
             }
             if (look < 3) c_look2 += 1; else c_look3 += 1;
             if (look < 3) {
-                apply(p23_phase2(s, look, active, A.gh, A.sqrt_pi, A.z95));
+                apply(p23_phase2(s, p23_ties(y[1], y[2], y[3], n[1], n[2], n[3]), look, active, A.gh, A.sqrt_pi,
+                                 A.z95));
             } else {
                 const bool in_b = (cfg >> (sel - 1)) & 1;
                 if (look == 3) {

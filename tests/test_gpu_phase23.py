@@ -119,6 +119,19 @@ def test_phase23_large_tiles_selection_paths():
     n, R = _compare(w, seed=9, lam=0.06253)
 
 
+def test_phase23_exchangeable_arms_tie_exactly():
+    """Treatment arms with equal true rates: their data tie often, and then their posterior
+    summaries must be bit-identical so that the selection keeps the first of the tied arms on
+    both sides (the kernel's batched reciprocals preserve that symmetry)."""
+    w = W.phase23_grid((1, 1, 1, 1), 1, seed=2)
+    w["theta"] = np.array([[0.4, 0.0, 0.0, 0.0], [0.1, -0.3, -0.3, -0.3], [0.6, 0.3, 0.3, -0.2]])
+    w["radii"] = np.full((3, 4), 0.05)
+    w["sims"] = np.array([1500, 1500, 1500], np.int32)
+    w["name"] = "phase23_exchangeable_arms"
+    n, R = _compare(w, seed=2, lam=0.1)
+    assert n == 3 and R.sum() > 0
+
+
 def test_phase23_full_c5_sampled_boxes():
     """The bench's full Phase II/III launch (2^18 boxes, 2,048 .. 65,536 trials each, one
     calibration step with validation and gradient, ~40 s): every tile of sampled boxes with

@@ -212,7 +212,11 @@ def _replay(theta, cfg, seed, k, info, trace, S):
               for i in range(1, 4) if active[i]}
         q = [i for i in ps if ps[i] > thr[look]]
         if q:
-            assert sel == max(q, key=lambda i: (pb[i], -i))
+            best = 0   # largest p_best, lowest index on ties; equal data tie exactly
+            for i in q:
+                if best == 0 or (pb[i] > pb[best] and (y[i], n[i]) != (y[best], n[best])):
+                    best = i
+            assert sel == best
             p3 = look + 1
             break
         for i in range(1, 4):
