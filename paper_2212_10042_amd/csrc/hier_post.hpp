@@ -44,6 +44,14 @@ __device__ __forceinline__ double rcp_nr(double d) {
     return fma(r, e, r);
 }
 
+// 1/sqrt(d) for finite d > 0: hardware estimate and two Newton steps (error about one ulp).
+__device__ __forceinline__ double rsq_nr(double d) {
+    double y = __builtin_amdgcn_rsq(d);
+    const double h = 0.5 * d;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return fma(y, fma(-h * y, y, 0.5), y);
+}
+
 // expit(x), and with it softplus(x) = max(x, 0) + log1p(exp(-|x|)) from the same exponential.
 __device__ __forceinline__ double hp_expit(double x) {
     const double e = exp_cw(-fabs(x));          // in (0, 1]
@@ -173,7 +181,7 @@ __device__ __forceinline__ void hier_posterior(const int y[4], const double n[4]
             pc[i - 1] = 0.0;
             pr[i - 1] = 0.0;
             if ((need >> (i - 1)) & 1) {
-                const double zs = (th[i] - th[0]) / sqrt(2.0 * vd[i - 1]);
+                const double zs = (th[i] - th[0]) * rsq_nr(2.0 * vd[i - 1]);
                 if (FULL) {   // one tail gives both: the smaller side directly, the other as 1 - it
                     const double tail = 0.5 * erfc(fabs(zs));
                     pc[i - 1] = zs >= 0.0 ? tail : 1.0 - tail;   // Phi(-z)

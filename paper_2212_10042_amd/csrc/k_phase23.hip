@@ -97,7 +97,7 @@ __device__ __forceinline__ int p23_phase2(const HierSummary &s, int ties, int lo
     double pb[4] = {0.0, 0.0, 0.0, 0.0};
     double isd[4];   // 1 / (sd * sqrt 2): Phi(z / sd) = erfc(-z isd) / 2
 #pragma unroll
-    for (int kk = 0; kk < 4; ++kk) isd[kk] = rcp_nr(sqrt(2.0 * s.var[kk]));
+    for (int kk = 0; kk < 4; ++kk) isd[kk] = rsq_nr(2.0 * s.var[kk]);
 #pragma unroll
     for (int i = 1; i < 4; ++i) {
         const double si = sqrt(2.0 * s.var[i]);
