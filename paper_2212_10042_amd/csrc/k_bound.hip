@@ -136,6 +136,9 @@ __device__ __forceinline__ double part1(int n, double x) {
     return (FAM == FAM_NORMAL) ? 0.5 * x * x : (double)n * softplus(x);
 }
 
+// Distinct displacement values per arm that the general form shares between vertices.
+constexpr int SHU = 2;
+
 // One tile's data for the search over q (D = parameter dimension, a compile-time constant so
 // the per-arm arrays stay in registers).
 template <int D>
@@ -148,7 +151,21 @@ struct TileGeom {
     const double *V;          // vertex displacements (general form)
     const double *psi1;       // per-vertex psi(theta, v, 1) (general form)
     double A0;
+    // general form with shared terms: the vertices' displacement along arm a takes at most SHU
+    // distinct values uv[a * SHU + .] (the pieces of a box cut at the null boundaries of the
+    // grids here keep two: the box's own faces), and bit a of vidx[j] picks vertex j's value;
+    // each arm's log-partition term is then evaluated once per distinct value instead of once
+    // per vertex
+    bool shared;
+    const double *uv;
+    const uint8_t *vidx;
 };
+
+// log-partition term of one arm at natural parameter x (without the patient count)
+template <int FAM>
+__device__ __forceinline__ double arm_term(double x) {
+    return (FAM == FAM_NORMAL) ? 0.5 * x * x : softplus(x);
+}
 
 // max over the tile's vertices of  psi(theta, v, q) / q - psi(theta, v, 1).
 // For a whole box A is a sum over arms and the vertices are all sign patterns (+-r_a), so the
@@ -168,6 +185,22 @@ __device__ double max_tilt_term(const TileGeom<D> &T, double q) {
         return s;
     }
     double w = -1e300;
+    if (T.shared) {
+        double sp[D][SHU];
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+#pragma unroll
+            for (int c = 0; c < SHU; ++c) sp[a][c] = arm_term<FAM>(T.th[a] + q * T.uv[a * SHU + c]);
+        for (int j = 0; j < T.nv; ++j) {
+            const uint32_t code = T.vidx[j];
+            double sum = 0.0;   // the same terms in the same order as part()
+#pragma unroll
+            for (int a = 0; a < D; ++a) sum += ((code >> a) & 1u) ? sp[a][1] : sp[a][0];
+            const double psiq = ((FAM == FAM_NORMAL) ? sum : (double)T.n * sum) - T.A0;
+            w = fmax(w, psiq * iq - T.psi1[j]);
+        }
+        return w;
+    }
     for (int j = 0; j < T.nv; ++j) {
         const double psiq = part<FAM, D>(T.n, T.th, q, T.V + j * D) - T.A0;
         w = fmax(w, psiq * iq - T.psi1[j]);
@@ -237,6 +270,8 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
                                                int32_t *__restrict__ k_out,
                                                double *__restrict__ cp_out) {
     __shared__ double s_psi1[256 / GB][MAXV];
+    __shared__ uint8_t s_vidx[256 / GB][MAXV];
+    __shared__ double s_uv[256 / GB][D * SHU];
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % GB, grp = threadIdx.x / GB;
     int64_t t = gid / GB;
@@ -262,10 +297,49 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
         T.p1[a][0] = part1<FAM>(n, T.th[a] - T.r[a]) - T.A0a[a];
         T.p1[a][1] = part1<FAM>(n, T.th[a] + T.r[a]) - T.A0a[a];
     }
-    if (!T.box)
+    T.shared = false;
+    if (!T.box) {
         for (int j = lane; j < T.nv; j += GB) s_psi1[grp][j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
+        // distinct displacement values per arm, in order of first appearance (every lane of the
+        // group finds the same ones); an arm with one value repeats it in the second slot
+        bool shared = true;
+        double v0[D], v1[D];
+        bool two[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            v0[a] = T.V[a];
+            v1[a] = v0[a];
+            two[a] = false;
+        }
+        for (int j = 0; j < T.nv; ++j) {
+            uint32_t code = 0u;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double x = T.V[j * D + a];
+                if (x != v0[a]) {
+                    if (!two[a]) {
+                        v1[a] = x;
+                        two[a] = true;
+                    } else if (x != v1[a]) {
+                        shared = false;
+                    }
+                    code |= 1u << a;
+                }
+            }
+            if (j % GB == lane) s_vidx[grp][j] = (uint8_t)code;
+        }
+        if (lane == 0)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                s_uv[grp][a * SHU] = v0[a];
+                s_uv[grp][a * SHU + 1] = v1[a];
+            }
+        T.shared = shared;
+    }
     __syncthreads();
     T.psi1 = s_psi1[grp];
+    T.vidx = s_vidx[grp];
+    T.uv = s_uv[grp];
 
     if (mode == 1) {
         double sb;
