@@ -212,11 +212,21 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
     // The step's dependencies: alpha' -> k -> selection; simulation -> selection, finish and
     // the validation bound.  The fused simulation runs alone (it fills the chip); afterwards
     // the validation bound (float64, latency-bound) runs on the side stream beside the
-    // selection, forked from and joined into `st` by events.
+    // selection, forked from and joined into `st` by events.  Captured as a graph, the
+    // inversion (which does not depend on the simulation) is a branch beside the simulation
+    // too; eager calls keep it in line, so that every kernel's own timing describes that
+    // kernel alone.
     // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
+    const bool branch_invert = t_capturing;
     {
-        Timed tm("bound_invert", st);
-        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, st));
+        hipStream_t is = branch_invert ? P.side : st;
+        if (branch_invert) {
+            CSE_HIP_TRY(hipEventRecord(P.ev_fork, st));
+            CSE_HIP_TRY(hipStreamWaitEvent(is, P.ev_fork, 0));
+        }
+        Timed tm("bound_invert", is);
+        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, is));
+        if (branch_invert) CSE_HIP_TRY(hipEventRecord(P.ev_inv, is));
     }
     if (int e = run_sim(P, seed, true, st)) return e;
     const bool want_bound = cp_upper || tile_bound;
@@ -233,6 +243,7 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
         }
         CSE_HIP_TRY(hipEventRecord(P.ev_val, side));
     }
+    if (branch_invert) CSE_HIP_TRY(hipStreamWaitEvent(st, P.ev_inv, 0));   // k before the selection
     {
         Timed tm("select", st);
         CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));

@@ -178,9 +178,10 @@ struct Platten {
     std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
 
     // side stream (default priority) and fork/join events of the calibration step: the
-    // validation bound runs beside the selection
+    // validation bound runs beside the selection, and in a captured graph the inversion beside
+    // the simulation
     hipStream_t side = nullptr;
-    hipEvent_t ev_sim = nullptr, ev_val = nullptr;
+    hipEvent_t ev_sim = nullptr, ev_val = nullptr, ev_fork = nullptr, ev_inv = nullptr;
 
     // Clopper-Pearson table: one entry per (N class, R), R = 0..N (classes = distinct N)
     int32_t n_cls = 0;

@@ -772,7 +772,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
     CSE_HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
-    for (hipEvent_t *e : {&P->ev_sim, &P->ev_val})
+    for (hipEvent_t *e : {&P->ev_sim, &P->ev_val, &P->ev_fork, &P->ev_inv})
         CSE_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return CSE_OK;
 }
@@ -876,7 +876,7 @@ void free_platten(Platten *P) {
                     P->d_h4mask};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
-    for (hipEvent_t e : {P->ev_sim, P->ev_val})
+    for (hipEvent_t e : {P->ev_sim, P->ev_val, P->ev_fork, P->ev_inv})
         if (e) (void)hipEventDestroy(e);
     if (P->side) (void)hipStreamDestroy(P->side);
 }
