@@ -181,6 +181,9 @@ struct Platten {
     // validation bound runs beside the selection, and in a captured graph the inversion beside
     // the simulation
     hipStream_t side = nullptr;
+    // device arenas holding the read-only per-tile arrays and design tables, each filled by one
+    // host-to-device copy at creation (base, bytes); the arrays point into them
+    std::vector<std::pair<void *, size_t>> arenas;
     hipEvent_t ev_sim = nullptr, ev_val = nullptr, ev_fork = nullptr, ev_inv = nullptr;
 
     // Clopper-Pearson table: one entry per (N class, R), R = 0..N (classes = distinct N)

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <functional>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <chrono>
 #include <tuple>
@@ -187,6 +188,67 @@ double normal_q95() {
     return z;
 }
 
+// Side streams of destroyed plattens, per device, for reuse (creating one costs ~35 us and
+// destroying it ~30 us; a platten is destroyed only after the device has been synchronised,
+// so a cached stream is idle).  Default priority, non-blocking.
+std::mutex g_stream_mu;
+std::map<int, std::vector<hipStream_t>> g_stream_cache;
+constexpr size_t STREAM_CACHE_MAX = 16;
+
+hipError_t take_side_stream(int device, hipStream_t *s) {
+    {
+        std::lock_guard<std::mutex> g(g_stream_mu);
+        auto &v = g_stream_cache[device];
+        if (!v.empty()) {
+            *s = v.back();
+            v.pop_back();
+            return hipSuccess;
+        }
+    }
+    return hipStreamCreateWithFlags(s, hipStreamNonBlocking);
+}
+
+void give_side_stream(int device, hipStream_t s) {
+    {
+        std::lock_guard<std::mutex> g(g_stream_mu);
+        auto &v = g_stream_cache[device];
+        if (v.size() < STREAM_CACHE_MAX) {
+            v.push_back(s);
+            return;
+        }
+    }
+    (void)hipStreamDestroy(s);
+}
+
+// Uploads gathered into one host buffer and copied with a single transfer into a device arena
+// (one synchronous copy per arena instead of one per array: each costs ~15 us of fixed
+// overhead).  The destinations are assigned when the arena is flushed and must not be read
+// before; they are freed with the arena.
+struct Stager {
+    std::vector<unsigned char> host;
+    std::vector<std::pair<void **, size_t>> dst;   // destination pointer, byte offset
+    template <class T>
+    void add(T **d, const T *src, size_t n) {
+        *d = nullptr;
+        if (n == 0) return;
+        const size_t off = (host.size() + 255) & ~(size_t)255;
+        host.resize(off + n * sizeof(T));
+        memcpy(host.data() + off, src, n * sizeof(T));
+        dst.emplace_back((void **)d, off);
+    }
+    int flush(Platten *P) {
+        if (dst.empty()) return CSE_OK;
+        void *a = nullptr;
+        CSE_HIP_TRY(hipMalloc(&a, host.size()));
+        P->arenas.emplace_back(a, host.size());
+        CSE_HIP_TRY(hipMemcpy(a, host.data(), host.size(), hipMemcpyHostToDevice));
+        for (auto &d : dst) *d.first = (unsigned char *)a + d.second;
+        host.clear();
+        dst.clear();
+        return CSE_OK;
+    }
+};
+
 template <class T>
 int upload(T **dst, const T *src, size_t n) {
     if (n == 0) {
@@ -202,6 +264,7 @@ int upload(T **dst, const T *src, size_t n) {
 
 int build_platten(const cse_design *design, int64_t n_boxes, const double *theta,
                   const double *radii, const int32_t *sims, int32_t flags, Platten *P) {
+    Stager stage;   // read-only arrays: one transfer at the end of the tile setup
     if (!design || !theta || !radii || !sims || n_boxes < 1) {
         set_error("cse_platten_create: NULL argument or n_boxes < 1");
         return CSE_EINVAL;
@@ -685,7 +748,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
                 }
             P->n_keys += ((int64_t)B.n_sims + 63) / 64 * KEY_CHUNK;
         }
-        if (int e = upload((Blk2 **)&P->d_blocks, blks.data(), blks.size())) return e;
+        stage.add((Blk2 **)&P->d_blocks, blks.data(), blks.size());
 
         // design tables of the pooled z test
         const int n = P->n_per_arm, n1 = n + 1;
@@ -711,10 +774,10 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return S[a] < S[b]; });
         for (int j = 0; j < n1 * n1; ++j)
             group[j] = (j > 0 && S[order[j]] == S[order[j - 1]]) ? group[j - 1] : j;
-        if (int e = upload(&P->d_cut_tbl, cut.data(), cut.size())) return e;
-        if (int e = upload(&P->d_S_tbl, S.data(), S.size())) return e;
-        if (int e = upload(&P->d_S_order, order.data(), order.size())) return e;
-        if (int e = upload(&P->d_S_group, group.data(), group.size())) return e;
+        stage.add(&P->d_cut_tbl, cut.data(), cut.size());
+        stage.add(&P->d_S_tbl, S.data(), S.size());
+        stage.add(&P->d_S_order, order.data(), order.size());
+        stage.add(&P->d_S_group, group.data(), group.size());
     }
 
     for (int64_t t = 0; t < P->n_tiles; ++t)
@@ -730,15 +793,14 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     if (kind == CSE_BINOM2_Z || kind == CSE_HIER4 || kind == CSE_BASKET4)
         if (int e = plan_group_items(P, P->tune_wgs)) return e;
 
-    if (int e = upload(&P->d_theta, P->tile_theta.data(), P->tile_theta.size())) return e;
-    if (int e = upload(&P->d_N, P->tile_N.data(), P->tile_N.size())) return e;
-    if (int e = upload(&P->d_vert_off, P->vert_off.data(), P->vert_off.size())) return e;
-    if (int e = upload(&P->d_verts, P->verts.data(), P->verts.size())) return e;
-    if (int e = upload(&P->d_radii, P->tile_radii.data(), P->tile_radii.size())) return e;
-    if (int e = upload(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size())) return e;
-    if (int e = upload(&P->d_key_off, key_off.data(), key_off.size())) return e;
-    if (int e = upload(&P->d_key_stride, key_stride.data(), key_stride.size())) return e;
-    if (kind == CSE_PHASE23) P->p23.key_off = P->d_key_off;
+    stage.add(&P->d_theta, P->tile_theta.data(), P->tile_theta.size());
+    stage.add(&P->d_N, P->tile_N.data(), P->tile_N.size());
+    stage.add(&P->d_vert_off, P->vert_off.data(), P->vert_off.size());
+    stage.add(&P->d_verts, P->verts.data(), P->verts.size());
+    stage.add(&P->d_radii, P->tile_radii.data(), P->tile_radii.size());
+    stage.add(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size());
+    stage.add(&P->d_key_off, key_off.data(), key_off.size());
+    stage.add(&P->d_key_stride, key_stride.data(), key_stride.size());
     // N classes for the Clopper-Pearson table
     {
         std::vector<int32_t> cls(P->tile_N.begin(), P->tile_N.end());
@@ -755,9 +817,11 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             base[t] = off[std::lower_bound(cls.begin(), cls.end(), P->tile_N[t]) - cls.begin()];
         P->n_cls = (int32_t)cls.size();
         P->n_cp = e;
-        if (int r = upload(&P->d_cls_N, cls.data(), cls.size())) return r;
-        if (int r = upload(&P->d_cls_off, off.data(), off.size())) return r;
-        if (int r = upload(&P->d_cp_base, base.data(), base.size())) return r;
+        stage.add(&P->d_cls_N, cls.data(), cls.size());
+        stage.add(&P->d_cls_off, off.data(), off.size());
+        stage.add(&P->d_cp_base, base.data(), base.size());
+        if (int r = stage.flush(P)) return r;
+        if (kind == CSE_PHASE23) P->p23.key_off = P->d_key_off;
         CSE_HIP_TRY(hipMalloc((void **)&P->d_cp_mark, (size_t)e * sizeof(uint32_t)));
         CSE_HIP_TRY(hipMalloc((void **)&P->d_cp_tbl, (size_t)e * sizeof(double)));
     }
@@ -771,7 +835,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
-    CSE_HIP_TRY(hipStreamCreateWithFlags(&P->side, hipStreamNonBlocking));
+    CSE_HIP_TRY(take_side_stream(P->device, &P->side));
     for (hipEvent_t *e : {&P->ev_sim, &P->ev_val, &P->ev_fork, &P->ev_inv})
         CSE_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
     return CSE_OK;
@@ -874,11 +938,20 @@ void free_platten(Platten *P) {
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
                     P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes,
                     P->d_h4mask};
+    auto in_arena = [&](void *q) {
+        for (auto &a : P->arenas)
+            if ((unsigned char *)q >= (unsigned char *)a.first && (unsigned char *)q < (unsigned char *)a.first + a.second)
+                return true;
+        return false;
+    };
     for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+        if (q && !in_arena(q)) (void)hipFree(q);
+    for (auto &a : P->arenas) (void)hipFree(a.first);
+    P->arenas.clear();
     for (hipEvent_t e : {P->ev_sim, P->ev_val, P->ev_fork, P->ev_inv})
         if (e) (void)hipEventDestroy(e);
-    if (P->side) (void)hipStreamDestroy(P->side);
+    if (P->side) give_side_stream(P->device, P->side);
+    P->side = nullptr;
 }
 
 }  // namespace cse
