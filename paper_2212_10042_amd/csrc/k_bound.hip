@@ -119,6 +119,10 @@ constexpr int GB = 8;
 // bracket 60 * (2/9)^12 ~ 9e-7 in s; near the optimum the objective is quadratic in s, so the
 // best sampled value is within (1/2) f'' (9e-7)^2 of the optimum (~1e-11 for |f''| ~ 50)
 constexpr int SECTION_ROUNDS = 12;
+// one lane per tile from this many tiles on (measured: at 33 k and 60 k tiles the serial chain
+// of 40 evaluations per tile is slower than the cooperative search; at 2^20 tiles the golden
+// search's fewer evaluations win, 1.20 -> 0.91 ms for the validation bound)
+constexpr int64_t BOUND_ONE_LANE_TILES = 262144;
 
 template <int FAM, int D>
 __device__ __forceinline__ double part(int n, const double *th, double q, const double *v) {
@@ -248,13 +252,72 @@ __device__ double section_search(int lane, const TileGeom<D> &T, double loga, do
     return sg * best;
 }
 
+// One lane per tile: golden-section search on s over the same bracket, each round one new
+// evaluation (the bracket shrinks by 0.618); 38 rounds leave 60 * 0.618^39 ~ 4e-7.  Fewer
+// evaluations than the cooperative search (40 against 12 x 8) for launches with enough tiles
+// to fill the chip; the best evaluated point is returned, as there.
+constexpr int GOLD_ROUNDS = 38;
+
+template <int FAM, int D, bool INV>
+__device__ double golden_search(const TileGeom<D> &T, double loga, double *s_best) {
+    const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
+    const double g = 0.6180339887498949;   // (sqrt 5 - 1) / 2
+    auto ev = [&](double s) {
+        const double f = sg * objective<FAM, D, INV>(T, loga, s);
+        return f != f ? INFINITY : f;
+    };
+    double lo = -30.0, hi = 30.0;
+    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
+    double f1 = ev(x1), f2 = ev(x2);
+    double best = f1, bs = x1;
+    if (f2 < best) {
+        best = f2;
+        bs = x2;
+    }
+    for (int r = 0; r < GOLD_ROUNDS; ++r) {
+        if (f1 <= f2) {   // the minimum lies in [lo, x2]
+            hi = x2;
+            x2 = x1;
+            f2 = f1;
+            x1 = hi - g * (hi - lo);
+            f1 = ev(x1);
+            if (f1 < best) {
+                best = f1;
+                bs = x1;
+            }
+        } else {          // in [x1, hi]
+            lo = x1;
+            x1 = x2;
+            f1 = f2;
+            x2 = lo + g * (hi - lo);
+            f2 = ev(x2);
+            if (f2 < best) {
+                best = f2;
+                bs = x2;
+            }
+        }
+    }
+    *s_best = bs;
+    return sg * best;
+}
+
+template <int L, int FAM, int D, bool INV>
+__device__ __forceinline__ double search(int lane, const TileGeom<D> &T, double loga, double *s_best) {
+    if constexpr (L == 1)
+        return golden_search<FAM, D, INV>(T, loga, s_best);
+    else
+        return section_search<FAM, D, INV>(lane, T, loga, s_best);
+}
+
 __global__ void k_negate1(double *x) { x[0] = -x[0]; }
 
 // mode 0: validate (CP then tilt), mode 1: invert (alpha', k), mode 2: tilt of given a,
 // mode 3: lower validation bound (Remark 2: the tilt of 1 - cp_lower = cp_upper(N - R), then
 // lower = 1 - that; cp_out receives cp_lower).
-template <int FAM, int D>
-__global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
+// L lanes per tile: GB (cooperative section search, 256-thread blocks of 32 tiles) or 1
+// (golden-section search, 64-thread blocks of 64 tiles).
+template <int FAM, int D, int L>
+__global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, int64_t n_tiles,
                                                const double *__restrict__ theta,
                                                const int32_t *__restrict__ vert_off,
                                                const double *__restrict__ verts,
@@ -269,12 +332,14 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
                                                double *__restrict__ q_out,
                                                int32_t *__restrict__ k_out,
                                                double *__restrict__ cp_out) {
-    __shared__ double s_psi1[256 / GB][MAXV];
-    __shared__ uint8_t s_vidx[256 / GB][MAXV];
-    __shared__ double s_uv[256 / GB][D * SHU];
+    constexpr int TPB = L == 1 ? 64 : 256 / GB;   // tiles per block
+    static_assert(L == 1 || L == GB, "lanes per tile");
+    __shared__ double s_psi1[TPB][MAXV];
+    __shared__ uint8_t s_vidx[TPB][MAXV];
+    __shared__ double s_uv[TPB][D * SHU];
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int lane = threadIdx.x % GB, grp = threadIdx.x / GB;
-    int64_t t = gid / GB;
+    const int lane = threadIdx.x % L, grp = threadIdx.x / L;
+    int64_t t = gid / L;
     const bool valid = t < n_tiles;
     if (!valid) t = n_tiles - 1;   // idle groups shadow the last tile and write nothing
     TileGeom<D> T;
@@ -299,7 +364,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
     }
     T.shared = false;
     if (!T.box) {
-        for (int j = lane; j < T.nv; j += GB) s_psi1[grp][j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
+        for (int j = lane; j < T.nv; j += L) s_psi1[grp][j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
         // distinct displacement values per arm, in order of first appearance (every lane of the
         // group finds the same ones); an arm with one value repeats it in the second slot
         bool shared = true;
@@ -326,7 +391,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
                     code |= 1u << a;
                 }
             }
-            if (j % GB == lane) s_vidx[grp][j] = (uint8_t)code;
+            if (j % L == lane) s_vidx[grp][j] = (uint8_t)code;
         }
         if (lane == 0)
 #pragma unroll
@@ -343,7 +408,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
 
     if (mode == 1) {
         double sb;
-        const double val = section_search<FAM, D, true>(lane, T, log(level), &sb);
+        const double val = search<L, FAM, D, true>(lane, T, log(level), &sb);
         if (valid && lane == 0) {
             const double ap = exp(val);
             out[t] = ap;
@@ -373,7 +438,7 @@ __global__ __launch_bounds__(256) void k_bound(int mode, int n, int64_t n_tiles,
         return;
     }
     double sb;
-    const double val = section_search<FAM, D, false>(lane, T, log(a), &sb);
+    const double val = search<L, FAM, D, false>(lane, T, log(a), &sb);
     if (valid && lane == 0) {
         const double ub = fmin(exp(val), 1.0);
         out[t] = lower ? 1.0 - ub : ub;
@@ -587,13 +652,23 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
         hipLaunchKernelGGL(k_cp_table, dim3((uint32_t)((P.max_cls_N + 1 + 63) / 64), (uint32_t)P.n_cls),
                            dim3(64), 0, st, P.d_cls_N, P.d_cls_off, P.d_cp_mark, level, zq, P.d_cp_tbl);
     }
-    const int bs = 256;
-    const int64_t threads = P.n_tiles * GB;
+    // enough tiles to give every SIMD work with one lane per tile: the golden search (fewer
+    // evaluations); otherwise GB lanes per tile shorten each tile's chain of evaluations
+    const bool one_lane = P.n_tiles >= BOUND_ONE_LANE_TILES;
+    const int bs = one_lane ? 64 : 256;
+    const int64_t threads = P.n_tiles * (one_lane ? 1 : GB);
     const int64_t grid = (threads + bs - 1) / bs;
-#define CSE_BOUND_LAUNCH(FAM, D)                                                                  \
-    hipLaunchKernelGGL((k_bound<FAM, D>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm,   \
-                       P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
-                       a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out)
+#define CSE_BOUND_LAUNCH(FAM, D)                                                                        \
+    do {                                                                                                \
+        if (one_lane)                                                                                   \
+            hipLaunchKernelGGL((k_bound<FAM, D, 1>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm, \
+                               P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
+                               a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);          \
+        else                                                                                            \
+            hipLaunchKernelGGL((k_bound<FAM, D, GB>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm, \
+                               P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
+                               a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);          \
+    } while (0)
     if (P.family == FAM_NORMAL && P.d == 1)
         CSE_BOUND_LAUNCH(FAM_NORMAL, 1);
     else if (P.family == FAM_BINOM && P.d == 2)
