@@ -120,17 +120,15 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
 #pragma unroll
         for (int v = 0; v < B2V; ++v) y1[v] = 0;
         if (live) {
+            // both arms in one loop: independent compares to schedule between each compare and
+            // the add that consumes its mask
 #pragma unroll 7
             for (int j = 0; j < NP35; ++j) {
-                const uint32_t x = words[j][lane];
+                const uint32_t x0 = words[j][lane], x1 = words[NP35 + j][lane];
 #pragma unroll
-                for (int u = 0; u < B2U; ++u) y0[u] += (x < T0[u]) ? 1 : 0;
-            }
-#pragma unroll 7
-            for (int j = NP35; j < NW; ++j) {
-                const uint32_t x = words[j][lane];
+                for (int u = 0; u < B2U; ++u) y0[u] += (x0 < T0[u]) ? 1 : 0;
 #pragma unroll
-                for (int v = 0; v < B2V; ++v) y1[v] += (x < T1[v]) ? 1 : 0;
+                for (int v = 0; v < B2V; ++v) y1[v] += (x1 < T1[v]) ? 1 : 0;
             }
         }
         __syncthreads();   // words consumed: the next chunk (or a flush) may overwrite them
