@@ -57,7 +57,7 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # HBM bytes per dispatch of k_binom2<true> on binom2_256_tri, from the FETCH_SIZE / WRITE_SIZE
 # counter runs in profiles/binom2_256_tri_hbm_counters.md (scaled by a 256 MiB copy).  Valid
 # only while that kernel is unchanged; other workloads report null.
-TRAFFIC_BINOM2_256_TRI = 604_449_883
+TRAFFIC_BINOM2_256_TRI = 605_256_615
 
 WORKLOADS = {
     "binom2_256_tri": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
