@@ -334,7 +334,7 @@ def main():
         taylor = {"kernel_ms": ms / max(cnt, 1), "max_bound": float(to["bound"].max().item()),
                   "max_tilt_bound": float(o["bound"].max().item())}
 
-    # the two-sided band (Remark 2), a confidence set (Section 7) and the randomised calibration,
+    # the two-sided band (Remark 2), a confidence set (Section 8) and the randomised calibration,
     # each on this step's outputs and timed on its own (not part of the step)
     ext = None
     if not args.no_extensions and n:

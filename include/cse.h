@@ -3,10 +3,10 @@
  *
  * Method: Yang, Thompson & Sklar, "Guarantees for Comprehensive Simulation
  * Assessment of Statistical Methods".  The library simulates a trial design at
- * the points of a platten (Section 4, Definition 1), counts rejections, forms
+ * the points of a platten (Section 5, Definition 1), counts rejections, forms
  * score-function gradient sums, selects the calibrated threshold of each tile
- * as an order statistic (Section 6.1), and evaluates the Clopper-Pearson plus
- * Tilt-Bound over each tile (Sections 5.1-5.2, 6.2).
+ * as an order statistic (Section 7.1), and evaluates the Clopper-Pearson plus
+ * Tilt-Bound over each tile (Sections 6.1-6.2, 7.2).
  *
  * Conventions for every entry point:
  *   - Status: CSE_OK (0) or a negative cse_status; errors never cross the ABI
@@ -21,12 +21,12 @@
  *   - Calls are asynchronous: a CSE_OK status covers argument validation and
  *     launch errors; results are ready when `stream` is synchronised.
  *   - A "tile" below is one piece box ∩ P(b) of a caller box with non-empty
- *     interior (null configuration b, Section 4).  Tiles are numbered in box
+ *     interior (null configuration b, Section 5).  Tiles are numbered in box
  *     order, then by b ascending.  cse_platten_describe maps them back.
  *   - Random numbers: simulation k of every tile uses the words
  *     Philox4x32-10(key = (seed lo, seed hi), ctr = (w/4, k, 0, 0))[w mod 4]
  *     (Salmon et al., SC'11), i.e. common random numbers across tiles, which
- *     the calibration guarantee allows (Section 6.3).
+ *     the calibration guarantee allows (Section 7.3).
  */
 #ifndef CSE_H
 #define CSE_H
@@ -61,7 +61,7 @@ typedef enum {
      * b: S_b = min_{i in b} (1 - P(p_i > p_0 | y)); reject when S_b < cut.  d = 4. */
     CSE_HIER4 = 3,
     /* Phase II/III Bayesian selection design (Section 10.2 and its appendix): four Bernoulli
-     * arms (arm 0 control) embedded with n_per_arm = 350 potential patients each (Section 8);
+     * arms (arm 0 control) embedded with n_per_arm = 350 potential patients each (Section 9);
      * Phase II of up to 400 patients with three looks (arm dropping for p_best < 0.15,
      * selection when p_success > 0.70, 0.60 at the last look), Phase III of up to 200 + 200
      * on the selected arm s and control with an interim (success when
@@ -98,7 +98,7 @@ typedef struct cse_platten cse_platten;
                                   null (their tile is the whole box, in_null = 0)   */
 
 /*
- * cse_platten_create -- build the platten of Definition 1 (Section 4) from caller boxes.
+ * cse_platten_create -- build the platten of Definition 1 (Section 5) from caller boxes.
  *   design   host, read once.
  *   n_boxes  number of boxes (>= 1).
  *   theta    host, float64 [n_boxes][d], the simulation point of each box (its centre).
@@ -107,7 +107,7 @@ typedef struct cse_platten cse_platten;
  *   flags    0 or CSE_PLATTEN_KEEP_ALL.
  *   out      receives the handle (destroy with cse_platten_destroy).
  * Splits each box into tiles box ∩ P(b) with non-empty interior (eq. of the null
- * partition, Section 4), enumerates each tile's vertices in float64 (the supremum of
+ * partition, Section 5), enumerates each tile's vertices in float64 (the supremum of
  * the bound over a convex polytope is attained at a vertex, Theorem 3), computes the
  * per-arm Bernoulli thresholds round(2^32 expit(theta)) in float64, plans the tile
  * batches the kernels run, and uploads everything to the current HIP device.
@@ -142,9 +142,9 @@ int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32
                          int32_t *in_null);
 
 /*
- * cse_simulate -- Monte Carlo at every tile with the design's fixed rule (Section 5.1 input).
+ * cse_simulate -- Monte Carlo at every tile with the design's fixed rule (Section 6.1 input).
  *   reject   int32 [n_tiles]       R_i = number of simulations whose F_b(X) = 1 (FWER event of
- *                                  the tile's configuration b, Section 4).
+ *                                  the tile's configuration b, Section 5).
  *   score_T  int64 [n_tiles][d] or NULL: binomial designs, sum over rejecting simulations of
  *                                  the sufficient statistic T(x) (arm success counts, Example 1);
  *                                  PHASE23: int64 [n_tiles][2d], the sums of the observed success
@@ -161,10 +161,10 @@ int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *
                  double *score_Z, double *grad, void *stream);
 
 /*
- * cse_validate -- Validation procedure (Algorithm 1, Section 5): simulate as cse_simulate, then
- *   cp_upper   float64 [n_tiles] Clopper-Pearson (1-delta) upper bound at theta_i (Section 5.1)
+ * cse_validate -- Validation procedure (Algorithm 1, Section 6): simulate as cse_simulate, then
+ *   cp_upper   float64 [n_tiles] Clopper-Pearson (1-delta) upper bound at theta_i (Section 6.1)
  *   tile_bound float64 [n_tiles] inf_q max_{v in vertices} U(theta_i, v, q, cp_upper_i)
- *                                (Tilewise Optimized Tilt-Bound, Remark 3, Section 5.2)
+ *                                (Tilewise Optimized Tilt-Bound, Remark 3, Section 6.2)
  *   q_star     float64 [n_tiles] or NULL: the optimising Holder exponent q.
  * reject/score_T/score_Z/grad as in cse_simulate (score pointers may be NULL).
  * Errors: CSE_EINVAL (delta outside (0,1)), CSE_EHIP.
@@ -174,12 +174,12 @@ int cse_validate(const cse_platten *p, uint64_t seed, double delta, int32_t *rej
                  double *tile_bound, double *q_star, void *stream);
 
 /*
- * cse_calibrate -- Calibration procedure (Algorithm 2, Section 6):
- *   alpha_prime   float64 [n_tiles]  sup_q min_v U^{-1}(theta_i, v, q, alpha) (Section 6.2)
+ * cse_calibrate -- Calibration procedure (Algorithm 2, Section 7):
+ *   alpha_prime   float64 [n_tiles]  sup_q min_v U^{-1}(theta_i, v, q, alpha) (Section 7.2)
  *   k             int32   [n_tiles]  floor((N_i + 1) alpha'_i)
  *   lambda_tile   float64 [n_tiles]  lambda*_i = S_(k_i), the k_i-th smallest statistic of the
- *                                    tile (Section 6.1); -inf when k_i = 0
- *   lambda_global float64 [1]        min_i lambda*_i (Section 6.3)
+ *                                    tile (Section 7.1); -inf when k_i = 0
+ *   lambda_global float64 [1]        min_i lambda*_i (Section 7.3)
  *   reject_at_lambda int32 [n_tiles] or NULL: #{simulations with S < lambda*_i}
  * Validation outputs at the design's fixed rule (reject, score_T, score_Z, grad, cp_upper,
  * tile_bound) may be requested in the same pass (each may be NULL; cp_upper/tile_bound use
@@ -230,13 +230,13 @@ int cse_taylor(const cse_platten *p, const double *f, const double *grad, double
                double *point, void *stream);
 
 /*
- * cse_validate_lower -- the lower side of a two-sided validation band (Remark 2, Section 4: the
+ * cse_validate_lower -- the lower side of a two-sided validation band (Remark 2, Section 4.1: the
  * Tilt-Bound applied to 1 - F gives f(theta0 + v) >= 1 - U(theta0, v, q, 1 - f(theta0))).
  *   R        int32 [n_tiles] device rejection counts of this platten's tiles (the `reject`
  *                            output of cse_simulate / cse_validate / cse_calibrate)
  *   cp_lower float64 [n_tiles] or NULL: Clopper-Pearson (1-delta) lower bound
  *                            Beta^{-1}(delta; R, N - R + 1) at theta_i (0 when R = 0), computed
- *                            as 1 - cp_upper(N - R) (Section 5.1)
+ *                            as 1 - cp_upper(N - R) (Section 6.1)
  *   lower    float64 [n_tiles] 1 - inf_q max_v U(theta_i, v, q, 1 - cp_lower_i): with
  *                            probability >= 1 - delta, f >= lower on the whole tile
  *                            (with cse_validate's tile_bound: a band at level 1 - 2 delta)
@@ -247,7 +247,7 @@ int cse_validate_lower(const cse_platten *p, const int32_t *R, double delta, dou
                        double *q_star, void *stream);
 
 /*
- * cse_confidence_set -- confidence set from a calibration (Section 7).  Each tile's test
+ * cse_confidence_set -- confidence set from a calibration (Section 8).  Each tile's test
  * rejects the observed statistic when s_i < lambda_i; the confidence region is the union of
  * the tiles it does not reject, and the confidence set of an estimand e(theta) is the image of
  * that region.
@@ -274,7 +274,7 @@ int cse_confidence_set(const cse_platten *p, const double *s_obs, int64_t s_stri
 
 /*
  * cse_calibrate_tiebreak -- randomised calibration (the adjoined uniform discussed with
- * Theorem (pointwise calibration), Section 6.1): every simulation k also draws
+ * Theorem (pointwise calibration), Section 7.1): every simulation k also draws
  * u_k = first word of Philox4x32-10(key = seed, counter = (0, k, 1, 0)) (shared by all tiles,
  * disjoint from the data words), the statistic is the pair (S, u) and the threshold the pair
  * (lambda, c), both ordered lexicographically; a new observation (s, u) is rejected when

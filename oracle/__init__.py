@@ -116,7 +116,7 @@ def pooled_z(y0: int, y1: int, n: int = N_PER_ARM) -> float:
 
 # ------------------------------------------------------------------- designs
 def sim_ztest1(theta, sims, seed: int, cut: float = 1.96, want_S: bool = False):
-    """1-D z-test (Section 4.2, Section 5.4): R, sum of Z over rejections, S = -X."""
+    """1-D z-test (Section 4.2, Section 6.4): R, sum of Z over rejections, S = -X."""
     th = np.ascontiguousarray(np.asarray(theta, np.float64).reshape(-1))
     sm = np.ascontiguousarray(sims, np.int32)
     n = th.size
@@ -174,7 +174,7 @@ def sim_hier4(theta_tiles, cfg, sims, seed: int, cut: float, n: int = N_PER_ARM,
     return R, sT, S, Y
 
 
-N_EMBED_P23 = 350   # patients per arm in the embedding of the Phase II/III design (Section 8)
+N_EMBED_P23 = 350   # patients per arm in the embedding of the Phase II/III design (Section 9)
 
 
 def hier4_summary(y, n):
@@ -329,7 +329,7 @@ def log_tilt(family, theta0, v, q, a, n=N_PER_ARM):
 
 
 def log_inv_tilt(family, theta0, v, q, alpha, n=N_PER_ARM):
-    """log of the Inverted Tilt-Bound U^{-1}(theta0, v, q, alpha) (Section 6.2)."""
+    """log of the Inverted Tilt-Bound U^{-1}(theta0, v, q, alpha) (Section 7.2)."""
     return q / (q - 1.0) * (np.log(alpha) - psi(family, theta0, v, q, n) / q + psi(family, theta0, v, 1.0, n))
 
 
@@ -392,7 +392,7 @@ def tile_bound(family, theta0, V, a, n=N_PER_ARM):
 
 
 def tile_inverse(family, theta0, V, alpha, n=N_PER_ARM):
-    """alpha' = sup_q min_{v in V} U^{-1}(theta0, v, q, alpha) (Section 6.2).  Returns (alpha', q_star)."""
+    """alpha' = sup_q min_{v in V} U^{-1}(theta0, v, q, alpha) (Section 7.2).  Returns (alpha', q_star)."""
     theta0 = np.asarray(theta0, np.float64)
     V = np.asarray(V, np.float64)
     m = theta0.shape[0]
@@ -443,7 +443,7 @@ def taylor_bound(family, theta0, radii, V, f, g, n=N_PER_ARM):
 
 
 def cp_upper(R, N, delta):
-    """Clopper-Pearson (1-delta) upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 5.1); 1 when R == N."""
+    """Clopper-Pearson (1-delta) upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 6.1); 1 when R == N."""
     R = np.asarray(R, np.float64)
     N = np.asarray(N, np.float64)
     out = np.ones(np.broadcast(R, N).shape)
@@ -454,7 +454,7 @@ def cp_upper(R, N, delta):
 
 
 def cp_lower(R, N, delta):
-    """Clopper-Pearson (1-delta) lower bound Beta^{-1}(delta; R, N-R+1) (Section 5.1); 0 when R == 0."""
+    """Clopper-Pearson (1-delta) lower bound Beta^{-1}(delta; R, N-R+1) (Section 6.1); 0 when R == 0."""
     R = np.asarray(R, np.float64)
     N = np.asarray(N, np.float64)
     out = np.zeros(np.broadcast(R, N).shape)
@@ -473,7 +473,7 @@ def tile_lower(family, theta0, V, b, n=N_PER_ARM):
 
 # ------------------------------------------------------------- the platten
 def hypotheses(design: str, d: int):
-    """Null hypotheses as half-spaces g . theta <= h (Section 4):
+    """Null hypotheses as half-spaces g . theta <= h (Section 5):
     z-test H0: theta <= 0; multi-arm designs (arm 0 control): H_i: theta_i <= theta_0."""
     if design == "ztest1":
         return [(np.array([1.0]), 0.0)]
@@ -494,7 +494,7 @@ def family_of(design: str) -> str:
 
 def n_of(design: str) -> int:
     """Patients per arm of the exponential family the bound is taken in: the Phase II/III
-    design is a function of its embedding with 350 potential patients per arm (Section 8)."""
+    design is a function of its embedding with 350 potential patients per arm (Section 9)."""
     return N_EMBED_P23 if design == "phase23" else N_PER_ARM
 
 
@@ -514,7 +514,7 @@ def _enumerate_vertices(G, h, d, tol=1e-12):
 
 def subtiles(design: str, theta, radii, keep_all: bool = False, theta0=None):
     """Split each box into its null-configuration pieces box ∩ P(b) with non-empty interior
-    (Section 4, Definition 1).  Returns a list of (box index, b bitmask, vertices [nv, d],
+    (Section 5, Definition 1).  Returns a list of (box index, b bitmask, vertices [nv, d],
     in_null flag); b bit j-1 is hypothesis j.  With keep_all (single-hypothesis designs only),
     a box that meets no null is kept whole with in_null = False.
     """
@@ -661,7 +661,7 @@ def order_statistic(S_row: np.ndarray, k: int) -> float:
 
 def tiebreak_u(seed: int, n: int) -> np.ndarray:
     """The uniform adjoined to each simulation by the randomised test (discussion of Theorem
-    (pointwise calibration), Section 6.1): u_k = first word of Philox4x32-10 at counter
+    (pointwise calibration), Section 7.1): u_k = first word of Philox4x32-10 at counter
     (0, k, 1, 0) with the seed as key, as an integer in [0, 2^32); P(u < c) = c / 2^32.  It is
     disjoint from the data words (counter word 2 = 0) and shared by all tiles."""
     out = np.zeros(max(int(n), 0), np.uint32)
@@ -737,9 +737,9 @@ def calibrate_tiebreak(design: str, theta, radii, sims, seed: int, alpha: float,
                 c_global=int(c[g]) if len(lam) else 0, N=N, subs=subs)
 
 
-# ---------------------------------------------------- confidence sets (Section 7)
+# ---------------------------------------------------- confidence sets (Section 8)
 def estimand_range(subs, coef, link: str = "linear"):
-    """Range of e over each tile (Section 7's image of a tile under e):
+    """Range of e over each tile (Section 8's image of a tile under e):
     e(theta) = c0 + sum_a c_a g(theta_a), coef = (c_1 .. c_d, c0), g the identity ("linear")
     or expit ("expit", e.g. p_1 - p_0).  Linear: min / max over the tile's vertices (exact on a
     polytope).  Expit: the sum over coordinates of the extremes of c_a expit(theta_a) over the
@@ -764,7 +764,7 @@ def estimand_range(subs, coef, link: str = "linear"):
 
 
 def confidence_set(subs, lam, s_obs, coef, link: str = "linear", key_dtype=np.float32):
-    """Section 7: with the observed statistic s_i of each tile and its calibrated threshold
+    """Section 8: with the observed statistic s_i of each tile and its calibrated threshold
     lambda_i, the confidence region is the union of the tiles not rejected, s_i >= lambda_i
     (the test rejects when s_i < lambda_i; compared in key_dtype, the precision of the
     simulated statistic), and the confidence set of e is the image of that region: returns

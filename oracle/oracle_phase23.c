@@ -30,7 +30,7 @@
  *    P(theta_s > theta_0) > 0.95 -> success (rejection of H_s);  else p_succ_s with m = 100
  *    below 0.20 -> futility;  else 100 more each and the final analysis, which rejects H_s when
  *    P(theta_s > theta_0) > 1 - lambda.
- *  Embedding (Section 8): patient j of arm a uses word a * 350 + j of the simulation's stream
+ *  Embedding (Section 9): patient j of arm a uses word a * 350 + j of the simulation's stream
  *    (at most 350 patients per arm), response iff word < T(theta_a).
  *  Calibration statistic for a tile with null configuration b (bit i-1 set when H_i is true):
  *    S = -inf if s is in b and the trial succeeded at the Phase III interim;

@@ -15,10 +15,10 @@
  *   - word(seed, k, w) = Philox4x32-10(key = (seed lo, seed hi),
  *                                      ctr = (w / 4, k, 0, 0))[w mod 4].
  *     Simulation k draws the same words at every tile (common random numbers;
- *     allowed because each tile's own simulations stay i.i.d., Section 6.3).
+ *     allowed because each tile's own simulations stay i.i.d., Section 7.3).
  *   - Bernoulli(expit(theta)) draw from word u: success iff u < T(theta) with
  *     T(theta) = round(2^32 / (1 + exp(-theta))) clamped to [0, 2^32 - 1].
- *     Arm a, patient j uses word a * n + j (the i.i.d. embedding of Section 8).
+ *     Arm a, patient j uses word a * n + j (the i.i.d. embedding of Section 9).
  *   - Normal draw (z-test): u_i = ((word_i >> 9) + 1/2) * 2^-23 for words 0, 1;
  *     Z = sqrt(-2 ln u_0) * cos(2 pi u_1) (Box & Muller, 1958).
  */
@@ -97,7 +97,7 @@ double orc_box_muller(uint32_t w0, uint32_t w1) {
 
 /* ------------------------------------------------------------- z-test (1-D)
  * X ~ N(theta, 1); reject H0: theta <= 0 when X > cut (Section 4.2).
- * Calibration statistic S = -X, rejection S < lambda (Section 6).
+ * Calibration statistic S = -X, rejection S < lambda (Section 7).
  * Score of the normal location family: T(x) - grad A(theta) = x - theta = Z.
  * Outputs per tile: R (rejections at `cut`), sum over rejections of Z, and
  * optionally S for every simulation (row stride s_stride).

@@ -6,9 +6,9 @@ every computation runs in the library's HIP kernels.  If libcse.so is missing th
 import fails; there is no other execution path.
 
 Method: Yang, Thompson & Sklar, "Guarantees for Comprehensive Simulation
-Assessment of Statistical Methods" -- validation (Algorithm 1, Section 5) and
-calibration (Algorithm 2, Section 6) over a platten of tiles (Definition 1,
-Section 4), with the Tilt-Bound of Theorem 1.
+Assessment of Statistical Methods" -- validation (Algorithm 1, Section 6) and
+calibration (Algorithm 2, Section 7) over a platten of tiles (Definition 1,
+Section 5), with the Tilt-Bound of Theorem 1.
 """
 from __future__ import annotations
 
@@ -441,7 +441,7 @@ class Platten:
         return out
 
     def confidence_set(self, s_obs, lambda_tile, coef, link="linear", device="cuda"):
-        """Confidence set from a calibration (Section 7): keep mask, per-tile range of e and the
+        """Confidence set from a calibration (Section 8): keep mask, per-tile range of e and the
         range over kept tiles.  s_obs: a float or a per-tile float64 tensor."""
         n = self.n_tiles
         if isinstance(s_obs, torch.Tensor):

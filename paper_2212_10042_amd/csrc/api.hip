@@ -216,7 +216,7 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
     // inversion (which does not depend on the simulation) is a branch beside the simulation
     // too; eager calls keep it in line, so that every kernel's own timing describes that
     // kernel alone.
-    // target level of each tile (Section 6.2), then its order-statistic index (Section 6.1)
+    // target level of each tile (Section 7.2), then its order-statistic index (Section 7.1)
     const bool branch_invert = t_capturing;
     {
         hipStream_t is = branch_invert ? P.side : st;

@@ -1,11 +1,11 @@
 // k_bound.hip -- float64 bound of each tile, eight lanes per tile.
 //
-//  * Clopper-Pearson upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 5.1): the regularized
+//  * Clopper-Pearson upper bound Beta^{-1}(1-delta; R+1, N-R) (Section 6.1): the regularized
 //    incomplete beta function by the continued fraction of DLMF 8.17.22 (modified Lentz
 //    evaluation), inverted by bracketed Newton steps on log(1 - I_x).
 //  * Tilewise Optimized Tilt-Bound inf_q max_{v in vertices} U(theta, v, q, a) (Theorem 1,
 //    Remark 3, Theorem 3) and the calibration target sup_q min_v U^{-1}(theta, v, q, alpha)
-//    (Section 6.2), exponential-family form psi(theta, v, q) = A(theta + q v) - A(theta)
+//    (Section 7.2), exponential-family form psi(theta, v, q) = A(theta + q v) - A(theta)
 //    (Example 1).  Both objectives are quasi-convex (quasi-concave) in q (Theorem 2), so a
 //    parallel section search over s = log(q - 1) in [-30, 30] finds the optimum.
 //  Log-partition A(theta): normal location sum theta^2/2; independent Bernoulli arms with n
@@ -515,7 +515,7 @@ hipError_t launch_taylor(const Platten &P, const double *f, const double *g, dou
     return hipGetLastError();
 }
 
-// ---- confidence sets from calibration (Section 7) ----
+// ---- confidence sets from calibration (Section 8) ----
 // Per tile: kept when its test does not reject the observed statistic, s_i >= lambda_i
 // (compared in the precision of the design's keys: float64 outcome statistics for the 2-arm
 // design, float32 otherwise), and the range of e(theta) = c0 + sum_a c_a g(theta_a) over the

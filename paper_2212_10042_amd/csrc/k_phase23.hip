@@ -15,7 +15,7 @@
 //   Phase III: 100 + 100 on the selected arm s and control, interim: success if
 //   P(theta_s > theta_0) > 0.95, futility if p_succ_s (100 added) < 0.20; else 100 + 100 more and
 //   the final analysis.
-//   Embedding (Section 8): patient j of arm a draws word a * 350 + j of the simulation's stream.
+//   Embedding (Section 9): patient j of arm a draws word a * 350 + j of the simulation's stream.
 //   Statistic of a tile with null configuration b: -inf for an early success with s in b,
 //   1 - P_final(theta_s > theta_0) for a final analysis with s in b, +inf otherwise; the
 //   design's rule at lambda rejects (falsely) when S < lambda.

@@ -1,6 +1,6 @@
 // k_select.hip -- the calibrated threshold of each tile, lambda*_i = S_(k_i), the k_i-th
-// smallest statistic among the tile's N_i simulations (Section 6.1), the count of
-// simulations strictly below it, and lambda* = min_i lambda*_i (Section 6.3).
+// smallest statistic among the tile's N_i simulations (Section 7.1), the count of
+// simulations strictly below it, and lambda* = min_i lambda*_i (Section 7.3).
 // One workgroup per tile, counts in LDS.  Plus the small per-tile finishing kernels
 // (score gradient, fixed-point conversion, zero fill).
 #include <math.h>

@@ -2,7 +2,7 @@
 //
 // One wave owns one tile batch for a range of simulations.  Per simulation (one per lane)
 // the Philox words are generated in registers, turned into draws, shared by every tile
-// of the batch (common random numbers, Section 6.3), and reduced into per-tile rejection
+// of the batch (common random numbers, Section 7.3), and reduced into per-tile rejection
 // counts R and score sums (sufficient statistic over rejections, Example 1).  In
 // calibration mode each (simulation, tile) also stores its key: the outcome index
 // (2-arm design) or the statistic S in float32 (z-test).  Nothing else reaches memory.

@@ -1,4 +1,4 @@
-// platten.cpp -- host side of the platten (Section 4, Definition 1): the null partition of
+// platten.cpp -- host side of the platten (Section 5, Definition 1): the null partition of
 // each box, the vertices of every tile (float64), the Bernoulli thresholds, the design
 // tables and the tile batches ("blocks") the kernels run.  Everything is uploaded once.
 #include <math.h>
@@ -359,7 +359,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         hyp[j] = hs;
     }
 
-    // ---- the null partition of every box (Section 4) ----
+    // ---- the null partition of every box (Section 5) ----
     const int ncorner = 1 << d;
     std::vector<double> centre;   // simulation point of each tile
     if (kind == CSE_BASKET4) {

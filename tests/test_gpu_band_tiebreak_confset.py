@@ -1,5 +1,5 @@
 """GPU parity of the lower validation bound (Remark 2, two-sided bands), randomised calibration
-(the adjoined uniform of Section 6.1) and confidence sets from calibration (Section 7) through
+(the adjoined uniform of Section 7.1) and confidence sets from calibration (Section 8) through
 the C ABI vs the oracle.
 
 Bars: rejection counts, k, the tie-break thresholds c_i (uint32), counts below the pair

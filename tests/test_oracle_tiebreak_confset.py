@@ -1,6 +1,6 @@
 """Pins of the oracle's randomised calibration (the adjoined uniform of the discussion of
-Theorem (pointwise calibration), Section 6.1) and of confidence sets from calibration
-(Section 7), each against something other than the oracle's own formulas:
+Theorem (pointwise calibration), Section 7.1) and of confidence sets from calibration
+(Section 8), each against something other than the oracle's own formulas:
 
 - the tie-break stream against the Philox block function (pinned by published known-answer
   values) and a uniformity check; the pair order statistic against Python's tuple sort;

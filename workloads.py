@@ -2,7 +2,7 @@
 
 This module holds *inputs only*: tile centres, half-widths and simulations per
 tile, laid out the way the case studies of the paper lay out their grids
-(equally spaced centres of equal boxes, Section 5.4 and Section 10.2; n = 35
+(equally spaced centres of equal boxes, Section 6.4 and Section 10.2; n = 35
 patients per arm, Section 10.1; alpha = 2.5%, Section 1; 2,048 or more
 simulations per tile, Section 10.2).  It contains none of the method's
 arithmetic: no thresholds, no null-hypothesis clipping, no vertices, no
@@ -29,7 +29,7 @@ def _centres(lo: float, hi: float, m: int) -> np.ndarray:
 
 def ztest_1d(n_tiles: int = 64, sims: int = 10_000, lo: float = -1.0, hi: float = 0.0,
              seed: int = 0) -> dict:
-    """1-D normal z-test grid: equal tiles over [lo, hi] (Section 5.4, Section 6.4)."""
+    """1-D normal z-test grid: equal tiles over [lo, hi] (Section 6.4, Section 7.4)."""
     c = _centres(lo, hi, n_tiles)
     r = (hi - lo) / (2 * n_tiles)
     return dict(name=f"ztest1d_{n_tiles}x{sims}", design="ztest1",
