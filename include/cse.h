@@ -195,6 +195,27 @@ int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alp
                   void *stream);
 
 /*
+ * cse_calibrate_noalloc -- cse_calibrate for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).  Same arguments,
+ * launches and results as cse_calibrate, but the calibration keys live in a static workspace of
+ * CSE_NOALLOC_SCRATCH_BYTES bytes compiled into the library (one copy per device, resident until the
+ * process ends) instead of memory allocated on the first calibration: the call allocates and frees
+ * nothing.  The keys need 2 bytes (CSE_BINOM2_Z) or 4 bytes (other designs) per key slot
+ * (n_key_slots of cse_platten_stats); a larger platten is refused with CSE_EINVAL.
+ * Every call on a device shares that device's workspace, which keeps the last call's contents:
+ * calls whose execution overlaps on one device (other streams or threads) race and must be
+ * ordered by the caller, as calls on one platten must be anyway.  The first call on a device looks
+ * the workspace's address up (hipGetSymbolAddress) with that device current.
+ * Errors: as cse_calibrate, plus CSE_EINVAL (keys exceed the workspace) and CSE_EHIP (lookup failed).
+ */
+#define CSE_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+int cse_calibrate_noalloc(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime,
+                          int32_t *k, double *lambda_tile, double *lambda_global,
+                          int32_t *reject_at_lambda, double delta, int32_t *reject, int64_t *score_T,
+                          double *score_Z, double *grad, double *cp_upper, double *tile_bound,
+                          void *stream);
+
+/*
  * cse_bound -- the float64 bound of each tile, without simulation.
  *   mode 0 (validate): R int32 [n_tiles] device rejection counts; out = tilewise optimized
  *          Tilt-Bound of the Clopper-Pearson bound at level delta_or_alpha = delta.

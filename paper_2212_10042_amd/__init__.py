@@ -33,7 +33,7 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
             "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
             "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_adagrid_decide",
-            "cse_adagrid_apply", "cse_platten_tiles", "cse_last_error")
+            "cse_adagrid_apply", "cse_platten_tiles", "cse_calibrate_noalloc", "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -70,6 +70,7 @@ def _load():
     L.cse_simulate.argtypes = [P, u64, P, P, P, P, P]
     L.cse_validate.argtypes = [P, u64, dbl, P, P, P, P, P, P, P, P]
     L.cse_calibrate.argtypes = [P, u64, dbl, P, P, P, P, P, dbl, P, P, P, P, P, P, P]
+    L.cse_calibrate_noalloc.argtypes = [P, u64, dbl, P, P, P, P, P, dbl, P, P, P, P, P, P, P]
     L.cse_bound.argtypes = [P, i32, P, P, dbl, P, P, P]
     L.cse_simulate_per_tile.argtypes = [P, u64, i64, i64, P, P]
     L.cse_platten_stats.argtypes = [P, P]
@@ -202,6 +203,19 @@ def cse_calibrate(h, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, re
                                              _ptr(lambda_global), _ptr(reject_at_lambda), delta,
                                              _ptr(reject), _ptr(score_T), _ptr(score_Z), _ptr(grad),
                                              _ptr(cp_upper), _ptr(tile_bound), _stream(stream)))
+
+
+def cse_calibrate_noalloc(h, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda=None,
+                          delta=0.01, reject=None, score_T=None, score_Z=None, grad=None, cp_upper=None,
+                          tile_bound=None, stream=None):
+    _check("cse_calibrate_noalloc", _L.cse_calibrate_noalloc(
+        h, seed, alpha, _ptr(alpha_prime), _ptr(k), _ptr(lambda_tile), _ptr(lambda_global), _ptr(reject_at_lambda),
+        delta, _ptr(reject), _ptr(score_T), _ptr(score_Z), _ptr(grad), _ptr(cp_upper), _ptr(tile_bound),
+        _stream(stream)))
+
+
+# bytes of the static calibration workspace of cse_calibrate_noalloc (CSE_NOALLOC_SCRATCH_BYTES)
+NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def cse_bound(h, mode, R, a, level, out, q_star=None, stream=None):
@@ -406,7 +420,7 @@ class Platten:
                      o["cp_upper"], o["tile_bound"], o["q_star"])
         return o
 
-    def calibrate(self, seed=0, alpha=0.025, delta=0.01, with_validation=True, device="cuda"):
+    def calibrate(self, seed=0, alpha=0.025, delta=0.01, with_validation=True, device="cuda", noalloc=False):
         n = self.n_tiles
         o = self._alloc(device) if with_validation else {}
         o.update(alpha_prime=torch.empty(n, dtype=torch.float64, device=device),
@@ -417,9 +431,10 @@ class Platten:
         if with_validation:
             o["cp_upper"] = torch.empty(n, dtype=torch.float64, device=device)
             o["tile_bound"] = torch.empty(n, dtype=torch.float64, device=device)
-        cse_calibrate(self.handle, seed, alpha, o["alpha_prime"], o["k"], o["lambda_tile"], o["lambda_global"],
-                      o["reject_at_lambda"], delta, o.get("reject"), o.get("score_T"), o.get("score_Z"),
-                      o.get("grad"), o.get("cp_upper"), o.get("tile_bound"))
+        fn = cse_calibrate_noalloc if noalloc else cse_calibrate
+        fn(self.handle, seed, alpha, o["alpha_prime"], o["k"], o["lambda_tile"], o["lambda_global"],
+           o["reject_at_lambda"], delta, o.get("reject"), o.get("score_T"), o.get("score_Z"),
+           o.get("grad"), o.get("cp_upper"), o.get("tile_bound"))
         return o
 
     def taylor(self, f, grad, device="cuda"):

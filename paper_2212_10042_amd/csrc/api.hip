@@ -17,6 +17,12 @@ struct cse_platten {
     cse::Platten P;
 };
 
+// Calibration key workspace of cse_calibrate_noalloc: compiled into the library, one copy per
+// device (resident from the library's first use on that device until the process ends).  In host
+// code this name is a host-side handle, not a device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (noalloc_workspace below).
+static __device__ __align__(256) unsigned char scratch[(size_t)CSE_NOALLOC_SCRATCH_BYTES];
+
 struct cse_plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -51,6 +57,32 @@ int check_handle(const cse_platten *h, const char *fn) {
 }
 
 bool in_unit(double x) { return x > 0.0 && x < 1.0; }
+
+// Device address of `scratch` per device, looked up on the first cse_calibrate_noalloc call with
+// that device current (no allocation: the array exists once the library's code is loaded there).
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+int noalloc_workspace(int dev, void **out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) {
+        set_error("cse_calibrate_noalloc: device index outside the static workspace table");
+        return CSE_EINVAL;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error(std::string("cse_calibrate_noalloc: hipGetSymbolAddress of the static workspace failed: ") +
+                      hipGetErrorString(e));
+            return CSE_EHIP;
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return CSE_OK;
+}
 
 // The 4-arm design produces rejection counts and calibration keys; score sums are not formed.
 int check_scores(const cse::Platten &P, const void *score_T, const void *score_Z, const void *grad,
@@ -121,32 +153,37 @@ void prof_collect() {
     g_pending.clear();
 }
 
-// Simulation with the design's fixed rule into the workspaces (R, score sums, optional keys).
-int run_sim(const cse::Platten &P, uint64_t seed, bool keys, hipStream_t st) {
+// Simulation with the design's fixed rule into the workspaces (R, score sums) and, when `keys` is not
+// NULL, the calibration keys into `keys` (n_keys entries laid out as the platten's key offsets say).
+int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st) {
     CSE_LAUNCH(cse::launch_zero(P.d_Rw, P.n_tiles * sizeof(uint32_t), st));
     if (P.family == cse::FAM_NORMAL) {
         CSE_LAUNCH(cse::launch_zero(P.d_Zw, P.n_tiles * sizeof(unsigned long long), st));
         Timed tm(keys ? "ztest1_calib" : "ztest1", st);
-        CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, keys ? (float *)P.d_keys : nullptr, st));
+        CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, (float *)keys, st));
     } else if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {
         const bool bk = P.design.kind == CSE_BASKET4;
         Timed tm(keys ? (bk ? "basket4_calib" : "hier4_calib") : (bk ? "basket4" : "hier4"), st);
-        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, keys ? (float *)P.d_keys : nullptr, st));
+        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, (float *)keys, st));
     } else if (P.design.kind == CSE_PHASE23) {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * 2 * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "phase23_calib" : "phase23", st);
-        CSE_LAUNCH(cse::launch_phase23(P, seed, P.d_Rw, P.d_Tw, keys ? (float *)P.d_keys : nullptr, st));
+        CSE_LAUNCH(cse::launch_phase23(P, seed, P.d_Rw, P.d_Tw, (float *)keys, st));
     } else {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "binom2_calib" : "binom2", st);
-        CSE_LAUNCH(cse::launch_binom2(P, seed, P.d_Rw, P.d_Tw, keys ? (uint16_t *)P.d_keys : nullptr, st));
+        CSE_LAUNCH(cse::launch_binom2(P, seed, P.d_Rw, P.d_Tw, (uint16_t *)keys, st));
     }
     return CSE_OK;
 }
 
-int ensure_keys(cse::Platten &P) {
+size_t key_bytes(const cse::Platten &P) {
     const size_t esz = (P.design.kind == CSE_BINOM2_Z) ? 2 : 4;
-    const size_t need = (size_t)P.n_keys * esz;
+    return (size_t)P.n_keys * esz;
+}
+
+int ensure_keys(cse::Platten &P) {
+    const size_t need = key_bytes(P);
     if (P.d_keys && P.keys_bytes >= need) return CSE_OK;
     if (P.d_keys) {
         (void)hipFree(P.d_keys);
@@ -194,15 +231,15 @@ int check_calibrate(const cse_platten *p, double alpha, double delta, const void
 int validate_impl(const cse::Platten &P, uint64_t seed, double delta, int32_t *reject, int64_t *score_T,
                   double *score_Z, double *grad, double *cp_upper, double *tile_bound, double *q_star,
                   hipStream_t st) {
-    if (int e = run_sim(P, seed, false, st)) return e;
+    if (int e = run_sim(P, seed, nullptr, st)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
     Timed tm("bound_validate", st);
     CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tile_bound, q_star, nullptr, cp_upper, st));
     return CSE_OK;
 }
 
-// Calibration (Algorithm 2) on stream st; the key workspace must exist (ensure_keys).
-int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+// Calibration (Algorithm 2) on stream st with the key workspace `keys` (key_bytes(P) bytes).
+int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
                    double *lambda_tile, double *lambda_global, int32_t *reject_at_lambda, double delta,
                    int32_t *reject, int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
                    double *tile_bound, hipStream_t st) {
@@ -228,7 +265,7 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
         CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, is));
         if (branch_invert) CSE_HIP_TRY(hipEventRecord(P.ev_inv, is));
     }
-    if (int e = run_sim(P, seed, true, st)) return e;
+    if (int e = run_sim(P, seed, keys, st)) return e;
     const bool want_bound = cp_upper || tile_bound;
     if (want_bound) {
         hipStream_t side = P.side;
@@ -246,7 +283,7 @@ int calibrate_impl(cse::Platten &P, uint64_t seed, double alpha, double *alpha_p
     if (branch_invert) CSE_HIP_TRY(hipStreamWaitEvent(st, P.ev_inv, 0));   // k before the selection
     {
         Timed tm("select", st);
-        CSE_LAUNCH(cse::launch_select(P, kk, lam, reject_at_lambda, st));
+        CSE_LAUNCH(cse::launch_select(P, keys, kk, lam, reject_at_lambda, st));
     }
     CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
     if (reject || score_T || score_Z || grad)
@@ -339,7 +376,7 @@ int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *
     const auto &P = p->P;
     if (int e = check_scores(P, score_T, score_Z, grad, "cse_simulate")) return e;
     hipStream_t st = (hipStream_t)stream;
-    if (int e = run_sim(P, seed, false, st)) return e;
+    if (int e = run_sim(P, seed, nullptr, st)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
     return CSE_OK;
 }
@@ -361,7 +398,28 @@ int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alp
         return e;
     auto &P = const_cast<cse_platten *>(p)->P;
     if (int e = ensure_keys(P)) return e;
-    return calibrate_impl(P, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
+    return calibrate_impl(P, P.d_keys, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
+                          reject, score_T, score_Z, grad, cp_upper, tile_bound, (hipStream_t)stream);
+}
+
+int cse_calibrate_noalloc(const cse_platten *p, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
+                          double *lambda_tile, double *lambda_global, int32_t *reject_at_lambda, double delta,
+                          int32_t *reject, int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
+                          double *tile_bound, void *stream) {
+    if (int e = check_calibrate(p, alpha, delta, score_T, score_Z, grad, cp_upper || tile_bound,
+                                "cse_calibrate_noalloc"))
+        return e;
+    const auto &P = p->P;
+    const size_t need = key_bytes(P);
+    if (need > (size_t)CSE_NOALLOC_SCRATCH_BYTES) {
+        set_error("cse_calibrate_noalloc: the platten's calibration keys need " + std::to_string(need) +
+                  " bytes, more than the static workspace of " + std::to_string((long long)CSE_NOALLOC_SCRATCH_BYTES) +
+                  " bytes (use cse_calibrate)");
+        return CSE_EINVAL;
+    }
+    void *ws = nullptr;
+    if (int e = noalloc_workspace(P.device, &ws)) return e;
+    return calibrate_impl(P, ws, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
                           reject, score_T, score_Z, grad, cp_upper, tile_bound, (hipStream_t)stream);
 }
 
@@ -439,7 +497,7 @@ int cse_plan_calibrate(const cse_platten *p, uint64_t seed, double alpha, double
     auto &P = const_cast<cse_platten *>(p)->P;
     if (int e = ensure_keys(P)) return e;   // allocation stays outside the graph
     return capture_plan(p, [&](hipStream_t cs) {
-        return calibrate_impl(P, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
+        return calibrate_impl(P, P.d_keys, seed, alpha, alpha_prime, k, lambda_tile, lambda_global, reject_at_lambda, delta,
                               reject, score_T, score_Z, grad, cp_upper, tile_bound, cs);
     }, out, "cse_plan_calibrate");
 }
@@ -553,7 +611,7 @@ int cse_autotune(cse_platten *p, uint64_t seed, int64_t max_trials, int64_t out[
         const int64_t v = group ? cands[i] : wave_cands[i];
         if (int e = group ? cse::plan_group_items(&P, v) : cse::plan_work_items(&P, v)) return e;
         float ms = 0.0f;
-        if (int e = timeit([&]() { return run_sim(P, seed, true, st); }, 3, &ms)) return e;
+        if (int e = timeit([&]() { return run_sim(P, seed, P.d_keys, st); }, 3, &ms)) return e;
         if (ms < best) {
             best = ms;
             bv = v;
@@ -662,7 +720,7 @@ int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, do
     if (int e = ensure_keys(P)) return e;
     hipStream_t st = (hipStream_t)stream;
     int32_t *kk = k ? k : P.d_kw;
-    if (int e = calibrate_impl(P, seed, alpha, alpha_prime, kk, lambda_tile, nullptr, reject_at_lambda, 0.5, nullptr,
+    if (int e = calibrate_impl(P, P.d_keys, seed, alpha, alpha_prime, kk, lambda_tile, nullptr, reject_at_lambda, 0.5, nullptr,
                                nullptr, nullptr, nullptr, nullptr, nullptr, st))
         return e;
     {

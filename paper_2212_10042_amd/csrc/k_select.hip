@@ -592,18 +592,18 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
+hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st) {
     if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4)   // 64-key chunks at 256-byte offsets: float4 loads
         hipLaunchKernelGGL(k_select_f32<true>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
-                           (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
+                           (const float *)keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else if (P.design.kind != CSE_BINOM2_Z)
         hipLaunchKernelGGL(k_select_f32<false>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
-                           (const float *)P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
+                           (const float *)keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
     else
         hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG),
                            2 * (size_t)P.n_outcomes * sizeof(uint32_t), st,
-                           (const uint16_t *)P.d_keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
+                           (const uint16_t *)keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
                            P.d_S_group, P.n_outcomes, lam, rej_at);
     return hipGetLastError();
 }

@@ -13,7 +13,7 @@ hipError_t launch_plain_tile(const Platten &P, uint64_t seed, int64_t t, uint32_
 hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const double *a_in,
                         double level, double *out, double *q_out, int32_t *k_out, double *cp_out,
                         hipStream_t st);
-hipError_t launch_select(const Platten &P, const int32_t *k, double *lam, int32_t *rej_at,
+hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st);
 hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st);
 hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,

@@ -30,6 +30,13 @@ def test_header_declarations_exported():
     assert set(cse.EXPORTED) == set(decl)
 
 
+def test_noalloc_workspace_size_matches_header():
+    import paper_2212_10042_amd as cse
+    src = open(os.path.join(ROOT, "include", "cse.h")).read()
+    m = re.search(r"#define CSE_NOALLOC_SCRATCH_BYTES \(\(int64_t\)(\d+) << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == cse.NOALLOC_SCRATCH_BYTES
+
+
 def test_header_compiles_as_c():
     src = "#include \"cse.h\"\nint main(void){cse_design d={0};(void)d;return 0;}\n"
     r = subprocess.run(["gcc", "-x", "c", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
@@ -97,6 +104,8 @@ def test_null_handles_rejected_newer_entry_points():
     assert L.cse_validate_lower(None, None, 0.01, None, None, None, None) == cse.CSE_EINVAL
     assert L.cse_confidence_set(None, None, 0, None, None, 0, None, None, None, None, None) == cse.CSE_EINVAL
     assert L.cse_calibrate_tiebreak(None, 0, 0.025, None, None, None, None, None, None, None, None) == cse.CSE_EINVAL
+    assert L.cse_calibrate_noalloc(None, 0, 0.025, None, None, None, None, None, 0.01, None, None, None, None, None,
+                                   None, None) == cse.CSE_EINVAL
     assert L.cse_taylor(None, None, None, None, None, None, None) == cse.CSE_EINVAL
     assert L.cse_platten_tiles(None, None, None) == cse.CSE_EINVAL
     assert L.cse_adagrid_decide(None, 0, None, None, 0, None, None, None, None, None) == cse.CSE_EINVAL
