@@ -370,7 +370,10 @@ int cse_adagrid_apply(int32_t d, int64_t n_boxes, const double *theta, const dou
  *        cse_calibrate (no stream: capture uses a private stream); out receives the plan.
  *   cse_plan_launch: enqueue one replay on `stream` (asynchronous).  Replays of one plan,
  *        and plans or eager calls on the same platten, share the platten's workspaces:
- *        order them on one stream.
+ *        order them on one stream.  A plan is tied to its platten's launch shape: after
+ *        cse_autotune has rebuilt it, or after the platten is destroyed, cse_plan_launch returns
+ *        CSE_EINVAL without replaying (capture a new plan; a plan must not be replayed after its
+ *        platten is gone, and only cse_plan_destroy may be called on it then).
  *   cse_plan_nodes: number of graph nodes (-1 for NULL).
  *   cse_plan_destroy: synchronises the device and releases the graph; NULL is a no-op.
  * Errors: CSE_EINVAL, CSE_ENOMEM, CSE_EHIP (capture or instantiation failed).
@@ -399,6 +402,7 @@ int cse_plan_destroy(cse_plan *plan);
  *                          holding at most max_trials trials.
  * The fastest is kept in the platten.  Results of every later call are unchanged (integer
  * reductions are order-independent and keys are laid out by tile, not by launch shape).
+ * Plans captured on this platten before the call become stale (cse_plan_launch refuses them).
  *   out  host int64 [2]: the chosen value and, for CSE_PHASE23, the grid (else 0).
  * Errors: CSE_EINVAL (NULL out, max_trials < 1), CSE_ENOMEM, CSE_EHIP.
  */

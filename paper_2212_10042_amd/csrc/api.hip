@@ -28,6 +28,10 @@ struct cse_plan {
     hipGraphExec_t exec = nullptr;
     int device = 0;
     int64_t n_nodes = 0;
+    // the platten's launch-shape generation at capture: the graph's kernel arguments point into
+    // that generation's work-item arrays, so the plan replays only while it is unchanged
+    std::shared_ptr<std::atomic<uint64_t>> shape_gen;
+    uint64_t gen_at_capture = 0;
 };
 
 namespace {
@@ -469,6 +473,8 @@ int capture_plan(const cse_platten *p, const std::function<int(hipStream_t)> &bo
     pl->graph = g;
     pl->exec = ex;
     pl->device = p->P.device;
+    pl->shape_gen = p->P.shape_gen;
+    pl->gen_at_capture = p->P.shape_gen->load();
     pl->n_nodes = 0;
     size_t nn = 0;
     if (hipGraphGetNodes(g, nullptr, &nn) == hipSuccess) pl->n_nodes = (int64_t)nn;
@@ -510,6 +516,14 @@ int cse_plan_launch(const cse_plan *plan, void *stream) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != plan->device) {
         set_error("cse_plan_launch: the current HIP device is not the plan's device");
+        return CSE_EINVAL;
+    }
+    const uint64_t gen = plan->shape_gen ? plan->shape_gen->load() : cse::PLATTEN_GONE;
+    if (gen != plan->gen_at_capture) {
+        set_error(gen == cse::PLATTEN_GONE
+                      ? "cse_plan_launch: the plan's platten has been destroyed"
+                      : "cse_plan_launch: cse_autotune rebuilt the platten's launch shape after this plan was "
+                        "captured; capture a new plan");
         return CSE_EINVAL;
     }
     CSE_HIP_TRY(hipGraphLaunch(plan->exec, (hipStream_t)stream));

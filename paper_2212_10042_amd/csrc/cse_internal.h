@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -15,6 +17,7 @@ constexpr int WG = 256;              // 4 waves per workgroup
 constexpr int MAX_D = 4;
 constexpr int NP35 = 35;             // patients per arm of the binomial designs
 constexpr int P23_NMAX_ARM = 350;    // embedded patients per arm of the Phase II/III design
+constexpr uint64_t PLATTEN_GONE = ~0ull;   // shape generation of a destroyed platten
 
 // ---- tile batches ("blocks"): each wave owns one block for a range of simulations ----
 // 2-arm designs: an 8 x 8 product of distinct arm-0 and arm-1 thresholds, so one
@@ -176,6 +179,11 @@ struct Platten {
     int32_t n_outcomes = 0;
 
     std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
+
+    // launch-shape generation: advanced whenever the work-item arrays a captured plan refers to are
+    // rebuilt (cse_autotune), and set to PLATTEN_GONE when the platten is destroyed.  Plans hold a
+    // reference to this counter and refuse to replay once it differs from its value at capture.
+    std::shared_ptr<std::atomic<uint64_t>> shape_gen = std::make_shared<std::atomic<uint64_t>>(0);
 
     // side stream (default priority) and fork/join events of the calibration step: the
     // validation bound runs beside the selection, and in a captured graph the inversion beside

@@ -858,6 +858,7 @@ int plan_work_items(Platten *P, int64_t target_waves) {
             items.push_back(w);
         }
     }
+    P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
     if (P->d_items) CSE_HIP_TRY(hipFree(P->d_items));
     P->d_items = nullptr;
     P->n_items = (int64_t)items.size();
@@ -892,6 +893,7 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
             gi.push_back(it);
         }
     }
+    P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
     if (P->d_gitems) CSE_HIP_TRY(hipFree(P->d_gitems));
     P->d_gitems = nullptr;
     P->n_gitems = (int64_t)gi.size();
@@ -916,6 +918,7 @@ int plan_queue_items(Platten *P, int32_t chunk, int64_t grid) {
         }
     }
     P->p23_item_off.push_back((int64_t)items.size());
+    P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
     if (P->d_p23items) CSE_HIP_TRY(hipFree(P->d_p23items));
     P->d_p23items = nullptr;
     if (int e = upload(&P->d_p23items, items.data(), items.size())) return e;
@@ -929,6 +932,7 @@ int plan_queue_items(Platten *P, int32_t chunk, int64_t grid) {
 
 void free_platten(Platten *P) {
     if (!P) return;
+    if (P->shape_gen) P->shape_gen->store(PLATTEN_GONE);   // plans on this platten refuse to replay
     (void)hipDeviceSynchronize();
     void *ptrs[] = {P->d_theta, P->d_N,    P->d_vert_off, P->d_verts,   P->d_key_off,
                     P->d_blocks, P->d_items, P->d_gitems, P->d_cut_tbl, P->d_S_tbl,  P->d_S_order,

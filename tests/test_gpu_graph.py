@@ -140,3 +140,35 @@ def test_autotune_changes_speed_only(kind):
     torch.cuda.synchronize()
     _same(ref, out)
     P.close()
+
+
+@pytest.mark.parametrize("kind", ["binom2", "phase23"])
+def test_stale_plans_are_refused(kind):
+    """A plan captured before cse_autotune rebuilt the launch shape, or one whose platten was
+    destroyed, is refused by cse_plan_launch (CSE_EINVAL) and never replayed; a plan captured after
+    tuning replays as usual."""
+    w = _case(kind)
+    print(f"[graph] stale plan {kind}", flush=True)
+    P = cse.Platten.create(kind, w["theta"], w["radii"], w["sims"], cut=w.get("cut"))
+    out = _alloc(P)
+    plan = cse.cse_plan_calibrate(P.handle, 3, 0.025, *_calib_args(out))
+    try:
+        cse.cse_autotune(P.handle, seed=3, max_trials=5_000)
+        torch.cuda.synchronize()
+        with pytest.raises(cse.CseError) as e:
+            cse.cse_plan_launch(plan)
+        assert e.value.status == cse.CSE_EINVAL
+    finally:
+        cse.cse_plan_destroy(plan)
+    fresh = cse.cse_plan_calibrate(P.handle, 3, 0.025, *_calib_args(out))
+    cse.cse_plan_launch(fresh)
+    torch.cuda.synchronize()
+    ref = _alloc(P)
+    _eager(P, 3, ref)
+    torch.cuda.synchronize()
+    _same(ref, out)
+    P.close()
+    with pytest.raises(cse.CseError) as e:
+        cse.cse_plan_launch(fresh)
+    assert e.value.status == cse.CSE_EINVAL
+    cse.cse_plan_destroy(fresh)

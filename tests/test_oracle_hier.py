@@ -10,6 +10,12 @@ oracle_hier.c) against facts independent of its code:
 - node weights: at large n the Laplace log-evidence must match adaptive Gauss-Hermite
   quadrature of the exact marginal likelihood p(y | s2) (ratios across nodes), so a wrong
   determinant or quadratic term fails;
+- the statistic P(theta_i > theta_0 | y) against direct numerical integration of the exact
+  posterior (sigma^2 on a log grid, mu on a grid, and given both the arms independent, each on a
+  theta grid): within 0.002 at n = 400 and 2000 (where the Laplace node mixture is accurate), so a
+  wrong scale of the difference's standard deviation, a dropped posterior covariance between arm i
+  and the control, or another link fails; the gap at the design's n = 35 is printed and bounded by
+  0.02;
 - the tilt bound of the 4-arm family follows from the same exponential-family code as the
   2-arm one (pinned in test_oracle_bounds.py).
 """
@@ -19,7 +25,7 @@ import math
 
 import numpy as np
 import pytest
-from scipy import optimize, stats
+from scipy import optimize, special, stats
 
 import oracle as O
 
@@ -198,3 +204,70 @@ def test_design_simulation_reduces_to_counts_and_posteriors():
         rej = S[t, : sims[t]] < cut
         assert R[t] == rej.sum() and 0 < R[t] < sims[t]
         assert np.array_equal(sT[t], y[rej].sum(axis=0))
+
+
+def _exact_p_gt_control(y, n, ns2=150, ngh=40):
+    """P(theta_i > theta_0 | y), i = 1..3, of the 4-arm hierarchical model (Section 10.1) by
+    quadrature of the exact posterior: sigma^2 on a log grid (trapezoid, Jacobian s2), mu on a
+    grid, and given (mu, sigma^2) the four arms independent with density proportional to
+    Binomial(y_a; n, expit theta_a) N(theta_a; mu, sigma^2) on a common theta grid (Gauss-Hermite
+    nodes of the prior where sigma is narrow against the grid); each pair (arm i, control) is
+    compared as point masses on the grid, ties counted one half."""
+    y = np.asarray(y, np.float64)
+    dhat = np.log((y + 0.5) / (n - y + 0.5))
+    sd_lik = 1.0 / np.sqrt(n * 0.25 * (1 - np.abs(2 * (y + 0.5) / (n + 1) - 1)) + 1.0)
+    ls2 = np.linspace(np.log(1e-6), np.log(1e3), ns2)
+    s2 = np.exp(ls2)
+    w_s2 = np.full(ns2, ls2[1] - ls2[0])
+    w_s2[[0, -1]] *= 0.5
+    a_, b_ = 0.0005, 0.000005
+    logp_s2 = a_ * np.log(b_) - special.gammaln(a_) - (a_ + 1) * ls2 - b_ / s2 + ls2 + np.log(w_s2)
+    c = dhat.mean()
+    mu = np.unique(np.concatenate([np.linspace(-8, 6, 141), np.linspace(c - 1.5, c + 1.5, 601)]))
+    w_mu = np.zeros(len(mu))
+    dm = np.diff(mu)
+    w_mu[:-1] += dm / 2
+    w_mu[1:] += dm / 2
+    logp_mu = stats.norm.logpdf(mu, -1.34, 10.0) + np.log(w_mu)
+    h = sd_lik.min() / 12.0
+    d = h * np.arange(np.floor((dhat - 12 * sd_lik).min() / h), np.ceil((dhat + 12 * sd_lik).max() / h) + 1)
+    tw = np.full(len(d), h)
+    tw[[0, -1]] *= 0.5
+    lik = np.exp(stats.binom.logpmf(y[:, None], n, special.expit(d[None, :])))
+    gx, gw = np.polynomial.hermite_e.hermegauss(ngh)
+    gw = gw / np.sqrt(2 * np.pi)
+    logL = np.zeros((ns2, len(mu)))
+    pgt = np.zeros((3, ns2, len(mu)))
+    for i in range(ns2):
+        sd = np.sqrt(s2[i])
+        if sd < 2 * h:
+            x = mu[:, None] + sd * gx[None, :]
+            q = np.exp(stats.binom.logpmf(y[:, None, None], n, special.expit(x[None]))) * gw
+        else:
+            q = lik[:, None, :] * stats.norm.pdf(d[None, :], mu[:, None], sd)[None] * tw
+        m = q.sum(-1)
+        logL[i] = np.log(np.maximum(m, 1e-300)).sum(0)
+        q = q / np.maximum(m, 1e-300)[..., None]
+        above = np.cumsum(q[..., ::-1], axis=-1)[..., ::-1] - 0.5 * q
+        for a in range(1, 4):
+            pgt[a - 1, i] = (q[0] * above[a]).sum(-1)
+    lw = logL + logp_s2[:, None] + logp_mu[None, :]
+    w = np.exp(lw - lw.max())
+    w /= w.sum()
+    return np.array([(w * pgt[a]).sum() for a in range(3)])
+
+
+@pytest.mark.parametrize("y,n,tol", [
+    ((300, 310, 295, 320), 2000, 0.002),
+    ((700, 690, 720, 705), 2000, 0.002),
+    ((60, 64, 58, 70), 400, 0.002),
+    ((10, 13, 9, 16), 35, 0.02),
+    ((2, 5, 9, 14), 35, 0.02),
+])
+def test_p_gt_control_vs_quadrature(y, n, tol):
+    ex = _exact_p_gt_control(y, n)
+    lap = post(y, n)
+    print(f"y={y} n={n}: quadrature {np.round(ex, 5)}, oracle {np.round(lap, 5)}, "
+          f"gap {np.abs(ex - lap).max():.2e}")
+    assert np.max(np.abs(ex - lap)) < tol
+    assert np.all((ex > 0.05) & (ex < 0.98)) or n == 35   # informative (not saturated) cases

@@ -11,10 +11,17 @@ reading in oracle_phase23.c), each against something other than the oracle's own
 - every simulated trial replayed in Python against the protocol: allocations, the words its
   responses come from (Philox, pinned by its known-answer test), each look's decision from the
   separately pinned summary / p_best / p_success, the calibration statistic, and the caps of
-  350 patients per arm and 800 in total.
+  350 patients per arm and 800 in total;
+- the score-function gradient with observed counts and sizes, (sum_rej y_a - sum_rej n_a expit
+  theta_a) / N, against the change of the rejection rate itself: under common random numbers
+  the count difference R(theta + h e_a) - R(theta - h e_a) must equal Simpson's integral of the
+  score estimate over [theta - h, theta + h] within the paired per-trial standard error, on every
+  arm (a wrong sample size such as the embedded 350, a sign or a dropped arm fails by > 10 or
+  > 3 standard errors).
 """
 import itertools
 import math
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -262,3 +269,36 @@ def test_trials_follow_the_protocol():
         np.testing.assert_array_equal(o["sumN"][t], o["info"][t, : sims[t], 3:7][rej].sum(0))
         np.testing.assert_array_equal(o["sumY"][t], o["info"][t, : sims[t], 7:11][rej].sum(0))
     assert {0, 2, 3} <= seen   # futility, early success and final analyses all occur
+
+
+def test_score_gradient_vs_crn_rate_difference():
+    lam, N, h, cfg = 0.06253, 16000, 0.1, 7
+    theta = np.array([0.0, 0.1, -0.1, 0.0])
+    O.sim_phase23(theta[None], np.array([cfg], np.int32), np.array([1], np.int32), 1, lam)  # rule constants
+    pts = [theta] + [theta + s * h * np.eye(D)[a] for a in range(D) for s in (-1, 1)]
+
+    def run(t):   # the C oracle releases the GIL: one thread per point
+        return O.sim_phase23(t[None], np.array([cfg], np.int32), np.array([N], np.int32), 5, lam,
+                             want_S=True, want_info=True)
+
+    with ThreadPoolExecutor(len(pts)) as ex:
+        res = list(ex.map(run, pts))
+
+    def per_trial(o, t, a):
+        rej = (o["S"][0] < lam).astype(np.float64)
+        n = o["info"][0, :, 3 + a].astype(np.float64)
+        y = o["info"][0, :, 7 + a].astype(np.float64)
+        return rej, rej * (y - n * special.expit(t[a]))
+
+    for a in range(D):
+        rm, sm = per_trial(res[1 + 2 * a], pts[1 + 2 * a], a)
+        _, s0 = per_trial(res[0], theta, a)
+        rp, sp = per_trial(res[2 + 2 * a], pts[2 + 2 * a], a)
+        fd = rp - rm
+        Dk = fd - 2 * h * (sm + 4 * s0 + sp) / 6          # paired per trial (same words)
+        se = Dk.std() / math.sqrt(N)
+        print(f"arm {a}: R difference {fd.mean():+.5f}, integrated score {fd.mean() - Dk.mean():+.5f}, "
+              f"z {Dk.mean() / se:+.2f}")
+        assert abs(Dk.mean()) < 4.5 * se
+        if a < 2:   # the control and the arm that tends to be selected: the change is informative
+            assert abs(fd.mean()) > 5 * fd.std() / math.sqrt(N)
