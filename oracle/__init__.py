@@ -699,7 +699,7 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
     for t in range(len(subs)):
         row = S[t, : N[t]].astype(key_dtype)
         lam[t] = order_statistic(row, int(k[t]))
-        rej[t] = int(np.sum(row < key_dtype(lam[t]) if np.isfinite(lam[t]) else 0))
+        rej[t] = int(np.sum(row < key_dtype(lam[t])))   # #{S < lambda*_i}, also for lambda*_i = +inf
     return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, q=qs, k=k,
                 lam=lam, lam_global=float(lam.min()) if len(lam) else math.inf,
                 reject_at_lam=rej, N=N, subs=subs)
