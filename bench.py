@@ -2,19 +2,23 @@
 """Throughput of one step of the CSE hot path on one MI355X.
 
 Default workload (the metric's configuration): 2-arm binomial design (n = 35 per arm, pooled
-two-proportion z, reject z > 1.96), 256 x 256 boxes on logit [-3, 1]^2 kept to
-theta1 <= theta0 (32,896 tiles, 256 of them triangles cut by the null boundary), 8,192
-simulations per tile, seed 0.  --workload selects the others (2^20-tile forward + gradient,
-4-arm hierarchical calibration, 1-D z-test); they are listed in WORKLOADS.
+two-proportion z, reject z > 1.96), all 1024 x 1024 boxes on logit [-3, 1]^2 (2^20 tiles, of them
+524,800 meeting the null theta1 <= theta0, 1,024 cut into triangles), 16,384 simulations per tile,
+seed 0, alpha 2.5%, delta 1%.  --workload selects the others (listed in WORKLOADS); the default run
+also measures the 256 x 256 calibration grid and the 4-arm hierarchical calibration as sub-records.
 
 One step = one call of cse_calibrate with every output requested: the inverted Tilt-Bound
 target alpha'_i and k_i, the fused simulation (Philox common random numbers, draws, design
 statistic, rejection counts at the fixed cut, score sums for the gradient, per-simulation
-calibration keys), the order-statistic selection lambda*_i and its count below,
-lambda* = min, the gradient, and the Clopper-Pearson + Tilt-Bound of every tile.  For the
-2^20-tile workload the step is cse_validate (forward, gradient, bound; no calibration).  The
-platten (null clipping, vertices, thresholds, batch plan, 4-arm posterior table) is built
-once before timing and reported separately.
+calibration records), the order-statistic selection lambda*_i and its count below,
+lambda* = min over the tiles in the null space, the gradient, and the Clopper-Pearson +
+Tilt-Bound of every tile.  The basket workload is validation only.  The platten (null clipping,
+vertices, thresholds, batch plan, 4-arm posterior table) is built once before timing and
+reported separately.
+
+The oracle baseline runs first, before anything touches the GPU: the C/numpy oracle on a
+bounded uniform sample of the same workload, on one core and then on all cores this process may
+use (at most 16, by fork), with the CPU model and core counts stated.
 
 Prints one JSON line.  --gpus above 1 is refused: the library runs on one GPU.
 """
@@ -34,9 +38,11 @@ VALU_PEAK = 256 * 4 * 64 * 2.4e9 / 4   # lane-ops/s: 256 CUs x 4 SIMDs x one wav
 
 # Algorithmic integer work per unit (lane-ops), by fused kernel:
 #   2-arm: per (workgroup, simulation) 18 Philox blocks x 10 rounds x (2 32x32->64 products
-#   + 2 xor3), shared by the 4 batches of the group; per (batch, simulation) 70 words x 8
-#   thresholds x (compare + add); per (simulation, tile) decision, accumulate, key store.
-B2_PHILOX, B2_COUNT, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 2 * 35 * 8 * 2, 5, 4
+#   + 2 xor3), shared by the 4 batches of the group's 2 x 2 square, and the square's 4 sets of
+#   8 thresholds x 35 words x (compare + add), each counted once; per (simulation, tile) decision
+#   (med3), packed multiply-add and its share of the count unpacking (the calibration record is
+#   one 16-byte store per (simulation, batch)).
+B2_PHILOX, B2_COUNT_G, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 4 * 8 * 35 * 2, 4, 4
 #   4-arm: per (workgroup, simulation) 35 Philox blocks; per (batch, simulation) 35 words x
 #   (4 + 4 + 2 + 2) thresholds x (compare + add); per (simulation, box) outcome index (3),
 #   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store.
@@ -54,18 +60,39 @@ BK_SLOT = 11
 #   kernel's own counters for the launch (cse_work_counters).
 P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800, 100
 
-# HBM bytes per dispatch of k_binom2<true> on binom2_256_tri, from the FETCH_SIZE / WRITE_SIZE
-# counter runs in profiles/binom2_256_tri_hbm_counters.md (scaled by a 256 MiB copy).  Valid
-# only while that kernel is unchanged; other workloads report null.
-TRAFFIC_BINOM2_256_TRI = 605_256_615
+# HBM bytes per dispatch of the dominant kernel, by workload, from FETCH_SIZE + WRITE_SIZE counter
+# runs (profiles/*_hbm_counters.md, scaled by a copy of known size).  Valid only while that
+# kernel is unchanged; workloads not listed report null.
+TRAFFIC = {}
+
+DEFAULT = "binom2_1024_full"
+SUB_RECORDS = ("binom2_256_tri", "hier4_16")
+
+
+def b2_method_min_ops(P, w, calibrating):
+    """The 2-arm method's own integer work per launch, each distinct threshold counted once per
+    simulation: per (N class, simulation) 18 Philox blocks and 35 compare-adds at every distinct
+    arm-0 and arm-1 threshold of the class, plus the per-(simulation, tile) decision and accumulate
+    (and record share) -- the count that batching can approach but not go below."""
+    import numpy as np
+
+    th = np.asarray(P.tiles["theta"])
+    sims = np.asarray(w["sims"])[np.asarray(P.tiles["box"])]
+    total = 0
+    for N in np.unique(sims):
+        sel = sims == N
+        u = len(np.unique(th[sel, 0])) + len(np.unique(th[sel, 1]))
+        total += int(N) * (B2_PHILOX + u * 35 * 2) + int(N) * int(sel.sum()) * (B2_TILE_CAL if calibrating
+                                                                                else B2_TILE_FWD)
+    return total
 
 WORKLOADS = {
     "binom2_256_tri": "binom2 n=35 pooled-z, 256x256 boxes on [-3,1]^2 kept to theta1<=theta0 "
                       "(32,896 tiles), 8,192 sims/tile, seed 0, alpha 0.025, delta 0.01; "
                       "step = calibrate + validate + gradient",
-    "binom2_1024_full": "binom2 n=35 pooled-z, all 1024x1024 boxes on [-3,1]^2 (1,048,576 tiles), "
-                        "16,384 sims/tile, seed 0, delta 0.01; step = forward TIE + score gradient + "
-                        "Clopper-Pearson/Tilt-Bound (validate)",
+    "binom2_1024_full": "binom2 n=35 pooled-z, all 1024x1024 boxes on [-3,1]^2 (1,048,576 tiles simulated, "
+                        "524,800 meet theta1<=theta0), 16,384 sims/tile, seed 0, alpha 0.025, delta 0.01; "
+                        "step = calibrate (lambda* over the null tiles) + validate + score gradient",
     "hier4_16": "hier4 n=35 hierarchical Bayes (90-node sigma^2 quadrature), 16^4 boxes on [-1,1]^4 clipped "
                 "to the null configurations, 32,768 sims/tile, seed 0, alpha 0.025, delta 0.01; "
                 "step = calibrate + validate",
@@ -163,41 +190,73 @@ def run_adaptive(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(name, w, design, target_s: float = 15.0):
-    """The oracle as it stands, same step as the GPU (validate, and calibrate where the
-    GPU step calibrates), on a uniform sample of boxes of the same workload."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_run(args):
+    """One oracle pass (validate, and calibrate where the GPU step calibrates) over sampled boxes;
+    returns (seconds, sim-tiles)."""
     import numpy as np
 
     import oracle as O
     import workloads as W
 
+    name, w, design, idx = args
+    keep_all = name == "binom2_1024_full"
+    validation_only = name == "basket4_16"
+    cut = w.get("cut", 0.05 if design == "hier4" else 1.96)
+    s = W.subsample(w, idx)
+    if design == "phase23":
+        s["sims"] = np.minimum(s["sims"], 256).astype(np.int32)   # ~0.6 ms per oracle trial
+    t = time.perf_counter()
+    v = O.validate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["delta"], cut=cut, keep_all=keep_all)
+    if not validation_only:
+        O.calibrate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"], cut=cut, keep_all=keep_all,
+                    key_dtype=np.float32 if design in ("hier4", "phase23") else np.float64)
+    return time.perf_counter() - t, int(np.asarray(s["sims"])[v["box"]].sum()), len(v["box"])
+
+
+def cpu_baseline(name, w, design, target_s: float = 8.0, par_target_s: float = 3.0):
+    """The oracle as it stands, same step as the GPU, on uniform samples of boxes of the same
+    workload: one core, then all usable cores (at most 16) each taking a share of a larger sample.
+    Runs before the GPU is initialised, so the worker processes are forked safely."""
+    import multiprocessing as mp
+
+    import numpy as np
+
     rng = np.random.default_rng(1234)
     n = w["theta"].shape[0]
-    keep_all = name == "binom2_1024_full"
-    validation_only = name in ("binom2_1024_full", "basket4_16")
-    cut = w.get("cut", 0.05 if design == "hier4" else 1.96)
-
-    def run(m):
-        idx = np.sort(rng.choice(n, m, replace=False))
-        s = W.subsample(w, idx)
-        if design == "phase23":
-            s["sims"] = np.minimum(s["sims"], 256).astype(np.int32)   # ~0.6 ms per oracle trial
-        t = time.perf_counter()
-        v = O.validate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["delta"], cut=cut,
-                       keep_all=keep_all)
-        if not validation_only:
-            O.calibrate(design, s["theta"], s["radii"], s["sims"], w["seed"], w["alpha"], cut=cut,
-                        key_dtype=np.float32 if design in ("hier4", "phase23") else np.float64)
-        return time.perf_counter() - t, int(np.asarray(s["sims"])[v["box"]].sum()), len(v["box"])
-
-    dt, st, nt = run(4)
-    m = int(min(n, max(4, 4 * target_s / max(dt, 1e-3))))
-    dt, st, nt = run(m)
+    dt, _, _ = _oracle_run((name, w, design, np.sort(rng.choice(n, 4, replace=False))))
+    per_box = max(dt, 1e-3) / 4
+    m1 = int(min(n, max(4, target_s / per_box)))
+    idx1 = np.sort(rng.choice(n, m1, replace=False))
+    dt1, st1, nt1 = _oracle_run((name, w, design, idx1))
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    mp_ = int(min(n, max(cores, cores * par_target_s / per_box)))
+    idxp = np.sort(rng.choice(n, mp_, replace=False))
+    parts = [(name, w, design, idxp[i::cores]) for i in range(cores)]
+    t = time.perf_counter()
+    with mp.get_context("fork").Pool(cores) as pool:
+        res = pool.map(_oracle_run, parts)
+    dtp = time.perf_counter() - t
+    stp = sum(r[1] for r in res)
+    ntp = sum(r[2] for r in res)
     sims_note = "min(N, 256) sims of each" if design == "phase23" else "all sims of each"
-    return {"value": st / dt, "unit": "sim·tiles/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} boxes ({nt} tiles) drawn uniformly (seed 1234) of the same workload, {sims_note}; "
-                      f"oracle {'validate' if validation_only else 'validate + calibrate'}, "
-                      f"{dt:.1f} s single-threaded"}
+    step = "validate" if name == "basket4_16" else "validate + calibrate"
+    return {"value": stp / dtp, "unit": "sim·tiles/s", "cores": cores, "kind": "oracle",
+            "sample": f"{mp_} boxes ({ntp} tiles) drawn uniformly (seed 1234) of the same workload, {sims_note}, "
+                      f"split over {cores} forked processes: oracle {step}, {dtp:.1f} s wall",
+            "one_core": {"value": st1 / dt1, "cores": 1,
+                         "sample": f"{m1} boxes ({nt1} tiles), {sims_note}: oracle {step}, {dt1:.1f} s"},
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0))}
 
 
 def main():
@@ -205,7 +264,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="binom2_256_tri")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default=DEFAULT)
+    ap.add_argument("--no-sub", action="store_true", help="skip the sub-record workloads of the default run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--autotune", action="store_true",
@@ -224,16 +284,17 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
 
-    import paper_2212_10042_amd as cse
     import workloads as W
 
-    torch.cuda.set_device(0)
     if args.workload == "binom2_adaptive":
+        import torch
+        torch.cuda.set_device(0)
         run_adaptive(args)
         return
     if args.copy_probe:
+        import torch
+        torch.cuda.set_device(0)
         src = torch.ones(args.copy_probe // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(3):
@@ -242,6 +303,29 @@ def main():
         print(json.dumps({"copy_probe_bytes": args.copy_probe, "copies": 3}), flush=True)
         return
     name = args.workload
+    w, design = load_workload(name)
+    # the oracle first: its worker processes are forked before anything initialises the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(name, w, design)
+    import torch
+    torch.cuda.set_device(0)
+    res = measure(name, w, design, args, full=True)
+    res["cpu_baseline"] = cpu
+    if name == DEFAULT and not args.no_sub:
+        res["sub_records"] = {}
+        for sub in SUB_RECORDS:
+            ws, ds = load_workload(sub)
+            r = measure(sub, ws, ds, args, full=False)
+            res["sub_records"][sub] = {k: r[k] for k in ("value", "unit", "ms_per_step", "steps", "config",
+                                                        "kernel_avg_ms", "roofline", "speedup_vs_plain_fwd",
+                                                        "lambda_global") if k in r}
+    print(json.dumps(res), flush=True)
+
+
+def load_workload(name):
+    import numpy as np
+
+    import workloads as W
+
     if name == "phase23_c5_sub256":
         w5 = W.phase23_c5()
         w = W.subsample(w5, np.arange(0, w5["theta"].shape[0], 256))
@@ -250,8 +334,21 @@ def main():
     design = {"binom2_256_tri": "binom2", "binom2_1024_full": "binom2", "hier4_16": "hier4",
               "ztest1d_64": "ztest1", "phase23_c5": "phase23", "phase23_c5_sub256": "phase23",
               "basket4_16": "basket4"}[name]
+    return w, design
+
+
+def measure(name, w, design, args, full=True):
+    """Time `args.steps` steps of workload `name` after `args.warmup`; with full=False (sub-records)
+    at most 10 steps and no graph, extension or Taylor timings."""
+    import numpy as np
+    import torch
+
+    import paper_2212_10042_amd as cse
+
+    steps = args.steps if full else min(args.steps, 10)
+    warmup = args.warmup if full else min(args.warmup, 2)
     keep_all = name == "binom2_1024_full"
-    calibrating = name not in ("binom2_1024_full", "basket4_16")
+    calibrating = name != "basket4_16"
     t0 = time.perf_counter()
     P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all, cut=w.get("cut"))
     platten_ms = (time.perf_counter() - t0) * 1e3
@@ -290,7 +387,7 @@ def main():
 
     t_start = time.perf_counter()
     note(f"platten of {P.n_tiles} tiles built in {platten_ms:.0f} ms")
-    for i in range(args.warmup):
+    for i in range(warmup):
         step()
         if args.progress:
             torch.cuda.synchronize()
@@ -300,7 +397,7 @@ def main():
     cse.cse_profile_enable(True)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for i in range(args.steps):
+    for i in range(steps):
         step()
         if args.progress:
             torch.cuda.synchronize()
@@ -312,18 +409,18 @@ def main():
                   "basket4": "basket4"}[design] + \
         ("_calib" if calibrating else "")
     kern = {}
-    for kn in (sim_kernel, "select", "bound_invert", "bound_validate"):
+    for kn in (sim_kernel, "select", "b2_bracket", "bound_invert", "bound_validate"):
         cnt, ms = cse.cse_profile_get(kn)
         if cnt:
             kern[kn] = round(ms / cnt, 5)
-    total = st["total_sims"] * args.steps
+    total = st["total_sims"] * steps
     value = total / dt
-    ms_step = dt / args.steps * 1e3
+    ms_step = dt / steps * 1e3
 
     # the Taylor comparison bound and worst-case vertex (Section 4.3) from this step's outputs,
     # timed on its own (not part of the step)
     taylor = None
-    if "grad" in o and o["grad"] is not None:
+    if full and "grad" in o and o["grad"] is not None:
         cse.cse_profile_reset()
         cse.cse_profile_enable(True)
         for _ in range(5):
@@ -337,7 +434,7 @@ def main():
     # the two-sided band (Remark 2), a confidence set (Section 8) and the randomised calibration,
     # each on this step's outputs and timed on its own (not part of the step)
     ext = None
-    if not args.no_extensions and n:
+    if full and not args.no_extensions and n:
         ext = {}
         cse.cse_profile_reset()
         cse.cse_profile_enable(True)
@@ -354,7 +451,7 @@ def main():
             cnt, ms = cse.cse_profile_get("confidence_set")
             ext["confidence_set"] = {"ms": ms / max(cnt, 1), "kept": int(cs["keep"].sum().item()),
                                      "e_range": [float(x) for x in cs["e_range"].tolist()]}
-            reps = args.steps if ms_step < 1000.0 else 1      # long steps: one call, no warm-up
+            reps = steps if ms_step < 1000.0 else 1      # long steps: one call, no warm-up
             if reps > 1:
                 tb = P.calibrate_tiebreak(w["seed"], alpha=w["alpha"])
                 torch.cuda.synchronize()
@@ -373,7 +470,7 @@ def main():
 
     # the same step captured once as a HIP graph and replayed (outputs checked against eager)
     graph = None
-    if not args.no_graph:
+    if full and not args.no_graph:
         ref = {k: v.clone() for k, v in o.items() if v is not None}
         t_cap = time.perf_counter()
         if calibrating:
@@ -387,7 +484,7 @@ def main():
         cse.cse_plan_launch(plan)
         torch.cuda.synchronize()
         tg = time.perf_counter()
-        for i in range(args.steps):
+        for i in range(steps):
             cse.cse_plan_launch(plan)
             if args.progress:
                 torch.cuda.synchronize()
@@ -395,7 +492,7 @@ def main():
         torch.cuda.synchronize()
         dtg = time.perf_counter() - tg
         same = all(torch.equal(ref[k], o[k]) for k in ref)
-        graph = {"ms_per_step": dtg / args.steps * 1e3, "value": st["total_sims"] * args.steps / dtg,
+        graph = {"ms_per_step": dtg / steps * 1e3, "value": st["total_sims"] * steps / dtg,
                  "capture_ms": cap_ms, "nodes": cse.cse_plan_nodes(plan), "identical_to_eager": same}
         cse.cse_plan_destroy(plan)
         if not same:
@@ -403,9 +500,11 @@ def main():
             sys.exit(1)
 
     # roofline of the dominant kernel: the fused simulation
+    ops_min = None
     if design == "binom2":
-        ops = (st["group_sims"] * B2_PHILOX + st["batch_sims"] * B2_COUNT
+        ops = (st["group_sims"] * (B2_PHILOX + B2_COUNT_G)
                + st["total_sims"] * (B2_TILE_CAL if calibrating else B2_TILE_FWD))
+        ops_min = b2_method_min_ops(P, w, calibrating)
         kname = f"k_binom2<KEYS={'true' if calibrating else 'false'}>"
     elif design == "hier4":
         boxes = np.unique(P.tiles["box"])
@@ -435,8 +534,11 @@ def main():
                 "kernel": kname, "kernel_ms": kern[sim_kernel], "ops_per_launch": ops}
         if design == "phase23":
             roof["work"] = wc
-        if name == "binom2_256_tri":
-            roof["traffic"] = TRAFFIC_BINOM2_256_TRI
+        if ops_min is not None:
+            roof["ops_method_minimal"] = ops_min
+            roof["frac_method_minimal"] = ops_min / k_s / VALU_PEAK
+        if name in TRAFFIC:
+            roof["traffic"] = TRAFFIC[name]
             roof["traffic_unit"] = "bytes per launch"
 
     # the plain forward-only per-tile path, same tiles, seed and N: identical counts (equal bound)
@@ -457,10 +559,9 @@ def main():
             print("bench.py: per-tile path counts differ from the fused path", file=sys.stderr)
             sys.exit(1)
 
-    cpu = None if args.no_cpu_baseline else cpu_baseline(name, w, design)
     res = {
-        "metric": METRIC, "value": value, "unit": "sim·tiles/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "metric": METRIC, "value": value, "unit": "sim·tiles/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u32/f32/f64", "data": "synthetic",
         "config": {"workload": WORKLOADS[name], "name": name, "tiles": n,
                    "sims_per_tile": int(np.max(w["sims"])), "parallelism": "single GPU"},
@@ -475,14 +576,13 @@ def main():
         "platten_build_ms": platten_ms,
         "max_tile_bound": float(o["bound"].max().item()) if n else None,
         "roofline": roof,
-        "cpu_baseline": cpu,
     }
     if calibrating:
         res["lambda_global"] = float(o["lam_g"].item())
     if design in ("hier4", "phase23"):
         res["design_table_build_ms"] = st["table_build_us"] / 1e3
-    print(json.dumps(res), flush=True)
     P.close()
+    return res
 
 
 if __name__ == "__main__":

@@ -200,8 +200,9 @@ int cse_calibrate(const cse_platten *p, uint64_t seed, double alpha, double *alp
  * launches and results as cse_calibrate, but the calibration keys live in a static workspace of
  * CSE_NOALLOC_SCRATCH_BYTES bytes compiled into the library (one copy per device, resident until the
  * process ends) instead of memory allocated on the first calibration: the call allocates and frees
- * nothing.  The keys need 2 bytes (CSE_BINOM2_Z) or 4 bytes (other designs) per key slot
- * (n_key_slots of cse_platten_stats); a larger platten is refused with CSE_EINVAL.
+ * nothing.  The keys need 16 bytes per key slot for CSE_BINOM2_Z (one record of success counts per
+ * simulation and tile batch) or 4 bytes for the other designs (one float32 statistic per simulation
+ * and tile), n_key_slots of cse_platten_stats; a larger platten is refused with CSE_EINVAL.
  * Every call on a device shares that device's workspace, which keeps the last call's contents:
  * calls whose execution overlaps on one device (other streams or threads) race and must be
  * ordered by the caller, as calls on one platten must be anyway.  The first call on a device looks
@@ -444,7 +445,8 @@ int cse_posterior_table(const cse_platten *p, float *out, int64_t capacity, int6
 /*
  * cse_platten_stats -- sizes of the planned launch (host), out[0..11] =
  *   n_tiles, n_batches (tile batches of the fused kernel), n_work_items (waves or workgroups
- *   launched by one simulation pass), n_key_slots (calibration keys), total simulations (sum of N
+ *   launched by one simulation pass), n_key_slots (calibration keys: CSE_BINOM2_Z one 16-byte record
+ *   per (simulation, batch), other designs one float32 per (simulation, tile)), total simulations (sum of N
  *   over tiles), tiles per batch, max N, batch-simulation pairs (sum over batches of their N),
  *   workgroup-simulation pairs (sum over workgroup items of their simulation count; the unit of
  *   shared random-number generation), number of distinct N, microseconds spent building the

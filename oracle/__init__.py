@@ -700,8 +700,11 @@ def calibrate(design: str, theta, radii, sims, seed: int, alpha: float, keep_all
         row = S[t, : N[t]].astype(key_dtype)
         lam[t] = order_statistic(row, int(k[t]))
         rej[t] = int(np.sum(row < key_dtype(lam[t])))   # #{S < lambda*_i}, also for lambda*_i = +inf
+    in_null = np.array([bool(s[3]) for s in subs], bool)
+    # lambda* = min over the tiles covering the null space (Section 7.3); boxes kept outside it
+    # (keep_all) have no Type I Error to control
     return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, q=qs, k=k,
-                lam=lam, lam_global=float(lam.min()) if len(lam) else math.inf,
+                lam=lam, lam_global=float(lam[in_null].min()) if in_null.any() else math.inf,
                 reject_at_lam=rej, N=N, subs=subs)
 
 
@@ -731,10 +734,11 @@ def calibrate_tiebreak(design: str, theta, radii, sims, seed: int, alpha: float,
         if k[t] > 0:
             L = key_dtype(lam[t])
             rej[t] = int(np.sum(row < L) + np.sum((row == L) & (ur < c[t])))
-    g = int(np.lexsort((c, lam))[0]) if len(lam) else 0
+    in_null = np.flatnonzero([bool(s[3]) for s in subs])   # the minimum runs over the null space
+    g = int(in_null[np.lexsort((c[in_null], lam[in_null]))[0]]) if len(in_null) else -1
     return dict(box=box, b=np.array([s[1] for s in subs]), alpha_prime=ap, k=k, lam=lam, c=c,
-                reject_at=rej, lam_global=float(lam[g]) if len(lam) else math.inf,
-                c_global=int(c[g]) if len(lam) else 0, N=N, subs=subs)
+                reject_at=rej, lam_global=float(lam[g]) if g >= 0 else math.inf,
+                c_global=int(c[g]) if g >= 0 else 0, N=N, subs=subs)
 
 
 # ---------------------------------------------------- confidence sets (Section 8)

@@ -176,13 +176,13 @@ int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st) {
     } else {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "binom2_calib" : "binom2", st);
-        CSE_LAUNCH(cse::launch_binom2(P, seed, P.d_Rw, P.d_Tw, (uint16_t *)keys, st));
+        CSE_LAUNCH(cse::launch_binom2(P, seed, P.d_Rw, P.d_Tw, (uint4 *)keys, st));
     }
     return CSE_OK;
 }
 
 size_t key_bytes(const cse::Platten &P) {
-    const size_t esz = (P.design.kind == CSE_BINOM2_Z) ? 2 : 4;
+    const size_t esz = (P.design.kind == CSE_BINOM2_Z) ? cse::REC2_BYTES : 4;
     return (size_t)P.n_keys * esz;
 }
 
@@ -254,9 +254,9 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
     // the validation bound.  The fused simulation runs alone (it fills the chip); afterwards
     // the validation bound (float64, latency-bound) runs on the side stream beside the
     // selection, forked from and joined into `st` by events.  Captured as a graph, the
-    // inversion (which does not depend on the simulation) is a branch beside the simulation
-    // too; eager calls keep it in line, so that every kernel's own timing describes that
-    // kernel alone.
+    // inversion and the 2-arm brackets (which do not depend on the simulation) are a branch
+    // beside the simulation too; eager calls keep them in line, so that every kernel's own
+    // timing describes that kernel alone.
     // target level of each tile (Section 7.2), then its order-statistic index (Section 7.1)
     const bool branch_invert = t_capturing;
     {
@@ -265,8 +265,14 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
             CSE_HIP_TRY(hipEventRecord(P.ev_fork, st));
             CSE_HIP_TRY(hipStreamWaitEvent(is, P.ev_fork, 0));
         }
-        Timed tm("bound_invert", is);
-        CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, is));
+        {
+            Timed tm("bound_invert", is);
+            CSE_LAUNCH(cse::launch_bound(P, 1, nullptr, nullptr, alpha, ap, nullptr, kk, nullptr, is));
+        }
+        if (P.design.kind == CSE_BINOM2_Z) {   // the selection's brackets need k only
+            Timed tm("b2_bracket", is);
+            CSE_LAUNCH(cse::launch_b2_bracket(P, kk, is));
+        }
         if (branch_invert) CSE_HIP_TRY(hipEventRecord(P.ev_inv, is));
     }
     if (int e = run_sim(P, seed, keys, st)) return e;
@@ -289,7 +295,7 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
         Timed tm("select", st);
         CSE_LAUNCH(cse::launch_select(P, keys, kk, lam, reject_at_lambda, st));
     }
-    CSE_LAUNCH(cse::launch_min(lam, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
+    CSE_LAUNCH(cse::launch_min(P, lam, P.d_in_null, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
     if (reject || score_T || score_Z || grad)
         CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
     if (want_bound) CSE_HIP_TRY(hipStreamWaitEvent(st, P.ev_val, 0));   // join
@@ -741,7 +747,7 @@ int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, do
         Timed tm("tiebreak", st);
         CSE_LAUNCH(cse::launch_tiebreak(P, seed, kk, lambda_tile, reject_at_lambda, u_tile, st));
     }
-    CSE_LAUNCH(cse::launch_min_pair(lambda_tile, u_tile, P.n_tiles, lambda_global, u_global, st));
+    CSE_LAUNCH(cse::launch_min_pair(lambda_tile, u_tile, P.d_in_null, P.n_tiles, lambda_global, u_global, st));
     return CSE_OK;
 }
 

@@ -18,6 +18,7 @@ constexpr int MAX_D = 4;
 constexpr int NP35 = 35;             // patients per arm of the binomial designs
 constexpr int P23_NMAX_ARM = 350;    // embedded patients per arm of the Phase II/III design
 constexpr uint64_t PLATTEN_GONE = ~0ull;   // shape generation of a destroyed platten
+constexpr int MIN_PARTS = 256;            // partial minima of the large min reductions
 
 // ---- tile batches ("blocks"): each wave owns one block for a range of simulations ----
 // 2-arm designs: an 8 x 8 product of distinct arm-0 and arm-1 thresholds, so one
@@ -29,10 +30,13 @@ struct Blk2 {
     int32_t tile[B2U * B2V];   // tile id of slot (u, v) = u * B2V + v, or -1
     int32_t n_sims;            // simulations of every tile of this block
     int32_t pad;
-    int64_t key_base;          // calibration keys: chunk-major, key of simulation k in slot s
-                               // at key_base + ((k / 64) * 64 + s) * 64 + k % 64
+    int64_t key_base;          // calibration records: simulation k of this block has its record
+                               // (Rec2) at key_base + k (k < n_sims rounded up to 64)
 };
-constexpr int64_t KEY_CHUNK = (int64_t)B2U * B2V * 64;   // keys per 64-simulation chunk
+// Calibration record of one simulation of a 2-arm block: the success counts at the block's
+// thresholds, y0[u] in byte u of (w0, w1) and y1[v] in byte v of (w2, w3).  Every tile's outcome
+// y0[u] (n+1) + y1[v] follows from it, so 16 bytes serve the block's 64 tiles.
+constexpr int REC2_BYTES = 16;
 
 // z-test: 64 tiles share each simulation's normal draw.
 constexpr int B1T = 64;
@@ -68,8 +72,11 @@ struct WorkItem {
     int32_t pad;
 };
 
-// Workgroup item of the 2-arm kernel: its 4 waves simulate the same sims [k_begin, k_end)
-// for up to 4 blocks of equal N (blk = -1: idle wave), sharing each simulation's Philox words.
+// Workgroup item of the group kernels: its 4 waves simulate the same sims [k_begin, k_end) for up to
+// 4 blocks of equal N (blk = -1: no block), sharing each simulation's Philox words.  For the 2-arm
+// design the 4 blocks form a 2 x 2 square of the threshold grid: blk[w] is the block of row group
+// w >> 1 (8 arm-0 thresholds) and column group w & 1 (8 arm-1 thresholds), so the square's
+// 16 + 16 distinct thresholds serve 256 tiles.
 struct GroupItem {
     int32_t blk[4];
     uint32_t k_begin;
@@ -140,6 +147,7 @@ struct Platten {
     double *d_verts = nullptr;
     double *d_radii = nullptr;           // [n_tiles * d] half-widths of the tile's box
     int32_t *d_is_box = nullptr;         // [n_tiles] 1 when the tile is its whole box
+    int32_t *d_in_null = nullptr;        // [n_tiles] 1 when the tile lies in the null space
     int64_t *d_key_off = nullptr;        // [n_tiles] each tile's first key in d_keys
     int64_t *d_key_stride = nullptr;     // [n_tiles] distance between its 64-simulation chunks
     int64_t n_keys = 0;                  // key slots (sum over blocks of 64 * n_sims)
@@ -169,6 +177,7 @@ struct Platten {
     // group kernels
     int64_t tune_waves = 16384, tune_wgs = 4096;
     std::vector<int64_t> blk_sims;       // simulations of each block
+    std::vector<int64_t> blk_row, blk_col;   // 2-arm: each block's row / column group of 8 thresholds
     std::vector<int64_t> p23_item_off;   // [n_tiles + 1] first queue item of each tile
     int64_t h4_outcomes = 0;
     double table_ms = 0.0;               // time to build the design table at platten creation
@@ -176,7 +185,20 @@ struct Platten {
     double *d_S_tbl = nullptr;           // 2-arm: S = -z per outcome y0*(n+1)+y1
     int32_t *d_S_order = nullptr;        // 2-arm: outcomes sorted by S ascending
     int32_t *d_S_group = nullptr;        // 2-arm: index of first outcome with equal S in that order
+    int32_t *d_S_pos = nullptr;          // 2-arm: position of each outcome in that order
+    int32_t *d_gstart = nullptr;         // 2-arm: first position of each tie group of S, [n_groups + 1]
+    uint8_t *d_gcut = nullptr;           // 2-arm: per tie group g and y0, #{y1 : S(y0, y1) >= S_g}, [n_groups + 1][n + 1]
+    int32_t n_groups = 0;
     int32_t n_outcomes = 0;
+    // 2-arm calibration: per-tile bracket of S-order positions [lo, hi] expected to hold the
+    // k-th smallest statistic, and the list of tiles the bracketed selection left to the exact
+    // full-histogram pass ([0] = count, then tile ids)
+    int2 *d_b2br = nullptr;
+    uint32_t *d_b2fb = nullptr;
+    // 2-arm calibration: per block, row group u and arm-0 count y0, the cut points on y1 of the
+    // row's 8 tiles as bytes: x, y = clo (S < S(lo) iff y1 >= clo), z, w = chi (S <= S(hi) iff
+    // y1 >= chi); [n_blocks][8][n + 1]
+    uint4 *d_b2cut = nullptr;
 
     std::vector<uint32_t> tile_T;        // [n_tiles * d] Bernoulli thresholds (binomial designs)
 
@@ -212,6 +234,7 @@ struct Platten {
     int32_t *d_kw = nullptr;             // k
     double *d_lamw = nullptr;            // lambda*_i
     double *d_lamg = nullptr;            // lambda* (1)
+    double *d_minpart = nullptr;         // [MIN_PARTS] partial minima of the reductions over tiles
 
     // calibration keys (allocated on first calibration): n_keys entries of 2 (outcome
     // index) or 4 (float32 statistic) bytes

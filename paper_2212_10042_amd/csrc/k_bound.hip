@@ -600,8 +600,8 @@ hipError_t launch_confset(const Platten &P, const double *s_obs, int64_t s_strid
 #undef CSE_CONF_LAUNCH
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = launch_min(wmin, P.n_tiles, e_range, st)) != hipSuccess) return e;
-    if ((e = launch_min(wmax, P.n_tiles, e_range + 1, st)) != hipSuccess) return e;
+    if ((e = launch_min(P, wmin, nullptr, P.n_tiles, e_range, st)) != hipSuccess) return e;
+    if ((e = launch_min(P, wmax, nullptr, P.n_tiles, e_range + 1, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_negate1, dim3(1), dim3(1), 0, st, e_range + 1);
     return hipGetLastError();
 }

@@ -5,6 +5,8 @@
 // (score gradient, fixed-point conversion, zero fill).
 #include <math.h>
 
+#include <algorithm>
+
 #include "cse_internal.h"
 #include "kernels.h"
 #include "philox.hpp"
@@ -32,86 +34,380 @@ __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
     __syncthreads();   // wave_tot may be rewritten by the next call only after every wave read it
 }
 
-// ---- discrete statistic (2-arm design): keys are outcome indices y0*(n+1)+y1 ----
-// The tile's histogram of outcomes is built in LDS; one wave then walks the outcomes in
-// ascending-S order (S_order, ties grouped by S_group) with wave prefix sums and stops at the
-// first position whose cumulative count reaches k: its S value is lambda*, and the count
-// before its tie group is the number of simulations with S < lambda*.
+// ---- discrete statistic (2-arm design) ----
+// The fused kernel stores one record per (simulation, batch): the success counts y0[u], y1[v] at
+// the batch's 8 + 8 thresholds (Rec2), so tile (u, v)'s outcome of simulation j is
+// y0[u] (n+1) + y1[v].  The statistic S = -z is a function of the outcome; outcomes sorted by S
+// (S_order, ties grouped by S_group: the first position with equal S) give each outcome a
+// position S_pos, and the k-th smallest S of a tile is the S of the first position whose
+// cumulative count reaches k.
+//
+// Selection in three kernels:
+//  * k_b2_bracket: per tile, the exact law of (y0, y1) under the simulated model (independent
+//    Binomial(35, T/2^32) arms) gives a bracket [lo, hi] of positions (whole tie groups, found by
+//    binary search over the groups) holding the k-th smallest S unless the count below lo reaches
+//    k or the count up to hi stays below k, each about 5 standard deviations of the count away.
+//    As S does not increase with y1 for fixed y0, S < S(lo) iff y1 >= clo(y0) and S <= S(hi) iff
+//    y1 >= chi(y0): the kernel also writes, per batch row u and count y0, the cut points clo, chi
+//    of the row's 8 tiles as bytes (16 bytes);
+//  * k_b2_select: one workgroup per batch reads the batch's records once.  Per simulation and
+//    row, one LDS read of the row's cut bytes classifies its 8 tiles four at a time (byte-wise
+//    compares of the record's packed y1 bytes): tiles below the bracket are counted in packed
+//    byte counters per lane, and the rare tiles inside it look up the outcome's position and
+//    add to an LDS histogram of the bracket; the k-th smallest is read off the histogram;
+//  * k_b2_full: tiles whose k-th smallest fell outside the bracket, or whose bracket did not fit
+//    the LDS histogram, are selected from a full 1,296-bin histogram of their records.
+// Either way lambda*_i is the exact k-th smallest S and rej_at the exact count strictly below it.
+constexpr int B2_N1 = NP35 + 1;            // outcomes per arm
+constexpr int B2_NOUT = B2_N1 * B2_N1;     // 1,296 outcomes
+constexpr float B2_Z = 5.0f;               // bracket margin in standard deviations of the count
+constexpr int B2_HB = 8192;                // LDS histogram bins of one batch (32 KB)
+
+__device__ __forceinline__ uint32_t rec_byte(uint32_t w, int b) { return (w >> (8 * b)) & 0xFFu; }
+__device__ __forceinline__ uint32_t rec_outcome(const uint4 r, int s) {
+    const int u = s >> 3, v = s & 7;
+    const uint32_t y0 = rec_byte(u < 4 ? r.x : r.y, u & 3);
+    const uint32_t y1 = rec_byte(v < 4 ? r.z : r.w, v & 3);
+    return y0 * (uint32_t)B2_N1 + y1;
+}
+
 __device__ __forceinline__ void lds_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__global__ __launch_bounds__(SEL_WG) void k_select_outcomes(
-    const uint16_t *__restrict__ keys, const int64_t *__restrict__ key_off,
-    const int32_t *__restrict__ N, const int32_t *__restrict__ kk, const double *__restrict__ S_tbl,
-    const int32_t *__restrict__ S_order, const int32_t *__restrict__ S_group, int n_out,
-    double *__restrict__ lam, int32_t *__restrict__ rej_at) {
-    extern __shared__ uint32_t sm[];
-    uint32_t *hist = sm;           // [n_out]
-    uint32_t *cumx = sm + n_out;   // [n_out] exclusive cumulative counts in S order
-    const int64_t t = blockIdx.x;
-    const int tid = threadIdx.x;
-    const int32_t n = N[t];
-    const int32_t k = kk[t];
-    if (k <= 0 || k > n) {
-        if (tid == 0) {
+// One wave per batch, lane = slot.  Also resets the fallback list (before k_b2_select runs).
+// Under the exact law, P(S < S_g) = sum_y0 P(y0) P(y1 >= cut_g(y0)) for each tie group g (S does
+// not increase with y1), so each bracket end is a binary search over the tie groups with 36 terms
+// per evaluation, and the cut bytes of the selection are the table rows of the two groups found.
+__global__ __launch_bounds__(WAVE) void k_b2_bracket(const Blk2 *__restrict__ blocks, const int32_t *__restrict__ kk,
+                                                     const int32_t *__restrict__ gstart,
+                                                     const uint8_t *__restrict__ gcut, int n_groups,
+                                                     int2 *__restrict__ br, uint4 *__restrict__ cut,
+                                                     uint32_t *__restrict__ fb) {
+    __shared__ float tail1[B2_N1 + 1][WAVE];   // P(y1 >= c) of each lane's tile, c = 0..36
+    __shared__ uint8_t cb[B2U][B2_N1][16];     // per row and y0: clo of the 8 tiles, then chi
+    const int lane = threadIdx.x;
+    const Blk2 *__restrict__ B = blocks + blockIdx.x;
+    if (blockIdx.x == 0 && lane == 0) fb[0] = 0u;
+    const int32_t t = B->tile[lane];
+    const int32_t N = B->n_sims;
+    const int32_t k = t >= 0 ? kk[t] : 0;
+    const bool live = t >= 0 && k >= 1 && k <= N;
+    // Binomial(35, p) probabilities in float32 from log C(35, y) + y log p + (35 - y) log(1 - p),
+    // p = T / 2^32 (the simulated draw rule); p = 0 puts all mass on y = 0
+    const float p0 = (float)B->T0[lane >> 3] * 0x1p-32f, p1 = (float)B->T1[lane & 7] * 0x1p-32f;
+    const float l0 = logf(p0), m0 = log1pf(-p0), l1 = logf(p1), m1 = log1pf(-p1);
+    float lc[B2_N1];   // log y!, then log C(35, y)
+    {
+        float lfac = 0.0f;
+#pragma unroll
+        for (int y = 0; y < B2_N1; ++y) {
+            if (y > 0) lfac += logf((float)y);
+            lc[y] = lfac;
+        }
+    }
+    float b0[B2_N1];
+    float run = 0.0f;
+    tail1[B2_N1][lane] = 0.0f;
+#pragma unroll
+    for (int y = B2_N1 - 1; y >= 0; --y) {
+        const float c = lc[NP35] - lc[y] - lc[NP35 - y];
+        b0[y] = p0 > 0.0f ? expf(c + (float)y * l0 + (float)(NP35 - y) * m0) : (y == 0 ? 1.0f : 0.0f);
+        run += p1 > 0.0f ? expf(c + (float)y * l1 + (float)(NP35 - y) * m1) : (y == 0 ? 1.0f : 0.0f);
+        tail1[y][lane] = run;
+    }
+    lds_wave_sync();
+    auto below = [&](int g) -> float {   // P(S < S_g) of this lane's tile
+        const uint32_t *__restrict__ cw = reinterpret_cast<const uint32_t *>(gcut + (size_t)g * B2_N1);
+        uint32_t w[B2_N1 / 4];
+#pragma unroll
+        for (int i = 0; i < B2_N1 / 4; ++i) w[i] = cw[i];
+        float sum = 0.0f;
+#pragma unroll
+        for (int y0 = 0; y0 < B2_N1; ++y0) sum += b0[y0] * tail1[(w[y0 >> 2] >> (8 * (y0 & 3))) & 0xFFu][lane];
+        return sum;
+    };
+    const float kf = (float)k, sd = sqrtf(kf + 1.0f);
+    const float lo_t = kf - B2_Z * sd - 2.0f, hi_t = kf + B2_Z * sd + 2.0f;
+    const float Nf = (float)N;
+    int a = 0, b = n_groups;            // lo group: the last g with N P(S < S_g) <= lo_t (g = 0 has 0)
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (Nf * below(m) <= lo_t) a = m; else b = m;
+    }
+    const int glo = a;
+    a = -1;
+    b = n_groups - 1;                   // hi group: the first g with N P(S <= S_g) >= hi_t
+    while (b - a > 1) {
+        const int m = (a + b) >> 1;
+        if (Nf * below(m + 1) >= hi_t) b = m; else a = m;
+    }
+    const int ghi = b;
+    if (t >= 0) br[t] = make_int2(gstart[glo], gstart[ghi + 1] - 1);
+    // cut points of this tile: clo = cut of its first group, chi = cut of the group after its last
+    const uint8_t *__restrict__ clo = gcut + (size_t)glo * B2_N1, *__restrict__ chi = gcut + (size_t)(ghi + 1) * B2_N1;
+    for (int y0 = 0; y0 < B2_N1; ++y0) {
+        cb[lane >> 3][y0][lane & 7] = live ? clo[y0] : (uint8_t)B2_N1;
+        cb[lane >> 3][y0][8 + (lane & 7)] = live ? chi[y0] : (uint8_t)B2_N1;
+    }
+    lds_wave_sync();
+    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(&cb[0][0][0]);
+    uint4 *__restrict__ dst = cut + (size_t)blockIdx.x * B2U * B2_N1;
+    for (int i = lane; i < B2U * B2_N1; i += WAVE) dst[i] = src[i];
+}
+
+// One workgroup per batch.  Simulations go in rounds of B2_ROUND chunks per wave: the byte-wise
+// pass counts the tiles below their bracket and lists the simulations that fall inside some
+// tile's bracket (under common random numbers such a simulation is usually inside the brackets
+// of many of the batch's neighbouring tiles at once, so a per-lane loop over its tiles would
+// stall the wave); after the round the listed simulations are taken one per wave-step with
+// lane = tile: position lookup and histogram add without divergence.
+constexpr int B2_ROUND = 8;
+__global__ __launch_bounds__(SEL_WG) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_b2_select(
+    const Blk2 *__restrict__ blocks, const uint4 *__restrict__ recs, const int32_t *__restrict__ kk,
+    const int2 *__restrict__ br, const uint4 *__restrict__ cut, const int32_t *__restrict__ S_pos,
+    const int32_t *__restrict__ S_order, const int32_t *__restrict__ S_group, const double *__restrict__ S_tbl,
+    double *__restrict__ lam, int32_t *__restrict__ rej_at, uint32_t *__restrict__ fb) {
+    constexpr int NT = B2U * B2V;
+    constexpr int NWV = SEL_WG / WAVE;
+    constexpr uint32_t H = 0x80808080u, ONES = 0x01010101u;
+    __shared__ uint16_t spos[B2_NOUT];
+    __shared__ uint4 ct[B2U][B2_N1];
+    __shared__ uint32_t hist[B2_HB];
+    __shared__ int2 prm[NT];          // per slot: (first bin - lo, histogram present)
+    __shared__ uint32_t below[NT];    // per slot: simulations with S < S(lo)
+    __shared__ uint32_t lst[NWV * B2_ROUND * WAVE];   // simulations of the round inside some bracket
+    __shared__ uint32_t s_nl;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
+    const Blk2 *__restrict__ B = blocks + blockIdx.x;
+    const int32_t N = B->n_sims;
+    for (int o = tid; o < B2_NOUT; o += SEL_WG) spos[o] = (uint16_t)S_pos[o];
+    {
+        const uint4 *__restrict__ cs = cut + (size_t)blockIdx.x * B2U * B2_N1;
+        for (int i = tid; i < B2U * B2_N1; i += SEL_WG) (&ct[0][0])[i] = cs[i];
+    }
+    for (int i = tid; i < B2_HB; i += SEL_WG) hist[i] = 0u;
+    if (tid == 0) s_nl = 0u;
+    // lane = slot for the list pass and the setup: the slot's bracket and histogram region
+    int my_lo = 0, my_hi = -1, my_base = 0;
+    {
+        const int32_t t = B->tile[lane];
+        const int32_t k = t >= 0 ? kk[t] : 0;
+        int lo = 0, W = 0;
+        if (t >= 0 && k >= 1 && k <= N) {
+            const int2 b = br[t];
+            lo = b.x;
+            W = b.y - b.x + 1;
+        } else if (t >= 0 && wv == 0) {   // outside Theorem 4's range: +-inf, no selection
             lam[t] = k <= 0 ? -INFINITY : INFINITY;
-            if (rej_at) rej_at[t] = k <= 0 ? 0 : n;
+            rej_at[t] = k <= 0 ? 0 : N;
         }
-        return;
-    }
-    for (int j = tid; j < n_out; j += SEL_WG) hist[j] = 0u;
-    __syncthreads();
-    // chunk-major keys: chunk c of this tile is 64 contiguous keys at key_off + c * KEY_CHUNK;
-    // eight threads read one chunk as eight 16-byte pieces
-    const uint16_t *__restrict__ kt = keys + key_off[t];
-    const int nch = (n + WAVE - 1) / WAVE;
-    constexpr int LPT = 4;   // 16-byte loads in flight per thread before its LDS atomics
-    for (int j0 = tid; j0 < nch * 8; j0 += SEL_WG * LPT) {
-        uint4 v[LPT];
+        int x = W;
 #pragma unroll
-        for (int l = 0; l < LPT; ++l) {
-            const int j = j0 + l * SEL_WG;
-            if (j < nch * 8)
-                v[l] = *reinterpret_cast<const uint4 *>(kt + (int64_t)(j >> 3) * KEY_CHUNK + (j & 7) * 8);
+        for (int off = 1; off < WAVE; off <<= 1) {
+            const int y = __shfl_up(x, off);
+            if (lane >= off) x += y;
         }
-#pragma unroll
-        for (int l = 0; l < LPT; ++l) {
-            const int j = j0 + l * SEL_WG;
-            if (j >= nch * 8) break;
-            const int k0 = (j >> 3) * WAVE + (j & 7) * 8;
-            const uint32_t w[4] = {v[l].x, v[l].y, v[l].z, v[l].w};
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                if (k0 + e < n) atomicAdd(&hist[(w[e >> 1] >> (16 * (e & 1))) & 0xFFFFu], 1u);
+        const int hoff = x - W;
+        const bool fits = W > 0 && hoff + W <= B2_HB;   // else: exact full pass
+        if (wv == 0) {
+            below[lane] = 0u;
+            prm[lane] = make_int2(hoff - lo, fits ? 1 : 0);
+        }
+        if (fits) {
+            my_lo = lo;
+            my_hi = lo + W - 1;
+            my_base = hoff - lo;
         }
     }
     __syncthreads();
-    if (tid >= WAVE) return;
-    uint32_t run = 0u;
-    for (int base = 0; base < n_out; base += WAVE) {
-        const int p = base + tid;
-        const uint32_t c = p < n_out ? hist[S_order[p]] : 0u;
-        uint32_t incl = c;
+    const uint4 *__restrict__ rb = recs + B->key_base;
+    const int nch = (N + WAVE - 1) / WAVE;
+    uint32_t acc[B2U][2];   // per row and half: packed byte counts of simulations below the bracket
 #pragma unroll
-        for (int o = 1; o < WAVE; o <<= 1) {
-            const uint32_t y = __shfl_up(incl, o);
-            if (tid >= o) incl += y;
-        }
-        const uint32_t excl = run + incl - c;
-        if (p < n_out) cumx[p] = excl;
-        lds_wave_sync();
-        const bool hit = p < n_out && excl < (uint32_t)k && excl + c >= (uint32_t)k;
-        if (__ballot(hit)) {
-            if (hit) {
-                lam[t] = S_tbl[S_order[p]];
-                if (rej_at) rej_at[t] = (int32_t)cumx[S_group[p]];
+    for (int u = 0; u < B2U; ++u) acc[u][0] = acc[u][1] = 0u;
+    auto flush = [&]() {    // wave sums of the byte counters (as 16-bit pairs) into below[]
+#pragma unroll
+        for (int u = 0; u < B2U; ++u)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                uint32_t ev = acc[u][h] & 0x00FF00FFu, od = (acc[u][h] >> 8) & 0x00FF00FFu;
+#pragma unroll
+                for (int off = 32; off >= 1; off >>= 1) {
+                    ev += __shfl_xor(ev, off);
+                    od += __shfl_xor(od, off);
+                }
+                if (lane == 0) {
+                    atomicAdd(&below[u * B2V + 4 * h + 0], ev & 0xFFFFu);
+                    atomicAdd(&below[u * B2V + 4 * h + 1], od & 0xFFFFu);
+                    atomicAdd(&below[u * B2V + 4 * h + 2], ev >> 16);
+                    atomicAdd(&below[u * B2V + 4 * h + 3], od >> 16);
+                }
+                acc[u][h] = 0u;
             }
-            return;
+    };
+    int since = 0;
+    // the record of this wave's next chunk is loaded one chunk ahead (records are padded to whole
+    // chunks, so a chunk index below nch is always in bounds)
+    uint4 rnext = wv < nch ? rb[wv * WAVE + lane] : make_uint4(0u, 0u, 0u, 0u);
+    for (int c0 = 0; c0 < nch; c0 += NWV * B2_ROUND) {
+        for (int i = 0; i < B2_ROUND; ++i) {
+            const int c = c0 + wv + NWV * i;
+            if (c >= nch) break;   // uniform over the wave
+            const int j = c * WAVE + lane;
+            const uint4 r = rnext;
+            if (c + NWV < nch) rnext = rb[(c + NWV) * WAVE + lane];
+            const uint32_t live = j < N ? ONES : 0u;
+            const uint32_t ya = r.z | H, yb = r.w | H;   // y1 of v = 0..3, 4..7, each byte's high bit set
+            uint32_t inb = 0u;
+#pragma unroll
+            for (int u = 0; u < B2U; ++u) {
+                const uint32_t y0 = rec_byte(u < 4 ? r.x : r.y, u & 3);
+                const uint4 T = ct[u][y0];
+                const uint32_t bl = ((ya - T.x) >> 7) & live, bh = ((yb - T.y) >> 7) & live;   // y1 >= clo
+                const uint32_t al = ((ya - T.z) >> 7) & live, ah = ((yb - T.w) >> 7) & live;   // y1 >= chi
+                acc[u][0] += bl;
+                acc[u][1] += bh;
+                inb |= (al ^ bl) | (ah ^ bh);
+            }
+            const bool in = inb != 0u;
+            const unsigned long long bal = __ballot(in);
+            if (bal) {
+                uint32_t base = 0u;
+                if (lane == 0) base = atomicAdd(&s_nl, (uint32_t)__popcll(bal));
+                base = __shfl(base, 0);
+                if (in) lst[base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull))] = (uint32_t)j;
+            }
+            if (++since == 255) {   // byte counters: at most 255 increments between flushes
+                flush();
+                since = 0;
+            }
         }
-        run += __shfl(incl, WAVE - 1);
+        __syncthreads();
+        // the round's listed simulations, lane = tile: exact position, histogram of the bracket
+        const uint32_t nl = s_nl;
+        const int u = lane >> 3, v = lane & 7;
+        for (uint32_t li = (uint32_t)wv; li < nl; li += NWV) {
+            const uint32_t j = __builtin_amdgcn_readfirstlane(lst[li]);
+            const uint4 r = rb[j];
+            const uint32_t y0 = rec_byte(u < 4 ? r.x : r.y, u & 3), y1 = rec_byte(v < 4 ? r.z : r.w, v & 3);
+            const int pos = (int)spos[y0 * B2_N1 + y1];
+            if (pos >= my_lo && pos <= my_hi) atomicAdd(&hist[my_base + pos], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) s_nl = 0u;
+        __syncthreads();
+    }
+    flush();
+    __syncthreads();
+    // per tile: walk the bracket's histogram in position order (one wave per tile)
+    for (int s = wv; s < NT; s += SEL_WG / WAVE) {
+        const int32_t t = B->tile[s];
+        if (t < 0) continue;
+        const int32_t k = kk[t];
+        if (k <= 0 || k > N) continue;
+        const int2 q = prm[s];
+        const int2 b = br[t];
+        bool done = false;
+        const uint32_t bel = below[s];
+        if (q.y && bel < (uint32_t)k) {
+            const int lo = b.x, W = b.y - b.x + 1, h0 = q.x + lo;
+            uint32_t run = bel;
+            for (int i0 = 0; i0 < W && !done; i0 += WAVE) {
+                const int i = i0 + lane;
+                const uint32_t c = i < W ? hist[h0 + i] : 0u;
+                uint32_t incl = c;
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o);
+                    if (lane >= o) incl += y;
+                }
+                const uint32_t excl = run + incl - c;
+                if (i < W) hist[h0 + i] = excl;   // count strictly before position lo + i
+                lds_wave_sync();
+                const bool hit = i < W && excl < (uint32_t)k && excl + c >= (uint32_t)k;
+                const unsigned long long bal = __ballot(hit);
+                if (bal) {
+                    if (hit) {
+                        const int p = lo + i;
+                        const int g = S_group[p];   // >= lo: the bracket starts a tie group
+                        lam[t] = S_tbl[S_order[p]];
+                        rej_at[t] = (int32_t)hist[h0 + (g - lo)];
+                    }
+                    done = true;
+                }
+                run += __shfl(incl, WAVE - 1);
+            }
+        }
+        if (!done && lane == 0) {   // outside the bracket or not histogrammed: exact full pass
+            const uint32_t slot = atomicAdd(&fb[0], 1u);
+            fb[1 + slot] = (uint32_t)t;
+        }
+    }
+}
+
+// Exact selection from the full histogram of a tile's 1,296 outcomes, for the tiles listed in fb;
+// a fixed grid of workgroups takes the listed tiles in turn.
+__global__ __launch_bounds__(SEL_WG) void k_b2_full(const uint4 *__restrict__ recs, const int64_t *__restrict__ key_off,
+                                                    const int64_t *__restrict__ key_slot,
+                                                    const int32_t *__restrict__ N, const int32_t *__restrict__ kk,
+                                                    const double *__restrict__ S_tbl,
+                                                    const int32_t *__restrict__ S_order,
+                                                    const int32_t *__restrict__ S_group,
+                                                    const uint32_t *__restrict__ fb, double *__restrict__ lam,
+                                                    int32_t *__restrict__ rej_at) {
+    __shared__ uint32_t hist[B2_NOUT];
+    __shared__ uint32_t cumx[B2_NOUT];   // exclusive cumulative counts in S order
+    const int tid = threadIdx.x;
+    const uint32_t n_list = fb[0];
+    for (uint32_t li = blockIdx.x; li < n_list; li += gridDim.x) {
+        const int32_t t = (int32_t)fb[1 + li];
+        const int32_t n = N[t], k = kk[t];
+        const int s = (int)key_slot[t];
+        const uint4 *__restrict__ rb = recs + key_off[t];
+        for (int j = tid; j < B2_NOUT; j += SEL_WG) hist[j] = 0u;
+        __syncthreads();
+        constexpr int LPT = 4;   // records in flight per thread
+        for (int j0 = tid; j0 < n; j0 += SEL_WG * LPT) {
+            uint4 r[LPT];
+#pragma unroll
+            for (int l = 0; l < LPT; ++l) {
+                const int j = j0 + l * SEL_WG;
+                if (j < n) r[l] = rb[j];
+            }
+#pragma unroll
+            for (int l = 0; l < LPT; ++l)
+                if (j0 + l * SEL_WG < n) atomicAdd(&hist[rec_outcome(r[l], s)], 1u);
+        }
+        __syncthreads();
+        if (tid < WAVE) {
+            uint32_t run = 0u;
+            for (int base = 0; base < B2_NOUT; base += WAVE) {
+                const int p = base + tid;
+                const uint32_t c = p < B2_NOUT ? hist[S_order[p]] : 0u;
+                uint32_t incl = c;
+#pragma unroll
+                for (int o = 1; o < WAVE; o <<= 1) {
+                    const uint32_t y = __shfl_up(incl, o);
+                    if (tid >= o) incl += y;
+                }
+                const uint32_t excl = run + incl - c;
+                if (p < B2_NOUT) cumx[p] = excl;
+                lds_wave_sync();
+                const bool hit = p < B2_NOUT && excl < (uint32_t)k && excl + c >= (uint32_t)k;
+                if (__ballot(hit)) {
+                    if (hit) {
+                        lam[t] = S_tbl[S_order[p]];
+                        rej_at[t] = (int32_t)cumx[S_group[p]];
+                    }
+                    break;
+                }
+                run += __shfl(incl, WAVE - 1);
+            }
+        }
+        __syncthreads();   // hist and cumx are rewritten for the next listed tile
     }
 }
 
@@ -320,9 +616,9 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
 // mapped to 0xFFFFFFFF (which cannot change a rank <= the number of ties).  On exit rej_at[t]
 // holds the number of pairs strictly below (lambda, c).
 // Key layouts: TB_F32 float32 keys at kt[(j / 64) * stride + j % 64]; TB_F32V4 the same with
-// 256-byte aligned 64-key chunks (read as float4); TB_OUT 2-arm outcome indices, chunk-major
-// (64 keys per KEY_CHUNK), read as 16-byte pieces of eight keys and tested against an LDS
-// bitmask of the outcomes whose statistic equals lambda.
+// 256-byte aligned 64-key chunks (read as float4); TB_OUT the 2-arm records (the tile's outcome
+// from record key_off + j and its slot key_stride), tested against an LDS bitmask of the
+// outcomes whose statistic equals lambda.
 enum { TB_F32 = 0, TB_F32V4 = 1, TB_OUT = 2 };
 constexpr int TB_MASK_WORDS = 2048;   // 65,536 outcome indices (16-bit keys)
 constexpr int TB_RANK = 512;          // tie classes up to this size are ranked by counting
@@ -358,7 +654,8 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     const uint32_t need = (uint32_t)k - below_lam;   // >= 1: the k-th key is a tie
     const int64_t stride = key_stride[t];
     const float *__restrict__ kf = (const float *)keys_ + key_off[t];
-    const uint16_t *__restrict__ ko = (const uint16_t *)keys_ + key_off[t];
+    const uint4 *__restrict__ ko = (const uint4 *)keys_ + key_off[t];   // TB_OUT: the batch's records
+    const int slot = (int)stride;                                        // TB_OUT: the tile's slot
     if (MODE == TB_OUT) {
         for (int w = tid; w < TB_MASK_WORDS; w += SEL_WG) tmask[w] = 0u;
         __syncthreads();
@@ -369,7 +666,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     __syncthreads();
     auto is_tie_out = [&](uint32_t key) { return (tmask[key >> 5] >> (key & 31)) & 1u; };
     auto tied = [&](int j) -> bool {
-        if (MODE == TB_OUT) return is_tie_out(ko[(int64_t)(j >> 6) * KEY_CHUNK + (j & 63)]);
+        if (MODE == TB_OUT) return is_tie_out(rec_outcome(ko[j], slot));
         return f2ord(kf[(int64_t)(j >> 6) * stride + (j & 63)]) == Lord;
     };
     // append simulation j's uniform when `in` (called by every lane of the wave)
@@ -387,25 +684,17 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     // counts are uniform so that every lane takes part in the ballots
     constexpr int LB = 4;
     if (MODE == TB_OUT) {
-        const int nq = ((n + 63) >> 6) * 8;   // 16-byte pieces
-        for (int q0 = 0; q0 < nq; q0 += SEL_WG * LB) {
-            uint4 v[LB];
+        for (int j0 = 0; j0 < n; j0 += SEL_WG * LB) {
+            uint4 r[LB];
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
-                const int q = q0 + i * SEL_WG + tid;
-                v[i] = q < nq ? *reinterpret_cast<const uint4 *>(ko + (int64_t)(q >> 3) * KEY_CHUNK + (q & 7) * 8)
-                              : make_uint4(0u, 0u, 0u, 0u);
+                const int j = j0 + i * SEL_WG + tid;
+                r[i] = j < n ? ko[j] : make_uint4(0u, 0u, 0u, 0u);
             }
 #pragma unroll
             for (int i = 0; i < LB; ++i) {
-                const int q = q0 + i * SEL_WG + tid;
-                const int j0 = (q >> 3) * 64 + (q & 7) * 8;
-                const uint32_t wd[4] = {v[i].x, v[i].y, v[i].z, v[i].w};
-#pragma unroll
-                for (int e = 0; e < 8; ++e) {
-                    const uint32_t key = (wd[e >> 1] >> (16 * (e & 1))) & 0xFFFFu;
-                    take(q < nq && j0 + e < n && is_tie_out(key), j0 + e);
-                }
+                const int j = j0 + i * SEL_WG + tid;
+                take(j < n && is_tie_out(rec_outcome(r[i], slot)), j);
             }
         }
     } else if (MODE == TB_F32V4) {
@@ -484,13 +773,14 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
 
 // lexicographic minimum over tiles of (lambda_i, c_i), one workgroup.
 __global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v, const uint32_t *__restrict__ c,
-                                                   int64_t n, double *__restrict__ out_v,
-                                                   uint32_t *__restrict__ out_c) {
+                                                   const int32_t *__restrict__ in_null, int64_t n,
+                                                   double *__restrict__ out_v, uint32_t *__restrict__ out_c) {
     __shared__ double sv[1024];
     __shared__ uint32_t sc[1024];
     double mv = INFINITY;
     uint32_t mc = 0xFFFFFFFFu;
     for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        if (in_null && !in_null[i]) continue;
         const double x = v[i];
         const uint32_t y = c[i];
         if (x < mv || (x == mv && y < mc)) {
@@ -519,11 +809,13 @@ __global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v,
 }
 
 // min over tiles of lambda*_i, one workgroup.
-__global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, int64_t n,
-                                              double *__restrict__ out) {
+// min over the tiles in the null space (in_null[i] != 0; every tile when in_null is NULL)
+__global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, const int32_t *__restrict__ in_null,
+                                              int64_t n, double *__restrict__ out) {
     __shared__ double sm[1024];
     double m = INFINITY;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) m = fmin(m, v[i]);
+    for (int64_t i = threadIdx.x; i < n; i += 1024)
+        if (!in_null || in_null[i]) m = fmin(m, v[i]);
     sm[threadIdx.x] = m;
     __syncthreads();
     for (int s = 512; s > 0; s >>= 1) {
@@ -531,6 +823,22 @@ __global__ __launch_bounds__(1024) void k_min(const double *__restrict__ v, int6
         __syncthreads();
     }
     if (threadIdx.x == 0) out[0] = sm[0];
+}
+
+// partial minima: workgroup g takes the tiles g, g + MIN_PARTS, ... (in 1024-tile strides)
+__global__ __launch_bounds__(1024) void k_min_part(const double *__restrict__ v, const int32_t *__restrict__ in_null,
+                                                   int64_t n, double *__restrict__ part) {
+    __shared__ double sm[1024];
+    double m = INFINITY;
+    for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 1024)
+        if (!in_null || in_null[i]) m = fmin(m, v[i]);
+    sm[threadIdx.x] = m;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if (threadIdx.x < s) sm[threadIdx.x] = fmin(sm[threadIdx.x], sm[threadIdx.x + s]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
 }
 
 // Score-function gradient (sum over rejections of T(x) - R grad A(theta)) / N, float64;
@@ -600,11 +908,23 @@ hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, d
     else if (P.design.kind != CSE_BINOM2_Z)
         hipLaunchKernelGGL(k_select_f32<false>, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st,
                            (const float *)keys, P.d_key_off, P.d_key_stride, P.d_N, k, lam, rej_at);
-    else
-        hipLaunchKernelGGL(k_select_outcomes, dim3((uint32_t)P.n_tiles), dim3(SEL_WG),
-                           2 * (size_t)P.n_outcomes * sizeof(uint32_t), st,
-                           (const uint16_t *)keys, P.d_key_off, P.d_N, k, P.d_S_tbl, P.d_S_order,
-                           P.d_S_group, P.n_outcomes, lam, rej_at);
+    else {   // the 2-arm bracket (launch_b2_bracket) must have run after k was computed
+        const Blk2 *blk = (const Blk2 *)P.d_blocks;
+        hipLaunchKernelGGL(k_b2_select, dim3((uint32_t)P.n_blocks), dim3(SEL_WG), 0, st, blk, (const uint4 *)keys, k,
+                           P.d_b2br, P.d_b2cut, P.d_S_pos, P.d_S_order, P.d_S_group, P.d_S_tbl, lam, rej_at,
+                           P.d_b2fb);
+        const uint32_t grid = (uint32_t)std::min<int64_t>(P.n_tiles, 1024);
+        hipLaunchKernelGGL(k_b2_full, dim3(grid), dim3(SEL_WG), 0, st, (const uint4 *)keys, P.d_key_off,
+                           P.d_key_stride, P.d_N, k, P.d_S_tbl, P.d_S_order, P.d_S_group, P.d_b2fb, lam, rej_at);
+    }
+    return hipGetLastError();
+}
+
+// 2-arm calibration: brackets and cut points from k (independent of the simulation); resets the
+// list of tiles left to the exact full pass.
+hipError_t launch_b2_bracket(const Platten &P, const int32_t *k, hipStream_t st) {
+    hipLaunchKernelGGL(k_b2_bracket, dim3((uint32_t)P.n_blocks), dim3(WAVE), 0, st, (const Blk2 *)P.d_blocks, k,
+                       P.d_gstart, P.d_gcut, P.n_groups, P.d_b2br, P.d_b2cut, P.d_b2fb);
     return hipGetLastError();
 }
 
@@ -626,14 +946,22 @@ hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, co
     return hipGetLastError();
 }
 
-hipError_t launch_min_pair(const double *v, const uint32_t *c, int64_t n, double *out_v, uint32_t *out_c,
-                           hipStream_t st) {
-    hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, v, c, n, out_v, out_c);
+hipError_t launch_min_pair(const double *v, const uint32_t *c, const int32_t *in_null, int64_t n, double *out_v,
+                           uint32_t *out_c, hipStream_t st) {
+    hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, v, c, in_null, n, out_v, out_c);
     return hipGetLastError();
 }
 
-hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st) {
-    hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, st, v, n, out);
+hipError_t launch_min(const Platten &P, const double *v, const int32_t *in_null, int64_t n, double *out,
+                      hipStream_t st) {
+    // large inputs: MIN_PARTS workgroups of partial minima first, then one workgroup over them
+    if (n > 64 * 1024 && P.d_minpart) {
+        hipLaunchKernelGGL(k_min_part, dim3(MIN_PARTS), dim3(1024), 0, st, v, in_null, n, P.d_minpart);
+        hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, st, (const double *)P.d_minpart, (const int32_t *)nullptr,
+                           (int64_t)MIN_PARTS, out);
+    } else {
+        hipLaunchKernelGGL(k_min, dim3(1), dim3(1024), 0, st, v, in_null, n, out);
+    }
     return hipGetLastError();
 }
 

@@ -4,8 +4,9 @@
 // the Philox words are generated in registers, turned into draws, shared by every tile
 // of the batch (common random numbers, Section 7.3), and reduced into per-tile rejection
 // counts R and score sums (sufficient statistic over rejections, Example 1).  In
-// calibration mode each (simulation, tile) also stores its key: the outcome index
-// (2-arm design) or the statistic S in float32 (z-test).  Nothing else reaches memory.
+// calibration mode the 2-arm kernel also stores, per (simulation, batch), the 16 success
+// counts from which every tile's outcome follows (one 16-byte record for 64 tiles), and the
+// z-test each (simulation, tile)'s statistic S in float32.  Nothing else reaches memory.
 #include "cse_internal.h"
 #include "kernels.h"
 #include "philox.hpp"
@@ -23,10 +24,16 @@ __device__ __forceinline__ void wave_sync() {
 // 2-arm binomial, n = 35 per arm, pooled z.  Words 0..34 are arm 0, 35..69 arm 1
 // (18 Philox blocks).  Each wave's batch is an 8 x 8 product of thresholds: the success
 // counts y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  The four waves of
-// a workgroup run four batches over the same simulations: each wave generates a quarter of
-// the Philox blocks of the chunk's 64 simulations into LDS, and every wave reads all 70
-// words.  Rejection at the design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0;
-// checked on the host).
+// a workgroup run the four batches of a 2 x 2 square of the threshold grid over the same
+// simulations: each wave generates a quarter of the Philox blocks of the chunk's 64 simulations
+// into LDS, and each counts one of the square's four sets of 8 thresholds (the two arm-0 row
+// groups, the two arm-1 column groups) over its arm's 35 words, once per simulation; the counts
+// (8 bytes per simulation and set) go through LDS to the two waves whose batches use them.
+// Rejection at the design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0; checked on
+// the host).
+//
+// In calibration mode each lane also writes its simulation's record (Rec2: y0[0..7], y1[0..7] as
+// bytes, 16 bytes; a wave stores 1 KB contiguous per chunk).
 //
 // Per-lane accumulators are packed per tile: bits 0-5 rejections, 6-17 sum of y0 over
 // rejections, 18-29 sum of y1 over rejections; exact for up to 63 simulations per lane
@@ -44,7 +51,7 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
                                                const int32_t *__restrict__ cut_tbl,
                                                uint32_t *__restrict__ R,
                                                unsigned long long *__restrict__ sumT,
-                                               uint16_t *__restrict__ keys) {
+                                               uint4 *__restrict__ recs) {
     constexpr int NT = B2U * B2V;
     constexpr int NW = 2 * NP35;
     constexpr int NB = (NW + 3) / 4;
@@ -54,6 +61,7 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     // flushes the same memory holds the chunk's Philox words.  33 KB: three workgroups per CU.
     __shared__ uint32_t lds[NWAVES][HALF][WAVE + 1];
     __shared__ int32_t s_cut[64];
+    __shared__ uint2 cnt[NWAVES][WAVE];   // per counting set and lane: its 8 counts as bytes
     uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [4*NB][64]
     static_assert(4 * NB * WAVE <= NWAVES * HALF * (WAVE + 1), "word buffer must fit");
 
@@ -64,15 +72,19 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     if (it >= n_items) return;   // uniform over the workgroup
     const GroupItem *__restrict__ G = items + it;
     const int32_t blk = G->blk[wv];   // read in place: a register copy indexed by wv would go to scratch
-    const bool live = blk >= 0;
-    const Blk2 *__restrict__ B = blocks + (live ? blk : G->blk[0]);
+    const bool live = blk >= 0;       // this wave's batch (row group wv >> 1, column group wv & 1)
+    const Blk2 *__restrict__ B = blocks + (live ? blk : 0);   // dereferenced only when live
     const uint32_t kb = G->k_begin, ke = G->k_end;
-    uint32_t T0[B2U], T1[B2V];
+    // counting set of this wave: arm wv >> 1 at the 8 thresholds of group wv & 1, taken from a
+    // block of the square that has them (row group g: blocks 2g, 2g+1; column group g: g, g+2)
+    const int carm = wv >> 1, cg = wv & 1;
+    int32_t csrc = carm == 0 ? G->blk[2 * cg] : G->blk[cg];
+    if (csrc < 0) csrc = carm == 0 ? G->blk[2 * cg + 1] : G->blk[cg + 2];
+    const bool counting = csrc >= 0;   // false: no batch of the square uses this set
+    uint32_t Tc[B2U];
 #pragma unroll
-    for (int u = 0; u < B2U; ++u) T0[u] = B->T0[u];
-#pragma unroll
-    for (int v = 0; v < B2V; ++v) T1[v] = B->T1[v];
-    uint16_t *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
+    for (int u = 0; u < B2U; ++u) Tc[u] = counting ? (carm == 0 ? blocks[csrc].T0[u] : blocks[csrc].T1[u]) : 0u;
+    uint4 *__restrict__ rbase = recs + ((KEYS && live) ? B->key_base : 0);
 
     uint32_t acc[NT];
 #pragma unroll
@@ -114,36 +126,34 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
             words[4 * b + 3][lane] = w.w;
         }
         __syncthreads();
-        int y0[B2U], y1[B2V];
+        {
+            uint32_t yc[B2U];
 #pragma unroll
-        for (int u = 0; u < B2U; ++u) y0[u] = 0;
-#pragma unroll
-        for (int v = 0; v < B2V; ++v) y1[v] = 0;
-        if (live) {
-            // both arms in one loop: independent compares to schedule between each compare and
-            // the add that consumes its mask
+            for (int u = 0; u < B2U; ++u) yc[u] = 0u;
+            if (counting) {
 #pragma unroll 7
-            for (int j = 0; j < NP35; ++j) {
-                const uint32_t x0 = words[j][lane], x1 = words[NP35 + j][lane];
+                for (int j = 0; j < NP35; ++j) {
+                    const uint32_t x = words[carm * NP35 + j][lane];
 #pragma unroll
-                for (int u = 0; u < B2U; ++u) y0[u] += (x0 < T0[u]) ? 1 : 0;
-#pragma unroll
-                for (int v = 0; v < B2V; ++v) y1[v] += (x1 < T1[v]) ? 1 : 0;
+                    for (int u = 0; u < B2U; ++u) yc[u] += (x < Tc[u]) ? 1u : 0u;
+                }
             }
+            cnt[wv][lane] = make_uint2(yc[0] | (yc[1] << 8) | (yc[2] << 16) | (yc[3] << 24),
+                                       yc[4] | (yc[5] << 8) | (yc[6] << 16) | (yc[7] << 24));
         }
-        __syncthreads();   // words consumed: the next chunk (or a flush) may overwrite them
+        __syncthreads();   // words consumed, counts shared: the next chunk (or a flush) may overwrite the words
         if (live) {
+            const uint2 rc = cnt[wv >> 1][lane];        // the batch's row group: arm-0 counts
+            const uint2 cc = cnt[2 + (wv & 1)][lane];   // its column group: arm-1 counts
+            int y0[B2U], y1[B2V];
+#pragma unroll
+            for (int u = 0; u < B2U; ++u) y0[u] = (int)(((u < 4 ? rc.x : rc.y) >> (8 * (u & 3))) & 0xFFu);
+#pragma unroll
+            for (int v = 0; v < B2V; ++v) y1[v] = (int)(((v < 4 ? cc.x : cc.y) >> (8 * (v & 3))) & 0xFFu);
             if (KEYS) {
-                // chunk-major key layout: this chunk's 64 slots are 128-byte rows of one 8 KB
-                // piece.  Every slot and every lane of a chunk has storage (empty slots and the
-                // lanes past N in the last chunk included; the selection ignores them), so the
-                // stores need no test.
-                uint16_t *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * KEY_CHUNK + lane;
-#pragma unroll
-                for (int u = 0; u < B2U; ++u)
-#pragma unroll
-                    for (int v = 0; v < B2V; ++v)
-                        kc[(u * B2V + v) * WAVE] = (uint16_t)(y0[u] * (NP35 + 1) + y1[v]);
+                // the block's records are padded to whole chunks: lanes past N store too (the
+                // selection reads records k < N only)
+                rbase[k] = make_uint4(rc.x, rc.y, cc.x, cc.y);
             }
             // reject indicator r = [y1 >= c(y0)] = med3(y1 - c + 1, 0, 1), added as r * packed
             // (24-bit multiply-add; no compare masks, so nothing is held in scalar registers)
@@ -332,7 +342,7 @@ __global__ __launch_bounds__(WG) void k_ztest1_plain(float theta, float cut, uin
 
 // ------------------------------------------------------------------------------ launchers
 hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
-                         uint16_t *keys, hipStream_t st) {
+                         uint4 *keys, hipStream_t st) {
     const int64_t grid = P.n_gitems;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (keys)

@@ -5,7 +5,7 @@
 namespace cse {
 
 hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
-                         uint16_t *keys, hipStream_t st);
+                         uint4 *recs, hipStream_t st);
 hipError_t launch_ztest1(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumZfx,
                          float *keys, hipStream_t st);
 hipError_t launch_plain_tile(const Platten &P, uint64_t seed, int64_t t, uint32_t T0, uint32_t T1,
@@ -15,11 +15,13 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
                         hipStream_t st);
 hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, double *lam, int32_t *rej_at,
                          hipStream_t st);
-hipError_t launch_min(const double *v, int64_t n, double *out, hipStream_t st);
+hipError_t launch_b2_bracket(const Platten &P, const int32_t *k, hipStream_t st);
+hipError_t launch_min(const Platten &P, const double *v, const int32_t *in_null, int64_t n, double *out,
+                      hipStream_t st);
 hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,
                            uint32_t *c_tile, hipStream_t st);
-hipError_t launch_min_pair(const double *v, const uint32_t *c, int64_t n, double *out_v, uint32_t *out_c,
-                           hipStream_t st);
+hipError_t launch_min_pair(const double *v, const uint32_t *c, const int32_t *in_null, int64_t n, double *out_v,
+                           uint32_t *out_c, hipStream_t st);
 hipError_t launch_confset(const Platten &P, const double *s_obs, int64_t s_stride, const double *lam,
                           const double *coef, int link, int32_t *keep, double *e_lo, double *e_hi,
                           double *e_range, hipStream_t st);

@@ -736,17 +736,22 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
         }
         std::vector<Blk2> blks;
         for (auto &kv : blkmap)
-            for (auto &b : kv.second) blks.push_back(b);
+            for (auto &b : kv.second) {
+                blks.push_back(b);
+                P->blk_row.push_back(std::get<1>(kv.first));
+                P->blk_col.push_back(std::get<2>(kv.first));
+            }
         P->n_blocks = (int64_t)blks.size();
         for (auto &B : blks) {
             blk_sims.push_back(B.n_sims);
+            // one 16-byte record per simulation of the block (chunks of 64, the last one padded)
             B.key_base = P->n_keys;
             for (int j = 0; j < B2U * B2V; ++j)
                 if (B.tile[j] >= 0) {
-                    key_off[B.tile[j]] = B.key_base + (int64_t)j * 64;
-                    key_stride[B.tile[j]] = KEY_CHUNK;
+                    key_off[B.tile[j]] = B.key_base;   // the block's first record
+                    key_stride[B.tile[j]] = j;         // the tile's slot u * 8 + v
                 }
-            P->n_keys += ((int64_t)B.n_sims + 63) / 64 * KEY_CHUNK;
+            P->n_keys += ((int64_t)B.n_sims + 63) / 64 * 64;
         }
         stage.add((Blk2 **)&P->d_blocks, blks.data(), blks.size());
 
@@ -769,15 +774,49 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
                     return CSE_EUNSUPPORTED;
                 }
         }
+        // the calibration selection classifies outcomes by cut points on y1 per y0: S must not
+        // increase with y1 for fixed y0 (so {y1 : S < s} is a suffix for every s)
+        for (int y0 = 0; y0 <= n; ++y0)
+            for (int y1 = 0; y1 < n; ++y1)
+                if (S[y0 * n1 + y1 + 1] > S[y0 * n1 + y1]) {
+                    set_error("internal: the 2-arm statistic is not monotone in y1");
+                    return CSE_EUNSUPPORTED;
+                }
         std::vector<int32_t> order(n1 * n1), group(n1 * n1);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return S[a] < S[b]; });
-        for (int j = 0; j < n1 * n1; ++j)
+        std::vector<int32_t> pos(n1 * n1);
+        for (int j = 0; j < n1 * n1; ++j) {
             group[j] = (j > 0 && S[order[j]] == S[order[j - 1]]) ? group[j - 1] : j;
+            pos[order[j]] = j;
+        }
         stage.add(&P->d_cut_tbl, cut.data(), cut.size());
         stage.add(&P->d_S_tbl, S.data(), S.size());
         stage.add(&P->d_S_order, order.data(), order.size());
         stage.add(&P->d_S_group, group.data(), group.size());
+        stage.add(&P->d_S_pos, pos.data(), pos.size());
+        // tie groups of S in ascending order: first position of each (and n1 * n1 after the
+        // last), and per group g the cut vector cut_g(y0) = #{y1 : S(y0, y1) >= S_g}, so that
+        // S < S_g iff y1 >= cut_g(y0); group n_groups has cut 0 (every outcome below it)
+        {
+            std::vector<int32_t> gstart;
+            for (int j = 0; j < n1 * n1; ++j)
+                if (group[j] == j) gstart.push_back(j);
+            const int ng = (int)gstart.size();
+            std::vector<uint8_t> gcut((size_t)(ng + 1) * n1, 0);
+            for (int g = 0; g < ng; ++g) {
+                const double Sg = S[order[gstart[g]]];
+                for (int y0 = 0; y0 <= n; ++y0) {
+                    int c = 0;
+                    while (c <= n && S[y0 * n1 + c] >= Sg) ++c;
+                    gcut[(size_t)g * n1 + y0] = (uint8_t)c;
+                }
+            }
+            gstart.push_back(n1 * n1);
+            P->n_groups = ng;
+            stage.add(&P->d_gstart, gstart.data(), gstart.size());
+            stage.add(&P->d_gcut, gcut.data(), gcut.size());
+        }
     }
 
     for (int64_t t = 0; t < P->n_tiles; ++t)
@@ -799,6 +838,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     stage.add(&P->d_verts, P->verts.data(), P->verts.size());
     stage.add(&P->d_radii, P->tile_radii.data(), P->tile_radii.size());
     stage.add(&P->d_is_box, P->tile_is_box.data(), P->tile_is_box.size());
+    stage.add(&P->d_in_null, P->tile_in_null.data(), P->tile_in_null.size());
     stage.add(&P->d_key_off, key_off.data(), key_off.size());
     stage.add(&P->d_key_stride, key_stride.data(), key_stride.size());
     // N classes for the Clopper-Pearson table
@@ -835,6 +875,12 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_minpart, MIN_PARTS * sizeof(double)));
+    if (kind == CSE_BINOM2_Z) {
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_b2cut, (size_t)P->n_blocks * B2U * (NP35 + 1) * sizeof(uint4)));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_b2br, nt * sizeof(int2)));
+        CSE_HIP_TRY(hipMalloc((void **)&P->d_b2fb, (nt + 1) * sizeof(uint32_t)));
+    }
     CSE_HIP_TRY(take_side_stream(P->device, &P->side));
     for (hipEvent_t *e : {&P->ev_sim, &P->ev_val, &P->ev_fork, &P->ev_inv})
         CSE_HIP_TRY(hipEventCreateWithFlags(e, hipEventDisableTiming));
@@ -870,18 +916,41 @@ int plan_work_items(Platten *P, int64_t target_waves) {
 // (blocks are ordered by N) whose four waves share the Philox words of a simulation range;
 // ranges sliced so that the grid has about target_wgs workgroups.
 int plan_group_items(Platten *P, int64_t target_wgs) {
-    std::vector<std::vector<int64_t>> groups;
-    for (int64_t b = 0; b < P->n_blocks; ++b) {
-        if (groups.empty() || groups.back().size() == 4 || P->blk_sims[groups.back()[0]] != P->blk_sims[b])
-            groups.push_back({});
-        groups.back().push_back(b);
+    std::vector<std::vector<int64_t>> groups;   // up to 4 blocks each (-1: none)
+    if (P->design.kind == CSE_BINOM2_Z) {
+        // 2 x 2 squares of blocks of equal N: block (row r, column c) goes to position
+        // ((r & 1) << 1) | (c & 1) of square (r >> 1, c >> 1); a second block with the same
+        // coordinates (two tiles at one grid point) opens another square
+        std::map<std::tuple<int64_t, int64_t, int64_t, int64_t>, std::vector<int64_t>> sq;
+        for (int64_t b = 0; b < P->n_blocks; ++b) {
+            const int64_t r = P->blk_row[b], c = P->blk_col[b];
+            const int pos = (int)(((r & 1) << 1) | (c & 1));
+            for (int64_t dup = 0;; ++dup) {
+                auto &g = sq[std::make_tuple(P->blk_sims[b], r >> 1, c >> 1, dup)];
+                if (g.empty()) g.assign(4, -1);
+                if (g[pos] < 0) {
+                    g[pos] = b;
+                    break;
+                }
+            }
+        }
+        for (auto &kv : sq) groups.push_back(kv.second);
+    } else {
+        for (int64_t b = 0; b < P->n_blocks; ++b) {
+            if (groups.empty() || groups.back().size() == 4 || P->blk_sims[groups.back()[0]] != P->blk_sims[b])
+                groups.push_back({});
+            groups.back().push_back(b);
+        }
     }
     const int64_t ng = (int64_t)groups.size();
     const int64_t slices = std::max<int64_t>(1, (target_wgs + ng - 1) / ng);
     std::vector<GroupItem> gi;
     int64_t gs = 0;
     for (auto &g : groups) {
-        const int64_t N = P->blk_sims[g[0]];
+        int64_t first = -1;
+        for (int64_t b : g)
+            if (b >= 0 && first < 0) first = b;
+        const int64_t N = P->blk_sims[first];
         const int64_t chunks = (N + WAVE - 1) / WAVE;
         const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
         for (int64_t k0 = 0; k0 < N; k0 += per) {
@@ -941,7 +1010,7 @@ void free_platten(Platten *P) {
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
                     P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes,
-                    P->d_h4mask};
+                    P->d_h4mask, P->d_S_pos, P->d_b2br, P->d_b2fb, P->d_b2cut, P->d_minpart, P->d_gstart, P->d_gcut};
     auto in_arena = [&](void *q) {
         for (auto &a : P->arenas)
             if ((unsigned char *)q >= (unsigned char *)a.first && (unsigned char *)q < (unsigned char *)a.first + a.second)
