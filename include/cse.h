@@ -154,7 +154,10 @@ int cse_platten_describe(const cse_platten *p, int64_t *box, int32_t *cfg, int32
  *                                  (sum_rej T(x) - R grad A(theta)) / N  (exponential family);
  *                                  PHASE23: (sum_rej y_a - sum_rej n_a expit(theta_a)) / N (the
  *                                  unobserved embedded patients contribute zero in expectation).
- *                                  CSE_HIER4 provides neither (CSE_EUNSUPPORTED).
+ *                                  HIER4 and BASKET4 give score_T [n_tiles][4] (arm success
+ *                                  counts summed over the simulations whose event at the tile's
+ *                                  configuration b holds) and grad as for the binomial designs;
+ *                                  score_Z is ZTEST1 only (CSE_EUNSUPPORTED otherwise).
  * Errors: CSE_EINVAL (NULL reject, bad handle), CSE_EHIP.
  */
 int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *score_T,

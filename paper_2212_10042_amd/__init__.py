@@ -399,10 +399,10 @@ class Platten:
         kind = self.design.kind
         return dict(
             reject=torch.empty(n, dtype=torch.int32, device=dev),
-            score_T=(torch.empty((n, d), dtype=torch.int64, device=dev) if kind == CSE_BINOM2_Z else
-                     torch.empty((n, 2 * d), dtype=torch.int64, device=dev) if kind == CSE_PHASE23 else None),
+            score_T=(torch.empty((n, 2 * d), dtype=torch.int64, device=dev) if kind == CSE_PHASE23 else
+                     torch.empty((n, d), dtype=torch.int64, device=dev) if kind != CSE_ZTEST1 else None),
             score_Z=torch.empty(n, dtype=torch.float64, device=dev) if kind == CSE_ZTEST1 else None,
-            grad=torch.empty((n, d), dtype=torch.float64, device=dev) if kind not in (CSE_HIER4, CSE_BASKET4) else None,
+            grad=torch.empty((n, d), dtype=torch.float64, device=dev),
         )
 
     def simulate(self, seed=0, device="cuda"):

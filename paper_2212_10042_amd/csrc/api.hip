@@ -88,11 +88,13 @@ int noalloc_workspace(int dev, void **out) {
     return CSE_OK;
 }
 
-// The 4-arm design produces rejection counts and calibration keys; score sums are not formed.
+// score_Z is the z-test's score sum; the binomial designs give score_T.
 int check_scores(const cse::Platten &P, const void *score_T, const void *score_Z, const void *grad,
                  const char *fn) {
-    if ((P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) && (score_T || score_Z || grad)) {
-        set_error(std::string(fn) + ": score sums and gradients are not available for CSE_HIER4 and CSE_BASKET4");
+    (void)score_T;
+    (void)grad;
+    if (P.design.kind != CSE_ZTEST1 && score_Z) {
+        set_error(std::string(fn) + ": score_Z is the z-test's score sum (CSE_ZTEST1 only)");
         return CSE_EUNSUPPORTED;
     }
     return CSE_OK;
@@ -159,7 +161,9 @@ void prof_collect() {
 
 // Simulation with the design's fixed rule into the workspaces (R, score sums) and, when `keys` is not
 // NULL, the calibration keys into `keys` (n_keys entries laid out as the platten's key offsets say).
-int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st) {
+// The 4-arm designs form score sums only when `scores` is set (they cost that kernel extra work);
+// the others always do.
+int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st, bool scores = false) {
     CSE_LAUNCH(cse::launch_zero(P.d_Rw, P.n_tiles * sizeof(uint32_t), st));
     if (P.family == cse::FAM_NORMAL) {
         CSE_LAUNCH(cse::launch_zero(P.d_Zw, P.n_tiles * sizeof(unsigned long long), st));
@@ -167,8 +171,9 @@ int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st) {
         CSE_LAUNCH(cse::launch_ztest1(P, seed, P.d_Rw, P.d_Zw, (float *)keys, st));
     } else if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {
         const bool bk = P.design.kind == CSE_BASKET4;
+        if (scores) CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? (bk ? "basket4_calib" : "hier4_calib") : (bk ? "basket4" : "hier4"), st);
-        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, (float *)keys, st));
+        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, scores ? P.d_Tw : nullptr, (float *)keys, st));
     } else if (P.design.kind == CSE_PHASE23) {
         CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * 2 * P.d * sizeof(unsigned long long), st));
         Timed tm(keys ? "phase23_calib" : "phase23", st);
@@ -235,7 +240,7 @@ int check_calibrate(const cse_platten *p, double alpha, double delta, const void
 int validate_impl(const cse::Platten &P, uint64_t seed, double delta, int32_t *reject, int64_t *score_T,
                   double *score_Z, double *grad, double *cp_upper, double *tile_bound, double *q_star,
                   hipStream_t st) {
-    if (int e = run_sim(P, seed, nullptr, st)) return e;
+    if (int e = run_sim(P, seed, nullptr, st, score_T || grad)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
     Timed tm("bound_validate", st);
     CSE_LAUNCH(cse::launch_bound(P, 0, P.d_Rw, nullptr, delta, tile_bound, q_star, nullptr, cp_upper, st));
@@ -275,7 +280,7 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
         }
         if (branch_invert) CSE_HIP_TRY(hipEventRecord(P.ev_inv, is));
     }
-    if (int e = run_sim(P, seed, keys, st)) return e;
+    if (int e = run_sim(P, seed, keys, st, score_T || grad)) return e;
     const bool want_bound = cp_upper || tile_bound;
     if (want_bound) {
         hipStream_t side = P.side;
@@ -386,7 +391,7 @@ int cse_simulate(const cse_platten *p, uint64_t seed, int32_t *reject, int64_t *
     const auto &P = p->P;
     if (int e = check_scores(P, score_T, score_Z, grad, "cse_simulate")) return e;
     hipStream_t st = (hipStream_t)stream;
-    if (int e = run_sim(P, seed, nullptr, st)) return e;
+    if (int e = run_sim(P, seed, nullptr, st, score_T || grad)) return e;
     CSE_LAUNCH(cse::launch_finish(P, P.d_Rw, P.d_Tw, P.d_Zw, reject, score_T, score_Z, grad, st));
     return CSE_OK;
 }

@@ -117,12 +117,20 @@ __device__ __forceinline__ void wave_sync4() {
 // BASKET: the basket design (four hypotheses, arm a <-> bit a, q.w used): every slot holds one
 // piece with a single configuration b, so each lane counts that configuration's events in a
 // plain 32-bit counter per slot (no packed fields, one flush at the end).
-template <bool KEYS, bool BASKET>
+// SCORE: also the score sums of every tile, sum over its rejecting simulations of the arm counts
+// y_a (the sufficient statistic, Example 1).  Rejecting lanes add (y0 | y1 << 16, y2 | y3 << 16)
+// to their tile's row in LDS with LDS atomics (at most 64 * 35 per row and chunk, so the 16-bit
+// fields hold 15 chunks); the rows are added to the 64-bit tile sums in global memory at every
+// flush.  Rows past H4_SROWS (rare batches with many cut boxes) add to global memory directly.
+constexpr int H4_SROWS = 128;
+constexpr uint64_t H4_REJ = 0xFEFCFAF0EECCAA00ull;   // byte m: configurations b (bits 1..7) with m & b != 0
+template <bool KEYS, bool BASKET, bool SCORE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
                                               const float4 *__restrict__ tbl, const uint8_t *__restrict__ mtbl,
-                                              float cut, uint32_t *__restrict__ R, float *__restrict__ keys) {
+                                              float cut, uint32_t *__restrict__ R,
+                                              unsigned long long *__restrict__ sumT, float *__restrict__ keys) {
     constexpr int NP = NP35;
     constexpr int NW = 4 * NP;
     constexpr int NB = NW / 4;   // 35 Philox blocks
@@ -133,6 +141,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     // The chunk's Philox words; between chunks the same memory holds the flush transposes
     // (per wave HALF x (64 + 1) words, padded against bank conflicts).
     __shared__ uint32_t words[NW][WAVE];
+    __shared__ uint2 ysum[SCORE ? NWAVES : 1][SCORE ? H4_SROWS : 1];   // per wave and key row: packed y sums
     static_assert(NWAVES * HALF * (WAVE + 1) <= NW * WAVE, "flush transposes must fit in the word buffer");
     uint32_t(*tr)[HALF][WAVE + 1] = reinterpret_cast<uint32_t(*)[HALF][WAVE + 1]>(&words[0][0]);
 
@@ -156,6 +165,43 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     for (int u = 0; u < B4N3; ++u) T3[u] = B->T3[u];
     const int32_t n_rows = B->n_rows;
     float *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
+
+    if (SCORE)
+        for (int r = lane; r < H4_SROWS; r += WAVE) ysum[wv][r] = make_uint2(0u, 0u);
+    // a rejecting simulation's counts into its tile's row (LDS) or, past the LDS rows, its tile
+    auto add_score = [&](int32_t row, int32_t tile, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+        if (row < H4_SROWS) {
+            atomicAdd(&ysum[wv][row].x, a | (b << 16));
+            atomicAdd(&ysum[wv][row].y, c | (d << 16));
+        } else {
+            atomicAdd(&sumT[4 * (int64_t)tile + 0], (unsigned long long)a);
+            atomicAdd(&sumT[4 * (int64_t)tile + 1], (unsigned long long)b);
+            atomicAdd(&sumT[4 * (int64_t)tile + 2], (unsigned long long)c);
+            atomicAdd(&sumT[4 * (int64_t)tile + 3], (unsigned long long)d);
+        }
+    };
+    // the LDS rows into the tiles' 64-bit sums (lanes take a slot's rows), then cleared
+    auto flush_scores = [&]() {
+        wave_sync4();
+        for (int s = 0; s < B4S; ++s) {
+            const int32_t r0 = B->row0[s];
+            if (r0 < 0) continue;   // uniform
+            const int nq = BASKET ? 1 : __popc(B->bmask[s]);
+            const int r = r0 + lane;
+            if (lane < nq && r < H4_SROWS) {
+                const uint2 v = ysum[wv][r];
+                if (v.x | v.y) {
+                    const int64_t t = (int64_t)B->tile0[s] + lane;
+                    atomicAdd(&sumT[4 * t + 0], (unsigned long long)(v.x & 0xFFFFu));
+                    atomicAdd(&sumT[4 * t + 1], (unsigned long long)(v.x >> 16));
+                    atomicAdd(&sumT[4 * t + 2], (unsigned long long)(v.y & 0xFFFFu));
+                    atomicAdd(&sumT[4 * t + 3], (unsigned long long)(v.y >> 16));
+                    ysum[wv][r] = make_uint2(0u, 0u);
+                }
+            }
+        }
+        wave_sync4();
+    };
 
     // per slot: seven 4-bit counters, field m-1 counting the simulations with rejection mask m
     uint32_t acc[B4S];
@@ -274,6 +320,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
                                 acc[s] += (m & b) ? 1u : 0u;
+                                if (SCORE && (m & b))
+                                    add_score(row0, B->tile0[s], (uint32_t)y0[u0], (uint32_t)y1[u1], (uint32_t)y2[u2],
+                                              (uint32_t)y3[u3]);
                                 if (KEYS) {
                                     float sb = INFINITY;
                                     if (b & 1u) sb = fminf(sb, q.x);
@@ -285,6 +334,19 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                                 continue;
                             }
                             acc[s] += m ? (1u << (4u * (m - 1u))) : 0u;
+                            if (SCORE) {
+                                // the box's configurations b whose event m & b != 0 happened: byte m of
+                                // H4_REJ has bit b set when m & b != 0
+                                const uint32_t bm = B->bmask[s];
+                                uint32_t rej = (uint32_t)(H4_REJ >> (8u * m)) & bm;
+                                while (rej) {
+                                    const uint32_t b = (uint32_t)__builtin_ctz(rej);
+                                    rej &= rej - 1u;
+                                    const int q = __popc(bm & ((1u << b) - 1u));   // the tile's rank in the box
+                                    add_score(row0 + q, B->tile0[s] + q, (uint32_t)y0[u0], (uint32_t)y1[u1],
+                                              (uint32_t)y2[u2], (uint32_t)y3[u3]);
+                                }
+                            }
                             if (KEYS) {
                                 const uint32_t bm = B->bmask[s];
                                 int row = row0;
@@ -301,12 +363,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             }
                         }
         }
-        if (!BASKET && ++since == FLUSH_EVERY) {   // basket counters are plain 32-bit
-            flush();
+        if (++since == FLUSH_EVERY) {   // basket counters are plain 32-bit: only the score rows
+            if (!BASKET) flush();
+            if (SCORE && live) flush_scores();
             since = 0;
         }
     }
     flush();
+    if (SCORE && live) flush_scores();
     if (!live) return;
     // totals of slot s: lanes s & 31 and (s & 31) + 32 each hold half of the lanes' counts
 #pragma unroll
@@ -339,21 +403,29 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
 }
 
-hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st) {
+hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
+                        hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const float cut = (float)P.design.cut;
     const bool basket = P.design.kind == CSE_BASKET4;
-#define CSE_H4_LAUNCH(K, BK)                                                                                \
-    hipLaunchKernelGGL((k_hier4<K, BK>), dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
-                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, P.d_h4mask, cut, R, keys)
-    if (keys && basket)
-        CSE_H4_LAUNCH(true, true);
-    else if (keys)
-        CSE_H4_LAUNCH(true, false);
-    else if (basket)
-        CSE_H4_LAUNCH(false, true);
-    else
-        CSE_H4_LAUNCH(false, false);
+#define CSE_H4_LAUNCH(K, BK, SC)                                                                                  \
+    hipLaunchKernelGGL((k_hier4<K, BK, SC>), dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
+                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, P.d_h4mask, cut, R, sumT, keys)
+#define CSE_H4_SC(K, BK)            \
+    if (sumT)                       \
+        CSE_H4_LAUNCH(K, BK, true); \
+    else                            \
+        CSE_H4_LAUNCH(K, BK, false)
+    if (keys && basket) {
+        CSE_H4_SC(true, true);
+    } else if (keys) {
+        CSE_H4_SC(true, false);
+    } else if (basket) {
+        CSE_H4_SC(false, true);
+    } else {
+        CSE_H4_SC(false, false);
+    }
+#undef CSE_H4_SC
 #undef CSE_H4_LAUNCH
     return hipGetLastError();
 }

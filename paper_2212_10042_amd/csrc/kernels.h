@@ -34,7 +34,8 @@ hipError_t launch_taylor(const Platten &P, const double *f, const double *g, dou
 hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st);
 hipError_t launch_h4_mask(const float4 *tbl, int64_t n, float cut, int nbits, uint8_t *mask, hipStream_t st);
 hipError_t launch_basket_table(int n, const double *theta0, float4 *tbl, const HierNode *nodes, hipStream_t st);
-hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, float *keys, hipStream_t st);
+hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
+                        hipStream_t st);
 hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
                           hipStream_t st);
 hipError_t launch_p23_look1(const Platten &P, hipStream_t st);

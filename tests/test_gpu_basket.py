@@ -60,6 +60,11 @@ def _compare(w, seed, theta0=None, cut=0.15):
     ov = O.validate("basket4", th, rd, sm, seed, w["delta"], cut=cut, theta0=theta0)
     oc = O.calibrate("basket4", th, rd, sm, seed, w["alpha"], cut=cut, key_dtype=np.float32, theta0=theta0)
     assert np.array_equal(_np(g["reject"]), ov["R"])
+    # score sums (sum over rejecting simulations of the arm counts) and the score gradient
+    assert np.array_equal(_np(g["score_T"]), ov["score"])
+    cen = np.array([q[2] for q in pieces])
+    go = O.score_gradient("basket4", cen, ov["R"], ov["score"], ov["N"])
+    np.testing.assert_allclose(_np(g["grad"]), go, rtol=1e-12, atol=1e-15)
     np.testing.assert_allclose(_np(g["cp_upper"]), ov["cp"], rtol=1e-9)
     np.testing.assert_allclose(_np(g["tile_bound"]), ov["bound"], rtol=1e-9)
     np.testing.assert_allclose(_np(g["alpha_prime"]), oc["alpha_prime"], rtol=1e-9)
@@ -100,8 +105,13 @@ def test_per_tile_path_and_determinism():
     torch.cuda.synchronize()
     assert torch.equal(a["reject"], b["reject"]) and torch.equal(R, a["reject"])
     assert int(R.sum()) > 0
-    with pytest.raises(cse.CseError):
-        cse.cse_simulate(P.handle, 5, R, None, None, torch.empty((P.n_tiles, 4), dtype=torch.float64, device="cuda"))
+    # the pass without score sums decides exactly as the pass with them
+    R2 = torch.empty_like(R)
+    cse.cse_simulate(P.handle, 5, R2)
+    torch.cuda.synchronize()
+    assert torch.equal(R2, R)
+    with pytest.raises(cse.CseError):   # the z-test score is not a basket output
+        cse.cse_simulate(P.handle, 5, R, None, torch.empty(P.n_tiles, dtype=torch.float64, device="cuda"))
     P.close()
 
 

@@ -86,6 +86,12 @@ def test_posterior_table_exchangeability(table):
     np.testing.assert_allclose(T[..., 0], 1.0 - np.transpose(T[..., 0], (1, 0, 2, 3)), rtol=0, atol=3e-7)
 
 
+def _counts(idx):
+    """Arm counts (y0, y1, y2, y3) of outcome indices ((y0 m + y1) m + y2) m + y3."""
+    idx = np.asarray(idx, np.int64)
+    return np.stack([(idx // M**3) % M, (idx // M**2) % M, (idx // M) % M, idx % M], axis=-1)
+
+
 def _decide32(S, cut):
     """float32 decisions / keys from the oracle's float64 statistic."""
     return S.astype(np.float32), np.float32(cut)
@@ -103,11 +109,16 @@ def _compare(w, seed, cut=0.05):
     torch.cuda.synchronize()
     box = np.array([s[0] for s in subs])
     cfg = np.array([s[1] for s in subs], np.int32)
-    _, _, S, _ = O.sim_hier4(th[box], cfg, sm[box], seed, cut, want_S=True)
+    _, _, S, Y = O.sim_hier4(th[box], cfg, sm[box], seed, cut, want_S=True)
     S32, c32 = _decide32(S, cut)
     N = sm[box]
     R = np.array([np.sum(S32[t, : N[t]] < c32) for t in range(len(subs))])
     assert np.array_equal(_np(g["reject"]), R)
+    # score sums over the rejecting simulations (float32 decisions), and the score gradient
+    sT = np.array([_counts(Y[t, : N[t]][S32[t, : N[t]] < c32]).sum(0) for t in range(len(subs))]).reshape(-1, 4)
+    assert np.array_equal(_np(g["score_T"]), sT)
+    go = O.score_gradient("hier4", th[box], R, sT, N)
+    np.testing.assert_allclose(_np(g["grad"]), go, rtol=1e-12, atol=1e-15)
     cp = O.cp_upper(R, N, w["delta"])
     V = O._pad_vertices(subs, th)
     ub, _ = O.tile_bound("binom", th[box], V, cp)
@@ -140,7 +151,7 @@ def test_hier4_full_workload_sampled_tiles(oracle_table):
     """16^4 boxes on [-1,1]^4, 32,768 sims per tile (the calibration workload): every tile of >= 40
     sampled boxes (some cut by the null hyperplanes) against the oracle, with the strict rule:
     k equal unless (N+1) alpha' is within 1e-7 of an integer, then lambda*_i, #{S < lambda*_i},
-    the rejection count at the cut, cp_upper and the tile bound."""
+    the rejection count at the cut, its score sums and gradient, cp_upper and the tile bound."""
     w = W.hier4_16()
     th, rd, sm = w["theta"], w["radii"], w["sims"]
     P = cse.Platten.create("hier4", th, rd, sm)
@@ -162,16 +173,22 @@ def test_hier4_full_workload_sampled_tiles(oracle_table):
     assert len(ids) == int(counts[boxes].sum()) and len(ids) >= 40
     N = sub["sims"][[s_[0] for s_ in subs]]
     m = M
-    stat = {}
+    stat, ys = {}, {}
     for j in range(len(boxes)):   # the oracle's arm counts per simulation and its table
         Y = O.arm_counts(sub["theta"][j], int(sub["sims"][j]), w["seed"]).astype(np.int64)
         stat[j] = oracle_table[((Y[:, 0] * m + Y[:, 1]) * m + Y[:, 2]) * m + Y[:, 3]]
+        ys[j] = Y
     S32 = []
     for j, b, *_ in subs:
         cols = [i - 1 for i in (1, 2, 3) if (b >> (i - 1)) & 1]
         S32.append(stat[j][:, cols].min(axis=1).astype(np.float32))
     R = np.array([np.sum(x < np.float32(cut)) for x in S32])
     assert np.array_equal(_np(g["reject"])[ids], R)
+    # score sums of the sampled tiles from the oracle's arm counts at their rejecting simulations
+    sT = np.array([ys[s_[0]][S32[t] < np.float32(cut)].sum(0) for t, s_ in enumerate(subs)])
+    assert np.array_equal(_np(g["score_T"])[ids], sT)
+    go = O.score_gradient("hier4", sub["theta"][[s_[0] for s_ in subs]], R, sT, N)
+    np.testing.assert_allclose(_np(g["grad"])[ids], go, rtol=1e-12, atol=1e-15)
     cp = O.cp_upper(R, N, w["delta"])
     V = O._pad_vertices(subs, sub["theta"])
     cen = sub["theta"][[s_[0] for s_ in subs]]
