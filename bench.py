@@ -45,7 +45,8 @@ VALU_PEAK = 256 * 4 * 64 * 2.4e9 / 4   # lane-ops/s: 256 CUs x 4 SIMDs x one wav
 B2_PHILOX, B2_COUNT_G, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 4 * 8 * 35 * 2, 4, 4
 #   4-arm: per (workgroup, simulation) 35 Philox blocks; per (batch, simulation) 35 words x
 #   (4 + 4 + 2 + 2) thresholds x (compare + add); per (simulation, box) outcome index (3),
-#   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store.
+#   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store
+#   (the score sums add per rejecting simulation only, a few % of the simulations).
 H4_PHILOX, H4_COUNT, H4_BOX, H4_TILE = 35 * 10 * 4, 35 * 12 * 2, 9, 3
 #   basket (the same kernel, one configuration per slot): per (simulation, piece) outcome index
 #   (3), table gather (1), 4 compares, mask, event test, accumulate.
@@ -511,10 +512,10 @@ def measure(name, w, design, args, full=True):
         box_sims = int(np.asarray(w["sims"])[boxes].sum())
         ops = (st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + box_sims * H4_BOX
                + st["total_sims"] * H4_TILE)
-        kname = "k_hier4<KEYS=true>"
+        kname = "k_hier4<KEYS=true, BASKET=false, SCORE=true>"
     elif design == "basket4":
         ops = st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + st["total_sims"] * BK_SLOT
-        kname = "k_hier4<KEYS=false, BASKET=true>"
+        kname = "k_hier4<KEYS=false, BASKET=true, SCORE=true>"
     elif design == "phase23":
         wc = cse.cse_work_counters(P.handle)
         ops = (wc["looks_phase2"] * (90 * P23_NODE + P23_P2_EXTRA)

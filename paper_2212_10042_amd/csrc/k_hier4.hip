@@ -118,11 +118,27 @@ __device__ __forceinline__ void wave_sync4() {
 // piece with a single configuration b, so each lane counts that configuration's events in a
 // plain 32-bit counter per slot (no packed fields, one flush at the end).
 // SCORE: also the score sums of every tile, sum over its rejecting simulations of the arm counts
-// y_a (the sufficient statistic, Example 1).  Rejecting lanes add (y0 | y1 << 16, y2 | y3 << 16)
-// to their tile's row in LDS with LDS atomics (at most 64 * 35 per row and chunk, so the 16-bit
-// fields hold 15 chunks); the rows are added to the 64-bit tile sums in global memory at every
-// flush.  Rows past H4_SROWS (rare batches with many cut boxes) add to global memory directly.
+// y_a (the sufficient statistic, Example 1), as packed pairs (y0 | y1 << 16, y2 | y3 << 16),
+// added to the tile's row in LDS with LDS atomics.  4-arm lanes add their own pairs (rejections
+// are rare at that design's cut).  Basket slots, where most simulations of a piece may reject, do
+// so only when a few lanes reject; otherwise the pairs are first summed over each 16-lane row by
+// DPP shifts and the four row totals are added (atomics of many lanes to one LDS word
+// serialise).  At most 64 * 35 per row and
+// chunk, so the 16-bit fields hold 15 chunks; the rows are added to the 64-bit tile sums in global
+// memory at every flush.  Rows past H4_SROWS (rare batches with many cut boxes) add to global
+// memory directly.
 constexpr int H4_SROWS = 128;
+constexpr int H4_FEW = 4;   // at most this many rejecting lanes: atomics straight from the lanes
+
+// Inclusive scan over the 16 lanes of each DPP row by row shifts of 1, 2, 4, 8 (shifted-in lanes
+// read 0): lane 15 of each row ends with the row's total.  Call with every lane active.
+__device__ __forceinline__ uint32_t row16_sum(uint32_t v) {
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);   // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);   // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);   // row_shr:8
+    return v;
+}
 constexpr uint64_t H4_REJ = 0xFEFCFAF0EECCAA00ull;   // byte m: configurations b (bits 1..7) with m & b != 0
 template <bool KEYS, bool BASKET, bool SCORE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
@@ -168,8 +184,20 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 
     if (SCORE)
         for (int r = lane; r < H4_SROWS; r += WAVE) ysum[wv][r] = make_uint2(0u, 0u);
-    // a rejecting simulation's counts into its tile's row (LDS) or, past the LDS rows, its tile
-    auto add_score = [&](int32_t row, int32_t tile, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
+    // packed count pairs into a tile's row (LDS) or, past the LDS rows, its 64-bit sums
+    auto add_pairs = [&](int32_t row, int32_t tile, uint32_t lo, uint32_t hi) {
+        if (row < H4_SROWS) {
+            atomicAdd(&ysum[wv][row].x, lo);
+            atomicAdd(&ysum[wv][row].y, hi);
+        } else {
+            atomicAdd(&sumT[4 * (int64_t)tile + 0], (unsigned long long)(lo & 0xFFFFu));
+            atomicAdd(&sumT[4 * (int64_t)tile + 1], (unsigned long long)(lo >> 16));
+            atomicAdd(&sumT[4 * (int64_t)tile + 2], (unsigned long long)(hi & 0xFFFFu));
+            atomicAdd(&sumT[4 * (int64_t)tile + 3], (unsigned long long)(hi >> 16));
+        }
+    };
+    // one lane's counts (y0, y1, y2, y3) into a tile's sums
+    auto add_counts = [&](int32_t row, int32_t tile, uint32_t a, uint32_t b, uint32_t c, uint32_t d) {
         if (row < H4_SROWS) {
             atomicAdd(&ysum[wv][row].x, a | (b << 16));
             atomicAdd(&ysum[wv][row].y, c | (d << 16));
@@ -179,6 +207,17 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             atomicAdd(&sumT[4 * (int64_t)tile + 2], (unsigned long long)c);
             atomicAdd(&sumT[4 * (int64_t)tile + 3], (unsigned long long)d);
         }
+    };
+    // the counts of the lanes whose simulation rejects (ev) into the tile's sums; every lane calls
+    auto add_score = [&](bool ev, int32_t row, int32_t tile, uint32_t lo, uint32_t hi) {
+        const unsigned long long bal = __ballot(ev);
+        if (!bal) return;
+        if (__popcll(bal) <= H4_FEW) {
+            if (ev) add_pairs(row, tile, lo, hi);
+            return;
+        }
+        const uint32_t a = row16_sum(ev ? lo : 0u), b = row16_sum(ev ? hi : 0u);
+        if ((lane & 15) == 15 && (a | b)) add_pairs(row, tile, a, b);
     };
     // the LDS rows into the tiles' 64-bit sums (lanes take a slot's rows), then cleared
     auto flush_scores = [&]() {
@@ -320,9 +359,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
                                 acc[s] += (m & b) ? 1u : 0u;
-                                if (SCORE && (m & b))
-                                    add_score(row0, B->tile0[s], (uint32_t)y0[u0], (uint32_t)y1[u1], (uint32_t)y2[u2],
-                                              (uint32_t)y3[u3]);
+                                if (SCORE)
+                                    add_score((m & b) != 0u, row0, B->tile0[s], (uint32_t)(y0[u0] | (y1[u1] << 16)),
+                                              (uint32_t)(y2[u2] | (y3[u3] << 16)));
                                 if (KEYS) {
                                     float sb = INFINITY;
                                     if (b & 1u) sb = fminf(sb, q.x);
@@ -336,15 +375,16 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                             acc[s] += m ? (1u << (4u * (m - 1u))) : 0u;
                             if (SCORE) {
                                 // the box's configurations b whose event m & b != 0 happened: byte m of
-                                // H4_REJ has bit b set when m & b != 0
+                                // H4_REJ has bit b set when m & b != 0.  Rejections are rare at the 4-arm
+                                // design's cut, so the lanes add their own counts.
                                 const uint32_t bm = B->bmask[s];
                                 uint32_t rej = (uint32_t)(H4_REJ >> (8u * m)) & bm;
                                 while (rej) {
                                     const uint32_t b = (uint32_t)__builtin_ctz(rej);
                                     rej &= rej - 1u;
                                     const int q = __popc(bm & ((1u << b) - 1u));   // the tile's rank in the box
-                                    add_score(row0 + q, B->tile0[s] + q, (uint32_t)y0[u0], (uint32_t)y1[u1],
-                                              (uint32_t)y2[u2], (uint32_t)y3[u3]);
+                                    add_counts(row0 + q, B->tile0[s] + q, (uint32_t)y0[u0], (uint32_t)y1[u1],
+                                               (uint32_t)y2[u2], (uint32_t)y3[u3]);
                                 }
                             }
                             if (KEYS) {
