@@ -62,9 +62,13 @@ BK_SLOT = 11
 P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800, 100
 
 # HBM bytes per dispatch of the dominant kernel, by workload, from FETCH_SIZE + WRITE_SIZE counter
-# runs (profiles/*_hbm_counters.md, scaled by a copy of known size).  Valid only while that
-# kernel is unchanged; workloads not listed report null.
-TRAFFIC = {}
+# runs (profiles/<workload>_counters.md, scaled by what the counters read for a copy of known
+# size).  Valid only while that kernel is unchanged; workloads not listed report null.
+TRAFFIC = {
+    "binom2_1024_full": 4_343_206_424,   # k_binom2<true>: 10.5 MB read, 4,332.7 MB written (records)
+    "hier4_16": 12_532_581_389,          # k_hier4<true, false, true>: 4,459.6 MB read, 8,073.0 MB written
+    "phase23_c5_sub256": 1_624_933_596,  # k_phase23: 228.5 MB read, 1,396.4 MB written
+}
 
 DEFAULT = "binom2_1024_full"
 SUB_RECORDS = ("binom2_256_tri", "hier4_16")

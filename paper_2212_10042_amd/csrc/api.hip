@@ -628,15 +628,19 @@ int cse_autotune(cse_platten *p, uint64_t seed, int64_t max_trials, int64_t out[
     // one-wave-per-block (z-test) or group kernels (2-arm, 4-arm): time the calibration launch
     if (int e = ensure_keys(P)) return e;
     const bool group = P.design.kind == CSE_BINOM2_Z || P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4;
-    const int64_t cands[5] = {1024, 2048, 4096, 8192, 16384};
-    const int64_t wave_cands[5] = {4096, 8192, 16384, 32768, 65536};
+    const int64_t cands[7] = {1024, 2048, 4096, 8192, 16384, 32768, 65536};
+    const int64_t wave_cands[7] = {4096, 8192, 16384, 32768, 65536, 131072, 262144};
     float best = 3.4e38f;
     int64_t bv = group ? P.tune_wgs : P.tune_waves;
-    for (int i = 0; i < 5; ++i) {
+    for (int i = 0; i < 7; ++i) {
         const int64_t v = group ? cands[i] : wave_cands[i];
         if (int e = group ? cse::plan_group_items(&P, v) : cse::plan_work_items(&P, v)) return e;
-        float ms = 0.0f;
+        // the calibration launch (keys) and the validation launch (no keys) together: the
+        // best shape of one need not be the best of the other
+        float ms = 0.0f, ms_val = 0.0f;
         if (int e = timeit([&]() { return run_sim(P, seed, P.d_keys, st); }, 3, &ms)) return e;
+        if (int e = timeit([&]() { return run_sim(P, seed, nullptr, st); }, 3, &ms_val)) return e;
+        ms += ms_val;
         if (ms < best) {
             best = ms;
             bv = v;

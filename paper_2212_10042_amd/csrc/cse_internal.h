@@ -175,7 +175,7 @@ struct Platten {
     int32_t p23_chunk = 256;             // simulations per queue item
     // launch shapes (cse_autotune): waves of the one-wave-per-block kernels, workgroups of the
     // group kernels
-    int64_t tune_waves = 16384, tune_wgs = 4096;
+    int64_t tune_waves = 16384, tune_wgs = 16384;
     std::vector<int64_t> blk_sims;       // simulations of each block
     std::vector<int64_t> blk_row, blk_col;   // 2-arm: each block's row / column group of 8 thresholds
     std::vector<int64_t> p23_item_off;   // [n_tiles + 1] first queue item of each tile

@@ -944,6 +944,9 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
     }
     const int64_t ng = (int64_t)groups.size();
     const int64_t slices = std::max<int64_t>(1, (target_wgs + ng - 1) / ng);
+    // at least 4 chunks of 64 simulations per item: an item's fixed work (thresholds, the final
+    // transposes and atomics) then stays small beside its simulations
+    constexpr int64_t MIN_ITEM_CHUNKS = 4;
     std::vector<GroupItem> gi;
     int64_t gs = 0;
     for (auto &g : groups) {
@@ -952,7 +955,7 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
             if (b >= 0 && first < 0) first = b;
         const int64_t N = P->blk_sims[first];
         const int64_t chunks = (N + WAVE - 1) / WAVE;
-        const int64_t per = std::max<int64_t>(1, (chunks + slices - 1) / slices) * WAVE;
+        const int64_t per = std::max<int64_t>(MIN_ITEM_CHUNKS, (chunks + slices - 1) / slices) * WAVE;
         for (int64_t k0 = 0; k0 < N; k0 += per) {
             GroupItem it{};
             for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;

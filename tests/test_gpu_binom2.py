@@ -277,3 +277,31 @@ def test_full_c3_forward_gradient_sampled_and_fd():
         print(f"[binom2] FD vs score, arm {a}: mean diff {d.mean():.2e}, z {z:.2f} over {m} tiles", flush=True)
         assert abs(z) < 5
     Q.close()
+
+
+def test_bound_search_paths_agree():
+    """The float64 search over q takes eight lanes per tile (a parallel section search) on
+    plattens below 2^18 tiles and one lane per tile (golden section) from 2^18 tiles on.  Each
+    returns the best point it evaluated; on the same tiles alpha' (inversion) and the
+    validation bound agree within 1e-9 relative."""
+    w = W.binom2_grid(512, 1000, lower_triangle=False)
+    P = cse.Platten.create("binom2", w["theta"], w["radii"], w["sims"], keep_all=True)
+    assert P.n_tiles >= 1 << 18
+    idx = np.arange(0, w["theta"].shape[0], 97)
+    s = W.subsample(w, idx)
+    Q = cse.Platten.create("binom2", s["theta"], s["radii"], s["sims"], keep_all=True)
+    assert Q.n_tiles < 1 << 18
+    print(f"[binom2] bound search paths: {P.n_tiles} vs {Q.n_tiles} tiles", flush=True)
+    bp, bq = P.tiles["box"], Q.tiles["box"]
+    assert np.array_equal(bp, np.arange(P.n_tiles)) and np.array_equal(bq, np.arange(Q.n_tiles))
+    ap, _ = P.bound(1, level=0.025)
+    aq, _ = Q.bound(1, level=0.025)
+    Rp = torch.tensor((np.arange(P.n_tiles) * 7) % 100, dtype=torch.int32, device="cuda")
+    Rq = torch.tensor((idx * 7) % 100, dtype=torch.int32, device="cuda")
+    up, _ = P.bound(0, R=Rp, level=0.01)
+    uq, _ = Q.bound(0, R=Rq, level=0.01)
+    torch.cuda.synchronize()
+    np.testing.assert_allclose(_np(ap)[idx], _np(aq), rtol=1e-9)
+    np.testing.assert_allclose(_np(up)[idx], _np(uq), rtol=1e-9)
+    P.close()
+    Q.close()
