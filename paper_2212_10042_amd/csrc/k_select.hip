@@ -470,12 +470,18 @@ __device__ void radix_kth(int n, uint32_t k, Get get, uint32_t *hist, uint32_t *
 // LDS.  Larger tiles: the first SEL_SAMPLE simulations (i.i.d. draws of the statistic) give
 // sample order statistics lo, hi that bracket rank k/N with a margin of z binomial standard
 // deviations (z = 5, lowered to no less than 3 where the expected number of keys in the
-// bracket would exceed 60% of the SEL_CAND candidate slots); one pass over
-// the tile's keys counts those below lo and gathers those in [lo, hi] into LDS; if the k-th
-// smallest lies among them it is selected there, else the exact radix passes run over HBM.
-// Either way the result is the exact k-th smallest key.
+// bracket would exceed SEL_FILL of the SEL_CAND candidate slots); one pass over the tile's
+// keys counts those below lo and keeps those in [lo, hi] in per-thread LDS slots, compacted
+// afterwards; if the k-th smallest lies among them it is selected there, else (bracket missed,
+// a thread's slots or the candidate buffer full) the exact radix passes run over HBM.  Either
+// way the result is the exact k-th smallest key.
 constexpr int SEL_SAMPLE = 2048;
 constexpr int SEL_CAND = 2048;
+// candidate slots per thread in the pass over the tile (the last one takes the keys outside the
+// bracket), and the share of SEL_CAND the bracket aims to fill: at 0.45 a thread of a
+// 32,768-key tile expects 3.6 bracket keys, and more than 15 has probability ~1e-7
+constexpr int SEL_TSLOTS = 16;
+constexpr double SEL_FILL = 0.45;
 
 template <bool VEC4>
 __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__ keys,
@@ -485,12 +491,15 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
                                                        const int32_t *__restrict__ kk,
                                                        double *__restrict__ lam,
                                                        int32_t *__restrict__ rej_at) {
-    __shared__ uint32_t hist[2048];
+    // hist (radix passes) and the per-thread candidate slots of the pass over the tile share
+    // one buffer: the pass runs between the bracket's radix passes and the final one
+    __shared__ uint32_t hist_slots[SEL_TSLOTS * SEL_WG > 2048 ? SEL_TSLOTS * SEL_WG : 2048];
+    uint32_t *const hist = hist_slots, *const slots = hist_slots;
     __shared__ uint32_t part[SEL_WG];
     // the sample is used up (bracket chosen) before the pass fills the candidates: one buffer
     __shared__ uint32_t samp_cand[SEL_CAND > SEL_SAMPLE ? SEL_CAND : SEL_SAMPLE];
     uint32_t *const samp = samp_cand, *const cand = samp_cand;
-    __shared__ uint32_t s_bin, s_below, s_cnt, s_lt;
+    __shared__ uint32_t s_bin, s_below, s_lt, s_over;
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
     const int lane = tid & (WAVE - 1);
@@ -523,7 +532,7 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
         const double pr = (double)k / (double)n;
         const double sd = sqrt((double)m * pr * (1.0 - pr));
         // expected keys in the bracket: n (2 z sd + 2) / m
-        const double z_fit = (0.6 * SEL_CAND * m / (double)n - 2.0) / (2.0 * sd);
+        const double z_fit = (SEL_FILL * SEL_CAND * m / (double)n - 2.0) / (2.0 * sd);
         const double z = fmin(5.0, fmax(3.0, z_fit));
         const int lo_r = (int)floor(pr * m - z * sd) - 1;   // sample ranks (1-based) of the bracket
         const int hi_r = (int)ceil(pr * m + z * sd) + 1;
@@ -536,29 +545,26 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
             hi |= 0x3FFu;
         }
         if (tid == 0) {
-            s_cnt = 0u;
             s_lt = 0u;
+            s_over = 0u;
         }
         __syncthreads();
-        // one pass over the tile: count below the bracket, gather the bracket into LDS.  Each
+        // one pass over the tile: count below the bracket, keep the bracket's keys.  Each
         // thread loads a batch of keys before using any (many loads in flight; with VEC4 the
-        // tile's 64-key chunks are 256-byte aligned and read as float4), and the trip count is
-        // uniform so that every lane takes part in the ballots.
-        uint32_t lt = 0u;
+        // tile's 64-key chunks are 256-byte aligned and read as float4).  Every key is written,
+        // without a branch, to the thread's next free slot when it lies in the bracket and to
+        // the thread's last slot (scratch) otherwise; a thread with more than SEL_TSLOTS - 1
+        // bracket keys sends the tile to the exact path.
+        uint32_t lt = 0u, nin = 0u;
         auto take = [&](uint32_t u, bool valid) {
             lt += (valid && u < lo) ? 1u : 0u;
-            const bool in = valid && u >= lo && u <= hi;
-            const unsigned long long bal = __ballot(in);
-            if (bal) {   // uniform
-                uint32_t base = 0u;
-                if (lane == 0) base = atomicAdd(&s_cnt, (uint32_t)__popcll(bal));
-                base = __shfl(base, 0);
-                const uint32_t pos = base + (uint32_t)__popcll(bal & ((1ull << lane) - 1ull));
-                if (in && pos < (uint32_t)SEL_CAND) cand[pos] = u;
-            }
+            const bool in = valid && u - lo <= hi - lo;
+            const uint32_t sl = (in && nin < (uint32_t)(SEL_TSLOTS - 1)) ? nin : (uint32_t)(SEL_TSLOTS - 1);
+            slots[sl * SEL_WG + tid] = u;
+            nin += in ? 1u : 0u;
         };
         if (VEC4) {
-            constexpr int QB = 8;   // float4 per thread per round: 32 keys
+            constexpr int QB = 4;   // float4 per thread per round: 16 keys
             const int nq = ((n + 63) >> 6) * 16;
             for (int q0 = 0; q0 < nq; q0 += SEL_WG * QB) {
                 float4 v[QB];
@@ -592,8 +598,17 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
         }
         for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
         if (lane == 0) atomicAdd(&s_lt, lt);
+        if (nin > (uint32_t)(SEL_TSLOTS - 1)) s_over = 1u;
+        // the threads' bracket keys, compacted into the candidate buffer in thread order
+        const uint32_t mine = nin < (uint32_t)(SEL_TSLOTS - 1) ? nin : (uint32_t)(SEL_TSLOTS - 1);
+        block_exclusive_scan(mine, part);   // synchronises: s_lt and s_over are complete after it
+        const uint32_t off = part[tid];
+        if (tid == SEL_WG - 1) s_bin = off + mine;   // total, through a spare word
         __syncthreads();
-        const uint32_t nc = s_cnt, nlt = s_lt;
+        const uint32_t nc = s_over ? 0xFFFFFFFFu : s_bin, nlt = s_lt;
+        if (nc <= (uint32_t)SEL_CAND)
+            for (uint32_t j = 0; j < mine; ++j) cand[off + j] = slots[j * SEL_WG + tid];
+        __syncthreads();
         if (nc <= (uint32_t)SEL_CAND && nlt < (uint32_t)k && (uint32_t)k <= nlt + nc) {
             radix_kth((int)nc, (uint32_t)k - nlt, from_cand, hist, part, &s_bin, &s_below, key, below);
             below += nlt;
