@@ -38,11 +38,11 @@ VALU_PEAK = 256 * 4 * 64 * 2.4e9 / 4   # lane-ops/s: 256 CUs x 4 SIMDs x one wav
 
 # Algorithmic integer work per unit (lane-ops), by fused kernel:
 #   2-arm: per (workgroup, simulation) 18 Philox blocks x 10 rounds x (2 32x32->64 products
-#   + 2 xor3), shared by the 4 batches of the group's 2 x 2 square, and the square's 4 sets of
+#   + 2 xor3), shared by the 16 batches of the group's 4 x 4 square, and the square's 8 sets of
 #   8 thresholds x 35 words x (compare + add), each counted once; per (simulation, tile) decision
 #   (med3), packed multiply-add and its share of the count unpacking (the calibration record is
 #   one 16-byte store per (simulation, batch)).
-B2_PHILOX, B2_COUNT_G, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 4 * 8 * 35 * 2, 4, 4
+B2_PHILOX, B2_COUNT_G, B2_TILE_CAL, B2_TILE_FWD = 18 * 10 * 4, 8 * 8 * 35 * 2, 4, 4
 #   4-arm: per (workgroup, simulation) 35 Philox blocks; per (batch, simulation) 35 words x
 #   (4 + 4 + 2 + 2) thresholds x (compare + add); per (simulation, box) outcome index (3),
 #   table gather (1), 3 compares, mask, 2 accumulates; per (simulation, tile) min + key store
@@ -65,7 +65,6 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # runs (profiles/<workload>_counters.md, scaled by what the counters read for a copy of known
 # size).  Valid only while that kernel is unchanged; workloads not listed report null.
 TRAFFIC = {
-    "binom2_1024_full": 4_343_206_424,   # k_binom2<true>: 10.5 MB read, 4,332.7 MB written (records)
     "hier4_16": 12_532_581_389,          # k_hier4<true, false, true>: 4,459.6 MB read, 8,073.0 MB written
     "phase23_c5_sub256": 1_624_933_596,  # k_phase23: 228.5 MB read, 1,396.4 MB written
 }

@@ -84,6 +84,17 @@ struct GroupItem {
     int32_t pad[2];
 };
 
+// Workgroup item of the 2-arm kernel: its 16 waves simulate [k_begin, k_end) for the batches of a
+// 4 x 4 square of the threshold grid (equal N): blk[4 r + c] is the batch of row group r and
+// column group c of the square (-1: none).
+constexpr int SQ2 = 4;                   // square side (batches)
+constexpr int SQ2W = SQ2 * SQ2;          // waves per workgroup
+struct SquareItem {
+    int32_t blk[SQ2W];
+    uint32_t k_begin;
+    uint32_t k_end;
+};
+
 // Per-node constants of the hierarchical posterior (90 nodes equally spaced in log s2 on
 // [log 1e-6, log 1e3]), computed once on the host: log s2, s2, 1/s2, c = 100 / (s2 + 400),
 // beta = c / s2, and lconst = log|Q|/2 + log of the inverse-gamma density of s2 + log of the
@@ -155,7 +166,8 @@ struct Platten {
     int64_t n_blocks = 0;
     WorkItem *d_items = nullptr;
     int64_t n_items = 0;
-    GroupItem *d_gitems = nullptr;       // 2-arm design
+    GroupItem *d_gitems = nullptr;       // 4-arm designs
+    SquareItem *d_sqitems = nullptr;     // 2-arm design
     int64_t n_gitems = 0;
 
     // design tables (device)

@@ -23,14 +23,15 @@ __device__ __forceinline__ void wave_sync() {
 // ------------------------------------------------------------------------------------
 // 2-arm binomial, n = 35 per arm, pooled z.  Words 0..34 are arm 0, 35..69 arm 1
 // (18 Philox blocks).  Each wave's batch is an 8 x 8 product of thresholds: the success
-// counts y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  The four waves of
-// a workgroup run the four batches of a 2 x 2 square of the threshold grid over the same
-// simulations: each wave generates a quarter of the Philox blocks of the chunk's 64 simulations
-// into LDS, and each counts one of the square's four sets of 8 thresholds (the two arm-0 row
-// groups, the two arm-1 column groups) over its arm's 35 words, once per simulation; the counts
-// (8 bytes per simulation and set) go through LDS to the two waves whose batches use them.
-// Rejection at the design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0; checked on
-// the host).
+// counts y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  The 16 waves of a
+// workgroup run the 16 batches of a 4 x 4 square of the threshold grid over the same
+// simulations (wave 4 r + c: row group r, column group c): the chunk's 18 Philox blocks are
+// generated once into LDS (one per wave, waves 0 and 1 a second), and the square's eight sets
+// of 8 thresholds (four arm-0 row groups, four arm-1 column groups) are each counted once per
+// simulation, by a pair of waves over the two halves of the arm's 35 words; the partial counts
+// (8 bytes per simulation, a byte per threshold) go through LDS, and a batch adds the two
+// halves of its row set and of its column set (bytes stay below 36: no carries).  Rejection at
+// the design's cut is y1 >= c(y0) (z is increasing in y1 for fixed y0; checked on the host).
 //
 // In calibration mode each lane also writes its simulation's record (Rec2: y0[0..7], y1[0..7] as
 // bytes, 16 bytes; a wave stores 1 KB contiguous per chunk).
@@ -41,50 +42,59 @@ __device__ __forceinline__ void wave_sync() {
 // LDS in two halves of 32 tiles, lanes l and l + 32 each summing half of tile l's column into
 // 32-bit totals (joined by one shuffle at the end); the final totals are added to global
 // memory with integer atomics (order-independent, hence deterministic).  The word buffer and
-// the transpose buffers share 33 KB of LDS (workgroup barriers separate their uses), so four
-// workgroups fit on a CU.
+// the transpose buffers share 130 KB of LDS (workgroup barriers separate their uses): one
+// workgroup of 16 waves per CU, four waves per SIMD.
 // ------------------------------------------------------------------------------------
+constexpr int WG2 = SQ2W * WAVE;   // 1024 threads
 template <bool KEYS>
-__global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
-                                               const GroupItem *__restrict__ items,
-                                               int64_t n_items, uint32_t key0, uint32_t key1,
-                                               const int32_t *__restrict__ cut_tbl,
-                                               uint32_t *__restrict__ R,
-                                               unsigned long long *__restrict__ sumT,
-                                               uint4 *__restrict__ recs) {
+__global__ __launch_bounds__(WG2) void k_binom2(const Blk2 *__restrict__ blocks,
+                                                const SquareItem *__restrict__ items,
+                                                int64_t n_items, uint32_t key0, uint32_t key1,
+                                                const int32_t *__restrict__ cut_tbl,
+                                                uint32_t *__restrict__ R,
+                                                unsigned long long *__restrict__ sumT,
+                                                uint4 *__restrict__ recs) {
     constexpr int NT = B2U * B2V;
     constexpr int NW = 2 * NP35;
     constexpr int NB = (NW + 3) / 4;
-    constexpr int NWAVES = WG / WAVE;
+    constexpr int NWAVES = SQ2W;
     constexpr int HALF = NT / 2;   // slots per flush half
+    constexpr int JH = (NP35 + 1) / 2;   // words of the first counting half (18; the second 17)
     // flush transposes (per wave HALF x (64 + 1) words, padded against bank conflicts); between
-    // flushes the same memory holds the chunk's Philox words.  33 KB: three workgroups per CU.
+    // flushes the same memory holds the chunk's Philox words
     __shared__ uint32_t lds[NWAVES][HALF][WAVE + 1];
     __shared__ int32_t s_cut[64];
-    __shared__ uint2 cnt[NWAVES][WAVE];   // per counting set and lane: its 8 counts as bytes
+    __shared__ uint2 cnt[NWAVES][WAVE];   // per counting wave and lane: its 8 partial counts as bytes
     uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [4*NB][64]
     static_assert(4 * NB * WAVE <= NWAVES * HALF * (WAVE + 1), "word buffer must fit");
+    static_assert(NB <= 2 * NWAVES, "at most two Philox blocks per wave");
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (threadIdx.x < 64) s_cut[threadIdx.x] = threadIdx.x <= NP35 ? cut_tbl[threadIdx.x] : 64;
     const int64_t it = blockIdx.x;
     if (it >= n_items) return;   // uniform over the workgroup
-    const GroupItem *__restrict__ G = items + it;
+    const SquareItem *__restrict__ G = items + it;
     const int32_t blk = G->blk[wv];   // read in place: a register copy indexed by wv would go to scratch
-    const bool live = blk >= 0;       // this wave's batch (row group wv >> 1, column group wv & 1)
+    const bool live = blk >= 0;       // this wave's batch (row group wv >> 2, column group wv & 3)
     const Blk2 *__restrict__ B = blocks + (live ? blk : 0);   // dereferenced only when live
     const uint32_t kb = G->k_begin, ke = G->k_end;
-    // counting set of this wave: arm wv >> 1 at the 8 thresholds of group wv & 1, taken from a
-    // block of the square that has them (row group g: blocks 2g, 2g+1; column group g: g, g+2)
-    const int carm = wv >> 1, cg = wv & 1;
-    int32_t csrc = carm == 0 ? G->blk[2 * cg] : G->blk[cg];
-    if (csrc < 0) csrc = carm == 0 ? G->blk[2 * cg + 1] : G->blk[cg + 2];
+    // counting set of this wave: set cs = wv >> 1 (0..3: arm 0, row group cs; 4..7: arm 1, column
+    // group cs - 4) over word half wv & 1; thresholds from a block of the square that has them
+    const int cs = wv >> 1, carm = cs >> 2, cgrp = cs & 3, chalf = wv & 1;
+    int32_t csrc = -1;
+    for (int i = 0; i < SQ2; ++i) {   // uniform
+        const int32_t b = carm == 0 ? G->blk[cgrp * SQ2 + i] : G->blk[i * SQ2 + cgrp];
+        if (csrc < 0 && b >= 0) csrc = b;
+    }
     const bool counting = csrc >= 0;   // false: no batch of the square uses this set
     uint32_t Tc[B2U];
 #pragma unroll
     for (int u = 0; u < B2U; ++u) Tc[u] = counting ? (carm == 0 ? blocks[csrc].T0[u] : blocks[csrc].T1[u]) : 0u;
+    const int jw0 = carm * NP35 + (chalf ? JH : 0);   // first word of this wave's half
+    const int jn = chalf ? NP35 - JH : JH;            // its word count
     uint4 *__restrict__ rbase = recs + ((KEYS && live) ? B->key_base : 0);
+    const int rsrc = (wv >> 2) * 2, csrc2 = 2 * (SQ2 + (wv & 3));   // counting waves of this batch's sets
 
     uint32_t acc[NT];
 #pragma unroll
@@ -117,7 +127,7 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
     for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
         const bool act = k < ke;
-        // this wave's share of the chunk's Philox blocks
+        // this wave's Philox blocks of the chunk: block wv, and block wv + 16 for waves 0 and 1
         for (int b = wv; b < NB; b += NWAVES) {
             const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
             words[4 * b + 0][lane] = w.x;
@@ -131,9 +141,9 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
 #pragma unroll
             for (int u = 0; u < B2U; ++u) yc[u] = 0u;
             if (counting) {
-#pragma unroll 7
-                for (int j = 0; j < NP35; ++j) {
-                    const uint32_t x = words[carm * NP35 + j][lane];
+#pragma unroll 6
+                for (int j = 0; j < jn; ++j) {
+                    const uint32_t x = words[jw0 + j][lane];
 #pragma unroll
                     for (int u = 0; u < B2U; ++u) yc[u] += (x < Tc[u]) ? 1u : 0u;
                 }
@@ -143,8 +153,12 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
         }
         __syncthreads();   // words consumed, counts shared: the next chunk (or a flush) may overwrite the words
         if (live) {
-            const uint2 rc = cnt[wv >> 1][lane];        // the batch's row group: arm-0 counts
-            const uint2 cc = cnt[2 + (wv & 1)][lane];   // its column group: arm-1 counts
+            // the batch's row set (arm-0 counts) and column set (arm-1 counts), each the byte-wise
+            // sum of its two halves
+            const uint2 ra = cnt[rsrc][lane], rb = cnt[rsrc + 1][lane];
+            const uint2 ca = cnt[csrc2][lane], cb = cnt[csrc2 + 1][lane];
+            const uint2 rc = make_uint2(ra.x + rb.x, ra.y + rb.y);
+            const uint2 cc = make_uint2(ca.x + cb.x, ca.y + cb.y);
             int y0[B2U], y1[B2V];
 #pragma unroll
             for (int u = 0; u < B2U; ++u) y0[u] = (int)(((u < 4 ? rc.x : rc.y) >> (8 * (u & 3))) & 0xFFu);
@@ -198,6 +212,7 @@ __global__ __launch_bounds__(WG) void k_binom2(const Blk2 *__restrict__ blocks,
         }
     }
 }
+
 
 // ------------------------------------------------------------------------------------
 // z-test: X = theta + Z, Z from words 0 and 1 by Box-Muller in float32,
@@ -344,14 +359,15 @@ __global__ __launch_bounds__(WG) void k_ztest1_plain(float theta, float cut, uin
 hipError_t launch_binom2(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT,
                          uint4 *keys, hipStream_t st) {
     const int64_t grid = P.n_gitems;
+    if (grid <= 0) return hipSuccess;
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     if (keys)
-        hipLaunchKernelGGL(k_binom2<true>, dim3((uint32_t)grid), dim3(WG), 0, st,
-                           (const Blk2 *)P.d_blocks, P.d_gitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
+        hipLaunchKernelGGL(k_binom2<true>, dim3((uint32_t)grid), dim3(WG2), 0, st,
+                           (const Blk2 *)P.d_blocks, P.d_sqitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
                            sumT, keys);
     else
-        hipLaunchKernelGGL(k_binom2<false>, dim3((uint32_t)grid), dim3(WG), 0, st,
-                           (const Blk2 *)P.d_blocks, P.d_gitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
+        hipLaunchKernelGGL(k_binom2<false>, dim3((uint32_t)grid), dim3(WG2), 0, st,
+                           (const Blk2 *)P.d_blocks, P.d_sqitems, P.n_gitems, k0, k1, P.d_cut_tbl, R,
                            sumT, keys);
     return hipGetLastError();
 }

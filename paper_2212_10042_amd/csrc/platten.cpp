@@ -916,18 +916,19 @@ int plan_work_items(Platten *P, int64_t target_waves) {
 // (blocks are ordered by N) whose four waves share the Philox words of a simulation range;
 // ranges sliced so that the grid has about target_wgs workgroups.
 int plan_group_items(Platten *P, int64_t target_wgs) {
-    std::vector<std::vector<int64_t>> groups;   // up to 4 blocks each (-1: none)
-    if (P->design.kind == CSE_BINOM2_Z) {
-        // 2 x 2 squares of blocks of equal N: block (row r, column c) goes to position
-        // ((r & 1) << 1) | (c & 1) of square (r >> 1, c >> 1); a second block with the same
+    std::vector<std::vector<int64_t>> groups;   // up to 4 (16 for the 2-arm design) blocks each (-1: none)
+    const bool sq2 = P->design.kind == CSE_BINOM2_Z;
+    if (sq2) {
+        // 4 x 4 squares of blocks of equal N: block (row r, column c) goes to position
+        // 4 (r & 3) + (c & 3) of square (r >> 2, c >> 2); a second block with the same
         // coordinates (two tiles at one grid point) opens another square
         std::map<std::tuple<int64_t, int64_t, int64_t, int64_t>, std::vector<int64_t>> sq;
         for (int64_t b = 0; b < P->n_blocks; ++b) {
             const int64_t r = P->blk_row[b], c = P->blk_col[b];
-            const int pos = (int)(((r & 1) << 1) | (c & 1));
+            const int pos = (int)(((r & (SQ2 - 1)) * SQ2) | (c & (SQ2 - 1)));
             for (int64_t dup = 0;; ++dup) {
-                auto &g = sq[std::make_tuple(P->blk_sims[b], r >> 1, c >> 1, dup)];
-                if (g.empty()) g.assign(4, -1);
+                auto &g = sq[std::make_tuple(P->blk_sims[b], r / SQ2, c / SQ2, dup)];
+                if (g.empty()) g.assign(SQ2W, -1);
                 if (g[pos] < 0) {
                     g[pos] = b;
                     break;
@@ -948,6 +949,7 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
     // transposes and atomics) then stays small beside its simulations
     constexpr int64_t MIN_ITEM_CHUNKS = 4;
     std::vector<GroupItem> gi;
+    std::vector<SquareItem> si;
     int64_t gs = 0;
     for (auto &g : groups) {
         int64_t first = -1;
@@ -957,20 +959,32 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
         const int64_t chunks = (N + WAVE - 1) / WAVE;
         const int64_t per = std::max<int64_t>(MIN_ITEM_CHUNKS, (chunks + slices - 1) / slices) * WAVE;
         for (int64_t k0 = 0; k0 < N; k0 += per) {
-            GroupItem it{};
-            for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
-            it.k_begin = (uint32_t)k0;
-            it.k_end = (uint32_t)std::min<int64_t>(N, k0 + per);
-            gs += (int64_t)(it.k_end - it.k_begin);
-            gi.push_back(it);
+            const uint32_t kb = (uint32_t)k0, ke = (uint32_t)std::min<int64_t>(N, k0 + per);
+            gs += (int64_t)(ke - kb);
+            if (sq2) {
+                SquareItem it{};
+                for (int w = 0; w < SQ2W; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
+                it.k_begin = kb;
+                it.k_end = ke;
+                si.push_back(it);
+            } else {
+                GroupItem it{};
+                for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
+                it.k_begin = kb;
+                it.k_end = ke;
+                gi.push_back(it);
+            }
         }
     }
     P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
     if (P->d_gitems) CSE_HIP_TRY(hipFree(P->d_gitems));
+    if (P->d_sqitems) CSE_HIP_TRY(hipFree(P->d_sqitems));
     P->d_gitems = nullptr;
-    P->n_gitems = (int64_t)gi.size();
+    P->d_sqitems = nullptr;
+    P->n_gitems = (int64_t)(sq2 ? si.size() : gi.size());
     P->group_sims = gs;
     P->tune_wgs = target_wgs;
+    if (sq2) return upload(&P->d_sqitems, si.data(), si.size());
     return upload(&P->d_gitems, gi.data(), gi.size());
 }
 
@@ -1013,7 +1027,7 @@ void free_platten(Platten *P) {
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
                     P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes,
-                    P->d_h4mask, P->d_S_pos, P->d_b2br, P->d_b2fb, P->d_b2cut, P->d_minpart, P->d_gstart, P->d_gcut};
+                    P->d_h4mask, P->d_S_pos, P->d_b2br, P->d_b2fb, P->d_b2cut, P->d_minpart, P->d_gstart, P->d_gcut, P->d_sqitems};
     auto in_arena = [&](void *q) {
         for (auto &a : P->arenas)
             if ((unsigned char *)q >= (unsigned char *)a.first && (unsigned char *)q < (unsigned char *)a.first + a.second)
