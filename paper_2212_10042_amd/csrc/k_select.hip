@@ -261,18 +261,20 @@ __global__ __launch_bounds__(SEL_WG) __attribute__((amdgpu_waves_per_eu(3, 8))) 
             if (c + NWV < nch) rnext = rb[(c + NWV) * WAVE + lane];
             const uint32_t live = j < N ? ONES : 0u;
             const uint32_t ya = r.z | H, yb = r.w | H;   // y1 of v = 0..3, 4..7, each byte's high bit set
+            // byte high bits of ya - clo: y1 >= clo (below the bracket); of ya - chi: y1 >= chi.
+            // In the bracket: chi <= y1 < clo, the high bits of the xor of the two differences;
+            // the xors are or-ed whole and masked once (their low bits are ignored).
             uint32_t inb = 0u;
 #pragma unroll
             for (int u = 0; u < B2U; ++u) {
                 const uint32_t y0 = rec_byte(u < 4 ? r.x : r.y, u & 3);
                 const uint4 T = ct[u][y0];
-                const uint32_t bl = ((ya - T.x) >> 7) & live, bh = ((yb - T.y) >> 7) & live;   // y1 >= clo
-                const uint32_t al = ((ya - T.z) >> 7) & live, ah = ((yb - T.w) >> 7) & live;   // y1 >= chi
-                acc[u][0] += bl;
-                acc[u][1] += bh;
-                inb |= (al ^ bl) | (ah ^ bh);
+                const uint32_t dl = ya - T.x, dh = yb - T.y, el = ya - T.z, eh = yb - T.w;
+                acc[u][0] += (dl >> 7) & live;
+                acc[u][1] += (dh >> 7) & live;
+                inb |= (dl ^ el) | (dh ^ eh);
             }
-            const bool in = inb != 0u;
+            const bool in = live != 0u && (inb & H) != 0u;
             const unsigned long long bal = __ballot(in);
             if (bal) {
                 uint32_t base = 0u;
