@@ -231,7 +231,7 @@ int cse_calibrate_noalloc(const cse_platten *p, uint64_t seed, double alpha, dou
  *   q_star float64 [n_tiles] or NULL.
  * The optimisation over q (s = log(q - 1) in [-30, 30], quasi-convex by Theorem 2) is a parallel
  * section search with eight lanes per tile (12 rounds of 8 points) on plattens below 2^18 tiles
- * and a golden-section search with one lane per tile (40 evaluations) from 2^18 tiles on; each
+ * and Brent's search (parabolic and golden-section steps) with one lane per tile from 2^18 tiles on; each
  * returns the best point it evaluated, and the two agree within 1e-9 relative on the same tile.
  * Errors: CSE_EINVAL, CSE_EHIP.
  */

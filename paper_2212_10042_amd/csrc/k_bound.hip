@@ -120,8 +120,8 @@ constexpr int GB = 8;
 // best sampled value is within (1/2) f'' (9e-7)^2 of the optimum (~1e-11 for |f''| ~ 50)
 constexpr int SECTION_ROUNDS = 12;
 // one lane per tile from this many tiles on (measured: at 33 k and 60 k tiles the serial chain
-// of 40 evaluations per tile is slower than the cooperative search; at 2^20 tiles the golden
-// search's fewer evaluations win, 1.20 -> 0.91 ms for the validation bound)
+// of evaluations per tile is slower than the cooperative search; at 2^20 tiles the single
+// lane's fewer evaluations win)
 constexpr int64_t BOUND_ONE_LANE_TILES = 262144;
 
 template <int FAM, int D>
@@ -252,59 +252,88 @@ __device__ double section_search(int lane, const TileGeom<D> &T, double loga, do
     return sg * best;
 }
 
-// One lane per tile: golden-section search on s over the same bracket, each round one new
-// evaluation (the bracket shrinks by 0.618); 38 rounds leave 60 * 0.618^39 ~ 4e-7.  Fewer
-// evaluations than the cooperative search (40 against 12 x 8) for launches with enough tiles
-// to fill the chip; the best evaluated point is returned, as there.
-constexpr int GOLD_ROUNDS = 38;
+// One lane per tile: Brent's minimisation on s over the same bracket (Brent, Algorithms for
+// Minimization without Derivatives, 1973): a parabola through the three best points when its
+// vertex falls well inside the bracket, else a golden-section step into the larger part; stops
+// when the bracket around the best point is within BRENT_TOL in s (the objective is quadratic
+// near its optimum, so the best value is within ~f'' BRENT_TOL^2 of the optimum).  The
+// objective is unimodal in s (Theorem 2), so the bracket keeps the optimum; the best evaluated
+// point is returned, as by the cooperative search.  Fewer evaluations than a golden-section
+// search to the same bracket (about 15 against 40), for launches with enough tiles to fill the
+// chip with one lane per tile.
+constexpr double BRENT_TOL = 2e-7;
+constexpr int BRENT_MAXIT = 80;
 
 template <int FAM, int D, bool INV>
-__device__ double golden_search(const TileGeom<D> &T, double loga, double *s_best) {
+__device__ double brent_search(const TileGeom<D> &T, double loga, double *s_best) {
     const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
-    const double g = 0.6180339887498949;   // (sqrt 5 - 1) / 2
-    auto ev = [&](double s) {
-        const double f = sg * objective<FAM, D, INV>(T, loga, s);
+    const double cg = 0.3819660112501051;  // (3 - sqrt 5) / 2
+    auto ev = [&](double x) {
+        const double f = sg * objective<FAM, D, INV>(T, loga, x);
         return f != f ? INFINITY : f;
     };
-    double lo = -30.0, hi = 30.0;
-    double x1 = hi - g * (hi - lo), x2 = lo + g * (hi - lo);
-    double f1 = ev(x1), f2 = ev(x2);
-    double best = f1, bs = x1;
-    if (f2 < best) {
-        best = f2;
-        bs = x2;
-    }
-    for (int r = 0; r < GOLD_ROUNDS; ++r) {
-        if (f1 <= f2) {   // the minimum lies in [lo, x2]
-            hi = x2;
-            x2 = x1;
-            f2 = f1;
-            x1 = hi - g * (hi - lo);
-            f1 = ev(x1);
-            if (f1 < best) {
-                best = f1;
-                bs = x1;
+    double a = -30.0, b = 30.0;
+    double x = a + cg * (b - a), w = x, v = x;
+    double fx = ev(x), fw = fx, fv = fx;
+    double d = 0.0, e = 0.0;
+    for (int it = 0; it < BRENT_MAXIT; ++it) {
+        const double xm = 0.5 * (a + b);
+        const double tol1 = 0.5 * BRENT_TOL, tol2 = BRENT_TOL;
+        if (fabs(x - xm) <= tol2 - 0.5 * (b - a)) break;
+        bool golden = true;
+        if (fabs(e) > tol1) {   // parabola through x, w, v
+            const double r = (x - w) * (fx - fv);
+            double q = (x - v) * (fx - fw);
+            double p = (x - v) * q - (x - w) * r;
+            q = 2.0 * (q - r);
+            if (q > 0.0) p = -p;
+            else q = -q;
+            const double etemp = e;
+            e = d;
+            if (fabs(p) < fabs(0.5 * q * etemp) && p > q * (a - x) && p < q * (b - x)) {
+                d = p / q;
+                const double u = x + d;
+                if (u - a < tol2 || b - u < tol2) d = xm >= x ? tol1 : -tol1;
+                golden = false;
             }
-        } else {          // in [x1, hi]
-            lo = x1;
-            x1 = x2;
-            f1 = f2;
-            x2 = lo + g * (hi - lo);
-            f2 = ev(x2);
-            if (f2 < best) {
-                best = f2;
-                bs = x2;
+        }
+        if (golden) {
+            e = x >= xm ? a - x : b - x;
+            d = cg * e;
+        }
+        const double u = fabs(d) >= tol1 ? x + d : x + (d > 0.0 ? tol1 : -tol1);
+        const double fu = ev(u);
+        if (fu <= fx) {
+            if (u >= x) a = x;
+            else b = x;
+            v = w;
+            fv = fw;
+            w = x;
+            fw = fx;
+            x = u;
+            fx = fu;
+        } else {
+            if (u < x) a = u;
+            else b = u;
+            if (fu <= fw || w == x) {
+                v = w;
+                fv = fw;
+                w = u;
+                fw = fu;
+            } else if (fu <= fv || v == x || v == w) {
+                v = u;
+                fv = fu;
             }
         }
     }
-    *s_best = bs;
-    return sg * best;
+    *s_best = x;
+    return sg * fx;
 }
 
 template <int L, int FAM, int D, bool INV>
 __device__ __forceinline__ double search(int lane, const TileGeom<D> &T, double loga, double *s_best) {
     if constexpr (L == 1)
-        return golden_search<FAM, D, INV>(T, loga, s_best);
+        return brent_search<FAM, D, INV>(T, loga, s_best);
     else
         return section_search<FAM, D, INV>(lane, T, loga, s_best);
 }
@@ -315,7 +344,7 @@ __global__ void k_negate1(double *x) { x[0] = -x[0]; }
 // mode 3: lower validation bound (Remark 2: the tilt of 1 - cp_lower = cp_upper(N - R), then
 // lower = 1 - that; cp_out receives cp_lower).
 // L lanes per tile: GB (cooperative section search, 256-thread blocks of 32 tiles) or 1
-// (golden-section search, 64-thread blocks of 64 tiles).
+// (Brent's search, 64-thread blocks of 64 tiles).
 template <int FAM, int D, int L>
 __global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, int64_t n_tiles,
                                                const double *__restrict__ theta,
@@ -652,7 +681,7 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
         hipLaunchKernelGGL(k_cp_table, dim3((uint32_t)((P.max_cls_N + 1 + 63) / 64), (uint32_t)P.n_cls),
                            dim3(64), 0, st, P.d_cls_N, P.d_cls_off, P.d_cp_mark, level, zq, P.d_cp_tbl);
     }
-    // enough tiles to give every SIMD work with one lane per tile: the golden search (fewer
+    // enough tiles to give every SIMD work with one lane per tile: Brent's search (fewer
     // evaluations); otherwise GB lanes per tile shorten each tile's chain of evaluations
     const bool one_lane = P.n_tiles >= BOUND_ONE_LANE_TILES;
     const int bs = one_lane ? 64 : 256;

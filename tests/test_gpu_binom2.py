@@ -281,7 +281,7 @@ def test_full_c3_forward_gradient_sampled_and_fd():
 
 def test_bound_search_paths_agree():
     """The float64 search over q takes eight lanes per tile (a parallel section search) on
-    plattens below 2^18 tiles and one lane per tile (golden section) from 2^18 tiles on.  Each
+    plattens below 2^18 tiles and one lane per tile (Brent's search) from 2^18 tiles on.  Each
     returns the best point it evaluated; on the same tiles alpha' (inversion) and the
     validation bound agree within 1e-9 relative."""
     w = W.binom2_grid(512, 1000, lower_triangle=False)
