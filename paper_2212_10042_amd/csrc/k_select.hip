@@ -61,7 +61,7 @@ __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
 constexpr int B2_N1 = NP35 + 1;            // outcomes per arm
 constexpr int B2_NOUT = B2_N1 * B2_N1;     // 1,296 outcomes
 constexpr float B2_Z = 5.0f;               // bracket margin in standard deviations of the count
-constexpr int B2_HB = 8192;                // LDS histogram bins of one batch (32 KB)
+constexpr int B2_HB = 4096;                // LDS histogram bins of one batch (16 KB)
 
 __device__ __forceinline__ uint32_t rec_byte(uint32_t w, int b) { return (w >> (8 * b)) & 0xFFu; }
 __device__ __forceinline__ uint32_t rec_outcome(const uint4 r, int s) {
