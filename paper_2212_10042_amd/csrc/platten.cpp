@@ -829,6 +829,9 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     for (int64_t b = 0; b < P->n_blocks; ++b) P->block_sims += blk_sims[b];
     if (P->n_blocks > 0)
         if (int e = plan_work_items(P, P->tune_waves)) return e;
+    // default workgroup counts (measured against cse_autotune): the 2-arm kernel's workgroups
+    // hold 16 waves, the 4-arm kernels' 4
+    if (kind == CSE_BINOM2_Z) P->tune_wgs = 2048;
     if (kind == CSE_BINOM2_Z || kind == CSE_HIER4 || kind == CSE_BASKET4)
         if (int e = plan_group_items(P, P->tune_wgs)) return e;
 
