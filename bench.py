@@ -65,9 +65,9 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # runs (profiles/<workload>_counters.md, scaled by what the counters read for a copy of known
 # size).  Valid only while that kernel is unchanged; workloads not listed report null.
 TRAFFIC = {
-    "binom2_1024_full": 4_971_842_746,   # k_binom2<true>: 72.9 MB read, 4,898.9 MB written (records + sums)
-    "hier4_16": 10_663_342_246,          # k_hier4<true, false, true>: 2,422.5 MB read, 8,240.8 MB written
-    "phase23_c5_sub256": 1_625_066_636,  # k_phase23: 228.4 MB read, 1,396.6 MB written
+    "binom2_1024_full": 4_388_219_655,   # k_binom2<true>: 17.8 MB read, 4,370.5 MB written (records + sums)
+    "hier4_16": 10_664_024_030,          # k_hier4<true, false, true>: 2,423.2 MB read, 8,240.8 MB written
+    "phase23_c5_sub256": 1_625_015_253,  # k_phase23: 228.9 MB read, 1,396.1 MB written
 }
 
 DEFAULT = "binom2_1024_full"
