@@ -77,6 +77,22 @@ def test_keep_all_square_uneven_sims():
     _full_compare(w, seed=5, keep_all=True)
 
 
+def test_repeated_grid_points_and_partial_squares():
+    """Boxes that share a grid point (the same centre three times, another twice) and a grid
+    whose 4 x 4 squares of 8 x 8 batches are only partly filled (17 x 13 boxes, some with a
+    different N): the workgroup items open extra squares for the repeated points and leave
+    empty batches idle, with exact results."""
+    w = W.binom2_grid(17, 700, lower_triangle=False, seed=11)
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    rep = np.array([5, 5, 5, 100, 100])
+    w["theta"] = np.concatenate([th, th[rep]])
+    w["radii"] = np.concatenate([rd, rd[rep]])
+    sims = np.concatenate([sm, sm[rep]])
+    sims[::7] = 400   # a second N class
+    w["sims"] = sims.astype(np.int32)
+    _full_compare(w, seed=11, keep_all=True)
+
+
 def test_edge_single_tile_and_one_sim():
     for sims in (1, 63, 64, 65):
         w = dict(name=f"single{sims}", theta=np.array([[0.25, -0.5]]), radii=np.array([[0.125, 0.125]]),
