@@ -72,11 +72,8 @@ struct WorkItem {
     int32_t pad;
 };
 
-// Workgroup item of the group kernels: its 4 waves simulate the same sims [k_begin, k_end) for up to
-// 4 blocks of equal N (blk = -1: no block), sharing each simulation's Philox words.  For the 2-arm
-// design the 4 blocks form a 2 x 2 square of the threshold grid: blk[w] is the block of row group
-// w >> 1 (8 arm-0 thresholds) and column group w & 1 (8 arm-1 thresholds), so the square's
-// 16 + 16 distinct thresholds serve 256 tiles.
+// Workgroup item of the 4-arm kernels: its 4 waves simulate the same sims [k_begin, k_end) for up
+// to 4 blocks of equal N (blk = -1: no block), sharing each simulation's Philox words.
 struct GroupItem {
     int32_t blk[4];
     uint32_t k_begin;
@@ -85,8 +82,9 @@ struct GroupItem {
 };
 
 // Workgroup item of the 2-arm kernel: its 16 waves simulate [k_begin, k_end) for the batches of a
-// 4 x 4 square of the threshold grid (equal N): blk[4 r + c] is the batch of row group r and
-// column group c of the square (-1: none).
+// 4 x 4 square of the threshold grid (equal N): blk[4 r + c] is the batch of row group r (8 arm-0
+// thresholds) and column group c (8 arm-1 thresholds) of the square (-1: none), so the square's
+// 32 + 32 distinct thresholds serve 1,024 tiles.
 constexpr int SQ2 = 4;                   // square side (batches)
 constexpr int SQ2W = SQ2 * SQ2;          // waves per workgroup
 struct SquareItem {
