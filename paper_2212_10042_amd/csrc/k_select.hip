@@ -164,7 +164,7 @@ __global__ __launch_bounds__(WAVE) void k_b2_bracket(const Blk2 *__restrict__ bl
 // of many of the batch's neighbouring tiles at once, so a per-lane loop over its tiles would
 // stall the wave); after the round the listed simulations are taken one per wave-step with
 // lane = tile: position lookup and histogram add without divergence.
-constexpr int B2_ROUND = 8;
+constexpr int B2_ROUND = 4;
 __global__ __launch_bounds__(SEL_WG) __attribute__((amdgpu_waves_per_eu(3, 8))) void k_b2_select(
     const Blk2 *__restrict__ blocks, const uint4 *__restrict__ recs, const int32_t *__restrict__ kk,
     const int2 *__restrict__ br, const uint4 *__restrict__ cut, const int32_t *__restrict__ S_pos,
