@@ -314,7 +314,8 @@ int cse_confidence_set(const cse_platten *p, const double *s_obs, int64_t s_stri
  *   alpha_prime, k  as cse_calibrate (k may be NULL, alpha_prime may be NULL)
  *   lambda_tile     float64 [n_tiles], u_tile uint32 [n_tiles]: the k_i-th smallest pair
  *                   ((-inf, 0) when k_i = 0)
- *   lambda_global   float64 [1], u_global uint32 [1]: the lexicographic minimum over tiles
+ *   lambda_global   float64 [1], u_global uint32 [1]: the lexicographic minimum over the
+ *                   tiles in the null space
  *   reject_at_lambda int32 [n_tiles]: pairs strictly below (lambda_i, c_i) (k_i - 1 when the
  *                   tied simulations' u are distinct)
  * Errors: CSE_EINVAL (alpha outside (0,1), NULL outputs, empty platten), CSE_ENOMEM, CSE_EHIP.

@@ -756,7 +756,7 @@ int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, do
         Timed tm("tiebreak", st);
         CSE_LAUNCH(cse::launch_tiebreak(P, seed, kk, lambda_tile, reject_at_lambda, u_tile, st));
     }
-    CSE_LAUNCH(cse::launch_min_pair(lambda_tile, u_tile, P.d_in_null, P.n_tiles, lambda_global, u_global, st));
+    CSE_LAUNCH(cse::launch_min_pair(P, lambda_tile, u_tile, P.d_in_null, P.n_tiles, lambda_global, u_global, st));
     return CSE_OK;
 }
 

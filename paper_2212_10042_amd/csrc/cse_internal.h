@@ -244,7 +244,8 @@ struct Platten {
     int32_t *d_kw = nullptr;             // k
     double *d_lamw = nullptr;            // lambda*_i
     double *d_lamg = nullptr;            // lambda* (1)
-    double *d_minpart = nullptr;         // [MIN_PARTS] partial minima of the reductions over tiles
+    double *d_minpart = nullptr;         // [2 * MIN_PARTS] partial minima of the reductions over tiles
+                                         // (values; for pairs, their second components after them)
 
     // calibration keys (allocated on first calibration): n_keys entries of 2 (outcome
     // index) or 4 (float32 statistic) bytes

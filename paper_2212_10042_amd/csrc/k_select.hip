@@ -633,11 +633,9 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
 // mapped to 0xFFFFFFFF (which cannot change a rank <= the number of ties).  On exit rej_at[t]
 // holds the number of pairs strictly below (lambda, c).
 // Key layouts: TB_F32 float32 keys at kt[(j / 64) * stride + j % 64]; TB_F32V4 the same with
-// 256-byte aligned 64-key chunks (read as float4); TB_OUT the 2-arm records (the tile's outcome
-// from record key_off + j and its slot key_stride), tested against an LDS bitmask of the
-// outcomes whose statistic equals lambda.
-enum { TB_F32 = 0, TB_F32V4 = 1, TB_OUT = 2 };
-constexpr int TB_MASK_WORDS = 2048;   // 65,536 outcome indices (16-bit keys)
+// 256-byte aligned 64-key chunks (read as float4).  The 2-arm designs' records serve a batch of
+// tiles at once and take the batch-level kernel below instead.
+enum { TB_F32 = 0, TB_F32V4 = 1 };
 constexpr int TB_RANK = 512;          // tie classes up to this size are ranked by counting
 constexpr int TB_CAND = 4096;         // tied simulations gathered in LDS
 
@@ -645,7 +643,6 @@ template <int MODE>
 __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ keys_,
                                                      const int64_t *__restrict__ key_off,
                                                      const int64_t *__restrict__ key_stride,
-                                                     const double *__restrict__ S_tbl, int n_out,
                                                      const int32_t *__restrict__ N,
                                                      const int32_t *__restrict__ kk,
                                                      const double *__restrict__ lam, uint32_t key0,
@@ -654,7 +651,6 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     __shared__ uint32_t hist[2048];
     __shared__ uint32_t part[SEL_WG];
     __shared__ uint32_t cand[TB_CAND];
-    __shared__ uint32_t tmask[MODE == TB_OUT ? TB_MASK_WORDS : 1];
     __shared__ uint32_t s_bin, s_below, s_cnt;
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x;
@@ -671,21 +667,9 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     const uint32_t need = (uint32_t)k - below_lam;   // >= 1: the k-th key is a tie
     const int64_t stride = key_stride[t];
     const float *__restrict__ kf = (const float *)keys_ + key_off[t];
-    const uint4 *__restrict__ ko = (const uint4 *)keys_ + key_off[t];   // TB_OUT: the batch's records
-    const int slot = (int)stride;                                        // TB_OUT: the tile's slot
-    if (MODE == TB_OUT) {
-        for (int w = tid; w < TB_MASK_WORDS; w += SEL_WG) tmask[w] = 0u;
-        __syncthreads();
-        for (int o = tid; o < n_out; o += SEL_WG)
-            if (S_tbl[o] == L) atomicOr(&tmask[o >> 5], 1u << (o & 31));
-    }
     if (tid == 0) s_cnt = 0u;
     __syncthreads();
-    auto is_tie_out = [&](uint32_t key) { return (tmask[key >> 5] >> (key & 31)) & 1u; };
-    auto tied = [&](int j) -> bool {
-        if (MODE == TB_OUT) return is_tie_out(rec_outcome(ko[j], slot));
-        return f2ord(kf[(int64_t)(j >> 6) * stride + (j & 63)]) == Lord;
-    };
+    auto tied = [&](int j) -> bool { return f2ord(kf[(int64_t)(j >> 6) * stride + (j & 63)]) == Lord; };
     // append simulation j's uniform when `in` (called by every lane of the wave)
     auto take = [&](bool in, int j) {
         const unsigned long long bal = __ballot(in);
@@ -700,21 +684,7 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     // one pass over the tile with several 16-byte (or 4-byte) loads in flight per thread; trip
     // counts are uniform so that every lane takes part in the ballots
     constexpr int LB = 4;
-    if (MODE == TB_OUT) {
-        for (int j0 = 0; j0 < n; j0 += SEL_WG * LB) {
-            uint4 r[LB];
-#pragma unroll
-            for (int i = 0; i < LB; ++i) {
-                const int j = j0 + i * SEL_WG + tid;
-                r[i] = j < n ? ko[j] : make_uint4(0u, 0u, 0u, 0u);
-            }
-#pragma unroll
-            for (int i = 0; i < LB; ++i) {
-                const int j = j0 + i * SEL_WG + tid;
-                take(j < n && is_tie_out(rec_outcome(r[i], slot)), j);
-            }
-        }
-    } else if (MODE == TB_F32V4) {
+    if (MODE == TB_F32V4) {
         const int nq = ((n + 63) >> 6) * 16;   // float4 pieces
         for (int q0 = 0; q0 < nq; q0 += SEL_WG * LB) {
             float4 v[LB];
@@ -788,7 +758,335 @@ __global__ __launch_bounds__(SEL_WG) void k_tiebreak(const void *__restrict__ ke
     }
 }
 
-// lexicographic minimum over tiles of (lambda_i, c_i), one workgroup.
+// 2-arm designs: the tie-break of a whole batch in one workgroup, each record read once per pass.
+// Tile (u, v)'s simulation is tied at lambda iff its outcome lies in lambda's tie group g; as S
+// does not increase with y1 for fixed y0, that is cut_{g+1}(y0) <= y1 < cut_g(y0) (the tie-group
+// cut table), so one LDS read per row and simulation classifies the row's 8 tiles by byte-wise
+// compares, as in the plain selection.  k_b2_tiecut finds each tile's group (one wave per batch,
+// lane = slot) and writes the batch's tie ranges over the selection's cut bytes, which are free
+// once lambda is known.  A tied simulation's uniform then goes to the tiles it ties:
+//  * first pass: into a fixed LDS region of TBB_CAPT words per tile, with an exact count; tiles
+//    with at most TBB_CAPT ties pick c by counting ranks there;
+//  * the other tiles continue with 8-bit radix passes over their tied uniforms (per-tile
+//    histograms), and once every remaining tile's candidate bin is small, one pass gathers the
+//    bins' uniforms into LDS and ranks them.
+// The result is the exact (need)-th smallest uniform among the tied simulations either way.
+constexpr int TBB_WG = 512;
+constexpr int TBB_CAPT = 256;                  // uniforms per tile in the first pass
+constexpr int TBB_BUF = B2U * B2V * TBB_CAPT;  // 16,384 words: first-pass regions, histograms, gathers
+constexpr int TBB_RANK = 512;                  // largest candidate bin ranked by counting
+constexpr int TBB_DEPTH = 4;                   // record loads in flight per lane
+
+__global__ __launch_bounds__(WAVE) void k_b2_tiecut(const Blk2 *__restrict__ blocks, const int32_t *__restrict__ kk,
+                                                    const double *__restrict__ lam, const double *__restrict__ S_tbl,
+                                                    const int32_t *__restrict__ S_order,
+                                                    const int32_t *__restrict__ gstart,
+                                                    const uint8_t *__restrict__ gcut, int n_groups,
+                                                    uint4 *__restrict__ cut, uint32_t *__restrict__ c_out) {
+    __shared__ uint8_t cb[B2U][B2_N1][16];   // per row and y0: lo of the 8 tiles, then hi
+    const int lane = threadIdx.x;
+    const Blk2 *__restrict__ B = blocks + blockIdx.x;
+    const int32_t t = B->tile[lane];
+    const int32_t N = B->n_sims;
+    bool live = false;
+    int g = 0;
+    if (t >= 0) {
+        const int32_t k = kk[t];
+        if (k <= 0 || k > N) {
+            c_out[t] = k <= 0 ? 0u : 0xFFFFFFFFu;
+        } else {
+            const double L = lam[t];
+            int a = 0, b = n_groups - 1;   // the group whose value is lambda (groups ascend)
+            while (a < b) {
+                const int m = (a + b) >> 1;
+                if (S_tbl[S_order[gstart[m]]] < L) a = m + 1; else b = m;
+            }
+            g = a;
+            live = S_tbl[S_order[gstart[g]]] == L;   // else no tie class: the tie-break writes c = max
+        }
+    }
+    const int u = lane >> 3, v = lane & 7;
+    for (int y0 = 0; y0 < B2_N1; ++y0) {   // empty ranges (lo = hi = 0) for slots without ties
+        cb[u][y0][v] = live ? gcut[(size_t)(g + 1) * B2_N1 + y0] : (uint8_t)0;
+        cb[u][y0][8 + v] = live ? gcut[(size_t)g * B2_N1 + y0] : (uint8_t)0;
+    }
+    lds_wave_sync();
+    const uint4 *__restrict__ src = reinterpret_cast<const uint4 *>(&cb[0][0][0]);
+    uint4 *__restrict__ dst = cut + (size_t)blockIdx.x * B2U * B2_N1;
+    for (int i = lane; i < B2U * B2_N1; i += WAVE) dst[i] = src[i];
+}
+
+// Per wave, tied simulations are first listed in LDS (index and 64-bit slot mask) and taken 64
+// at a time, one per lane, so that the uniform is drawn and the slots are visited only for
+// simulations tied somewhere (most simulations of a chunk are tied nowhere).
+struct TbbList {
+    uint32_t j[TBB_WG / WAVE][WAVE];
+    uint64_t m[TBB_WG / WAVE][WAVE];
+};
+
+template <int MODE>   // 0 first pass, 1 histogram of the next 8 bits, 2 gather
+__device__ __forceinline__ void tbb_take(uint32_t j, uint64_t m, uint32_t *buf, uint32_t *fill, const uint32_t *pre,
+                                         const uint32_t *off, const uint32_t *cnt, int lvl, uint32_t key0,
+                                         uint32_t key1) {
+    const uint32_t x = philox_tiebreak(j, key0, key1);
+    while (m) {
+        const int b = __builtin_ctzll(m);   // bit 8 v + u of slot (u, v)
+        m &= m - 1ull;
+        const int s = ((b & 7) << 3) | (b >> 3);
+        if (MODE == 0) {
+            const uint32_t p = atomicAdd(&fill[s], 1u);
+            if (p < (uint32_t)TBB_CAPT) buf[s * TBB_CAPT + p] = x;
+        } else if ((uint32_t)((uint64_t)x >> (32 - lvl)) == pre[s]) {
+            if (MODE == 1) {
+                atomicAdd(&buf[s * 256 + ((x >> (24 - lvl)) & 255u)], 1u);
+            } else {
+                const uint32_t p = atomicAdd(&fill[s], 1u);
+                if (p < cnt[s]) buf[off[s] + p] = x;   // cnt[s] of them by construction
+            }
+        }
+    }
+}
+
+template <int MODE>
+__device__ __forceinline__ void tbb_sweep(const uint4 *__restrict__ rb, int N, const uint4 (*ct)[B2_N1],
+                                          TbbList &L, uint32_t *buf, uint32_t *fill, const uint32_t *pre,
+                                          const uint32_t *off, const uint32_t *cnt, int lvl, uint32_t key0,
+                                          uint32_t key1) {
+    constexpr int NWV = TBB_WG / WAVE;
+    constexpr uint32_t H = 0x80808080u;
+    const int lane = threadIdx.x & (WAVE - 1), wv = threadIdx.x >> 6;
+    const int nch = (N + WAVE - 1) / WAVE;
+    int nl = 0;   // listed simulations of this wave (uniform)
+    for (int c0 = wv; c0 < nch; c0 += NWV * TBB_DEPTH) {
+        uint4 r[TBB_DEPTH];
+#pragma unroll
+        for (int i = 0; i < TBB_DEPTH; ++i) {   // records padded to whole chunks
+            const int c = c0 + NWV * i;
+            r[i] = c < nch ? rb[c * WAVE + lane] : make_uint4(0u, 0u, 0u, 0u);
+        }
+#pragma unroll
+        for (int i = 0; i < TBB_DEPTH; ++i) {
+            const int c = c0 + NWV * i;
+            if (c >= nch) break;   // uniform over the wave
+            const int j = c * WAVE + lane;
+            const uint32_t ya = r[i].z | H, yb = r[i].w | H;
+            // tied: y1 >= lo and not y1 >= hi, byte-wise; row u's flags (bits 7, 15, 23, 31 for
+            // v = 0..3 or 4..7) shifted to bits u, 8 + u, ...: bit 8 v + u of the slot mask
+            uint32_t ma = 0u, mb = 0u;
+#pragma unroll
+            for (int u = 0; u < B2U; ++u) {
+                const uint32_t y0 = rec_byte(u < 4 ? r[i].x : r[i].y, u & 3);
+                const uint4 T = ct[u][y0];
+                ma |= ((ya - T.x) & ~(ya - T.z) & H) >> (7 - u);
+                mb |= ((yb - T.y) & ~(yb - T.w) & H) >> (7 - u);
+            }
+            const bool tied = j < N && (ma | mb) != 0u;
+            const unsigned long long bal = __ballot(tied);
+            if (bal == 0ull) continue;   // uniform
+            const int n = __popcll(bal);
+            const int rk = (int)__popcll(bal & ((1ull << lane) - 1ull));
+            const int first = min(n, WAVE - nl);
+            const uint64_t m = (uint64_t)ma | ((uint64_t)mb << 32);
+            if (tied && rk < first) {
+                L.j[wv][nl + rk] = (uint32_t)j;
+                L.m[wv][nl + rk] = m;
+            }
+            if (nl + n < WAVE) {
+                nl += n;
+                continue;
+            }
+            lds_wave_sync();
+            tbb_take<MODE>(L.j[wv][lane], L.m[wv][lane], buf, fill, pre, off, cnt, lvl, key0, key1);
+            lds_wave_sync();
+            if (tied && rk >= first) {
+                L.j[wv][rk - first] = (uint32_t)j;
+                L.m[wv][rk - first] = m;
+            }
+            nl = n - first;
+        }
+    }
+    lds_wave_sync();
+    if (lane < nl) tbb_take<MODE>(L.j[wv][lane], L.m[wv][lane], buf, fill, pre, off, cnt, lvl, key0, key1);
+}
+
+// The nd-th smallest c of the n <= 64 K values v[0..n) (wave-wide, K values per lane in
+// registers), and the number lt of values below it: c is fixed bit by bit from the top, bit b
+// staying 0 when at least nd values lie at or below the prefix with bits b-1..0 set.  One compare
+// and one ballot per bit and register; the result is the same in every lane.
+template <int K>
+__device__ __forceinline__ void tbb_select(const uint32_t *v, uint32_t n, uint32_t nd, uint32_t &c, uint32_t &lt) {
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint32_t x[K];
+    bool ok[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        const uint32_t i = (uint32_t)(lane + q * WAVE);
+        ok[q] = i < n;
+        x[q] = ok[q] ? v[i] : 0u;
+    }
+    uint32_t p = 0u;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t thr = p | ((1u << b) - 1u);
+        uint32_t le = 0u;
+#pragma unroll
+        for (int q = 0; q < K; ++q) le += (uint32_t)__popcll(__ballot(ok[q] && x[q] <= thr));
+        if (le < nd) p |= 1u << b;
+    }
+    uint32_t below = 0u;
+#pragma unroll
+    for (int q = 0; q < K; ++q) below += (uint32_t)__popcll(__ballot(ok[q] && x[q] < p));
+    c = p;
+    lt = below;
+}
+
+__global__ __launch_bounds__(TBB_WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_b2_tiebreak(const Blk2 *__restrict__ blocks, const uint4 *__restrict__ recs,
+                                                        const int32_t *__restrict__ kk, const uint4 *__restrict__ cut,
+                                                        uint32_t key0, uint32_t key1, int32_t *__restrict__ rej_at,
+                                                        uint32_t *__restrict__ c_out) {
+    constexpr int NT = B2U * B2V;
+    constexpr int NWV = TBB_WG / WAVE;
+    __shared__ uint4 ct[B2U][B2_N1];   // per row u and y0: tie range [lo, hi) of the row's 8 tiles
+    __shared__ uint32_t buf[TBB_BUF];
+    __shared__ uint32_t pre[NT];       // leading bits of c found so far
+    __shared__ uint32_t need[NT];      // rank of c among the tied uniforms with those bits (1-based)
+    __shared__ uint32_t bel[NT];       // tied uniforms below those bits
+    __shared__ uint32_t cnt[NT];       // tied uniforms with those bits (0: slot finished or idle)
+    __shared__ uint32_t off[NT];       // start of the slot's LDS region
+    __shared__ uint32_t fill[NT];
+    __shared__ int s_next;             // 0: done, 1: histogram pass, 2: gather pass
+    __shared__ TbbList lst;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wv = tid >> 6;
+    const Blk2 *__restrict__ B = blocks + blockIdx.x;
+    const int32_t N = B->n_sims;
+    const int32_t my_t = B->tile[lane];   // lane = slot in the set-up and bookkeeping steps
+    {
+        const uint4 *__restrict__ cs = cut + (size_t)blockIdx.x * B2U * B2_N1;
+        for (int i = tid; i < B2U * B2_N1; i += TBB_WG) (&ct[0][0])[i] = cs[i];
+    }
+    if (wv == 0) {
+        bool live = false;
+        if (my_t >= 0) {
+            const int32_t k = kk[my_t];
+            live = k >= 1 && k <= N;   // else c was written with the tie ranges
+            if (live) need[lane] = (uint32_t)(k - rej_at[my_t]);
+        }
+        pre[lane] = 0u;
+        bel[lane] = 0u;
+        cnt[lane] = live ? 1u : 0u;   // marks the live slots until the first pass counts
+        fill[lane] = 0u;
+    }
+    __syncthreads();
+    const uint4 *__restrict__ rb = recs + B->key_base;
+    // c of slot s: the need-th smallest of the n uniforms at buf[o..o+n) (wave-wide), written out
+    auto finish_rank = [&](int s, uint32_t o, uint32_t n) {
+        const int32_t t = B->tile[s];
+        const uint32_t nd = need[s];
+        if (nd > n) {   // no tie class at lambda (lambda not a value of S)
+            if (lane == 0) c_out[t] = 0xFFFFFFFFu;
+            return;
+        }
+        uint32_t c, lt;
+        if (n <= (uint32_t)WAVE) tbb_select<1>(buf + o, n, nd, c, lt);
+        else if (n <= 2u * WAVE) tbb_select<2>(buf + o, n, nd, c, lt);
+        else if (n <= 4u * WAVE) tbb_select<4>(buf + o, n, nd, c, lt);
+        else tbb_select<8>(buf + o, n, nd, c, lt);
+        if (lane == 0) {
+            c_out[t] = c;
+            rej_at[t] += (int32_t)(bel[s] + lt);
+        }
+    };
+    tbb_sweep<0>(rb, N, ct, lst, buf, fill, pre, off, cnt, 0, key0, key1);
+    __syncthreads();
+    for (int s = wv; s < NT; s += NWV) {
+        if (cnt[s] == 0u) continue;
+        const uint32_t n = fill[s];
+        if (n <= (uint32_t)TBB_CAPT) {
+            finish_rank(s, (uint32_t)(s * TBB_CAPT), n);
+            if (lane == 0) cnt[s] = 0u;   // done
+        } else if (lane == 0) {
+            cnt[s] = n;
+        }
+    }
+    __syncthreads();
+    int lvl = 0;
+    for (;;) {   // at most 4 rounds: lvl grows by 8 each
+        // wave 0: empty the tie ranges of finished slots, decide the next pass
+        if (wv == 0) {
+            const bool act = cnt[lane] != 0u;
+            if (!act) {
+                uint8_t *cb = reinterpret_cast<uint8_t *>(&ct[0][0]);
+                const int u = lane >> 3, v = lane & 7;
+                for (int y0 = 0; y0 < B2_N1; ++y0) cb[(u * B2_N1 + y0) * 16 + 8 + v] = 0;   // hi = 0: empty
+            }
+            uint32_t mx = cnt[lane], sm = cnt[lane];
+            for (int o = 32; o >= 1; o >>= 1) {
+                mx = max(mx, __shfl_xor(mx, o));
+                sm += __shfl_xor(sm, o);
+            }
+            if (lane == 0)
+                s_next = mx == 0u ? 0 : (lvl > 0 && mx <= (uint32_t)TBB_RANK && sm <= (uint32_t)TBB_BUF ? 2 : 1);
+            // gather regions: exclusive prefix of the counts
+            const uint32_t mine = act ? cnt[lane] : 0u;
+            uint32_t x = mine;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            off[lane] = x - mine;
+            fill[lane] = 0u;
+        }
+        for (int i = tid; i < TBB_BUF; i += TBB_WG) buf[i] = 0u;
+        __syncthreads();
+        const int next = s_next;
+        if (next == 0) break;
+        if (next == 2) {
+            tbb_sweep<2>(rb, N, ct, lst, buf, fill, pre, off, cnt, lvl, key0, key1);
+            __syncthreads();
+            for (int s = wv; s < NT; s += NWV)
+                if (cnt[s] != 0u) finish_rank(s, off[s], cnt[s]);
+            break;
+        }
+        // histogram of the next 8 bits of the uniforms matching the lvl bits known
+        tbb_sweep<1>(rb, N, ct, lst, buf, fill, pre, off, cnt, lvl, key0, key1);
+        __syncthreads();
+        // per active slot (one wave each): the bin holding the need-th uniform
+        for (int s = wv; s < NT; s += NWV) {
+            if (cnt[s] == 0u) continue;
+            const uint32_t *h = buf + s * 256;
+            const uint32_t hv[4] = {h[4 * lane], h[4 * lane + 1], h[4 * lane + 2], h[4 * lane + 3]};
+            const uint32_t loc = hv[0] + hv[1] + hv[2] + hv[3];
+            uint32_t x = loc;
+            for (int o = 1; o < WAVE; o <<= 1) {
+                const uint32_t y = __shfl_up(x, o);
+                if (lane >= o) x += y;
+            }
+            const uint32_t nd = need[s];
+            uint32_t run = x - loc;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                if (run < nd && run + hv[q] >= nd) {
+                    pre[s] = (pre[s] << 8) | (uint32_t)(4 * lane + q);
+                    need[s] = nd - run;
+                    bel[s] += run;
+                    cnt[s] = hv[q];
+                }
+                run += hv[q];
+            }
+        }
+        __syncthreads();
+        lvl += 8;
+        if (lvl == 32) {   // every bit known: c = pre, the ties below it counted in bel
+            if (wv == 0 && cnt[lane] != 0u) {
+                c_out[my_t] = pre[lane];
+                rej_at[my_t] += (int32_t)bel[lane];
+            }
+            break;
+        }
+    }
+}
+
+// lexicographic minimum of (lambda_i, c_i) over the tiles in the null space; workgroup g takes
+// the tiles g, g + gridDim, ... (in 1024-tile strides) and writes its minimum to out_v[g], out_c[g].
 __global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v, const uint32_t *__restrict__ c,
                                                    const int32_t *__restrict__ in_null, int64_t n,
                                                    double *__restrict__ out_v, uint32_t *__restrict__ out_c) {
@@ -796,7 +1094,7 @@ __global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v,
     __shared__ uint32_t sc[1024];
     double mv = INFINITY;
     uint32_t mc = 0xFFFFFFFFu;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+    for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 1024) {
         if (in_null && !in_null[i]) continue;
         const double x = v[i];
         const uint32_t y = c[i];
@@ -820,8 +1118,8 @@ __global__ __launch_bounds__(1024) void k_min_pair(const double *__restrict__ v,
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        out_v[0] = sv[0];
-        out_c[0] = sc[0];
+        out_v[blockIdx.x] = sv[0];
+        out_c[blockIdx.x] = sc[0];
     }
 }
 
@@ -949,23 +1247,37 @@ hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, co
                            uint32_t *c_tile, hipStream_t st) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const dim3 grid((uint32_t)P.n_tiles), blk(SEL_WG);
-    if (P.design.kind == CSE_BINOM2_Z) {
-        if (P.n_outcomes > 32 * TB_MASK_WORDS) return hipErrorInvalidValue;
-        hipLaunchKernelGGL(k_tiebreak<TB_OUT>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
-                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+    if (P.design.kind == CSE_BINOM2_Z) {   // one workgroup per batch of 64 tiles
+        if (P.n_blocks > 0) {
+            const Blk2 *blk2 = (const Blk2 *)P.d_blocks;
+            hipLaunchKernelGGL(k_b2_tiecut, dim3((uint32_t)P.n_blocks), dim3(WAVE), 0, st, blk2, k, lam, P.d_S_tbl,
+                               P.d_S_order, P.d_gstart, P.d_gcut, P.n_groups, P.d_b2cut, c_tile);
+            hipLaunchKernelGGL(k_b2_tiebreak, dim3((uint32_t)P.n_blocks), dim3(TBB_WG), 0, st, blk2,
+                               (const uint4 *)P.d_keys, k, P.d_b2cut, k0, k1, rej_at, c_tile);
+        }
     } else if (P.design.kind == CSE_HIER4 || P.design.kind == CSE_BASKET4) {   // 64-key chunks at 256-byte offsets
-        hipLaunchKernelGGL(k_tiebreak<TB_F32V4>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
-                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+        hipLaunchKernelGGL(k_tiebreak<TB_F32V4>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k,
+                           lam, k0, k1, rej_at, c_tile);
     } else {
-        hipLaunchKernelGGL(k_tiebreak<TB_F32>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_S_tbl,
-                           P.n_outcomes, P.d_N, k, lam, k0, k1, rej_at, c_tile);
+        hipLaunchKernelGGL(k_tiebreak<TB_F32>, grid, blk, 0, st, P.d_keys, P.d_key_off, P.d_key_stride, P.d_N, k,
+                           lam, k0, k1, rej_at, c_tile);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_min_pair(const double *v, const uint32_t *c, const int32_t *in_null, int64_t n, double *out_v,
-                           uint32_t *out_c, hipStream_t st) {
-    hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, v, c, in_null, n, out_v, out_c);
+hipError_t launch_min_pair(const Platten &P, const double *v, const uint32_t *c, const int32_t *in_null, int64_t n,
+                           double *out_v, uint32_t *out_c, hipStream_t st) {
+    // large inputs: MIN_PARTS partial minima first (values, then their c in the second half of
+    // the partial buffer), then one workgroup over them
+    if (n > 64 * 1024 && P.d_minpart) {
+        double *pv = P.d_minpart;
+        uint32_t *pc = reinterpret_cast<uint32_t *>(P.d_minpart + MIN_PARTS);
+        hipLaunchKernelGGL(k_min_pair, dim3(MIN_PARTS), dim3(1024), 0, st, v, c, in_null, n, pv, pc);
+        hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, (const double *)pv, (const uint32_t *)pc,
+                           (const int32_t *)nullptr, (int64_t)MIN_PARTS, out_v, out_c);
+    } else {
+        hipLaunchKernelGGL(k_min_pair, dim3(1), dim3(1024), 0, st, v, c, in_null, n, out_v, out_c);
+    }
     return hipGetLastError();
 }
 

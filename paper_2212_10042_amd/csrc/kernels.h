@@ -20,8 +20,8 @@ hipError_t launch_min(const Platten &P, const double *v, const int32_t *in_null,
                       hipStream_t st);
 hipError_t launch_tiebreak(const Platten &P, uint64_t seed, const int32_t *k, const double *lam, int32_t *rej_at,
                            uint32_t *c_tile, hipStream_t st);
-hipError_t launch_min_pair(const double *v, const uint32_t *c, const int32_t *in_null, int64_t n, double *out_v,
-                           uint32_t *out_c, hipStream_t st);
+hipError_t launch_min_pair(const Platten &P, const double *v, const uint32_t *c, const int32_t *in_null, int64_t n,
+                           double *out_v, uint32_t *out_c, hipStream_t st);
 hipError_t launch_confset(const Platten &P, const double *s_obs, int64_t s_stride, const double *lam,
                           const double *coef, int link, int32_t *keep, double *e_lo, double *e_hi,
                           double *e_range, hipStream_t st);

@@ -878,7 +878,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
     CSE_HIP_TRY(hipMalloc((void **)&P->d_kw, nt * sizeof(int32_t)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamw, nt * sizeof(double)));
     CSE_HIP_TRY(hipMalloc((void **)&P->d_lamg, sizeof(double)));
-    CSE_HIP_TRY(hipMalloc((void **)&P->d_minpart, MIN_PARTS * sizeof(double)));
+    CSE_HIP_TRY(hipMalloc((void **)&P->d_minpart, 2 * MIN_PARTS * sizeof(double)));
     if (kind == CSE_BINOM2_Z) {
         CSE_HIP_TRY(hipMalloc((void **)&P->d_b2cut, (size_t)P->n_blocks * B2U * (NP35 + 1) * sizeof(uint4)));
         CSE_HIP_TRY(hipMalloc((void **)&P->d_b2br, nt * sizeof(int2)));

@@ -142,8 +142,9 @@ def test_tiebreak_parity(design):
 
 
 def test_tiebreak_many_ties_radix_fallback():
-    """A tile whose tie class at lambda holds more than the 4,096 LDS candidates: the exact
-    radix passes over the whole tile pick c."""
+    """A tile whose tie class at lambda holds more than 4,096 simulations: more than the 2-arm
+    batch tie-break's 256-word first-pass region, so one 8-bit histogram pass and a gather pass
+    pick c."""
     w = dict(name="binom2_ties", theta=np.array([[-4.0, -4.0], [-1.0, -1.2]]), radii=np.full((2, 2), 0.05),
              sims=np.array([100_000, 5000], np.int32))
     oc = _tiebreak_compare("binom2", w, seed=3, alpha=0.025)
@@ -151,6 +152,38 @@ def test_tiebreak_many_ties_radix_fallback():
     ties = [int(np.sum(S[t, : oc["N"][t]] == oc["lam"][t])) for t in range(len(oc["subs"]))]
     print(f"[tiebreak] tie class sizes {ties}", flush=True)
     assert max(ties) > 4096
+
+
+def test_tiebreak_heavy_ties_two_histogram_passes():
+    """Tie classes of about 200,000 simulations in one batch (theta near (-5, -5), alpha 0.3:
+    lambda is the statistic of the equal-count outcomes): the 2-arm batch tie-break overflows its
+    first-pass regions and needs two 8-bit histogram passes before the candidate bins fit LDS."""
+    w = dict(name="binom2_heavy_ties", theta=np.array([[-5.0, -5.0], [-4.8, -5.0], [-1.0, -1.2]]),
+             radii=np.full((3, 2), 0.05), sims=np.full(3, 300_000, np.int32))
+    oc = _tiebreak_compare("binom2", w, seed=3, alpha=0.3)
+    _, _, S = O._tile_simulation("binom2", w["theta"], w["sims"], oc["subs"], 3, 1.96, True)
+    ties = [int(np.sum(S[t, : oc["N"][t]] == oc["lam"][t])) for t in range(len(oc["subs"]))]
+    print(f"[tiebreak] tie class sizes {ties}", flush=True)
+    assert max(ties) > 512 * 256
+
+
+def test_tiebreak_global_pair_many_tiles():
+    """More than 65,536 tiles (the global pair is reduced by partial minima, then one workgroup):
+    (lambda*, c*) is the lexicographic minimum of the per-tile pairs over the null-space tiles."""
+    w = W.binom2_grid(300, 512, lo=-2.0, hi=0.5, lower_triangle=False, seed=4)
+    P = cse.Platten.create("binom2", w["theta"], w["radii"], w["sims"], keep_all=True)
+    assert P.n_tiles > 65_536
+    print(f"[tiebreak] global pair over {P.n_tiles} tiles", flush=True)
+    g = P.calibrate_tiebreak(4, alpha=0.05)
+    torch.cuda.synchronize()
+    lam = _np(g["lambda_tile"])
+    u = _np(g["u_tile"]).view(np.uint32).astype(np.int64)
+    inn = np.asarray(P.tiles["in_null"]).astype(bool)
+    assert inn.any() and not inn.all()
+    order = np.lexsort((u[inn], lam[inn]))
+    assert float(_np(g["lambda_global"])[0]) == lam[inn][order[0]]
+    assert int(_np(g["u_global"]).view(np.uint32)[0]) == u[inn][order[0]]
+    P.close()
 
 
 # ------------------------------------------------------------------ confidence sets
