@@ -246,9 +246,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     uint32_t acc[B4S];
 #pragma unroll
     for (int s = 0; s < B4S; ++s) acc[s] = 0u;
-    // lane l: partial totals (over lanes of half l >> 5) of slot l & 31 (tot0) and 32 + (l & 31) (tot1)
-    uint32_t tot0[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u}, tot1[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-
+    // the counters of the chunks since the last flush into R: per half of the slots, the wave
+    // transposes the counters through the word buffer, lanes l and l + 32 sum slot l's fields over
+    // their halves of the simulations, and lane l adds the slot's per-configuration totals
     auto flush = [&]() {
         __syncthreads();   // the word buffer is free: every wave has finished counting
 #pragma unroll
@@ -257,25 +257,39 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
             for (int s = 0; s < HALF; ++s) tr[wv][s][lane] = acc[h * HALF + s];
             wave_sync4();
             const int sl = lane & (HALF - 1), j0 = (lane >> 5) * HALF;
+            uint32_t t[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
             for (int j = j0; j < j0 + HALF; ++j) {
                 const uint32_t x = tr[wv][sl][j];
                 if (BASKET) {
-                    if (h == 0)
-                        tot0[1] += x;
-                    else
-                        tot1[1] += x;
+                    t[1] += x;
                     continue;
                 }
 #pragma unroll
-                for (int m = 1; m <= 7; ++m) {
-                    const uint32_t f = (x >> (4 * (m - 1))) & 15u;
-                    if (h == 0)
-                        tot0[m] += f;
-                    else
-                        tot1[m] += f;
-                }
+                for (int m = 1; m <= 7; ++m) t[m] += (x >> (4 * (m - 1))) & 15u;
             }
             wave_sync4();
+#pragma unroll
+            for (int m = 1; m <= 7; ++m) t[m] += __shfl_xor(t[m], HALF);
+            const int s = h * HALF + sl;
+            const int32_t t0 = B->tile0[s];
+            if (live && lane < HALF && t0 >= 0) {
+                if (BASKET) {
+                    if (t[1]) atomicAdd(&R[t0], t[1]);
+                } else {
+                    const uint32_t bm = B->bmask[s];
+                    int q = 0;
+#pragma unroll
+                    for (int b = 1; b <= 7; ++b) {
+                        if (!(bm & (1u << b))) continue;
+                        uint32_t r = 0u;
+#pragma unroll
+                        for (int m = 1; m <= 7; ++m)
+                            if (m & b) r += t[m];
+                        if (r) atomicAdd(&R[t0 + q], r);
+                        ++q;
+                    }
+                }
+            }
         }
 #pragma unroll
         for (int s = 0; s < B4S; ++s) acc[s] = 0u;
@@ -332,6 +346,23 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         __syncthreads();
         if (live) {
             float *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * n_rows * WAVE + lane;
+            // Neighbouring thresholds of an arm often give a simulation the same count, and then
+            // two slots share the outcome: the table row (or mask byte) of (u2, u3) is kept for
+            // the (u2, u3) entries of the current u1 taken so far and of the previous u1 for the
+            // rest, and a slot whose outcome equals one of those (same y1 as the previous u1, or
+            // same y2 or y3 as the previous u2 or u3) takes it without a gather.  The table is
+            // read through L2 at random rows, so fewer gathers are fewer L2 requests.
+            float4 qs[B4N2][B4N3];
+            uint32_t ms[B4N2][B4N3];
+            bool hv[B4N2][B4N3];   // uniform: the entry holds a processed slot's row
+#pragma unroll
+            for (int u2 = 0; u2 < B4N2; ++u2)
+#pragma unroll
+                for (int u3 = 0; u3 < B4N3; ++u3) {
+                    qs[u2][u3] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ms[u2][u3] = 0u;
+                    hv[u2][u3] = false;
+                }
 #pragma unroll
             for (int u0 = 0; u0 < B4N0; ++u0)
 #pragma unroll
@@ -342,20 +373,41 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                         for (int u3 = 0; u3 < B4N3; ++u3) {
                             const int s = ((u0 * B4N1 + u1) * B4N2 + u2) * B4N3 + u3;
                             const int32_t row0 = B->row0[s];
-                            if (row0 < 0) continue;   // uniform: the slot holds no box
+                            if (row0 < 0) {   // uniform: the slot holds no box
+                                hv[u2][u3] = false;
+                                continue;
+                            }
+                            const int p2 = u2 > 0 ? u2 - 1 : 0, p3 = u3 > 0 ? u3 - 1 : 0;
+                            const bool r1 = u1 > 0 && hv[u2][u3] && y1[u1] == y1[u1 > 0 ? u1 - 1 : 0];
+                            const bool r3 = u3 > 0 && hv[u2][p3] && y3[u3] == y3[p3];
+                            const bool r2 = u2 > 0 && hv[p2][u3] && y2[u2] == y2[p2];
+                            const bool fresh = !(r1 || r2 || r3);
                             const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
                             // without keys only the rejection mask at the cut is needed: one byte
                             // per outcome (a 128-byte line covers 128 neighbouring outcomes)
                             float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
                             uint32_t m;
                             if (KEYS) {
-                                q = tbl[idx];
+                                // selects between values, not between array elements (a select of
+                                // addresses would keep the array out of registers)
+                                const float4 a1 = qs[u2][u3], a3 = qs[u2][p3], a2 = qs[p2][u3];
+                                q.x = r1 ? a1.x : (r3 ? a3.x : a2.x);
+                                q.y = r1 ? a1.y : (r3 ? a3.y : a2.y);
+                                q.z = r1 ? a1.z : (r3 ? a3.z : a2.z);
+                                if (BASKET) q.w = r1 ? a1.w : (r3 ? a3.w : a2.w);
+                                if (fresh) q = tbl[idx];
+                                qs[u2][u3] = q;
                                 m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u) |
                                            (BASKET && q.w < cut ? 8u : 0u))
                                         : 0u;
                             } else {
-                                m = act ? (uint32_t)mtbl[idx] : 0u;
+                                const uint32_t b1 = ms[u2][u3], b3 = ms[u2][p3], b2 = ms[p2][u3];
+                                uint32_t mm = r1 ? b1 : (r3 ? b3 : b2);
+                                if (fresh) mm = (uint32_t)mtbl[idx];
+                                ms[u2][u3] = mm;
+                                m = act ? mm : 0u;
                             }
+                            hv[u2][u3] = true;
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
                                 acc[s] += (m & b) ? 1u : 0u;
@@ -411,36 +463,6 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     }
     flush();
     if (SCORE && live) flush_scores();
-    if (!live) return;
-    // totals of slot s: lanes s & 31 and (s & 31) + 32 each hold half of the lanes' counts
-#pragma unroll
-    for (int m = 1; m <= 7; ++m) {
-        tot0[m] += __shfl_xor(tot0[m], HALF);
-        tot1[m] += __shfl_xor(tot1[m], HALF);
-    }
-    if (lane >= HALF) return;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const int s = h * HALF + lane;
-        const int32_t t0 = B->tile0[s];
-        if (t0 < 0) continue;
-        if (BASKET) {
-            atomicAdd(&R[t0], (h == 0) ? tot0[1] : tot1[1]);
-            continue;
-        }
-        const uint32_t bm = B->bmask[s];
-        int q = 0;
-#pragma unroll
-        for (int b = 1; b <= 7; ++b) {
-            if (!(bm & (1u << b))) continue;
-            uint32_t r = 0u;
-#pragma unroll
-            for (int m = 1; m <= 7; ++m)
-                if (m & b) r += (h == 0) ? tot0[m] : tot1[m];
-            atomicAdd(&R[t0 + q], r);
-            ++q;
-        }
-    }
 }
 
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
