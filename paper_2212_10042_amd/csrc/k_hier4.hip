@@ -347,67 +347,69 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         if (live) {
             float *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * n_rows * WAVE + lane;
             // Neighbouring thresholds of an arm often give a simulation the same count, and then
-            // two slots share the outcome: the table row (or mask byte) of (u2, u3) is kept for
-            // the (u2, u3) entries of the current u1 taken so far and of the previous u1 for the
-            // rest, and a slot whose outcome equals one of those (same y1 as the previous u1, or
-            // same y2 or y3 as the previous u2 or u3) takes it without a gather.  The table is
-            // read through L2 at random rows, so fewer gathers are fewer L2 requests.
-            float4 qs[B4N2][B4N3];
-            uint32_t ms[B4N2][B4N3];
-            bool hv[B4N2][B4N3];   // uniform: the entry holds a processed slot's row
-#pragma unroll
-            for (int u2 = 0; u2 < B4N2; ++u2)
-#pragma unroll
-                for (int u3 = 0; u3 < B4N3; ++u3) {
-                    qs[u2][u3] = make_float4(0.f, 0.f, 0.f, 0.f);
-                    ms[u2][u3] = 0u;
-                    hv[u2][u3] = false;
-                }
+            // two slots share the outcome.  The slots of one (u0, u1) form a group: its gathers
+            // are issued first, skipping a slot whose outcome equals that of the slot at the
+            // previous u3 or u2 (fewer gathers are fewer L2 requests, the table being read at
+            // random rows), then one wait, then the slots are evaluated and their keys stored.
+            // Vector memory counts loads and stores together, so a gather used right after the
+            // previous slot's key stores would also wait for those stores.
 #pragma unroll
             for (int u0 = 0; u0 < B4N0; ++u0)
 #pragma unroll
-                for (int u1 = 0; u1 < B4N1; ++u1)
+                for (int u1 = 0; u1 < B4N1; ++u1) {
+                    float4 qs[B4N2][B4N3];
+                    uint32_t ms[B4N2][B4N3];
+                    auto slot_of = [&](int u2, int u3) { return ((u0 * B4N1 + u1) * B4N2 + u2) * B4N3 + u3; };
 #pragma unroll
                     for (int u2 = 0; u2 < B4N2; ++u2)
 #pragma unroll
                         for (int u3 = 0; u3 < B4N3; ++u3) {
-                            const int s = ((u0 * B4N1 + u1) * B4N2 + u2) * B4N3 + u3;
-                            const int32_t row0 = B->row0[s];
-                            if (row0 < 0) {   // uniform: the slot holds no box
-                                hv[u2][u3] = false;
-                                continue;
+                            qs[u2][u3] = make_float4(0.f, 0.f, 0.f, 0.f);
+                            ms[u2][u3] = 0u;
+                            const int s = slot_of(u2, u3);
+                            if (B->row0[s] < 0) continue;   // uniform: the slot holds no box
+                            const bool r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[u3 > 0 ? u3 - 1 : 0];
+                            const bool r2 = u2 > 0 && B->row0[u2 > 0 ? s - B4N3 : s] >= 0 &&
+                                            y2[u2] == y2[u2 > 0 ? u2 - 1 : 0];
+                            if (!(r2 || r3)) {
+                                const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
+                                if (KEYS) qs[u2][u3] = tbl[idx];
+                                else ms[u2][u3] = (uint32_t)mtbl[idx];
                             }
+                        }
+                    // vmcnt 0, expcnt and lgkmcnt left alone: the group's rows are in registers
+                    __builtin_amdgcn_s_waitcnt(0x0F70);
+#pragma unroll
+                    for (int u2 = 0; u2 < B4N2; ++u2)
+#pragma unroll
+                        for (int u3 = 0; u3 < B4N3; ++u3) {
+                            const int s = slot_of(u2, u3);
+                            const int32_t row0 = B->row0[s];
+                            if (row0 < 0) continue;   // uniform
                             const int p2 = u2 > 0 ? u2 - 1 : 0, p3 = u3 > 0 ? u3 - 1 : 0;
-                            const bool r1 = u1 > 0 && hv[u2][u3] && y1[u1] == y1[u1 > 0 ? u1 - 1 : 0];
-                            const bool r3 = u3 > 0 && hv[u2][p3] && y3[u3] == y3[p3];
-                            const bool r2 = u2 > 0 && hv[p2][u3] && y2[u2] == y2[p2];
-                            const bool fresh = !(r1 || r2 || r3);
-                            const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
-                            // without keys only the rejection mask at the cut is needed: one byte
-                            // per outcome (a 128-byte line covers 128 neighbouring outcomes)
+                            const bool r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[p3];
+                            const bool r2 = u2 > 0 && B->row0[u2 > 0 ? s - B4N3 : s] >= 0 && y2[u2] == y2[p2];
+                            // a repeat takes its source's row (resolved earlier in the group);
+                            // selects between values, not between array elements (a select of
+                            // addresses would keep the arrays out of registers)
                             float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
                             uint32_t m;
                             if (KEYS) {
-                                // selects between values, not between array elements (a select of
-                                // addresses would keep the array out of registers)
-                                const float4 a1 = qs[u2][u3], a3 = qs[u2][p3], a2 = qs[p2][u3];
-                                q.x = r1 ? a1.x : (r3 ? a3.x : a2.x);
-                                q.y = r1 ? a1.y : (r3 ? a3.y : a2.y);
-                                q.z = r1 ? a1.z : (r3 ? a3.z : a2.z);
-                                if (BASKET) q.w = r1 ? a1.w : (r3 ? a3.w : a2.w);
-                                if (fresh) q = tbl[idx];
+                                const float4 a3 = qs[u2][p3], a2 = qs[p2][u3], a0 = qs[u2][u3];
+                                q.x = r3 ? a3.x : (r2 ? a2.x : a0.x);
+                                q.y = r3 ? a3.y : (r2 ? a2.y : a0.y);
+                                q.z = r3 ? a3.z : (r2 ? a2.z : a0.z);
+                                if (BASKET) q.w = r3 ? a3.w : (r2 ? a2.w : a0.w);
                                 qs[u2][u3] = q;
                                 m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u) |
                                            (BASKET && q.w < cut ? 8u : 0u))
                                         : 0u;
                             } else {
-                                const uint32_t b1 = ms[u2][u3], b3 = ms[u2][p3], b2 = ms[p2][u3];
-                                uint32_t mm = r1 ? b1 : (r3 ? b3 : b2);
-                                if (fresh) mm = (uint32_t)mtbl[idx];
+                                const uint32_t b3 = ms[u2][p3], b2 = ms[p2][u3], b0 = ms[u2][u3];
+                                const uint32_t mm = r3 ? b3 : (r2 ? b2 : b0);
                                 ms[u2][u3] = mm;
                                 m = act ? mm : 0u;
                             }
-                            hv[u2][u3] = true;
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
                                 acc[s] += (m & b) ? 1u : 0u;
@@ -454,6 +456,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                                 }
                             }
                         }
+                }
         }
         if (++since == FLUSH_EVERY) {   // basket counters are plain 32-bit: only the score rows
             if (!BASKET) flush();
