@@ -152,14 +152,11 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     constexpr int NB = NW / 4;   // 35 Philox blocks
     constexpr int NWAVES = WG / WAVE;
     constexpr int M1 = NP + 1;
-    constexpr int HALF = B4S / 2;          // slots per flush half
-    constexpr int FLUSH_EVERY = 15;        // 4-bit counters: at most 15 increments between flushes
-    // The chunk's Philox words; between chunks the same memory holds the flush transposes
-    // (per wave HALF x (64 + 1) words, padded against bank conflicts).
+    constexpr int FLUSH_EVERY = 15;        // score rows: 16-bit fields hold 15 chunks
+    // The chunk's Philox words; between chunks the same memory holds the counter transposes
+    // (per wave 32 x (64 + 1) words, padded against bank conflicts).
     __shared__ uint32_t words[NW][WAVE];
     __shared__ uint2 ysum[SCORE ? NWAVES : 1][SCORE ? H4_SROWS : 1];   // per wave and key row: packed y sums
-    static_assert(NWAVES * HALF * (WAVE + 1) <= NW * WAVE, "flush transposes must fit in the word buffer");
-    uint32_t(*tr)[HALF][WAVE + 1] = reinterpret_cast<uint32_t(*)[HALF][WAVE + 1]>(&words[0][0]);
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -242,61 +239,77 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         wave_sync4();
     };
 
-    // per slot: seven 4-bit counters, field m-1 counting the simulations with rejection mask m
-    uint32_t acc[B4S];
+    // One word per pair of slots (2p, 2p + 1).  4-arm: seven 2-bit fields per slot, field m - 1 of
+    // slot 2p + h at bit 14 h + 2 (m - 1), counting the simulations with rejection mask m (at most
+    // ACC_EVERY = 3 per lane between flushes); basket: a 16-bit count per slot at bit 16 h.
+    // Half the registers of one word per slot, which leaves room for a whole group's table rows.
+    constexpr int NACC = B4S / 2;
+    constexpr int ACC_EVERY = BASKET ? 4096 : 3;
+    static_assert(NWAVES * NACC * (WAVE + 1) <= NW * WAVE, "flush transposes must fit in the word buffer");
+    uint32_t(*tr)[NACC][WAVE + 1] = reinterpret_cast<uint32_t(*)[NACC][WAVE + 1]>(&words[0][0]);
+    uint32_t acc[NACC];
 #pragma unroll
-    for (int s = 0; s < B4S; ++s) acc[s] = 0u;
-    // the counters of the chunks since the last flush into R: per half of the slots, the wave
-    // transposes the counters through the word buffer, lanes l and l + 32 sum slot l's fields over
-    // their halves of the simulations, and lane l adds the slot's per-configuration totals
+    for (int p = 0; p < NACC; ++p) acc[p] = 0u;
+    // the counters of the chunks since the last flush into R: the wave transposes the words
+    // through the word buffer, lanes l and l + 32 sum word l over their halves of the simulations
+    // (byte-wise: four fields at a time, at most 3 x 64 per byte), and lane l adds the per-
+    // configuration totals of slots 2l and 2l + 1
     auto flush = [&]() {
         __syncthreads();   // the word buffer is free: every wave has finished counting
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
+        for (int p = 0; p < NACC; ++p) tr[wv][p][lane] = acc[p];
+        wave_sync4();
+        const int pw = lane & (NACC - 1), j0 = (lane >> 5) * (WAVE / 2);
+        uint32_t A[4] = {0u, 0u, 0u, 0u};
+        for (int j = j0; j < j0 + WAVE / 2; ++j) {
+            const uint32_t x = tr[wv][pw][j];
+            if (BASKET) {
+                A[0] += x & 0xFFFFu;
+                A[1] += x >> 16;
+                continue;
+            }
 #pragma unroll
-            for (int s = 0; s < HALF; ++s) tr[wv][s][lane] = acc[h * HALF + s];
-            wave_sync4();
-            const int sl = lane & (HALF - 1), j0 = (lane >> 5) * HALF;
-            uint32_t t[8] = {0u, 0u, 0u, 0u, 0u, 0u, 0u, 0u};
-            for (int j = j0; j < j0 + HALF; ++j) {
-                const uint32_t x = tr[wv][sl][j];
+            for (int c = 0; c < 4; ++c) A[c] += (x >> (2 * c)) & 0x03030303u;
+        }
+        wave_sync4();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) A[c] += __shfl_xor(A[c], WAVE / 2);
+        if (live && lane < NACC) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int s = 2 * pw + h;
+                const int32_t t0 = B->tile0[s];
+                if (t0 < 0) continue;
                 if (BASKET) {
-                    t[1] += x;
+                    if (A[h]) atomicAdd(&R[t0], A[h]);
                     continue;
                 }
+                uint32_t cnt[8];
 #pragma unroll
-                for (int m = 1; m <= 7; ++m) t[m] += (x >> (4 * (m - 1))) & 15u;
-            }
-            wave_sync4();
+                for (int m = 1; m <= 7; ++m) {
+                    const int f = 7 * h + m - 1;   // field f: byte f / 4 of class f % 4
+                    cnt[m] = (A[f % 4] >> (8 * (f / 4))) & 0xFFu;
+                }
+                const uint32_t bm = B->bmask[s];
+                int q = 0;
 #pragma unroll
-            for (int m = 1; m <= 7; ++m) t[m] += __shfl_xor(t[m], HALF);
-            const int s = h * HALF + sl;
-            const int32_t t0 = B->tile0[s];
-            if (live && lane < HALF && t0 >= 0) {
-                if (BASKET) {
-                    if (t[1]) atomicAdd(&R[t0], t[1]);
-                } else {
-                    const uint32_t bm = B->bmask[s];
-                    int q = 0;
+                for (int b = 1; b <= 7; ++b) {
+                    if (!(bm & (1u << b))) continue;
+                    uint32_t r = 0u;
 #pragma unroll
-                    for (int b = 1; b <= 7; ++b) {
-                        if (!(bm & (1u << b))) continue;
-                        uint32_t r = 0u;
-#pragma unroll
-                        for (int m = 1; m <= 7; ++m)
-                            if (m & b) r += t[m];
-                        if (r) atomicAdd(&R[t0 + q], r);
-                        ++q;
-                    }
+                    for (int m = 1; m <= 7; ++m)
+                        if (m & b) r += cnt[m];
+                    if (r) atomicAdd(&R[t0 + q], r);
+                    ++q;
                 }
             }
         }
 #pragma unroll
-        for (int s = 0; s < B4S; ++s) acc[s] = 0u;
+        for (int p = 0; p < NACC; ++p) acc[p] = 0u;
         __syncthreads();   // transposes read before the next chunk's words overwrite them
     };
 
-    int since = 0;
+    int since = 0, since_acc = 0;
     for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
         const bool act = k < ke;
@@ -347,72 +360,71 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         if (live) {
             float *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * n_rows * WAVE + lane;
             // Neighbouring thresholds of an arm often give a simulation the same count, and then
-            // two slots share the outcome.  The slots of one (u0, u1) form a group: its gathers
-            // are issued first, skipping a slot whose outcome equals that of the slot at the
-            // previous u3 or u2 (fewer gathers are fewer L2 requests, the table being read at
-            // random rows), then one wait, then the slots are evaluated and their keys stored.
-            // Vector memory counts loads and stores together, so a gather used right after the
-            // previous slot's key stores would also wait for those stores.
+            // two slots share the outcome.  The 16 slots of one u0 form a group: its gathers are
+            // issued first, skipping a slot whose outcome equals that of the slot at the previous
+            // u1, u3 or u2 (fewer gathers are fewer L2 requests, the table being read at random
+            // rows), then one wait, then the slots are evaluated and their keys stored.  Vector
+            // memory counts loads and stores together, so a gather used right after the previous
+            // slot's key stores would also wait for those stores.
+            constexpr int S2 = B4N3, S1 = B4N2 * B4N3, G = B4N1 * S1;
 #pragma unroll
-            for (int u0 = 0; u0 < B4N0; ++u0)
+            for (int u0 = 0; u0 < B4N0; ++u0) {
+                float4 qs[G];
+                uint32_t ms[G];
+                // whether slot i of the group repeats the outcome of the slot at u1 - 1, u3 - 1, u2 - 1
+                auto repeats = [&](int i, bool &r1, bool &r3, bool &r2) {
+                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
+                    r1 = u1 > 0 && B->row0[u1 > 0 ? s - S1 : s] >= 0 && y1[u1] == y1[u1 > 0 ? u1 - 1 : 0];
+                    r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[u3 > 0 ? u3 - 1 : 0];
+                    r2 = u2 > 0 && B->row0[u2 > 0 ? s - S2 : s] >= 0 && y2[u2] == y2[u2 > 0 ? u2 - 1 : 0];
+                };
 #pragma unroll
-                for (int u1 = 0; u1 < B4N1; ++u1) {
-                    float4 qs[B4N2][B4N3];
-                    uint32_t ms[B4N2][B4N3];
-                    auto slot_of = [&](int u2, int u3) { return ((u0 * B4N1 + u1) * B4N2 + u2) * B4N3 + u3; };
+                for (int i = 0; i < G; ++i) {
+                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
+                    qs[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+                    ms[i] = 0u;
+                    if (B->row0[s] < 0) continue;   // uniform: the slot holds no box
+                    bool r1, r3, r2;
+                    repeats(i, r1, r3, r2);
+                    if (!(r1 || r2 || r3)) {
+                        const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
+                        if (KEYS) qs[i] = tbl[idx];
+                        else ms[i] = (uint32_t)mtbl[idx];
+                    }
+                }
+                // vmcnt 0, expcnt and lgkmcnt left alone: the group's rows are in registers
+                __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
-                    for (int u2 = 0; u2 < B4N2; ++u2)
-#pragma unroll
-                        for (int u3 = 0; u3 < B4N3; ++u3) {
-                            qs[u2][u3] = make_float4(0.f, 0.f, 0.f, 0.f);
-                            ms[u2][u3] = 0u;
-                            const int s = slot_of(u2, u3);
-                            if (B->row0[s] < 0) continue;   // uniform: the slot holds no box
-                            const bool r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[u3 > 0 ? u3 - 1 : 0];
-                            const bool r2 = u2 > 0 && B->row0[u2 > 0 ? s - B4N3 : s] >= 0 &&
-                                            y2[u2] == y2[u2 > 0 ? u2 - 1 : 0];
-                            if (!(r2 || r3)) {
-                                const int idx = ((y0[u0] * M1 + y1[u1]) * M1 + y2[u2]) * M1 + y3[u3];
-                                if (KEYS) qs[u2][u3] = tbl[idx];
-                                else ms[u2][u3] = (uint32_t)mtbl[idx];
-                            }
-                        }
-                    // vmcnt 0, expcnt and lgkmcnt left alone: the group's rows are in registers
-                    __builtin_amdgcn_s_waitcnt(0x0F70);
-#pragma unroll
-                    for (int u2 = 0; u2 < B4N2; ++u2)
-#pragma unroll
-                        for (int u3 = 0; u3 < B4N3; ++u3) {
-                            const int s = slot_of(u2, u3);
-                            const int32_t row0 = B->row0[s];
-                            if (row0 < 0) continue;   // uniform
-                            const int p2 = u2 > 0 ? u2 - 1 : 0, p3 = u3 > 0 ? u3 - 1 : 0;
-                            const bool r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[p3];
-                            const bool r2 = u2 > 0 && B->row0[u2 > 0 ? s - B4N3 : s] >= 0 && y2[u2] == y2[p2];
-                            // a repeat takes its source's row (resolved earlier in the group);
-                            // selects between values, not between array elements (a select of
-                            // addresses would keep the arrays out of registers)
-                            float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
-                            uint32_t m;
-                            if (KEYS) {
-                                const float4 a3 = qs[u2][p3], a2 = qs[p2][u3], a0 = qs[u2][u3];
-                                q.x = r3 ? a3.x : (r2 ? a2.x : a0.x);
-                                q.y = r3 ? a3.y : (r2 ? a2.y : a0.y);
-                                q.z = r3 ? a3.z : (r2 ? a2.z : a0.z);
-                                if (BASKET) q.w = r3 ? a3.w : (r2 ? a2.w : a0.w);
-                                qs[u2][u3] = q;
-                                m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u) |
-                                           (BASKET && q.w < cut ? 8u : 0u))
-                                        : 0u;
-                            } else {
-                                const uint32_t b3 = ms[u2][p3], b2 = ms[p2][u3], b0 = ms[u2][u3];
-                                const uint32_t mm = r3 ? b3 : (r2 ? b2 : b0);
-                                ms[u2][u3] = mm;
-                                m = act ? mm : 0u;
-                            }
+                for (int i = 0; i < G; ++i) {
+                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
+                    const int32_t row0 = B->row0[s];
+                    if (row0 < 0) continue;   // uniform
+                    bool r1, r3, r2;
+                    repeats(i, r1, r3, r2);
+                    const int i1 = u1 > 0 ? i - S1 : i, i3 = u3 > 0 ? i - 1 : i, i2 = u2 > 0 ? i - S2 : i;
+                    // a repeat takes its source's row (resolved earlier in the group); selects
+                    // between values, not between array elements (a select of addresses would keep
+                    // the arrays out of registers)
+                    float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
+                    uint32_t m;
+                    if (KEYS) {
+                        const float4 a1 = qs[i1], a3 = qs[i3], a2 = qs[i2], a0 = qs[i];
+                        q.x = r1 ? a1.x : (r3 ? a3.x : (r2 ? a2.x : a0.x));
+                        q.y = r1 ? a1.y : (r3 ? a3.y : (r2 ? a2.y : a0.y));
+                        q.z = r1 ? a1.z : (r3 ? a3.z : (r2 ? a2.z : a0.z));
+                        if (BASKET) q.w = r1 ? a1.w : (r3 ? a3.w : (r2 ? a2.w : a0.w));
+                        qs[i] = q;
+                        m = act ? ((q.x < cut ? 1u : 0u) | (q.y < cut ? 2u : 0u) | (q.z < cut ? 4u : 0u) |
+                                   (BASKET && q.w < cut ? 8u : 0u))
+                                : 0u;
+                    } else {
+                        const uint32_t mm = r1 ? ms[i1] : (r3 ? ms[i3] : (r2 ? ms[i2] : ms[i]));
+                        ms[i] = mm;
+                        m = act ? mm : 0u;
+                    }
                             if (BASKET) {
                                 const uint32_t b = (uint32_t)__builtin_ctz(B->bmask[s]);   // the slot's one b
-                                acc[s] += (m & b) ? 1u : 0u;
+                                acc[s >> 1] += (m & b) ? 1u << (16 * (s & 1)) : 0u;
                                 if (SCORE)
                                     add_score((m & b) != 0u, row0, B->tile0[s], (uint32_t)(y0[u0] | (y1[u1] << 16)),
                                               (uint32_t)(y2[u2] | (y3[u3] << 16)));
@@ -426,7 +438,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                                 }
                                 continue;
                             }
-                            acc[s] += m ? (1u << (4u * (m - 1u))) : 0u;
+                            acc[s >> 1] += m ? 1u << (14 * (s & 1) + 2 * (m - 1)) : 0u;
                             if (SCORE) {
                                 // the box's configurations b whose event m & b != 0 happened: byte m of
                                 // H4_REJ has bit b set when m & b != 0.  Rejections are rare at the 4-arm
@@ -455,12 +467,15 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
                                     ++row;
                                 }
                             }
-                        }
                 }
+            }
         }
-        if (++since == FLUSH_EVERY) {   // basket counters are plain 32-bit: only the score rows
-            if (!BASKET) flush();
-            if (SCORE && live) flush_scores();
+        if (++since_acc == ACC_EVERY) {
+            flush();
+            since_acc = 0;
+        }
+        if (SCORE && ++since == FLUSH_EVERY) {
+            if (live) flush_scores();
             since = 0;
         }
     }
