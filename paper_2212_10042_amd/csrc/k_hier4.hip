@@ -102,10 +102,10 @@ hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStre
 // chunk's 140 words through LDS.  Per (simulation, box slot): one 16-byte gather of
 // (1 - P_1, 1 - P_2, 1 - P_3) at the outcome y; the design rejects treatment arm i when
 // 1 - P_i < cut, giving a 3-bit mask m; configuration b's FWER event is m & b != 0.  Per box the
-// lanes count each mask value (7 packed 4-bit counters in one word, exact for 15 simulations
-// per lane between flushes, which transpose the counters through the word buffer in two
-// halves of 32 slots), so R_b = sum_{m & b != 0} count[m] for every b of the box.  LDS is the
-// 35 KB word buffer only, so four workgroups fit on a CU.
+// lanes count each mask value (7 packed 2-bit counters per slot, two slots per word, exact for
+// 3 simulations per lane between flushes, which transpose the counters through the word
+// buffer), so R_b = sum_{m & b != 0} count[m] for every b of the box.  LDS is the 35 KB word
+// buffer and the score rows, so four workgroups fit on a CU.
 // Calibration keys: S_b = min_{i in b} (1 - P_i) per (simulation, tile), float32.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ void wave_sync4() {
@@ -115,8 +115,8 @@ __device__ __forceinline__ void wave_sync4() {
 }
 
 // BASKET: the basket design (four hypotheses, arm a <-> bit a, q.w used): every slot holds one
-// piece with a single configuration b, so each lane counts that configuration's events in a
-// plain 32-bit counter per slot (no packed fields, one flush at the end).
+// piece with a single configuration b, so each lane counts that configuration's events in one
+// 16-bit field per slot (two slots per word, flushed every 4,096 chunks).
 // SCORE: also the score sums of every tile, sum over its rejecting simulations of the arm counts
 // y_a (the sufficient statistic, Example 1), as packed pairs (y0 | y1 << 16, y2 | y3 << 16),
 // added to the tile's row in LDS with LDS atomics.  4-arm lanes add their own pairs (rejections
