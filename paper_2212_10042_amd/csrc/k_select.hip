@@ -557,15 +557,27 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
         // without a branch, to the thread's next free slot when it lies in the bracket and to
         // the thread's last slot (scratch) otherwise; a thread with more than SEL_TSLOTS - 1
         // bracket keys sends the tile to the exact path.
-        uint32_t lt = 0u, nin = 0u;
+        // lt: this wave's keys below the bracket (the same in every lane); per key two compares,
+        // scalar adds for the count, and the slot store
+        // nin_w: this wave's keys in the bracket; a thread whose bracket keys outnumber its
+        // SEL_TSLOTS - 1 slots makes the wave's filled slots fall short of nin_w
+        uint32_t lt = 0u, nin_w = 0u;
+        char *const sbase = reinterpret_cast<char *>(slots);
+        const uint32_t scratch_off = (uint32_t)(((SEL_TSLOTS - 1) * SEL_WG + tid) * 4);
+        uint32_t next_off = (uint32_t)(tid * 4);   // byte offset of the thread's next free slot (stops at the scratch slot)
         auto take = [&](uint32_t u, bool valid) {
-            lt += (valid && u < lo) ? 1u : 0u;
-            const bool in = valid && u - lo <= hi - lo;
-            const uint32_t sl = (in && nin < (uint32_t)(SEL_TSLOTS - 1)) ? nin : (uint32_t)(SEL_TSLOTS - 1);
-            slots[sl * SEL_WG + tid] = u;
-            nin += in ? 1u : 0u;
+            const bool ge = u >= lo, le = u <= hi;
+            const bool in = valid && ge && le;
+            lt += (uint32_t)__popcll(__ballot(valid && !ge));
+            nin_w += (uint32_t)__popcll(__ballot(in));
+            *reinterpret_cast<uint32_t *>(sbase + (in ? next_off : scratch_off)) = u;
+            next_off = min(next_off + (in ? (uint32_t)(SEL_WG * 4) : 0u), scratch_off);
         };
         if (VEC4) {
+            // the 4-arm and basket keys are 1 - P >= +0 (min over arms of float64 values in
+            // [0, 1], rounded): their order key is the bit pattern with the sign bit set, which
+            // is f2ord for non-negative floats (the sample and the exact paths keep f2ord)
+            auto ord_nn = [](float x) { return __float_as_uint(x) ^ 0x80000000u; };
             constexpr int QB = 4;   // float4 per thread per round: 16 keys
             const int nq = ((n + 63) >> 6) * 16;
             for (int q0 = 0; q0 < nq; q0 += SEL_WG * QB) {
@@ -576,13 +588,23 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
                     v[i] = q < nq ? *reinterpret_cast<const float4 *>(kt + (int64_t)(q >> 4) * stride + (q & 15) * 4)
                                   : make_float4(0.f, 0.f, 0.f, 0.f);
                 }
+                if (4 * (q0 + SEL_WG * QB) <= n) {   // uniform: every key of the round is a simulation's
+#pragma unroll
+                    for (int i = 0; i < QB; ++i) {
+                        take(ord_nn(v[i].x), true);
+                        take(ord_nn(v[i].y), true);
+                        take(ord_nn(v[i].z), true);
+                        take(ord_nn(v[i].w), true);
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int i = 0; i < QB; ++i) {
                     const int j = 4 * (q0 + i * SEL_WG + tid);
-                    take(f2ord(v[i].x), j + 0 < n);
-                    take(f2ord(v[i].y), j + 1 < n);
-                    take(f2ord(v[i].z), j + 2 < n);
-                    take(f2ord(v[i].w), j + 3 < n);
+                    take(ord_nn(v[i].x), j + 0 < n);
+                    take(ord_nn(v[i].y), j + 1 < n);
+                    take(ord_nn(v[i].z), j + 2 < n);
+                    take(ord_nn(v[i].w), j + 3 < n);
                 }
             }
         } else {
@@ -598,11 +620,14 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
                 for (int i = 0; i < SEL_BATCH; ++i) take(u[i], j0 + i * SEL_WG + tid < n);
             }
         }
-        for (int off = 32; off >= 1; off >>= 1) lt += __shfl_xor(lt, off);
-        if (lane == 0) atomicAdd(&s_lt, lt);
-        if (nin > (uint32_t)(SEL_TSLOTS - 1)) s_over = 1u;
         // the threads' bracket keys, compacted into the candidate buffer in thread order
-        const uint32_t mine = nin < (uint32_t)(SEL_TSLOTS - 1) ? nin : (uint32_t)(SEL_TSLOTS - 1);
+        const uint32_t mine = (next_off - (uint32_t)(tid * 4)) / (uint32_t)(SEL_WG * 4);
+        uint32_t filled = mine;
+        for (int off = 32; off >= 1; off >>= 1) filled += __shfl_xor(filled, off);
+        if (lane == 0) {
+            atomicAdd(&s_lt, lt);
+            if (filled != nin_w) s_over = 1u;   // some thread ran out of slots
+        }
         block_exclusive_scan(mine, part);   // synchronises: s_lt and s_over are complete after it
         const uint32_t off = part[tid];
         if (tid == SEL_WG - 1) s_bin = off + mine;   // total, through a spare word
