@@ -141,7 +141,7 @@ __device__ __forceinline__ uint32_t row16_sum(uint32_t v) {
 }
 constexpr uint64_t H4_REJ = 0xFEFCFAF0EECCAA00ull;   // byte m: configurations b (bits 1..7) with m & b != 0
 template <bool KEYS, bool BASKET, bool SCORE>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_hier4(const Blk4 *__restrict__ blocks,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(KEYS ? 4 : 5, KEYS ? 4 : 5))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
                                               const float4 *__restrict__ tbl, const uint8_t *__restrict__ mtbl,
@@ -150,12 +150,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     constexpr int NP = NP35;
     constexpr int NW = 4 * NP;
     constexpr int NB = NW / 4;   // 35 Philox blocks
+    constexpr int NBH = (NB + 1) / 2;   // blocks of the first half (18: words 0..71), then 17 (words 72..139)
+    constexpr int NWH = 4 * NBH;        // words held at once
     constexpr int NWAVES = WG / WAVE;
     constexpr int M1 = NP + 1;
     constexpr int FLUSH_EVERY = 15;        // score rows: 16-bit fields hold 15 chunks
-    // The chunk's Philox words; between chunks the same memory holds the counter transposes
-    // (per wave 32 x (64 + 1) words, padded against bank conflicts).
-    __shared__ uint32_t words[NW][WAVE];
+    // Half of the chunk's Philox words at a time; between chunks the same memory holds the
+    // counter transposes (per wave 16 x (64 + 1) words, padded against bank conflicts).
+    __shared__ uint32_t words[NWH][WAVE];
     __shared__ uint2 ysum[SCORE ? NWAVES : 1][SCORE ? H4_SROWS : 1];   // per wave and key row: packed y sums
 
     const int lane = threadIdx.x & (WAVE - 1);
@@ -245,8 +247,9 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     // Half the registers of one word per slot, which leaves room for a whole group's table rows.
     constexpr int NACC = B4S / 2;
     constexpr int ACC_EVERY = BASKET ? 4096 : 3;
-    static_assert(NWAVES * NACC * (WAVE + 1) <= NW * WAVE, "flush transposes must fit in the word buffer");
-    uint32_t(*tr)[NACC][WAVE + 1] = reinterpret_cast<uint32_t(*)[NACC][WAVE + 1]>(&words[0][0]);
+    constexpr int TRW = NACC / 2;   // counter words per flush half
+    static_assert(NWAVES * TRW * (WAVE + 1) <= NWH * WAVE, "flush transposes must fit in the word buffer");
+    uint32_t(*tr)[TRW][WAVE + 1] = reinterpret_cast<uint32_t(*)[TRW][WAVE + 1]>(&words[0][0]);
     uint32_t acc[NACC];
 #pragma unroll
     for (int p = 0; p < NACC; ++p) acc[p] = 0u;
@@ -257,52 +260,59 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     auto flush = [&]() {
         __syncthreads();   // the word buffer is free: every wave has finished counting
 #pragma unroll
-        for (int p = 0; p < NACC; ++p) tr[wv][p][lane] = acc[p];
-        wave_sync4();
-        const int pw = lane & (NACC - 1), j0 = (lane >> 5) * (WAVE / 2);
-        uint32_t A[4] = {0u, 0u, 0u, 0u};
-        for (int j = j0; j < j0 + WAVE / 2; ++j) {
-            const uint32_t x = tr[wv][pw][j];
-            if (BASKET) {
-                A[0] += x & 0xFFFFu;
-                A[1] += x >> 16;
-                continue;
-            }
+        for (int h = 0; h < 2; ++h) {   // counter words 16 h .. 16 h + 15 (slots 32 h .. 32 h + 31)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) A[c] += (x >> (2 * c)) & 0x03030303u;
-        }
-        wave_sync4();
-#pragma unroll
-        for (int c = 0; c < 4; ++c) A[c] += __shfl_xor(A[c], WAVE / 2);
-        if (live && lane < NACC) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const int s = 2 * pw + h;
-                const int32_t t0 = B->tile0[s];
-                if (t0 < 0) continue;
+            for (int p = 0; p < TRW; ++p) tr[wv][p][lane] = acc[h * TRW + p];
+            wave_sync4();
+            const int pw = lane & (TRW - 1), j0 = (lane / TRW) * (WAVE / 4);
+            uint32_t A[4] = {0u, 0u, 0u, 0u};
+            for (int j = j0; j < j0 + WAVE / 4; ++j) {
+                const uint32_t x = tr[wv][pw][j];
                 if (BASKET) {
-                    if (A[h]) atomicAdd(&R[t0], A[h]);
+                    A[0] += x & 0xFFFFu;
+                    A[1] += x >> 16;
                     continue;
                 }
-                uint32_t cnt[8];
 #pragma unroll
-                for (int m = 1; m <= 7; ++m) {
-                    const int f = 7 * h + m - 1;   // field f: byte f / 4 of class f % 4
-                    cnt[m] = (A[f % 4] >> (8 * (f / 4))) & 0xFFu;
-                }
-                const uint32_t bm = B->bmask[s];
-                int q = 0;
+                for (int c = 0; c < 4; ++c) A[c] += (x >> (2 * c)) & 0x03030303u;
+            }
+            wave_sync4();
 #pragma unroll
-                for (int b = 1; b <= 7; ++b) {
-                    if (!(bm & (1u << b))) continue;
-                    uint32_t r = 0u;
+            for (int c = 0; c < 4; ++c) {   // the four lane groups' sums (at most 3 x 64 per byte)
+                A[c] += __shfl_xor(A[c], TRW);
+                A[c] += __shfl_xor(A[c], 2 * TRW);
+            }
+            if (live && lane < TRW) {
 #pragma unroll
-                    for (int m = 1; m <= 7; ++m)
-                        if (m & b) r += cnt[m];
-                    if (r) atomicAdd(&R[t0 + q], r);
-                    ++q;
+                for (int hh = 0; hh < 2; ++hh) {
+                    const int s = 2 * (h * TRW + pw) + hh;
+                    const int32_t t0 = B->tile0[s];
+                    if (t0 < 0) continue;
+                    if (BASKET) {
+                        if (A[hh]) atomicAdd(&R[t0], A[hh]);
+                        continue;
+                    }
+                    uint32_t cnt[8];
+#pragma unroll
+                    for (int m = 1; m <= 7; ++m) {
+                        const int f = 7 * hh + m - 1;   // field f: byte f / 4 of class f % 4
+                        cnt[m] = (A[f % 4] >> (8 * (f / 4))) & 0xFFu;
+                    }
+                    const uint32_t bm = B->bmask[s];
+                    int q = 0;
+#pragma unroll
+                    for (int b = 1; b <= 7; ++b) {
+                        if (!(bm & (1u << b))) continue;
+                        uint32_t r = 0u;
+#pragma unroll
+                        for (int m = 1; m <= 7; ++m)
+                            if (m & b) r += cnt[m];
+                        if (r) atomicAdd(&R[t0 + q], r);
+                        ++q;
+                    }
                 }
             }
+            wave_sync4();   // this half's transposes are read before the next half's are written
         }
 #pragma unroll
         for (int p = 0; p < NACC; ++p) acc[p] = 0u;
@@ -313,14 +323,8 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
     for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
         const uint32_t k = k0 + (uint32_t)lane;
         const bool act = k < ke;
-        for (int b = wv; b < NB; b += NWAVES) {
-            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
-            words[4 * b + 0][lane] = w.x;
-            words[4 * b + 1][lane] = w.y;
-            words[4 * b + 2][lane] = w.z;
-            words[4 * b + 3][lane] = w.w;
-        }
-        __syncthreads();
+        // the words in two halves (LDS for half of them at a time): blocks 0..17 give arms 0
+        // and 1 and the first two words of arm 2, blocks 18..34 the rest of arm 2 and arm 3
         int y0[B4N0], y1[B4N1], y2[B4N2], y3[B4N3];
 #pragma unroll
         for (int u = 0; u < B4N0; ++u) y0[u] = 0;
@@ -330,6 +334,14 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
         for (int u = 0; u < B4N2; ++u) y2[u] = 0;
 #pragma unroll
         for (int u = 0; u < B4N3; ++u) y3[u] = 0;
+        for (int b = wv; b < NBH; b += NWAVES) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+            words[4 * b + 0][lane] = w.x;
+            words[4 * b + 1][lane] = w.y;
+            words[4 * b + 2][lane] = w.z;
+            words[4 * b + 3][lane] = w.w;
+        }
+        __syncthreads();
         if (live) {
 #pragma unroll 7
             for (int j = 0; j < NP; ++j) {
@@ -343,15 +355,32 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(4, 4))) void
 #pragma unroll
                 for (int u = 0; u < B4N1; ++u) y1[u] += (x < T1[u]) ? 1 : 0;
             }
-#pragma unroll 7
-            for (int j = 2 * NP; j < 3 * NP; ++j) {
+#pragma unroll
+            for (int j = 2 * NP; j < NWH; ++j) {
                 const uint32_t x = words[j][lane];
+#pragma unroll
+                for (int u = 0; u < B4N2; ++u) y2[u] += (x < T2[u]) ? 1 : 0;
+            }
+        }
+        __syncthreads();   // the first half is counted: its memory takes the second
+        for (int b = NBH + wv; b < NB; b += NWAVES) {
+            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
+            words[4 * (b - NBH) + 0][lane] = w.x;
+            words[4 * (b - NBH) + 1][lane] = w.y;
+            words[4 * (b - NBH) + 2][lane] = w.z;
+            words[4 * (b - NBH) + 3][lane] = w.w;
+        }
+        __syncthreads();
+        if (live) {
+#pragma unroll 11
+            for (int j = NWH; j < 3 * NP; ++j) {
+                const uint32_t x = words[j - NWH][lane];
 #pragma unroll
                 for (int u = 0; u < B4N2; ++u) y2[u] += (x < T2[u]) ? 1 : 0;
             }
 #pragma unroll 7
             for (int j = 3 * NP; j < 4 * NP; ++j) {
-                const uint32_t x = words[j][lane];
+                const uint32_t x = words[j - NWH][lane];
 #pragma unroll
                 for (int u = 0; u < B4N3; ++u) y3[u] += (x < T3[u]) ? 1 : 0;
             }
