@@ -141,7 +141,7 @@ __device__ __forceinline__ uint32_t row16_sum(uint32_t v) {
 }
 constexpr uint64_t H4_REJ = 0xFEFCFAF0EECCAA00ull;   // byte m: configurations b (bits 1..7) with m & b != 0
 template <bool KEYS, bool BASKET, bool SCORE>
-__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(KEYS ? 4 : 5, KEYS ? 4 : 5))) void k_hier4(const Blk4 *__restrict__ blocks,
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
                                               const float4 *__restrict__ tbl, const uint8_t *__restrict__ mtbl,
@@ -389,27 +389,35 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(KEYS ? 4 : 5
         if (live) {
             float *__restrict__ kc = kbase + (size_t)(k0 / WAVE) * n_rows * WAVE + lane;
             // Neighbouring thresholds of an arm often give a simulation the same count, and then
-            // two slots share the outcome.  The 16 slots of one u0 form a group: its gathers are
-            // issued first, skipping a slot whose outcome equals that of the slot at the previous
-            // u1, u3 or u2 (fewer gathers are fewer L2 requests, the table being read at random
-            // rows), then one wait, then the slots are evaluated and their keys stored.  Vector
-            // memory counts loads and stores together, so a gather used right after the previous
-            // slot's key stores would also wait for those stores.
-            constexpr int S2 = B4N3, S1 = B4N2 * B4N3, G = B4N1 * S1;
+            // two slots share the outcome.  The slots of one u0 and GU1 consecutive u1 form a
+            // group (16 slots; 8 in the keyed variants, whose rows take three registers each and
+            // which run 5 waves per SIMD): its gathers are issued first, skipping a slot whose
+            // outcome equals that of the slot at the previous u1 (same group), u3 or u2 (fewer
+            // gathers are fewer L2 requests, the table being read at random rows), then one
+            // wait, then the slots are evaluated and their keys stored.  Vector memory counts
+            // loads and stores together, so a gather used right after the previous slot's key
+            // stores would also wait for those stores.
+            constexpr int S2 = B4N3, S1 = B4N2 * B4N3;
+            constexpr int GU1 = KEYS ? 2 : B4N1;   // u1 values per group (keyed: fewer rows in registers)
+            constexpr int G = GU1 * S1;
 #pragma unroll
-            for (int u0 = 0; u0 < B4N0; ++u0) {
+            for (int ug = 0; ug < B4N0 * (B4N1 / GU1); ++ug) {
+                const int u0 = ug / (B4N1 / GU1), u1b = (ug % (B4N1 / GU1)) * GU1;
                 float4 qs[G];
                 uint32_t ms[G];
-                // whether slot i of the group repeats the outcome of the slot at u1 - 1, u3 - 1, u2 - 1
+                // whether slot i of the group repeats the outcome of the slot at u1 - 1 (same group),
+                // u3 - 1 or u2 - 1
                 auto repeats = [&](int i, bool &r1, bool &r3, bool &r2) {
-                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
-                    r1 = u1 > 0 && B->row0[u1 > 0 ? s - S1 : s] >= 0 && y1[u1] == y1[u1 > 0 ? u1 - 1 : 0];
+                    const int i1 = i / S1, u1 = u1b + i1, u2 = (i / S2) % B4N2, u3 = i % S2;
+                    const int s = (u0 * B4N1 + u1) * S1 + u2 * S2 + u3;
+                    r1 = i1 > 0 && B->row0[i1 > 0 ? s - S1 : s] >= 0 && y1[u1] == y1[u1 > 0 ? u1 - 1 : 0];
                     r3 = u3 > 0 && B->row0[u3 > 0 ? s - 1 : s] >= 0 && y3[u3] == y3[u3 > 0 ? u3 - 1 : 0];
                     r2 = u2 > 0 && B->row0[u2 > 0 ? s - S2 : s] >= 0 && y2[u2] == y2[u2 > 0 ? u2 - 1 : 0];
                 };
 #pragma unroll
                 for (int i = 0; i < G; ++i) {
-                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
+                    const int u1 = u1b + i / S1, u2 = (i / S2) % B4N2, u3 = i % S2;
+                    const int s = (u0 * B4N1 + u1) * S1 + u2 * S2 + u3;
                     qs[i] = make_float4(0.f, 0.f, 0.f, 0.f);
                     ms[i] = 0u;
                     if (B->row0[s] < 0) continue;   // uniform: the slot holds no box
@@ -425,12 +433,13 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(KEYS ? 4 : 5
                 __builtin_amdgcn_s_waitcnt(0x0F70);
 #pragma unroll
                 for (int i = 0; i < G; ++i) {
-                    const int u1 = i / S1, u2 = (i / S2) % B4N2, u3 = i % S2, s = u0 * G + i;
+                    const int u1 = u1b + i / S1, u2 = (i / S2) % B4N2, u3 = i % S2;
+                    const int s = (u0 * B4N1 + u1) * S1 + u2 * S2 + u3;
                     const int32_t row0 = B->row0[s];
                     if (row0 < 0) continue;   // uniform
                     bool r1, r3, r2;
                     repeats(i, r1, r3, r2);
-                    const int i1 = u1 > 0 ? i - S1 : i, i3 = u3 > 0 ? i - 1 : i, i2 = u2 > 0 ? i - S2 : i;
+                    const int i1 = i >= S1 ? i - S1 : i, i3 = u3 > 0 ? i - 1 : i, i2 = u2 > 0 ? i - S2 : i;
                     // a repeat takes its source's row (resolved earlier in the group); selects
                     // between values, not between array elements (a select of addresses would keep
                     // the arrays out of registers)
