@@ -436,10 +436,26 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
  * (cse_simulate / cse_validate / cse_calibrate): out (host int64 [4]) = trials simulated,
  * posterior evaluations at Phase II looks and at Phase III looks (the first look of every
  * trial is a table lookup and is not counted), Newton steps over all nodes of those looks.
+ * On a CSE_BINOM2_Z platten: out[0] = tiles that the last calibration's bracketed selection
+ * left to the exact full-histogram pass (k-th statistic outside the bracket, or the batch's
+ * brackets too wide for the histogram), out[1..3] = 0.
  * Synchronises `stream`.  Used to state the kernel's arithmetic per launch.
  * Errors: CSE_EINVAL (NULL out), CSE_EUNSUPPORTED (other designs), CSE_EHIP.
  */
 int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream);
+
+/*
+ * cse_platten_set_option -- tuning options of a platten (host call, no GPU work).
+ *   CSE_OPT_B2_MARGIN (CSE_BINOM2_Z calibration): the selection's bracket around each tile's
+ *        k-th statistic, in standard deviations of the count (default 5).  Results do not
+ *        depend on it: tiles whose k-th statistic falls outside the bracket take an exact
+ *        full-histogram pass (cse_work_counters counts them); a smaller margin lists fewer
+ *        simulations in the bracketed pass but sends more tiles to the exact one.  A plan
+ *        captured earlier keeps the margin it was captured with.
+ * Errors: CSE_EINVAL (bad handle, unknown option, value outside [0, 100]).
+ */
+#define CSE_OPT_B2_MARGIN 1
+int cse_platten_set_option(cse_platten *p, int32_t option, double value);
 
 /*
  * cse_posterior_table -- the design table of a CSE_HIER4 platten: for every outcome

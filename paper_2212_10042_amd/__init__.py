@@ -33,7 +33,8 @@ EXPORTED = ("cse_platten_create", "cse_platten_destroy", "cse_platten_size", "cs
             "cse_posterior_table", "cse_work_counters", "cse_plan_validate", "cse_plan_calibrate",
             "cse_plan_launch", "cse_plan_nodes", "cse_plan_destroy", "cse_autotune", "cse_taylor",
             "cse_validate_lower", "cse_confidence_set", "cse_calibrate_tiebreak", "cse_adagrid_decide",
-            "cse_adagrid_apply", "cse_platten_tiles", "cse_calibrate_noalloc", "cse_last_error")
+            "cse_adagrid_apply", "cse_platten_tiles", "cse_calibrate_noalloc", "cse_platten_set_option",
+            "cse_last_error")
 
 
 class CseError(RuntimeError):
@@ -76,6 +77,7 @@ def _load():
     L.cse_platten_stats.argtypes = [P, P]
     L.cse_posterior_table.argtypes = [P, P, i64, ctypes.POINTER(i64), P]
     L.cse_work_counters.argtypes = [P, P, P]
+    L.cse_platten_set_option.argtypes = [P, i32, dbl]
     L.cse_plan_validate.argtypes = [P, u64, dbl] + [P] * 7 + [ctypes.POINTER(P)]
     L.cse_plan_calibrate.argtypes = [P, u64, dbl, P, P, P, P, P, dbl] + [P] * 6 + [ctypes.POINTER(P)]
     L.cse_plan_launch.argtypes = [P, P]
@@ -321,9 +323,18 @@ def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):
     return int(out[0]), int(out[1])
 
 
+CSE_OPT_B2_MARGIN = 1   # 2-arm calibration: bracket margin (standard deviations of the count)
+
+
+def cse_platten_set_option(h, option, value):
+    """Set a platten tuning option (CSE_OPT_B2_MARGIN)."""
+    _check("cse_platten_set_option", _L.cse_platten_set_option(h, int(option), float(value)))
+
+
 def cse_work_counters(h, stream=None) -> dict:
     """Phase II/III design: trials, posterior looks (Phase II, Phase III) and Newton steps of
-    the last simulation launch."""
+    the last simulation launch.  2-arm design: `trials` holds the tiles the last calibration
+    left to the exact full-histogram pass."""
     out = np.zeros(4, np.int64)
     _check("cse_work_counters", _L.cse_work_counters(h, _ptr(out), _stream(stream)))
     return dict(trials=int(out[0]), looks_phase2=int(out[1]), looks_phase3=int(out[2]),

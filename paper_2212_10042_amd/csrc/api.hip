@@ -825,6 +825,20 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
     return CSE_OK;
 }
 
+int cse_platten_set_option(cse_platten *p, int32_t option, double value) {
+    if (int e = check_handle(p, "cse_platten_set_option")) return e;
+    if (option != CSE_OPT_B2_MARGIN) {
+        set_error("cse_platten_set_option: unknown option");
+        return CSE_EINVAL;
+    }
+    if (!(value >= 0.0 && value <= 100.0)) {
+        set_error("cse_platten_set_option: the bracket margin must lie in [0, 100]");
+        return CSE_EINVAL;
+    }
+    p->P.b2_margin = (float)value;
+    return CSE_OK;
+}
+
 int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream) {
     if (int e = check_handle(p, "cse_work_counters")) return e;
     const auto &P = p->P;
@@ -832,8 +846,17 @@ int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream) {
         set_error("cse_work_counters: NULL out");
         return CSE_EINVAL;
     }
+    if (P.design.kind == CSE_BINOM2_Z) {   // tiles of the last calibration left to the exact pass
+        uint32_t n_fb = 0u;
+        hipStream_t st = (hipStream_t)stream;
+        CSE_HIP_TRY(hipMemcpyAsync(&n_fb, P.d_b2fb, sizeof n_fb, hipMemcpyDeviceToHost, st));
+        CSE_HIP_TRY(hipStreamSynchronize(st));
+        out[0] = (int64_t)n_fb;
+        out[1] = out[2] = out[3] = 0;
+        return CSE_OK;
+    }
     if (P.design.kind != CSE_PHASE23) {
-        set_error("cse_work_counters: only the Phase II/III design counts its work");
+        set_error("cse_work_counters: only the Phase II/III and 2-arm designs count their work");
         return CSE_EUNSUPPORTED;
     }
     unsigned long long h[4] = {0, 0, 0, 0};

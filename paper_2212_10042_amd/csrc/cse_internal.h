@@ -199,6 +199,7 @@ struct Platten {
     int32_t *d_gstart = nullptr;         // 2-arm: first position of each tie group of S, [n_groups + 1]
     uint8_t *d_gcut = nullptr;           // 2-arm: per tie group g and y0, #{y1 : S(y0, y1) >= S_g}, [n_groups + 1][n + 1]
     int32_t n_groups = 0;
+    float b2_margin = 5.0f;              // 2-arm selection: bracket margin in standard deviations of the count
     int32_t n_outcomes = 0;
     // 2-arm calibration: per-tile bracket of S-order positions [lo, hi] expected to hold the
     // k-th smallest statistic, and the list of tiles the bracketed selection left to the exact

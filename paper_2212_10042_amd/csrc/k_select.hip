@@ -46,7 +46,8 @@ __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
 //  * k_b2_bracket: per tile, the exact law of (y0, y1) under the simulated model (independent
 //    Binomial(35, T/2^32) arms) gives a bracket [lo, hi] of positions (whole tie groups, found by
 //    binary search over the groups) holding the k-th smallest S unless the count below lo reaches
-//    k or the count up to hi stays below k, each about 5 standard deviations of the count away.
+//    k or the count up to hi stays below k, each a margin (5 by default, cse_platten_set_option)
+//    of standard deviations of the count away.
 //    As S does not increase with y1 for fixed y0, S < S(lo) iff y1 >= clo(y0) and S <= S(hi) iff
 //    y1 >= chi(y0): the kernel also writes, per batch row u and count y0, the cut points clo, chi
 //    of the row's 8 tiles as bytes (16 bytes);
@@ -60,7 +61,6 @@ __device__ void block_exclusive_scan(uint32_t v, uint32_t *part) {
 // Either way lambda*_i is the exact k-th smallest S and rej_at the exact count strictly below it.
 constexpr int B2_N1 = NP35 + 1;            // outcomes per arm
 constexpr int B2_NOUT = B2_N1 * B2_N1;     // 1,296 outcomes
-constexpr float B2_Z = 5.0f;               // bracket margin in standard deviations of the count
 constexpr int B2_HB = 4096;                // LDS histogram bins of one batch (16 KB)
 
 __device__ __forceinline__ uint32_t rec_byte(uint32_t w, int b) { return (w >> (8 * b)) & 0xFFu; }
@@ -85,7 +85,7 @@ __global__ __launch_bounds__(WAVE) void k_b2_bracket(const Blk2 *__restrict__ bl
                                                      const int32_t *__restrict__ gstart,
                                                      const uint8_t *__restrict__ gcut, int n_groups,
                                                      int2 *__restrict__ br, uint4 *__restrict__ cut,
-                                                     uint32_t *__restrict__ fb) {
+                                                     uint32_t *__restrict__ fb, float zmargin) {
     __shared__ float tail1[B2_N1 + 1][WAVE];   // P(y1 >= c) of each lane's tile, c = 0..36
     __shared__ uint8_t cb[B2U][B2_N1][16];     // per row and y0: clo of the 8 tiles, then chi
     const int lane = threadIdx.x;
@@ -130,7 +130,7 @@ __global__ __launch_bounds__(WAVE) void k_b2_bracket(const Blk2 *__restrict__ bl
         return sum;
     };
     const float kf = (float)k, sd = sqrtf(kf + 1.0f);
-    const float lo_t = kf - B2_Z * sd - 2.0f, hi_t = kf + B2_Z * sd + 2.0f;
+    const float lo_t = kf - zmargin * sd - 2.0f, hi_t = kf + zmargin * sd + 2.0f;
     const float Nf = (float)N;
     int a = 0, b = n_groups;            // lo group: the last g with N P(S < S_g) <= lo_t (g = 0 has 0)
     while (b - a > 1) {
@@ -1264,7 +1264,7 @@ hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, d
 // list of tiles left to the exact full pass.
 hipError_t launch_b2_bracket(const Platten &P, const int32_t *k, hipStream_t st) {
     hipLaunchKernelGGL(k_b2_bracket, dim3((uint32_t)P.n_blocks), dim3(WAVE), 0, st, (const Blk2 *)P.d_blocks, k,
-                       P.d_gstart, P.d_gcut, P.n_groups, P.d_b2br, P.d_b2cut, P.d_b2fb);
+                       P.d_gstart, P.d_gcut, P.n_groups, P.d_b2br, P.d_b2cut, P.d_b2fb, P.b2_margin);
     return hipGetLastError();
 }
 

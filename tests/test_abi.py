@@ -109,6 +109,8 @@ def test_null_handles_rejected_newer_entry_points():
     assert L.cse_taylor(None, None, None, None, None, None, None) == cse.CSE_EINVAL
     assert L.cse_platten_tiles(None, None, None) == cse.CSE_EINVAL
     assert L.cse_adagrid_decide(None, 0, None, None, 0, None, None, None, None, None) == cse.CSE_EINVAL
+    assert L.cse_platten_set_option(None, cse.CSE_OPT_B2_MARGIN, 3.0) == cse.CSE_EINVAL
+    assert L.cse_work_counters(None, None, None) == cse.CSE_EINVAL
 
 
 @pytest.mark.parametrize("case", ["basket_theta0_nan", "basket_n_per_arm", "sims_too_many"])

@@ -321,3 +321,39 @@ def test_bound_search_paths_agree():
     np.testing.assert_allclose(_np(up)[idx], _np(uq), rtol=1e-9)
     P.close()
     Q.close()
+
+
+@pytest.mark.parametrize("margin", [0.0, 100.0])
+def test_selection_exact_pass_forced(margin):
+    """The bracketed selection with a zero margin (most tiles' k-th statistic falls outside the
+    bracket) or a very wide one (the batches' brackets overflow the LDS histogram): those tiles
+    take the exact full-histogram pass, and lambda*_i and the counts below it still equal the
+    oracle's and the default margin's; cse_work_counters counts the tiles sent there."""
+    w = W.binom2_grid(16, 3000, lo=-2.0, hi=0.5, seed=7)
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    print(f"[binom2] exact selection pass, margin {margin}", flush=True)
+    P = cse.Platten.create("binom2", th, rd, sm)
+    g0 = P.calibrate(7, alpha=0.05, with_validation=False)
+    torch.cuda.synchronize()
+    n0 = cse.cse_work_counters(P.handle)["trials"]
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_B2_MARGIN, margin)
+    g1 = P.calibrate(7, alpha=0.05, with_validation=False)
+    torch.cuda.synchronize()
+    n1 = cse.cse_work_counters(P.handle)["trials"]
+    print(f"[binom2] tiles in the exact pass: {n0} at the default margin, {n1} at {margin}", flush=True)
+    assert n1 > n0
+    if margin == 0.0:
+        assert n1 >= P.n_tiles // 4
+    for key in ("lambda_tile", "reject_at_lambda", "k"):
+        assert np.array_equal(_np(g1[key]), _np(g0[key]))
+    assert float(_np(g1["lambda_global"])[0]) == float(_np(g0["lambda_global"])[0])
+    oc = O.calibrate("binom2", th, rd, sm, 7, 0.05)
+    _check_k(_np(g1["k"]), oc["k"], oc["alpha_prime"], oc["N"])
+    same_k = _np(g1["k"]) == oc["k"]
+    assert np.array_equal(_np(g1["lambda_tile"])[same_k], oc["lam"][same_k])
+    assert np.array_equal(_np(g1["reject_at_lambda"])[same_k], oc["reject_at_lam"][same_k])
+    with pytest.raises(cse.CseError):
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_B2_MARGIN, -1.0)
+    with pytest.raises(cse.CseError):
+        cse.cse_platten_set_option(P.handle, 99, 1.0)
+    P.close()
