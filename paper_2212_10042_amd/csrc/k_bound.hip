@@ -264,6 +264,40 @@ __device__ double section_search(int lane, const TileGeom<D> &T, double loga, do
 constexpr double BRENT_TOL = 2e-7;
 constexpr int BRENT_MAXIT = 80;
 
+// A starting point for the search: expanding the log-partition differences to second order,
+// psi(theta, v, q) / q - psi(theta, v, 1) ~ (q - 1) v'H v / 2 with H the Fisher information at
+// theta, so log U ~ (1 - 1/q) L + (q - 1) sigma^2 / 2 (sigma^2 the largest v'H v over the
+// vertices), least at q = sqrt(2 |L| / sigma^2); returns log(q - 1), or NaN when the expansion
+// gives no point.  The same point serves the inverse (its optimum differs at higher order).
+template <int FAM, int D>
+__device__ double start_s(const TileGeom<D> &T, double L) {
+    double h[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (FAM == FAM_NORMAL) {
+            h[a] = 1.0;
+        } else {
+            const double p = 1.0 / (1.0 + exp(-T.th[a]));
+            h[a] = (double)T.n * p * (1.0 - p);
+        }
+    }
+    double s2 = 0.0;
+    if (T.box) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) s2 += T.r[a] * T.r[a] * h[a];
+    } else {
+        for (int j = 0; j < T.nv; ++j) {
+            double t = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) t += T.V[j * D + a] * T.V[j * D + a] * h[a];
+            s2 = fmax(s2, t);
+        }
+    }
+    if (!(s2 > 0.0) || !(L < 0.0)) return NAN;
+    const double q = sqrt(-2.0 * L / s2);
+    return q > 1.0 + 1e-9 ? log(q - 1.0) : NAN;
+}
+
 template <int FAM, int D, bool INV>
 __device__ double brent_search(const TileGeom<D> &T, double loga, double *s_best) {
     const double sg = INV ? -1.0 : 1.0;    // minimise sg * objective
@@ -273,9 +307,47 @@ __device__ double brent_search(const TileGeom<D> &T, double loga, double *s_best
         return f != f ? INFINITY : f;
     };
     double a = -30.0, b = 30.0;
-    double x = a + cg * (b - a), w = x, v = x;
-    double fx = ev(x), fw = fx, fv = fx;
+    double x, w, v, fx, fw, fv;
     double d = 0.0, e = 0.0;
+    // three points around the expansion's optimum s0: when the middle one is lowest the optimum
+    // lies within s0 +- 1 (the objective is unimodal), else on the side of the lower end; the
+    // search then starts from those points with a parabolic step.  The start changes the work,
+    // not the optimum found (to BRENT_TOL).
+    const double s0 = start_s<FAM, D>(T, loga);
+    bool seeded = false;
+    if (s0 > -29.0 && s0 < 29.0) {
+        const double sl = s0 - 1.0, sh = s0 + 1.0;
+        const double fl = ev(sl), fm = ev(s0), fh = ev(sh);
+        if (fm < INFINITY) {
+            seeded = true;
+            if (fm <= fl && fm <= fh) {
+                a = sl;
+                b = sh;
+                x = s0, fx = fm;
+                w = sl, fw = fl;
+                v = sh, fv = fh;
+            } else if (fl < fm) {   // the optimum lies below s0
+                b = s0;
+                x = sl, fx = fl;
+                w = s0, fw = fm;
+                v = s0, fv = fm;
+            } else {                // above s0
+                a = s0;
+                x = sh, fx = fh;
+                w = s0, fw = fm;
+                v = s0, fv = fm;
+            }
+            e = b - a;
+        }
+    }
+    if (!seeded) {
+        x = a + cg * (b - a);
+        w = x;
+        v = x;
+        fx = ev(x);
+        fw = fx;
+        fv = fx;
+    }
     for (int it = 0; it < BRENT_MAXIT; ++it) {
         const double xm = 0.5 * (a + b);
         const double tol1 = 0.5 * BRENT_TOL, tol2 = BRENT_TOL;
