@@ -66,7 +66,7 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # size).  Valid only while that kernel is unchanged; workloads not listed report null.
 TRAFFIC = {
     "binom2_1024_full": 4_388_219_655,   # k_binom2<true>: 17.8 MB read, 4,370.5 MB written (records + sums)
-    "hier4_16": 11_522_939_464,          # k_hier4<true, false, true>: 3,146.9 MB read, 8,376.0 MB written
+    "hier4_16": 11_961_285_520,          # k_hier4<true, false, true>: 3,551.9 MB read, 8,409.3 MB written
     "phase23_c5_sub256": 1_625_015_253,  # k_phase23: 228.9 MB read, 1,396.1 MB written
 }
 

@@ -236,6 +236,7 @@ struct Platten {
     uint32_t *d_cp_mark = nullptr;       // [n_cp] R values present in this call
     double *d_cp_tbl = nullptr;          // [n_cp]
     int32_t max_cls_N = 0;
+    int32_t max_nv = 1;   // most vertices of any tile (the bound kernel's per-tile LDS rows)
 
     // per-tile workspaces (allocated with the platten)
     uint32_t *d_Rw = nullptr;            // rejection counts

@@ -443,9 +443,14 @@ __global__ void k_negate1(double *x) { x[0] = -x[0]; }
 // mode 3: lower validation bound (Remark 2: the tilt of 1 - cp_lower = cp_upper(N - R), then
 // lower = 1 - that; cp_out receives cp_lower).
 // L lanes per tile: GB (cooperative section search, 256-thread blocks of 32 tiles) or 1
-// (Brent's search, 64-thread blocks of 64 tiles).
+// (Brent's search, 64-thread blocks of 64 tiles).  The per-tile vertex rows live in dynamic LDS
+// sized for mv vertices (the launch's largest tile), bound_lds_bytes: sized for the 64-vertex
+// maximum, one-lane blocks would hold 38 KB each and a CU would fit only one wave per SIMD.
+static size_t bound_lds_bytes(int d, int tpb, int mv) {
+    return (size_t)tpb * ((size_t)mv * sizeof(double) + (size_t)d * SHU * sizeof(double) + (size_t)mv);
+}
 template <int FAM, int D, int L>
-__global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, int64_t n_tiles,
+__global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, int64_t n_tiles, int mv,
                                                const double *__restrict__ theta,
                                                const int32_t *__restrict__ vert_off,
                                                const double *__restrict__ verts,
@@ -462,9 +467,10 @@ __global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, in
                                                double *__restrict__ cp_out) {
     constexpr int TPB = L == 1 ? 64 : 256 / GB;   // tiles per block
     static_assert(L == 1 || L == GB, "lanes per tile");
-    __shared__ double s_psi1[TPB][MAXV];
-    __shared__ uint8_t s_vidx[TPB][MAXV];
-    __shared__ double s_uv[TPB][D * SHU];
+    extern __shared__ double s_dyn[];
+    double *s_psi1 = s_dyn;                                          // [TPB][mv]
+    double *s_uv = s_dyn + (size_t)TPB * mv;                         // [TPB][D * SHU]
+    uint8_t *s_vidx = reinterpret_cast<uint8_t *>(s_uv + TPB * D * SHU);   // [TPB][mv]
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x % L, grp = threadIdx.x / L;
     int64_t t = gid / L;
@@ -479,7 +485,7 @@ __global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, in
         T.r[a] = radii[t * D + a];
     }
     T.V = verts + (int64_t)vert_off[t] * D;
-    T.nv = min(vert_off[t + 1] - vert_off[t], MAXV);
+    T.nv = min(vert_off[t + 1] - vert_off[t], mv);
     double zero[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) zero[a] = 0.0;
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, in
     }
     T.shared = false;
     if (!T.box) {
-        for (int j = lane; j < T.nv; j += L) s_psi1[grp][j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
+        for (int j = lane; j < T.nv; j += L) s_psi1[grp * mv + j] = part<FAM, D>(n, T.th, 1.0, T.V + j * D) - T.A0;
         // distinct displacement values per arm, in order of first appearance (every lane of the
         // group finds the same ones); an arm with one value repeats it in the second slot
         bool shared = true;
@@ -519,20 +525,20 @@ __global__ __launch_bounds__(L == 1 ? 64 : 256) void k_bound(int mode, int n, in
                     code |= 1u << a;
                 }
             }
-            if (j % L == lane) s_vidx[grp][j] = (uint8_t)code;
+            if (j % L == lane) s_vidx[grp * mv + j] = (uint8_t)code;
         }
         if (lane == 0)
 #pragma unroll
             for (int a = 0; a < D; ++a) {
-                s_uv[grp][a * SHU] = v0[a];
-                s_uv[grp][a * SHU + 1] = v1[a];
+                s_uv[grp * D * SHU + a * SHU] = v0[a];
+                s_uv[grp * D * SHU + a * SHU + 1] = v1[a];
             }
         T.shared = shared;
     }
     __syncthreads();
-    T.psi1 = s_psi1[grp];
-    T.vidx = s_vidx[grp];
-    T.uv = s_uv[grp];
+    T.psi1 = s_psi1 + grp * mv;
+    T.vidx = s_vidx + grp * mv;
+    T.uv = s_uv + grp * D * SHU;
 
     if (mode == 1) {
         double sb;
@@ -786,15 +792,18 @@ hipError_t launch_bound(const Platten &P, int mode, const uint32_t *R, const dou
     const int bs = one_lane ? 64 : 256;
     const int64_t threads = P.n_tiles * (one_lane ? 1 : GB);
     const int64_t grid = (threads + bs - 1) / bs;
+    const int mv = std::min(std::max(P.max_nv, 1), MAXV);
 #define CSE_BOUND_LAUNCH(FAM, D)                                                                        \
     do {                                                                                                \
         if (one_lane)                                                                                   \
-            hipLaunchKernelGGL((k_bound<FAM, D, 1>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm, \
-                               P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
+            hipLaunchKernelGGL((k_bound<FAM, D, 1>), dim3((uint32_t)grid), dim3(bs),                     \
+                               bound_lds_bytes(D, 64, mv), st,      mode, P.n_per_arm,                  \
+                               P.n_tiles, mv, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
                                a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);          \
         else                                                                                            \
-            hipLaunchKernelGGL((k_bound<FAM, D, GB>), dim3((uint32_t)grid), dim3(bs), 0, st, mode, P.n_per_arm, \
-                               P.n_tiles, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
+            hipLaunchKernelGGL((k_bound<FAM, D, GB>), dim3((uint32_t)grid), dim3(bs),                   \
+                               bound_lds_bytes(D, 256 / GB, mv), st,      mode, P.n_per_arm,            \
+                               P.n_tiles, mv, P.d_theta, P.d_vert_off, P.d_verts, P.d_radii, P.d_is_box, P.d_N, R, \
                                a_in, level, P.d_cp_tbl, P.d_cp_base, out, q_out, k_out, cp_out);          \
     } while (0)
     if (P.family == FAM_NORMAL && P.d == 1)

@@ -528,6 +528,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
             set_error("cse_platten_create: a tile has more than 64 vertices");
             return CSE_EUNSUPPORTED;
         }
+        P->max_nv = std::max(P->max_nv, P->tile_nv[t]);
     }
     if (P->family == FAM_BINOM) {
         P->tile_T.resize(P->n_tiles * d);
