@@ -66,7 +66,7 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # size).  Valid only while that kernel is unchanged; workloads not listed report null.
 TRAFFIC = {
     "binom2_1024_full": 4_388_219_655,   # k_binom2<true>: 17.8 MB read, 4,370.5 MB written (records + sums)
-    "hier4_16": 11_961_285_520,          # k_hier4<true, false, true>: 3,551.9 MB read, 8,409.3 MB written
+    "hier4_16": 11_961_285_520,          # k_hier4<1, false, true>: 3,551.9 MB read, 8,409.3 MB written
     "phase23_c5_sub256": 1_625_015_253,  # k_phase23: 228.9 MB read, 1,396.1 MB written
 }
 
@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the fused kernel's launch shape with cse_autotune before timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--h4-bracket", action="store_true",
+                    help="4-arm calibration from bracketed keys (pilot + in-bracket candidates) instead of every key")
     ap.add_argument("--no-extensions", action="store_true",
                     help="skip the lower-bound, confidence-set and randomised-calibration timings")
     ap.add_argument("--progress", action="store_true",
@@ -357,6 +359,8 @@ def measure(name, w, design, args, full=True):
     t0 = time.perf_counter()
     P = cse.Platten.create(design, w["theta"], w["radii"], w["sims"], keep_all=keep_all, cut=w.get("cut"))
     platten_ms = (time.perf_counter() - t0) * 1e3
+    if args.h4_bracket and design == "hier4":
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
     st = cse.cse_platten_stats(P.handle)
     n, d = P.n_tiles, P.d
     dev = "cuda"
@@ -414,7 +418,7 @@ def measure(name, w, design, args, full=True):
                   "basket4": "basket4"}[design] + \
         ("_calib" if calibrating else "")
     kern = {}
-    for kn in (sim_kernel, "select", "b2_bracket", "bound_invert", "bound_validate"):
+    for kn in (sim_kernel, "select", "b2_bracket", "hier4_pilot", "h4_bracket", "bound_invert", "bound_validate"):
         cnt, ms = cse.cse_profile_get(kn)
         if cnt:
             kern[kn] = round(ms / cnt, 5)
@@ -516,10 +520,14 @@ def measure(name, w, design, args, full=True):
         box_sims = int(np.asarray(w["sims"])[boxes].sum())
         ops = (st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + box_sims * H4_BOX
                + st["total_sims"] * H4_TILE)
-        kname = "k_hier4<KEYS=true, BASKET=false, SCORE=true>"
+        kname = "k_hier4<1, false, true>"
+        if args.h4_bracket:   # the timed kernel is the pass after the 2,048-simulation pilot
+            sims = np.asarray(w["sims"])[boxes].astype(np.int64)
+            ops = ops * float(np.maximum(sims - 2048, 0).sum()) / float(sims.sum())
+            kname = "k_hier4<2, false, true>"
     elif design == "basket4":
         ops = st["group_sims"] * H4_PHILOX + st["batch_sims"] * H4_COUNT + st["total_sims"] * BK_SLOT
-        kname = "k_hier4<KEYS=false, BASKET=true, SCORE=true>"
+        kname = "k_hier4<0, true, true>"
     elif design == "phase23":
         wc = cse.cse_work_counters(P.handle)
         ops = (wc["looks_phase2"] * (90 * P23_NODE + P23_P2_EXTRA)

@@ -438,7 +438,9 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
  * trial is a table lookup and is not counted), Newton steps over all nodes of those looks.
  * On a CSE_BINOM2_Z platten: out[0] = tiles that the last calibration's bracketed selection
  * left to the exact full-histogram pass (k-th statistic outside the bracket, or the batch's
- * brackets too wide for the histogram), out[1..3] = 0.
+ * brackets too wide for the histogram), out[1..3] = 0.  On a CSE_HIER4 platten: out[0] = tiles
+ * whose k-th key the last bracketed calibration did not hold among its candidates (selected
+ * exactly from keys regenerated by the counter-based generator), out[1..3] = 0.
  * Synchronises `stream`.  Used to state the kernel's arithmetic per launch.
  * Errors: CSE_EINVAL (NULL out), CSE_EUNSUPPORTED (other designs), CSE_EHIP.
  */
@@ -452,9 +454,23 @@ int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream);
  *        full-histogram pass (cse_work_counters counts them); a smaller margin lists fewer
  *        simulations in the bracketed pass but sends more tiles to the exact one.  A plan
  *        captured earlier keeps the margin it was captured with.
- * Errors: CSE_EINVAL (bad handle, unknown option, value outside [0, 100]).
+ *   CSE_OPT_H4_BRACKET (CSE_HIER4 calibration): 1 selects from bracketed keys: a pilot pass keeps
+ *        the float32 keys of the first 2,048 simulations, whose order statistics around rank
+ *        (k/N) 2048 bracket each tile's k-th key; the fused pass over the other simulations
+ *        counts the keys below the bracket and keeps only those inside it (about a tenth of the
+ *        HBM traffic of storing every key).  0 (default) stores every float32 key and selects
+ *        from them, as cse_calibrate_tiebreak always does.  Same results either way.
+ *   CSE_OPT_H4_MARGIN (CSE_HIER4 bracketed calibration): the bracket's margin in standard
+ *        deviations of the pilot rank (default 6, lowered towards 3 where the bracket would
+ *        hold too many keys).  Results do not depend on it: a tile whose k-th key is not among
+ *        the kept ones is selected from its keys regenerated one by one from the counter-based
+ *        generator (slow; cse_work_counters counts them).
+ * Errors: CSE_EINVAL (bad handle, unknown option, value outside [0, 100]; 0 or 1 for
+ * CSE_OPT_H4_BRACKET).
  */
 #define CSE_OPT_B2_MARGIN 1
+#define CSE_OPT_H4_MARGIN 2
+#define CSE_OPT_H4_BRACKET 3
 int cse_platten_set_option(cse_platten *p, int32_t option, double value);
 
 /*

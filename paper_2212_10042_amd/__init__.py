@@ -324,17 +324,20 @@ def cse_autotune(h, seed=0, max_trials=1 << 24, stream=None):
 
 
 CSE_OPT_B2_MARGIN = 1   # 2-arm calibration: bracket margin (standard deviations of the count)
+CSE_OPT_H4_MARGIN = 2   # 4-arm calibration: bracket margin (standard deviations of the pilot rank)
+CSE_OPT_H4_BRACKET = 3   # 4-arm calibration: 1 = bracketed keys, 0 = every float32 key in HBM (default)
 
 
 def cse_platten_set_option(h, option, value):
-    """Set a platten tuning option (CSE_OPT_B2_MARGIN)."""
+    """Set a platten tuning option (CSE_OPT_B2_MARGIN, CSE_OPT_H4_BRACKET, CSE_OPT_H4_MARGIN)."""
     _check("cse_platten_set_option", _L.cse_platten_set_option(h, int(option), float(value)))
 
 
 def cse_work_counters(h, stream=None) -> dict:
     """Phase II/III design: trials, posterior looks (Phase II, Phase III) and Newton steps of
     the last simulation launch.  2-arm design: `trials` holds the tiles the last calibration
-    left to the exact full-histogram pass."""
+    left to the exact full-histogram pass; 4-arm design: the tiles whose k-th key the last
+    bracketed calibration selected from regenerated keys."""
     out = np.zeros(4, np.int64)
     _check("cse_work_counters", _L.cse_work_counters(h, _ptr(out), _stream(stream)))
     return dict(trials=int(out[0]), looks_phase2=int(out[1]), looks_phase3=int(out[2]),

@@ -186,6 +186,29 @@ int run_sim(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st, bo
     return CSE_OK;
 }
 
+// The 4-arm calibration with bracketed keys: pilot pass (float32 keys of the first H4_PILOT
+// simulations), brackets once k is known (k_ready: the event after which it is, or null when
+// it already is on st), then the pass over the other simulations (bracketed keys).  R and the
+// score sums cover every simulation, as run_sim's.
+int run_sim_h4(const cse::Platten &P, uint64_t seed, void *keys, hipStream_t st, bool scores, hipEvent_t k_ready,
+               const int32_t *kk, double *lam, int32_t *rej_at) {
+    CSE_LAUNCH(cse::launch_zero(P.d_Rw, P.n_tiles * sizeof(uint32_t), st));
+    if (scores) CSE_LAUNCH(cse::launch_zero(P.d_Tw, P.n_tiles * P.d * sizeof(unsigned long long), st));
+    unsigned long long *sT = scores ? P.d_Tw : nullptr;
+    {
+        Timed tm("hier4_pilot", st);
+        CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, sT, (float *)keys, st, cse::H4_PASS_PILOT));
+    }
+    if (k_ready) CSE_HIP_TRY(hipStreamWaitEvent(st, k_ready, 0));
+    {
+        Timed tm("h4_bracket", st);
+        CSE_LAUNCH(cse::launch_h4_bracket(P, (const float *)keys, kk, lam, rej_at, st));
+    }
+    Timed tm("hier4_calib", st);
+    CSE_LAUNCH(cse::launch_hier4(P, seed, P.d_Rw, sT, nullptr, st, cse::H4_PASS_MAIN));
+    return CSE_OK;
+}
+
 size_t key_bytes(const cse::Platten &P) {
     const size_t esz = (P.design.kind == CSE_BINOM2_Z) ? cse::REC2_BYTES : 4;
     return (size_t)P.n_keys * esz;
@@ -251,8 +274,11 @@ int validate_impl(const cse::Platten &P, uint64_t seed, double delta, int32_t *r
 int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alpha, double *alpha_prime, int32_t *k,
                    double *lambda_tile, double *lambda_global, int32_t *reject_at_lambda, double delta,
                    int32_t *reject, int64_t *score_T, double *score_Z, double *grad, double *cp_upper,
-                   double *tile_bound, hipStream_t st) {
+                   double *tile_bound, hipStream_t st, bool full_keys = false) {
     double *ap = alpha_prime ? alpha_prime : P.d_apw;
+    // 4-arm design: bracketed keys when the platten asks for them (CSE_OPT_H4_BRACKET) and every key
+    // need not reach HBM (the randomised tie-break reads them)
+    const bool h4b = P.design.kind == CSE_HIER4 && !full_keys && P.h4_bracket && P.d_h4cand;
     int32_t *kk = k ? k : P.d_kw;
     double *lam = lambda_tile ? lambda_tile : P.d_lamw;
     // The step's dependencies: alpha' -> k -> selection; simulation -> selection, finish and
@@ -280,7 +306,13 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
         }
         if (branch_invert) CSE_HIP_TRY(hipEventRecord(P.ev_inv, is));
     }
-    if (int e = run_sim(P, seed, keys, st, score_T || grad)) return e;
+    if (h4b) {
+        if (int e = run_sim_h4(P, seed, keys, st, score_T || grad, branch_invert ? P.ev_inv : nullptr, kk, lam,
+                               reject_at_lambda))
+            return e;
+    } else if (int e = run_sim(P, seed, keys, st, score_T || grad)) {
+        return e;
+    }
     const bool want_bound = cp_upper || tile_bound;
     if (want_bound) {
         hipStream_t side = P.side;
@@ -298,7 +330,10 @@ int calibrate_impl(const cse::Platten &P, void *keys, uint64_t seed, double alph
     if (branch_invert) CSE_HIP_TRY(hipStreamWaitEvent(st, P.ev_inv, 0));   // k before the selection
     {
         Timed tm("select", st);
-        CSE_LAUNCH(cse::launch_select(P, keys, kk, lam, reject_at_lambda, st));
+        if (h4b)
+            CSE_LAUNCH(cse::launch_h4_select(P, seed, kk, lam, reject_at_lambda, st));
+        else
+            CSE_LAUNCH(cse::launch_select(P, keys, kk, lam, reject_at_lambda, st));
     }
     CSE_LAUNCH(cse::launch_min(P, lam, P.d_in_null, P.n_tiles, lambda_global ? lambda_global : P.d_lamg, st));
     if (reject || score_T || score_Z || grad)
@@ -750,7 +785,7 @@ int cse_calibrate_tiebreak(const cse_platten *p, uint64_t seed, double alpha, do
     hipStream_t st = (hipStream_t)stream;
     int32_t *kk = k ? k : P.d_kw;
     if (int e = calibrate_impl(P, P.d_keys, seed, alpha, alpha_prime, kk, lambda_tile, nullptr, reject_at_lambda, 0.5, nullptr,
-                               nullptr, nullptr, nullptr, nullptr, nullptr, st))
+                               nullptr, nullptr, nullptr, nullptr, nullptr, st, true))
         return e;
     {
         Timed tm("tiebreak", st);
@@ -827,7 +862,15 @@ int cse_platten_stats(const cse_platten *p, int64_t out[12]) {
 
 int cse_platten_set_option(cse_platten *p, int32_t option, double value) {
     if (int e = check_handle(p, "cse_platten_set_option")) return e;
-    if (option != CSE_OPT_B2_MARGIN) {
+    if (option == CSE_OPT_H4_BRACKET) {
+        if (value != 0.0 && value != 1.0) {
+            set_error("cse_platten_set_option: CSE_OPT_H4_BRACKET takes 0 or 1");
+            return CSE_EINVAL;
+        }
+        p->P.h4_bracket = value == 1.0;
+        return CSE_OK;
+    }
+    if (option != CSE_OPT_B2_MARGIN && option != CSE_OPT_H4_MARGIN) {
         set_error("cse_platten_set_option: unknown option");
         return CSE_EINVAL;
     }
@@ -835,7 +878,10 @@ int cse_platten_set_option(cse_platten *p, int32_t option, double value) {
         set_error("cse_platten_set_option: the bracket margin must lie in [0, 100]");
         return CSE_EINVAL;
     }
-    p->P.b2_margin = (float)value;
+    if (option == CSE_OPT_B2_MARGIN)
+        p->P.b2_margin = (float)value;
+    else
+        p->P.h4_margin = (float)value;
     return CSE_OK;
 }
 
@@ -846,17 +892,18 @@ int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream) {
         set_error("cse_work_counters: NULL out");
         return CSE_EINVAL;
     }
-    if (P.design.kind == CSE_BINOM2_Z) {   // tiles of the last calibration left to the exact pass
+    if (P.design.kind == CSE_BINOM2_Z || P.design.kind == CSE_HIER4) {   // tiles the last selection took exactly
         uint32_t n_fb = 0u;
         hipStream_t st = (hipStream_t)stream;
-        CSE_HIP_TRY(hipMemcpyAsync(&n_fb, P.d_b2fb, sizeof n_fb, hipMemcpyDeviceToHost, st));
+        CSE_HIP_TRY(hipMemcpyAsync(&n_fb, P.design.kind == CSE_HIER4 ? P.d_h4fb : P.d_b2fb, sizeof n_fb,
+                                   hipMemcpyDeviceToHost, st));
         CSE_HIP_TRY(hipStreamSynchronize(st));
         out[0] = (int64_t)n_fb;
         out[1] = out[2] = out[3] = 0;
         return CSE_OK;
     }
     if (P.design.kind != CSE_PHASE23) {
-        set_error("cse_work_counters: only the Phase II/III and 2-arm designs count their work");
+        set_error("cse_work_counters: only the Phase II/III, 2-arm and 4-arm designs count their work");
         return CSE_EUNSUPPORTED;
     }
     unsigned long long h[4] = {0, 0, 0, 0};

@@ -78,8 +78,18 @@ struct GroupItem {
     int32_t blk[4];
     uint32_t k_begin;
     uint32_t k_end;
-    int32_t pad[2];
+    int32_t slice;   // index of the item's simulation range among its group's ranges
+    int32_t pad;
 };
+
+// 4-arm calibration with bracketed keys: a pilot pass stores the keys of the first H4_PILOT
+// simulations; per tile they give a bracket [lo, hi] around the k-th smallest key; the fused pass
+// over the remaining simulations counts the keys below lo and keeps those in [lo, hi] in the
+// tile's candidate regions (H4_PCAP slots for the pilot's, then h4_caps per item range).
+constexpr int H4_PILOT = 2048;
+constexpr int H4_PCAP = 1024;
+constexpr int H4_MAXS = 1024;   // item ranges per group at most (the selection's region table)
+constexpr int H4_BROWS = 128;   // key rows per wave whose counters live in LDS (the rest: global atomics)
 
 // Workgroup item of the 2-arm kernel: its 16 waves simulate [k_begin, k_end) for the batches of a
 // 4 x 4 square of the threshold grid (equal N): blk[4 r + c] is the batch of row group r (8 arm-0
@@ -167,6 +177,22 @@ struct Platten {
     GroupItem *d_gitems = nullptr;       // 4-arm designs
     SquareItem *d_sqitems = nullptr;     // 2-arm design
     int64_t n_gitems = 0;
+    // 4-arm calibration with bracketed keys (CSE_HIER4): pilot items over the first H4_PILOT
+    // simulations; per tile the bracket (lo, hi), the keys below lo, the candidates kept per region
+    // ([0] the pilot's, [1 + s] item range s) and the candidate regions themselves; the tiles the
+    // last selection regenerated ([0] = count)
+    GroupItem *d_gitems_pilot = nullptr;
+    int64_t n_gitems_pilot = 0;
+    int32_t h4_maxs = 0, h4_caps = 0;    // item ranges per group (at most), candidate slots per range
+    int32_t h4_max_rows = 0;             // most key rows of a block
+    int64_t h4_tot = 0;                  // candidate slots per tile: H4_PCAP + h4_maxs * h4_caps
+    float2 *d_h4brk = nullptr;
+    uint32_t *d_h4below = nullptr;
+    uint32_t *d_h4cnt = nullptr;
+    float *d_h4cand = nullptr;
+    uint32_t *d_h4fb = nullptr;
+    float h4_margin = 6.0f;              // bracket margin in standard deviations of the pilot rank
+    bool h4_bracket = false;             // calibrate with bracketed keys (else every key in HBM, the f32 selection)
 
     // design tables (device)
     float4 *d_h4tbl = nullptr;           // 4-arm: (1 - P_1, 1 - P_2, 1 - P_3, 0) per outcome

@@ -140,13 +140,30 @@ __device__ __forceinline__ uint32_t row16_sum(uint32_t v) {
     return v;
 }
 constexpr uint64_t H4_REJ = 0xFEFCFAF0EECCAA00ull;   // byte m: configurations b (bits 1..7) with m & b != 0
-template <bool KEYS, bool BASKET, bool SCORE>
+
+// Bracketed keys (KEYS = 2; blocks of at most H4_BROWS key rows): per tile the bracket (lo, hi)
+// from the pilot; the pass counts the keys below lo (per wave and key row in LDS, added to the
+// tile at the end of the item) and keeps
+// those in [lo, hi] in the tile's region of the item's range (caps slots; the count goes on past
+// caps, which sends the tile to the exact path).
+struct H4Brk {
+    const float2 *brk;
+    uint32_t *below;
+    uint32_t *cnt;     // per tile [1 + maxs]: [0] the pilot's candidates, [1 + s] item range s
+    float *cand;       // per tile [tot]: H4_PCAP pilot slots, then caps per item range
+    int64_t tot;
+    int32_t maxs, caps;
+    uint32_t k_lo;     // first simulation of the pass (the pilot holds the ones before)
+};
+template <int KEYS, bool BASKET, bool SCORE>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void k_hier4(const Blk4 *__restrict__ blocks,
                                               const GroupItem *__restrict__ items, int64_t n_items,
                                               uint32_t key0, uint32_t key1,
                                               const float4 *__restrict__ tbl, const uint8_t *__restrict__ mtbl,
                                               float cut, uint32_t *__restrict__ R,
-                                              unsigned long long *__restrict__ sumT, float *__restrict__ keys) {
+                                              unsigned long long *__restrict__ sumT, float *__restrict__ keys,
+                                              H4Brk hb) {
+    static_assert(KEYS != 2 || !BASKET, "bracketed keys serve the 4-arm design");
     constexpr int NP = NP35;
     constexpr int NW = 4 * NP;
     constexpr int NB = NW / 4;   // 35 Philox blocks
@@ -159,6 +176,10 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
     // counter transposes (per wave 16 x (64 + 1) words, padded against bank conflicts).
     __shared__ uint32_t words[NWH][WAVE];
     __shared__ uint2 ysum[SCORE ? NWAVES : 1][SCORE ? H4_SROWS : 1];   // per wave and key row: packed y sums
+    // bracketed keys: per wave and key row, the tile's bracket (lo, hi as float bits), the keys
+    // below it and the candidates kept in this item; and the row's tile
+    __shared__ uint4 rcnt[KEYS == 2 ? NWAVES : 1][KEYS == 2 ? H4_BROWS : 1];
+    __shared__ int32_t rtile[KEYS == 2 ? NWAVES : 1][KEYS == 2 ? H4_BROWS : 1];
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -168,7 +189,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
     const int32_t blk = G->blk[wv];   // read in place: a register copy indexed by wv would go to scratch
     const bool live = blk >= 0;
     const Blk4 *__restrict__ B = blocks + (live ? blk : G->blk[0]);
-    const uint32_t kb = G->k_begin, ke = G->k_end;
+    const uint32_t kb = KEYS == 2 ? max(G->k_begin, hb.k_lo) : G->k_begin, ke = G->k_end;
     uint32_t T0[B4N0], T1[B4N1], T2[B4N2], T3[B4N3];
 #pragma unroll
     for (int u = 0; u < B4N0; ++u) T0[u] = B->T0[u];
@@ -179,7 +200,41 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
 #pragma unroll
     for (int u = 0; u < B4N3; ++u) T3[u] = B->T3[u];
     const int32_t n_rows = B->n_rows;
-    float *__restrict__ kbase = keys + (KEYS ? B->key_base : 0);
+    float *__restrict__ kbase = keys + (KEYS == 1 ? B->key_base : 0);
+    const int32_t slice = G->slice;
+    if (KEYS == 2 && live) {
+        static_assert(B4S == WAVE, "one lane per slot");
+        const int32_t r0 = B->row0[lane];
+        if (r0 >= 0) {
+            const int nq = __popc(B->bmask[lane]);
+            for (int q = 0; q < nq && r0 + q < H4_BROWS; ++q) {
+                const int32_t t = B->tile0[lane] + q;
+                const float2 br = hb.brk[t];
+                rtile[wv][r0 + q] = t;
+                rcnt[wv][r0 + q] = make_uint4(__float_as_uint(br.x), __float_as_uint(br.y), 0u, 0u);
+            }
+        }
+        wave_sync4();
+    }
+    // one key of a bracketed row (every lane of the wave calls): below the bracket it is counted,
+    // inside it kept at the next free slot of the tile's region for this item range
+    // (the plattens that take this pass have at most H4_BROWS key rows per block)
+    auto take_key = [&](bool act_key, int32_t row, int32_t tile, float sb) {
+        const uint4 v = rcnt[wv][row];   // bracket and counts (one LDS read, the same address in every lane)
+        const float lo = __uint_as_float(v.x), hi = __uint_as_float(v.y);
+        const bool bl = act_key && sb < lo;
+        const bool in = act_key && sb >= lo && sb <= hi;
+        const unsigned long long mb = __ballot(bl), mi = __ballot(in);
+        if (!(mb | mi)) return;   // uniform
+        if (lane == 0) {
+            rcnt[wv][row].z = v.z + (uint32_t)__popcll(mb);
+            rcnt[wv][row].w = v.w + (uint32_t)__popcll(mi);
+        }
+        if (in) {
+            const uint32_t pos = v.w + (uint32_t)__popcll(mi & ((1ull << lane) - 1ull));
+            if (pos < (uint32_t)hb.caps) hb.cand[(int64_t)tile * hb.tot + H4_PCAP + (int64_t)slice * hb.caps + pos] = sb;
+        }
+    };
 
     if (SCORE)
         for (int r = lane; r < H4_SROWS; r += WAVE) ysum[wv][r] = make_uint2(0u, 0u);
@@ -398,7 +453,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
             // loads and stores together, so a gather used right after the previous slot's key
             // stores would also wait for those stores.
             constexpr int S2 = B4N3, S1 = B4N2 * B4N3;
-            constexpr int GU1 = KEYS ? 2 : B4N1;   // u1 values per group (keyed: fewer rows in registers)
+            constexpr int GU1 = KEYS == 2 ? 1 : (KEYS ? 2 : B4N1);   // u1 values per group (keyed: fewer rows in registers)
             constexpr int G = GU1 * S1;
 #pragma unroll
             for (int ug = 0; ug < B4N0 * (B4N1 / GU1); ++ug) {
@@ -491,7 +546,7 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
                                                (uint32_t)y2[u2], (uint32_t)y3[u3]);
                                 }
                             }
-                            if (KEYS) {
+                            if constexpr (KEYS == 1) {
                                 const uint32_t bm = B->bmask[s];
                                 int row = row0;
 #pragma unroll
@@ -502,6 +557,22 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
                                     if (b & 2) sb = fminf(sb, q.y);
                                     if (b & 4) sb = fminf(sb, q.z);
                                     kc[(size_t)row * WAVE] = sb;
+                                    ++row;
+                                }
+                            } else if constexpr (KEYS == 2) {
+                                // a loop, not unrolled: seven copies of the bracket step per slot would
+                                // keep the slot loop from unrolling (and its rows from registers)
+                                uint32_t bm = B->bmask[s];
+                                int row = row0;
+#pragma unroll 1
+                                while (bm) {   // uniform
+                                    const uint32_t b = (uint32_t)__builtin_ctz(bm);
+                                    bm &= bm - 1u;
+                                    float sb = INFINITY;
+                                    if (b & 1u) sb = fminf(sb, q.x);
+                                    if (b & 2u) sb = fminf(sb, q.y);
+                                    if (b & 4u) sb = fminf(sb, q.z);
+                                    take_key(act, row, B->tile0[s] + (row - row0), sb);
                                     ++row;
                                 }
                             }
@@ -519,29 +590,52 @@ __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(5, 5))) void
     }
     flush();
     if (SCORE && live) flush_scores();
+    if (KEYS == 2 && live) {   // this item's counts of the LDS rows into their tiles
+        wave_sync4();
+        const int nr = min(B->n_rows, H4_BROWS);
+        for (int r = lane; r < nr; r += WAVE) {
+            const uint4 v = rcnt[wv][r];
+            const int32_t t = rtile[wv][r];
+            if (v.z) atomicAdd(&hb.below[t], v.z);
+            hb.cnt[(int64_t)t * (hb.maxs + 1) + 1 + slice] = v.w;
+        }
+    }
 }
 
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
-                        hipStream_t st) {
+                        hipStream_t st, int pass) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     const float cut = (float)P.design.cut;
     const bool basket = P.design.kind == CSE_BASKET4;
+    H4Brk hb{P.d_h4brk, P.d_h4below, P.d_h4cnt, P.d_h4cand, P.h4_tot, P.h4_maxs, P.h4_caps, (uint32_t)H4_PILOT};
+    const GroupItem *items = P.d_gitems;
+    int64_t n_items = P.n_gitems;
+    if (pass == H4_PASS_PILOT) {
+        if (basket || !keys) return hipErrorInvalidValue;
+        items = P.d_gitems_pilot;
+        n_items = P.n_gitems_pilot;
+    } else if (pass == H4_PASS_MAIN && (basket || !P.d_h4cand)) {
+        return hipErrorInvalidValue;
+    }
+    if (n_items == 0) return hipSuccess;
 #define CSE_H4_LAUNCH(K, BK, SC)                                                                                  \
-    hipLaunchKernelGGL((k_hier4<K, BK, SC>), dim3((uint32_t)P.n_gitems), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
-                       P.d_gitems, P.n_gitems, k0, k1, P.d_h4tbl, P.d_h4mask, cut, R, sumT, keys)
+    hipLaunchKernelGGL((k_hier4<K, BK, SC>), dim3((uint32_t)n_items), dim3(WG), 0, st, (const Blk4 *)P.d_blocks, \
+                       items, n_items, k0, k1, P.d_h4tbl, P.d_h4mask, cut, R, sumT, keys, hb)
 #define CSE_H4_SC(K, BK)            \
     if (sumT)                       \
         CSE_H4_LAUNCH(K, BK, true); \
     else                            \
         CSE_H4_LAUNCH(K, BK, false)
-    if (keys && basket) {
-        CSE_H4_SC(true, true);
+    if (pass == H4_PASS_MAIN) {
+        CSE_H4_SC(2, false);
+    } else if (keys && basket) {
+        CSE_H4_SC(1, true);
     } else if (keys) {
-        CSE_H4_SC(true, false);
+        CSE_H4_SC(1, false);
     } else if (basket) {
-        CSE_H4_SC(false, true);
+        CSE_H4_SC(0, true);
     } else {
-        CSE_H4_SC(false, false);
+        CSE_H4_SC(0, false);
     }
 #undef CSE_H4_SC
 #undef CSE_H4_LAUNCH

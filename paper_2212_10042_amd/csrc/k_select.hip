@@ -649,6 +649,199 @@ __global__ __launch_bounds__(SEL_WG) void k_select_f32(const float *__restrict__
     }
 }
 
+// ---- 4-arm design, bracketed keys ----
+// The pilot pass stores the float32 keys of the first H4_PILOT simulations.  k_h4_bracket takes
+// them as the sample of k_select_f32 (order statistics of rank (k/N) m -+ z sd, widened to 22-bit
+// bins, z at most the margin and lowered towards 3 so that the bracket expects at most H4_FILL of
+// the H4_SELCAND candidate slots), counts the pilot keys below the bracket and keeps those in it;
+// tiles of at most H4_PILOT simulations are selected there and then.  The fused pass over the
+// other simulations adds its own counts and candidates (k_hier4, KEYS = 2).  k_h4_select then
+// finds the k-th smallest key among the candidates when it lies there (count below < k <= count
+// below + candidates, no region overflowed); otherwise it takes three radix passes over the tile's
+// keys regenerated one by one from the counter-based generator (the fused pass's arithmetic on
+// the tile's own thresholds), so the result is the exact k-th smallest key either way.
+constexpr int H4_SELCAND = 4096;
+constexpr double H4_FILL = 0.45;
+
+__global__ __launch_bounds__(SEL_WG) void k_h4_bracket(const float *__restrict__ keys,
+                                                       const int64_t *__restrict__ key_off,
+                                                       const int64_t *__restrict__ key_stride,
+                                                       const int32_t *__restrict__ N, const int32_t *__restrict__ kk,
+                                                       float margin, int32_t maxs, int64_t tot,
+                                                       float2 *__restrict__ brk, uint32_t *__restrict__ below,
+                                                       uint32_t *__restrict__ cnt, float *__restrict__ cand,
+                                                       double *__restrict__ lam, int32_t *__restrict__ rej_at) {
+    __shared__ uint32_t hist[2048];
+    __shared__ uint32_t part[SEL_WG];
+    __shared__ uint32_t samp[H4_PILOT];
+    __shared__ uint32_t s_bin, s_below, s_lt, s_in;
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int32_t n = N[t];
+    const int32_t k = kk[t];
+    uint32_t *__restrict__ ct = cnt + t * (int64_t)(maxs + 1);
+    for (int i = tid; i <= maxs; i += SEL_WG) ct[i] = 0u;   // the pass's regions start empty
+    const float2 none = make_float2(-INFINITY, -INFINITY);    // no key below or inside
+    if (k <= 0 || k > n) {   // outside Theorem 4's range: -+inf, no selection
+        if (tid == 0) {
+            lam[t] = k <= 0 ? -INFINITY : INFINITY;
+            if (rej_at) rej_at[t] = k <= 0 ? 0 : n;
+            brk[t] = none;
+            below[t] = 0u;
+        }
+        return;
+    }
+    const float *__restrict__ kt = keys + key_off[t];
+    const int64_t stride = key_stride[t];
+    const int m = n < H4_PILOT ? n : H4_PILOT;
+    for (int j = tid; j < m; j += SEL_WG) samp[j] = f2ord(kt[(int64_t)(j >> 6) * stride + (j & 63)]);
+    __syncthreads();
+    auto from_samp = [&](int j) { return samp[j]; };
+    if (n <= H4_PILOT) {   // the pilot is the whole tile
+        uint32_t key = 0u, bel = 0u;
+        radix_kth(n, (uint32_t)k, from_samp, hist, part, &s_bin, &s_below, key, bel);
+        if (tid == 0) {
+            lam[t] = (double)ord2f(key);
+            if (rej_at) rej_at[t] = (int32_t)bel;
+            brk[t] = none;
+            below[t] = 0u;
+        }
+        return;
+    }
+    const double pr = (double)k / (double)n;
+    const double sd = sqrt((double)m * pr * (1.0 - pr));
+    const double z_fit = (H4_FILL * H4_SELCAND * m / (double)n - 2.0) / (2.0 * sd);
+    const double z = fmin((double)margin, fmax(3.0, z_fit));
+    const int lo_r = (int)floor(pr * m - z * sd) - 1;
+    const int hi_r = (int)ceil(pr * m + z * sd) + 1;
+    uint32_t lo = 0u, hi = 0xFFFFFFFFu, dummy = 0u;
+    if (lo_r >= 1) radix_kth<2>(m, (uint32_t)lo_r, from_samp, hist, part, &s_bin, &s_below, lo, dummy);
+    if (hi_r <= m) {
+        radix_kth<2>(m, (uint32_t)hi_r, from_samp, hist, part, &s_bin, &s_below, hi, dummy);
+        hi |= 0x3FFu;
+    }
+    // float bounds, compared as the fused pass compares them
+    const float lo_f = lo_r >= 1 ? ord2f(lo) : -INFINITY;
+    const float hi_f = hi_r <= m ? ord2f(hi) : INFINITY;
+    if (tid == 0) {
+        s_lt = 0u;
+        s_in = 0u;
+    }
+    __syncthreads();
+    uint32_t lt = 0u;
+    float *__restrict__ cp = cand + t * tot;   // the pilot's region
+    for (int j = tid; j < m; j += SEL_WG) {
+        const float v = ord2f(samp[j]);
+        if (v < lo_f) {
+            ++lt;
+        } else if (v <= hi_f) {
+            const uint32_t p = atomicAdd(&s_in, 1u);
+            if (p < (uint32_t)H4_PCAP) cp[p] = v;
+        }
+    }
+    if (lt) atomicAdd(&s_lt, lt);
+    __syncthreads();
+    if (tid == 0) {
+        below[t] = s_lt;
+        ct[0] = s_in;   // more than H4_PCAP: the tile takes the exact path
+        brk[t] = make_float2(lo_f, hi_f);
+    }
+}
+
+// The 4-arm statistic of simulation k at one tile (thresholds T of the four arms, configuration
+// b): the fused pass's arithmetic for that single (simulation, tile).
+__device__ __forceinline__ float h4_regen_key(uint32_t k, const uint32_t T[4], uint32_t b, uint32_t key0,
+                                              uint32_t key1, const float4 *__restrict__ tbl) {
+    constexpr int M1 = NP35 + 1;
+    int y[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int blk = 0; blk < NP35; ++blk) {   // 4 arms x 35 words = 35 blocks; word w is arm w / 35's
+        const u32x4 w = philox_block((uint32_t)blk, k, key0, key1);
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            const int a = (4 * blk + l) / NP35;
+            y[a] += (u32x4_get(w, l) < T[a]) ? 1 : 0;
+        }
+    }
+    const float4 q = tbl[((y[0] * M1 + y[1]) * M1 + y[2]) * M1 + y[3]];
+    float sb = INFINITY;
+    if (b & 1u) sb = fminf(sb, q.x);
+    if (b & 2u) sb = fminf(sb, q.y);
+    if (b & 4u) sb = fminf(sb, q.z);
+    return sb;
+}
+
+__global__ __launch_bounds__(SEL_WG) void k_h4_select(const int32_t *__restrict__ N, const int32_t *__restrict__ kk,
+                                                      const uint32_t *__restrict__ below,
+                                                      const uint32_t *__restrict__ cnt, const float *__restrict__ cand,
+                                                      int32_t maxs, int32_t caps, int64_t tot,
+                                                      const uint32_t *__restrict__ tileT,
+                                                      const int32_t *__restrict__ cfg,
+                                                      const float4 *__restrict__ tbl, uint32_t key0, uint32_t key1,
+                                                      uint32_t *__restrict__ fb, double *__restrict__ lam,
+                                                      int32_t *__restrict__ rej_at) {
+    __shared__ uint32_t hist[2048];
+    __shared__ uint32_t part[SEL_WG];
+    __shared__ uint32_t cbuf[H4_SELCAND];
+    __shared__ uint32_t spre[H4_MAXS + 2];   // first candidate of each region in cbuf
+    __shared__ uint32_t s_bin, s_below, s_over;
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int32_t n = N[t];
+    const int32_t k = kk[t];
+    if (k <= 0 || k > n || n <= H4_PILOT) return;   // selected by k_h4_bracket
+    const uint32_t *__restrict__ ct = cnt + t * (int64_t)(maxs + 1);
+    if (tid == 0) s_over = 0u;
+    __syncthreads();
+    uint32_t run = 0u;   // the same in every thread
+    for (int base = 0; base <= maxs; base += SEL_WG) {
+        const int r = base + tid;
+        const uint32_t c = r <= maxs ? ct[r] : 0u;
+        if (r <= maxs && c > (r == 0 ? (uint32_t)H4_PCAP : (uint32_t)caps)) s_over = 1u;   // some keys were not kept
+        block_exclusive_scan(c, part);
+        if (r <= maxs) spre[r] = run + part[tid];
+        if (tid == SEL_WG - 1) s_bin = part[tid] + c;
+        __syncthreads();
+        run += s_bin;
+        __syncthreads();
+    }
+    if (tid == 0) spre[maxs + 1] = run;
+    const uint32_t bl = below[t];
+    __syncthreads();
+    uint32_t key = 0u, bel = 0u;
+    if (!s_over && run <= (uint32_t)H4_SELCAND && bl < (uint32_t)k && (uint32_t)k <= bl + run) {
+        const float *__restrict__ cp = cand + t * tot;
+        for (uint32_t i = tid; i < run; i += SEL_WG) {
+            int a = 0, b = maxs + 1;   // region: spre[a] <= i < spre[a + 1]
+            while (b - a > 1) {
+                const int mid = (a + b) >> 1;
+                if (spre[mid] <= i)
+                    a = mid;
+                else
+                    b = mid;
+            }
+            const uint32_t j = i - spre[a];
+            const int64_t off = a == 0 ? (int64_t)j : (int64_t)H4_PCAP + (int64_t)(a - 1) * caps + j;
+            cbuf[i] = f2ord(cp[off]);
+        }
+        __syncthreads();
+        radix_kth((int)run, (uint32_t)k - bl, [&](int j) { return cbuf[j]; }, hist, part, &s_bin, &s_below, key, bel);
+        bel += bl;
+    } else {
+        if (tid == 0) fb[1 + atomicAdd(&fb[0], 1u)] = (uint32_t)t;
+        uint32_t T[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) T[a] = tileT[4 * t + a];
+        const uint32_t b = (uint32_t)cfg[t];
+        radix_kth(n, (uint32_t)k, [&](int j) { return f2ord(h4_regen_key((uint32_t)j, T, b, key0, key1, tbl)); },
+                  hist, part, &s_bin, &s_below, key, bel);
+    }
+    if (tid == 0) {
+        lam[t] = (double)ord2f(key);
+        if (rej_at) rej_at[t] = (int32_t)bel;
+    }
+}
+
 // ---- randomised calibration: the statistic is the pair (S, u), u the simulation's adjoined
 // uniform (philox_tiebreak), ordered lexicographically.  Given the k-th smallest S, lambda, and
 // the count `below` of keys strictly under it (the selection's outputs), the k-th smallest pair
@@ -1257,6 +1450,25 @@ hipError_t launch_select(const Platten &P, const void *keys, const int32_t *k, d
         hipLaunchKernelGGL(k_b2_full, dim3(grid), dim3(SEL_WG), 0, st, (const uint4 *)keys, P.d_key_off,
                            P.d_key_stride, P.d_N, k, P.d_S_tbl, P.d_S_order, P.d_S_group, P.d_b2fb, lam, rej_at);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_h4_bracket(const Platten &P, const float *keys, const int32_t *k, double *lam, int32_t *rej_at,
+                             hipStream_t st) {
+    if (P.n_tiles == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_h4_bracket, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, keys, P.d_key_off,
+                       P.d_key_stride, P.d_N, k, P.h4_margin, P.h4_maxs, P.h4_tot, P.d_h4brk, P.d_h4below,
+                       P.d_h4cnt, P.d_h4cand, lam, rej_at);
+    return hipGetLastError();
+}
+
+hipError_t launch_h4_select(const Platten &P, uint64_t seed, const int32_t *k, double *lam, int32_t *rej_at,
+                            hipStream_t st) {
+    hipError_t e = launch_zero(P.d_h4fb, sizeof(uint32_t), st);   // the regenerated tiles' list starts empty
+    if (e != hipSuccess || P.n_tiles == 0) return e;
+    hipLaunchKernelGGL(k_h4_select, dim3((uint32_t)P.n_tiles), dim3(SEL_WG), 0, st, P.d_N, k, P.d_h4below, P.d_h4cnt,
+                       P.d_h4cand, P.h4_maxs, P.h4_caps, P.h4_tot, P.d_tileT, P.d_cfg, P.d_h4tbl, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), P.d_h4fb, lam, rej_at);
     return hipGetLastError();
 }
 

@@ -34,8 +34,18 @@ hipError_t launch_taylor(const Platten &P, const double *f, const double *g, dou
 hipError_t launch_hier4_table(int n, float4 *tbl, const HierNode *nodes, hipStream_t st);
 hipError_t launch_h4_mask(const float4 *tbl, int64_t n, float cut, int nbits, uint8_t *mask, hipStream_t st);
 hipError_t launch_basket_table(int n, const double *theta0, float4 *tbl, const HierNode *nodes, hipStream_t st);
+// pass: H4_PASS_ALL every simulation (keys: float32 keys of all of them, or none); H4_PASS_PILOT the
+// first H4_PILOT simulations with float32 keys; H4_PASS_MAIN the rest, bracketed keys (4-arm design)
+enum { H4_PASS_ALL = 0, H4_PASS_PILOT = 1, H4_PASS_MAIN = 2 };
 hipError_t launch_hier4(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
-                        hipStream_t st);
+                        hipStream_t st, int pass = H4_PASS_ALL);
+// bracketed 4-arm selection: brackets from the pilot keys (after k is known), then, after the
+// main pass, lambda*_i and the count below it (exact; tiles whose k-th key is not among the
+// candidates regenerate their keys from the counter-based generator)
+hipError_t launch_h4_bracket(const Platten &P, const float *keys, const int32_t *k, double *lam, int32_t *rej_at,
+                             hipStream_t st);
+hipError_t launch_h4_select(const Platten &P, uint64_t seed, const int32_t *k, double *lam, int32_t *rej_at,
+                            hipStream_t st);
 hipError_t launch_phase23(const Platten &P, uint64_t seed, uint32_t *R, unsigned long long *sumT, float *keys,
                           hipStream_t st);
 hipError_t launch_p23_look1(const Platten &P, hipStream_t st);

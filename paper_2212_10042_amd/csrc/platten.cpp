@@ -632,6 +632,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
                 rows += __builtin_popcount(B.bmask[j]);
             }
             B.n_rows = rows;
+            P->h4_max_rows = std::max(P->h4_max_rows, rows);
             B.key_base = P->n_keys;
             for (int j = 0; j < B4S; ++j) {
                 if (B.row0[j] < 0) continue;
@@ -662,6 +663,15 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
                                    P->d_h4mask, nullptr));
         CSE_HIP_TRY(hipDeviceSynchronize());
         P->table_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        if (kind == CSE_HIER4) {   // bracketed calibration keys: the exact path regenerates a tile's keys
+            if (int e = upload(&P->d_tileT, P->tile_T.data(), P->tile_T.size())) return e;
+            if (int e = upload(&P->d_cfg, P->tile_cfg.data(), P->tile_cfg.size())) return e;
+            const size_t nt = (size_t)std::max<int64_t>(P->n_tiles, 1);
+            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4brk, nt * sizeof(float2)));
+            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4below, nt * sizeof(uint32_t)));
+            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4fb, (nt + 1) * sizeof(uint32_t)));
+            CSE_HIP_TRY(hipMemset(P->d_h4fb, 0, sizeof(uint32_t)));
+        }
     } else if (kind == CSE_PHASE23) {
         // one trial per lane: keys contiguous per tile, work items of p23_chunk simulations
         for (int64_t t = 0; t < P->n_tiles; ++t) {
@@ -948,13 +958,15 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
         }
     }
     const int64_t ng = (int64_t)groups.size();
-    const int64_t slices = std::max<int64_t>(1, (target_wgs + ng - 1) / ng);
+    int64_t slices = std::max<int64_t>(1, (target_wgs + ng - 1) / ng);
+    if (P->design.kind == CSE_HIER4) slices = std::min<int64_t>(slices, H4_MAXS);
     // at least 4 chunks of 64 simulations per item: an item's fixed work (thresholds, the final
     // transposes and atomics) then stays small beside its simulations
     constexpr int64_t MIN_ITEM_CHUNKS = 4;
-    std::vector<GroupItem> gi;
+    std::vector<GroupItem> gi, gpil;
     std::vector<SquareItem> si;
     int64_t gs = 0;
+    int32_t maxs = 0, caps = 64;
     for (auto &g : groups) {
         int64_t first = -1;
         for (int64_t b : g)
@@ -962,6 +974,27 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
         const int64_t N = P->blk_sims[first];
         const int64_t chunks = (N + WAVE - 1) / WAVE;
         const int64_t per = std::max<int64_t>(MIN_ITEM_CHUNKS, (chunks + slices - 1) / slices) * WAVE;
+        if (!sq2) {
+            // bracketed keys: the pilot's ranges, and room for twice the candidates an item range
+            // expects (the bracket holds at most SEL_FILL_H4 of H4_SELCAND keys of the tile on
+            // average) plus 32
+            maxs = std::max<int32_t>(maxs, (int32_t)((N + per - 1) / per));
+            if (N > H4_PILOT) {
+                const double expect = 0.45 * 4096.0 * (double)std::min<int64_t>(per, N) / (double)N;
+                caps = std::max<int32_t>(caps, (int32_t)((2.0 * expect + 32.0 + 31.0) / 32.0) * 32);
+            }
+            const int64_t np = std::min<int64_t>(N, H4_PILOT);
+            const int64_t pper = std::max<int64_t>(MIN_ITEM_CHUNKS * WAVE, std::min<int64_t>(per, 4 * WAVE));
+            for (int64_t k0 = 0; k0 < np; k0 += pper) {
+                GroupItem it{};
+                for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
+                it.k_begin = (uint32_t)k0;
+                it.k_end = (uint32_t)std::min<int64_t>(np, k0 + pper);
+                it.slice = -1;
+                gpil.push_back(it);
+            }
+        }
+        int32_t slice = 0;
         for (int64_t k0 = 0; k0 < N; k0 += per) {
             const uint32_t kb = (uint32_t)k0, ke = (uint32_t)std::min<int64_t>(N, k0 + per);
             gs += (int64_t)(ke - kb);
@@ -976,8 +1009,32 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
                 for (int w = 0; w < 4; ++w) it.blk[w] = w < (int)g.size() ? (int32_t)g[w] : -1;
                 it.k_begin = kb;
                 it.k_end = ke;
+                it.slice = slice++;
                 gi.push_back(it);
             }
+        }
+    }
+    if (P->design.kind == CSE_HIER4) {
+        if (P->d_gitems_pilot) CSE_HIP_TRY(hipFree(P->d_gitems_pilot));
+        P->d_gitems_pilot = nullptr;
+        P->n_gitems_pilot = (int64_t)gpil.size();
+        if (!gpil.empty())
+            if (int e = upload(&P->d_gitems_pilot, gpil.data(), gpil.size())) return e;
+        const int64_t tot = (int64_t)H4_PCAP + (int64_t)maxs * caps;
+        // the bracketed pass keeps its row counters in LDS: H4_BROWS rows per block at most,
+        // else the platten calibrates with every key in HBM (d_h4cand stays null)
+        const bool rows_fit = P->h4_max_rows <= H4_BROWS;
+        if (rows_fit && (maxs != P->h4_maxs || tot != P->h4_tot)) {   // regions sized for these ranges
+            if (P->d_h4cnt) CSE_HIP_TRY(hipFree(P->d_h4cnt));
+            if (P->d_h4cand) CSE_HIP_TRY(hipFree(P->d_h4cand));
+            P->d_h4cnt = nullptr;
+            P->d_h4cand = nullptr;
+            const size_t nt = (size_t)std::max<int64_t>(P->n_tiles, 1);
+            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4cnt, nt * (size_t)(maxs + 1) * sizeof(uint32_t)));
+            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4cand, nt * (size_t)tot * sizeof(float)));
+            P->h4_maxs = maxs;
+            P->h4_caps = caps;
+            P->h4_tot = tot;
         }
     }
     P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
@@ -1031,7 +1088,8 @@ void free_platten(Platten *P) {
                     P->d_cls_off, P->d_cp_base, P->d_cp_mark, P->d_cp_tbl,  P->d_radii,
                     P->d_is_box, P->d_key_stride, P->d_h4tbl, P->d_tileT, P->d_cfg,
                     P->d_queue,  P->d_p23items, P->d_gh, P->d_p23stats, P->d_p23look1, P->d_hnodes,
-                    P->d_h4mask, P->d_S_pos, P->d_b2br, P->d_b2fb, P->d_b2cut, P->d_minpart, P->d_gstart, P->d_gcut, P->d_sqitems};
+                    P->d_h4mask, P->d_S_pos, P->d_b2br, P->d_b2fb, P->d_b2cut, P->d_minpart, P->d_gstart, P->d_gcut, P->d_sqitems,
+                    P->d_gitems_pilot, P->d_h4brk, P->d_h4below, P->d_h4cnt, P->d_h4cand, P->d_h4fb};
     auto in_arena = [&](void *q) {
         for (auto &a : P->arenas)
             if ((unsigned char *)q >= (unsigned char *)a.first && (unsigned char *)q < (unsigned char *)a.first + a.second)

@@ -97,10 +97,12 @@ def _decide32(S, cut):
     return S.astype(np.float32), np.float32(cut)
 
 
-def _compare(w, seed, cut=0.05):
+def _compare(w, seed, cut=0.05, bracket=False):
     th, rd, sm = w["theta"], w["radii"], w["sims"]
-    print(f"[hier4] compare {w['name']} seed={seed}", flush=True)
+    print(f"[hier4] compare {w['name']} seed={seed} bracketed keys {bracket}", flush=True)
     P = cse.Platten.create("hier4", th, rd, sm, cut=cut)
+    if bracket:
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
     subs = O.subtiles("hier4", th, rd)
     got = list(zip(P.tiles["box"].tolist(), P.tiles["cfg"].tolist()))
     assert got == [(int(s[0]), int(s[1])) for s in subs]
@@ -145,6 +147,58 @@ def test_hier4_uneven_sims_and_cut():
     w = W.hier4_grid(2, 100, lo=-0.5, hi=0.5, seed=6)
     w["sims"] = W.uneven_sims(w["theta"].shape[0], seed=3, lo_pow=6, n_classes=3)   # 64..256
     _compare(w, seed=6, cut=0.2)
+
+
+def test_hier4_bracketed_keys_vs_oracle():
+    """5,000 simulations per tile on small boxes (k = 53): the pilot's 2,048 keys bracket each
+    tile's k-th key and the fused pass keeps only the keys inside the bracket; every output
+    against the oracle."""
+    w = W.hier4_grid(2, 5000, lo=-0.1, hi=0.1, seed=8)
+    P = cse.Platten.create("hier4", w["theta"], w["radii"], w["sims"])
+    g = P.calibrate(8, alpha=w["alpha"], with_validation=False)
+    torch.cuda.synchronize()
+    assert int(_np(g["k"]).min()) > 0   # every tile selects
+    P.close()
+    _compare(w, seed=8, bracket=True)
+
+
+def test_hier4_exact_path_forced():
+    """Bracketed keys with a margin of 0 standard deviations: many tiles' k-th key falls outside
+    the bracket and is selected from keys regenerated one by one; lambda*_i, the counts below it
+    and k equal those of the default margin, of the every-key selection (the default path) and
+    the oracle's; cse_work_counters counts the regenerated tiles."""
+    margin = 0.0
+    w = W.hier4_grid(2, 3000, lo=-0.08, hi=0.08, seed=9)   # k = 38 on every tile
+    th, rd, sm = w["theta"], w["radii"], w["sims"]
+    print(f"[hier4] exact path forced, margin {margin}", flush=True)
+    P = cse.Platten.create("hier4", th, rd, sm)
+    g_all = P.calibrate(9, alpha=w["alpha"], with_validation=False)   # every key in HBM
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
+    g0 = P.calibrate(9, alpha=w["alpha"], with_validation=False)
+    torch.cuda.synchronize()
+    n0 = cse.cse_work_counters(P.handle)["trials"]
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_MARGIN, margin)
+    g1 = P.calibrate(9, alpha=w["alpha"], with_validation=False)
+    torch.cuda.synchronize()
+    n1 = cse.cse_work_counters(P.handle)["trials"]
+    print(f"[hier4] regenerated tiles: {n0} at the default margin, {n1} at {margin} of {P.n_tiles}", flush=True)
+    assert int(_np(g0["k"]).min()) > 0
+    assert n1 > n0
+    for key in ("lambda_tile", "reject_at_lambda", "k"):
+        assert np.array_equal(_np(g1[key]), _np(g0[key]))
+        assert np.array_equal(_np(g_all[key]), _np(g0[key]))
+    oc = O.calibrate("hier4", th, rd, sm, 9, w["alpha"], key_dtype=np.float32)
+    frac = (oc["N"] + 1.0) * oc["alpha_prime"]
+    near = np.abs(frac - np.round(frac)) < 1e-7
+    assert np.all((_np(g1["k"]) == oc["k"]) | near)
+    same = _np(g1["k"]) == oc["k"]
+    assert np.array_equal(_np(g1["lambda_tile"])[same], oc["lam"][same])
+    assert np.array_equal(_np(g1["reject_at_lambda"])[same], oc["reject_at_lam"][same])
+    with pytest.raises(cse.CseError):
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 2)
+    with pytest.raises(cse.CseError):
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_MARGIN, 101.0)
+    P.close()
 
 
 def test_hier4_full_workload_sampled_tiles(oracle_table):
@@ -212,6 +266,13 @@ def test_hier4_full_workload_sampled_tiles(oracle_table):
     lam = _np(g["lambda_tile"])
     assert float(_np(g["lambda_global"])[0]) == lam.min()
     assert np.all(_np(g["reject_at_lambda"]) < _np(g["k"]))
+    # bracketed keys (pilot + in-bracket candidates) select the same on every tile of the launch
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
+    gb = P.calibrate(w["seed"], alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    print(f"[hier4] bracketed keys: {cse.cse_work_counters(P.handle)['trials']} tiles regenerated", flush=True)
+    for key in ("lambda_tile", "reject_at_lambda", "k", "reject", "score_T"):
+        assert np.array_equal(_np(gb[key]), _np(g[key])), key
     P.close()
 
 
