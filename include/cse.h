@@ -447,7 +447,7 @@ int cse_simulate_per_tile(const cse_platten *p, uint64_t seed, int64_t tile_begi
 int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream);
 
 /*
- * cse_platten_set_option -- tuning options of a platten (host call, no GPU work).
+ * cse_platten_set_option -- tuning options of a platten (host call, no kernel launch).
  *   CSE_OPT_B2_MARGIN (CSE_BINOM2_Z calibration): the selection's bracket around each tile's
  *        k-th statistic, in standard deviations of the count (default 5).  Results do not
  *        depend on it: tiles whose k-th statistic falls outside the bracket take an exact
@@ -459,14 +459,17 @@ int cse_work_counters(const cse_platten *p, int64_t out[4], void *stream);
  *        (k/N) 2048 bracket each tile's k-th key; the fused pass over the other simulations
  *        counts the keys below the bracket and keeps only those inside it (about a tenth of the
  *        HBM traffic of storing every key).  0 (default) stores every float32 key and selects
- *        from them, as cse_calibrate_tiebreak always does.  Same results either way.
+ *        from them, as cse_calibrate_tiebreak always does.  Same results either way.  Turning
+ *        it on allocates the candidate regions (device memory; about 20 KB per tile at 32,768
+ *        simulations per tile with the default launch shape), turning it off frees them; the
+ *        plattens whose batches hold more than 128 key rows keep the every-key path.
  *   CSE_OPT_H4_MARGIN (CSE_HIER4 bracketed calibration): the bracket's margin in standard
  *        deviations of the pilot rank (default 6, lowered towards 3 where the bracket would
  *        hold too many keys).  Results do not depend on it: a tile whose k-th key is not among
  *        the kept ones is selected from its keys regenerated one by one from the counter-based
  *        generator (slow; cse_work_counters counts them).
  * Errors: CSE_EINVAL (bad handle, unknown option, value outside [0, 100]; 0 or 1 for
- * CSE_OPT_H4_BRACKET).
+ * CSE_OPT_H4_BRACKET), CSE_ENOMEM (the candidate regions could not be allocated).
  */
 #define CSE_OPT_B2_MARGIN 1
 #define CSE_OPT_H4_MARGIN 2

@@ -868,6 +868,10 @@ int cse_platten_set_option(cse_platten *p, int32_t option, double value) {
             return CSE_EINVAL;
         }
         p->P.h4_bracket = value == 1.0;
+        if (int e = cse::h4_regions(&p->P)) {   // the candidate regions live while the option is on
+            p->P.h4_bracket = false;
+            return e;
+        }
         return CSE_OK;
     }
     if (option != CSE_OPT_B2_MARGIN && option != CSE_OPT_H4_MARGIN) {

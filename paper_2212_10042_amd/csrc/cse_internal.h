@@ -186,6 +186,7 @@ struct Platten {
     int32_t h4_maxs = 0, h4_caps = 0;    // item ranges per group (at most), candidate slots per range
     int32_t h4_max_rows = 0;             // most key rows of a block
     int64_t h4_tot = 0;                  // candidate slots per tile: H4_PCAP + h4_maxs * h4_caps
+    size_t h4_cnt_alloc = 0, h4_cand_alloc = 0;   // entries of d_h4cnt / d_h4cand now allocated
     float2 *d_h4brk = nullptr;
     uint32_t *d_h4below = nullptr;
     uint32_t *d_h4cnt = nullptr;
@@ -290,6 +291,7 @@ int build_platten(const cse_design *design, int64_t n_boxes, const double *theta
 void free_platten(Platten *P);
 int plan_work_items(Platten *P, int64_t target_waves);
 int plan_group_items(Platten *P, int64_t target_wgs);
+int h4_regions(Platten *P);
 int plan_queue_items(Platten *P, int32_t chunk, int64_t grid);
 
 }  // namespace cse

@@ -929,6 +929,34 @@ int plan_work_items(Platten *P, int64_t target_waves) {
 // Workgroup items of the 2-arm and 4-arm kernels: groups of 4 consecutive blocks of equal N
 // (blocks are ordered by N) whose four waves share the Philox words of a simulation range;
 // ranges sliced so that the grid has about target_wgs workgroups.
+// The candidate regions of the bracketed 4-arm calibration, sized for the current item ranges:
+// allocated while the platten asks for that calibration (and its blocks' key rows fit the
+// fused pass's LDS counters), freed otherwise.
+int h4_regions(Platten *P) {
+    const bool want = P->design.kind == CSE_HIER4 && P->h4_bracket && P->h4_max_rows <= H4_BROWS;
+    const size_t nt = (size_t)std::max<int64_t>(P->n_tiles, 1);
+    const size_t n_cnt = want ? nt * (size_t)(P->h4_maxs + 1) : 0, n_cand = want ? nt * (size_t)P->h4_tot : 0;
+    if (n_cnt == P->h4_cnt_alloc && n_cand == P->h4_cand_alloc) return CSE_OK;
+    if (P->d_h4cnt) CSE_HIP_TRY(hipFree(P->d_h4cnt));
+    if (P->d_h4cand) CSE_HIP_TRY(hipFree(P->d_h4cand));
+    P->d_h4cnt = nullptr;
+    P->d_h4cand = nullptr;
+    P->h4_cnt_alloc = P->h4_cand_alloc = 0;
+    if (!want) return CSE_OK;
+    if (hipMalloc((void **)&P->d_h4cnt, n_cnt * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc((void **)&P->d_h4cand, n_cand * sizeof(float)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (P->d_h4cnt) (void)hipFree(P->d_h4cnt);
+        P->d_h4cnt = nullptr;
+        P->d_h4cand = nullptr;
+        set_error("cannot allocate the bracketed calibration's candidate regions");
+        return CSE_ENOMEM;
+    }
+    P->h4_cnt_alloc = n_cnt;
+    P->h4_cand_alloc = n_cand;
+    return CSE_OK;
+}
+
 int plan_group_items(Platten *P, int64_t target_wgs) {
     std::vector<std::vector<int64_t>> groups;   // up to 4 (16 for the 2-arm design) blocks each (-1: none)
     const bool sq2 = P->design.kind == CSE_BINOM2_Z;
@@ -1020,22 +1048,10 @@ int plan_group_items(Platten *P, int64_t target_wgs) {
         P->n_gitems_pilot = (int64_t)gpil.size();
         if (!gpil.empty())
             if (int e = upload(&P->d_gitems_pilot, gpil.data(), gpil.size())) return e;
-        const int64_t tot = (int64_t)H4_PCAP + (int64_t)maxs * caps;
-        // the bracketed pass keeps its row counters in LDS: H4_BROWS rows per block at most,
-        // else the platten calibrates with every key in HBM (d_h4cand stays null)
-        const bool rows_fit = P->h4_max_rows <= H4_BROWS;
-        if (rows_fit && (maxs != P->h4_maxs || tot != P->h4_tot)) {   // regions sized for these ranges
-            if (P->d_h4cnt) CSE_HIP_TRY(hipFree(P->d_h4cnt));
-            if (P->d_h4cand) CSE_HIP_TRY(hipFree(P->d_h4cand));
-            P->d_h4cnt = nullptr;
-            P->d_h4cand = nullptr;
-            const size_t nt = (size_t)std::max<int64_t>(P->n_tiles, 1);
-            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4cnt, nt * (size_t)(maxs + 1) * sizeof(uint32_t)));
-            CSE_HIP_TRY(hipMalloc((void **)&P->d_h4cand, nt * (size_t)tot * sizeof(float)));
-            P->h4_maxs = maxs;
-            P->h4_caps = caps;
-            P->h4_tot = tot;
-        }
+        P->h4_maxs = maxs;
+        P->h4_caps = caps;
+        P->h4_tot = (int64_t)H4_PCAP + (int64_t)maxs * caps;
+        if (int e = h4_regions(P)) return e;
     }
     P->shape_gen->fetch_add(1);   // plans captured on the old arrays become stale
     if (P->d_gitems) CSE_HIP_TRY(hipFree(P->d_gitems));
