@@ -72,6 +72,37 @@ def _same(a, b):
         assert torch.equal(a[key], b[key]), key
 
 
+def test_bracketed_hier4_plan_replays_match_eager():
+    """The 4-arm calibration from bracketed keys captured as a graph (the inversion on a branch
+    beside the pilot pass, the brackets after both): every replay equals the eager bracketed call
+    and the every-key call, with eager work between replays."""
+    w = W.hier4_grid(2, 3000, lo=-0.08, hi=0.08, seed=5)   # k > 0 on every tile, N > the pilot
+    print("[graph] bracketed 4-arm calibration plan", flush=True)
+    P = cse.Platten.create("hier4", w["theta"], w["radii"], w["sims"])
+    every = _alloc(P)
+    _eager(P, 3, every)
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
+    ref = _alloc(P)
+    _eager(P, 3, ref)
+    torch.cuda.synchronize()
+    assert int(ref["k"].min().item()) > 0
+    _same(every, ref)
+    out = _alloc(P)
+    other = _alloc(P)
+    plan = cse.cse_plan_calibrate(P.handle, 3, 0.025, *_calib_args(out))
+    try:
+        for rep in range(3):
+            _fill(out)
+            cse.cse_plan_launch(plan)
+            torch.cuda.synchronize()
+            _same(ref, out)
+            _eager(P, 100 + rep, other)
+            torch.cuda.synchronize()
+    finally:
+        cse.cse_plan_destroy(plan)
+    P.close()
+
+
 @pytest.mark.parametrize("kind", KINDS)
 def test_calibration_plan_replays_match_eager(kind):
     w = _case(kind)
