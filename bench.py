@@ -276,6 +276,8 @@ def main():
     ap.add_argument("--autotune", action="store_true",
                     help="pick the fused kernel's launch shape with cse_autotune before timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the HIP-graph replay measurement")
+    ap.add_argument("--b2-margin", type=float, default=None,
+                    help="2-arm calibration: the selection's bracket margin in standard deviations (default 5)")
     ap.add_argument("--h4-bracket", action="store_true",
                     help="4-arm calibration from bracketed keys (pilot + in-bracket candidates) instead of every key")
     ap.add_argument("--no-extensions", action="store_true",
@@ -361,6 +363,8 @@ def measure(name, w, design, args, full=True):
     platten_ms = (time.perf_counter() - t0) * 1e3
     if args.h4_bracket and design == "hier4":
         cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
+    if args.b2_margin is not None and design == "binom2":
+        cse.cse_platten_set_option(P.handle, cse.CSE_OPT_B2_MARGIN, args.b2_margin)
     st = cse.cse_platten_stats(P.handle)
     n, d = P.n_tiles, P.d
     dev = "cuda"
