@@ -162,6 +162,26 @@ def test_hier4_bracketed_keys_vs_oracle():
     _compare(w, seed=8, bracket=True)
 
 
+def test_hier4_bracketed_keys_pilot_edges():
+    """Bracketed keys on boxes whose N sits at the pilot's edges (1,000, 2,047, 2,048, 2,049, 2,111,
+    2,112 and 4,200 simulations: the pilot is the whole tile, the pass after it has one simulation,
+    a ragged last chunk, a whole chunk, several chunks): lambda*_i, the counts below it, k, R and
+    the score sums equal the every-key path's on every tile."""
+    w = W.hier4_grid(2, 3000, lo=-0.08, hi=0.08, seed=11)
+    edge = np.array([1000, 2047, 2048, 2049, 2111, 2112, 4200], np.int32)
+    w["sims"] = edge[np.arange(w["theta"].shape[0]) % edge.size]
+    P = cse.Platten.create("hier4", w["theta"], w["radii"], w["sims"])
+    print(f"[hier4] bracketed keys at the pilot's edges: {P.n_tiles} tiles", flush=True)
+    g_all = P.calibrate(11, alpha=w["alpha"], delta=w["delta"])
+    cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
+    g_b = P.calibrate(11, alpha=w["alpha"], delta=w["delta"])
+    torch.cuda.synchronize()
+    assert int(_np(g_all["k"]).min()) > 0
+    for key in ("lambda_tile", "reject_at_lambda", "k", "reject", "score_T", "lambda_global"):
+        assert np.array_equal(_np(g_b[key]), _np(g_all[key])), key
+    P.close()
+
+
 def test_hier4_exact_path_forced():
     """Bracketed keys with a margin of 0 standard deviations: many tiles' k-th key falls outside
     the bracket and is selected from keys regenerated one by one; lambda*_i, the counts below it
