@@ -23,7 +23,12 @@ def _cases():
     zs = W.ztest_1d(16, 77)
     p23 = W.phase23_grid((2, 2, 2, 2), sims=300)
     p23s = W.phase23_grid((1, 2, 1, 2), sims=65)
-    return [("binom2", big, small), ("hier4", h4, h4s), ("ztest1", z, zs), ("phase23", p23, p23s)], cse
+    # the 4-arm calibration from bracketed keys (CSE_OPT_H4_BRACKET): small boxes (k > 0), N past
+    # the 2,048-simulation pilot
+    h4b = W.hier4_grid(2, 3000, lo=-0.08, hi=0.08, seed=6)
+    h4bs = W.hier4_grid(2, 2500, lo=-0.06, hi=0.06, seed=7)
+    return [("binom2", big, small), ("hier4", h4, h4s), ("ztest1", z, zs), ("phase23", p23, p23s),
+            ("hier4+bracket", h4b, h4bs)], cse
 
 
 def _run(P, noalloc, seed):
@@ -32,13 +37,15 @@ def _run(P, noalloc, seed):
     return {k: (v.cpu().numpy() if v is not None else None) for k, v in o.items()}
 
 
-@pytest.mark.parametrize("i", [0, 1, 2, 3])
+@pytest.mark.parametrize("i", [0, 1, 2, 3, 4])
 def test_noalloc_matches_calibrate_twice(i):
     torch.cuda.set_device(0)
     cases, cse = _cases()
     kind, first, second = cases[i]
     for w, seed in ((first, 11), (second, 12)):   # the second call on a smaller platten
-        P = cse.Platten.create(kind, w["theta"], w["radii"], w["sims"], cut=w.get("cut"))
+        P = cse.Platten.create(kind.split("+")[0], w["theta"], w["radii"], w["sims"], cut=w.get("cut"))
+        if kind.endswith("+bracket"):
+            cse.cse_platten_set_option(P.handle, cse.CSE_OPT_H4_BRACKET, 1)
         print(f"noalloc case {kind}: {P.n_tiles} tiles, seed {seed}", flush=True)
         ref = _run(P, False, seed)
         got = _run(P, True, seed)
