@@ -25,8 +25,8 @@ __device__ __forceinline__ void wave_sync() {
 // (18 Philox blocks).  Each wave's batch is an 8 x 8 product of thresholds: the success
 // counts y0[u], y1[v] at 16 thresholds give the outcomes of all 64 tiles.  The 16 waves of a
 // workgroup run the 16 batches of a 4 x 4 square of the threshold grid over the same
-// simulations (wave 4 r + c: row group r, column group c): the chunk's 18 Philox blocks are
-// generated once into LDS (one per wave, waves 0 and 1 a second), and the square's eight sets
+// simulations (wave 4 r + c: row group r, column group c): the Philox blocks of two chunks at a
+// time (36) are generated once into LDS (two or three per wave), and the square's eight sets
 // of 8 thresholds (four arm-0 row groups, four arm-1 column groups) are each counted once per
 // simulation, by a pair of waves over the two halves of the arm's 35 words; the partial counts
 // (8 bytes per simulation, a byte per threshold) go through LDS, and a batch adds the two
@@ -62,12 +62,16 @@ __global__ __launch_bounds__(WG2) void k_binom2(const Blk2 *__restrict__ blocks,
     constexpr int JH = (NP35 + 1) / 2;   // words of the first counting half (18; the second 17)
     // flush transposes (per wave HALF x (64 + 1) words, padded against bank conflicts); between
     // flushes the same memory holds the chunk's Philox words
+    // Two chunks per barrier phase: their 36 Philox blocks spread over the 16 waves (at most three
+    // per wave, against two of one chunk's 18 on waves 0 and 1 while the other 14 wait), and half
+    // the barriers.
+    constexpr int CPB = 2;
     __shared__ uint32_t lds[NWAVES][HALF][WAVE + 1];
     __shared__ int32_t s_cut[64];
-    __shared__ uint2 cnt[NWAVES][WAVE];   // per counting wave and lane: its 8 partial counts as bytes
-    uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [4*NB][64]
-    static_assert(4 * NB * WAVE <= NWAVES * HALF * (WAVE + 1), "word buffer must fit");
-    static_assert(NB <= 2 * NWAVES, "at most two Philox blocks per wave");
+    __shared__ uint2 cnt[CPB][NWAVES][WAVE];   // per chunk, counting wave and lane: its 8 partial counts as bytes
+    uint32_t(*words)[WAVE] = reinterpret_cast<uint32_t(*)[WAVE]>(&lds[0][0][0]);   // [CPB][4*NB][64]
+    static_assert(CPB * 4 * NB * WAVE <= NWAVES * HALF * (WAVE + 1), "word buffer must fit");
+    static_assert(CPB * NB <= 3 * NWAVES, "at most three Philox blocks per wave");
 
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -124,39 +128,48 @@ __global__ __launch_bounds__(WG2) void k_binom2(const Blk2 *__restrict__ blocks,
     };
 
     int since = 0;
-    for (uint32_t k0 = kb; k0 < ke; k0 += WAVE) {
-        const uint32_t k = k0 + (uint32_t)lane;
-        const bool act = k < ke;
-        // this wave's Philox blocks of the chunk: block wv, and block wv + 16 for waves 0 and 1
-        for (int b = wv; b < NB; b += NWAVES) {
-            const u32x4 w = philox_block((uint32_t)b, k, key0, key1);
-            words[4 * b + 0][lane] = w.x;
-            words[4 * b + 1][lane] = w.y;
-            words[4 * b + 2][lane] = w.z;
-            words[4 * b + 3][lane] = w.w;
+    for (uint32_t k00 = kb; k00 < ke; k00 += CPB * WAVE) {
+        // this wave's Philox blocks of the phase's chunks: (chunk, block) pairs wv, wv + 16, wv + 32
+        // of the 36 (words of a chunk past the item's end are generated and never used)
+        for (int bb = wv; bb < CPB * NB; bb += NWAVES) {
+            const int c = bb / NB, b = bb - c * NB;
+            const u32x4 w = philox_block((uint32_t)b, k00 + (uint32_t)(c * WAVE + lane), key0, key1);
+            uint32_t(*wc)[WAVE] = words + c * 4 * NB;
+            wc[4 * b + 0][lane] = w.x;
+            wc[4 * b + 1][lane] = w.y;
+            wc[4 * b + 2][lane] = w.z;
+            wc[4 * b + 3][lane] = w.w;
         }
         __syncthreads();
-        {
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) {
             uint32_t yc[B2U];
 #pragma unroll
             for (int u = 0; u < B2U; ++u) yc[u] = 0u;
             if (counting) {
+                uint32_t(*wc)[WAVE] = words + c * 4 * NB;
 #pragma unroll 6
                 for (int j = 0; j < jn; ++j) {
-                    const uint32_t x = words[jw0 + j][lane];
+                    const uint32_t x = wc[jw0 + j][lane];
 #pragma unroll
                     for (int u = 0; u < B2U; ++u) yc[u] += (x < Tc[u]) ? 1u : 0u;
                 }
             }
-            cnt[wv][lane] = make_uint2(yc[0] | (yc[1] << 8) | (yc[2] << 16) | (yc[3] << 24),
-                                       yc[4] | (yc[5] << 8) | (yc[6] << 16) | (yc[7] << 24));
+            cnt[c][wv][lane] = make_uint2(yc[0] | (yc[1] << 8) | (yc[2] << 16) | (yc[3] << 24),
+                                          yc[4] | (yc[5] << 8) | (yc[6] << 16) | (yc[7] << 24));
         }
-        __syncthreads();   // words consumed, counts shared: the next chunk (or a flush) may overwrite the words
-        if (live) {
+        __syncthreads();   // words consumed, counts shared: the next phase (or a flush) may overwrite the words
+#pragma unroll
+        for (int c = 0; c < CPB; ++c) {
+        const uint32_t k0 = k00 + (uint32_t)(c * WAVE);
+        if (!live || k0 >= ke) break;   // uniform: the item's range ends in the phase's first chunk
+        const uint32_t k = k0 + (uint32_t)lane;
+        const bool act = k < ke;
+        {
             // the batch's row set (arm-0 counts) and column set (arm-1 counts), each the byte-wise
             // sum of its two halves
-            const uint2 ra = cnt[rsrc][lane], rb = cnt[rsrc + 1][lane];
-            const uint2 ca = cnt[csrc2][lane], cb = cnt[csrc2 + 1][lane];
+            const uint2 ra = cnt[c][rsrc][lane], rb = cnt[c][rsrc + 1][lane];
+            const uint2 ca = cnt[c][csrc2][lane], cb = cnt[c][csrc2 + 1][lane];
             const uint2 rc = make_uint2(ra.x + rb.x, ra.y + rb.y);
             const uint2 cc = make_uint2(ca.x + cb.x, ca.y + cb.y);
             int y0[B2U], y1[B2V];
@@ -188,7 +201,9 @@ __global__ __launch_bounds__(WG2) void k_binom2(const Blk2 *__restrict__ blocks,
                     acc[u * B2V + v] += __umul24(r, P0[u] + P1[v]);
                 }
         }
-        if (++since == 63) {
+        }
+        since += CPB;
+        if (since > 63 - CPB) {   // at most 63 simulations per lane between flushes
             flush();
             since = 0;
         }
