@@ -129,9 +129,13 @@ __global__ __launch_bounds__(WG2) void k_binom2(const Blk2 *__restrict__ blocks,
 
     int since = 0;
     for (uint32_t k00 = kb; k00 < ke; k00 += CPB * WAVE) {
-        // this wave's Philox blocks of the phase's chunks: (chunk, block) pairs wv, wv + 16, wv + 32
-        // of the 36 (words of a chunk past the item's end are generated and never used)
-        for (int bb = wv; bb < CPB * NB; bb += NWAVES) {
+        // this wave's Philox blocks of the phase's chunks, (chunk, block) pairs numbered 0..35: wv and
+        // wv + 16, and 32 + wv / 2 for waves 1, 3, 5 and 7, which count the shorter (17-word) halves
+        // (words of a chunk past the item's end are generated and never used)
+        static_assert(CPB * NB == 2 * NWAVES + 4, "two blocks per wave and four more");
+        const int nbb = (wv & 1) && wv < 8 ? 3 : 2;
+        for (int i = 0; i < nbb; ++i) {
+            const int bb = i < 2 ? wv + i * NWAVES : 2 * NWAVES + (wv >> 1);
             const int c = bb / NB, b = bb - c * NB;
             const u32x4 w = philox_block((uint32_t)b, k00 + (uint32_t)(c * WAVE + lane), key0, key1);
             uint32_t(*wc)[WAVE] = words + c * 4 * NB;
