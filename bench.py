@@ -65,9 +65,9 @@ P23_NODE, P23_NEWTON, P23_TAIL, P23_P2_EXTRA, P23_P3_EXTRA = 400, 200, 104, 6800
 # runs (profiles/<workload>_counters.md, scaled by what the counters read for a copy of known
 # size).  Valid only while that kernel is unchanged; workloads not listed report null.
 TRAFFIC = {
-    "binom2_1024_full": 4_388_275_669,   # k_binom2<true>: 17.8 MB read, 4,370.5 MB written (records + sums)
-    "hier4_16": 11_977_501_568,          # k_hier4<1, false, true>: 3,568.2 MB read, 8,409.3 MB written
-    "phase23_c5_sub256": 1_625_516_480,  # k_phase23: 228.6 MB read, 1,396.9 MB written
+    "binom2_1024_full": 4_388_248_490,   # k_binom2<true>: 17.8 MB read, 4,370.5 MB written (records + sums)
+    "hier4_16": 11_977_047_296,          # k_hier4<1, false, true>: 3,567.7 MB read, 8,409.3 MB written
+    "phase23_c5_sub256": 1_625_325_749,  # k_phase23: 228.7 MB read, 1,396.7 MB written
 }
 
 DEFAULT = "binom2_1024_full"
